@@ -1,0 +1,225 @@
+"""Seeded synthetic PINN workloads shared by the oracle, the tests and the benchmark.
+
+This module holds problem *data* only: collocation points and their kind, Monte Carlo quadrature
+weights, the source / boundary / initial values of the manufactured solutions, Glorot-uniform initial
+parameters and Gaussian test matrices. It contains none of the method's arithmetic (no network
+evaluation, no Jacobian, no Gramian, no sketch, no CG), so both the FP64 oracle and the GPU path can
+read the same inputs without sharing any computation.
+
+Point sets follow the paper's Monte Carlo quadrature (uniform points drawn once and kept fixed,
+experimental details of the appendix): interior weights are meas(domain)/N_interior and boundary
+weights meas(boundary)/N_boundary, so that sum_r w_r res_r^2 approximates the L2 norms of the
+least-squares energy of the Poisson problem (Section 5.1.1) and of the heat problem (Section 5.1.2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+KIND_INTERIOR = 0   # PDE residual row
+KIND_BOUNDARY = 1   # Dirichlet row: res = u - g
+KIND_INITIAL = 2    # initial-condition row (heat): res = u - g
+
+PDE_POISSON = 0     # interior res = Laplace(u) + f      (-Laplace(u) = f)
+PDE_HEAT = 1        # interior res = u_t - Laplace_x(u) - f (last input coordinate is time)
+
+# purposes for independent random streams
+_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE = range(6)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One PINN least-squares problem: network shape plus the fixed quadrature data."""
+
+    name: str
+    pde: int                      # PDE_POISSON or PDE_HEAT
+    widths: tuple                 # (d, n_1, ..., n_L, 1)
+    X: np.ndarray                 # (N, d) float64 collocation points
+    kind: np.ndarray              # (N,) int8 row kind
+    w: np.ndarray                 # (N,) float64 quadrature weights
+    f: np.ndarray                 # (N,) float64 source on interior rows (0 elsewhere)
+    g: np.ndarray                 # (N,) float64 target value on boundary / initial rows (0 elsewhere)
+    dtype: str = "f64"            # working precision of the GPU path ("f64" | "f32")
+    ell: int = 100                # sketch size
+    lam: Optional[float] = None   # fixed damping, or None for the adaptive rule
+    sketch_dtype: str = "f64"     # "f64" | "f32" | "bf16"
+    seed: int = 0
+
+    @property
+    def n_rows(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.X.shape[1])
+
+    @property
+    def n_params(self) -> int:
+        return num_params(self.widths)
+
+    def cast(self, dtype: str) -> "Problem":
+        """The same problem with all floating data rounded to `dtype` and promoted back to float64.
+
+        Comparing the FP64 oracle against a reduced-precision GPU run on the rounded inputs isolates
+        the arithmetic error of the GPU path from the rounding of its inputs.
+        """
+        if dtype == "f64":
+            return self
+        np_t = {"f32": np.float32}[dtype]
+        rd = lambda a: a.astype(np_t).astype(np.float64)
+        return dataclasses.replace(self, X=rd(self.X), w=rd(self.w), f=rd(self.f), g=rd(self.g))
+
+
+def num_params(widths: Sequence[int]) -> int:
+    """p = sum_l (n_l n_{l-1} + n_l) (Section 2.3)."""
+    return int(sum(a * b + b for a, b in zip(widths[:-1], widths[1:])))
+
+
+def _rng(seed: int, purpose: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(purpose)]))
+
+
+def glorot_theta(widths: Sequence[int], seed: int) -> np.ndarray:
+    """Flat parameters [W_1, b_1, ..., W_{L+1}, b_{L+1}] (W row-major, out x in), Glorot-uniform
+    weights U(-a, a) with a = sqrt(6 / (n_in + n_out)) and zero biases."""
+    rng = _rng(seed, _P_THETA)
+    parts = []
+    for n_in, n_out in zip(widths[:-1], widths[1:]):
+        a = math.sqrt(6.0 / (n_in + n_out))
+        parts.append(rng.uniform(-a, a, size=(n_out, n_in)).ravel())
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts)
+
+
+def gaussian_omega(n_params: int, ell: int, seed: int, counter: int = 0) -> np.ndarray:
+    """Standard normal test matrix Omega, shape (p, ell), for sketch number `counter`."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), _P_OMEGA, int(counter)]))
+    return rng.standard_normal((n_params, ell))
+
+
+def probe_vectors(n: int, k: int, seed: int) -> np.ndarray:
+    """k standard normal probe vectors of length n, shape (n, k)."""
+    return _rng(seed, _P_PROBE).standard_normal((n, k))
+
+
+# ----------------------------------------------------------------------------------------------
+# manufactured solutions
+# ----------------------------------------------------------------------------------------------
+
+def _sinprod(X: np.ndarray) -> np.ndarray:
+    return np.prod(np.sin(np.pi * X), axis=1)
+
+
+def _sinsum(X: np.ndarray) -> np.ndarray:
+    return np.sum(np.sin(np.pi * X), axis=1)
+
+
+def _box_boundary(rng, n: int, d: int) -> np.ndarray:
+    """n points uniform on the boundary of [0,1]^d: a face (2d of them) uniformly, then uniform on it."""
+    X = rng.uniform(0.0, 1.0, size=(n, d))
+    face = rng.integers(0, 2 * d, size=n)
+    X[np.arange(n), face // 2] = (face % 2).astype(np.float64)
+    return X
+
+
+def _assemble(name, pde, widths, blocks, **kw) -> Problem:
+    X = np.concatenate([b[0] for b in blocks])
+    kind = np.concatenate([np.full(len(b[0]), b[1], np.int8) for b in blocks])
+    w = np.concatenate([np.full(len(b[0]), b[2]) for b in blocks])
+    f = np.concatenate([b[3] for b in blocks])
+    g = np.concatenate([b[4] for b in blocks])
+    return Problem(name=name, pde=pde, widths=tuple(int(v) for v in widths), X=X, kind=kind, w=w,
+                   f=f, g=g, **kw)
+
+
+def poisson2d_grid(widths=(2, 32, 32, 1), n_side=30, seed=0, dtype="f64", ell=100, lam=1e-6,
+                   sketch_dtype="f64") -> Problem:
+    """2D Poisson on [0,1]^2, u* = sin(pi x) sin(pi y), f = 2 pi^2 u*, g = 0.
+
+    Interior: the n_side^2 cell centres of a uniform grid. Boundary: n_side points per edge at the
+    edge-cell midpoints (no corners, no duplicates)."""
+    c = (np.arange(n_side) + 0.5) / n_side
+    xx, yy = np.meshgrid(c, c, indexing="ij")
+    Xi = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    z, o = np.zeros(n_side), np.ones(n_side)
+    Xb = np.concatenate([np.stack([c, z], 1), np.stack([c, o], 1), np.stack([z, c], 1), np.stack([o, c], 1)])
+    ni, nb = len(Xi), len(Xb)
+    blocks = [(Xi, KIND_INTERIOR, 1.0 / ni, 2 * np.pi ** 2 * _sinprod(Xi), np.zeros(ni)),
+              (Xb, KIND_BOUNDARY, 4.0 / nb, np.zeros(nb), np.zeros(nb))]
+    return _assemble("poisson2d_grid", PDE_POISSON, widths, blocks, dtype=dtype, ell=ell, lam=lam,
+                     sketch_dtype=sketch_dtype, seed=seed)
+
+
+def poisson_random(d=2, widths=(2, 64, 64, 64, 1), n_interior=4096, n_boundary=512, seed=0,
+                   dtype="f32", ell=400, lam=None, sketch_dtype="f32", solution="sinprod") -> Problem:
+    """Poisson on [0,1]^d with uniform random interior and boundary points.
+
+    solution="sinprod": u* = prod_i sin(pi x_i), f = d pi^2 u*, g = u* on the boundary (= 0).
+    solution="sinsum":  u* = sum_i sin(pi x_i),  f = pi^2 u*,   g = u* on the boundary."""
+    rng_i, rng_b = _rng(seed, _P_INTERIOR), _rng(seed, _P_BOUNDARY)
+    Xi = rng_i.uniform(0.0, 1.0, size=(n_interior, d))
+    Xb = _box_boundary(rng_b, n_boundary, d)
+    if solution == "sinprod":
+        fi, gb = d * np.pi ** 2 * _sinprod(Xi), _sinprod(Xb)
+    elif solution == "sinsum":
+        fi, gb = np.pi ** 2 * _sinsum(Xi), _sinsum(Xb)
+    else:
+        raise ValueError(solution)
+    blocks = [(Xi, KIND_INTERIOR, 1.0 / n_interior, fi, np.zeros(n_interior)),
+              (Xb, KIND_BOUNDARY, 2.0 * d / n_boundary, np.zeros(n_boundary), gb)]
+    return _assemble(f"poisson{d}d_random", PDE_POISSON, widths, blocks, dtype=dtype, ell=ell,
+                     lam=lam, sketch_dtype=sketch_dtype, seed=seed)
+
+
+def heat2d(widths=(3, 64, 64, 64, 64, 1), n_interior=8192, n_lateral=1024, n_initial=1024, seed=0,
+           dtype="f32", ell=400, lam=None, sketch_dtype="f32") -> Problem:
+    """Heat equation u_t = Laplace_x u on [0,1]^2 x [0,1]; u* = exp(-2 pi^2 t) sin(pi x) sin(pi y).
+
+    Inputs are (x, y, t). Lateral rows have g = 0, initial rows (t = 0) have g = sin(pi x) sin(pi y)."""
+    rng_i, rng_b, rng_0 = _rng(seed, _P_INTERIOR), _rng(seed, _P_BOUNDARY), _rng(seed, _P_INITIAL)
+    Xi = rng_i.uniform(0.0, 1.0, size=(n_interior, 3))
+    Xl = np.concatenate([_box_boundary(rng_b, n_lateral, 2), rng_b.uniform(0, 1, (n_lateral, 1))], 1)
+    X0 = np.concatenate([rng_0.uniform(0, 1, (n_initial, 2)), np.zeros((n_initial, 1))], 1)
+    blocks = [(Xi, KIND_INTERIOR, 1.0 / n_interior, np.zeros(n_interior), np.zeros(n_interior)),
+              (Xl, KIND_BOUNDARY, 4.0 / n_lateral, np.zeros(n_lateral), np.zeros(n_lateral)),
+              (X0, KIND_INITIAL, 1.0 / n_initial, np.zeros(n_initial), _sinprod(X0[:, :2]))]
+    return _assemble("heat2d", PDE_HEAT, widths, blocks, dtype=dtype, ell=ell, lam=lam,
+                     sketch_dtype=sketch_dtype, seed=seed)
+
+
+# ----------------------------------------------------------------------------------------------
+# named configurations
+# ----------------------------------------------------------------------------------------------
+
+def config(name: str, seed: int = 0) -> Problem:
+    """The named workloads.
+
+    c1: 2D Poisson, 2-32-32-1, 30x30 grid + 120 boundary points, FP64, lambda = 1e-6, ell = 100.
+    c2: 2D Poisson, 2-64-64-64-1, 4,096 + 512 random points, FP32, ell = 400, adaptive damping.
+    c3: 5D Poisson (u* = sum sin), 5-128-128-128-1, 16,384 + 2,048 points, BF16 sketch, ell = 800.
+    c4: 2+1D heat, 3-64-64-64-64-1, 8,192 + 1,024 lateral + 1,024 initial points, FP32, ell = 400.
+    """
+    if name == "c1":
+        return poisson2d_grid(seed=seed)
+    if name == "c2":
+        return poisson_random(seed=seed)
+    if name == "c3":
+        return poisson_random(d=5, widths=(5, 128, 128, 128, 1), n_interior=16384, n_boundary=2048,
+                              seed=seed, ell=800, sketch_dtype="bf16", solution="sinsum")
+    if name == "c4":
+        return heat2d(seed=seed)
+    raise KeyError(name)
+
+
+def small_problem(pde=PDE_POISSON, d=2, widths=(2, 8, 8, 1), n_interior=24, n_boundary=12, seed=0,
+                  dtype="f64", ell=10, lam=1e-3) -> Problem:
+    """Tiny instances for brute-force pins (random points, sinprod manufactured data)."""
+    if pde == PDE_HEAT:
+        return heat2d(widths=widths, n_interior=n_interior, n_lateral=n_boundary // 2,
+                      n_initial=n_boundary - n_boundary // 2, seed=seed, dtype=dtype, ell=ell, lam=lam,
+                      sketch_dtype=dtype)
+    return poisson_random(d=d, widths=widths, n_interior=n_interior, n_boundary=n_boundary, seed=seed,
+                          dtype=dtype, ell=ell, lam=lam, sketch_dtype=dtype)
