@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark: Nystrom-preconditioned NGD steps per second on one MI355X, against plain CG.
+
+Workload (default): 2D Poisson -Laplace u = f on [0,1]^2, u* = sin(pi x) sin(pi y), tanh MLP
+2-64-64-64-1 (P = 8,577), 4,096 uniform interior + 512 boundary points, FP32 residuals / Jacobian /
+matvecs with FP64 CG scalars, sketch size ell = 400, PCG to relative residual 1e-6, damping
+mu = max(10 eps lam1_hat, 1e-4 L^2). One step = residuals + Jacobian + gradient, Gaussian sketch
+and FP64 Nystrom core, damping, PCG, Armijo line search and update: the whole hot path.
+
+Prints one JSON line with the steps/s of the Nystrom-PCG loop (`value`), plain-CG steps/s, the
+one-pass Gramian-matvec bandwidth with its roofline, and the FP64 CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": "2D Poisson 2-32-32-1 tanh (P=1,185), 30x30 grid + 120 boundary points, FP64, ell=100, "
+          "lambda=1e-6, PCG rtol 1e-6",
+    "c2": "2D Poisson 2-64-64-64-1 tanh (P=8,577), 4,096 + 512 random points, FP32 (FP64 CG scalars), "
+          "ell=400, PCG rtol 1e-6",
+    "c3": "5D Poisson 5-128-128-128-1 tanh (P=33,921), 16,384 + 2,048 points, FP32 Jacobian, BF16 sketch, "
+          "FP64 core, ell=800, PCG rtol 1e-6",
+}
+
+
+def _cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = max((i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"), default=0)
+        if n:
+            return int(n)
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(cfg: str, seed: int, steps: int = 1):
+    """The FP64 NumPy oracle's NGD step on the same workload (bounded sample)."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import ngd as ongd
+
+    prob = wl.config(cfg, seed=seed)
+    theta = wl.glorot_theta(prob.widths, seed)
+    prob64 = prob.cast(prob.dtype)
+    th = theta.astype(np.float32).astype(np.float64) if prob.dtype == "f32" else theta
+    t0 = time.perf_counter()
+    for k in range(steps):
+        Om = wl.gaussian_omega(prob.n_params, prob.ell, seed=seed, counter=k)
+        th, _ = ongd.ngd_step(th, prob64, solver="nystrom", Omega=Om, rtol=1e-6, maxit=1000)
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "NGD steps/s", "cores": _cpu_threads(), "kind": "oracle",
+            "sample": f"{steps} Nystrom-PCG NGD step(s) of workload {cfg} (same data, ell={prob.ell}, "
+                      f"rtol 1e-6) in the FP64 NumPy oracle, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cg-steps", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2505_11638_amd.driver import NGD
+
+    prob = wl.config(a.config, seed=a.seed)
+    theta0 = wl.glorot_theta(prob.widths, a.seed)
+    P, N = prob.n_params, prob.n_rows
+    rtol = 1e-6
+
+    # ---- Nystrom-PCG NGD ----
+    nys = NGD(prob, theta0, solver="nystrom", rtol=rtol, seed=a.seed)
+    for _ in range(a.warmup):
+        nys.step()
+    gp = nys.gp
+    gp.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [nys.step() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timers = gp.timers()
+    gp.timing(False)
+    nys_sps = a.steps / (t1 - t0)
+
+    # ---- plain CG NGD (same start, power-method damping, maxit = P) ----
+    cg = NGD(prob, theta0, solver="cg", rtol=rtol, seed=a.seed)
+    cg.step()  # warmup
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    creps = [cg.step() for _ in range(a.cg_steps)]
+    torch.cuda.synchronize()
+    c1 = time.perf_counter()
+    cg_sps = a.cg_steps / (c1 - c0)
+
+    # ---- roofline of the one-pass Gramian matvec kernel ----
+    n_mv, ms_mv = timers["matvec_rows"]
+    avg_ms = ms_mv / max(n_mv, 1)
+    elem = 8 if prob.dtype == "f64" else 4
+    alg_bytes = N * P * elem + 2 * P * 8
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    phases = {k: {"launches": n, "avg_ms": (ms / n if n else 0.0), "ms_per_step": ms / a.steps}
+              for k, (n, ms) in timers.items()}
+
+    line = {
+        "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
+        "value": nys_sps,
+        "unit": "NGD steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1000.0 / nys_sps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prob.dtype == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}", "P": P, "N": N, "ell": prob.ell,
+                   "sketch_dtype": prob.sketch_dtype},
+        "plain_cg": {"value": cg_sps, "unit": "NGD steps/s", "steps": a.cg_steps,
+                     "mean_cg_iters": float(np.mean([r.iters for r in creps])),
+                     "converged": all(r.converged for r in creps)},
+        "nystrom_mean_pcg_iters": float(np.mean([r.iters for r in reps])),
+        "nystrom_converged": all(r.converged for r in reps),
+        "speedup_vs_plain_cg": nys_sps / cg_sps,
+        "matvec_gbs": achieved,
+        "loss_first_last": [reps[0].loss, reps[-1].loss_new],
+        "phases": phases,
+        "roofline": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv},
+    }
+    # release the library handles while the runtime is alive
+    torch.cuda.synchronize()
+    nys.gp.close()
+    cg.gp.close()
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(a.config, a.seed, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

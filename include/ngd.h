@@ -1,0 +1,227 @@
+/*
+ * ngd.h -- C ABI of libngd: the Gramian hot path of Nystrom-preconditioned matrix-free natural
+ * gradient descent for PINNs (arXiv 2505.11638), on one AMD MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - "device" pointers are HIP device allocations owned by the caller; the library never frees or
+ *   retains them beyond the call. "host" pointers are ordinary host memory.
+ * - Every call enqueues its work on `stream` (a hipStream_t passed as void*, NULL = the default
+ *   stream) and returns without waiting, unless its comment says it synchronises (calls that
+ *   return scalars to host memory do).
+ * - Working precision ("dtype") is fixed per problem handle: NGD_F64 or NGD_F32. Buffers typed
+ *   "dtype" hold values of that type; buffers typed "double" are always FP64.
+ * - Matrices are row-major with an explicit leading dimension (elements between consecutive rows).
+ *   A set of k vectors of length P is stored as k rows: vector j starts at base + j*ld.
+ * - Every call returns an ngd_status. Argument errors are detected on the host before anything is
+ *   enqueued and leave all outputs untouched; ngd_last_error() then describes the problem. Nothing
+ *   is thrown across the ABI. The calls are not thread-safe on one handle.
+ *
+ * Notation (paper -> here): parameters p -> P, collocation points q -> N, Jacobian J_theta F -> J_w
+ * (rows weighted by sqrt(w_r)), damping mu -> lambda, sketch size ell, test matrix Omega.
+ */
+#ifndef NGD_H
+#define NGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NGD_OK = 0,
+  NGD_ERR_INVALID = 1,        /* bad argument (null pointer, size, leading dimension, dtype) */
+  NGD_ERR_OOM = 2,            /* workspace allocation failed */
+  NGD_ERR_NOT_PD = 3,         /* numerical failure in the FP64 sketch core */
+  NGD_ERR_BREAKDOWN = 4,      /* PCG met p^T (G + lambda I) p <= 0 or a non-finite value */
+  NGD_ERR_NOT_CONVERGED = 5,  /* PCG stopped at maxit above the tolerance (outputs are valid) */
+  NGD_ERR_HIP = 6             /* a HIP runtime call failed */
+} ngd_status;
+
+typedef enum { NGD_F64 = 0, NGD_F32 = 1, NGD_BF16 = 2 } ngd_dtype;
+
+/* PDE of the residual rows (Section 5.1.1 eq. energy_poisson, Section 5.1.2 eq. heat_energy). */
+typedef enum { NGD_PDE_POISSON = 0, NGD_PDE_HEAT = 1 } ngd_pde;
+
+/* Kind of one collocation row. */
+typedef enum { NGD_ROW_INTERIOR = 0, NGD_ROW_BOUNDARY = 1, NGD_ROW_INITIAL = 2 } ngd_row_kind;
+
+/*
+ * One PINN least-squares problem: a tanh MLP (Section 2.3) and fixed quadrature data.
+ *   widths[0] = d (input dimension), widths[1..n_layers-1] hidden widths, widths[n_layers] = 1.
+ *   Poisson: all d inputs are space; interior residual = Laplace(u) + f.
+ *   Heat:    inputs are (x_1..x_{d-1}, t); interior residual = u_t - Laplace_x(u) - f.
+ *   Boundary and initial rows: residual = u - g. Weighted residual r_w = sqrt(w) * residual.
+ * Parameter vector theta (length P): [W_1, b_1, ..., W_L+1, b_L+1], each W row-major (out x in).
+ * Limits: 1 <= n_layers <= 8, 1 <= d <= 6, widths <= 256, N >= 1.
+ */
+typedef struct {
+  int32_t n_layers;        /* number of affine layers (hidden layers + 1) */
+  const int32_t* widths;   /* host, n_layers + 1 entries; copied at create */
+  int32_t pde;             /* ngd_pde */
+  int32_t dtype;           /* NGD_F64 or NGD_F32: precision of theta, X, w, f, g, J_w, r_w */
+  int64_t n_rows;          /* N */
+  const void* X;           /* device, N x d row-major (ld = d), dtype */
+  const void* w;           /* device, N, dtype: quadrature weights (> 0) */
+  const void* f;           /* device, N, dtype: source on interior rows */
+  const void* g;           /* device, N, dtype: target on boundary / initial rows */
+  const int8_t* row_kind;  /* device, N: ngd_row_kind */
+  int32_t max_ell;         /* largest sketch size that will be used with this handle (>= 1) */
+} ngd_problem_desc;
+
+typedef struct ngd_problem ngd_problem;  /* opaque; owns device workspace only */
+
+/* The linear operator J_w at a fixed theta. J must be the stored Jacobian (N x P, leading
+ * dimension ldJ >= P, dtype) produced by ngd_residual_jacobian for `theta`. */
+typedef struct {
+  const void* theta;       /* device, P, dtype (kept for reference; not read by the stored path) */
+  const void* J;           /* device, N x ldJ, dtype; P <= ldJ <= ngd_recommended_ld */
+  int64_t ldJ;
+} ngd_operator;
+
+/* Create a handle: copies the descriptor (pointers are kept, data is not copied) and allocates the
+ * workspace for N, P and max_ell. Returns NGD_ERR_INVALID, NGD_ERR_OOM or NGD_ERR_HIP on failure. */
+ngd_status ngd_problem_create(const ngd_problem_desc* desc, ngd_problem** out);
+ngd_status ngd_problem_destroy(ngd_problem* h);
+/* P = sum_l (n_l n_{l-1} + n_l) (Section 2.3); -1 for a null handle. */
+int64_t ngd_num_params(const ngd_problem* h);
+/* Recommended leading dimension of J_w and of P-vector sets: P rounded up to 64 elements. */
+int64_t ngd_recommended_ld(const ngd_problem* h);
+/* Bytes of device workspace owned by the handle. */
+int64_t ngd_workspace_bytes(const ngd_problem* h);
+/* Thread-local description of the last non-OK status (empty string if none). */
+const char* ngd_last_error(void);
+
+/*
+ * Residuals, Jacobian, gradient and loss at theta (Section 4.1.1 "Computing the full Gramian";
+ * Theorem thm:matfree, eq. G_matrixfree; Alg. 1 first step).
+ *   theta : device, P, dtype.
+ *   r_w   : device, N, dtype, out: sqrt(w_r) * residual_r.
+ *   J_w   : device, N x ldJ, dtype, out: d r_w / d theta (columns P..ldJ-1 are set to 0). ldJ >= P.
+ *   grad  : device, P, double, out (nullable): J_w^T r_w = grad L. Requires J_w.
+ *   loss  : device, 1 double, out (nullable): L = 1/2 sum r_w^2.
+ * J_w may be NULL to evaluate residuals and loss only (forward pass, no Jacobian); grad must then
+ * be NULL.
+ */
+ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, void* J_w, int64_t ldJ,
+                                 double* grad, double* loss, void* stream);
+
+/*
+ * Damped Gramian products Y[j] = (J_w^T J_w + lambda I) V[j] for j < k (eq. G_matrixfree,
+ * eq. regularized_ng; "Precompute Jacobian only" strategy of Section 4.1.2). k = 1 is the
+ * conjugate-gradient matvec (one pass over J_w); k > 1 is the block product of the sketch.
+ *   V : device, k x ldV, dtype (vector j at V + j*ldV). Y : device, k x ldY, dtype, out.
+ *   lambda >= 0. Y must not alias V or J_w.
+ */
+ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void* V, int64_t ldV,
+                              int64_t k, double lambda, void* Y, int64_t ldY, void* stream);
+
+/*
+ * Counter-based standard normal test matrix (Philox4x32-10 of Salmon et al. SC'11 with Box-Muller):
+ * row j of `omega` (j < ell) is column j of the P x ell matrix Omega of eq. nystrom_approx.
+ *   omega : device, ell x ld, dtype, out. ld >= P.
+ */
+ngd_status ngd_gaussian_omega(ngd_problem* h, uint64_t seed, uint64_t counter, int64_t ell,
+                              void* omega, int64_t ld, void* stream);
+
+typedef struct {
+  double nu;        /* shift added to the ell x ell core (0 if none was needed) */
+  double lam1;      /* largest Nystrom eigenvalue */
+  double lam_ell;   /* smallest (ell-th) Nystrom eigenvalue */
+  int32_t rank_z;   /* numerical rank of the sketch J_w Omega */
+  int32_t rank;     /* number of nonzero Nystrom eigenvalues kept */
+} ngd_nystrom_info;
+
+/*
+ * Randomized Nystrom approximation of the undamped Gramian G = J_w^T J_w (eq. nystrom_approx;
+ * Alg. 4 first step; Alg. 6): G_nys = U diag(lam_hat) U^T.
+ *   ell           : sketch size, 1 <= ell <= min(max_ell, P).
+ *   omega         : device, ell x ldO, dtype (row j = column j of Omega), or NULL to generate it
+ *                   on the device from (seed, counter) exactly as ngd_gaussian_omega does.
+ *   sketch_dtype  : precision of the two N x P x ell products: NGD_F64 (dtype F64 only), NGD_F32
+ *                   (dtype F32) or NGD_BF16 (dtype F32; BF16 inputs, FP32 accumulation). The
+ *                   ell x ell core always runs in FP64.
+ *   U             : device, ell x ldU, dtype, out: row i = eigenvector i (unit norm, orthogonal),
+ *                   rows for dropped (zero) eigenvalues are zero. ldU >= P.
+ *   lam_hat       : device, ell doubles, out: eigenvalues, descending, >= 0.
+ *   info          : host, nullable. If non-NULL the call synchronises `stream` and fills it.
+ */
+ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed,
+                              uint64_t counter, const void* omega, int64_t ldO, int32_t sketch_dtype,
+                              void* U, int64_t ldU, double* lam_hat, ngd_nystrom_info* info,
+                              void* stream);
+
+/* Nystrom preconditioner of eq. nystrom_inverse for G + mu I with mu = the solve's lambda:
+ * P^{-1} v = U (Lambda + mu I)^{-1} U^T v + (lam_hat[ell-1] + mu)^{-1} (v - U U^T v). */
+typedef struct {
+  const void* U;           /* device, ell x ldU, dtype (as written by ngd_nystrom_sketch) */
+  int64_t ldU;
+  const double* lam_hat;   /* device, ell, descending */
+  int64_t ell;
+} ngd_precond;
+
+typedef struct {
+  int64_t iters;           /* iterations performed */
+  double rel_res;          /* ||r_k|| / ||g|| of the recursively updated residual */
+  int32_t converged;       /* rel_res <= rtol */
+  int32_t breakdown;       /* p^T (G + lambda I) p <= 0 or non-finite */
+} ngd_pcg_info;
+
+/*
+ * Solve (J_w^T J_w + lambda I) d = g by conjugate gradients, preconditioned by eq. nystrom_inverse
+ * when prec != NULL, plain CG otherwise (Alg. 3: pCG(G_fun + mu Id, g, maxit, P_fun)).
+ * x_0 = 0; stops when ||r_k||_2 <= rtol ||g||_2 or after maxit iterations.
+ *   g : device, P doubles. d : device, P doubles, out. lambda > 0, rtol >= 0, maxit >= 0.
+ *   info : host, required. The call synchronises `stream` (it polls the device-side convergence
+ *          flag every few iterations). Returns NGD_ERR_NOT_CONVERGED if maxit was reached first and
+ *          NGD_ERR_BREAKDOWN on breakdown; d holds the last iterate in both cases.
+ */
+ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
+                         const ngd_precond* prec, double rtol, int64_t maxit, double* d,
+                         ngd_pcg_info* info, void* stream);
+
+/*
+ * Largest-eigenvalue estimate of J_w^T J_w by the power method (Section 4.3: 2-4 iterations):
+ * v <- G v / ||G v||, returning the Rayleigh quotient v^T G v of the last normalised iterate.
+ *   v0 : device, P doubles (nonzero start vector; not modified). lam1 : host, out. Synchronises.
+ */
+ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const double* v0, int32_t iters,
+                                double* lam1, void* stream);
+
+/*
+ * Armijo backtracking along theta - alpha d (Alg. 1, Linesearch; Section 4.4): alpha = 1, 1/2, ...
+ * until L(theta - alpha d) <= loss0 - c1 alpha grad^T d, at most max_halvings halvings; alpha = 0 if
+ * none is accepted. Writes theta_out = theta - alpha d (dtype; may alias theta).
+ *   d, grad : device, P doubles. alpha, loss_new : host, out. Synchronises.
+ */
+ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, const double* grad,
+                           double loss0, double c1, int32_t max_halvings, void* theta_out,
+                           double* alpha, double* loss_new, void* stream);
+
+/*
+ * Kernel timers (measurement support, not part of the method). When enabled, the library records a
+ * HIP event pair on the call's stream around every launch of the timed kernels and accumulates the
+ * elapsed times, so a benchmark can read the average duration of, e.g., the one-pass Gramian matvec
+ * kernel while the NGD loop runs.
+ */
+typedef enum {
+  NGD_TIMER_MATVEC_ROWS = 0,      /* one-pass J^T (J v) kernel (PCG iteration, power method, matvec) */
+  NGD_TIMER_RESIDUAL_JACOBIAN = 1,/* residual + Jacobian kernel (Jacobian-writing launches only) */
+  NGD_TIMER_SKETCH_Z = 2,         /* Z = J_w Omega contraction */
+  NGD_TIMER_SKETCH_W = 3,         /* J_w^T Q contraction */
+  NGD_TIMER_CORE = 4,             /* FP64 ell x ell core (both eigendecompositions and small products) */
+  NGD_TIMER_PRECOND = 5,          /* preconditioner application inside PCG */
+  NGD_NUM_TIMERS = 6
+} ngd_timer_id;
+
+/* enable != 0 turns timing on and resets all counters; enable == 0 turns it off. */
+ngd_status ngd_timing_enable(ngd_problem* h, int32_t enable);
+/* Launch count and total milliseconds of timer `id`; waits for the recorded events. */
+ngd_status ngd_timing_read(ngd_problem* h, int32_t id, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NGD_H */

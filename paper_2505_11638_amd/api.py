@@ -1,0 +1,202 @@
+"""Thin Python binding of libngd with the C ABI's names. PyTorch supplies device memory and streams;
+every computation runs in the library's HIP kernels.
+
+The functions take torch tensors on a ROCm device, check dtypes / shapes / contiguity, and pass
+raw pointers and the current stream to the corresponding `ngd_*` entry point.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_TORCH = {L.NGD_F64: torch.float64, L.NGD_F32: torch.float32}
+_DTYPE = {"f64": L.NGD_F64, "f32": L.NGD_F32, "bf16": L.NGD_BF16}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+@dataclasses.dataclass
+class NystromResult:
+    U: torch.Tensor          # (ell, ldU), rows = eigenvectors
+    lam_hat: torch.Tensor    # (ell,) float64 descending
+    info: dict
+
+
+@dataclasses.dataclass
+class PcgResult:
+    d: torch.Tensor          # (P,) float64
+    iters: int
+    rel_res: float
+    converged: bool
+    breakdown: bool
+    status: int
+
+
+class Problem:
+    """A PINN least-squares problem bound to a libngd handle.
+
+    `data` needs attributes widths, pde, X (N x d), w, f, g, kind (as in `workloads.Problem`); they are
+    copied to the device in the working precision `dtype` ("f64" or "f32")."""
+
+    def __init__(self, data, dtype: Optional[str] = None, max_ell: Optional[int] = None, device="cuda"):
+        self.lib = L.load()
+        self.dtype_name = dtype or data.dtype
+        self.dtype = _DTYPE[self.dtype_name]
+        self.tdtype = _TORCH[self.dtype]
+        self.device = torch.device(device)
+        self.widths = tuple(int(v) for v in data.widths)
+        self.pde = int(data.pde)
+        to = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t, device=self.device)
+        self.X = to(data.X, self.tdtype)
+        self.w = to(data.w, self.tdtype)
+        self.f = to(data.f, self.tdtype)
+        self.g = to(data.g, self.tdtype)
+        self.kind = to(data.kind, torch.int8)
+        self.N = int(self.X.shape[0])
+        self._widths_c = (C.c_int32 * len(self.widths))(*self.widths)
+        desc = L.ProblemDesc(len(self.widths) - 1, self._widths_c, self.pde, self.dtype, self.N,
+                             self.X.data_ptr(), self.w.data_ptr(), self.f.data_ptr(), self.g.data_ptr(),
+                             self.kind.data_ptr(), int(max_ell or getattr(data, "ell", 1)))
+        h = C.c_void_p()
+        L.check(self.lib.ngd_problem_create(C.byref(desc), C.byref(h)), "ngd_problem_create")
+        self.h = h
+        self.P = int(self.lib.ngd_num_params(h))
+        self.ld = int(self.lib.ngd_recommended_ld(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ngd_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        import sys
+        if sys.is_finalizing():  # the HIP runtime may already be torn down: leave it to process exit
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ----------------------------------------------------------------------------------
+    def theta(self, values) -> torch.Tensor:
+        return torch.as_tensor(np.asarray(values), dtype=self.tdtype, device=self.device).contiguous()
+
+    def new_jacobian(self) -> torch.Tensor:
+        return torch.empty((self.N, self.ld), dtype=self.tdtype, device=self.device)
+
+    def _op(self, J: torch.Tensor, theta: Optional[torch.Tensor] = None) -> L.Operator:
+        _need(J, self.tdtype, "J")
+        if J.dim() != 2 or J.shape[0] != self.N or J.stride(1) != 1:
+            raise ValueError("J must be an N x ld row-major tensor")
+        return L.Operator(None if theta is None else theta.data_ptr(), J.data_ptr(), J.stride(0))
+
+    # -- entry points -------------------------------------------------------------------------------
+    def residual_jacobian(self, theta: torch.Tensor, J: Optional[torch.Tensor] = None, want_grad=True,
+                          want_loss=True):
+        """ngd_residual_jacobian: returns (r_w, J or None, grad or None, loss tensor or None)."""
+        _need(theta, self.tdtype, "theta")
+        r = torch.empty(self.N, dtype=self.tdtype, device=self.device)
+        grad = torch.empty(self.P, dtype=torch.float64, device=self.device) if (want_grad and J is not None) else None
+        loss = torch.empty(1, dtype=torch.float64, device=self.device) if want_loss else None
+        ldJ = J.stride(0) if J is not None else 0
+        if J is not None:
+            _need(J, self.tdtype, "J")
+        L.check(self.lib.ngd_residual_jacobian(self.h, _ptr(theta), _ptr(r), _ptr(J), ldJ, _ptr(grad), _ptr(loss),
+                                               _stream()), "ngd_residual_jacobian")
+        return r, J, grad, loss
+
+    def gramian_matvec(self, J: torch.Tensor, V: torch.Tensor, lam: float) -> torch.Tensor:
+        """ngd_gramian_matvec: V (k, ld) or (P,) in the working dtype; returns Y of the same shape."""
+        _need(V, self.tdtype, "V")
+        vec = V.dim() == 1
+        V2 = V.reshape(1, -1) if vec else V
+        Y = torch.empty_like(V2)
+        L.check(self.lib.ngd_gramian_matvec(self.h, C.byref(self._op(J)), _ptr(V2), V2.stride(0), V2.shape[0],
+                                            float(lam), _ptr(Y), Y.stride(0), _stream()), "ngd_gramian_matvec")
+        return Y.reshape(-1) if vec else Y
+
+    def gaussian_omega(self, seed: int, counter: int, ell: int) -> torch.Tensor:
+        out = torch.zeros((ell, self.ld), dtype=self.tdtype, device=self.device)
+        L.check(self.lib.ngd_gaussian_omega(self.h, seed, counter, ell, _ptr(out), self.ld, _stream()),
+                "ngd_gaussian_omega")
+        return out
+
+    def nystrom_sketch(self, J: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
+                       omega: Optional[torch.Tensor] = None, sketch_dtype: Optional[str] = None,
+                       want_info=True) -> NystromResult:
+        sd = _DTYPE[sketch_dtype or ("f64" if self.dtype == L.NGD_F64 else "f32")]
+        U = torch.empty((ell, self.ld), dtype=self.tdtype, device=self.device)
+        lam = torch.empty(ell, dtype=torch.float64, device=self.device)
+        info = L.NystromInfo()
+        ldO = 0
+        if omega is not None:
+            _need(omega, self.tdtype, "omega")
+            ldO = omega.stride(0)
+        L.check(self.lib.ngd_nystrom_sketch(self.h, C.byref(self._op(J)), ell, seed, counter, _ptr(omega), ldO, sd,
+                                            _ptr(U), U.stride(0), _ptr(lam), C.byref(info) if want_info else None,
+                                            _stream()), "ngd_nystrom_sketch")
+        d = {k: getattr(info, k) for k, _ in L.NystromInfo._fields_} if want_info else {}
+        return NystromResult(U, lam, d)
+
+    def pcg_solve(self, J: torch.Tensor, g: torch.Tensor, lam: float, precond: Optional[NystromResult] = None,
+                  rtol: float = 1e-6, maxit: int = 1000, raise_on_fail=False) -> PcgResult:
+        _need(g, torch.float64, "g")
+        d = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        info = L.PcgInfo()
+        pc = None
+        if precond is not None:
+            pc = L.Precond(precond.U.data_ptr(), precond.U.stride(0), precond.lam_hat.data_ptr(),
+                           precond.lam_hat.numel())
+        st = self.lib.ngd_pcg_solve(self.h, C.byref(self._op(J)), _ptr(g), float(lam),
+                                    C.byref(pc) if pc is not None else None, float(rtol), int(maxit), _ptr(d),
+                                    C.byref(info), _stream())
+        allow = () if raise_on_fail else (L.NGD_ERR_NOT_CONVERGED, L.NGD_ERR_BREAKDOWN)
+        L.check(st, "ngd_pcg_solve", allow)
+        return PcgResult(d, int(info.iters), float(info.rel_res), bool(info.converged), bool(info.breakdown), st)
+
+    def power_lambda_max(self, J: torch.Tensor, v0: torch.Tensor, iters: int = 4) -> float:
+        _need(v0, torch.float64, "v0")
+        out = C.c_double()
+        L.check(self.lib.ngd_power_lambda_max(self.h, C.byref(self._op(J)), _ptr(v0), iters, C.byref(out),
+                                              _stream()), "ngd_power_lambda_max")
+        return out.value
+
+    def timing(self, enable: bool):
+        L.check(self.lib.ngd_timing_enable(self.h, 1 if enable else 0), "ngd_timing_enable")
+
+    def timers(self) -> dict:
+        """{name: (launches, total_ms)} of the library's kernel timers."""
+        out = {}
+        for name, tid in L.TIMERS.items():
+            n, ms = C.c_int64(), C.c_double()
+            L.check(self.lib.ngd_timing_read(self.h, tid, C.byref(n), C.byref(ms)), "ngd_timing_read")
+            out[name] = (int(n.value), float(ms.value))
+        return out
+
+    def line_search(self, theta: torch.Tensor, d: torch.Tensor, grad: torch.Tensor, loss0: float, c1=1e-4,
+                    max_halvings=30, theta_out: Optional[torch.Tensor] = None):
+        theta_out = torch.empty_like(theta) if theta_out is None else theta_out
+        a, ln = C.c_double(), C.c_double()
+        L.check(self.lib.ngd_line_search(self.h, _ptr(theta), _ptr(d), _ptr(grad), float(loss0), float(c1),
+                                         int(max_halvings), _ptr(theta_out), C.byref(a), C.byref(ln), _stream()),
+                "ngd_line_search")
+        return theta_out, a.value, ln.value

@@ -1,0 +1,573 @@
+// C ABI of libngd (include/ngd.h): argument validation, workspace, and the host-side sequencing of
+// the device kernels for each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace ngd {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace ngd
+
+using namespace ngd;
+
+struct ngd_problem {
+  NetDesc net;
+  int dtype;
+  int64_t N, P, ldP;
+  int max_ell;
+  const void *X, *w, *f, *g;
+  const int8_t* kind;
+  int tp;            // rows per residual workgroup
+  int res_blocks;    // residual workgroups per parameter vector
+  int nwg;           // one-pass matvec workgroups
+  size_t elem;
+  // device workspace (one allocation)
+  void* base;
+  size_t bytes;
+  void* partial;     // nwg x ldP, dtype
+  double* tsq;       // nwg
+  double* loss_part; // res_blocks * kTrials
+  double* grad_work; // gradient_chunks(N) x P
+  double* vtmp[4];   // P-vectors (FP64)
+  double* scal;      // small scalars / dot workspace (128 doubles)
+  double* pcg_r;
+  double* pcg_z;
+  double* pcg_p[2];
+  double* pcg_s;     // max_ell
+  double* pcg_part;  // block partials (P / 256)
+  PcgState* pcg_st;
+  void* omega;       // max_ell x ldP, dtype
+  void* Z;           // N x max_ell, dtype
+  void* Q;           // N x max_ell, dtype
+  void* Bt;          // max_ell x ldP, dtype
+  double* M;         // ell x ell
+  double* Ev;        // ell x ell eigenvectors (rows)
+  double* F;         // ell x ell
+  double* evals;     // ell
+  void* eigw;        // eig workspace
+  void* trial;       // kTrials x ldP, dtype (line search)
+  double* alphas;    // kTrials
+  double* losses;    // kTrials
+  // pinned host staging
+  void* host;
+  // kernel timers
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double t_ms[NGD_NUM_TIMERS] = {};
+  int64_t t_n[NGD_NUM_TIMERS] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(ngd_problem* h) {
+  if (!h->ev_free.empty()) {
+    hipEvent_t e = h->ev_free.back();
+    h->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ngd_status flush_timers(ngd_problem* h) {
+  for (auto& p : h->ev_pending) {
+    NGD_HIP_TRY(hipEventSynchronize(p.second.second));
+    float ms = 0.f;
+    NGD_HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    h->t_ms[p.first] += ms;
+    h->t_n[p.first] += 1;
+    h->ev_free.push_back(p.second.first);
+    h->ev_free.push_back(p.second.second);
+  }
+  h->ev_pending.clear();
+  return NGD_OK;
+}
+
+// Run `fn` (which enqueues one kernel sequence on s); when timing is on, bracket it with events.
+template <typename F>
+ngd_status timed(ngd_problem* h, int id, hipStream_t s, F&& fn) {
+  if (!h->timing || id < 0) return fn();
+  if (h->ev_pending.size() > 4096) {
+    ngd_status st = flush_timers(h);
+    if (st != NGD_OK) return st;
+  }
+  hipEvent_t a = take_event(h), b = take_event(h);
+  if (!a || !b) {
+    set_error("hipEventCreate failed");
+    return NGD_ERR_HIP;
+  }
+  NGD_HIP_TRY(hipEventRecord(a, s));
+  ngd_status st = fn();
+  NGD_HIP_TRY(hipEventRecord(b, s));
+  h->ev_pending.push_back({id, {a, b}});
+  return st;
+}
+
+}  // namespace
+
+namespace {
+
+constexpr int kTrials = 8;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define NGD_CHECK(cond, msg)          \
+  do {                                \
+    if (!(cond)) {                    \
+      ::ngd::set_error(msg);          \
+      return NGD_ERR_INVALID;         \
+    }                                 \
+  } while (0)
+
+#define NGD_TRY(expr)                 \
+  do {                                \
+    ngd_status st_ = (expr);          \
+    if (st_ != NGD_OK) return st_;    \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+ngd_status check_op(const ngd_problem* h, const ngd_operator* op) {
+  NGD_CHECK(op != nullptr, "operator is NULL");
+  NGD_CHECK(op->J != nullptr, "operator has no stored Jacobian (recompute mode is not available in this entry point)");
+  NGD_CHECK(op->ldJ >= h->P, "ldJ < P");
+  NGD_CHECK(op->ldJ <= h->ldP, "ldJ must not exceed ngd_recommended_ld");
+  const int vn = h->dtype == NGD_F64 ? 2 : 4;
+  NGD_CHECK(op->ldJ % vn == 0, "ldJ must be a multiple of 16 bytes / element size");
+  NGD_CHECK(aligned16(op->J), "J must be 16-byte aligned");
+  NGD_CHECK(gram_rows_supported(h->dtype, op->ldJ), "ldJ too large for the one-pass matvec");
+  return NGD_OK;
+}
+
+// y = (J^T J + lambda I) v, all FP64 P-vectors
+ngd_status gram_apply(ngd_problem* h, const ngd_operator* op, const double* v, double lambda, double* y, hipStream_t s) {
+  NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
+    return launch_gram_rows(h->dtype, op->J, op->ldJ, h->N, h->P, v, h->partial, h->tsq, h->nwg, s);
+  }));
+  return launch_gram_reduce(h->dtype, h->partial, h->nwg, op->ldJ, h->P, v, lambda, y, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ngd_last_error(void) { return g_last_error.c_str(); }
+
+ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
+  NGD_CHECK(d != nullptr && out != nullptr, "NULL argument");
+  *out = nullptr;
+  NGD_CHECK(d->n_layers >= 1 && d->n_layers <= kMaxLayers, "n_layers out of range [1, 8]");
+  NGD_CHECK(d->widths != nullptr, "widths is NULL");
+  NGD_CHECK(d->pde == NGD_PDE_POISSON || d->pde == NGD_PDE_HEAT, "unknown pde");
+  NGD_CHECK(d->dtype == NGD_F64 || d->dtype == NGD_F32, "dtype must be NGD_F64 or NGD_F32");
+  NGD_CHECK(d->n_rows >= 1, "n_rows must be >= 1");
+  NGD_CHECK(d->X && d->w && d->f && d->g && d->row_kind, "problem data pointer is NULL");
+  NGD_CHECK(d->max_ell >= 1, "max_ell must be >= 1");
+  NetDesc net{};
+  net.n_layers = d->n_layers;
+  int64_t off = 0;
+  int maxw = 0;
+  for (int l = 0; l <= d->n_layers; ++l) {
+    NGD_CHECK(d->widths[l] >= 1 && d->widths[l] <= kMaxWidth, "widths out of range [1, 256]");
+    net.widths[l] = d->widths[l];
+    maxw = std::max(maxw, d->widths[l]);
+  }
+  NGD_CHECK(d->widths[d->n_layers] == 1, "the output width must be 1");
+  for (int l = 0; l < d->n_layers; ++l) {
+    net.woff[l] = off;
+    off += (int64_t)net.widths[l] * net.widths[l + 1];
+    net.boff[l] = off;
+    off += net.widths[l + 1];
+  }
+  net.P = off;
+  net.d = d->widths[0];
+  NGD_CHECK(net.d <= kMaxDim, "input dimension must be <= 6");
+  NGD_CHECK(d->pde != NGD_PDE_HEAT || net.d >= 2, "heat needs at least one space and the time input");
+  net.nS = d->pde == NGD_PDE_POISSON ? net.d : net.d - 1;
+  net.has_t = d->pde == NGD_PDE_HEAT ? 1 : 0;
+  net.C = 1 + net.nS + 1 + net.has_t;
+  net.pde = d->pde;
+  net.max_width = maxw;
+
+  ngd_problem* h = new ngd_problem();
+  h->net = net;
+  h->dtype = d->dtype;
+  h->N = d->n_rows;
+  h->P = net.P;
+  h->ldP = (int64_t)align_up((size_t)net.P, 64);
+  h->max_ell = (int)std::min<int64_t>(d->max_ell, net.P);
+  h->X = d->X;
+  h->w = d->w;
+  h->f = d->f;
+  h->g = d->g;
+  h->kind = d->row_kind;
+  h->elem = d->dtype == NGD_F64 ? 8 : 4;
+  h->tp = residual_block_rows(net, d->dtype);
+  h->res_blocks = (int)((h->N + h->tp - 1) / h->tp);
+  h->nwg = gram_rows_grid(d->dtype, h->N, h->P);
+
+  const int64_t N = h->N, P = h->P, ldP = h->ldP, L = h->max_ell;
+  const size_t e = h->elem;
+  std::vector<std::pair<void**, size_t>> plan;
+  plan.push_back({&h->partial, (size_t)h->nwg * ldP * e});
+  plan.push_back({(void**)&h->tsq, sizeof(double) * 1024});
+  plan.push_back({(void**)&h->loss_part, sizeof(double) * (size_t)h->res_blocks * kTrials});
+  plan.push_back({(void**)&h->grad_work, sizeof(double) * (size_t)gradient_chunks(N) * P});
+  for (int i = 0; i < 4; ++i) plan.push_back({(void**)&h->vtmp[i], sizeof(double) * ldP});
+  plan.push_back({(void**)&h->scal, sizeof(double) * 256});
+  plan.push_back({(void**)&h->pcg_r, sizeof(double) * ldP});
+  plan.push_back({(void**)&h->pcg_z, sizeof(double) * ldP});
+  plan.push_back({(void**)&h->pcg_p[0], sizeof(double) * ldP});
+  plan.push_back({(void**)&h->pcg_p[1], sizeof(double) * ldP});
+  plan.push_back({(void**)&h->pcg_s, sizeof(double) * (size_t)L});
+  plan.push_back({(void**)&h->pcg_part, sizeof(double) * (size_t)((P + 255) / 256 + 64)});
+  plan.push_back({(void**)&h->pcg_st, sizeof(PcgState)});
+  plan.push_back({&h->omega, (size_t)L * ldP * e});
+  plan.push_back({&h->Z, (size_t)N * L * e});
+  plan.push_back({&h->Q, (size_t)N * L * e});
+  plan.push_back({&h->Bt, (size_t)L * ldP * e});
+  plan.push_back({(void**)&h->M, sizeof(double) * (size_t)L * L});
+  plan.push_back({(void**)&h->Ev, sizeof(double) * (size_t)L * L});
+  plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
+  plan.push_back({(void**)&h->evals, sizeof(double) * (size_t)L});
+  plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
+  plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
+  plan.push_back({(void**)&h->alphas, sizeof(double) * kTrials});
+  plan.push_back({(void**)&h->losses, sizeof(double) * kTrials});
+  size_t total = 0;
+  for (auto& p : plan) total += align_up(p.second, 256);
+  void* base = nullptr;
+  if (hipMalloc(&base, total) != hipSuccess) {
+    delete h;
+    set_error("hipMalloc of the workspace failed");
+    return NGD_ERR_OOM;
+  }
+  if (hipMemset(base, 0, total) != hipSuccess) {
+    (void)hipFree(base);
+    delete h;
+    set_error("hipMemset of the workspace failed");
+    return NGD_ERR_HIP;
+  }
+  size_t o = 0;
+  for (auto& p : plan) {
+    *p.first = static_cast<char*>(base) + o;
+    o += align_up(p.second, 256);
+  }
+  h->base = base;
+  h->bytes = total;
+  if (hipHostMalloc(&h->host, 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(base);
+    delete h;
+    set_error("hipHostMalloc failed");
+    return NGD_ERR_OOM;
+  }
+  *out = h;
+  return NGD_OK;
+}
+
+ngd_status ngd_problem_destroy(ngd_problem* h) {
+  if (h == nullptr) return NGD_OK;
+  (void)flush_timers(h);
+  for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
+  (void)hipFree(h->base);
+  (void)hipHostFree(h->host);
+  delete h;
+  return NGD_OK;
+}
+
+int64_t ngd_num_params(const ngd_problem* h) { return h ? h->P : -1; }
+int64_t ngd_recommended_ld(const ngd_problem* h) { return h ? h->ldP : -1; }
+int64_t ngd_workspace_bytes(const ngd_problem* h) { return h ? (int64_t)h->bytes : -1; }
+
+ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, void* J_w, int64_t ldJ, double* grad,
+                                 double* loss, void* stream) {
+  NGD_CHECK(h != nullptr && theta != nullptr && r_w != nullptr, "NULL argument");
+  NGD_CHECK(grad == nullptr || J_w != nullptr, "grad requires J_w");
+  if (J_w != nullptr) NGD_CHECK(ldJ >= h->P, "ldJ < P");
+  hipStream_t s = S(stream);
+  NGD_TRY(timed(h, J_w ? NGD_TIMER_RESIDUAL_JACOBIAN : -1, s, [&] {
+    return launch_residual_jacobian(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, r_w, J_w, ldJ,
+                                    h->loss_part, 0, 1, s, nullptr);
+  }));
+  if (loss != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, 1, 0.5, loss, s));
+  if (grad != nullptr) NGD_TRY(launch_gradient(h->dtype, J_w, ldJ, h->N, h->P, r_w, h->grad_work, grad, s));
+  return NGD_OK;
+}
+
+ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void* V, int64_t ldV, int64_t k,
+                              double lambda, void* Y, int64_t ldY, void* stream) {
+  NGD_CHECK(h != nullptr && V != nullptr && Y != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(k >= 1, "k must be >= 1");
+  NGD_CHECK(k == 1 || (ldV >= h->P && ldY >= h->P), "ldV, ldY must be >= P");
+  NGD_CHECK(lambda >= 0.0, "lambda must be >= 0");
+  NGD_CHECK(V != Y, "Y must not alias V");
+  hipStream_t s = S(stream);
+  const int64_t P = h->P;
+  if (k == 1) {
+    NGD_TRY(launch_cast(h->dtype, V, NGD_F64, h->vtmp[0], P, s));
+    NGD_TRY(gram_apply(h, op, h->vtmp[0], lambda, h->vtmp[1], s));
+    return launch_cast(NGD_F64, h->vtmp[1], h->dtype, Y, P, s);
+  }
+  // block product through the sketch buffers, max_ell columns at a time
+  const int gt = h->dtype == NGD_F64 ? G_F64 : G_F32;
+  for (int64_t c0 = 0; c0 < k; c0 += h->max_ell) {
+    const int64_t kc = std::min<int64_t>(h->max_ell, k - c0);
+    const char* Vc = static_cast<const char*>(V) + (size_t)c0 * ldV * h->elem;
+    char* Yc = static_cast<char*>(Y) + (size_t)c0 * ldY * h->elem;
+    GemmArgs z{h->N, kc, P, op->J, op->ldJ, true, Vc, ldV, true, h->Z, kc, h->dtype, h->dtype, h->dtype, gt, 1.0, 0.0};
+    NGD_TRY(launch_gemm(z, s));
+    GemmArgs y{kc, P, h->N, h->Z, kc, false, op->J, op->ldJ, false, Yc, ldY, h->dtype, h->dtype, h->dtype, gt, 1.0, 0.0};
+    NGD_TRY(launch_gemm(y, s));
+    if (lambda != 0.0) NGD_TRY(launch_add_scaled(h->dtype, Vc, ldV, lambda, Yc, ldY, kc, P, s));
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_gaussian_omega(ngd_problem* h, uint64_t seed, uint64_t counter, int64_t ell, void* omega, int64_t ld,
+                              void* stream) {
+  NGD_CHECK(h != nullptr && omega != nullptr, "NULL argument");
+  NGD_CHECK(ell >= 1 && ld >= h->P, "ell >= 1 and ld >= P required");
+  return launch_gaussian_omega(h->dtype, seed, counter, h->P, ell, omega, ld, S(stream));
+}
+
+ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
+                              const void* omega, int64_t ldO, int32_t sketch_dtype, void* U, int64_t ldU,
+                              double* lam_hat, ngd_nystrom_info* info, void* stream) {
+  NGD_CHECK(h != nullptr && U != nullptr && lam_hat != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(ell >= 1 && ell <= h->max_ell, "ell must be in [1, min(max_ell, P)]");
+  NGD_CHECK(ldU >= h->P, "ldU < P");
+  NGD_CHECK(omega == nullptr || ldO >= h->P, "ldO < P");
+  int gt;
+  if (h->dtype == NGD_F64) {
+    NGD_CHECK(sketch_dtype == NGD_F64, "an FP64 problem sketches in FP64");
+    gt = G_F64;
+  } else {
+    NGD_CHECK(sketch_dtype == NGD_F32 || sketch_dtype == NGD_BF16, "an FP32 problem sketches in FP32 or BF16");
+    gt = sketch_dtype == NGD_F32 ? G_F32 : G_BF16;
+  }
+  hipStream_t s = S(stream);
+  const int64_t N = h->N, P = h->P, L = ell;
+  const int T = h->dtype;
+  if (omega == nullptr) {
+    NGD_TRY(launch_gaussian_omega(T, seed, counter, P, L, h->omega, h->ldP, s));
+    omega = h->omega;
+    ldO = h->ldP;
+  }
+  // Z = J Omega (N x ell)
+  GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
+  NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] { return launch_gemm(g1, s); }));
+  // M = Z^T Z (FP64), eigenpairs, whitening F = V_M D^{-1/2} (pseudo-inverse of the core), and
+  // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
+  NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
+    GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0};
+    NGD_TRY(launch_gemm(g2, s));
+    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-13, h->evals, h->Ev, h->eigw, s));
+    NGD_TRY(launch_whitening(h->evals, h->Ev, (int)L, h->F, s));
+    GemmArgs g3{N, L, L, h->Z, L, true, h->F, L, false, h->Q, L, T, NGD_F64, T, G_F64, 1.0, 0.0};
+    return launch_gemm(g3, s);
+  }));
+  // B^T = Q^T J (ell x P)
+  GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, T, T, T, gt, 1.0, 0.0};
+  NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] { return launch_gemm(g4, s); }));
+  // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
+  NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
+    GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0};
+    NGD_TRY(launch_gemm(g5, s));
+    // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
+    // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
+    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s));
+    NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
+    GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
+    return launch_gemm(g6, s);
+  }));
+  if (info != nullptr) {
+    std::vector<double> lh(L), ez(L);
+    NGD_HIP_TRY(hipMemcpyAsync(lh.data(), lam_hat, sizeof(double) * L, hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipMemcpyAsync(ez.data(), h->evals, sizeof(double) * L, hipMemcpyDeviceToHost, s));
+    int err = 0;
+    NGD_HIP_TRY(hipMemcpyAsync(&err, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    if (err) {
+      set_error("grid barrier of the tridiagonalisation timed out");
+      return NGD_ERR_HIP;
+    }
+    info->nu = 0.0;
+    info->lam1 = lh[0];
+    info->lam_ell = lh[L - 1];
+    info->rank = (int32_t)std::count_if(lh.begin(), lh.end(), [](double v) { return v > 0.0; });
+    info->rank_z = (int32_t)std::count_if(ez.begin(), ez.end(), [](double v) { return v > 0.0; });
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
+                         const ngd_precond* prec, double rtol, int64_t maxit, double* d, ngd_pcg_info* info,
+                         void* stream) {
+  NGD_CHECK(h != nullptr && g != nullptr && d != nullptr && info != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
+  NGD_CHECK(rtol >= 0.0 && maxit >= 0, "rtol >= 0 and maxit >= 0 required");
+  if (prec != nullptr) {
+    NGD_CHECK(prec->U != nullptr && prec->lam_hat != nullptr, "preconditioner pointers are NULL");
+    NGD_CHECK(prec->ell >= 1 && prec->ell <= h->max_ell && prec->ldU >= h->P, "bad preconditioner ell / ldU");
+  }
+  hipStream_t s = S(stream);
+  const int64_t P = h->P;
+  const int plain = prec == nullptr;
+  PcgState* hs = reinterpret_cast<PcgState*>(h->host);
+  std::memset(hs, 0, sizeof(PcgState));
+  hs->lambda = lambda;
+  hs->maxit = maxit;
+  NGD_HIP_TRY(hipMemcpyAsync(h->pcg_st, hs, sizeof(PcgState), hipMemcpyHostToDevice, s));
+  NGD_TRY(pcg_launch_init(g, P, d, h->pcg_r, h->pcg_p[0], h->pcg_part, h->pcg_st, rtol, plain, s));
+  double* zsrc = h->pcg_r;
+  if (!plain) {
+    NGD_TRY(pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, lambda, h->pcg_s,
+                               h->pcg_r, h->pcg_z, h->pcg_part, h->pcg_st, s));
+    zsrc = h->pcg_z;
+  }
+  int64_t k = 0;
+  int64_t chunk = 4;
+  while (true) {
+    const int64_t upto = std::min<int64_t>(maxit, k + chunk);
+    for (; k < upto; ++k) {
+      double* pprev = h->pcg_p[k & 1];
+      double* pcur = h->pcg_p[(k + 1) & 1];
+      NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
+        return pcg_launch_rows(h->dtype, op->J, op->ldJ, h->N, P, zsrc, pprev, pcur, h->pcg_st, h->partial, h->tsq,
+                               h->nwg, s);
+      }));
+      NGD_TRY(pcg_launch_update(h->dtype, h->partial, h->nwg, op->ldJ, P, pcur, h->tsq, d, h->pcg_r, h->pcg_part,
+                                h->pcg_st, plain, s));
+      if (!plain)
+        NGD_TRY(timed(h, NGD_TIMER_PRECOND, s, [&] {
+          return pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, lambda, h->pcg_s,
+                                    h->pcg_r, h->pcg_z, h->pcg_part, h->pcg_st, s);
+        }));
+    }
+    NGD_HIP_TRY(hipMemcpyAsync(hs, h->pcg_st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    if (hs->done || k >= maxit) break;
+    chunk = std::min<int64_t>(chunk * 2, 64);
+  }
+  info->iters = hs->iters;
+  info->rel_res = hs->bnorm2 > 0 ? std::sqrt(hs->rr / hs->bnorm2) : 0.0;
+  info->converged = hs->converged;
+  info->breakdown = hs->breakdown;
+  if (hs->breakdown) {
+    set_error("PCG breakdown (non-positive curvature or non-finite value)");
+    return NGD_ERR_BREAKDOWN;
+  }
+  if (!hs->converged) {
+    set_error("PCG reached maxit before the tolerance");
+    return NGD_ERR_NOT_CONVERGED;
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const double* v0, int32_t iters, double* lam1,
+                                void* stream) {
+  NGD_CHECK(h != nullptr && v0 != nullptr && lam1 != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(iters >= 1, "iters must be >= 1");
+  hipStream_t s = S(stream);
+  const int64_t P = h->P;
+  double* v = h->vtmp[0];
+  double* w = h->vtmp[1];
+  double* sc = h->scal;  // [0] v.w, [1] w.w, [2] v0.v0, [8..] dot workspace
+  NGD_TRY(launch_dot(v0, v0, P, sc + 8, sc + 2, s));
+  NGD_TRY(launch_scale_rsqrt(v0, sc + 2, P, v, s));
+  for (int it = 0; it < iters; ++it) {
+    NGD_TRY(gram_apply(h, op, v, 0.0, w, s));
+    NGD_TRY(launch_dot(v, w, P, sc + 8, sc + 0, s));
+    NGD_TRY(launch_dot(w, w, P, sc + 8, sc + 1, s));
+    NGD_TRY(launch_scale_rsqrt(w, sc + 1, P, v, s));
+  }
+  double* hv = reinterpret_cast<double*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  *lam1 = hv[0];
+  return NGD_OK;
+}
+
+ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, const double* grad, double loss0,
+                           double c1, int32_t max_halvings, void* theta_out, double* alpha, double* loss_new,
+                           void* stream) {
+  NGD_CHECK(h != nullptr && theta && d && grad && theta_out && alpha && loss_new, "NULL argument");
+  NGD_CHECK(max_halvings >= 0 && c1 >= 0.0, "max_halvings >= 0 and c1 >= 0 required");
+  hipStream_t s = S(stream);
+  const int64_t P = h->P;
+  double* hv = reinterpret_cast<double*>(h->host);  // [0] slope, [8..15] alphas, [16..23] losses
+  NGD_TRY(launch_dot(grad, d, P, h->scal + 8, h->scal + 0, s));
+  NGD_HIP_TRY(hipMemcpyAsync(hv, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  const double slope = hv[0];
+  int tried = 0;
+  double accepted = 0.0, acc_loss = loss0;
+  bool found = false;
+  int batch = 1;
+  while (!found && tried <= max_halvings) {
+    const int nt = std::min(batch, max_halvings + 1 - tried);
+    for (int t = 0; t < nt; ++t) hv[8 + t] = std::ldexp(1.0, -(tried + t));
+    NGD_HIP_TRY(hipMemcpyAsync(h->alphas, hv + 8, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    NGD_TRY(launch_axpy_theta(h->dtype, theta, d, h->alphas, nt, P, h->trial, h->ldP, s));
+    NGD_TRY(launch_residual_jacobian(h->net, h->dtype, h->trial, h->N, h->X, h->w, h->f, h->g, h->kind, nullptr,
+                                     nullptr, 0, h->loss_part, h->ldP, nt, s, nullptr));
+    NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, nt, 0.5, h->losses, s));
+    NGD_HIP_TRY(hipMemcpyAsync(hv + 16, h->losses, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    for (int t = 0; t < nt; ++t) {
+      const double a = hv[8 + t], Lt = hv[16 + t];
+      if (Lt <= loss0 - c1 * a * slope) {
+        accepted = a;
+        acc_loss = Lt;
+        found = true;
+        break;
+      }
+    }
+    tried += nt;
+    batch = kTrials;
+  }
+  // theta_out = theta - alpha d (alpha = 0 copies theta)
+  hv[8] = accepted;
+  NGD_HIP_TRY(hipMemcpyAsync(h->alphas, hv + 8, sizeof(double), hipMemcpyHostToDevice, s));
+  NGD_TRY(launch_axpy_theta(h->dtype, theta, d, h->alphas, 1, P, theta_out, h->ldP, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  *alpha = accepted;
+  *loss_new = acc_loss;
+  return NGD_OK;
+}
+
+ngd_status ngd_timing_enable(ngd_problem* h, int32_t enable) {
+  NGD_CHECK(h != nullptr, "NULL handle");
+  NGD_TRY(flush_timers(h));
+  h->timing = enable != 0;
+  for (int i = 0; i < NGD_NUM_TIMERS; ++i) {
+    h->t_ms[i] = 0.0;
+    h->t_n[i] = 0;
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_timing_read(ngd_problem* h, int32_t id, int64_t* launches, double* total_ms) {
+  NGD_CHECK(h != nullptr && launches != nullptr && total_ms != nullptr, "NULL argument");
+  NGD_CHECK(id >= 0 && id < NGD_NUM_TIMERS, "timer id out of range");
+  NGD_TRY(flush_timers(h));
+  *launches = h->t_n[id];
+  *total_ms = h->t_ms[id];
+  return NGD_OK;
+}
+
+}  // extern "C"

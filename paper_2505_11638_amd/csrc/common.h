@@ -1,0 +1,173 @@
+// Internal declarations shared by the libngd HIP sources (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <type_traits>
+
+#include "../../include/ngd.h"
+
+namespace ngd {
+
+constexpr int kMaxLayers = 8;   // affine layers
+constexpr int kMaxDim = 6;      // input dimension d
+constexpr int kMaxWidth = 256;
+constexpr int kMaxChan = 8;     // value + |S| gradient + Laplacian + time <= 1 + 5 + 1 + 1
+
+// Network and PDE description passed by value to the kernels.
+struct NetDesc {
+  int n_layers;                  // affine layers
+  int widths[kMaxLayers + 1];
+  int64_t woff[kMaxLayers];      // offset of W_l in theta
+  int64_t boff[kMaxLayers];      // offset of b_l in theta
+  int d;                         // input dimension
+  int nS;                        // Laplacian coordinates (first nS inputs)
+  int has_t;                     // heat: input d-1 is time
+  int C;                         // channels: 1 + nS + 1 + has_t
+  int pde;
+  int max_width;
+  int64_t P;
+};
+
+// Device-side solver state of one PCG solve (FP64 scalars).
+struct PcgState {
+  double rz;        // r^T z of the current iterate
+  double rr;        // r^T r
+  double bnorm2;    // ||g||^2
+  double alpha;
+  double beta;      // used to form the next search direction
+  double pp;        // ||p||^2 of the current search direction
+  double lambda;
+  double rtol2bb;   // rtol^2 ||g||^2
+  double mu_c;      // preconditioner: 1 / (lam_ell + mu)
+  long long iters;
+  long long maxit;
+  int done;
+  int converged;
+  int breakdown;
+  unsigned counter; // arrival counter for last-block reductions
+};
+
+void set_error(const std::string& msg);
+
+#define NGD_HIP_TRY(expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::ngd::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return NGD_ERR_HIP;                                                        \
+    }                                                                            \
+  } while (0)
+
+// ---- device helpers -----------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum; `red` must hold blockDim.x/64 elements. Result is returned to every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// Last-block detection for deterministic two-stage reductions inside one launch: every block
+// publishes its partial, then the block that arrives last sees all partials.
+__device__ __forceinline__ bool arrive_last(unsigned* counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+  return last != 0;
+}
+
+// ---- launchers (defined in the .hip files) ------------------------------------------------------
+
+// residual.hip
+ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* theta, int64_t N,
+                                    const void* X, const void* w, const void* f, const void* g,
+                                    const int8_t* kind, void* r_w, void* J, int64_t ldJ, double* loss_partial,
+                                    int64_t theta_stride, int n_theta, hipStream_t s, int* n_blocks_out);
+ngd_status launch_reduce_sum(const double* partial, int64_t n_per, int n_sets, double scale, double* out,
+                             hipStream_t s);
+ngd_status launch_gradient(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const void* r,
+                           double* work, double* grad, hipStream_t s);
+int gradient_chunks(int64_t N);
+
+// matvec.hip
+int gram_rows_grid(int dtype, int64_t N, int64_t P);
+ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* v,
+                            void* partial, double* tsq, int nwg, hipStream_t s);
+ngd_status launch_gram_reduce(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* v,
+                              double lambda, double* y, hipStream_t s);
+
+// gemm.hip: C(m,n) = alpha * sum_k A(m,k) B(k,n) (+ beta C), row-major C with ldc.
+enum GemmType { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
+struct GemmArgs {
+  int64_t M, N, K;
+  const void* A; int64_t lda; bool a_kmajor;   // A(m,k) = A[m*lda+k] if kmajor else A[k*lda+m]
+  const void* B; int64_t ldb; bool b_kmajor;   // B(k,n) = B[n*ldb+k] if kmajor else B[k*ldb+n]
+  void* C; int64_t ldc;
+  int a_type, b_type, c_type;                  // storage types: NGD_F64 / NGD_F32
+  int compute;                                 // GemmType
+  double alpha, beta;
+};
+ngd_status launch_gemm(const GemmArgs& a, hipStream_t s);
+
+// eig.hip: symmetric eigendecomposition of an n x n FP64 matrix (row-major, ld = n), in place.
+// Eigenpairs below drop_rel * ||T|| (Gershgorin bound) are returned as zeros. A is overwritten.
+size_t eig_workspace_bytes(int n);
+ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
+                          hipStream_t s);
+const int* eig_error_flag(void* work, int n);
+
+// misc.hip
+ngd_status launch_gaussian_omega(int dtype, uint64_t seed, uint64_t counter, int64_t P, int64_t ell, void* out,
+                                 int64_t ld, hipStream_t s);
+ngd_status launch_cast(int src_type, const void* src, int dst_type, void* dst, int64_t n, hipStream_t s);
+ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, const double* alphas, int n_alpha,
+                             int64_t P, void* out, int64_t out_stride, hipStream_t s);
+ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// matvec.hip (continued)
+bool gram_rows_supported(int dtype, int64_t ldJ);
+ngd_status launch_dot(const double* a, const double* b, int64_t n, double* work, double* out, hipStream_t s);
+ngd_status launch_scale_rsqrt(const double* w, const double* ww, int64_t n, double* v, hipStream_t s);
+ngd_status pcg_launch_init(const double* g, int64_t P, double* x, double* r, double* p_prev, double* part,
+                           PcgState* st, double rtol, int plain, hipStream_t s);
+ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* z,
+                           const double* p_prev, double* p_cur, PcgState* st, void* partial, double* tsq, int nwg,
+                           hipStream_t s);
+ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,
+                             const double* tsq, double* x, double* r, double* rr_part, PcgState* st, int plain,
+                             hipStream_t s);
+ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
+                              double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
+
+// nystrom helpers (misc.hip)
+ngd_status launch_whitening(const double* evals, const double* evec_rows, int ell, double* F, hipStream_t s);
+ngd_status launch_add_scaled(int dtype, const void* X, int64_t ldx, double a, void* Y, int64_t ldy, int64_t rows,
+                             int64_t cols, hipStream_t s);
+int residual_block_rows(const NetDesc& net, int dtype);
+
+}  // namespace ngd

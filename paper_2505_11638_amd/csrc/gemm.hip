@@ -1,0 +1,198 @@
+// Dense contractions on the MFMA matrix cores: C(m,n) = alpha sum_k A(m,k) B(k,n) + beta C(m,n).
+//
+// Used for the sketch products Z = J_w Omega and J_w^T Q (the ell simultaneous matvecs of the
+// "Precompute Jacobian only" strategy, Section 4.1.2 / Table tab:matvec_costs, and Alg. 6's
+// Y = G Omega), and for the FP64 products of the ell x ell Nystrom core. Operands are read with
+// either layout (K-contiguous or M/N-contiguous), converted to the compute type while they are
+// staged in LDS (FP32 -> BF16 for the BF16 sketch, FP32 -> FP64 for the FP64 core), and multiplied
+// with v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32 or v_mfma_f32_16x16x32_bf16.
+//
+// Tiling: 256 threads = 4 wave64s in a 2 x 2 arrangement; workgroup tile BM x BN = 64 x 64, each
+// wave a 32 x 32 block of 2 x 2 MFMA tiles. The next K-slab is fetched into registers while the
+// current one is multiplied out of LDS. Blocks that share an A row-panel are adjacent in launch
+// order so the panel is reused from L2.
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64, NT = 256;
+
+template <typename E> struct Cfg;
+template <> struct Cfg<double> { static constexpr int BK = 16; };
+template <> struct Cfg<float> { static constexpr int BK = 16; };
+template <> struct Cfg<__bf16> { static constexpr int BK = 32; };
+
+template <typename TS>
+__device__ __forceinline__ TS ldg(const TS* p) { return *p; }
+
+// Stage a BM x BK tile of A (or BN x BK of B^T) into registers: element (row, k) of the tile.
+// kmajor: X(row, k) = X[row*ld + k]; otherwise X[k*ld + row].
+template <typename TS, typename E, int BK, int ROWS>
+struct Stager {
+  static constexpr int PER = ROWS * BK / NT;
+  E v[PER];
+  __device__ __forceinline__ void load(const TS* __restrict__ X, int64_t ld, bool kmajor, int64_t row0, int64_t nrows,
+                                       int64_t k0, int64_t K) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      int r, k;
+      if (kmajor) { k = idx % BK; r = idx / BK; }
+      else { r = idx % ROWS; k = idx / ROWS; }
+      const int64_t gr = row0 + r, gk = k0 + k;
+      E val = E(0);
+      if (gr < nrows && gk < K) val = (E)(kmajor ? ldg(X + gr * ld + gk) : ldg(X + gk * ld + gr));
+      v[e] = val;
+    }
+  }
+  // LDS layout: [row][BK + PAD] (k contiguous) for bf16, [k][ROWS + PAD] otherwise
+  __device__ __forceinline__ void store(E* lds, bool kmajor) const {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      int r, k;
+      if (kmajor) { k = idx % BK; r = idx / BK; }
+      else { r = idx % ROWS; k = idx / ROWS; }
+      if constexpr (sizeof(E) == 2) lds[r * (BK + 8) + k] = v[e];
+      else lds[k * (ROWS + 4) + r] = v[e];
+    }
+  }
+};
+
+template <typename TA, typename TB, typename TC, typename E>
+__global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
+                                                  int64_t lda, int a_kmajor, const TB* __restrict__ B, int64_t ldb,
+                                                  int b_kmajor, TC* __restrict__ C, int64_t ldc, double alpha,
+                                                  double beta, int n_tiles_n) {
+  constexpr int BK = Cfg<E>::BK;
+  constexpr bool IS_BF = sizeof(E) == 2;
+  constexpr int A_ELEMS = IS_BF ? BM * (BK + 8) : BK * (BM + 4);
+  constexpr int B_ELEMS = IS_BF ? BN * (BK + 8) : BK * (BN + 4);
+  __shared__ __align__(16) E As[A_ELEMS];
+  __shared__ __align__(16) E Bs[B_ELEMS];
+  using Acc = typename std::conditional<sizeof(E) == 8, d4, f4>::type;
+
+  const int tile = blockIdx.x;
+  const int64_t m0 = (int64_t)(tile / n_tiles_n) * BM;
+  const int64_t n0 = (int64_t)(tile % n_tiles_n) * BN;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+
+  Acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+
+  Stager<TA, E, BK, BM> sa;
+  Stager<TB, E, BK, BN> sb;
+  sa.load(A, lda, a_kmajor, m0, M, 0, K);
+  sb.load(B, ldb, b_kmajor, n0, N, 0, K);
+  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    sa.store(As, a_kmajor);
+    sb.store(Bs, b_kmajor);
+    __syncthreads();
+    if (k0 + BK < K) {
+      sa.load(A, lda, a_kmajor, m0, M, k0 + BK, K);
+      sb.load(B, ldb, b_kmajor, n0, N, k0 + BK, K);
+    }
+    if constexpr (IS_BF) {
+      bf8 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const E* pa = As + (wm + i * 16 + (lane & 15)) * (BK + 8) + 8 * (lane >> 4);
+        const E* pb = Bs + (wn + i * 16 + (lane & 15)) * (BK + 8) + 8 * (lane >> 4);
+        a[i] = *reinterpret_cast<const bf8*>(pa);
+        b[i] = *reinterpret_cast<const bf8*>(pb);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        E a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[i] = As[kr * (BM + 4) + wm + i * 16 + (lane & 15)];
+          b[i] = Bs[kr * (BN + 4) + wn + i * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if constexpr (sizeof(E) == 8)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+  // epilogue: lane holds column lane % 16 of each 16 x 16 tile, rows 4*(lane/16) + r for the FP32
+  // accumulating instructions and lane/16 + 4*r for v_mfma_f64_16x16x4f64 (measured lane layouts)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row_in_tile = sizeof(E) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int64_t gm = m0 + wm + i * 16 + row_in_tile;
+        const int64_t gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          double v = alpha * (double)acc[i][j][r];
+          if (beta != 0.0) v += beta * (double)C[gm * ldc + gn];
+          C[gm * ldc + gn] = (TC)v;
+        }
+      }
+}
+
+template <typename TA, typename TB, typename TC, typename E>
+ngd_status run(const GemmArgs& g, hipStream_t s) {
+  const int tn = (int)((g.N + BN - 1) / BN), tm = (int)((g.M + BM - 1) / BM);
+  const int64_t tiles = (int64_t)tn * tm;
+  if (tiles == 0) return NGD_OK;
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, E>), dim3((unsigned)tiles), dim3(NT), 0, s, g.M, g.N, g.K,
+                     (const TA*)g.A, g.lda, (int)g.a_kmajor, (const TB*)g.B, g.ldb, (int)g.b_kmajor, (TC*)g.C, g.ldc,
+                     g.alpha, g.beta, tn);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+template <typename E>
+ngd_status dispatch_types(const GemmArgs& g, hipStream_t s) {
+  const bool a64 = g.a_type == NGD_F64, b64 = g.b_type == NGD_F64, c64 = g.c_type == NGD_F64;
+  if (a64 && b64 && c64) return run<double, double, double, E>(g, s);
+  if (!a64 && !b64 && !c64) return run<float, float, float, E>(g, s);
+  if (!a64 && !b64 && c64) return run<float, float, double, E>(g, s);
+  if (!a64 && b64 && c64) return run<float, double, double, E>(g, s);
+  if (!a64 && b64 && !c64) return run<float, double, float, E>(g, s);
+  if (a64 && !b64 && !c64) return run<double, float, float, E>(g, s);
+  if (a64 && !b64 && c64) return run<double, float, double, E>(g, s);
+  return run<double, double, float, E>(g, s);
+}
+
+}  // namespace
+
+ngd_status launch_gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M < 0 || g.N < 0 || g.K < 0) {
+    set_error("gemm: negative size");
+    return NGD_ERR_INVALID;
+  }
+  switch (g.compute) {
+    case G_F64: return dispatch_types<double>(g, s);
+    case G_F32: return dispatch_types<float>(g, s);
+    default: return dispatch_types<__bf16>(g, s);
+  }
+}
+
+}  // namespace ngd

@@ -1,0 +1,158 @@
+// Small kernels: counter-based Gaussian test matrix, precision casts, trial parameters for the
+// line search, zero fill (a kernel rather than hipMemsetAsync so the work can be graph-captured).
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplications,
+// word recombination with the key, and a Weyl increment of the key between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  const uint64_t v = ((uint64_t)(a >> 5) << 26) + (uint64_t)(b >> 6);
+  return ((double)v + 0.5) * 1.1102230246251565e-16;  // 2^-53
+}
+
+// Omega^T row j (column j of the p x ell test matrix), entries 2m and 2m+1 from counter (m, j, c)
+template <typename T>
+__global__ void omega_kernel(uint64_t seed, uint64_t counter, int64_t P, int64_t ell, T* __restrict__ out,
+                             int64_t ld) {
+  const int64_t half = (P + 1) / 2;
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (m >= half || j >= ell) return;
+  uint32_t c[4] = {(uint32_t)m, (uint32_t)j, (uint32_t)counter, (uint32_t)(counter >> 32)};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double x1 = u53(c[0], c[1]), x2 = u53(c[2], c[3]);
+  const double rad = sqrt(-2.0 * log(x1));
+  const double ang = 6.283185307179586 * x2;
+  T* row = out + j * ld;
+  row[2 * m] = (T)(rad * cos(ang));
+  if (2 * m + 1 < P) row[2 * m + 1] = (T)(rad * sin(ang));
+}
+
+template <typename S, typename D>
+__global__ void cast_kernel(const S* __restrict__ s, D* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (D)s[i];
+}
+
+template <typename T>
+__global__ void theta_trial_kernel(const T* __restrict__ theta, const double* __restrict__ d,
+                                   const double* __restrict__ alphas, int64_t P, T* __restrict__ out, int64_t stride) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (j < P) out[t * stride + j] = (T)((double)theta[j] - alphas[t] * d[j]);
+}
+
+// F[k][i] = V[i][k] / sqrt(lam_i) for lam_i > 0, else 0 (rows of V are eigenvectors)
+__global__ void whitening_kernel(const double* __restrict__ evals, const double* __restrict__ V, int ell,
+                                 double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // column of F
+  const int k = blockIdx.y;                             // row of F
+  if (i >= ell) return;
+  const double lam = evals[i];
+  F[(int64_t)k * ell + i] = lam > 0.0 ? V[(int64_t)i * ell + k] / sqrt(lam) : 0.0;
+}
+
+template <typename T>
+__global__ void add_scaled_kernel(const T* __restrict__ X, int64_t ldx, double a, T* __restrict__ Y, int64_t ldy,
+                                  int64_t cols) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (j < cols) Y[r * ldy + j] = (T)((double)Y[r * ldy + j] + a * (double)X[r * ldx + j]);
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n_words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_words) p[i] = 0u;
+}
+
+}  // namespace
+
+ngd_status launch_gaussian_omega(int dtype, uint64_t seed, uint64_t counter, int64_t P, int64_t ell, void* out,
+                                 int64_t ld, hipStream_t s) {
+  dim3 grid((unsigned)(((P + 1) / 2 + 255) / 256), (unsigned)ell);
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, s, seed, counter, P, ell, (double*)out, ld);
+  else
+    hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, s, seed, counter, P, ell, (float*)out, ld);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_cast(int st, const void* src, int dt, void* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return NGD_OK;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (st == NGD_F64 && dt == NGD_F32)
+    hipLaunchKernelGGL((cast_kernel<double, float>), grid, dim3(256), 0, s, (const double*)src, (float*)dst, n);
+  else if (st == NGD_F32 && dt == NGD_F64)
+    hipLaunchKernelGGL((cast_kernel<float, double>), grid, dim3(256), 0, s, (const float*)src, (double*)dst, n);
+  else if (st == NGD_F64 && dt == NGD_F64)
+    hipLaunchKernelGGL((cast_kernel<double, double>), grid, dim3(256), 0, s, (const double*)src, (double*)dst, n);
+  else
+    hipLaunchKernelGGL((cast_kernel<float, float>), grid, dim3(256), 0, s, (const float*)src, (float*)dst, n);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, const double* alphas, int n_alpha,
+                             int64_t P, void* out, int64_t out_stride, hipStream_t s) {
+  dim3 grid((unsigned)((P + 255) / 256), (unsigned)n_alpha);
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(theta_trial_kernel<double>, grid, dim3(256), 0, s, (const double*)theta, d, alphas, P,
+                       (double*)out, out_stride);
+  else
+    hipLaunchKernelGGL(theta_trial_kernel<float>, grid, dim3(256), 0, s, (const float*)theta, d, alphas, P,
+                       (float*)out, out_stride);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_whitening(const double* evals, const double* evec_rows, int ell, double* F, hipStream_t s) {
+  hipLaunchKernelGGL(whitening_kernel, dim3((unsigned)((ell + 255) / 256), (unsigned)ell), dim3(256), 0, s, evals,
+                     evec_rows, ell, F);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_add_scaled(int dtype, const void* X, int64_t ldx, double a, void* Y, int64_t ldy, int64_t rows,
+                             int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return NGD_OK;
+  dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows);
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(add_scaled_kernel<double>, grid, dim3(256), 0, s, (const double*)X, ldx, a, (double*)Y, ldy, cols);
+  else
+    hipLaunchKernelGGL(add_scaled_kernel<float>, grid, dim3(256), 0, s, (const float*)X, ldx, a, (float*)Y, ldy, cols);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words <= 0) return NGD_OK;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, words);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+}  // namespace ngd

@@ -1,0 +1,418 @@
+// Residuals, parameter Jacobian, gradient and loss of the PINN least-squares problem.
+//
+// One workgroup owns a tile of TP collocation points. Per point it propagates C channels through
+// the tanh MLP (value, gradient with respect to the Laplacian coordinates, Laplacian, time
+// derivative: Taylor-mode forward Laplacian), forms the residual of the Poisson / heat energy and,
+// for the Jacobian, runs the reverse sweep of those channels. The parameter derivative of a layer
+// z = W h + b is the channel sum dW[o,i] = sum_c zbar_c[o] h_c[i], written row by row with
+// coalesced stores (consecutive lanes -> consecutive parameters of one point's Jacobian row).
+// Pre-activations of every hidden layer stay in LDS between the sweeps; post-activations are
+// recomputed elementwise from them. (Jacobian of eq. G_matrixfree, Section 4.1.1; network of
+// Section 2.3; residuals of eq. energy_poisson and eq. heat_energy.)
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+template <typename T>
+struct Lds {
+  T* Ws;    // current layer weights, n_out x (n_in + 1)
+  T* pre;   // pre-activation channels of every hidden layer: [layer][p][c][n]
+  T* hb;    // input channels of the current layer: [p][c][nmax]
+  T* ab;    // adjoint of the current layer outputs: [p][c][nmax]
+  T* zb;    // adjoint of the current layer pre-activations: [p][c][nmax]
+  T* ub;    // output-layer channel values / adjoint seeds: [p][kMaxChan]
+  T* red;   // reduction scratch
+};
+
+__host__ __device__ inline int64_t pre_offset(const NetDesc& net, int layer, int TP) {
+  // start of hidden layer `layer` (affine index, < n_layers-1) in the pre buffer
+  int64_t off = 0;
+  for (int l = 0; l < layer; ++l) off += (int64_t)TP * net.C * net.widths[l + 1];
+  return off;
+}
+
+__host__ inline size_t lds_elems(const NetDesc& net, int TP) {
+  size_t ws = 0;
+  for (int l = 0; l < net.n_layers; ++l) {
+    size_t s = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
+    ws = s > ws ? s : ws;
+  }
+  size_t pre = (size_t)pre_offset(net, net.n_layers - 1, TP);
+  size_t buf = (size_t)TP * net.C * net.max_width;
+  return ws + pre + 3 * buf + (size_t)TP * kMaxChan + 32;
+}
+
+template <typename T>
+__device__ void load_weights(const NetDesc& net, const T* theta, int l, T* Ws) {
+  const int n_in = net.widths[l], n_out = net.widths[l + 1];
+  const T* W = theta + net.woff[l];
+  for (int e = threadIdx.x; e < n_out * n_in; e += blockDim.x) {
+    int o = e / n_in, i = e - o * n_in;
+    Ws[o * (n_in + 1) + i] = W[e];
+  }
+}
+
+// input channels of layer 0 for the tile
+template <typename T>
+__device__ void input_channels(const NetDesc& net, const T* X, int64_t row0, int64_t N, int TP, T* hb) {
+  const int d = net.d, C = net.C, nm = net.max_width;
+  for (int e = threadIdx.x; e < TP * C * d; e += blockDim.x) {
+    int i = e % d, pc = e / d, c = pc % C, p = pc / C;
+    int64_t row = row0 + p;
+    T v = 0;
+    if (c == 0) {
+      v = row < N ? X[row * d + i] : T(0);
+    } else if (c <= net.nS) {
+      v = (i == c - 1) ? T(1) : T(0);
+    } else if (c == net.nS + 1) {
+      v = 0;
+    } else {
+      v = (i == d - 1) ? T(1) : T(0);
+    }
+    hb[pc * nm + i] = v;
+  }
+}
+
+// post-activation channels of hidden layer `l` (affine index) from its pre-activations
+template <typename T>
+__device__ void activate(const NetDesc& net, const T* pre_l, int n, int TP, T* hb) {
+  const int C = net.C, nS = net.nS, nm = net.max_width;
+  for (int e = threadIdx.x; e < TP * n; e += blockDim.x) {
+    int p = e / n, i = e - p * n;
+    const T* z = pre_l + (int64_t)p * C * n;
+    T a = tanh(z[i]);
+    T s1 = T(1) - a * a;
+    T s2 = T(-2) * a * s1;
+    T gsq = 0;
+    T* h = hb + (int64_t)p * C * nm;
+    h[i] = a;
+    for (int k = 1; k <= nS; ++k) {
+      T gz = z[k * n + i];
+      gsq += gz * gz;
+      h[k * nm + i] = s1 * gz;
+    }
+    h[(nS + 1) * nm + i] = s1 * z[(nS + 1) * n + i] + s2 * gsq;
+    if (net.has_t) h[(nS + 2) * nm + i] = s1 * z[(nS + 2) * n + i];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void residual_jacobian_kernel(
+    NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
+    const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
+    T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
+  const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
+  const int64_t row0 = (int64_t)blockIdx.x * TP;
+
+  Lds<T> s;
+  {
+    size_t ws = 0;
+    for (int l = 0; l < L; ++l) {
+      size_t q = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
+      ws = q > ws ? q : ws;
+    }
+    s.Ws = smem;
+    s.pre = s.Ws + ws;
+    s.hb = s.pre + pre_offset(net, L - 1, TP);
+    s.ab = s.hb + (size_t)TP * C * nm;
+    s.zb = s.ab + (size_t)TP * C * nm;
+    s.ub = s.zb + (size_t)TP * C * nm;
+    s.red = s.ub + TP * kMaxChan;
+  }
+
+  // ---------------- forward sweep ----------------
+  input_channels(net, X, row0, N, TP, s.hb);
+  for (int l = 0; l < L - 1; ++l) {
+    const int n_in = net.widths[l], n_out = net.widths[l + 1];
+    __syncthreads();
+    load_weights(net, theta, l, s.Ws);
+    __syncthreads();
+    T* pre_l = s.pre + pre_offset(net, l, TP);
+    const T* b = theta + net.boff[l];
+    for (int e = threadIdx.x; e < TP * C * n_out; e += blockDim.x) {
+      int o = e % n_out, pc = e / n_out;
+      const T* wrow = s.Ws + o * (n_in + 1);
+      const T* h = s.hb + pc * nm;
+      T acc = 0;
+      for (int i = 0; i < n_in; ++i) acc += wrow[i] * h[i];
+      if (pc % C == 0) acc += b[o];
+      pre_l[(int64_t)pc * n_out + o] = acc;
+    }
+    __syncthreads();
+    activate(net, pre_l, n_out, TP, s.hb);
+  }
+  // output layer: channel values of u
+  const int n_last = net.widths[L - 1];
+  const T* Wout = theta + net.woff[L - 1];
+  const T bout = theta[net.boff[L - 1]];
+  __syncthreads();
+  for (int pc = threadIdx.x; pc < TP * C; pc += blockDim.x) {
+    const T* h = s.hb + pc * nm;
+    T acc = 0;
+    for (int i = 0; i < n_last; ++i) acc += Wout[i] * h[i];
+    int p = pc / C, c = pc % C;
+    s.ub[p * kMaxChan + c] = acc + (c == 0 ? bout : T(0));
+  }
+  __syncthreads();
+  // residuals, loss and adjoint seeds (overwrite ub with the seeds after reading the values)
+  T lsum = 0;
+  if (threadIdx.x < TP) {
+    const int p = threadIdx.x;
+    const int64_t row = row0 + p;
+    T seed[kMaxChan];
+    for (int c = 0; c < kMaxChan; ++c) seed[c] = 0;
+    if (row < N) {
+      const T u = s.ub[p * kMaxChan], lap = s.ub[p * kMaxChan + nS + 1];
+      const T ut = net.has_t ? s.ub[p * kMaxChan + nS + 2] : T(0);
+      const T sw = sqrt(w[row]);
+      T res;
+      if (kind[row] == NGD_ROW_INTERIOR) {
+        if (net.pde == NGD_PDE_POISSON) {
+          res = lap + f[row];
+          seed[nS + 1] = sw;
+        } else {
+          res = ut - lap - f[row];
+          seed[nS + 1] = -sw;
+          seed[nS + 2] = sw;
+        }
+      } else {
+        res = u - g[row];
+        seed[0] = sw;
+      }
+      const T rw = sw * res;
+      if (r_w != nullptr && blockIdx.y == 0) r_w[row] = rw;
+      lsum = rw * rw;
+    }
+    for (int c = 0; c < kMaxChan; ++c) s.ub[p * kMaxChan + c] = seed[c];
+  }
+  {
+    __shared__ double red_d[4];
+    double tot = block_sum<double>((double)lsum, red_d);
+    if (threadIdx.x == 0 && loss_partial != nullptr)
+      loss_partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+  }
+  if (J == nullptr) return;
+  __syncthreads();
+
+  // ---------------- reverse sweep and Jacobian rows ----------------
+  const int64_t P = net.P;
+  const int nvalid = (int)((N - row0) < TP ? (N - row0) : TP);
+  // output layer: dr/dW_out[i] = sum_c seed_c h_c[i], dr/db_out = seed_value; zero padding
+  for (int p = 0; p < nvalid; ++p) {
+    T* Jrow = J + (row0 + p) * ldJ;
+    const T* sd = s.ub + p * kMaxChan;
+    for (int i = threadIdx.x; i < n_last; i += blockDim.x) {
+      T acc = 0;
+      for (int c = 0; c < C; ++c) acc += sd[c] * s.hb[(p * C + c) * nm + i];
+      Jrow[net.woff[L - 1] + i] = acc;
+    }
+    if (threadIdx.x == 0) Jrow[net.boff[L - 1]] = sd[0];
+    for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) Jrow[j] = 0;
+  }
+  // adjoint of the last hidden layer outputs: ab = W_out^T seed
+  for (int e = threadIdx.x; e < TP * C * n_last; e += blockDim.x) {
+    int i = e % n_last, pc = e / n_last, p = pc / C, c = pc % C;
+    s.ab[pc * nm + i] = Wout[i] * s.ub[p * kMaxChan + c];
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int n_in = net.widths[l], n_out = net.widths[l + 1];
+    const T* pre_l = s.pre + pre_offset(net, l, TP);
+    __syncthreads();
+    // zbar from abar through tanh (channel rules of the forward Laplacian)
+    for (int e = threadIdx.x; e < TP * n_out; e += blockDim.x) {
+      int p = e / n_out, o = e - p * n_out;
+      const T* z = pre_l + (int64_t)p * C * n_out;
+      const T* a_ = s.ab + (int64_t)p * C * nm;
+      T* zb = s.zb + (int64_t)p * C * nm;
+      T a = tanh(z[o]);
+      T s1 = T(1) - a * a;
+      T s2 = T(-2) * a * s1;
+      T s3 = T(-2) * s1 * (s1 - T(2) * a * a);
+      T aL = a_[(nS + 1) * nm + o];
+      T gsq = 0, gdot = 0;
+      for (int k = 1; k <= nS; ++k) {
+        T gz = z[k * n_out + o];
+        T ag = a_[k * nm + o];
+        gsq += gz * gz;
+        gdot += gz * ag;
+        zb[k * nm + o] = s1 * ag + T(2) * s2 * aL * gz;
+      }
+      T Lz = z[(nS + 1) * n_out + o];
+      zb[(nS + 1) * nm + o] = s1 * aL;
+      T zv = s1 * a_[o] + s2 * gdot + (s2 * Lz + s3 * gsq) * aL;
+      if (net.has_t) {
+        T aT = a_[(nS + 2) * nm + o];
+        zb[(nS + 2) * nm + o] = s1 * aT;
+        zv += s2 * z[(nS + 2) * n_out + o] * aT;
+      }
+      zb[o] = zv;
+    }
+    // input channels of this layer
+    if (l == 0)
+      input_channels(net, X, row0, N, TP, s.hb);
+    else
+      activate(net, s.pre + pre_offset(net, l - 1, TP), n_in, TP, s.hb);
+    __syncthreads();
+    // Jacobian segments of W_l and b_l
+    const int64_t wo = net.woff[l], bo = net.boff[l];
+    const int nel = n_out * n_in;
+    if ((int)blockDim.x % n_in == 0) {
+      const int i = threadIdx.x % n_in, ostep = blockDim.x / n_in, o0 = threadIdx.x / n_in;
+      for (int p = 0; p < nvalid; ++p) {
+        T hreg[kMaxChan];
+#pragma unroll
+        for (int c = 0; c < kMaxChan; ++c) hreg[c] = c < C ? s.hb[(p * C + c) * nm + i] : T(0);
+        T* Jrow = J + (row0 + p) * ldJ + wo;
+        const T* zbp = s.zb + (int64_t)p * C * nm;
+        for (int o = o0; o < n_out; o += ostep) {
+          T acc = 0;
+#pragma unroll
+          for (int c = 0; c < kMaxChan; ++c)
+            if (c < C) acc += zbp[c * nm + o] * hreg[c];
+          Jrow[o * n_in + i] = acc;
+        }
+      }
+    } else {
+      for (int p = 0; p < nvalid; ++p) {
+        T* Jrow = J + (row0 + p) * ldJ + wo;
+        const T* zbp = s.zb + (int64_t)p * C * nm;
+        const T* hbp = s.hb + (int64_t)p * C * nm;
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+          int o = e / n_in, i = e - o * n_in;
+          T acc = 0;
+          for (int c = 0; c < C; ++c) acc += zbp[c * nm + o] * hbp[c * nm + i];
+          Jrow[e] = acc;
+        }
+      }
+    }
+    for (int p = 0; p < nvalid; ++p) {
+      T* Jrow = J + (row0 + p) * ldJ + bo;
+      for (int o = threadIdx.x; o < n_out; o += blockDim.x) Jrow[o] = s.zb[(int64_t)p * C * nm + o];
+    }
+    if (l == 0) break;
+    // abar of the layer inputs: ab = W_l^T zbar
+    __syncthreads();
+    load_weights(net, theta, l, s.Ws);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TP * C * n_in; e += blockDim.x) {
+      int i = e % n_in, pc = e / n_in;
+      const T* zc = s.zb + pc * nm;
+      T acc = 0;
+      for (int o = 0; o < n_out; ++o) acc += s.Ws[o * (n_in + 1) + i] * zc[o];
+      s.ab[pc * nm + i] = acc;
+    }
+  }
+}
+
+// sum of n_per partials for each of n_sets sets, scaled: out[s] = scale * sum_i partial[s*n_per + i]
+__global__ void reduce_sum_kernel(const double* __restrict__ partial, int64_t n_per, double scale,
+                                  double* __restrict__ out) {
+  __shared__ double red[16];
+  const double* p = partial + (int64_t)blockIdx.x * n_per;
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < n_per; i += blockDim.x) acc += p[i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = scale * acc;
+}
+
+// gradient: grad[j] = sum_r r[r] J[r, j]; stage 1 per row chunk, stage 2 over chunks (FP64)
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_stage1(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+                                                     const T* __restrict__ r, int64_t rows_per,
+                                                     double* __restrict__ work) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = (r0 + rows_per) < N ? (r0 + rows_per) : N;
+  if (j >= P) return;
+  double acc = 0;
+  for (int64_t i = r0; i < r1; ++i) acc += (double)r[i] * (double)J[i * ldJ + j];
+  work[(int64_t)blockIdx.y * P + j] = acc;
+}
+
+__global__ void colsum_stage2(const double* __restrict__ work, int nchunk, int64_t P, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  double acc = 0;
+  for (int c = 0; c < nchunk; ++c) acc += work[(int64_t)c * P + j];
+  out[j] = acc;
+}
+
+}  // namespace
+
+static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes);
+
+int residual_block_rows(const NetDesc& net, int dtype) {
+  size_t b = 0;
+  return choose_tp(net, dtype == NGD_F64 ? 8 : 4, &b);
+}
+
+static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes) {
+  int tp = 16;
+  while (tp > 1 && lds_elems(net, tp) * elem > 96 * 1024) tp >>= 1;
+  *bytes = lds_elems(net, tp) * elem;
+  return tp;
+}
+
+ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* theta, int64_t N, const void* X,
+                                    const void* w, const void* f, const void* g, const int8_t* kind, void* r_w,
+                                    void* J, int64_t ldJ, double* loss_partial, int64_t theta_stride, int n_theta,
+                                    hipStream_t s, int* n_blocks_out) {
+  size_t elem = dtype == NGD_F64 ? 8 : 4;
+  size_t bytes = 0;
+  int tp = choose_tp(net, elem, &bytes);
+  if (bytes > 160 * 1024) {
+    set_error("network too wide for the residual kernel's LDS budget");
+    return NGD_ERR_INVALID;
+  }
+  dim3 grid((unsigned)((N + tp - 1) / tp), (unsigned)n_theta);
+  if (n_blocks_out) *n_blocks_out = (int)grid.x;
+  if (dtype == NGD_F64) {
+    auto k = residual_jacobian_kernel<double>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const double*)theta, theta_stride, N, (const double*)X,
+                       (const double*)w, (const double*)f, (const double*)g, kind, (double*)r_w, (double*)J, ldJ,
+                       loss_partial, tp);
+  } else {
+    auto k = residual_jacobian_kernel<float>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const float*)theta, theta_stride, N, (const float*)X,
+                       (const float*)w, (const float*)f, (const float*)g, kind, (float*)r_w, (float*)J, ldJ,
+                       loss_partial, tp);
+  }
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_reduce_sum(const double* partial, int64_t n_per, int n_sets, double scale, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(reduce_sum_kernel, dim3(n_sets), dim3(256), 0, s, partial, n_per, scale, out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+int gradient_chunks(int64_t N) {
+  int64_t c = (N + 255) / 256;
+  return (int)(c < 64 ? c : 64);
+}
+
+ngd_status launch_gradient(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const void* r,
+                           double* work, double* grad, hipStream_t s) {
+  const int nchunk = gradient_chunks(N);
+  const int64_t rows_per = (N + nchunk - 1) / nchunk;
+  dim3 grid((unsigned)((P + 255) / 256), (unsigned)nchunk);
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(colsum_stage1<double>, grid, dim3(256), 0, s, (const double*)J, ldJ, N, P,
+                       (const double*)r, rows_per, work);
+  else
+    hipLaunchKernelGGL(colsum_stage1<float>, grid, dim3(256), 0, s, (const float*)J, ldJ, N, P, (const float*)r,
+                       rows_per, work);
+  hipLaunchKernelGGL(colsum_stage2, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, work, nchunk, P, grad);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+}  // namespace ngd

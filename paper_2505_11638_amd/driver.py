@@ -1,0 +1,77 @@
+"""Natural gradient descent loop (Alg. 1) on top of the C ABI.
+
+One step: residuals, Jacobian and gradient; the direction from matrix-free PCG (Alg. 3) with the
+Nystrom builder of Alg. 4 at a fixed sketch size, or plain CG; the damping rule; Armijo backtracking
+and the update. Every numerical operation is a libngd call; the host only moves a few scalars
+(loss, largest eigenvalue estimate, Armijo decisions).
+
+Damping (Section 4.3 and the experimental setup of Section 5): mu = max(gamma eps lam1_hat, 1e-4 L^2)
+with gamma = 10 and eps the unit roundoff of the working precision, unless a fixed mu is given.
+Plain CG takes lam1_hat from 4 power iterations.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from .api import Problem
+
+EPS = {"f64": 2.0 ** -52, "f32": 2.0 ** -23}
+
+
+@dataclasses.dataclass
+class StepReport:
+    loss: float
+    mu: float
+    lam1: float
+    iters: int
+    rel_res: float
+    converged: bool
+    alpha: float
+    loss_new: float
+    rank: int = -1
+
+
+class NGD:
+    def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
+                 maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None):
+        self.gp = Problem(data, dtype=dtype, max_ell=ell or getattr(data, "ell", 1))
+        gp = self.gp
+        self.solver = solver
+        self.ell = min(int(ell or data.ell), gp.P)
+        self.sketch_dtype = sketch_dtype or getattr(data, "sketch_dtype", None)
+        if gp.dtype_name == "f64":
+            self.sketch_dtype = "f64"
+        self.rtol = rtol
+        self.maxit = maxit if maxit is not None else (1000 if solver == "nystrom" else gp.P)
+        self.lam = lam if lam is not None else getattr(data, "lam", None)
+        self.gamma = gamma
+        self.seed = seed
+        self.eps = EPS[gp.dtype_name]
+        self.theta = gp.theta(theta0)
+        self.J = gp.new_jacobian()
+        if power_v0 is None:
+            power_v0 = np.random.default_rng(np.random.SeedSequence([seed, 99])).standard_normal(gp.P)
+        self.v0 = torch.as_tensor(power_v0, dtype=torch.float64, device=gp.device)
+        self.k = 0
+
+    def step(self) -> StepReport:
+        gp = self.gp
+        r, J, grad, loss = gp.residual_jacobian(self.theta, self.J)
+        L0 = float(loss.item())
+        pc = None
+        rank = -1
+        if self.solver == "nystrom":
+            pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype)
+            lam1 = pc.info["lam1"]
+            rank = pc.info["rank"]
+        else:
+            lam1 = gp.power_lambda_max(J, self.v0, 4)
+        mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
+        out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit)
+        _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
+        self.k += 1
+        return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
