@@ -44,12 +44,13 @@ struct ngd_problem {
   PcgState* pcg_st;
   void* omega;       // max_ell x ldP, dtype
   void* Z;           // N x max_ell, dtype
-  void* Q;           // N x max_ell, dtype
+  void* Q;           // N x max_ell, FP64 (orthonormal basis of range(Z))
   void* Bt;          // max_ell x ldP, dtype
   double* M;         // ell x ell
   double* Ev;        // ell x ell eigenvectors (rows)
   double* F;         // ell x ell
   double* evals;     // ell
+  double* gemm_work; // split-K partials of the ell x ell Gram products (8 ell^2)
   void* eigw;        // eig workspace
   void* trial;       // kTrials x ldP, dtype (line search)
   double* alphas;    // kTrials
@@ -230,16 +231,17 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->pcg_p[0], sizeof(double) * ldP});
   plan.push_back({(void**)&h->pcg_p[1], sizeof(double) * ldP});
   plan.push_back({(void**)&h->pcg_s, sizeof(double) * (size_t)L});
-  plan.push_back({(void**)&h->pcg_part, sizeof(double) * (size_t)((P + 255) / 256 + 64)});
+  plan.push_back({(void**)&h->pcg_part, sizeof(double) * (size_t)((P + 31) / 32 + 64)});
   plan.push_back({(void**)&h->pcg_st, sizeof(PcgState)});
   plan.push_back({&h->omega, (size_t)L * ldP * e});
   plan.push_back({&h->Z, (size_t)N * L * e});
-  plan.push_back({&h->Q, (size_t)N * L * e});
+  plan.push_back({&h->Q, (size_t)N * L * sizeof(double)});
   plan.push_back({&h->Bt, (size_t)L * ldP * e});
   plan.push_back({(void**)&h->M, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->Ev, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->evals, sizeof(double) * (size_t)L});
+  plan.push_back({(void**)&h->gemm_work, sizeof(double) * 8 * (size_t)L * L});
   plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
   plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
   plan.push_back({(void**)&h->alphas, sizeof(double) * kTrials});
@@ -371,19 +373,22 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   // M = Z^T Z (FP64), eigenpairs, whitening F = V_M D^{-1/2} (pseudo-inverse of the core), and
   // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
-    GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0};
+    GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
+                h->gemm_work, 8 * L * L};
     NGD_TRY(launch_gemm(g2, s));
-    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-13, h->evals, h->Ev, h->eigw, s));
-    NGD_TRY(launch_whitening(h->evals, h->Ev, (int)L, h->F, s));
-    GemmArgs g3{N, L, L, h->Z, L, true, h->F, L, false, h->Q, L, T, NGD_F64, T, G_F64, 1.0, 0.0};
-    return launch_gemm(g3, s);
+    // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
+    NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
+                                    reinterpret_cast<int*>(h->scal + 210), s));
+    NGD_TRY(launch_cast(T, h->Z, NGD_F64, h->Q, N * L, s));
+    return launch_trsm_right_lt(h->M, (int)L, (double*)h->Q, L, N, s);
   }));
   // B^T = Q^T J (ell x P)
-  GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, T, T, T, gt, 1.0, 0.0};
+  GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] { return launch_gemm(g4, s); }));
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
-    GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0};
+    GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
+                h->gemm_work, 8 * L * L};
     NGD_TRY(launch_gemm(g5, s));
     // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
     // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
@@ -393,9 +398,9 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     return launch_gemm(g6, s);
   }));
   if (info != nullptr) {
-    std::vector<double> lh(L), ez(L);
+    std::vector<double> lh(L), core(16);
     NGD_HIP_TRY(hipMemcpyAsync(lh.data(), lam_hat, sizeof(double) * L, hipMemcpyDeviceToHost, s));
-    NGD_HIP_TRY(hipMemcpyAsync(ez.data(), h->evals, sizeof(double) * L, hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipMemcpyAsync(core.data(), h->scal + 200, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
     int err = 0;
     NGD_HIP_TRY(hipMemcpyAsync(&err, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
@@ -403,11 +408,13 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
       set_error("grid barrier of the tridiagonalisation timed out");
       return NGD_ERR_HIP;
     }
-    info->nu = 0.0;
+    int nmod = 0;
+    std::memcpy(&nmod, &core[10], sizeof(int));
+    info->nu = core[1];
     info->lam1 = lh[0];
     info->lam_ell = lh[L - 1];
     info->rank = (int32_t)std::count_if(lh.begin(), lh.end(), [](double v) { return v > 0.0; });
-    info->rank_z = (int32_t)std::count_if(ez.begin(), ez.end(), [](double v) { return v > 0.0; });
+    info->rank_z = (int32_t)(L - nmod);
   }
   return NGD_OK;
 }

@@ -1,0 +1,161 @@
+// Shifted Cholesky of the ell x ell core M + nu I = L L^T and the triangular solve Q = Z L^{-T}
+// (Alg. 6: C = chol(Omega^T Y_nu), B = Y_nu / C), both blocked by panels of kNb columns:
+//  * Cholesky panel j0: one workgroup factors the kNb x kNb diagonal block in LDS, then the rows
+//    below are solved, L21 = A21 L11^{-T}, one row per thread, and the trailing matrix is updated
+//    with one MFMA GEMM, A22 -= L21 L21^T.
+//  * Triangular solve, panel j0 of Q (FP64, N x ell): Q_J -= Q_<J L_J,<J^T by one GEMM, then
+//    Q_J = Q_J L_JJ^{-T} row by row.
+// A pivot that is not safely positive is replaced by a floor (pivot^2 = `floor`), so the
+// factorisation never fails; the directions involved are left shrunk in Q (the effect of the
+// shift nu in Alg. 6). Their count is reported as a rank deficit.
+#include <algorithm>
+
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+constexpr int kNb = 32;
+
+// factor the kNb x kNb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, row-major kNb x kNb)
+__device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb, double floor, double null_thresh,
+                            double* Ls, int* nmod) {
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e / nb, c = e - r * nb;
+    Ls[e] = c <= r ? A[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    __shared__ double piv;
+    if (threadIdx.x == 0) {
+      double a = Ls[c * nb + c];
+      if (!(a > null_thresh) && nmod) ++*nmod;  // direction at the level of the shift: numerically null
+      if (!(a > floor)) a = floor;
+      piv = sqrt(a);
+      Ls[c * nb + c] = piv;
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int r = c + 1 + threadIdx.x; r < nb; r += blockDim.x) Ls[r * nb + c] /= p;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+      const int r = e / nb, q = e - r * nb;
+      if (r > c && q > c && q <= r) Ls[e] -= Ls[r * nb + c] * Ls[q * nb + c];
+    }
+    __syncthreads();
+  }
+}
+
+// one row x (nb values) of X: solve x L^T = x in place, L lower kNb x kNb in LDS
+__device__ __forceinline__ void solve_row(double* __restrict__ x, const double* Ls, int nb) {
+  double v[kNb];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) v[j] = j < nb ? x[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    if (j < nb) {
+      double s = v[j];
+#pragma unroll
+      for (int k = 0; k < kNb; ++k)
+        if (k < j) s -= v[k] * Ls[j * nb + k];
+      v[j] = s / Ls[j * nb + j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kNb; ++j)
+    if (j < nb) x[j] = v[j];
+}
+
+// Cholesky of the diagonal block of panel j0, written back in place (one workgroup)
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int n, int j0, int nb,
+                                                        const double* __restrict__ floor_p, int* __restrict__ nmod) {
+  __shared__ double Ls[kNb * kNb];
+  __shared__ int local_mod;
+  if (threadIdx.x == 0) local_mod = 0;
+  __syncthreads();
+  factor_diag(A, n, j0, nb, floor_p[0], floor_p[2], Ls, &local_mod);
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e / nb, c = e - r * nb;
+    A[(int64_t)(j0 + r) * n + j0 + c] = c <= r ? Ls[e] : 0.0;
+  }
+  if (threadIdx.x == 0) *nmod += local_mod;
+}
+
+// rows of X (FP64, ld ldx): X[r, j0:j0+nb] <- X[r, j0:j0+nb] L_JJ^{-T}, L read from the factor
+__global__ __launch_bounds__(256) void trsm_rows_kernel(const double* __restrict__ L, int n, int j0, int nb,
+                                                        double* __restrict__ X, int64_t ldx, int64_t nrows) {
+  __shared__ double Ls[kNb * kNb];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e / nb, c = e - r * nb;
+    Ls[e] = c <= r ? L[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrows) solve_row(X + r * ldx + j0, Ls, nb);
+}
+
+// nu = shift_rel * trace(M) added to the diagonal; floor = floor_rel * trace(M)
+__global__ void shift_kernel(double* __restrict__ M, int n, double shift_rel, double floor_rel,
+                             double* __restrict__ floor_out, int* __restrict__ nmod) {
+  __shared__ double red[4];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) t += M[(int64_t)i * n + i];
+  t = block_sum(t, red);
+  const double nu = shift_rel * t;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) M[(int64_t)i * n + i] += nu;
+  if (threadIdx.x == 0) {
+    floor_out[0] = t > 0.0 ? floor_rel * t : 1e-300;
+    floor_out[1] = nu;
+    floor_out[2] = 100.0 * nu;
+    *nmod = 0;
+  }
+}
+
+}  // namespace
+
+// L (lower, in place of M) with L L^T = M + nu I, nu = shift_rel tr(M). `scal` holds 2 doubles
+// (floor, nu) and `nmod` the count of floored pivots (both device).
+ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(256), 0, s, M, n, shift_rel, floor_rel, scal, nmod);
+  NGD_HIP_TRY(hipGetLastError());
+  for (int j0 = 0; j0 < n; j0 += kNb) {
+    const int nb = std::min(kNb, n - j0);
+    const int below = n - j0 - nb;
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, M, n, j0, nb, scal, nmod);
+    NGD_HIP_TRY(hipGetLastError());
+    if (below > 0) {
+      // L21 = A21 L11^{-T}, row by row
+      hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, s, M, n, j0, nb,
+                         M + (int64_t)(j0 + nb) * n, (int64_t)n, (int64_t)below);
+      NGD_HIP_TRY(hipGetLastError());
+      // A22 -= L21 L21^T
+      const int t0 = j0 + nb;
+      GemmArgs g{below, below, nb, M + (int64_t)t0 * n + j0, n, true, M + (int64_t)t0 * n + j0, n, true,
+                 M + (int64_t)t0 * n + t0, n, NGD_F64, NGD_F64, NGD_F64, G_F64, -1.0, 1.0};
+      ngd_status st = launch_gemm(g, s);
+      if (st != NGD_OK) return st;
+    }
+  }
+  return NGD_OK;
+}
+
+// X (nrows x n, FP64, ld ldx) <- X L^{-T} with L from launch_shifted_cholesky
+ngd_status launch_trsm_right_lt(const double* L, int n, double* X, int64_t ldx, int64_t nrows, hipStream_t s) {
+  for (int j0 = 0; j0 < n; j0 += kNb) {
+    const int nb = std::min(kNb, n - j0);
+    if (j0 > 0) {
+      // X_J -= X_<J L_J,<J^T
+      GemmArgs g{nrows, nb, j0, X, ldx, true, L + (int64_t)j0 * n, n, true, X + j0, ldx, NGD_F64, NGD_F64, NGD_F64,
+                 G_F64, -1.0, 1.0};
+      ngd_status st = launch_gemm(g, s);
+      if (st != NGD_OK) return st;
+    }
+    hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, s, L, n, j0, nb, X, ldx,
+                       nrows);
+    NGD_HIP_TRY(hipGetLastError());
+  }
+  return NGD_OK;
+}
+
+}  // namespace ngd

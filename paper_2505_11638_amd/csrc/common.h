@@ -131,6 +131,8 @@ struct GemmArgs {
   int a_type, b_type, c_type;                  // storage types: NGD_F64 / NGD_F32
   int compute;                                 // GemmType
   double alpha, beta;
+  double* work = nullptr;                      // optional split-K workspace (FP64)
+  int64_t work_elems = 0;                      // its size in doubles
 };
 ngd_status launch_gemm(const GemmArgs& a, hipStream_t s);
 
@@ -163,6 +165,11 @@ ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld
                              hipStream_t s);
 ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
+
+// chol.hip: blocked shifted Cholesky of the core and the right triangular solve X <- X L^{-T}
+ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
+                                   hipStream_t s);
+ngd_status launch_trsm_right_lt(const double* L, int n, double* X, int64_t ldx, int64_t nrows, hipStream_t s);
 
 // nystrom helpers (misc.hip)
 ngd_status launch_whitening(const double* evals, const double* evec_rows, int ell, double* F, hipStream_t s);

@@ -68,7 +68,8 @@ template <typename TA, typename TB, typename TC, typename E>
 __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
                                                   int64_t lda, int a_kmajor, const TB* __restrict__ B, int64_t ldb,
                                                   int b_kmajor, TC* __restrict__ C, int64_t ldc, double alpha,
-                                                  double beta, int n_tiles_n) {
+                                                  double beta, int n_tiles_n, int64_t kchunk,
+                                                  double* __restrict__ work) {
   constexpr int BK = Cfg<E>::BK;
   constexpr bool IS_BF = sizeof(E) == 2;
   constexpr int A_ELEMS = IS_BF ? BM * (BK + 8) : BK * (BM + 4);
@@ -91,16 +92,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
 
   Stager<TA, E, BK, BM> sa;
   Stager<TB, E, BK, BN> sb;
-  sa.load(A, lda, a_kmajor, m0, M, 0, K);
-  sb.load(B, ldb, b_kmajor, n0, N, 0, K);
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
+  const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+  const int64_t kend = (kbeg + kchunk) < K ? (kbeg + kchunk) : K;
+  sa.load(A, lda, a_kmajor, m0, M, kbeg, kend);
+  sb.load(B, ldb, b_kmajor, n0, N, kbeg, kend);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
     sa.store(As, a_kmajor);
     sb.store(Bs, b_kmajor);
     __syncthreads();
-    if (k0 + BK < K) {
-      sa.load(A, lda, a_kmajor, m0, M, k0 + BK, K);
-      sb.load(B, ldb, b_kmajor, n0, N, k0 + BK, K);
+    if (k0 + BK < kend) {
+      sa.load(A, lda, a_kmajor, m0, M, k0 + BK, kend);
+      sb.load(B, ldb, b_kmajor, n0, N, k0 + BK, kend);
     }
     if constexpr (IS_BF) {
       bf8 a[2], b[2];
@@ -149,11 +152,29 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
         const int64_t gm = m0 + wm + i * 16 + row_in_tile;
         const int64_t gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
-          double v = alpha * (double)acc[i][j][r];
-          if (beta != 0.0) v += beta * (double)C[gm * ldc + gn];
-          C[gm * ldc + gn] = (TC)v;
+          if (work != nullptr) {  // split-K: raw partial sum of this K-slice
+            work[((int64_t)blockIdx.y * M + gm) * N + gn] = (double)acc[i][j][r];
+          } else {
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * (double)C[gm * ldc + gn];
+            C[gm * ldc + gn] = (TC)v;
+          }
         }
       }
+}
+
+// C = alpha * sum_s work[s] + beta * C, slices summed in a fixed order (deterministic)
+template <typename TC>
+__global__ void splitk_reduce_kernel(const double* __restrict__ work, int ks, int64_t M, int64_t N, TC* __restrict__ C,
+                                     int64_t ldc, double alpha, double beta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t m = idx / N, n = idx - m * N;
+  double acc = 0.0;
+  for (int s = 0; s < ks; ++s) acc += work[(int64_t)s * M * N + idx];
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * (double)C[m * ldc + n];
+  C[m * ldc + n] = (TC)v;
 }
 
 template <typename TA, typename TB, typename TC, typename E>
@@ -161,10 +182,23 @@ ngd_status run(const GemmArgs& g, hipStream_t s) {
   const int tn = (int)((g.N + BN - 1) / BN), tm = (int)((g.M + BM - 1) / BM);
   const int64_t tiles = (int64_t)tn * tm;
   if (tiles == 0) return NGD_OK;
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, E>), dim3((unsigned)tiles), dim3(NT), 0, s, g.M, g.N, g.K,
+  constexpr int BK = Cfg<E>::BK;
+  // split K when the output has too few tiles to fill the chip (Gram matrices of the ell x ell core)
+  int ks = 1;
+  if (g.work != nullptr && g.work_elems > 0) {
+    while (tiles * ks * 2 <= 1024 && g.K / (ks * 2) >= 8 * BK && (int64_t)ks * 2 * g.M * g.N <= g.work_elems) ks *= 2;
+  }
+  const int64_t kchunk = ks == 1 ? g.K : ((g.K + ks - 1) / ks + BK - 1) / BK * BK;
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, E>), dim3((unsigned)tiles, (unsigned)ks), dim3(NT), 0, s, g.M, g.N, g.K,
                      (const TA*)g.A, g.lda, (int)g.a_kmajor, (const TB*)g.B, g.ldb, (int)g.b_kmajor, (TC*)g.C, g.ldc,
-                     g.alpha, g.beta, tn);
+                     g.alpha, g.beta, tn, kchunk, ks > 1 ? g.work : nullptr);
   NGD_HIP_TRY(hipGetLastError());
+  if (ks > 1) {
+    const int64_t mn = g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel<TC>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.work, ks, g.M,
+                       g.N, (TC*)g.C, g.ldc, g.alpha, g.beta);
+    NGD_HIP_TRY(hipGetLastError());
+  }
   return NGD_OK;
 }
 

@@ -24,15 +24,25 @@ struct RowRegs {
   typename Vec<T>::type c[NK];
 };
 
-template <typename T, int NK>
-__device__ __forceinline__ void load_row(const T* __restrict__ row, int64_t nchunk, RowRegs<T, NK>& r) {
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// Row loads through a raw buffer resource over this workgroup's rows: the per-lane byte offset is
+// one VGPR and the per-row / per-chunk offset a scalar, so holding NK chunks of the current and
+// the next row costs no address registers; reads past the rows' extent return 0.
+template <typename T, int K0, int K1>
+__device__ __forceinline__ void load_chunks(__amdgpu_buffer_rsrc_t rsrc, int row_bytes, int64_t nchunk,
+                                            typename Vec<T>::type* dst) {
   using V = typename Vec<T>::type;
-  const V* rv = reinterpret_cast<const V*>(row);
+  const int vo = threadIdx.x * 16;
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
+  for (int k = K0; k < K1; ++k) {
     int64_t q = threadIdx.x + (int64_t)k * blockDim.x;
-    if (q < nchunk) r.c[k] = __builtin_nontemporal_load(rv + q);
-    else r.c[k] = V{};
+    if (q < nchunk) {
+      v4u raw = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vo, row_bytes + k * (int)blockDim.x * 16, 0);
+      dst[k - K0] = __builtin_bit_cast(V, raw);
+    } else {
+      dst[k - K0] = V{};
+    }
   }
 }
 
@@ -62,23 +72,32 @@ __device__ __forceinline__ void axpy_vec<double>(double t, const vd2& a, vd2& y)
 template <typename T, int NK>
 __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, int64_t r0, int64_t r1,
                                           const T* vs, RowRegs<T, NK>& acc, double& tsq) {
+  using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
+  constexpr int H = (NK + 1) / 2;  // chunks of the next row prefetched before the reduction
   __shared__ double red[2][16];
   const int64_t nchunk = ldJ / VN;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NK; ++k) acc.c[k] = typename Vec<T>::type{};
+  for (int k = 0; k < NK; ++k) acc.c[k] = V{};
   if (r0 >= r1) return;
-  RowRegs<T, NK> cur, nxt;
-  load_row<T, NK>(J + r0 * ldJ, nchunk, cur);
+  const int row_bytes = (int)(ldJ * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(J + r0 * ldJ), (short)0, (int)((r1 - r0) * row_bytes), 0x00020000);
+  V cur[NK];
+  load_chunks<T, 0, NK>(rsrc, 0, nchunk, cur);
   int parity = 0;
   for (int64_t r = r0; r < r1; ++r) {
-    if (r + 1 < r1) load_row<T, NK>(J + (r + 1) * ldJ, nchunk, nxt);
+    const bool more = r + 1 < r1;
+    const int next_bytes = (int)(r + 1 - r0) * row_bytes;
+    // first half of the next row in flight during the dot product and the reduction
+    V nxt_a[H];
+    if (more) load_chunks<T, 0, H>(rsrc, next_bytes, nchunk, nxt_a);
     T dot = 0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       int64_t q = threadIdx.x + (int64_t)k * blockDim.x;
-      if (q < nchunk) dot += dot_vec<T>(cur.c[k], vs + q * VN);
+      if (q < nchunk) dot += dot_vec<T>(cur[k], vs + q * VN);
     }
     dot = wave_sum(dot);
     if (lane == 0) red[parity][wid] = (double)dot;
@@ -89,9 +108,16 @@ __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, 
     tsq += t * t;
     const T tt = (T)t;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) axpy_vec<T>(tt, cur.c[k], acc.c[k]);
+    for (int k = 0; k < H; ++k) axpy_vec<T>(tt, cur[k], acc.c[k]);
+    // second half of the next row, into the registers the first half just released
+    V nxt_b[NK - H > 0 ? NK - H : 1];
+    if (more) load_chunks<T, H, NK>(rsrc, next_bytes, nchunk, nxt_b);
 #pragma unroll
-    for (int k = 0; k < NK; ++k) cur.c[k] = nxt.c[k];
+    for (int k = H; k < NK; ++k) axpy_vec<T>(tt, cur[k], acc.c[k]);
+#pragma unroll
+    for (int k = 0; k < H; ++k) cur[k] = nxt_a[k];
+#pragma unroll
+    for (int k = H; k < NK; ++k) cur[k] = nxt_b[k - H];
   }
 }
 
@@ -132,14 +158,35 @@ __global__ __launch_bounds__(1024) void gram_rows_kernel(const T* __restrict__ J
   if (threadIdx.x == 0 && tsq_out) tsq_out[blockIdx.x] = tsq;
 }
 
+// Column sums of the workgroup partials: a block covers kRedCols columns with kRedGroups threads
+// per column, each summing every kRedGroups-th partial; the groups are then added in a fixed order.
+constexpr int kRedCols = 32, kRedGroups = 8;
+
 template <typename T>
-__global__ void gram_reduce_kernel(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
-                                   const double* __restrict__ v, double lambda, double* __restrict__ y) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P) return;
+__device__ __forceinline__ double sum_partials(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
+                                               double (*buf)[kRedCols], int64_t* j_out) {
+  const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
+  const int64_t j = (int64_t)blockIdx.x * kRedCols + c;
   double acc = 0;
-  for (int b = 0; b < nwg; ++b) acc += (double)partial[(int64_t)b * ld + j];
-  y[j] = acc + lambda * v[j];
+  if (j < P)
+    for (int b = g; b < nwg; b += kRedGroups) acc += (double)partial[(int64_t)b * ld + j];
+  buf[g][c] = acc;
+  __syncthreads();
+  double tot = 0;
+  if (g == 0)
+    for (int q = 0; q < kRedGroups; ++q) tot += buf[q][c];
+  *j_out = j;
+  return tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ partial, int nwg, int64_t ld,
+                                                          int64_t P, const double* __restrict__ v, double lambda,
+                                                          double* __restrict__ y) {
+  __shared__ double buf[kRedGroups][kRedCols];
+  int64_t j;
+  const double acc = sum_partials(partial, nwg, ld, P, buf, &j);
+  if (threadIdx.x < kRedCols && j < P) y[j] = acc + lambda * v[j];
 }
 
 // ---------------- fused PCG iteration ----------------
@@ -195,10 +242,10 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
   const double alpha = s_alpha;
   const int bad = s_bad;
   double rr = 0;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (!bad && j < P) {
-    double q = 0;
-    for (int b = 0; b < nwg; ++b) q += (double)partial[(int64_t)b * ld + j];
+  __shared__ double buf[kRedGroups][kRedCols];
+  int64_t j;
+  double q = sum_partials(partial, nwg, ld, P, buf, &j);
+  if (!bad && threadIdx.x < kRedCols && j < P) {
     q += st->lambda * p[j];
     const double xj = x[j] + alpha * p[j];
     const double rj = r[j] - alpha * q;
@@ -433,7 +480,7 @@ ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, in
 
 ngd_status launch_gram_reduce(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* v,
                               double lambda, double* y, hipStream_t s) {
-  dim3 grid((unsigned)((P + 255) / 256));
+  dim3 grid((unsigned)((P + kRedCols - 1) / kRedCols));
   if (dtype == NGD_F64)
     hipLaunchKernelGGL(gram_reduce_kernel<double>, grid, dim3(256), 0, s, (const double*)partial, nwg, ld, P, v,
                        lambda, y);
@@ -508,7 +555,7 @@ ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int
 ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,
                              const double* tsq, double* x, double* r, double* rr_part, PcgState* st, int plain,
                              hipStream_t s) {
-  dim3 grid((unsigned)((P + 255) / 256));
+  dim3 grid((unsigned)((P + kRedCols - 1) / kRedCols));
   if (dtype == NGD_F64)
     hipLaunchKernelGGL(pcg_update_kernel<double>, grid, dim3(256), 0, s, (const double*)partial, nwg, ld, P, p, tsq,
                        x, r, rr_part, st, plain);

@@ -131,6 +131,31 @@ def test_nystrom_sketch_matches_alg6(name):
     _nystrom_compare(prob, th, gp)
 
 
+@pytest.mark.parametrize("ell", [1, 2, 3, 5])
+def test_nystrom_sketch_small_ell(ell):
+    prob, th, gp = _setup("poisson2d_f64")
+    import dataclasses
+    _nystrom_compare(dataclasses.replace(prob, ell=ell), th, gp)
+
+
+def test_nystrom_exact_when_rank_below_ell():
+    """N = 14 rows < ell = 24: the sketch captures range(G) and G_nys = G (eq. nystrom_approx)."""
+    prob, th = make(wl.small_problem(widths=(2, 16, 16, 1), n_interior=9, n_boundary=5, seed=8, ell=24, lam=1e-6))
+    gp = Problem(prob, dtype="f64", max_ell=24)
+    theta = gp.theta(th)
+    J = gp.new_jacobian()
+    gp.residual_jacobian(theta, J)
+    Jg = J.cpu().numpy()[:, :gp.P]
+    G = Jg.T @ Jg
+    res = gp.nystrom_sketch(J, 24, seed=3)
+    U = res.U.cpu().numpy()[:, :gp.P]
+    lam = res.lam_hat.cpu().numpy()
+    assert np.linalg.norm(U.T @ (lam[:, None] * U) - G) <= 1e-10 * np.linalg.norm(G)
+    assert res.info["rank"] <= 14 and res.info["rank_z"] <= 14
+    ev = np.sort(np.linalg.eigvalsh(G))[::-1]
+    np.testing.assert_allclose(lam[:14], ev[:14], rtol=0, atol=1e-10 * ev[0])
+
+
 def test_nystrom_sketch_bf16_before_refinement():
     prob, th, gp = _setup("poisson2d_f32")
     _nystrom_compare(prob, th, gp, sketch_dtype="bf16", tol=2e-2)
