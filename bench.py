@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dense MFMA peaks (TFLOP/s) by the sketch's compute type
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 WORKLOADS = {
     "c1": "2D Poisson 2-32-32-1 tanh (P=1,185), 30x30 grid + 120 boundary points, FP64, ell=100, "
@@ -75,6 +77,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cg", action="store_true", help="skip the plain-CG comparison loop")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (known bytes) to calibrate the HBM traffic counters")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -107,14 +112,25 @@ def main(argv=None):
     nys_sps = a.steps / (t1 - t0)
 
     # ---- plain CG NGD (same start, power-method damping, maxit = P) ----
-    cg = NGD(prob, theta0, solver="cg", rtol=rtol, seed=a.seed)
-    cg.step()  # warmup
-    torch.cuda.synchronize()
-    c0 = time.perf_counter()
-    creps = [cg.step() for _ in range(a.cg_steps)]
-    torch.cuda.synchronize()
-    c1 = time.perf_counter()
-    cg_sps = a.cg_steps / (c1 - c0)
+    cg = None
+    creps, cg_sps = [], float("nan")
+    if not a.no_cg:
+        cg = NGD(prob, theta0, solver="cg", rtol=rtol, seed=a.seed)
+        cg.step()  # warmup
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        creps = [cg.step() for _ in range(a.cg_steps)]
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        cg_sps = a.cg_steps / (c1 - c0)
+
+    if a.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- roofline of the one-pass Gramian matvec kernel ----
     n_mv, ms_mv = timers["matvec_rows"]
@@ -124,6 +140,12 @@ def main(argv=None):
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     phases = {k: {"launches": n, "avg_ms": (ms / n if n else 0.0), "ms_per_step": ms / a.steps}
               for k, (n, ms) in timers.items()}
+    # ---- MFMA roofline of the two sketch contractions (Z = J Omega, B^T = Q^T J) ----
+    sk_n = timers["sketch_z"][0] + timers["sketch_w"][0]
+    sk_ms = timers["sketch_z"][1] + timers["sketch_w"][1]
+    sk_flops = 2.0 * N * P * prob.ell
+    sk_achieved = sk_flops / (sk_ms / max(sk_n, 1) * 1e-3) / 1e12 if sk_n else 0.0
+    sk_peak = MFMA_PEAK_TFLOPS[prob.sketch_dtype]
 
     line = {
         "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
@@ -140,23 +162,29 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}", "P": P, "N": N, "ell": prob.ell,
                    "sketch_dtype": prob.sketch_dtype},
-        "plain_cg": {"value": cg_sps, "unit": "NGD steps/s", "steps": a.cg_steps,
-                     "mean_cg_iters": float(np.mean([r.iters for r in creps])),
-                     "converged": all(r.converged for r in creps)},
+        "plain_cg": ({"value": cg_sps, "unit": "NGD steps/s", "steps": a.cg_steps,
+                      "mean_cg_iters": float(np.mean([r.iters for r in creps])),
+                      "converged": all(r.converged for r in creps)} if creps else None),
         "nystrom_mean_pcg_iters": float(np.mean([r.iters for r in reps])),
         "nystrom_converged": all(r.converged for r in reps),
-        "speedup_vs_plain_cg": nys_sps / cg_sps,
+        "speedup_vs_plain_cg": (nys_sps / cg_sps) if creps else None,
         "matvec_gbs": achieved,
         "loss_first_last": [reps[0].loss, reps[-1].loss_new],
         "phases": phases,
         "roofline": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv},
+        "roofline_sketch": {"bound": "mfma", "kernel": "gemm_kernel (Z = J Omega and B^T = Q^T J)",
+                            "achieved": sk_achieved, "peak": sk_peak, "unit": "TFLOP/s",
+                            "frac": sk_achieved / sk_peak, "compute_dtype": prob.sketch_dtype,
+                            "alg_flops_per_launch": sk_flops, "avg_launch_ms": sk_ms / max(sk_n, 1),
+                            "launches": sk_n},
     }
     # release the library handles while the runtime is alive
     torch.cuda.synchronize()
     nys.gp.close()
-    cg.gp.close()
+    if cg is not None:
+        cg.gp.close()
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(a.config, a.seed, a.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -63,6 +63,8 @@ struct ngd_problem {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double t_ms[NGD_NUM_TIMERS] = {};
   int64_t t_n[NGD_NUM_TIMERS] = {};
+  // iterations of the previous solve (index: plain CG), used to size the first launch chunk
+  int64_t last_iters[2] = {4, 4};
 };
 
 namespace {
@@ -90,6 +92,19 @@ ngd_status flush_timers(ngd_problem* h) {
   }
   h->ev_pending.clear();
   return NGD_OK;
+}
+
+// Forget the last `count` pending records of timer `id` (launches that found the solver done and
+// returned at once; they are not launches of the timed kernel's work).
+void drop_tail(ngd_problem* h, int id, int64_t count) {
+  for (auto it = h->ev_pending.end(); count > 0 && it != h->ev_pending.begin();) {
+    --it;
+    if (it->first != id) continue;
+    h->ev_free.push_back(it->second.first);
+    h->ev_free.push_back(it->second.second);
+    it = h->ev_pending.erase(it);
+    --count;
+  }
 }
 
 // Run `fn` (which enqueues one kernel sequence on s); when timing is on, bracket it with events.
@@ -445,8 +460,11 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
                                h->pcg_r, h->pcg_z, h->pcg_part, h->pcg_st, s));
     zsrc = h->pcg_z;
   }
+  // Iterations are enqueued in chunks between host polls of the device state. The first chunk is the
+  // previous solve's iteration count; later ones follow the observed residual decay, so that few
+  // iterations are enqueued past convergence (they return at once) and few polls are needed.
   int64_t k = 0;
-  int64_t chunk = 4;
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(64, h->last_iters[plain]));
   while (true) {
     const int64_t upto = std::min<int64_t>(maxit, k + chunk);
     for (; k < upto; ++k) {
@@ -467,8 +485,24 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
     NGD_HIP_TRY(hipMemcpyAsync(hs, h->pcg_st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
     if (hs->done || k >= maxit) break;
-    chunk = std::min<int64_t>(chunk * 2, 64);
+    // rr_k ~ bnorm2 rate^k: predict the iterations left to reach rtol^2 bnorm2
+    int64_t guess = 1;
+    if (hs->rr > 0.0 && hs->bnorm2 > 0.0 && hs->rr < hs->bnorm2 && k > 0) {
+      const double lrate = std::log(hs->rr / hs->bnorm2) / (double)k;
+      const double need = std::log(hs->rtol2bb / hs->rr) / lrate;
+      if (std::isfinite(need)) guess = (int64_t)std::ceil(std::max(1.0, need));
+    } else {
+      guess = chunk;
+    }
+    chunk = std::max<int64_t>(1, std::min<int64_t>(64, guess));
   }
+  if (hs->done) {
+    // launches enqueued after the iteration that finished the solve did no work
+    const int64_t idle = k - hs->iters;
+    if (idle > 0) drop_tail(h, NGD_TIMER_MATVEC_ROWS, idle);
+    if (!plain) drop_tail(h, NGD_TIMER_PRECOND, idle + (hs->iters > 0 ? 1 : 0));
+  }
+  h->last_iters[plain] = hs->iters;
   info->iters = hs->iters;
   info->rel_res = hs->bnorm2 > 0 ? std::sqrt(hs->rr / hs->bnorm2) : 0.0;
   info->converged = hs->converged;

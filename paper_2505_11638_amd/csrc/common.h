@@ -83,6 +83,14 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return s;
 }
 
+// Sum of a[0..n) by the whole block in a fixed order (strided per-thread sums, then block_sum):
+// deterministic for a given blockDim. Every thread gets the result.
+__device__ __forceinline__ double block_sum_array(const double* __restrict__ a, int n, double* red) {
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
+  return block_sum(s, red);
+}
+
 // Last-block detection for deterministic two-stage reductions inside one launch: every block
 // publishes its partial, then the block that arrives last sees all partials.
 __device__ __forceinline__ bool arrive_last(unsigned* counter) {

@@ -168,8 +168,18 @@ __device__ __forceinline__ double sum_partials(const T* __restrict__ partial, in
   const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
   const int64_t j = (int64_t)blockIdx.x * kRedCols + c;
   double acc = 0;
-  if (j < P)
-    for (int b = g; b < nwg; b += kRedGroups) acc += (double)partial[(int64_t)b * ld + j];
+  if (j < P) {
+    // eight loads in flight per thread; the order of the additions is fixed
+    int b = g;
+    for (; b + 7 * kRedGroups < nwg; b += 8 * kRedGroups) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(b + u * kRedGroups) * ld + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; b < nwg; b += kRedGroups) acc += (double)partial[(int64_t)b * ld + j];
+  }
   buf[g][c] = acc;
   __syncthreads();
   double tot = 0;
@@ -228,19 +238,10 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
                                                          int plain_cg) {
   if (st->done) return;
   __shared__ double red[4];
-  __shared__ double s_alpha;
-  __shared__ int s_bad;
-  if (threadIdx.x == 0) {
-    double pGp = 0;
-    for (int b = 0; b < nwg; ++b) pGp += tsq[b];
-    const double pq = pGp + st->lambda * st->pp;
-    const double a = st->rz / pq;
-    s_bad = !(pq > 0.0) || !isfinite(a);
-    s_alpha = a;
-  }
-  __syncthreads();
-  const double alpha = s_alpha;
-  const int bad = s_bad;
+  const double pGp = block_sum_array(tsq, nwg, red);
+  const double pq = pGp + st->lambda * st->pp;
+  const double alpha = st->rz / pq;
+  const int bad = !(pq > 0.0) || !isfinite(alpha);
   double rr = 0;
   __shared__ double buf[kRedGroups][kRedCols];
   int64_t j;
@@ -255,14 +256,14 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
   }
   rr = block_sum(rr, red);
   if (threadIdx.x == 0) rr_part[blockIdx.x] = rr;
-  if (arrive_last(&st->counter) && threadIdx.x == 0) {
+  if (!arrive_last(&st->counter)) return;
+  const double tot = block_sum_array(rr_part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) {
     if (bad) {
       st->breakdown = 1;
       st->done = 1;
       return;
     }
-    double tot = 0;
-    for (int b = 0; b < (int)gridDim.x; ++b) tot += rr_part[b];
     st->alpha = alpha;
     st->iters += 1;
     st->rr = tot;
@@ -322,9 +323,9 @@ __global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict_
   if (st == nullptr) return;
   rz = block_sum(rz, red);
   if (threadIdx.x == 0) rz_part[blockIdx.x] = rz;
-  if (arrive_last(&st->counter) && threadIdx.x == 0) {
-    double tot = 0;
-    for (int b = 0; b < (int)gridDim.x; ++b) tot += rz_part[b];
+  if (!arrive_last(&st->counter)) return;
+  const double tot = block_sum_array(rz_part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) {
     if (st->iters == 0 && st->beta == 0.0) {
       st->rz = tot;                       // initial z_0 = P^{-1} r_0
     } else {
@@ -355,9 +356,9 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
   }
   gg = block_sum(gg, red);
   if (threadIdx.x == 0) part[blockIdx.x] = gg;
-  if (arrive_last(&st->counter) && threadIdx.x == 0) {
-    double tot = 0;
-    for (int b = 0; b < (int)gridDim.x; ++b) tot += part[b];
+  if (!arrive_last(&st->counter)) return;
+  const double tot = block_sum_array(part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) {
     st->bnorm2 = tot;
     st->rr = tot;
     st->rtol2bb = rtol * rtol * tot;
@@ -386,11 +387,9 @@ __global__ void dot_stage_kernel(const double* __restrict__ a, const double* __r
     acc += a[j] * b[j];
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
-  if (arrive_last(counter) && threadIdx.x == 0) {
-    double tot = 0;
-    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) tot += part[b2];
-    *out = tot;
-  }
+  if (!arrive_last(counter)) return;
+  const double tot = block_sum_array(part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) *out = tot;
 }
 
 __global__ void scale_by_rsqrt_kernel(const double* __restrict__ w, const double* __restrict__ ww, int64_t n,

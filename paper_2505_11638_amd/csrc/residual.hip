@@ -353,6 +353,8 @@ int residual_block_rows(const NetDesc& net, int dtype) {
 static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes) {
   int tp = 16;
   while (tp > 1 && lds_elems(net, tp) * elem > 96 * 1024) tp >>= 1;
+  // wide layers: trade occupancy for more points per staged weight matrix
+  while (tp < 4 && lds_elems(net, 2 * tp) * elem <= 150 * 1024) tp <<= 1;
   *bytes = lds_elems(net, tp) * elem;
   return tp;
 }
