@@ -65,7 +65,8 @@ SIGNATURES = {
     "ngd_timing_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
 
-TIMERS = {"matvec_rows": 0, "residual_jacobian": 1, "sketch_z": 2, "sketch_w": 3, "core": 4, "precond": 5}
+TIMERS = {"matvec_rows": 0, "residual_jacobian": 1, "sketch_z": 2, "sketch_w": 3, "core": 4, "precond": 5,
+          "sketch_prep": 6}
 
 _lib = None
 

@@ -46,6 +46,12 @@ struct ngd_problem {
   void* Z;           // N x max_ell, dtype
   void* Q;           // N x max_ell, FP64 (orthonormal basis of range(Z))
   void* Bt;          // max_ell x ldP, dtype
+  int64_t ldN;       // row stride of the transposed sketch operands (N rounded up to 64)
+  void* Jt;          // P x ldN, J_w^T in the sketch compute type (FP32 problems)
+  void* Qt;          // max_ell x ldN, Q^T in the sketch compute type (FP32 problems)
+  void* Ob;          // max_ell x ldP, Omega^T in BF16 (FP32 problems)
+  float* sk_work;    // split-K partials of the sketch products (FP32 problems)
+  int64_t sk_work_elems;
   double* M;         // ell x ell
   double* Ev;        // ell x ell eigenvectors (rows)
   double* F;         // ell x ell
@@ -252,6 +258,14 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({&h->Z, (size_t)N * L * e});
   plan.push_back({&h->Q, (size_t)N * L * sizeof(double)});
   plan.push_back({&h->Bt, (size_t)L * ldP * e});
+  h->ldN = (int64_t)align_up((size_t)N, 64);
+  if (d->dtype == NGD_F32) {  // sized for FP32, which also holds the BF16 copies
+    plan.push_back({&h->Jt, (size_t)P * h->ldN * 4});
+    plan.push_back({&h->Qt, (size_t)L * h->ldN * 4});
+    plan.push_back({&h->Ob, (size_t)L * ldP * 2});
+    h->sk_work_elems = (int64_t)16 << 20;  // 64 MB
+    plan.push_back({(void**)&h->sk_work, (size_t)h->sk_work_elems * 4});
+  }
   plan.push_back({(void**)&h->M, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->Ev, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
@@ -382,9 +396,32 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     omega = h->omega;
     ldO = h->ldP;
   }
+  // the NT kernel (large tiles, both operands K-contiguous) serves the FP32 / BF16 sketch
+  const int et = gt == G_BF16 ? NGD_BF16 : NGD_F32;
+  const bool nt = T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
+                  nt_gemm_supported(et, et, gt, P, L, N, h->ldN, h->ldN);
+  // Omega^T in the compute type (BF16: a rounded copy, read at half the bytes)
+  const void* om_nt = omega;
+  int64_t ld_nt = ldO;
+  int om_type = NGD_F32;
+  if (nt && gt == G_BF16) {
+    NGD_TRY(launch_cast_rows(NGD_F32, omega, ldO, L, P, NGD_BF16, h->Ob, h->ldP, s));
+    om_nt = h->Ob;
+    ld_nt = h->ldP;
+    om_type = NGD_BF16;
+  }
   // Z = J Omega (N x ell)
-  GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
-  NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] { return launch_gemm(g1, s); }));
+  NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] {
+    if (nt) return launch_nt_gemm(NGD_F32, op->J, op->ldJ, om_type, om_nt, ld_nt, gt, N, L, P, NGD_F32, h->Z, L,
+                                  false, 1.0, h->sk_work, h->sk_work_elems, s);
+    GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
+    return launch_gemm(g1, s);
+  }));
+  // J^T in the compute type for the second product; independent of the core below
+  if (nt)
+    NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, s, [&] {
+      return launch_transpose_cast(NGD_F32, op->J, op->ldJ, N, P, et, h->Jt, h->ldN, s);
+    }));
   // M = Z^T Z (FP64), eigenpairs, whitening F = V_M D^{-1/2} (pseudo-inverse of the core), and
   // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
@@ -397,9 +434,17 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     NGD_TRY(launch_cast(T, h->Z, NGD_F64, h->Q, N * L, s));
     return launch_trsm_right_lt(h->M, (int)L, (double*)h->Q, L, N, s);
   }));
-  // B^T = Q^T J (ell x P)
-  GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
-  NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] { return launch_gemm(g4, s); }));
+  // B^T = Q^T J (ell x P); on the NT path as (J^T Q)^T with Q^T in the compute type
+  if (nt)
+    NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, s, [&] {
+      return launch_transpose_cast(NGD_F64, h->Q, L, N, L, et, h->Qt, h->ldN, s);
+    }));
+  NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
+    if (nt) return launch_nt_gemm(et, h->Jt, h->ldN, et, h->Qt, h->ldN, gt, P, L, N, NGD_F32, h->Bt, h->ldP, true,
+                                  1.0, h->sk_work, h->sk_work_elems, s);
+    GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
+    return launch_gemm(g4, s);
+  }));
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
     GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,

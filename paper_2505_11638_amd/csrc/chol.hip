@@ -122,7 +122,8 @@ ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double fl
   for (int j0 = 0; j0 < n; j0 += kNb) {
     const int nb = std::min(kNb, n - j0);
     const int below = n - j0 - nb;
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, M, n, j0, nb, scal, nmod);
+    // a single wave: its barriers are nearly free, and the block is small
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, s, M, n, j0, nb, scal, nmod);
     NGD_HIP_TRY(hipGetLastError());
     if (below > 0) {
       // L21 = A21 L11^{-T}, row by row

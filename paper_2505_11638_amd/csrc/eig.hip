@@ -29,29 +29,35 @@ struct TriArgs {
   double* V;       // Householder vectors, row k = v_k (support k+1..n-1, v_k[k+1] = 1)
   double* tau;     // Householder scalars
   double* p;       // n: p = tau A v of the current step
-  unsigned* bar;   // [0] arrival count, [1] generation
+  unsigned* flags; // one barrier flag per workgroup
   int* err;
 };
 
-// Grid barrier number `epoch` (0, 1, 2, ...) on a counter that starts at 0 for the launch: every
-// workgroup adds 1 and waits for (epoch + 1) * gridDim.x arrivals. One agent-scope release fence
-// before arriving and one acquire fence after the wait (each is an L2 write-back or invalidate on
-// this GPU, so they are kept to the minimum). The wait is bounded: on timeout it raises `err`.
-__device__ bool grid_sync(unsigned* count, unsigned epoch, int* err) {
+// Grid barrier number `epoch` (0, 1, 2, ...): workgroup g publishes epoch + 1 in its own flag (no
+// contended atomic) and wave 0 polls all flags. One agent-scope release fence before publishing and
+// one acquire fence after the wait (each is an L2 write-back or invalidate on this GPU, so they are
+// kept to the minimum). The wait is bounded: on timeout it raises `err`.
+__device__ bool grid_sync(unsigned* flags, unsigned epoch, int* err) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned target = (epoch + 1u) * gridDim.x;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const unsigned target = epoch + 1u;
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     long spins = 0;
-    while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (true) {
+      int ok = 1;
+      for (int g = threadIdx.x; g < (int)gridDim.x; g += 64)
+        ok &= __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+      if (__all(ok)) break;
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1L << 25)) {  // a few seconds: give up instead of hanging
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (++spins > (1L << 24)) {  // seconds: give up instead of hanging
+        if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
@@ -61,7 +67,8 @@ __device__ bool grid_sync(unsigned* count, unsigned epoch, int* err) {
 // rows i = g, g + G, g + 2G, ... Each step applies the previous step's rank-2 update (v, w) to the
 // owned rows in place, forms p_i = tau A_i . v, and the owner of row k+1 publishes that updated row
 // (the next pivot row) to global memory. After one grid barrier every workgroup reads p and the
-// pivot row, forms w = p - (tau/2)(p . v) v and, from the pivot row, the next Householder vector.
+// pivot row together, forms w = p - (tau/2)(p . v) v and, from the pivot row, the next Householder
+// vector.
 __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, G = gridDim.x, g = blockIdx.x;
@@ -70,25 +77,28 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
   double* vprev = rows + (size_t)R * n;
   double* wprev = vprev + n;
   double* v = wprev + n;
+  double* pivl = v + n;  // the current pivot row
   __shared__ double red[8];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int r = 0; r < R; ++r) {
     const int i = g + r * G;
     for (int j = threadIdx.x; j < n; j += blockDim.x) rows[(size_t)r * n + j] = i < n ? a.A0[(int64_t)i * n + j] : 0.0;
   }
-  for (int j = threadIdx.x; j < n; j += blockDim.x) vprev[j] = wprev[j] = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    vprev[j] = wprev[j] = 0.0;
+    pivl[j] = a.A0[j];  // step 0: row 0 of A, no pending update
+  }
   __syncthreads();
-  const double* pivot = a.A0;  // step 0: row 0 of A, no pending update
   for (int k = 0; k + 2 < n; ++k) {
     // column k of A^(k) below the diagonal = pivot row k with the pending update applied
     double tail = 0.0;
     const double vk = vprev[k], wk = wprev[k];
     for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double x = pivot[j] - vk * wprev[j] - wk * vprev[j];
+      const double x = pivl[j] - vk * wprev[j] - wk * vprev[j];
       v[j] = x;
       if (j > k + 1) tail += x * x;
     }
-    const double dk = pivot[k] - 2.0 * vk * wk;
+    const double dk = pivl[k] - 2.0 * vk * wk;
     tail = block_sum(tail, red);
     const double alpha = v[k + 1];
     double tau, beta, scale;
@@ -132,16 +142,23 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
       acc = wave_sum(acc);
       if (lane == 0) a.p[i] = tau * acc;
     }
-    if (!grid_sync(a.bar, (unsigned)k, a.err)) return;
-    // w = p - (tau/2)(p . v) v, kept by every workgroup as the pending update
+    if (!grid_sync(a.flags, (unsigned)k, a.err)) return;
+    // p and the next pivot row are read together; w = p - (tau/2)(p . v) v is kept by every
+    // workgroup as the pending update
     double pv = 0.0;
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) pv += a.p[j] * v[j];
+    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
+      const double pj = a.p[j];
+      const double nx = next_pivot[j];
+      wprev[j] = pj;
+      pivl[j] = nx;
+      pv += pj * v[j];
+    }
     pv = block_sum(pv, red);
     const double c = 0.5 * tau * pv;
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       if (j > k) {
-        wprev[j] = a.p[j] - c * v[j];
+        wprev[j] = wprev[j] - c * v[j];
         vprev[j] = v[j];
       } else {
         wprev[j] = 0.0;
@@ -149,7 +166,6 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
       }
     }
     __syncthreads();
-    pivot = next_pivot;
   }
   // last 2 x 2 (or 1 x 1) block, from the owners' rows with the pending update
   if (threadIdx.x == 0) {
@@ -238,60 +254,65 @@ __global__ void bisect_kernel(const double* __restrict__ d, const double* __rest
 }
 
 // inverse iteration for eigenvalue i: solve (T - lam I) x = b by LU with partial pivoting
-// (tridiagonal; the U factor has two superdiagonals). Per-thread arrays are interleaved by thread
-// ([row][n]) so a wave's accesses are coalesced; the recurrences carry their values in registers
-// and every load address is known in advance, so the loads pipeline.
+// (tridiagonal; the U factor has two superdiagonals). A workgroup of `tpw` threads handles tpw
+// eigenvalues; d, e and the per-thread factor arrays live in LDS (interleaved by thread), so the
+// sequential recurrences wait on LDS rather than global-memory latency.
+constexpr int kInvArrays = 6;
 __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
                                                    const double* __restrict__ lam_asc,
                                                    const double* __restrict__ tnorm, double drop_rel,
-                                                   double* __restrict__ Z, double* __restrict__ wk) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   double* __restrict__ Z) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sd = reinterpret_cast<double*>(smem_raw);
+  double* se = sd + n;
+  double* arr = se + n;
+  const int tpw = blockDim.x;
+  for (int j = threadIdx.x; j < n; j += tpw) {
+    sd[j] = d[j];
+    se[j] = j < n - 1 ? e[j] : 0.0;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * tpw + t;
   if (i >= n) return;
   const double lam = lam_asc[i];
   const double drop = drop_rel * (*tnorm);
-  const int64_t nn = (int64_t)n * n;
-  double* __restrict__ rinv = wk;           // 1 / diagonal of U
-  double* __restrict__ u1 = wk + nn;        // first superdiagonal
-  double* __restrict__ u2 = wk + 2 * nn;    // second superdiagonal
-  double* __restrict__ ml = wk + 3 * nn;    // multipliers; sign bit = row interchange
-  double* __restrict__ y = wk + 4 * nn;     // right-hand side after the forward sweep
-#define W(arr, j) arr[(int64_t)(j) * n + i]
+#define W(k, j) arr[((int64_t)(k) * n + (j)) * tpw + t]
+  enum { RINV = 0, U1 = 1, U2 = 2, ML = 3, Y = 4, SWP = 5 };
   if (lam < drop) {
-    for (int j = 0; j < n; ++j) W(Z, j) = 0.0;
+    for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = 0.0;
     return;
   }
   const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
   // factorisation of T - lam I
-  double a = d[0] - lam, b = n > 1 ? e[0] : 0.0;
+  double a = sd[0] - lam, b = n > 1 ? se[0] : 0.0;
   for (int j = 0; j < n - 1; ++j) {
-    const double c = e[j], dn = d[j + 1] - lam, en = j + 1 < n - 1 ? e[j + 1] : 0.0;
+    const double c = se[j], dn = sd[j + 1] - lam, en = se[j + 1];
     double piv, m;
     if (fabs(a) >= fabs(c)) {
       piv = a;
       m = a != 0.0 ? c / a : 0.0;
-      W(u1, j) = b;
-      W(u2, j) = 0.0;
-      W(ml, j) = m;          // no interchange: stored as is (flag in a separate sign convention below)
+      W(U1, j) = b;
+      W(U2, j) = 0.0;
+      W(ML, j) = m;
       a = dn - m * b;
       b = en;
-      W(y, j) = 0.0;         // y doubles as the interchange flag during factorisation
+      W(SWP, j) = 0.0;
     } else {
       piv = c;
       m = a / c;
-      W(u1, j) = dn;
-      W(u2, j) = en;
-      W(ml, j) = m;
+      W(U1, j) = dn;
+      W(U2, j) = en;
+      W(ML, j) = m;
       a = b - m * dn;
       b = -m * en;
-      W(y, j) = 1.0;
+      W(SWP, j) = 1.0;
     }
     if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
-    W(rinv, j) = 1.0 / piv;
+    W(RINV, j) = 1.0 / piv;
   }
   if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-  W(rinv, n - 1) = 1.0 / a;
-  // interchange flags: keep them in the sign-free array `u2`'s companion by reusing Z as scratch
-  for (int j = 0; j < n - 1; ++j) W(Z, j) = W(y, j);
+  W(RINV, n - 1) = 1.0 / a;
   // start vector: deterministic pseudo-random entries in [0.5, 1.5)
   unsigned h = 2166136261u ^ ((unsigned)i * 16777619u);
   double scale = 1.0;
@@ -302,7 +323,7 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
       h = (h ^ 0u) * 16777619u + 0x9E3779B9u;
       carry = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
     } else {
-      carry = W(y, 0) * scale;
+      carry = W(Y, 0) * scale;
     }
     for (int j = 0; j < n - 1; ++j) {
       double nxt;
@@ -310,19 +331,19 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
         h = (h ^ (unsigned)(j + 1)) * 16777619u + 0x9E3779B9u;
         nxt = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
       } else {
-        nxt = W(y, j + 1) * scale;
+        nxt = W(Y, j + 1) * scale;
       }
-      const bool swp = W(Z, j) != 0.0;
+      const bool swp = W(SWP, j) != 0.0;
       const double x0 = swp ? nxt : carry, x1 = swp ? carry : nxt;
-      W(y, j) = x0;
-      carry = x1 - W(ml, j) * x0;
+      W(Y, j) = x0;
+      carry = x1 - W(ML, j) * x0;
     }
-    W(y, n - 1) = carry;
+    W(Y, n - 1) = carry;
     // backward substitution with U, in place on y; track the max-norm for scaling
     double x1 = 0.0, x2 = 0.0, nrm = 0.0;
     for (int j = n - 1; j >= 0; --j) {
-      const double x = (W(y, j) - W(u1, j) * x1 - W(u2, j) * x2) * W(rinv, j);
-      W(y, j) = x;
+      const double x = (W(Y, j) - W(U1, j) * x1 - W(U2, j) * x2) * W(RINV, j);
+      W(Y, j) = x;
       x2 = x1;
       x1 = x;
       nrm = fmax(nrm, fabs(x));
@@ -331,11 +352,11 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
   }
   double nrm2 = 0.0;
   for (int j = 0; j < n; ++j) {
-    const double v = W(y, j) * scale;
+    const double v = W(Y, j) * scale;
     nrm2 += v * v;
   }
   const double s2 = nrm2 > 0.0 ? scale / sqrt(nrm2) : 0.0;
-  for (int j = 0; j < n; ++j) W(Z, j) = W(y, j) * s2;
+  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = W(Y, j) * s2;
 #undef W
 }
 
@@ -368,10 +389,55 @@ __global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, co
   }
 }
 
-// V = H_0 ... H_{n-3} Z for NC columns per workgroup; writes eigenvector rows in descending order
-constexpr int kNC = 4;
+// Back-transformation V = H_0 H_1 ... H_{n-3} Z with the reflectors taken kNb at a time in compact
+// WY form: H_k0 ... H_k1 = I - Y T Y^T (Y = [v_k0 .. v_k1], T upper triangular, built as in the
+// forward-accumulation recurrence T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[:, 0:i]^T v_i).
+constexpr int kWy = 16;   // reflectors per block
+constexpr int kNC = 8;    // eigenvector columns per workgroup
+
+// T of every block (one workgroup per block), stored kWy x kWy per block
+__global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V, const double* __restrict__ tau, int n,
+                                                   double* __restrict__ Tall) {
+  const int nref = n - 2;
+  const int k0 = blockIdx.x * kWy;
+  const int m = min(kWy, nref - k0);
+  __shared__ double Gm[kWy][kWy];
+  __shared__ double Ts[kWy][kWy];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // Gm[a][i] = v_{k0+a} . v_{k0+i} for a < i (one wave per pair)
+  for (int q = wid; q < kWy * kWy; q += nw) {
+    const int a = q / kWy, i = q % kWy;
+    double acc = 0.0;
+    if (a < i && i < m) {
+      const double* va = V + (int64_t)(k0 + a) * n;
+      const double* vi = V + (int64_t)(k0 + i) * n;
+      for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += va[j] * vi[j];
+      acc = wave_sum(acc);
+    }
+    if (lane == 0) Gm[a][i] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kWy; ++i)
+      for (int a = 0; a < kWy; ++a) Ts[a][i] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double t = tau[k0 + i];
+      for (int a = 0; a < i; ++a) {
+        double acc = 0.0;
+        for (int b = a; b < i; ++b) acc += Ts[a][b] * Gm[b][i];
+        Ts[a][i] = -t * acc;
+      }
+      Ts[i][i] = t;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Tall[(int64_t)blockIdx.x * kWy * kWy + e] = (&Ts[0][0])[e];
+}
+
+// kNC columns of Z per workgroup: for each block from the last, Z <- Z - Y (T (Y^T Z)); then the
+// columns are written as eigenvector rows in descending eigenvalue order (dropped pairs as zeros)
 __global__ __launch_bounds__(256) void backtransform_kernel(const double* __restrict__ Z, const double* __restrict__ V,
-                                                            const double* __restrict__ tau,
+                                                            const double* __restrict__ Tall,
                                                             const double* __restrict__ lam_asc, int n,
                                                             const double* __restrict__ tnorm, double drop_rel,
                                                             double* __restrict__ evals_desc,
@@ -379,32 +445,52 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
   const double drop = drop_rel * (*tnorm);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* zc = reinterpret_cast<double*>(smem_raw);  // kNC x n
-  __shared__ double red[kNC][4];
+  __shared__ double W[kWy][kNC];
+  __shared__ double S[kWy][kNC];
   const int c0 = blockIdx.x * kNC;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int c = 0; c < kNC; ++c)
-    for (int j = threadIdx.x; j < n; j += blockDim.x)
-      zc[c * n + j] = (c0 + c < n) ? Z[(int64_t)j * n + c0 + c] : 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) zc[c * n + j] = (c0 + c < n) ? Z[(int64_t)j * n + c0 + c] : 0.0;
   __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;
-    const double* vk = V + (int64_t)k * n;
-    double s[kNC];
-    for (int c = 0; c < kNC; ++c) s[c] = 0.0;
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double vj = vk[j];
-      for (int c = 0; c < kNC; ++c) s[c] += vj * zc[c * n + j];
-    }
-    for (int c = 0; c < kNC; ++c) {
-      double w = wave_sum(s[c]);
-      if (lane == 0) red[c][wid] = w;
+  const int nref = n - 2;
+  const int nblk = nref > 0 ? (nref + kWy - 1) / kWy : 0;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * kWy;
+    const int m = min(kWy, nref - k0);
+    // W = Y^T Z (one wave per (reflector, column) pair)
+    for (int q = wid; q < kWy * kNC; q += nw) {
+      const int i = q / kNC, c = q % kNC;
+      double acc = 0.0;
+      if (i < m) {
+        const double* vi = V + (int64_t)(k0 + i) * n;
+        for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += vi[j] * zc[c * n + j];
+        acc = wave_sum(acc);
+      }
+      if (lane == 0) W[i][c] = acc;
     }
     __syncthreads();
-    for (int c = 0; c < kNC; ++c) s[c] = t * (red[c][0] + red[c][1] + red[c][2] + red[c][3]);
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double vj = vk[j];
-      for (int c = 0; c < kNC; ++c) zc[c * n + j] -= s[c] * vj;
+    // S = T W
+    if (threadIdx.x < kWy * kNC) {
+      const int i = threadIdx.x / kNC, c = threadIdx.x % kNC;
+      const double* T = Tall + (int64_t)b * kWy * kWy;
+      double acc = 0.0;
+      if (i < m)
+        for (int a = i; a < m; ++a) acc += T[i * kWy + a] * W[a][c];
+      S[i][c] = acc;
+    }
+    __syncthreads();
+    // Z -= Y S
+    for (int j = k0 + 1 + threadIdx.x; j < n; j += blockDim.x) {
+      double yv[kWy];
+#pragma unroll
+      for (int i = 0; i < kWy; ++i) yv[i] = (i < m && j > k0 + i) ? V[(int64_t)(k0 + i) * n + j] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kNC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kWy; ++i) acc += yv[i] * S[i][c];
+        zc[c * n + j] -= acc;
+      }
     }
     __syncthreads();
   }
@@ -419,32 +505,59 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
   }
 }
 
+// Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau, p, e2,
+// lam (n each), tnorm (8), the per-workgroup barrier flags (256 unsigned) and the error word, then
+// the T factors of the reflector blocks.
+struct EigWs {
+  double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *pbuf, *e2, *lam, *tnorm, *Tall;
+  unsigned* flags;
+  int* err;
+  size_t bytes;
+  EigWs(void* work, int n) {
+    double* w = reinterpret_cast<double*>(work);
+    const size_t nn = (size_t)n * n;
+    A1 = w;
+    V = A1 + nn;
+    Z = V + nn;
+    wk = Z + nn;
+    dvec = wk + 5 * nn;
+    evec = dvec + n;
+    tau = evec + n;
+    pbuf = tau + n;
+    e2 = pbuf + n;
+    lam = e2 + n;
+    tnorm = lam + n;
+    flags = reinterpret_cast<unsigned*>(tnorm + 8);
+    err = reinterpret_cast<int*>(flags + 256);
+    Tall = tnorm + 8 + 130;  // 256 unsigned + err word, rounded up to doubles
+    const size_t nblk = (size_t)(n + kWy - 1) / kWy + 1;
+    bytes = (size_t)((Tall + nblk * kWy * kWy) - w) * sizeof(double);
+  }
+};
+
 }  // namespace
 
-size_t eig_workspace_bytes(int n) {
-  // A1, V, Z (n*n each) + invit 5*n*n + vectors + barrier words
-  return sizeof(double) * ((size_t)8 * n * n + 8 * (size_t)n + 64) + 64;
-}
+size_t eig_workspace_bytes(int n) { return EigWs(nullptr, n).bytes; }
 
 ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
                                hipStream_t s) {
   if (n <= 0) return NGD_OK;
-  double* w = reinterpret_cast<double*>(work);
-  double* A1 = w;
-  double* V = A1 + (size_t)n * n;
-  double* Z = V + (size_t)n * n;
-  double* wk = Z + (size_t)n * n;           // 5 n^2
-  double* dvec = wk + (size_t)5 * n * n;
-  double* evec = dvec + n;
-  double* tau = evec + n;
-  double* pbuf = tau + n;
-  double* e2 = pbuf + n;
-  double* lam = e2 + n;
-  double* tnorm = lam + n;
-  unsigned* bar = reinterpret_cast<unsigned*>(tnorm + 8);
-  int* err = reinterpret_cast<int*>(bar + 4);
+  EigWs ws(work, n);
+  double* A1 = ws.A1;
+  double* V = ws.V;
+  double* Z = ws.Z;
+  double* wk = ws.wk;
+  double* dvec = ws.dvec;
+  double* evec = ws.evec;
+  double* tau = ws.tau;
+  double* pbuf = ws.pbuf;
+  double* e2 = ws.e2;
+  double* lam = ws.lam;
+  double* tnorm = ws.tnorm;
+  unsigned* bar = ws.flags;
+  int* err = ws.err;
   {
-    ngd_status st = launch_zero(bar, 4 * sizeof(unsigned) + sizeof(int) + 4, s);
+    ngd_status st = launch_zero(bar, 256 * sizeof(unsigned) + sizeof(int), s);
     if (st != NGD_OK) return st;
     st = launch_zero(tau, sizeof(double) * n, s);
     if (st != NGD_OK) return st;
@@ -452,7 +565,7 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   TriArgs ta{A, A1, n, dvec, evec, V, tau, pbuf, bar, err};
   // workgroups: enough that each one's rows fit in LDS next to three n-vectors
   int blocks = n < kTriBlocks ? (n < 1 ? 1 : n) : kTriBlocks;
-  auto lds_for = [&](int G) { return sizeof(double) * ((size_t)((n + G - 1) / G) * n + 3 * (size_t)n); };
+  auto lds_for = [&](int G) { return sizeof(double) * ((size_t)((n + G - 1) / G) * n + 4 * (size_t)n); };
   while (lds_for(blocks) > 144 * 1024 && blocks < 256) blocks *= 2;
   size_t lds = lds_for(blocks);
   if (lds > 144 * 1024) {
@@ -477,39 +590,53 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   const int tb = 256;
   hipLaunchKernelGGL(bisect_kernel, dim3((n + 3) / 4), dim3(tb), 2 * sizeof(double) * n, s, dvec, evec, n, e2,
                      lam, tnorm);
-  hipLaunchKernelGGL(invit_kernel, dim3((n + 63) / 64), dim3(64), 0, s, dvec, evec, n, lam, tnorm, drop_rel, Z, wk);
+  {
+    // as many eigenvalues per workgroup as fit: (2 + 6 tpw) n doubles of LDS
+    int tpw = (int)((150 * 1024 / sizeof(double) - 2 * (size_t)n) / ((size_t)kInvArrays * n));
+    tpw = tpw > 64 ? 64 : tpw;
+    if (tpw < 1) {
+      set_error("ell too large for inverse iteration in LDS");
+      return NGD_ERR_INVALID;
+    }
+    const size_t lds = sizeof(double) * ((size_t)2 * n + (size_t)kInvArrays * n * tpw);
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(invit_kernel, dim3((n + tpw - 1) / tpw), dim3(tpw), lds, s, dvec, evec, n, lam, tnorm,
+                       drop_rel, Z);
+  }
   hipLaunchKernelGGL(cluster_mgs_kernel, dim3(n), dim3(256), 0, s, lam, n, tnorm, drop_rel, Z);
   NGD_HIP_TRY(hipGetLastError());
   // one Newton-Schulz step Z <- 1.5 Z - 0.5 Z (Z^T Z) removes the residual non-orthogonality of the
   // inverse-iteration vectors (quadratic convergence; dropped columns stay zero)
   double* E = A1;   // free after the tridiagonalisation
   double* Z2 = wk;  // free after inverse iteration
+  double* nswork = wk + (size_t)n * n;  // split-K partials of the n x n products (4 n^2)
   for (int ns = 0; ns < 2; ++ns) {
-    GemmArgs e{n, n, n, Z, n, false, Z, n, false, E, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0};
+    GemmArgs e{n, n, n, Z, n, false, Z, n, false, E, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
+               nswork, 4 * (int64_t)n * n};
     ngd_status st = launch_gemm(e, s);
     if (st != NGD_OK) return st;
     st = launch_cast(NGD_F64, Z, NGD_F64, Z2, (int64_t)n * n, s);
     if (st != NGD_OK) return st;
-    GemmArgs u{n, n, n, Z, n, true, E, n, false, Z2, n, NGD_F64, NGD_F64, NGD_F64, G_F64, -0.5, 1.5};
+    GemmArgs u{n, n, n, Z, n, true, E, n, false, Z2, n, NGD_F64, NGD_F64, NGD_F64, G_F64, -0.5, 1.5,
+               nswork, 4 * (int64_t)n * n};
     st = launch_gemm(u, s);
     if (st != NGD_OK) return st;
     double* t = Z;
     Z = Z2;
     Z2 = t;
   }
+  // T factors of the reflector blocks (written over the multipliers of inverse iteration, free now)
+  double* Tall = ws.Tall;
+  const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
+  if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, Tall);
   NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(kNC * n * sizeof(double))));
-  hipLaunchKernelGGL(backtransform_kernel, dim3((n + kNC - 1) / kNC), dim3(256), kNC * n * sizeof(double), s, Z, V, tau,
-                     lam, n, tnorm, drop_rel, evals_desc, evec_rows);
+  hipLaunchKernelGGL(backtransform_kernel, dim3((n + kNC - 1) / kNC), dim3(256), kNC * n * sizeof(double), s, Z, V,
+                     Tall, lam, n, tnorm, drop_rel, evals_desc, evec_rows);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
 
-const int* eig_error_flag(void* work, int n) {
-  double* w = reinterpret_cast<double*>(work);
-  double* tnorm = w + (size_t)8 * n * n + 6 * (size_t)n;
-  unsigned* bar = reinterpret_cast<unsigned*>(tnorm + 8);
-  return reinterpret_cast<const int*>(bar + 4);
-}
+const int* eig_error_flag(void* work, int n) { return EigWs(work, n).err; }
 
 }  // namespace ngd

@@ -68,56 +68,89 @@ __device__ __forceinline__ void axpy_vec<double>(double t, const vd2& a, vd2& y)
 }
 
 // Core of the one-pass product over rows [r0, r1): acc += sum_r (J_r . vs) J_r, tsq += (J_r . vs)^2.
-// vs: the vector in LDS (ld elements, zero beyond P). Every thread returns with its own chunks.
-template <typename T, int NK>
+// vs: the vector in LDS (ld elements, zero beyond P). Rows are taken R at a time: their R dot
+// products share one workgroup reduction, and the next R rows are loaded in full while the current
+// ones are reduced and accumulated, so that about 2R rows per CU are in flight against HBM.
+// `stage` fills vs (and does any other per-launch set-up), followed by a workgroup barrier; for
+// short rows it runs after the first rows' loads have been issued, so its own reads overlap them.
+template <typename T, int NK, int R, typename Stage>
 __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, int64_t r0, int64_t r1,
-                                          const T* vs, RowRegs<T, NK>& acc, double& tsq) {
+                                          const T* vs, RowRegs<T, NK>& acc, double& tsq, Stage&& stage) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
-  constexpr int H = (NK + 1) / 2;  // chunks of the next row prefetched before the reduction
-  __shared__ double red[2][16];
+  __shared__ double red[2][R][16];
   const int64_t nchunk = ldJ / VN;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int row_bytes = (int)(ldJ * sizeof(T));
+  const int nrows = r1 > r0 ? (int)(r1 - r0) : 0;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(J + r0 * ldJ), (short)0, nrows * row_bytes, 0x00020000);
+  if (nrows == 0) {
+    stage();
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc.c[k] = V{};
+    return;
+  }
+  // long rows leave no registers to spare while staging: stage first there
+  constexpr bool kStageFirst = NK * R >= 12;
+  if constexpr (kStageFirst) {
+    stage();
+    __syncthreads();
+  }
+  V cur[R][NK], nxt[R][NK];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (q < nrows) load_chunks<T, 0, NK>(rsrc, q * row_bytes, nchunk, cur[q]);
+    else
+#pragma unroll
+      for (int k = 0; k < NK; ++k) cur[q][k] = V{};
+  }
+  if constexpr (!kStageFirst) {
+    stage();
+    __syncthreads();
+  }
 #pragma unroll
   for (int k = 0; k < NK; ++k) acc.c[k] = V{};
-  if (r0 >= r1) return;
-  const int row_bytes = (int)(ldJ * sizeof(T));
-  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(J + r0 * ldJ), (short)0, (int)((r1 - r0) * row_bytes), 0x00020000);
-  V cur[NK];
-  load_chunks<T, 0, NK>(rsrc, 0, nchunk, cur);
   int parity = 0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const bool more = r + 1 < r1;
-    const int next_bytes = (int)(r + 1 - r0) * row_bytes;
-    // first half of the next row in flight during the dot product and the reduction
-    V nxt_a[H];
-    if (more) load_chunks<T, 0, H>(rsrc, next_bytes, nchunk, nxt_a);
-    T dot = 0;
+  for (int base = 0; base < nrows; base += R) {
+    // rows base+R .. base+2R-1 in flight during this group's dot products and reduction
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      int64_t q = threadIdx.x + (int64_t)k * blockDim.x;
-      if (q < nchunk) dot += dot_vec<T>(cur[k], vs + q * VN);
+    for (int q = 0; q < R; ++q) {
+      if (base + R + q < nrows) load_chunks<T, 0, NK>(rsrc, (base + R + q) * row_bytes, nchunk, nxt[q]);
+      else
+#pragma unroll
+        for (int k = 0; k < NK; ++k) nxt[q][k] = V{};
     }
-    dot = wave_sum(dot);
-    if (lane == 0) red[parity][wid] = (double)dot;
+    T dot[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      dot[q] = 0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        int64_t c = threadIdx.x + (int64_t)k * blockDim.x;
+        if (c < nchunk) dot[q] += dot_vec<T>(cur[q][k], vs + c * VN);
+      }
+      dot[q] = wave_sum(dot[q]);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < R; ++q) red[parity][q][wid] = (double)dot[q];
     __syncthreads();
-    double t = 0;
-    for (int i = 0; i < nw; ++i) t += red[parity][i];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double t = 0;
+      for (int i = 0; i < nw; ++i) t += red[parity][q][i];
+      tsq += t * t;  // rows past the end are zero and add nothing
+      const T tt = (T)t;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) axpy_vec<T>(tt, cur[q][k], acc.c[k]);
+    }
     parity ^= 1;
-    tsq += t * t;
-    const T tt = (T)t;
 #pragma unroll
-    for (int k = 0; k < H; ++k) axpy_vec<T>(tt, cur[k], acc.c[k]);
-    // second half of the next row, into the registers the first half just released
-    V nxt_b[NK - H > 0 ? NK - H : 1];
-    if (more) load_chunks<T, H, NK>(rsrc, next_bytes, nchunk, nxt_b);
+    for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int k = H; k < NK; ++k) axpy_vec<T>(tt, cur[k], acc.c[k]);
-#pragma unroll
-    for (int k = 0; k < H; ++k) cur[k] = nxt_a[k];
-#pragma unroll
-    for (int k = H; k < NK; ++k) cur[k] = nxt_b[k - H];
+      for (int k = 0; k < NK; ++k) cur[q][k] = nxt[q][k];
   }
 }
 
@@ -141,19 +174,25 @@ __device__ __forceinline__ void row_range(int64_t N, int64_t* r0, int64_t* r1) {
 }
 
 // y partials of J^T (J v) for an FP64 input vector
-template <typename T, int NK>
-__global__ __launch_bounds__(1024) void gram_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+template <typename T, int NK, int R, int B>
+__global__ __launch_bounds__(B) void gram_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
                                                          const double* __restrict__ v, T* __restrict__ partial,
                                                          double* __restrict__ tsq_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* vs = reinterpret_cast<T*>(smem_raw);
-  for (int64_t j = threadIdx.x; j < ldJ; j += blockDim.x) vs[j] = j < P ? (T)v[j] : T(0);
-  __syncthreads();
   int64_t r0, r1;
   row_range(N, &r0, &r1);
   RowRegs<T, NK> acc;
   double tsq = 0;
-  rows_pass<T, NK>(J, ldJ, r0, r1, vs, acc, tsq);
+  rows_pass<T, NK, R>(J, ldJ, r0, r1, vs, acc, tsq, [&] {
+    // short rows: several loads in flight; long rows: registers are needed for the rows
+    if constexpr (NK * R < 12) {
+#pragma unroll 4
+      for (int64_t j = threadIdx.x; j < ldJ; j += B) vs[j] = j < P ? (T)v[j] : T(0);
+    } else {
+      for (int64_t j = threadIdx.x; j < ldJ; j += B) vs[j] = j < P ? (T)v[j] : T(0);
+    }
+  });
   store_partial<T, NK>(partial, ldJ, acc);
   if (threadIdx.x == 0 && tsq_out) tsq_out[blockIdx.x] = tsq;
 }
@@ -201,8 +240,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
 
 // ---------------- fused PCG iteration ----------------
 // (A) search direction p = z + beta p_prev staged on the fly, then the one-pass Gramian product
-template <typename T, int NK>
-__global__ __launch_bounds__(1024) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+template <typename T, int NK, int R, int B>
+__global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
                                                         const double* __restrict__ z, const double* __restrict__ p_prev,
                                                         double* __restrict__ p_cur, PcgState* __restrict__ st,
                                                         T* __restrict__ partial, double* __restrict__ tsq_out) {
@@ -210,21 +249,28 @@ __global__ __launch_bounds__(1024) void pcg_rows_kernel(const T* __restrict__ J,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* vs = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[16];
-  const double beta = st->beta;
-  double pp = 0;
-  for (int64_t j = threadIdx.x; j < ldJ; j += blockDim.x) {
-    double pj = j < P ? z[j] + beta * p_prev[j] : 0.0;
-    vs[j] = (T)pj;
-    pp += pj * pj;
-    if (blockIdx.x == 0 && j < P) p_cur[j] = pj;
-  }
-  pp = block_sum(pp, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->pp = pp;
   int64_t r0, r1;
   row_range(N, &r0, &r1);
   RowRegs<T, NK> acc;
   double tsq = 0;
-  rows_pass<T, NK>(J, ldJ, r0, r1, vs, acc, tsq);
+  rows_pass<T, NK, R>(J, ldJ, r0, r1, vs, acc, tsq, [&] {
+    const double beta = st->beta;
+    double pp = 0;
+    auto one = [&](int64_t j) {
+      double pj = j < P ? z[j] + beta * p_prev[j] : 0.0;
+      vs[j] = (T)pj;
+      pp += pj * pj;
+      if (blockIdx.x == 0 && j < P) p_cur[j] = pj;
+    };
+    if constexpr (NK * R < 12) {
+#pragma unroll 4
+      for (int64_t j = threadIdx.x; j < ldJ; j += B) one(j);
+    } else {
+      for (int64_t j = threadIdx.x; j < ldJ; j += B) one(j);
+    }
+    pp = block_sum(pp, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->pp = pp;
+  });
   store_partial<T, NK>(partial, ldJ, acc);
   if (threadIdx.x == 0) tsq_out[blockIdx.x] = tsq;
 }
@@ -402,21 +448,30 @@ __global__ void scale_by_rsqrt_kernel(const double* __restrict__ w, const double
 
 // ---------------- host launchers ----------------
 
+// One-pass configurations (block, NK, R): a workgroup per CU, so a lane may hold 256 VGPRs; R rows
+// per step are chosen so that the 2R row buffers and the accumulator, (2R + 1) NK 16-byte chunks,
+// fit beside the addressing registers. Rows longer than 512 x 18 chunks (147 KB) are not supported.
+#define NGD_ROWS_CONFIGS(X)                                                                     \
+  X(0, 256, 1, 4) X(1, 256, 2, 4) X(2, 256, 3, 4) X(3, 256, 4, 4) X(4, 512, 2, 4) X(5, 512, 3, 4) \
+  X(6, 512, 4, 4) X(7, 512, 5, 4) X(8, 512, 6, 2) X(9, 512, 7, 2) X(10, 512, 8, 2)              \
+  X(11, 512, 9, 2) X(12, 512, 10, 2) X(13, 512, 12, 1) X(14, 512, 14, 1) X(15, 512, 16, 1)     \
+  X(16, 512, 17, 1) X(17, 512, 18, 1)
+
 struct RowsCfg {
-  int block;
-  int nk;
+  int id, block, nk, r;
 };
 
 static bool rows_cfg(int dtype, int64_t ldJ, RowsCfg* c) {
   const int vn = dtype == NGD_F64 ? 2 : 4;
   const int64_t nchunk = ldJ / vn;
-  const int blocks[3] = {256, 512, 1024};
-  const int maxnk[3] = {8, 8, 10};
-  for (int i = 0; i < 3; ++i) {
-    int64_t nk = (nchunk + blocks[i] - 1) / blocks[i];
-    if (nk <= maxnk[i]) {
-      c->block = blocks[i];
-      c->nk = (int)(nk < 1 ? 1 : nk);
+  static const RowsCfg table[] = {
+#define NGD_ROW(ID, B, NK, R) {ID, B, NK, R},
+      NGD_ROWS_CONFIGS(NGD_ROW)
+#undef NGD_ROW
+  };
+  for (const RowsCfg& t : table) {
+    if ((int64_t)t.block * t.nk >= nchunk && (t.block == 512 || nchunk <= 256 * 4)) {
+      *c = t;
       return true;
     }
   }
@@ -435,18 +490,10 @@ bool gram_rows_supported(int dtype, int64_t ldJ) {
   return rows_cfg(dtype, ldJ, &c) && (size_t)ldJ * (dtype == NGD_F64 ? 8 : 4) <= 150 * 1024;
 }
 
-#define NGD_NK_DISPATCH(NKV, CALL) \
-  switch (NKV) {                   \
-    case 1: CALL(1); break;        \
-    case 2: CALL(2); break;        \
-    case 3: CALL(3); break;        \
-    case 4: CALL(4); break;        \
-    case 5: CALL(5); break;        \
-    case 6: CALL(6); break;        \
-    case 7: CALL(7); break;        \
-    case 8: CALL(8); break;        \
-    case 9: CALL(9); break;        \
-    default: CALL(10); break;      \
+#define NGD_CFG_DISPATCH(ID, CALL)                      \
+  switch (ID) {                                         \
+    NGD_ROWS_CONFIGS(CALL)                              \
+    default: break;                                     \
   }
 
 template <typename T>
@@ -458,13 +505,14 @@ static ngd_status gram_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, con
     return NGD_ERR_INVALID;
   }
   const size_t lds = (size_t)ldJ * sizeof(T);
-#define NGD_CALL(NK)                                                                                    \
-  do {                                                                                                  \
-    auto k = gram_rows_kernel<T, NK>;                                                                   \
+#define NGD_CALL(ID, B, NK, R)                                                                          \
+  case ID: {                                                                                            \
+    auto k = gram_rows_kernel<T, NK, R, B>;                                                             \
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    hipLaunchKernelGGL(k, dim3(nwg), dim3(c.block), lds, s, J, ldJ, N, P, v, partial, tsq);            \
-  } while (0)
-  NGD_NK_DISPATCH(c.nk, NGD_CALL)
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(B), lds, s, J, ldJ, N, P, v, partial, tsq);                  \
+    break;                                                                                              \
+  }
+  NGD_CFG_DISPATCH(c.id, NGD_CALL)
 #undef NGD_CALL
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
@@ -531,13 +579,14 @@ static ngd_status pcg_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, cons
     return NGD_ERR_INVALID;
   }
   const size_t lds = (size_t)ldJ * sizeof(T);
-#define NGD_CALL(NK)                                                                                    \
-  do {                                                                                                  \
-    auto k = pcg_rows_kernel<T, NK>;                                                                    \
+#define NGD_CALL(ID, B, NK, R)                                                                          \
+  case ID: {                                                                                            \
+    auto k = pcg_rows_kernel<T, NK, R, B>;                                                              \
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    hipLaunchKernelGGL(k, dim3(nwg), dim3(c.block), lds, s, J, ldJ, N, P, z, p_prev, p_cur, st, partial, tsq); \
-  } while (0)
-  NGD_NK_DISPATCH(c.nk, NGD_CALL)
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(B), lds, s, J, ldJ, N, P, z, p_prev, p_cur, st, partial, tsq); \
+    break;                                                                                              \
+  }
+  NGD_CFG_DISPATCH(c.id, NGD_CALL)
 #undef NGD_CALL
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;

@@ -1,0 +1,372 @@
+// The two large sketch contractions on the MFMA matrix cores, in "NT" form: C = alpha A B^T with
+// A (M x K) and B (N x K) both K-contiguous. Z = J_w Omega uses A = J_w (N x P, the stored FP32
+// Jacobian, converted to the compute type while it is staged) and B = Omega^T (ell x P); the
+// second product B^T = Q^T J_w of the structured Alg. 6 runs as (J_w^T Q)^T with A = J_w^T and
+// B = Q^T, both transposed copies in the compute type, and the result written transposed. These
+// are the ell simultaneous Gramian matvecs of the sketch (Section 4.1.2, Table tab:matvec_costs).
+//
+// Tiling for gfx950: a 256 x 128 workgroup tile, 4 wave64s in a 2 x 2 arrangement, so each wave
+// owns a 128 x 64 block of 8 x 4 MFMA tiles (v_mfma_f32_16x16x32_bf16 for BF16, or
+// v_mfma_f32_16x16x4f32 for FP32). One K-slab is 64 bytes per row in either type (32 BF16 or 16
+// FP32 values), staged in LDS with an 80-byte row pitch (conflict-free 16-byte operand reads) and
+// double-buffered: the next slab's global loads are in flight while the current one is multiplied
+// out, with a single barrier per slab. Registers are capped for two workgroups per CU (the other
+// workgroup's MFMA work covers this one's load latency). Tiles are numbered so that the workgroups that share an A
+// row panel run on the same XCD (workgroups are dealt to the 8 XCDs round-robin), where the panel
+// is then read from that XCD's L2.
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+
+constexpr int kBM = 256, kBN = 128, kThreads = 256;
+constexpr int kRowBytes = 64;                 // one K-slab of one row
+constexpr int kPitch = 80;                    // LDS row pitch in bytes
+constexpr int kXcd = 8;
+
+template <typename E> struct Slab { static constexpr int BK = kRowBytes / (int)sizeof(E); };
+
+// One 16-byte LDS chunk (8 BF16 or 4 FP32 compute values) of a staged row, from the source type.
+template <typename TS, typename E> struct Chunk;
+template <> struct Chunk<float, __bf16> {
+  static constexpr int N_LD = 2;  // two 16-byte global loads per chunk
+  static __device__ __forceinline__ u4 convert(const u4* raw) {
+    const f4 a = __builtin_bit_cast(f4, raw[0]), b = __builtin_bit_cast(f4, raw[1]);
+    bf8 o;
+    o[0] = (__bf16)a.x; o[1] = (__bf16)a.y; o[2] = (__bf16)a.z; o[3] = (__bf16)a.w;
+    o[4] = (__bf16)b.x; o[5] = (__bf16)b.y; o[6] = (__bf16)b.z; o[7] = (__bf16)b.w;
+    return __builtin_bit_cast(u4, o);
+  }
+};
+template <> struct Chunk<__bf16, __bf16> {
+  static constexpr int N_LD = 1;
+  static __device__ __forceinline__ u4 convert(const u4* raw) { return raw[0]; }
+};
+template <> struct Chunk<float, float> {
+  static constexpr int N_LD = 1;
+  static __device__ __forceinline__ u4 convert(const u4* raw) { return raw[0]; }
+};
+
+// Registers holding this thread's chunks of one ROWS x BK slab of a K-contiguous operand.
+// Chunk q = threadIdx.x + kThreads * i covers row q / 4, compute columns (q % 4) * CE ...
+template <typename TS, typename E, int ROWS>
+struct SlabLoader {
+  static constexpr int CHUNKS = ROWS * 4 / kThreads;
+  static constexpr int CE = 16 / (int)sizeof(E);             // compute values per chunk
+  static constexpr int LD_BYTES = CE * (int)sizeof(TS) / Chunk<TS, E>::N_LD;
+  u4 raw[CHUNKS][Chunk<TS, E>::N_LD];
+
+  // rsrc spans this tile's rows only, so rows past the operand's end read as zero; columns at or
+  // past K are zeroed explicitly in the last slab (they may hold the next row or padding).
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rsrc, int64_t ld, int64_t k0, int64_t K) {
+    const int c = threadIdx.x & 3;
+#pragma unroll
+    for (int i = 0; i < CHUNKS; ++i) {
+      const int row = (threadIdx.x >> 2) + i * (kThreads / 4);
+      const uint32_t off = (uint32_t)(((int64_t)row * ld + k0 + c * CE) * (int64_t)sizeof(TS));
+#pragma unroll
+      for (int h = 0; h < Chunk<TS, E>::N_LD; ++h)
+        raw[i][h] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + h * LD_BYTES, 0, 0);
+    }
+    if (k0 + Slab<E>::BK > K) {  // last, partial slab
+#pragma unroll
+      for (int i = 0; i < CHUNKS; ++i)
+#pragma unroll
+        for (int h = 0; h < Chunk<TS, E>::N_LD; ++h) {
+          constexpr int PER = LD_BYTES / (int)sizeof(TS);
+          TS v[PER];
+          __builtin_memcpy(v, &raw[i][h], 16);
+#pragma unroll
+          for (int e = 0; e < PER; ++e)
+            if (k0 + c * CE + h * PER + e >= K) v[e] = TS(0);
+          __builtin_memcpy(&raw[i][h], v, 16);
+        }
+    }
+  }
+  __device__ __forceinline__ void store(unsigned char* lds) const {
+    const int c = threadIdx.x & 3;
+#pragma unroll
+    for (int i = 0; i < CHUNKS; ++i) {
+      const int row = (threadIdx.x >> 2) + i * (kThreads / 4);
+      *reinterpret_cast<u4*>(lds + row * kPitch + c * 16) = Chunk<TS, E>::convert(raw[i]);
+    }
+  }
+};
+
+// Buffer resource over the tile's rows of an operand whose pointer has been advanced by `kbeg`
+// columns (a split-K slice): the extent ends where the operand's last row of the tile ends.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const T* base, int64_t row0, int64_t rows_total,
+                                                            int64_t rows_tile, int64_t ld, int64_t kbeg) {
+  const int64_t rows = rows_total - row0 < rows_tile ? rows_total - row0 : rows_tile;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(base + row0 * ld), (short)0,
+                                           (int)((rows * ld - kbeg) * (int64_t)sizeof(T)), 0x00020000);
+}
+
+// Multiply one staged slab: acc[i][j] (16 x 16 tiles) += A_slab(wave rows) B_slab(wave cols)^T
+template <typename E>
+__device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigned char* Bs, int wm, int wn,
+                                          f4 (&acc)[8][4]) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, kq = lane >> 4;
+  u4 b[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const u4*>(Bs + (wn + 16 * j + r16) * kPitch + 16 * kq);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const u4 a = *reinterpret_cast<const u4*>(As + (wm + 16 * i + r16) * kPitch + 16 * kq);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (sizeof(E) == 2) {
+        // lane holds k = 8 kq .. 8 kq + 7 of row r16 for both operands
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b[j]),
+                                                            acc[i][j], 0, 0, 0);
+      } else {
+        // four K-steps; in step s lane supplies k = 4 kq + s for both operands (the same
+        // permutation of the slab's 16 k on both sides leaves the sum unchanged)
+        const f4 av = __builtin_bit_cast(f4, a), bv = __builtin_bit_cast(f4, b[j]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// C (M x N, ldc) = alpha A B^T, or C^T stored (C[n * ldc + m]) when trans_c. With split K
+// (gridDim.y slices of kchunk), slice s writes its partial product to C + s * slice_stride.
+template <typename TA, typename TB, typename E, typename TC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void nt_gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
+                                                           int64_t lda, const TB* __restrict__ B, int64_t ldb,
+                                                           TC* __restrict__ C, int64_t ldc, int trans_c, float alpha,
+                                                           int tiles_n, int tiles, int per_xcd, int64_t kchunk,
+                                                           int64_t slice_stride) {
+  __shared__ __align__(16) unsigned char As[2][kBM * kPitch];
+  __shared__ __align__(16) unsigned char Bs[2][kBN * kPitch];
+  const int t = (int)(blockIdx.x % kXcd) * per_xcd + (int)(blockIdx.x / kXcd);
+  if (t >= tiles) return;
+  const int64_t m0 = (int64_t)(t / tiles_n) * kBM;
+  const int64_t n0 = (int64_t)(t % tiles_n) * kBN;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = (wid >> 1) * 128, wn = (wid & 1) * 64;
+  constexpr int BK = Slab<E>::BK;
+
+  // this slice's K range: the operands are offset to its start, K becomes its length
+  const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+  A += kbeg;
+  B += kbeg;
+  C += (int64_t)blockIdx.y * slice_stride;
+  K = (K - kbeg) < kchunk ? (K - kbeg) : kchunk;
+  const __amdgpu_buffer_rsrc_t ra = tile_rsrc(A, m0, M, kBM, lda, kbeg);
+  const __amdgpu_buffer_rsrc_t rb = tile_rsrc(B, n0, N, kBN, ldb, kbeg);
+  SlabLoader<TA, E, kBM> la;
+  SlabLoader<TB, E, kBN> lb;
+  f4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  la.load(ra, lda, 0, K);
+  lb.load(rb, ldb, 0, K);
+  la.store(As[0]);
+  lb.store(Bs[0]);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      la.load(ra, lda, (kt + 1) * BK, K);
+      lb.load(rb, ldb, (kt + 1) * BK, K);
+    }
+    slab_mfma<E>(As[cur], Bs[cur], wm, wn, acc);
+    if (more) {
+      la.store(As[cur ^ 1]);
+      lb.store(Bs[cur ^ 1]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds column lane % 16 and rows 4 (lane / 16) + r of each 16 x 16 tile
+  const int cn = lane & 15, rq = 4 * (lane >> 4);
+  const bool vec_ok = (ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gm = m0 + wm + 16 * i + rq;
+      const int64_t gn = n0 + wn + 16 * j + cn;
+      if (gn >= N) continue;
+      if (trans_c) {
+        TC* dst = C + gn * ldc + gm;
+        if constexpr (sizeof(TC) == 4) {
+          if (gm + 3 < M && vec_ok) {
+            *reinterpret_cast<f4*>(dst) = alpha * acc[i][j];
+            continue;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (gm + r < M) dst[r] = (TC)(alpha * acc[i][j][r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (gm + r < M) C[(gm + r) * ldc + gn] = (TC)(alpha * acc[i][j][r]);
+      }
+    }
+}
+
+// dst (cols x rows, ld_d) = src (rows x cols, ld_s)^T converted to TD, through a 64 x 64 LDS tile
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void transpose_cast_kernel(const TS* __restrict__ src, int64_t ld_s, int64_t rows,
+                                                             int64_t cols, TD* __restrict__ dst, int64_t ld_d) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = ty + 4 * k;
+    const int64_t gr = r0 + r, gc = c0 + tx;
+    tile[r][tx] = (gr < rows && gc < cols) ? (float)src[gr * ld_s + gc] : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int c = ty + 4 * k;
+    const int64_t gc = c0 + c, gr = r0 + tx;
+    if (gc < cols && gr < rows) dst[gc * ld_d + gr] = (TD)tile[tx][c];
+  }
+}
+
+// out = alpha sum_s work[s] over ks slices of `count` elements each, in a fixed order; out is laid out
+// as `rows` x `cols` with leading dimension ld_out, the slices as rows x cols packed.
+__global__ void splitk_sum_kernel(const float* __restrict__ work, int ks, int64_t rows, int64_t cols,
+                                  float* __restrict__ out, int64_t ld_out, float alpha) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t count = rows * cols;
+  if (idx >= count) return;
+  float acc = 0.f;
+  for (int q = 0; q < ks; ++q) acc += work[(int64_t)q * count + idx];
+  const int64_t r = idx / cols, c = idx - r * cols;
+  out[r * ld_out + c] = alpha * acc;
+}
+
+template <typename TA, typename TB, typename E, typename TC>
+ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                  int64_t ldc, bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s) {
+  const int64_t tm = (M + kBM - 1) / kBM, tn = (N + kBN - 1) / kBN;
+  const int64_t tiles = tm * tn;
+  if (tiles == 0) return NGD_OK;
+  const int64_t per = (tiles + kXcd - 1) / kXcd;
+  constexpr int BK = Slab<E>::BK;
+  // split K when the tiles alone leave most CUs idle, keeping at least 8 slabs per slice
+  int ks = 1;
+  if (work != nullptr && tiles < 384) {
+    const int64_t nk = (K + BK - 1) / BK;
+    while (tiles * ks * 2 <= 768 && nk / (ks * 2) >= 8 && (int64_t)ks * 2 * M * N <= work_elems) ks *= 2;
+  }
+  const int64_t kchunk = ks == 1 ? K : ((K + ks - 1) / ks + BK - 1) / BK * BK;
+  if (ks == 1) {
+    hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, TC>), dim3((unsigned)(per * kXcd), 1), dim3(kThreads), 0, s, M, N,
+                       K, (const TA*)A, lda, (const TB*)B, ldb, (TC*)C, ldc, (int)trans_c, (float)alpha, (int)tn,
+                       (int)tiles, (int)per, kchunk, (int64_t)0);
+    NGD_HIP_TRY(hipGetLastError());
+    return NGD_OK;
+  }
+  // slices in the output's own orientation (rows x cols packed), then one ordered sum
+  const int64_t rows = trans_c ? N : M, cols = trans_c ? M : N;
+  hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, float>), dim3((unsigned)(per * kXcd), (unsigned)ks), dim3(kThreads), 0,
+                     s, M, N, K, (const TA*)A, lda, (const TB*)B, ldb, work, cols, (int)trans_c, 1.0f, (int)tn,
+                     (int)tiles, (int)per, kchunk, rows * cols);
+  NGD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, s, work, ks, rows,
+                     cols, (float*)C, ldc, (float)alpha);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+template <typename TS, typename TD>
+__global__ void cast_rows_kernel(const TS* __restrict__ src, int64_t ld_s, int64_t rows, int64_t cols,
+                                 TD* __restrict__ dst, int64_t ld_d) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (c < cols && r < rows) dst[r * ld_d + c] = (TD)src[r * ld_s + c];
+}
+
+}  // namespace
+
+bool nt_gemm_supported(int a_type, int b_type, int compute, int64_t M, int64_t N, int64_t K, int64_t lda,
+                       int64_t ldb) {
+  auto sz = [](int t) { return t == NGD_BF16 ? 2 : (t == NGD_F32 ? 4 : 8); };
+  if (compute == G_F64 || a_type == NGD_F64 || b_type == NGD_F64) return false;
+  if (compute == G_F32 && (a_type != NGD_F32 || b_type != NGD_F32)) return false;
+  // 16-byte aligned rows, and 32-bit byte offsets within one tile's rows
+  if ((lda * sz(a_type)) % 16 != 0 || (ldb * sz(b_type)) % 16 != 0) return false;
+  if (lda < K || ldb < K) return false;
+  if ((int64_t)kBM * lda * sz(a_type) >= (int64_t)1 << 31 || (int64_t)kBN * ldb * sz(b_type) >= (int64_t)1 << 31)
+    return false;
+  const int64_t tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+  return tiles > 0 && tiles < ((int64_t)1 << 30);
+}
+
+ngd_status launch_nt_gemm(int a_type, const void* A, int64_t lda, int b_type, const void* B, int64_t ldb,
+                          int compute, int64_t M, int64_t N, int64_t K, int c_type, void* C, int64_t ldc,
+                          bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s) {
+  if (!nt_gemm_supported(a_type, b_type, compute, M, N, K, lda, ldb) || c_type != NGD_F32 ||
+      (trans_c ? (ldc < M || ldc % 4 != 0) : ldc < N)) {
+    set_error("nt_gemm: unsupported operand types or layout");
+    return NGD_ERR_INVALID;
+  }
+  if (compute == G_F32) return run_nt<float, float, float, float>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work, work_elems, s);
+  if (a_type == NGD_F32 && b_type == NGD_BF16)
+    return run_nt<float, __bf16, __bf16, float>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work, work_elems, s);
+  if (a_type == NGD_BF16 && b_type == NGD_BF16)
+    return run_nt<__bf16, __bf16, __bf16, float>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work, work_elems, s);
+  if (a_type == NGD_F32 && b_type == NGD_F32)
+    return run_nt<float, float, __bf16, float>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work, work_elems, s);
+  set_error("nt_gemm: unsupported operand types");
+  return NGD_ERR_INVALID;
+}
+
+ngd_status launch_cast_rows(int src_type, const void* src, int64_t ld_s, int64_t rows, int64_t cols, int dst_type,
+                            void* dst, int64_t ld_d, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return NGD_OK;
+  dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows);
+  if (src_type == NGD_F32 && dst_type == NGD_BF16)
+    hipLaunchKernelGGL((cast_rows_kernel<float, __bf16>), grid, dim3(256), 0, s, (const float*)src, ld_s, rows, cols,
+                       (__bf16*)dst, ld_d);
+  else {
+    set_error("cast_rows: unsupported types");
+    return NGD_ERR_INVALID;
+  }
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_transpose_cast(int src_type, const void* src, int64_t ld_s, int64_t rows, int64_t cols,
+                                 int dst_type, void* dst, int64_t ld_d, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return NGD_OK;
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+#define NGD_TC(TS, TD)                                                                                         \
+  hipLaunchKernelGGL((transpose_cast_kernel<TS, TD>), grid, dim3(256), 0, s, (const TS*)src, ld_s, rows, cols, \
+                     (TD*)dst, ld_d)
+  if (src_type == NGD_F32 && dst_type == NGD_BF16) NGD_TC(float, __bf16);
+  else if (src_type == NGD_F32 && dst_type == NGD_F32) NGD_TC(float, float);
+  else if (src_type == NGD_F64 && dst_type == NGD_BF16) NGD_TC(double, __bf16);
+  else if (src_type == NGD_F64 && dst_type == NGD_F32) NGD_TC(double, float);
+  else {
+    set_error("transpose_cast: unsupported types");
+    return NGD_ERR_INVALID;
+  }
+#undef NGD_TC
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+}  // namespace ngd
