@@ -7,8 +7,10 @@ matvecs with FP64 CG scalars, sketch size ell = 400, PCG to relative residual 1e
 mu = max(10 eps lam1_hat, 1e-4 L^2). One step = residuals + Jacobian + gradient, Gaussian sketch
 and FP64 Nystrom core, damping, PCG, Armijo line search and update: the whole hot path.
 
-Prints one JSON line with the steps/s of the Nystrom-PCG loop (`value`), plain-CG steps/s, the
-one-pass Gramian-matvec bandwidth with its roofline, and the FP64 CPU oracle timed on the host.
+Both solvers run the same trajectory length from the same start (default 2 warm-up + 48 timed NGD
+steps each, the 50-step comparison of the workload). Prints one JSON line with the steps/s of the
+Nystrom-PCG loop (`value`), plain-CG steps/s, the one-pass Gramian-matvec bandwidth with its roofline,
+the sketch contractions against the MFMA peak, and the FP64 CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -32,7 +34,21 @@ WORKLOADS = {
           "ell=400, PCG rtol 1e-6",
     "c3": "5D Poisson 5-128-128-128-1 tanh (P=33,921), 16,384 + 2,048 points, FP32 Jacobian, BF16 sketch, "
           "FP64 core, ell=800, PCG rtol 1e-6",
+    "c4": "2+1D heat 3-64-64-64-64-1 tanh (P=12,801), 8,192 + 1,024 lateral + 1,024 initial points, FP32, "
+          "J recomputed by the JVP / adjoint kernels (never stored), ell=400, PCG rtol 1e-6",
 }
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def recompute_matvec_flops(prob) -> float:
+    """Floating-point operations of one recompute-mode Gramian matvec (tangent pass + adjoint pass),
+    counted from the implemented recurrences: per point and channel, the tangent pass does the primal
+    and two tangent layer products (3 W multiply-adds, W = sum of n_in n_out over the layers), the
+    adjoint pass the primal and the adjoint products (2 W) plus the parameter derivative (P)."""
+    widths = prob.widths
+    W = sum(widths[i] * widths[i + 1] for i in range(len(widths) - 1))
+    C = 1 + (prob.d if prob.pde == 0 else prob.d - 1) + 1 + (0 if prob.pde == 0 else 1)
+    return 2.0 * prob.n_rows * C * (5 * W + prob.n_params)
 
 
 def _cpu_threads():
@@ -70,13 +86,14 @@ def cpu_baseline(cfg: str, seed: int, steps: int = 1):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=48)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--cg-steps", type=int, default=3)
+    ap.add_argument("--cg-steps", type=int, default=None,
+                    help="timed plain-CG steps after the same warm-up (default: --steps, the same trajectory length)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cg", action="store_true", help="skip the plain-CG comparison loop")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to calibrate the HBM traffic counters")
@@ -111,18 +128,20 @@ def main(argv=None):
     gp.timing(False)
     nys_sps = a.steps / (t1 - t0)
 
-    # ---- plain CG NGD (same start, power-method damping, maxit = P) ----
+    # ---- plain CG NGD: the same start, warm-up and number of steps (power-method damping, maxit = P) ----
     cg = None
     creps, cg_sps = [], float("nan")
-    if not a.no_cg:
+    cg_steps = a.steps if a.cg_steps is None else a.cg_steps
+    if not a.no_cg and cg_steps > 0:
         cg = NGD(prob, theta0, solver="cg", rtol=rtol, seed=a.seed)
-        cg.step()  # warmup
+        for _ in range(a.warmup):
+            cg.step()
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        creps = [cg.step() for _ in range(a.cg_steps)]
+        creps = [cg.step() for _ in range(cg_steps)]
         torch.cuda.synchronize()
         c1 = time.perf_counter()
-        cg_sps = a.cg_steps / (c1 - c0)
+        cg_sps = cg_steps / (c1 - c0)
 
     if a.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
@@ -138,6 +157,9 @@ def main(argv=None):
     elem = 8 if prob.dtype == "f64" else 4
     alg_bytes = N * P * elem + 2 * P * 8
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    if prob.recompute:  # no stored J: the matvec is bound by the vector ALUs, not HBM
+        mv_flops = recompute_matvec_flops(prob)
+        achieved_tf = mv_flops / (avg_ms * 1e-3) / 1e12
     phases = {k: {"launches": n, "avg_ms": (ms / n if n else 0.0), "ms_per_step": ms / a.steps}
               for k, (n, ms) in timers.items()}
     # ---- MFMA roofline of the two sketch contractions (Z = J Omega, B^T = Q^T J) ----
@@ -160,20 +182,30 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64" if prob.dtype == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}", "P": P, "N": N, "ell": prob.ell,
-                   "sketch_dtype": prob.sketch_dtype},
-        "plain_cg": ({"value": cg_sps, "unit": "NGD steps/s", "steps": a.cg_steps,
+        "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}; {a.warmup} + {a.steps} NGD steps per solver "
+                               f"from the same Glorot start (the last {a.steps} timed)",
+                   "P": P, "N": N, "ell": prob.ell, "sketch_dtype": prob.sketch_dtype,
+                   "recompute": bool(prob.recompute)},
+        "plain_cg": ({"value": cg_sps, "unit": "NGD steps/s", "steps": cg_steps, "warmup": a.warmup,
                       "mean_cg_iters": float(np.mean([r.iters for r in creps])),
-                      "converged": all(r.converged for r in creps)} if creps else None),
+                      "cg_iters": [r.iters for r in creps],
+                      "converged": all(r.converged for r in creps),
+                      "loss_first_last": [creps[0].loss, creps[-1].loss_new]} if creps else None),
         "nystrom_mean_pcg_iters": float(np.mean([r.iters for r in reps])),
+        "nystrom_pcg_iters": [r.iters for r in reps],
         "nystrom_converged": all(r.converged for r in reps),
         "speedup_vs_plain_cg": (nys_sps / cg_sps) if creps else None,
-        "matvec_gbs": achieved,
+        "matvec_gbs": None if prob.recompute else achieved,
         "loss_first_last": [reps[0].loss, reps[-1].loss_new],
         "phases": phases,
-        "roofline": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv},
+        "roofline": ({"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": achieved,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv}
+                     if not prob.recompute else
+                     {"bound": "alu", "kernel": "jvp_kernel + residual_jacobian_kernel<VJP> (J v, J^T t)",
+                      "achieved": achieved_tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                      "alg_flops_per_launch": mv_flops, "avg_launch_ms": avg_ms, "launches": n_mv}),
         "roofline_sketch": {"bound": "mfma", "kernel": "gemm_kernel (Z = J Omega and B^T = Q^T J)",
                             "achieved": sk_achieved, "peak": sk_peak, "unit": "TFLOP/s",
                             "frac": sk_achieved / sk_peak, "compute_dtype": prob.sketch_dtype,

@@ -72,12 +72,15 @@ typedef struct {
 
 typedef struct ngd_problem ngd_problem;  /* opaque; owns device workspace only */
 
-/* The linear operator J_w at a fixed theta. J must be the stored Jacobian (N x P, leading
- * dimension ldJ >= P, dtype) produced by ngd_residual_jacobian for `theta`. */
+/* The linear operator J_w at a fixed theta. Either J is the stored Jacobian (N x P, leading
+ * dimension ldJ >= P, dtype) produced by ngd_residual_jacobian for `theta`, or J is NULL: the
+ * recompute mode, where every product with J_w or J_w^T is formed from theta by the forward-
+ * tangent (ngd_jvp) and adjoint (ngd_vjp) kernels and J_w is never stored (for N x P beyond memory;
+ * "Recompute Jacobian" of Section 4.1.2). */
 typedef struct {
-  const void* theta;       /* device, P, dtype (kept for reference; not read by the stored path) */
-  const void* J;           /* device, N x ldJ, dtype; P <= ldJ <= ngd_recommended_ld */
-  int64_t ldJ;
+  const void* theta;       /* device, P, dtype (read only in the recompute mode) */
+  const void* J;           /* device, N x ldJ, dtype, or NULL (recompute mode) */
+  int64_t ldJ;             /* P <= ldJ <= ngd_recommended_ld when J != NULL */
 } ngd_operator;
 
 /* Create a handle: copies the descriptor (pointers are kept, data is not copied) and allocates the
@@ -99,13 +102,29 @@ const char* ngd_last_error(void);
  *   theta : device, P, dtype.
  *   r_w   : device, N, dtype, out: sqrt(w_r) * residual_r.
  *   J_w   : device, N x ldJ, dtype, out: d r_w / d theta (columns P..ldJ-1 are set to 0). ldJ >= P.
- *   grad  : device, P, double, out (nullable): J_w^T r_w = grad L. Requires J_w.
+ *   grad  : device, P, double, out (nullable): J_w^T r_w = grad L.
  *   loss  : device, 1 double, out (nullable): L = 1/2 sum r_w^2.
- * J_w may be NULL to evaluate residuals and loss only (forward pass, no Jacobian); grad must then
- * be NULL.
+ * J_w may be NULL (recompute mode): residuals and loss come from the forward pass alone, and grad
+ * (if requested) from the adjoint kernel of ngd_vjp.
  */
 ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, void* J_w, int64_t ldJ,
                                  double* grad, double* loss, void* stream);
+
+/*
+ * Forward-mode product with the residual Jacobian (the parameter JVP of r_w, eq. G_matrixfree):
+ * Y[j] = J_w(theta) V[j] for j < k, computed from theta without forming J_w.
+ *   V : device, k x ldV, dtype (direction j at V + j*ldV; ldV >= P when k > 1).
+ *   Y : device, k x ldY, dtype, out (N-vector j at Y + j*ldY; ldY >= N when k > 1).
+ */
+ngd_status ngd_jvp(ngd_problem* h, const void* theta, const void* V, int64_t ldV, int64_t k, void* Y,
+                   int64_t ldY, void* stream);
+
+/*
+ * Adjoint product (the VJP of r_w): out = J_w(theta)^T wv, by the reverse sweep with its seeds scaled
+ * by wv and the per-point parameter derivatives summed in workgroup partials (fixed-order sums).
+ *   wv : device, N, dtype. out : device, P doubles.
+ */
+ngd_status ngd_vjp(ngd_problem* h, const void* theta, const void* wv, double* out, void* stream);
 
 /*
  * Damped Gramian products Y[j] = (J_w^T J_w + lambda I) V[j] for j < k (eq. G_matrixfree,

@@ -50,6 +50,9 @@ SIGNATURES = {
                                         C.c_void_p, C.c_void_p]),
     "ngd_gramian_matvec": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int64, C.c_int64, C.c_double,
                                      C.c_void_p, C.c_int64, C.c_void_p]),
+    "ngd_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                          C.c_void_p]),
+    "ngd_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ngd_gaussian_omega": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint64, C.c_int64, C.c_void_p, C.c_int64,
                                      C.c_void_p]),
     "ngd_nystrom_sketch": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_int64, C.c_uint64, C.c_uint64, C.c_void_p,

@@ -51,6 +51,14 @@ class PcgResult:
     status: int
 
 
+class Recompute:
+    """Operator marker for the recompute mode: every product with J_w or J_w^T is formed from theta by
+    the forward-tangent and adjoint kernels; J_w is never stored."""
+
+    def __init__(self, theta: torch.Tensor):
+        self.theta = theta
+
+
 class Problem:
     """A PINN least-squares problem bound to a libngd handle.
 
@@ -103,7 +111,10 @@ class Problem:
     def new_jacobian(self) -> torch.Tensor:
         return torch.empty((self.N, self.ld), dtype=self.tdtype, device=self.device)
 
-    def _op(self, J: torch.Tensor, theta: Optional[torch.Tensor] = None) -> L.Operator:
+    def _op(self, J, theta: Optional[torch.Tensor] = None) -> L.Operator:
+        if isinstance(J, Recompute):
+            _need(J.theta, self.tdtype, "theta")
+            return L.Operator(J.theta.data_ptr(), None, 0)
         _need(J, self.tdtype, "J")
         if J.dim() != 2 or J.shape[0] != self.N or J.stride(1) != 1:
             raise ValueError("J must be an N x ld row-major tensor")
@@ -115,7 +126,7 @@ class Problem:
         """ngd_residual_jacobian: returns (r_w, J or None, grad or None, loss tensor or None)."""
         _need(theta, self.tdtype, "theta")
         r = torch.empty(self.N, dtype=self.tdtype, device=self.device)
-        grad = torch.empty(self.P, dtype=torch.float64, device=self.device) if (want_grad and J is not None) else None
+        grad = torch.empty(self.P, dtype=torch.float64, device=self.device) if want_grad else None
         loss = torch.empty(1, dtype=torch.float64, device=self.device) if want_loss else None
         ldJ = J.stride(0) if J is not None else 0
         if J is not None:
@@ -133,6 +144,25 @@ class Problem:
         L.check(self.lib.ngd_gramian_matvec(self.h, C.byref(self._op(J)), _ptr(V2), V2.stride(0), V2.shape[0],
                                             float(lam), _ptr(Y), Y.stride(0), _stream()), "ngd_gramian_matvec")
         return Y.reshape(-1) if vec else Y
+
+    def jvp(self, theta: torch.Tensor, V: torch.Tensor) -> torch.Tensor:
+        """ngd_jvp: J_w(theta) V for V (P,) or (k, ld); returns (N,) or (k, N) in the working dtype."""
+        _need(theta, self.tdtype, "theta")
+        _need(V, self.tdtype, "V")
+        vec = V.dim() == 1
+        V2 = V.reshape(1, -1) if vec else V
+        Y = torch.empty((V2.shape[0], self.N), dtype=self.tdtype, device=self.device)
+        L.check(self.lib.ngd_jvp(self.h, _ptr(theta), _ptr(V2), V2.stride(0), V2.shape[0], _ptr(Y), Y.stride(0),
+                                 _stream()), "ngd_jvp")
+        return Y.reshape(-1) if vec else Y
+
+    def vjp(self, theta: torch.Tensor, wv: torch.Tensor) -> torch.Tensor:
+        """ngd_vjp: J_w(theta)^T wv for wv (N,) in the working dtype; returns P doubles."""
+        _need(theta, self.tdtype, "theta")
+        _need(wv, self.tdtype, "wv")
+        out = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        L.check(self.lib.ngd_vjp(self.h, _ptr(theta), _ptr(wv), _ptr(out), _stream()), "ngd_vjp")
+        return out
 
     def gaussian_omega(self, seed: int, counter: int, ell: int) -> torch.Tensor:
         out = torch.zeros((ell, self.ld), dtype=self.tdtype, device=self.device)

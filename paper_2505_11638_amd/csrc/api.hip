@@ -50,6 +50,9 @@ struct ngd_problem {
   void* Jt;          // P x ldN, J_w^T in the sketch compute type (FP32 problems)
   void* Qt;          // max_ell x ldN, Q^T in the sketch compute type (FP32 problems)
   void* Ob;          // max_ell x ldP, Omega^T in BF16 (FP32 problems)
+  double* nvec[2];   // N-vectors (FP64): recompute-mode J v and adjoint weights
+  void* pt;          // ldP, dtype: the current CG direction for the recompute-mode JVP
+  int nwg_vjp;       // workgroups of the recompute-mode adjoint product
   float* sk_work;    // split-K partials of the sketch products (FP32 problems)
   int64_t sk_work_elems;
   double* M;         // ell x ell
@@ -161,7 +164,10 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 ngd_status check_op(const ngd_problem* h, const ngd_operator* op) {
   NGD_CHECK(op != nullptr, "operator is NULL");
-  NGD_CHECK(op->J != nullptr, "operator has no stored Jacobian (recompute mode is not available in this entry point)");
+  if (op->J == nullptr) {  // recompute mode: J_w products from theta by the JVP / adjoint kernels
+    NGD_CHECK(op->theta != nullptr, "recompute mode (J == NULL) needs theta");
+    return NGD_OK;
+  }
   NGD_CHECK(op->ldJ >= h->P, "ldJ < P");
   NGD_CHECK(op->ldJ <= h->ldP, "ldJ must not exceed ngd_recommended_ld");
   const int vn = h->dtype == NGD_F64 ? 2 : 4;
@@ -171,8 +177,21 @@ ngd_status check_op(const ngd_problem* h, const ngd_operator* op) {
   return NGD_OK;
 }
 
+// recompute mode: t = J_w v (v: P, dtype) into nvec[0], then the adjoint partials of J_w^T t
+ngd_status recompute_rows(ngd_problem* h, const ngd_operator* op, const void* v_dtype, hipStream_t s) {
+  NGD_TRY(launch_jvp(h->net, h->dtype, op->theta, v_dtype, h->ldP, 1, h->N, h->X, h->w, h->kind, NGD_F64, h->nvec[0],
+                     1, 0, s));
+  return launch_vjp(h->net, h->dtype, op->theta, h->N, h->X, h->w, h->f, h->g, h->kind, h->nvec[0], 1, h->partial,
+                    h->ldP, h->tsq, h->nwg_vjp, s);
+}
+
 // y = (J^T J + lambda I) v, all FP64 P-vectors
 ngd_status gram_apply(ngd_problem* h, const ngd_operator* op, const double* v, double lambda, double* y, hipStream_t s) {
+  if (op->J == nullptr) {
+    NGD_TRY(launch_cast(NGD_F64, v, h->dtype, h->pt, h->P, s));
+    NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] { return recompute_rows(h, op, h->pt, s); }));
+    return launch_gram_reduce(h->dtype, h->partial, h->nwg_vjp, h->ldP, h->P, v, lambda, y, s);
+  }
   NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
     return launch_gram_rows(h->dtype, op->J, op->ldJ, h->N, h->P, v, h->partial, h->tsq, h->nwg, s);
   }));
@@ -237,6 +256,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   h->tp = residual_block_rows(net, d->dtype);
   h->res_blocks = (int)((h->N + h->tp - 1) / h->tp);
   h->nwg = gram_rows_grid(d->dtype, h->N, h->P);
+  h->nwg_vjp = vjp_grid(net, d->dtype, h->N, h->nwg);
 
   const int64_t N = h->N, P = h->P, ldP = h->ldP, L = h->max_ell;
   const size_t e = h->elem;
@@ -273,6 +293,9 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->gemm_work, sizeof(double) * 8 * (size_t)L * L});
   plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
   plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
+  plan.push_back({(void**)&h->nvec[0], sizeof(double) * (size_t)N});
+  plan.push_back({(void**)&h->nvec[1], sizeof(double) * (size_t)N});
+  plan.push_back({&h->pt, (size_t)ldP * e});
   plan.push_back({(void**)&h->alphas, sizeof(double) * kTrials});
   plan.push_back({(void**)&h->losses, sizeof(double) * kTrials});
   size_t total = 0;
@@ -323,7 +346,7 @@ int64_t ngd_workspace_bytes(const ngd_problem* h) { return h ? (int64_t)h->bytes
 ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, void* J_w, int64_t ldJ, double* grad,
                                  double* loss, void* stream) {
   NGD_CHECK(h != nullptr && theta != nullptr && r_w != nullptr, "NULL argument");
-  NGD_CHECK(grad == nullptr || J_w != nullptr, "grad requires J_w");
+
   if (J_w != nullptr) NGD_CHECK(ldJ >= h->P, "ldJ < P");
   hipStream_t s = S(stream);
   NGD_TRY(timed(h, J_w ? NGD_TIMER_RESIDUAL_JACOBIAN : -1, s, [&] {
@@ -331,7 +354,15 @@ ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, v
                                     h->loss_part, 0, 1, s, nullptr);
   }));
   if (loss != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, 1, 0.5, loss, s));
-  if (grad != nullptr) NGD_TRY(launch_gradient(h->dtype, J_w, ldJ, h->N, h->P, r_w, h->grad_work, grad, s));
+  if (grad != nullptr && J_w != nullptr)
+    NGD_TRY(launch_gradient(h->dtype, J_w, ldJ, h->N, h->P, r_w, h->grad_work, grad, s));
+  if (grad != nullptr && J_w == nullptr) {
+    // recompute mode: grad = J_w^T r_w by the adjoint kernel
+    NGD_TRY(launch_cast(h->dtype, r_w, NGD_F64, h->nvec[1], h->N, s));
+    NGD_TRY(launch_vjp(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, h->nvec[1], 1, h->partial,
+                       h->ldP, h->tsq, h->nwg_vjp, s));
+    NGD_TRY(launch_gram_reduce(h->dtype, h->partial, h->nwg_vjp, h->ldP, h->P, nullptr, 0.0, grad, s));
+  }
   return NGD_OK;
 }
 
@@ -345,10 +376,15 @@ ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void
   NGD_CHECK(V != Y, "Y must not alias V");
   hipStream_t s = S(stream);
   const int64_t P = h->P;
-  if (k == 1) {
-    NGD_TRY(launch_cast(h->dtype, V, NGD_F64, h->vtmp[0], P, s));
-    NGD_TRY(gram_apply(h, op, h->vtmp[0], lambda, h->vtmp[1], s));
-    return launch_cast(NGD_F64, h->vtmp[1], h->dtype, Y, P, s);
+  if (k == 1 || op->J == nullptr) {  // one vector at a time (the recompute mode always)
+    for (int64_t j = 0; j < k; ++j) {
+      const char* Vj = static_cast<const char*>(V) + (size_t)j * ldV * h->elem;
+      char* Yj = static_cast<char*>(Y) + (size_t)j * ldY * h->elem;
+      NGD_TRY(launch_cast(h->dtype, Vj, NGD_F64, h->vtmp[0], P, s));
+      NGD_TRY(gram_apply(h, op, h->vtmp[0], lambda, h->vtmp[1], s));
+      NGD_TRY(launch_cast(NGD_F64, h->vtmp[1], h->dtype, Yj, P, s));
+    }
+    return NGD_OK;
   }
   // block product through the sketch buffers, max_ell columns at a time
   const int gt = h->dtype == NGD_F64 ? G_F64 : G_F32;
@@ -363,6 +399,23 @@ ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void
     if (lambda != 0.0) NGD_TRY(launch_add_scaled(h->dtype, Vc, ldV, lambda, Yc, ldY, kc, P, s));
   }
   return NGD_OK;
+}
+
+ngd_status ngd_jvp(ngd_problem* h, const void* theta, const void* V, int64_t ldV, int64_t k, void* Y, int64_t ldY,
+                   void* stream) {
+  NGD_CHECK(h != nullptr && theta != nullptr && V != nullptr && Y != nullptr, "NULL argument");
+  NGD_CHECK(k >= 1, "k must be >= 1");
+  NGD_CHECK(k == 1 || (ldV >= h->P && ldY >= h->N), "ldV >= P and ldY >= N required");
+  return launch_jvp(h->net, h->dtype, theta, V, ldV, k, h->N, h->X, h->w, h->kind, h->dtype, Y, 1, ldY, S(stream));
+}
+
+ngd_status ngd_vjp(ngd_problem* h, const void* theta, const void* wv, double* out, void* stream) {
+  NGD_CHECK(h != nullptr && theta != nullptr && wv != nullptr && out != nullptr, "NULL argument");
+  hipStream_t s = S(stream);
+  NGD_TRY(launch_cast(h->dtype, wv, NGD_F64, h->nvec[1], h->N, s));
+  NGD_TRY(launch_vjp(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, h->nvec[1], 1, h->partial,
+                     h->ldP, h->tsq, h->nwg_vjp, s));
+  return launch_gram_reduce(h->dtype, h->partial, h->nwg_vjp, h->ldP, h->P, nullptr, 0.0, out, s);
 }
 
 ngd_status ngd_gaussian_omega(ngd_problem* h, uint64_t seed, uint64_t counter, int64_t ell, void* omega, int64_t ld,
@@ -396,9 +449,12 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     omega = h->omega;
     ldO = h->ldP;
   }
+  // recompute mode: the ell columns of Z = J_w Omega by the JVP kernel, the rows of B^T = Q^T J_w by
+  // the adjoint kernel (one launch per column of Q); the products run in the problem's dtype
+  const bool rec = op->J == nullptr;
   // the NT kernel (large tiles, both operands K-contiguous) serves the FP32 / BF16 sketch
   const int et = gt == G_BF16 ? NGD_BF16 : NGD_F32;
-  const bool nt = T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
+  const bool nt = !rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
                   nt_gemm_supported(et, et, gt, P, L, N, h->ldN, h->ldN);
   // Omega^T in the compute type (BF16: a rounded copy, read at half the bytes)
   const void* om_nt = omega;
@@ -412,6 +468,8 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   }
   // Z = J Omega (N x ell)
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] {
+    if (rec)
+      return launch_jvp(h->net, T, op->theta, omega, ldO, L, N, h->X, h->w, h->kind, T, h->Z, L, 1, s);
     if (nt) return launch_nt_gemm(NGD_F32, op->J, op->ldJ, om_type, om_nt, ld_nt, gt, N, L, P, NGD_F32, h->Z, L,
                                   false, 1.0, h->sk_work, h->sk_work_elems, s);
     GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
@@ -440,6 +498,15 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
       return launch_transpose_cast(NGD_F64, h->Q, L, N, L, et, h->Qt, h->ldN, s);
     }));
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
+    if (rec) {
+      for (int64_t j = 0; j < L; ++j) {
+        NGD_TRY(launch_vjp(h->net, T, op->theta, N, h->X, h->w, h->f, h->g, h->kind, (const double*)h->Q + j, L,
+                           h->partial, h->ldP, h->tsq, h->nwg_vjp, s));
+        NGD_TRY(launch_partials_to_row(T, h->partial, h->nwg_vjp, h->ldP, P,
+                                       static_cast<char*>(h->Bt) + (size_t)j * h->ldP * h->elem, s));
+      }
+      return NGD_OK;
+    }
     if (nt) return launch_nt_gemm(et, h->Jt, h->ldN, et, h->Qt, h->ldN, gt, P, L, N, NGD_F32, h->Bt, h->ldP, true,
                                   1.0, h->sk_work, h->sk_work_elems, s);
     GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
@@ -515,12 +582,20 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
     for (; k < upto; ++k) {
       double* pprev = h->pcg_p[k & 1];
       double* pcur = h->pcg_p[(k + 1) & 1];
-      NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
-        return pcg_launch_rows(h->dtype, op->J, op->ldJ, h->N, P, zsrc, pprev, pcur, h->pcg_st, h->partial, h->tsq,
-                               h->nwg, s);
-      }));
-      NGD_TRY(pcg_launch_update(h->dtype, h->partial, h->nwg, op->ldJ, P, pcur, h->tsq, d, h->pcg_r, h->pcg_part,
-                                h->pcg_st, plain, s));
+      if (op->J != nullptr) {
+        NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
+          return pcg_launch_rows(h->dtype, op->J, op->ldJ, h->N, P, zsrc, pprev, pcur, h->pcg_st, h->partial, h->tsq,
+                                 h->nwg, s);
+        }));
+        NGD_TRY(pcg_launch_update(h->dtype, h->partial, h->nwg, op->ldJ, P, pcur, h->tsq, d, h->pcg_r, h->pcg_part,
+                                  h->pcg_st, plain, s));
+      } else {
+        // recompute mode: the same iteration with J_w p by the JVP and J_w^T (J_w p) by the adjoint kernel
+        NGD_TRY(pcg_launch_direction(h->dtype, zsrc, pprev, P, pcur, h->pt, h->pcg_part, h->pcg_st, s));
+        NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] { return recompute_rows(h, op, h->pt, s); }));
+        NGD_TRY(pcg_launch_update(h->dtype, h->partial, h->nwg_vjp, h->ldP, P, pcur, h->tsq, d, h->pcg_r,
+                                  h->pcg_part, h->pcg_st, plain, s));
+      }
       if (!plain)
         NGD_TRY(timed(h, NGD_TIMER_PRECOND, s, [&] {
           return pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, lambda, h->pcg_s,

@@ -16,38 +16,41 @@ namespace ngd {
 namespace {
 
 constexpr int kNb = 32;
+constexpr int kLd = kNb + 1;  // LDS row pitch of a staged block
 
-// factor the kNb x kNb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, row-major kNb x kNb)
+// factor the nb x nb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, kNb x kLd), one
+// wave: lane r % 32 owns row r, the two half-waves split the columns of the trailing update
 __device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb, double floor, double null_thresh,
                             double* Ls, int* nmod) {
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    Ls[e] = c <= r ? A[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  const int t = threadIdx.x;
+  for (int e = t; e < kNb * kNb; e += blockDim.x) {
+    const int r = e >> 5, c = e & 31;
+    Ls[r * kLd + c] = (r < nb && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
   }
   __syncthreads();
+  const int r = t & 31, half = t >> 5;
   for (int c = 0; c < nb; ++c) {
-    __shared__ double piv;
-    if (threadIdx.x == 0) {
-      double a = Ls[c * nb + c];
+    if (t == 0) {
+      double a = Ls[c * kLd + c];
       if (!(a > null_thresh) && nmod) ++*nmod;  // direction at the level of the shift: numerically null
       if (!(a > floor)) a = floor;
-      piv = sqrt(a);
-      Ls[c * nb + c] = piv;
+      Ls[c * kLd + c] = sqrt(a);
     }
     __syncthreads();
-    const double p = piv;
-    for (int r = c + 1 + threadIdx.x; r < nb; r += blockDim.x) Ls[r * nb + c] /= p;
+    const double rp = 1.0 / Ls[c * kLd + c];
+    if (half == 0 && r > c && r < nb) Ls[r * kLd + c] *= rp;
     __syncthreads();
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-      const int r = e / nb, q = e - r * nb;
-      if (r > c && q > c && q <= r) Ls[e] -= Ls[r * nb + c] * Ls[q * nb + c];
+    if (r > c && r < nb) {
+      const double lrc = Ls[r * kLd + c];
+      for (int q = c + 1 + half; q <= r; q += 2) Ls[r * kLd + q] -= lrc * Ls[q * kLd + c];
     }
     __syncthreads();
   }
 }
 
-// one row x (nb values) of X: solve x L^T = x in place, L lower kNb x kNb in LDS
-__device__ __forceinline__ void solve_row(double* __restrict__ x, const double* Ls, int nb) {
+// one row x (nb values) of X: solve x L^T = x in place; L lower in LDS (pitch kLd), rdiag its
+// reciprocal diagonal
+__device__ __forceinline__ void solve_row(double* __restrict__ x, const double* Ls, const double* rdiag, int nb) {
   double v[kNb];
 #pragma unroll
   for (int j = 0; j < kNb; ++j) v[j] = j < nb ? x[j] : 0.0;
@@ -57,8 +60,8 @@ __device__ __forceinline__ void solve_row(double* __restrict__ x, const double* 
       double s = v[j];
 #pragma unroll
       for (int k = 0; k < kNb; ++k)
-        if (k < j) s -= v[k] * Ls[j * nb + k];
-      v[j] = s / Ls[j * nb + j];
+        if (k < j) s -= v[k] * Ls[j * kLd + k];
+      v[j] = s * rdiag[j];
     }
   }
 #pragma unroll
@@ -66,17 +69,17 @@ __device__ __forceinline__ void solve_row(double* __restrict__ x, const double* 
     if (j < nb) x[j] = v[j];
 }
 
-// Cholesky of the diagonal block of panel j0, written back in place (one workgroup)
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int n, int j0, int nb,
-                                                        const double* __restrict__ floor_p, int* __restrict__ nmod) {
-  __shared__ double Ls[kNb * kNb];
+// Cholesky of the diagonal block of panel j0, written back in place (one wave)
+__global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, int n, int j0, int nb,
+                                                       const double* __restrict__ floor_p, int* __restrict__ nmod) {
+  __shared__ double Ls[kNb * kLd];
   __shared__ int local_mod;
   if (threadIdx.x == 0) local_mod = 0;
   __syncthreads();
   factor_diag(A, n, j0, nb, floor_p[0], floor_p[2], Ls, &local_mod);
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    A[(int64_t)(j0 + r) * n + j0 + c] = c <= r ? Ls[e] : 0.0;
+  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    const int r = e >> 5, c = e & 31;
+    if (r < nb && c < nb) A[(int64_t)(j0 + r) * n + j0 + c] = c <= r ? Ls[r * kLd + c] : 0.0;
   }
   if (threadIdx.x == 0) *nmod += local_mod;
 }
@@ -84,14 +87,17 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, 
 // rows of X (FP64, ld ldx): X[r, j0:j0+nb] <- X[r, j0:j0+nb] L_JJ^{-T}, L read from the factor
 __global__ __launch_bounds__(256) void trsm_rows_kernel(const double* __restrict__ L, int n, int j0, int nb,
                                                         double* __restrict__ X, int64_t ldx, int64_t nrows) {
-  __shared__ double Ls[kNb * kNb];
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    const int r = e / nb, c = e - r * nb;
-    Ls[e] = c <= r ? L[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
+  __shared__ double Ls[kNb * kLd];
+  __shared__ double rdiag[kNb];
+  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    const int r = e >> 5, c = e & 31;
+    Ls[r * kLd + c] = (r < nb && c <= r) ? L[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
   }
   __syncthreads();
+  if (threadIdx.x < kNb) rdiag[threadIdx.x] = threadIdx.x < nb ? 1.0 / Ls[threadIdx.x * kLd + threadIdx.x] : 0.0;
+  __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nrows) solve_row(X + r * ldx + j0, Ls, nb);
+  if (r < nrows) solve_row(X + r * ldx + j0, Ls, rdiag, nb);
 }
 
 // nu = shift_rel * trace(M) added to the diagonal; floor = floor_rel * trace(M)

@@ -118,6 +118,15 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
                                     int64_t theta_stride, int n_theta, hipStream_t s, int* n_blocks_out);
 ngd_status launch_reduce_sum(const double* partial, int64_t n_per, int n_sets, double scale, double* out,
                              hipStream_t s);
+// recompute mode: J_w^T wv accumulated into nwg partial rows (ld) and sum wv^2 into tsq[nwg];
+// J_w u_j for k directions into out[r * ldo + j * cs]
+int vjp_grid(const NetDesc& net, int dtype, int64_t N, int max_wg);
+ngd_status launch_vjp(const NetDesc& net, int dtype, const void* theta, int64_t N, const void* X, const void* w,
+                      const void* f, const void* g, const int8_t* kind, const double* wv, int64_t wv_stride,
+                      void* partial, int64_t ld, double* tsq, int nwg, hipStream_t s);
+ngd_status launch_jvp(const NetDesc& net, int dtype, const void* theta, const void* U, int64_t ldU, int64_t k,
+                      int64_t N, const void* X, const void* w, const int8_t* kind, int out_type, void* out,
+                      int64_t ldo, int64_t cs, hipStream_t s);
 ngd_status launch_gradient(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const void* r,
                            double* work, double* grad, hipStream_t s);
 int gradient_chunks(int64_t N);
@@ -183,6 +192,10 @@ ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int
 ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,
                              const double* tsq, double* x, double* r, double* rr_part, PcgState* st, int plain,
                              hipStream_t s);
+ngd_status launch_partials_to_row(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, void* out,
+                                  hipStream_t s);
+ngd_status pcg_launch_direction(int dtype, const double* z, const double* p_prev, int64_t P, double* p_cur, void* p_t,
+                                double* part, PcgState* st, hipStream_t s);
 ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
 

@@ -186,13 +186,19 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
   }
 }
 
+// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots of T - x I). The pivot
+// recurrence divides by the previous pivot through a reciprocal refined by one Newton step (within
+// an ulp or two of the quotient: the count is then that of a T perturbed at roundoff level, which
+// is all bisection needs).
 __device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0) ++cnt;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    q = (d[i] - x) - e2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0) ++cnt;
   }
@@ -395,12 +401,12 @@ __global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, co
 constexpr int kWy = 16;   // reflectors per block
 constexpr int kNC = 8;    // eigenvector columns per workgroup
 
-// T of every block (one workgroup per block), stored kWy x kWy per block
+// T of every block of wy (<= kWy) reflectors (one workgroup per block), stored kWy x kWy per block
 __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V, const double* __restrict__ tau, int n,
-                                                   double* __restrict__ Tall) {
+                                                   int wy, double* __restrict__ Tall) {
   const int nref = n - 2;
-  const int k0 = blockIdx.x * kWy;
-  const int m = min(kWy, nref - k0);
+  const int k0 = blockIdx.x * wy;
+  const int m = min(wy, nref - k0);
   __shared__ double Gm[kWy][kWy];
   __shared__ double Ts[kWy][kWy];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -434,10 +440,11 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V,
   for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Tall[(int64_t)blockIdx.x * kWy * kWy + e] = (&Ts[0][0])[e];
 }
 
-// kNC columns of Z per workgroup: for each block from the last, Z <- Z - Y (T (Y^T Z)); then the
-// columns are written as eigenvector rows in descending eigenvalue order (dropped pairs as zeros)
+// kNC columns of Z per workgroup: for each block of wy reflectors from the last, the block's
+// reflectors are staged in LDS and Z <- Z - Y (T (Y^T Z)); then the columns are written as
+// eigenvector rows in descending eigenvalue order (dropped pairs as zeros)
 __global__ __launch_bounds__(256) void backtransform_kernel(const double* __restrict__ Z, const double* __restrict__ V,
-                                                            const double* __restrict__ Tall,
+                                                            const double* __restrict__ Tall, int wy,
                                                             const double* __restrict__ lam_asc, int n,
                                                             const double* __restrict__ tnorm, double drop_rel,
                                                             double* __restrict__ evals_desc,
@@ -445,32 +452,35 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
   const double drop = drop_rel * (*tnorm);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* zc = reinterpret_cast<double*>(smem_raw);  // kNC x n
+  double* Ys = zc + (size_t)kNC * n;                 // wy x n
   __shared__ double W[kWy][kNC];
   __shared__ double S[kWy][kNC];
   const int c0 = blockIdx.x * kNC;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int c = 0; c < kNC; ++c)
     for (int j = threadIdx.x; j < n; j += blockDim.x) zc[c * n + j] = (c0 + c < n) ? Z[(int64_t)j * n + c0 + c] : 0.0;
-  __syncthreads();
   const int nref = n - 2;
-  const int nblk = nref > 0 ? (nref + kWy - 1) / kWy : 0;
+  const int nblk = nref > 0 ? (nref + wy - 1) / wy : 0;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int k0 = b * kWy;
-    const int m = min(kWy, nref - k0);
-    // W = Y^T Z (one wave per (reflector, column) pair)
-    for (int q = wid; q < kWy * kNC; q += nw) {
+    const int k0 = b * wy;
+    const int m = min(wy, nref - k0);
+    __syncthreads();
+    for (int i = 0; i < m; ++i)
+      for (int j = threadIdx.x; j < n; j += blockDim.x) Ys[i * n + j] = V[(int64_t)(k0 + i) * n + j];
+    __syncthreads();
+    // W = Y^T Z (one wave per (reflector, column) pair); v_k is zero at and above row k
+    for (int q = wid; q < wy * kNC; q += nw) {
       const int i = q / kNC, c = q % kNC;
       double acc = 0.0;
       if (i < m) {
-        const double* vi = V + (int64_t)(k0 + i) * n;
-        for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += vi[j] * zc[c * n + j];
+        for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += Ys[i * n + j] * zc[c * n + j];
         acc = wave_sum(acc);
       }
       if (lane == 0) W[i][c] = acc;
     }
     __syncthreads();
     // S = T W
-    if (threadIdx.x < kWy * kNC) {
+    if (threadIdx.x < wy * kNC) {
       const int i = threadIdx.x / kNC, c = threadIdx.x % kNC;
       const double* T = Tall + (int64_t)b * kWy * kWy;
       double acc = 0.0;
@@ -481,19 +491,19 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
     __syncthreads();
     // Z -= Y S
     for (int j = k0 + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      double yv[kWy];
+      double acc[kNC];
 #pragma unroll
-      for (int i = 0; i < kWy; ++i) yv[i] = (i < m && j > k0 + i) ? V[(int64_t)(k0 + i) * n + j] : 0.0;
+      for (int c = 0; c < kNC; ++c) acc[c] = 0.0;
+      for (int i = 0; i < m; ++i) {
+        const double y = j > k0 + i ? Ys[i * n + j] : 0.0;
 #pragma unroll
-      for (int c = 0; c < kNC; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int i = 0; i < kWy; ++i) acc += yv[i] * S[i][c];
-        zc[c * n + j] -= acc;
+        for (int c = 0; c < kNC; ++c) acc[c] += y * S[i][c];
       }
+#pragma unroll
+      for (int c = 0; c < kNC; ++c) zc[c * n + j] -= acc[c];
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int c = 0; c < kNC; ++c) {
     const int col = c0 + c;
     if (col >= n) break;
@@ -530,7 +540,7 @@ struct EigWs {
     flags = reinterpret_cast<unsigned*>(tnorm + 8);
     err = reinterpret_cast<int*>(flags + 256);
     Tall = tnorm + 8 + 130;  // 256 unsigned + err word, rounded up to doubles
-    const size_t nblk = (size_t)(n + kWy - 1) / kWy + 1;
+    const size_t nblk = (size_t)n + 1;  // blocks of as few as one reflector
     bytes = (size_t)((Tall + nblk * kWy * kWy) - w) * sizeof(double);
   }
 };
@@ -627,12 +637,20 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   }
   // T factors of the reflector blocks (written over the multipliers of inverse iteration, free now)
   double* Tall = ws.Tall;
-  const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
-  if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, Tall);
+  // reflectors per block: as many as fit in LDS beside the kNC columns
+  int wy = kWy;
+  while (wy > 1 && (size_t)(kNC + wy) * n * sizeof(double) > 150 * 1024) wy >>= 1;
+  const size_t bt_lds = (size_t)(kNC + wy) * n * sizeof(double);
+  if (bt_lds > 150 * 1024) {
+    set_error("ell too large for the back-transformation's LDS budget");
+    return NGD_ERR_INVALID;
+  }
+  const int nblk = n > 2 ? (n - 2 + wy - 1) / wy : 0;
+  if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, wy, Tall);
   NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(kNC * n * sizeof(double))));
-  hipLaunchKernelGGL(backtransform_kernel, dim3((n + kNC - 1) / kNC), dim3(256), kNC * n * sizeof(double), s, Z, V,
-                     Tall, lam, n, tnorm, drop_rel, evals_desc, evec_rows);
+                                  (int)bt_lds));
+  hipLaunchKernelGGL(backtransform_kernel, dim3((n + kNC - 1) / kNC), dim3(256), bt_lds, s, Z, V, Tall, wy, lam, n,
+                     tnorm, drop_rel, evals_desc, evec_rows);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -97,16 +97,29 @@ __device__ void activate(const NetDesc& net, const T* pre_l, int n, int TP, T* h
   }
 }
 
-template <typename T>
+// MODE kJacobian: one tile of TP points per workgroup; writes r_w, the loss partial and (J != NULL)
+// the Jacobian rows. MODE kVjp: the workgroup loops over tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... and accumulates sum_r wv[r] dr_w[r]/dtheta into its own row of `J` (then a partial-sum buffer
+// with leading dimension ldJ), plus sum_r wv[r]^2 into tsq_out[blockIdx.x]: the adjoint product
+// J_w^T wv without storing J_w (the reverse sweep with its seeds scaled by wv).
+enum { kJacobian = 0, kVjp = 1 };
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void residual_jacobian_kernel(
     NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
     const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
-    T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP) {
+    T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
+    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
   const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
-  const int64_t row0 = (int64_t)blockIdx.x * TP;
+  const int64_t ntiles = (N + TP - 1) / TP;
+  const int64_t tile_step = MODE == kVjp ? (int64_t)gridDim.x : ntiles;
+  double tsq_acc = 0.0;
+  bool first = true;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += tile_step, first = false) {
+  const int64_t row0 = tile * TP;
 
   Lds<T> s;
   {
@@ -184,34 +197,62 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
         seed[0] = sw;
       }
       const T rw = sw * res;
-      if (r_w != nullptr && blockIdx.y == 0) r_w[row] = rw;
-      lsum = rw * rw;
+      if constexpr (MODE == kJacobian) {
+        if (r_w != nullptr && blockIdx.y == 0) r_w[row] = rw;
+        lsum = rw * rw;
+      } else {
+        const double wvr = wv[row * wv_stride];
+        tsq_acc += wvr * wvr;
+        for (int c = 0; c < kMaxChan; ++c) seed[c] *= (T)wvr;
+      }
     }
     for (int c = 0; c < kMaxChan; ++c) s.ub[p * kMaxChan + c] = seed[c];
   }
-  {
+  if constexpr (MODE == kJacobian) {
     __shared__ double red_d[4];
     double tot = block_sum<double>((double)lsum, red_d);
     if (threadIdx.x == 0 && loss_partial != nullptr)
       loss_partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (J == nullptr) return;
   }
-  if (J == nullptr) return;
   __syncthreads();
+  // accumulate into this workgroup's partial row (kVjp); a thread always owns the same entries
+  auto put = [&](int64_t idx, T v) {
+    T* q = J + (int64_t)blockIdx.x * ldJ + idx;
+    *q = first ? v : *q + v;
+  };
+  (void)put;
 
   // ---------------- reverse sweep and Jacobian rows ----------------
   const int64_t P = net.P;
   const int nvalid = (int)((N - row0) < TP ? (N - row0) : TP);
   // output layer: dr/dW_out[i] = sum_c seed_c h_c[i], dr/db_out = seed_value; zero padding
-  for (int p = 0; p < nvalid; ++p) {
-    T* Jrow = J + (row0 + p) * ldJ;
-    const T* sd = s.ub + p * kMaxChan;
+  if constexpr (MODE == kJacobian) {
+    for (int p = 0; p < nvalid; ++p) {
+      T* Jrow = J + (row0 + p) * ldJ;
+      const T* sd = s.ub + p * kMaxChan;
+      for (int i = threadIdx.x; i < n_last; i += blockDim.x) {
+        T acc = 0;
+        for (int c = 0; c < C; ++c) acc += sd[c] * s.hb[(p * C + c) * nm + i];
+        Jrow[net.woff[L - 1] + i] = acc;
+      }
+      if (threadIdx.x == 0) Jrow[net.boff[L - 1]] = sd[0];
+      for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) Jrow[j] = 0;
+    }
+  } else {
     for (int i = threadIdx.x; i < n_last; i += blockDim.x) {
       T acc = 0;
-      for (int c = 0; c < C; ++c) acc += sd[c] * s.hb[(p * C + c) * nm + i];
-      Jrow[net.woff[L - 1] + i] = acc;
+      for (int p = 0; p < nvalid; ++p)
+        for (int c = 0; c < C; ++c) acc += s.ub[p * kMaxChan + c] * s.hb[(p * C + c) * nm + i];
+      put(net.woff[L - 1] + i, acc);
     }
-    if (threadIdx.x == 0) Jrow[net.boff[L - 1]] = sd[0];
-    for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) Jrow[j] = 0;
+    if (threadIdx.x == 0) {
+      T acc = 0;
+      for (int p = 0; p < nvalid; ++p) acc += s.ub[p * kMaxChan];
+      put(net.boff[L - 1], acc);
+    }
+    if (first)
+      for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) J[(int64_t)blockIdx.x * ldJ + j] = 0;
   }
   // adjoint of the last hidden layer outputs: ab = W_out^T seed
   for (int e = threadIdx.x; e < TP * C * n_last; e += blockDim.x) {
@@ -260,7 +301,23 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
     // Jacobian segments of W_l and b_l
     const int64_t wo = net.woff[l], bo = net.boff[l];
     const int nel = n_out * n_in;
-    if ((int)blockDim.x % n_in == 0) {
+    if constexpr (MODE == kVjp) {
+      for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int o = e / n_in, i = e - o * n_in;
+        T acc = 0;
+        for (int p = 0; p < nvalid; ++p) {
+          const T* zbp = s.zb + (int64_t)p * C * nm;
+          const T* hbp = s.hb + (int64_t)p * C * nm;
+          for (int c = 0; c < C; ++c) acc += zbp[c * nm + o] * hbp[c * nm + i];
+        }
+        put(wo + e, acc);
+      }
+      for (int o = threadIdx.x; o < n_out; o += blockDim.x) {
+        T acc = 0;
+        for (int p = 0; p < nvalid; ++p) acc += s.zb[(int64_t)p * C * nm + o];
+        put(bo + o, acc);
+      }
+    } else if ((int)blockDim.x % n_in == 0) {
       const int i = threadIdx.x % n_in, ostep = blockDim.x / n_in, o0 = threadIdx.x / n_in;
       for (int p = 0; p < nvalid; ++p) {
         T hreg[kMaxChan];
@@ -289,9 +346,11 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
         }
       }
     }
-    for (int p = 0; p < nvalid; ++p) {
-      T* Jrow = J + (row0 + p) * ldJ + bo;
-      for (int o = threadIdx.x; o < n_out; o += blockDim.x) Jrow[o] = s.zb[(int64_t)p * C * nm + o];
+    if constexpr (MODE == kJacobian) {
+      for (int p = 0; p < nvalid; ++p) {
+        T* Jrow = J + (row0 + p) * ldJ + bo;
+        for (int o = threadIdx.x; o < n_out; o += blockDim.x) Jrow[o] = s.zb[(int64_t)p * C * nm + o];
+      }
     }
     if (l == 0) break;
     // abar of the layer inputs: ab = W_l^T zbar
@@ -306,6 +365,142 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
       s.ab[pc * nm + i] = acc;
     }
   }
+  __syncthreads();
+  }  // tile loop
+  if constexpr (MODE == kVjp) {
+    __shared__ double red_t[4];
+    const double t = block_sum(tsq_acc, red_t);
+    if (threadIdx.x == 0 && tsq_out != nullptr) tsq_out[blockIdx.x] = t;
+  }
+}
+
+// Forward-mode product with the parameter Jacobian: out[r * ldo + j * cs] = (J_w u_j)[r] for the
+// direction u_j = U + j * ldU (j = blockIdx.y). Every channel of the forward Laplacian sweep carries a
+// tangent: for z = W h + b, zdot = W hdot + Wdot h (+ bdot on the value channel), and the tanh
+// channel rules are differentiated once more (s1' = -2 a a', s2' = -2 (a' s1 + a s1')). The
+// residual's tangent is read from the output channels as the residual itself is (eq. energy_poisson,
+// eq. heat_energy) and scaled by sqrt(w).
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void jvp_kernel(NetDesc net, const T* __restrict__ theta, const T* __restrict__ U,
+                                                  int64_t ldU, int64_t N, const T* __restrict__ X,
+                                                  const T* __restrict__ w, const int8_t* __restrict__ kind,
+                                                  TO* __restrict__ out, int64_t ldo, int64_t cs, int TP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
+  const int64_t row0 = (int64_t)blockIdx.x * TP;
+  const T* dth = U + (int64_t)blockIdx.y * ldU;
+  size_t ws = 0;
+  for (int l = 0; l < L; ++l) {
+    size_t q = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
+    ws = q > ws ? q : ws;
+  }
+  const size_t buf = (size_t)TP * C * nm;
+  T* Ws = smem;
+  T* Wd = Ws + ws;
+  T* hb = Wd + ws;     // [p][c][nm] channels entering the layer
+  T* hd = hb + buf;    // their tangents
+  T* zb = hd + buf;    // pre-activation channels
+  T* zd = zb + buf;    // their tangents
+  T* ud = zd + buf;    // output-channel tangents [p][kMaxChan]
+
+  input_channels(net, X, row0, N, TP, hb);
+  for (size_t e = threadIdx.x; e < buf; e += blockDim.x) hd[e] = 0;
+  for (int l = 0; l < L - 1; ++l) {
+    const int n_in = net.widths[l], n_out = net.widths[l + 1];
+    __syncthreads();
+    load_weights(net, theta, l, Ws);
+    load_weights(net, dth, l, Wd);
+    __syncthreads();
+    const T* b = theta + net.boff[l];
+    const T* bd = dth + net.boff[l];
+    for (int e = threadIdx.x; e < TP * C * n_out; e += blockDim.x) {
+      const int o = e % n_out, pc = e / n_out;
+      const T* wr = Ws + o * (n_in + 1);
+      const T* wdr = Wd + o * (n_in + 1);
+      const T* h = hb + pc * nm;
+      const T* hdt = hd + pc * nm;
+      T acc = 0, dacc = 0;
+      for (int i = 0; i < n_in; ++i) {
+        acc += wr[i] * h[i];
+        dacc += wr[i] * hdt[i] + wdr[i] * h[i];
+      }
+      if (pc % C == 0) {
+        acc += b[o];
+        dacc += bd[o];
+      }
+      zb[pc * nm + o] = acc;
+      zd[pc * nm + o] = dacc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TP * n_out; e += blockDim.x) {
+      const int p = e / n_out, o = e - p * n_out;
+      const T* z = zb + (int64_t)p * C * nm;
+      const T* zt = zd + (int64_t)p * C * nm;
+      T* h = hb + (int64_t)p * C * nm;
+      T* ht = hd + (int64_t)p * C * nm;
+      const T a = tanh(z[o]);
+      const T s1 = T(1) - a * a, s2 = T(-2) * a * s1;
+      const T ad = s1 * zt[o];
+      const T s1d = T(-2) * a * ad;
+      const T s2d = T(-2) * (ad * s1 + a * s1d);
+      h[o] = a;
+      ht[o] = ad;
+      T gsq = 0, gsqd = 0;
+      for (int k = 1; k <= nS; ++k) {
+        const T gz = z[k * nm + o], gzd = zt[k * nm + o];
+        gsq += gz * gz;
+        gsqd += T(2) * gz * gzd;
+        h[k * nm + o] = s1 * gz;
+        ht[k * nm + o] = s1d * gz + s1 * gzd;
+      }
+      const T lz = z[(nS + 1) * nm + o], lzd = zt[(nS + 1) * nm + o];
+      h[(nS + 1) * nm + o] = s1 * lz + s2 * gsq;
+      ht[(nS + 1) * nm + o] = s1d * lz + s1 * lzd + s2d * gsq + s2 * gsqd;
+      if (net.has_t) {
+        const T tz = z[(nS + 2) * nm + o], tzd = zt[(nS + 2) * nm + o];
+        h[(nS + 2) * nm + o] = s1 * tz;
+        ht[(nS + 2) * nm + o] = s1d * tz + s1 * tzd;
+      }
+    }
+  }
+  // output layer (linear): udot_c = w_out . hdot_c + wdot_out . h_c (+ bdot on the value channel)
+  const int n_last = net.widths[L - 1];
+  const T* Wout = theta + net.woff[L - 1];
+  const T* Wdout = dth + net.woff[L - 1];
+  const T bdout = dth[net.boff[L - 1]];
+  __syncthreads();
+  for (int pc = threadIdx.x; pc < TP * C; pc += blockDim.x) {
+    const T* h = hb + pc * nm;
+    const T* ht = hd + pc * nm;
+    T dacc = 0;
+    for (int i = 0; i < n_last; ++i) dacc += Wout[i] * ht[i] + Wdout[i] * h[i];
+    const int p = pc / C, c = pc % C;
+    ud[p * kMaxChan + c] = dacc + (c == 0 ? bdout : T(0));
+  }
+  __syncthreads();
+  if (threadIdx.x < TP) {
+    const int p = threadIdx.x;
+    const int64_t row = row0 + p;
+    if (row < N) {
+      const T* u = ud + p * kMaxChan;
+      T rd;
+      if (kind[row] == NGD_ROW_INTERIOR)
+        rd = net.pde == NGD_PDE_POISSON ? u[nS + 1] : u[nS + 2] - u[nS + 1];
+      else
+        rd = u[0];
+      out[row * ldo + (int64_t)blockIdx.y * cs] = (TO)(sqrt(w[row]) * rd);
+    }
+  }
+}
+
+__host__ inline size_t jvp_lds_elems(const NetDesc& net, int TP) {
+  size_t ws = 0;
+  for (int l = 0; l < net.n_layers; ++l) {
+    size_t s = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
+    ws = s > ws ? s : ws;
+  }
+  return 2 * ws + 4 * (size_t)TP * net.C * net.max_width + (size_t)TP * kMaxChan;
 }
 
 // sum of n_per partials for each of n_sets sets, scaled: out[s] = scale * sum_i partial[s*n_per + i]
@@ -373,18 +568,85 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
   dim3 grid((unsigned)((N + tp - 1) / tp), (unsigned)n_theta);
   if (n_blocks_out) *n_blocks_out = (int)grid.x;
   if (dtype == NGD_F64) {
-    auto k = residual_jacobian_kernel<double>;
+    auto k = residual_jacobian_kernel<double, kJacobian>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const double*)theta, theta_stride, N, (const double*)X,
                        (const double*)w, (const double*)f, (const double*)g, kind, (double*)r_w, (double*)J, ldJ,
-                       loss_partial, tp);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr);
   } else {
-    auto k = residual_jacobian_kernel<float>;
+    auto k = residual_jacobian_kernel<float, kJacobian>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const float*)theta, theta_stride, N, (const float*)X,
                        (const float*)w, (const float*)f, (const float*)g, kind, (float*)r_w, (float*)J, ldJ,
-                       loss_partial, tp);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr);
   }
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+int vjp_grid(const NetDesc& net, int dtype, int64_t N, int max_wg) {
+  size_t bytes = 0;
+  const int tp = choose_tp(net, dtype == NGD_F64 ? 8 : 4, &bytes);
+  const int64_t tiles = (N + tp - 1) / tp;
+  return (int)(tiles < max_wg ? tiles : max_wg);
+}
+
+ngd_status launch_vjp(const NetDesc& net, int dtype, const void* theta, int64_t N, const void* X, const void* w,
+                      const void* f, const void* g, const int8_t* kind, const double* wv, int64_t wv_stride,
+                      void* partial, int64_t ld, double* tsq, int nwg, hipStream_t s) {
+  size_t elem = dtype == NGD_F64 ? 8 : 4;
+  size_t bytes = 0;
+  int tp = choose_tp(net, elem, &bytes);
+  const int64_t tiles = (N + tp - 1) / tp;
+  if (nwg < 1 || nwg > tiles) {
+    set_error("vjp: workgroup count out of range");
+    return NGD_ERR_INVALID;
+  }
+  if (dtype == NGD_F64) {
+    auto k = residual_jacobian_kernel<double, kVjp>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const double*)theta, (int64_t)0, N, (const double*)X,
+                       (const double*)w, (const double*)f, (const double*)g, kind, nullptr, (double*)partial, ld,
+                       nullptr, tp, wv, wv_stride, tsq);
+  } else {
+    auto k = residual_jacobian_kernel<float, kVjp>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const float*)theta, (int64_t)0, N, (const float*)X,
+                       (const float*)w, (const float*)f, (const float*)g, kind, nullptr, (float*)partial, ld, nullptr,
+                       tp, wv, wv_stride, tsq);
+  }
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_jvp(const NetDesc& net, int dtype, const void* theta, const void* U, int64_t ldU, int64_t k,
+                      int64_t N, const void* X, const void* w, const int8_t* kind, int out_type, void* out,
+                      int64_t ldo, int64_t cs, hipStream_t s) {
+  if (k <= 0 || N <= 0) return NGD_OK;
+  const size_t elem = dtype == NGD_F64 ? 8 : 4;
+  int tp = 16;
+  while (tp > 1 && jvp_lds_elems(net, tp) * elem > 64 * 1024) tp >>= 1;
+  const size_t bytes = jvp_lds_elems(net, tp) * elem;
+  if (bytes > 150 * 1024) {
+    set_error("network too wide for the JVP kernel's LDS budget");
+    return NGD_ERR_INVALID;
+  }
+  dim3 grid((unsigned)((N + tp - 1) / tp), (unsigned)k);
+#define NGD_JVP(T, TO)                                                                                          \
+  do {                                                                                                         \
+    auto kf = jvp_kernel<T, TO>;                                                                               \
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)); \
+    hipLaunchKernelGGL(kf, grid, dim3(256), bytes, s, net, (const T*)theta, (const T*)U, ldU, N, (const T*)X,    \
+                       (const T*)w, kind, (TO*)out, ldo, cs, tp);                                              \
+  } while (0)
+  if (dtype == NGD_F64 && out_type == NGD_F64) NGD_JVP(double, double);
+  else if (dtype == NGD_F32 && out_type == NGD_F32) NGD_JVP(float, float);
+  else if (dtype == NGD_F32 && out_type == NGD_F64) NGD_JVP(float, double);
+  else {
+    set_error("jvp: unsupported output type");
+    return NGD_ERR_INVALID;
+  }
+#undef NGD_JVP
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -17,7 +17,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .api import Problem
+from .api import Problem, Recompute
 
 EPS = {"f64": 2.0 ** -52, "f32": 2.0 ** -23}
 
@@ -37,7 +37,7 @@ class StepReport:
 
 class NGD:
     def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
-                 maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None):
+                 maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None):
         self.gp = Problem(data, dtype=dtype, max_ell=ell or getattr(data, "ell", 1))
         gp = self.gp
         self.solver = solver
@@ -52,7 +52,10 @@ class NGD:
         self.seed = seed
         self.eps = EPS[gp.dtype_name]
         self.theta = gp.theta(theta0)
-        self.J = gp.new_jacobian()
+        # recompute mode (J_w never stored; products by the tangent / adjoint kernels): asked for, or
+        # the problem's own setting
+        self.recompute = bool(getattr(data, "recompute", False) if recompute is None else recompute)
+        self.J = None if self.recompute else gp.new_jacobian()
         if power_v0 is None:
             power_v0 = np.random.default_rng(np.random.SeedSequence([seed, 99])).standard_normal(gp.P)
         self.v0 = torch.as_tensor(power_v0, dtype=torch.float64, device=gp.device)
@@ -61,6 +64,8 @@ class NGD:
     def step(self) -> StepReport:
         gp = self.gp
         r, J, grad, loss = gp.residual_jacobian(self.theta, self.J)
+        if self.recompute:
+            J = Recompute(self.theta)
         L0 = float(loss.item())
         pc = None
         rank = -1

@@ -47,6 +47,7 @@ class Problem:
     lam: Optional[float] = None   # fixed damping, or None for the adaptive rule
     sketch_dtype: str = "f64"     # "f64" | "f32" | "bf16"
     seed: int = 0
+    recompute: bool = False       # products with J_w recomputed from theta instead of a stored J_w
 
     @property
     def n_rows(self) -> int:
@@ -200,7 +201,8 @@ def config(name: str, seed: int = 0) -> Problem:
     c1: 2D Poisson, 2-32-32-1, 30x30 grid + 120 boundary points, FP64, lambda = 1e-6, ell = 100.
     c2: 2D Poisson, 2-64-64-64-1, 4,096 + 512 random points, FP32, ell = 400, adaptive damping.
     c3: 5D Poisson (u* = sum sin), 5-128-128-128-1, 16,384 + 2,048 points, BF16 sketch, ell = 800.
-    c4: 2+1D heat, 3-64-64-64-64-1, 8,192 + 1,024 lateral + 1,024 initial points, FP32, ell = 400.
+    c4: 2+1D heat, 3-64-64-64-64-1, 8,192 + 1,024 lateral + 1,024 initial points, FP32, ell = 400,
+        J_w recomputed (never stored).
     """
     if name == "c1":
         return poisson2d_grid(seed=seed)
@@ -210,7 +212,7 @@ def config(name: str, seed: int = 0) -> Problem:
         return poisson_random(d=5, widths=(5, 128, 128, 128, 1), n_interior=16384, n_boundary=2048,
                               seed=seed, ell=800, sketch_dtype="bf16", solution="sinsum")
     if name == "c4":
-        return heat2d(seed=seed)
+        return dataclasses.replace(heat2d(seed=seed), recompute=True)
     raise KeyError(name)
 
 
