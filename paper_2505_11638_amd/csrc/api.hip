@@ -354,8 +354,17 @@ ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, v
                                     h->loss_part, 0, 1, s, nullptr);
   }));
   if (loss != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, 1, 0.5, loss, s));
-  if (grad != nullptr && J_w != nullptr)
-    NGD_TRY(launch_gradient(h->dtype, J_w, ldJ, h->N, h->P, r_w, h->grad_work, grad, s));
+  if (grad != nullptr && J_w != nullptr) {
+    // one pass over J_w when its rows suit the one-pass kernel, else the column-sum kernel
+    const ngd_operator gop{theta, J_w, ldJ};
+    if (ldJ <= h->ldP && ldJ % (h->dtype == NGD_F64 ? 2 : 4) == 0 && aligned16(J_w) &&
+        gram_rows_supported(h->dtype, ldJ) && check_op(h, &gop) == NGD_OK) {
+      NGD_TRY(launch_grad_rows(h->dtype, J_w, ldJ, h->N, r_w, h->partial, h->nwg, s));
+      NGD_TRY(launch_gram_reduce(h->dtype, h->partial, h->nwg, ldJ, h->P, nullptr, 0.0, grad, s));
+    } else {
+      NGD_TRY(launch_gradient(h->dtype, J_w, ldJ, h->N, h->P, r_w, h->grad_work, grad, s));
+    }
+  }
   if (grad != nullptr && J_w == nullptr) {
     // recompute mode: grad = J_w^T r_w by the adjoint kernel
     NGD_TRY(launch_cast(h->dtype, r_w, NGD_F64, h->nvec[1], h->N, s));

@@ -93,13 +93,13 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ a, 
 
 // Last-block detection for deterministic two-stage reductions inside one launch: every block
 // publishes its partial, then the block that arrives last sees all partials.
-__device__ __forceinline__ bool arrive_last(unsigned* counter) {
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
   __shared__ int last;
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
+    last = (prev == nblocks - 1);
   }
   __syncthreads();
   if (last) {
@@ -135,6 +135,8 @@ int gradient_chunks(int64_t N);
 int gram_rows_grid(int dtype, int64_t N, int64_t P);
 ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* v,
                             void* partial, double* tsq, int nwg, hipStream_t s);
+ngd_status launch_grad_rows(int dtype, const void* J, int64_t ldJ, int64_t N, const void* r, void* partial, int nwg,
+                            hipStream_t s);
 ngd_status launch_gram_reduce(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* v,
                               double lambda, double* y, hipStream_t s);
 
@@ -198,6 +200,49 @@ ngd_status pcg_launch_direction(int dtype, const double* z, const double* p_prev
                                 double* part, PcgState* st, hipStream_t s);
 ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
+
+// Batched PCG (several independent problems per launch): one entry per problem, in device memory.
+// The work items of a launch are numbered problem by problem; item0_* is the first item of this
+// problem in each kind of launch (row workgroups, update column blocks of 32, preconditioner rows,
+// element blocks of 256).
+struct PcgBatchItem {
+  const void* J;
+  int64_t ldJ, N, P;
+  const double* g;
+  double *x, *r, *z, *p0, *p1, *s, *part;
+  void* partial;
+  double* tsq;
+  PcgState* st;
+  const void* U;  // NULL: plain CG
+  int64_t ldU;
+  const double* lam;
+  double mu;
+  double rtol;
+  int ell, nwg, plain;
+  int item0_rows, item0_upd, item0_dots, item0_elem, item0_apply;
+};
+ngd_status pcg_batch_launch_init(int dtype, const PcgBatchItem* items, int n, int total_elem, hipStream_t s);
+ngd_status pcg_batch_launch_precond(int dtype, const PcgBatchItem* items, int n, int total_dots, int total_apply,
+                                    int max_ell, hipStream_t s);
+ngd_status pcg_batch_launch_rows(int dtype, const PcgBatchItem* items, int n, int total_rows, int64_t max_ldJ,
+                                 hipStream_t s);
+ngd_status pcg_batch_launch_update(int dtype, const PcgBatchItem* items, int n, int total_upd, hipStream_t s);
+// make the kernels of a batched launch ready for stream capture (function attributes set up front)
+ngd_status pcg_batch_prepare(int dtype, int64_t max_ldJ, int max_ell);
+
+// residual.hip: several problems' residuals, Jacobians and loss partials in one launch
+struct BatchResidualItem {
+  NetDesc net;
+  const void *theta, *X, *w, *f, *g;
+  const int8_t* kind;
+  void *r_w, *J;
+  int64_t ldJ, N, first_tile;
+  int TP;
+  double* loss_part;
+};
+ngd_status launch_batch_residual_jacobian(int dtype, const BatchResidualItem* items, int n, int64_t total_tiles,
+                                          size_t lds_bytes, hipStream_t s);
+size_t residual_lds_bytes(const NetDesc& net, int dtype, int* tp);
 
 // chol.hip: blocked shifted Cholesky of the core and the right triangular solve X <- X L^{-T}
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,

@@ -73,9 +73,12 @@ __device__ __forceinline__ void axpy_vec<double>(double t, const vd2& a, vd2& y)
 // ones are reduced and accumulated, so that about 2R rows per CU are in flight against HBM.
 // `stage` fills vs (and does any other per-launch set-up), followed by a workgroup barrier; for
 // short rows it runs after the first rows' loads have been issued, so its own reads overlap them.
+// With `wts` non-null the row coefficients are given (t_r = wts[r], no dot products and no
+// reductions): acc = sum_r wts[r] J_r, the one-pass form of the gradient J_w^T r_w.
 template <typename T, int NK, int R, typename Stage>
 __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, int64_t r0, int64_t r1,
-                                          const T* vs, RowRegs<T, NK>& acc, double& tsq, Stage&& stage) {
+                                          const T* vs, RowRegs<T, NK>& acc, double& tsq, Stage&& stage,
+                                          const T* __restrict__ wts = nullptr) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
   __shared__ double red[2][R][16];
@@ -122,6 +125,19 @@ __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, 
 #pragma unroll
         for (int k = 0; k < NK; ++k) nxt[q][k] = V{};
     }
+    if (wts != nullptr) {  // given coefficients: accumulate and move on
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const T tt = base + q < nrows ? wts[r0 + base + q] : T(0);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) axpy_vec<T>(tt, cur[q][k], acc.c[k]);
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) cur[q][k] = nxt[q][k];
+      continue;
+    }
     T dot[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -155,10 +171,11 @@ __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, 
 }
 
 template <typename T, int NK>
-__device__ __forceinline__ void store_partial(T* __restrict__ partial, int64_t ldJ, const RowRegs<T, NK>& acc) {
+__device__ __forceinline__ void store_partial(T* __restrict__ partial, int64_t ldJ, const RowRegs<T, NK>& acc,
+                                              int bid) {
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
-  V* out = reinterpret_cast<V*>(partial + (int64_t)blockIdx.x * ldJ);
+  V* out = reinterpret_cast<V*>(partial + (int64_t)bid * ldJ);
   const int64_t nchunk = ldJ / VN;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
@@ -167,8 +184,9 @@ __device__ __forceinline__ void store_partial(T* __restrict__ partial, int64_t l
   }
 }
 
-__device__ __forceinline__ void row_range(int64_t N, int64_t* r0, int64_t* r1) {
-  const int64_t per = N / gridDim.x, extra = N % gridDim.x, b = blockIdx.x;
+// rows of workgroup bid of nb: a contiguous, balanced share of [0, N)
+__device__ __forceinline__ void row_range(int64_t N, int64_t* r0, int64_t* r1, int bid, int nb) {
+  const int64_t per = N / nb, extra = N % nb, b = bid;
   *r0 = b * per + (b < extra ? b : extra);
   *r1 = *r0 + per + (b < extra ? 1 : 0);
 }
@@ -181,7 +199,7 @@ __global__ __launch_bounds__(B) void gram_rows_kernel(const T* __restrict__ J, i
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* vs = reinterpret_cast<T*>(smem_raw);
   int64_t r0, r1;
-  row_range(N, &r0, &r1);
+  row_range(N, &r0, &r1, blockIdx.x, gridDim.x);
   RowRegs<T, NK> acc;
   double tsq = 0;
   rows_pass<T, NK, R>(J, ldJ, r0, r1, vs, acc, tsq, [&] {
@@ -193,8 +211,20 @@ __global__ __launch_bounds__(B) void gram_rows_kernel(const T* __restrict__ J, i
       for (int64_t j = threadIdx.x; j < ldJ; j += B) vs[j] = j < P ? (T)v[j] : T(0);
     }
   });
-  store_partial<T, NK>(partial, ldJ, acc);
+  store_partial<T, NK>(partial, ldJ, acc, blockIdx.x);
   if (threadIdx.x == 0 && tsq_out) tsq_out[blockIdx.x] = tsq;
+}
+
+// partials of the gradient J^T r (r in the Jacobian's dtype): rows weighted by r, no reductions
+template <typename T, int NK, int R, int B>
+__global__ __launch_bounds__(B) void grad_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N,
+                                                      const T* __restrict__ r, T* __restrict__ partial) {
+  int64_t r0, r1;
+  row_range(N, &r0, &r1, blockIdx.x, gridDim.x);
+  RowRegs<T, NK> acc;
+  double tsq = 0;
+  rows_pass<T, NK, R>(J, ldJ, r0, r1, nullptr, acc, tsq, [] {}, r);
+  store_partial<T, NK>(partial, ldJ, acc, blockIdx.x);
 }
 
 // Column sums of the workgroup partials: a block covers kRedCols columns with kRedGroups threads
@@ -203,9 +233,9 @@ constexpr int kRedCols = 32, kRedGroups = 8;
 
 template <typename T>
 __device__ __forceinline__ double sum_partials(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
-                                               double (*buf)[kRedCols], int64_t* j_out) {
+                                               double (*buf)[kRedCols], int64_t* j_out, int bid) {
   const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
-  const int64_t j = (int64_t)blockIdx.x * kRedCols + c;
+  const int64_t j = (int64_t)bid * kRedCols + c;
   double acc = 0;
   if (j < P) {
     // eight loads in flight per thread; the order of the additions is fixed
@@ -234,7 +264,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
                                                           double* __restrict__ y) {
   __shared__ double buf[kRedGroups][kRedCols];
   int64_t j;
-  const double acc = sum_partials(partial, nwg, ld, P, buf, &j);
+  const double acc = sum_partials(partial, nwg, ld, P, buf, &j, blockIdx.x);
   if (threadIdx.x < kRedCols && j < P) y[j] = lambda != 0.0 ? acc + lambda * v[j] : acc;
 }
 
@@ -244,7 +274,7 @@ __global__ __launch_bounds__(256) void partials_to_row_kernel(const T* __restric
                                                               int64_t P, T* __restrict__ out) {
   __shared__ double buf[kRedGroups][kRedCols];
   int64_t j;
-  const double acc = sum_partials(partial, nwg, ld, P, buf, &j);
+  const double acc = sum_partials(partial, nwg, ld, P, buf, &j, blockIdx.x);
   if (threadIdx.x < kRedCols && j < P) out[j] = (T)acc;
 }
 
@@ -266,7 +296,7 @@ __global__ __launch_bounds__(256) void pcg_direction_kernel(const double* __rest
   }
   pp = block_sum(pp, red);
   if (threadIdx.x == 0) part[blockIdx.x] = pp;
-  if (!arrive_last(&st->counter)) return;
+  if (!arrive_last(&st->counter, gridDim.x)) return;
   const double tot = block_sum_array(part, (int)gridDim.x, red);
   if (threadIdx.x == 0) st->pp = tot;
 }
@@ -274,16 +304,16 @@ __global__ __launch_bounds__(256) void pcg_direction_kernel(const double* __rest
 // ---------------- fused PCG iteration ----------------
 // (A) search direction p = z + beta p_prev staged on the fly, then the one-pass Gramian product
 template <typename T, int NK, int R, int B>
-__global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
-                                                        const double* __restrict__ z, const double* __restrict__ p_prev,
-                                                        double* __restrict__ p_cur, PcgState* __restrict__ st,
-                                                        T* __restrict__ partial, double* __restrict__ tsq_out) {
+__device__ __forceinline__ void pcg_rows_body(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+                                              const double* __restrict__ z, const double* __restrict__ p_prev,
+                                              double* __restrict__ p_cur, PcgState* __restrict__ st,
+                                              T* __restrict__ partial, double* __restrict__ tsq_out, int bid, int nb) {
   if (st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* vs = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[16];
   int64_t r0, r1;
-  row_range(N, &r0, &r1);
+  row_range(N, &r0, &r1, bid, nb);
   RowRegs<T, NK> acc;
   double tsq = 0;
   rows_pass<T, NK, R>(J, ldJ, r0, r1, vs, acc, tsq, [&] {
@@ -293,7 +323,7 @@ __global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, in
       double pj = j < P ? z[j] + beta * p_prev[j] : 0.0;
       vs[j] = (T)pj;
       pp += pj * pj;
-      if (blockIdx.x == 0 && j < P) p_cur[j] = pj;
+      if (bid == 0 && j < P) p_cur[j] = pj;
     };
     if constexpr (NK * R < 12) {
 #pragma unroll 4
@@ -302,19 +332,27 @@ __global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, in
       for (int64_t j = threadIdx.x; j < ldJ; j += B) one(j);
     }
     pp = block_sum(pp, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->pp = pp;
+    if (bid == 0 && threadIdx.x == 0) st->pp = pp;
   });
-  store_partial<T, NK>(partial, ldJ, acc);
-  if (threadIdx.x == 0) tsq_out[blockIdx.x] = tsq;
+  store_partial<T, NK>(partial, ldJ, acc, bid);
+  if (threadIdx.x == 0) tsq_out[bid] = tsq;
+}
+
+template <typename T, int NK, int R, int B>
+__global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+                                                     const double* __restrict__ z, const double* __restrict__ p_prev,
+                                                     double* __restrict__ p_cur, PcgState* __restrict__ st,
+                                                     T* __restrict__ partial, double* __restrict__ tsq_out) {
+  pcg_rows_body<T, NK, R, B>(J, ldJ, N, P, z, p_prev, p_cur, st, partial, tsq_out, blockIdx.x, gridDim.x);
 }
 
 // (B) q = sum partials + lambda p; alpha = rz / (p^T q); x += alpha p; r -= alpha q; convergence
 template <typename T>
-__global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
-                                                         const double* __restrict__ p, const double* __restrict__ tsq,
-                                                         double* __restrict__ x, double* __restrict__ r,
-                                                         double* __restrict__ rr_part, PcgState* __restrict__ st,
-                                                         int plain_cg) {
+__device__ __forceinline__ void pcg_update_body(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
+                                                const double* __restrict__ p, const double* __restrict__ tsq,
+                                                double* __restrict__ x, double* __restrict__ r,
+                                                double* __restrict__ rr_part, PcgState* __restrict__ st, int plain_cg,
+                                                int bid, int nb) {
   if (st->done) return;
   __shared__ double red[4];
   const double pGp = block_sum_array(tsq, nwg, red);
@@ -324,7 +362,7 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
   double rr = 0;
   __shared__ double buf[kRedGroups][kRedCols];
   int64_t j;
-  double q = sum_partials(partial, nwg, ld, P, buf, &j);
+  double q = sum_partials(partial, nwg, ld, P, buf, &j, bid);
   if (!bad && threadIdx.x < kRedCols && j < P) {
     q += st->lambda * p[j];
     const double xj = x[j] + alpha * p[j];
@@ -334,9 +372,9 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
     rr = rj * rj;
   }
   rr = block_sum(rr, red);
-  if (threadIdx.x == 0) rr_part[blockIdx.x] = rr;
-  if (!arrive_last(&st->counter)) return;
-  const double tot = block_sum_array(rr_part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) rr_part[bid] = rr;
+  if (!arrive_last(&st->counter, nb)) return;
+  const double tot = block_sum_array(rr_part, nb, red);
   if (threadIdx.x == 0) {
     if (bad) {
       st->breakdown = 1;
@@ -362,27 +400,43 @@ __global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ p
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_update_kernel(const T* __restrict__ partial, int nwg, int64_t ld, int64_t P,
+                                                         const double* __restrict__ p, const double* __restrict__ tsq,
+                                                         double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ rr_part, PcgState* __restrict__ st,
+                                                         int plain_cg) {
+  pcg_update_body<T>(partial, nwg, ld, P, p, tsq, x, r, rr_part, st, plain_cg, blockIdx.x, gridDim.x);
+}
+
 // (C) s_i = U_i . r for every preconditioner row (one workgroup per row)
+template <typename T>
+__device__ __forceinline__ void precond_dots_body(const T* __restrict__ U, int64_t ldU, int64_t P,
+                                                  const double* __restrict__ r, double* __restrict__ s,
+                                                  const PcgState* __restrict__ st, int bid) {
+  if (st != nullptr && st->done) return;
+  __shared__ double red[4];
+  const T* u = U + (int64_t)bid * ldU;
+  double acc = 0;
+  for (int64_t j = threadIdx.x; j < P; j += blockDim.x) acc += (double)u[j] * r[j];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) s[bid] = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void precond_dots_kernel(const T* __restrict__ U, int64_t ldU, int64_t P,
                                                            const double* __restrict__ r, double* __restrict__ s,
                                                            const PcgState* __restrict__ st) {
-  if (st != nullptr && st->done) return;
-  __shared__ double red[4];
-  const T* u = U + (int64_t)blockIdx.x * ldU;
-  double acc = 0;
-  for (int64_t j = threadIdx.x; j < P; j += blockDim.x) acc += (double)u[j] * r[j];
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) s[blockIdx.x] = acc;
+  precond_dots_body<T>(U, ldU, P, r, s, st, blockIdx.x);
 }
 
 // (D) z = c r + sum_i (1/(lam_i + mu) - c) s_i U_i (eq. nystrom_inverse); rz = r^T z; beta
 template <typename T>
-__global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict__ U, int64_t ldU, int64_t P, int ell,
-                                                            const double* __restrict__ lam, double mu,
-                                                            const double* __restrict__ s, const double* __restrict__ r,
-                                                            double* __restrict__ z, double* __restrict__ rz_part,
-                                                            PcgState* __restrict__ st) {
+__device__ __forceinline__ void precond_apply_body(const T* __restrict__ U, int64_t ldU, int64_t P, int ell,
+                                                   const double* __restrict__ lam, double mu,
+                                                   const double* __restrict__ s, const double* __restrict__ r,
+                                                   double* __restrict__ z, double* __restrict__ rz_part,
+                                                   PcgState* __restrict__ st, int bid, int nb) {
   if (st != nullptr && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* coef = reinterpret_cast<double*>(smem_raw);
@@ -390,7 +444,7 @@ __global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict_
   const double c = 1.0 / (lam[ell - 1] + mu);
   for (int i = threadIdx.x; i < ell; i += blockDim.x) coef[i] = (1.0 / (lam[i] + mu) - c) * s[i];
   __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)bid * blockDim.x + threadIdx.x;
   double rz = 0;
   if (j < P) {
     double acc = 0;
@@ -401,9 +455,9 @@ __global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict_
   }
   if (st == nullptr) return;
   rz = block_sum(rz, red);
-  if (threadIdx.x == 0) rz_part[blockIdx.x] = rz;
-  if (!arrive_last(&st->counter)) return;
-  const double tot = block_sum_array(rz_part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) rz_part[bid] = rz;
+  if (!arrive_last(&st->counter, nb)) return;
+  const double tot = block_sum_array(rz_part, nb, red);
   if (threadIdx.x == 0) {
     if (st->iters == 0 && st->beta == 0.0) {
       st->rz = tot;                       // initial z_0 = P^{-1} r_0
@@ -418,13 +472,22 @@ __global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict_
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict__ U, int64_t ldU, int64_t P, int ell,
+                                                            const double* __restrict__ lam, double mu,
+                                                            const double* __restrict__ s, const double* __restrict__ r,
+                                                            double* __restrict__ z, double* __restrict__ rz_part,
+                                                            PcgState* __restrict__ st) {
+  precond_apply_body<T>(U, ldU, P, ell, lam, mu, s, r, z, rz_part, st, blockIdx.x, gridDim.x);
+}
+
 // initial state: x = 0, r = g, p_prev = 0; ||g||^2 and the stopping threshold
-__global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict__ g, int64_t P, double* __restrict__ x,
-                                                       double* __restrict__ r, double* __restrict__ p_prev,
-                                                       double* __restrict__ part, PcgState* __restrict__ st,
-                                                       double rtol, int plain_cg) {
+__device__ __forceinline__ void pcg_init_body(const double* __restrict__ g, int64_t P, double* __restrict__ x,
+                                              double* __restrict__ r, double* __restrict__ p_prev,
+                                              double* __restrict__ part, PcgState* __restrict__ st, double rtol,
+                                              int plain_cg, int bid, int nb) {
   __shared__ double red[4];
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)bid * blockDim.x + threadIdx.x;
   double gg = 0;
   if (j < P) {
     const double gj = g[j];
@@ -434,9 +497,9 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
     gg = gj * gj;
   }
   gg = block_sum(gg, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = gg;
-  if (!arrive_last(&st->counter)) return;
-  const double tot = block_sum_array(part, (int)gridDim.x, red);
+  if (threadIdx.x == 0) part[bid] = gg;
+  if (!arrive_last(&st->counter, nb)) return;
+  const double tot = block_sum_array(part, nb, red);
   if (threadIdx.x == 0) {
     st->bnorm2 = tot;
     st->rr = tot;
@@ -457,6 +520,13 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict_
   }
 }
 
+__global__ __launch_bounds__(256) void pcg_init_kernel(const double* __restrict__ g, int64_t P, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ p_prev,
+                                                       double* __restrict__ part, PcgState* __restrict__ st,
+                                                       double rtol, int plain_cg) {
+  pcg_init_body(g, P, x, r, p_prev, part, st, rtol, plain_cg, blockIdx.x, gridDim.x);
+}
+
 // small FP64 vector helpers
 __global__ void dot_stage_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
                                  double* __restrict__ part, double* __restrict__ out, unsigned* counter) {
@@ -466,7 +536,7 @@ __global__ void dot_stage_kernel(const double* __restrict__ a, const double* __r
     acc += a[j] * b[j];
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
-  if (!arrive_last(counter)) return;
+  if (!arrive_last(counter, gridDim.x)) return;
   const double tot = block_sum_array(part, (int)gridDim.x, red);
   if (threadIdx.x == 0) *out = tot;
 }
@@ -475,6 +545,59 @@ __global__ void scale_by_rsqrt_kernel(const double* __restrict__ w, const double
                                       double* __restrict__ v) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) v[j] = w[j] / sqrt(*ww);
+}
+
+// ---------------- batched PCG: several problems per launch ----------------
+// Item `it` of a launch belongs to the last problem whose first item of that kind is <= it (problems
+// with no items of a kind share their successor's first item and are never chosen).
+template <typename Key>
+__device__ __forceinline__ int find_problem(int n, int it, Key first) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(mid) <= it) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void pcg_batch_init_kernel(const PcgBatchItem* __restrict__ items, int n) {
+  const int it = blockIdx.x;
+  const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_elem; })];
+  pcg_init_body(b.g, b.P, b.x, b.r, b.p0, b.part, b.st, b.rtol, b.plain, it - b.item0_elem, (int)((b.P + 255) / 256));
+}
+
+template <typename T, int NK, int R, int B>
+__global__ __launch_bounds__(B) void pcg_batch_rows_kernel(const PcgBatchItem* __restrict__ items, int n) {
+  const int it = blockIdx.x;
+  const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_rows; })];
+  // iteration parity: the direction of the previous iteration and the slot for this one
+  const bool odd = (b.st->iters & 1) != 0;
+  pcg_rows_body<T, NK, R, B>((const T*)b.J, b.ldJ, b.N, b.P, b.plain ? b.r : b.z, odd ? b.p1 : b.p0,
+                             odd ? b.p0 : b.p1, b.st, (T*)b.partial, b.tsq, it - b.item0_rows, b.nwg);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_batch_update_kernel(const PcgBatchItem* __restrict__ items, int n) {
+  const int it = blockIdx.x;
+  const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_upd; })];
+  const bool odd = (b.st->iters & 1) != 0;
+  pcg_update_body<T>((const T*)b.partial, b.nwg, b.ldJ, b.P, odd ? b.p0 : b.p1, b.tsq, b.x, b.r, b.part, b.st,
+                     b.plain, it - b.item0_upd, (int)((b.P + kRedCols - 1) / kRedCols));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_batch_dots_kernel(const PcgBatchItem* __restrict__ items, int n) {
+  const int it = blockIdx.x;
+  const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_dots; })];
+  precond_dots_body<T>((const T*)b.U, b.ldU, b.P, b.r, b.s, b.st, it - b.item0_dots);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_batch_apply_kernel(const PcgBatchItem* __restrict__ items, int n) {
+  const int it = blockIdx.x;
+  const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_apply; })];
+  precond_apply_body<T>((const T*)b.U, b.ldU, b.P, b.ell, b.lam, b.mu, b.s, b.r, b.z, b.part, b.st,
+                        it - b.item0_apply, (int)((b.P + 255) / 256));
 }
 
 }  // namespace
@@ -549,6 +672,30 @@ static ngd_status gram_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, con
 #undef NGD_CALL
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
+}
+
+template <typename T>
+static ngd_status grad_rows_t(const T* J, int64_t ldJ, int64_t N, const T* r, T* partial, int nwg, hipStream_t s) {
+  RowsCfg c;
+  if (!rows_cfg(sizeof(T) == 8 ? NGD_F64 : NGD_F32, ldJ, &c)) {
+    set_error("Jacobian row too long for the one-pass gradient");
+    return NGD_ERR_INVALID;
+  }
+#define NGD_CALL(ID, B, NK, R)                                                            \
+  case ID: {                                                                              \
+    hipLaunchKernelGGL((grad_rows_kernel<T, NK, R, B>), dim3(nwg), dim3(B), 0, s, J, ldJ, N, r, partial); \
+    break;                                                                                \
+  }
+  NGD_CFG_DISPATCH(c.id, NGD_CALL)
+#undef NGD_CALL
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_grad_rows(int dtype, const void* J, int64_t ldJ, int64_t N, const void* r, void* partial, int nwg,
+                            hipStream_t s) {
+  if (dtype == NGD_F64) return grad_rows_t<double>((const double*)J, ldJ, N, (const double*)r, (double*)partial, nwg, s);
+  return grad_rows_t<float>((const float*)J, ldJ, N, (const float*)r, (float*)partial, nwg, s);
 }
 
 ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* v,
@@ -688,6 +835,91 @@ ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(precond_apply_kernel<float>, grid, dim3(256), lds, s, (const float*)U, ldU, P, ell, lam, mu,
                        sbuf, r, z, rz_part, st);
+  }
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+// ---------------- batched PCG launchers ----------------
+
+ngd_status pcg_batch_launch_init(int dtype, const PcgBatchItem* items, int n, int total_elem, hipStream_t s) {
+  (void)dtype;
+  if (total_elem <= 0) return NGD_OK;
+  hipLaunchKernelGGL(pcg_batch_init_kernel, dim3((unsigned)total_elem), dim3(256), 0, s, items, n);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status pcg_batch_prepare(int dtype, int64_t max_ldJ, int max_ell) {
+  RowsCfg c;
+  if (!rows_cfg(dtype, max_ldJ, &c)) {
+    set_error("Jacobian row too long for the one-pass matvec");
+    return NGD_ERR_INVALID;
+  }
+  const int lds = (int)(max_ldJ * (dtype == NGD_F64 ? 8 : 4));
+#define NGD_CALL(ID, B, NK, R)                                                                                   \
+  case ID: {                                                                                                     \
+    if (dtype == NGD_F64)                                                                                        \
+      NGD_HIP_TRY(hipFuncSetAttribute((const void*)pcg_batch_rows_kernel<double, NK, R, B>,                     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds));                        \
+    else                                                                                                         \
+      NGD_HIP_TRY(hipFuncSetAttribute((const void*)pcg_batch_rows_kernel<float, NK, R, B>,                      \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds));                        \
+    break;                                                                                                       \
+  }
+  NGD_CFG_DISPATCH(c.id, NGD_CALL)
+#undef NGD_CALL
+  const int plds = (int)(max_ell * sizeof(double));
+  NGD_HIP_TRY(hipFuncSetAttribute((const void*)pcg_batch_apply_kernel<double>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, plds));
+  NGD_HIP_TRY(hipFuncSetAttribute((const void*)pcg_batch_apply_kernel<float>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, plds));
+  return NGD_OK;
+}
+
+ngd_status pcg_batch_launch_rows(int dtype, const PcgBatchItem* items, int n, int total_rows, int64_t max_ldJ,
+                                 hipStream_t s) {
+  RowsCfg c;
+  if (!rows_cfg(dtype, max_ldJ, &c)) {
+    set_error("Jacobian row too long for the one-pass matvec");
+    return NGD_ERR_INVALID;
+  }
+  const size_t lds = (size_t)max_ldJ * (dtype == NGD_F64 ? 8 : 4);
+#define NGD_CALL(ID, B, NK, R)                                                                            \
+  case ID: {                                                                                              \
+    if (dtype == NGD_F64)                                                                                 \
+      hipLaunchKernelGGL((pcg_batch_rows_kernel<double, NK, R, B>), dim3((unsigned)total_rows), dim3(B), lds, s, \
+                         items, n);                                                                      \
+    else                                                                                                  \
+      hipLaunchKernelGGL((pcg_batch_rows_kernel<float, NK, R, B>), dim3((unsigned)total_rows), dim3(B), lds, s, \
+                         items, n);                                                                      \
+    break;                                                                                                \
+  }
+  NGD_CFG_DISPATCH(c.id, NGD_CALL)
+#undef NGD_CALL
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status pcg_batch_launch_update(int dtype, const PcgBatchItem* items, int n, int total_upd, hipStream_t s) {
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(pcg_batch_update_kernel<double>, dim3((unsigned)total_upd), dim3(256), 0, s, items, n);
+  else
+    hipLaunchKernelGGL(pcg_batch_update_kernel<float>, dim3((unsigned)total_upd), dim3(256), 0, s, items, n);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status pcg_batch_launch_precond(int dtype, const PcgBatchItem* items, int n, int total_dots, int total_apply,
+                                    int max_ell, hipStream_t s) {
+  if (total_dots <= 0) return NGD_OK;
+  const size_t lds = (size_t)max_ell * sizeof(double);
+  if (dtype == NGD_F64) {
+    hipLaunchKernelGGL(pcg_batch_dots_kernel<double>, dim3((unsigned)total_dots), dim3(256), 0, s, items, n);
+    hipLaunchKernelGGL(pcg_batch_apply_kernel<double>, dim3((unsigned)total_apply), dim3(256), lds, s, items, n);
+  } else {
+    hipLaunchKernelGGL(pcg_batch_dots_kernel<float>, dim3((unsigned)total_dots), dim3(256), 0, s, items, n);
+    hipLaunchKernelGGL(pcg_batch_apply_kernel<float>, dim3((unsigned)total_apply), dim3(256), lds, s, items, n);
   }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;

@@ -43,13 +43,30 @@ __host__ inline size_t lds_elems(const NetDesc& net, int TP) {
   return ws + pre + 3 * buf + (size_t)TP * kMaxChan + 32;
 }
 
+// Stage W_l (n_out x n_in, row-major in theta) into LDS with a padded row pitch n_in + 1. Each thread
+// issues its loads in batches of kLoadBatch before storing any, so a batch costs one L2 round trip.
+constexpr int kLoadBatch = 16;
 template <typename T>
 __device__ void load_weights(const NetDesc& net, const T* theta, int l, T* Ws) {
   const int n_in = net.widths[l], n_out = net.widths[l + 1];
+  const int total = n_out * n_in;
   const T* W = theta + net.woff[l];
-  for (int e = threadIdx.x; e < n_out * n_in; e += blockDim.x) {
-    int o = e / n_in, i = e - o * n_in;
-    Ws[o * (n_in + 1) + i] = W[e];
+  const int step = blockDim.x;
+  for (int base = threadIdx.x; base < total; base += step * kLoadBatch) {
+    T v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = base + u * step;
+      v[u] = e < total ? W[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = base + u * step;
+      if (e < total) {
+        const int o = e / n_in, i = e - o * n_in;
+        Ws[o * (n_in + 1) + i] = v[u];
+      }
+    }
   }
 }
 
@@ -104,21 +121,22 @@ __device__ void activate(const NetDesc& net, const T* pre_l, int n, int TP, T* h
 // J_w^T wv without storing J_w (the reverse sweep with its seeds scaled by wv).
 enum { kJacobian = 0, kVjp = 1 };
 
+// The workgroup's share of the work: tiles tile_first, tile_first + tile_step, ... of one problem.
+// write_r: store r_w; loss_slot: this workgroup's loss partial (kJacobian); part_row: its partial
+// row (kVjp); tsq_slot: its sum of wv^2 (kVjp).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void residual_jacobian_kernel(
-    NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
-    const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
-    T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
-    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out) {
+__device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, int64_t N, const T* __restrict__ X,
+                              const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g,
+                              const int8_t* __restrict__ kind, T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ,
+                              int TP, int64_t tile_first, int64_t tile_step, const double* __restrict__ wv,
+                              int64_t wv_stride, bool write_r, double* loss_slot, T* part_row, double* tsq_slot) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
   const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
   const int64_t ntiles = (N + TP - 1) / TP;
-  const int64_t tile_step = MODE == kVjp ? (int64_t)gridDim.x : ntiles;
   double tsq_acc = 0.0;
   bool first = true;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += tile_step, first = false) {
+  for (int64_t tile = tile_first; tile < ntiles; tile += tile_step, first = false) {
   const int64_t row0 = tile * TP;
 
   Lds<T> s;
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
       }
       const T rw = sw * res;
       if constexpr (MODE == kJacobian) {
-        if (r_w != nullptr && blockIdx.y == 0) r_w[row] = rw;
+        if (r_w != nullptr && write_r) r_w[row] = rw;
         lsum = rw * rw;
       } else {
         const double wvr = wv[row * wv_stride];
@@ -211,14 +229,13 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
   if constexpr (MODE == kJacobian) {
     __shared__ double red_d[4];
     double tot = block_sum<double>((double)lsum, red_d);
-    if (threadIdx.x == 0 && loss_partial != nullptr)
-      loss_partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0 && loss_slot != nullptr) *loss_slot = tot;
     if (J == nullptr) return;
   }
   __syncthreads();
   // accumulate into this workgroup's partial row (kVjp); a thread always owns the same entries
   auto put = [&](int64_t idx, T v) {
-    T* q = J + (int64_t)blockIdx.x * ldJ + idx;
+    T* q = part_row + idx;
     *q = first ? v : *q + v;
   };
   (void)put;
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
       put(net.boff[L - 1], acc);
     }
     if (first)
-      for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) J[(int64_t)blockIdx.x * ldJ + j] = 0;
+      for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) part_row[j] = 0;
   }
   // adjoint of the last hidden layer outputs: ab = W_out^T seed
   for (int e = threadIdx.x; e < TP * C * n_last; e += blockDim.x) {
@@ -370,7 +387,46 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
   if constexpr (MODE == kVjp) {
     __shared__ double red_t[4];
     const double t = block_sum(tsq_acc, red_t);
-    if (threadIdx.x == 0 && tsq_out != nullptr) tsq_out[blockIdx.x] = t;
+    if (threadIdx.x == 0 && tsq_slot != nullptr) *tsq_slot = t;
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void residual_jacobian_kernel(
+    NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
+    const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
+    T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
+    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out) {
+  const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
+  const int64_t ntiles = (N + TP - 1) / TP;
+  const int64_t tile_step = MODE == kVjp ? (int64_t)gridDim.x : ntiles;
+  double* loss_slot =
+      loss_partial != nullptr ? loss_partial + (int64_t)blockIdx.y * gridDim.x + blockIdx.x : nullptr;
+  T* part_row = MODE == kVjp ? J + (int64_t)blockIdx.x * ldJ : nullptr;
+  double* tsq_slot = tsq_out != nullptr ? tsq_out + blockIdx.x : nullptr;
+  residual_body<T, MODE>(net, theta, N, X, w, f, g, kind, r_w, J, ldJ, TP, blockIdx.x, tile_step, wv, wv_stride,
+                         blockIdx.y == 0, loss_slot, part_row, tsq_slot);
+}
+
+// Several problems in one launch: work item i is tile (i - first_tile[q]) of the problem q whose
+// tile range holds i; workgroups stride over the items (a persistent grid). loss_part has one slot
+// per tile of the problem.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_residual_jacobian_kernel(const BatchResidualItem* __restrict__ items,
+                                                                      int n_prob, int64_t total_tiles) {
+  for (int64_t it = blockIdx.x; it < total_tiles; it += gridDim.x) {
+    int lo = 0, hi = n_prob - 1;  // last problem whose first tile is <= it
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].first_tile <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchResidualItem& b = items[lo];
+    const int64_t tile = it - b.first_tile;
+    const int64_t ntiles = (b.N + b.TP - 1) / b.TP;
+    residual_body<T, kJacobian>(b.net, (const T*)b.theta, b.N, (const T*)b.X, (const T*)b.w, (const T*)b.f,
+                                (const T*)b.g, b.kind, (T*)b.r_w, (T*)b.J, b.ldJ, b.TP, tile, ntiles, nullptr, 0, true,
+                                b.loss_part + tile, nullptr, nullptr);
+    __syncthreads();
   }
 }
 
@@ -647,6 +703,34 @@ ngd_status launch_jvp(const NetDesc& net, int dtype, const void* theta, const vo
     return NGD_ERR_INVALID;
   }
 #undef NGD_JVP
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+size_t residual_lds_bytes(const NetDesc& net, int dtype, int* tp) {
+  size_t bytes = 0;
+  *tp = choose_tp(net, dtype == NGD_F64 ? 8 : 4, &bytes);
+  return bytes;
+}
+
+ngd_status launch_batch_residual_jacobian(int dtype, const BatchResidualItem* items, int n, int64_t total_tiles,
+                                          size_t lds_bytes, hipStream_t s) {
+  if (total_tiles <= 0) return NGD_OK;
+  if (lds_bytes > 160 * 1024) {
+    set_error("network too wide for the residual kernel's LDS budget");
+    return NGD_ERR_INVALID;
+  }
+  // a persistent grid: a few workgroups per CU, striding over all tiles of all problems
+  const int64_t grid = total_tiles < 2048 ? total_tiles : 2048;
+  if (dtype == NGD_F64) {
+    auto k = batch_residual_jacobian_kernel<double>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds_bytes, s, items, n, total_tiles);
+  } else {
+    auto k = batch_residual_jacobian_kernel<float>;
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds_bytes, s, items, n, total_tiles);
+  }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
