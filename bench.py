@@ -37,7 +37,71 @@ WORKLOADS = {
     "c4": "2+1D heat 3-64-64-64-64-1 tanh (P=12,801), 8,192 + 1,024 lateral + 1,024 initial points, FP32, "
           "J recomputed by the JVP / adjoint kernels (never stored), ell=400, PCG rtol 1e-6",
 }
+WORKLOADS["c5"] = ("32 independent 2D/3D Poisson PINNs, hidden widths from {32,48,64,96}, depth 2-4 (P 1,185-28,417), "
+                    "N_int 1,024-8,192 + N_int/8 boundary points, ell from {50,100,200,400}, FP32; batched residual/"
+                    "Jacobian launch, per-problem Nystrom sketch, batched graph-replayed PCG, per-problem Armijo")
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def bench_batch(a):
+    """The batched workload: NGD steps of all problems together; `value` counts problem-steps/s."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2505_11638_amd.driver import BatchNGD
+
+    probs = wl.batch_instances(seed=a.seed)
+    thetas = [wl.glorot_theta(p.widths, a.seed + i) for i, p in enumerate(probs)]
+    ngd = BatchNGD(probs, thetas, solver="nystrom", seed=a.seed)
+    for _ in range(a.warmup):
+        ngd.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, conv = [], True
+    for _ in range(a.steps):
+        L0, L1, outs = ngd.step()
+        iters.append(np.mean([o.iters for o in outs]))
+        conv = conv and all(o.converged for o in outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(probs)
+    line = {
+        "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
+        "value": n * a.steps / dt, "unit": "problem NGD steps/s (sum over the batch)", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5: {WORKLOADS['c5']}", "problems": n,
+                   "P": [p.n_params for p in probs], "N": [p.n_rows for p in probs], "ell": [p.ell for p in probs],
+                   },
+        "nystrom_mean_pcg_iters": float(np.mean(iters)), "nystrom_converged": conv,
+    }
+    ngd.batch.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pcg_rows_kernel_c2_c3_hbm_traffic.md")
+MATVEC_SOURCE = os.path.join(ROOT, "paper_2505_11638_amd", "csrc", "matvec.hip")
+
+
+def measured_traffic(config: str):
+    """HBM bytes per matvec launch from the committed counter summary, or None when the kernel source
+    has changed since the counters were taken (or none were taken for this workload)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(MATVEC_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals, sha = {}, None
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch":
+            vals[parts[1]] = float(parts[2])
+        if len(parts) == 2 and parts[0] == "source_sha256":
+            sha = parts[1]
+    return vals.get(config) if sha == src else None
 
 
 def recompute_matvec_flops(prob) -> float:
@@ -101,6 +165,9 @@ def main(argv=None):
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         return 2
+
+    if a.config == "c5":
+        return bench_batch(a)
 
     import numpy as np
     import torch
@@ -199,7 +266,8 @@ def main(argv=None):
         "loss_first_last": [reps[0].loss, reps[-1].loss_new],
         "phases": phases,
         "roofline": ({"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": achieved,
-                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                      "traffic": measured_traffic(a.config),
                       "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv}
                      if not prob.recompute else
                      {"bound": "alu", "kernel": "jvp_kernel + residual_jacobian_kernel<VJP> (J v, J^T t)",

@@ -219,6 +219,44 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
                            double* alpha, double* loss_new, void* stream);
 
 /*
+ * Batches: many independent PINN problems (uneven P, N, ell; one dtype) driven together. Each batch
+ * member is a full problem handle (ngd_batch_problem) usable with every single-problem entry point,
+ * e.g. for its Nystrom sketch and line search; the two calls below treat all members at once.
+ */
+typedef struct ngd_batch ngd_batch;  /* opaque */
+
+/* n problem descriptions (as for ngd_problem_create; all with the same dtype). */
+ngd_status ngd_batch_create(const ngd_problem_desc* descs, int32_t n, ngd_batch** out);
+ngd_status ngd_batch_destroy(ngd_batch* b);
+int32_t ngd_batch_size(const ngd_batch* b);
+/* Member i's problem handle (owned by the batch), or NULL if i is out of range. */
+ngd_problem* ngd_batch_problem(ngd_batch* b, int32_t i);
+
+/*
+ * ngd_residual_jacobian for every member in one launch: a persistent kernel whose workgroups stride
+ * over all members' point tiles. All arrays are host arrays of n entries holding device pointers as
+ * for ngd_residual_jacobian (J_w[i] with ldJ[i]; grad and loss may be NULL, or hold NULL entries).
+ * Synchronises `stream` on entry (the call reuses its host-side work table).
+ */
+ngd_status ngd_batch_residual_jacobian(ngd_batch* b, const void* const* theta, void* const* r_w,
+                                       void* const* J_w, const int64_t* ldJ, double* const* grad,
+                                       double* const* loss, void* stream);
+
+/*
+ * ngd_pcg_solve for every member (Alg. 3, stored Jacobians): each PCG stage of all members is one
+ * launch (matvec over all members' row blocks, update, preconditioner dot products and
+ * application), and one iteration of the whole batch is captured once as a hipGraph and replayed.
+ * The split of each member's rows over matvec workgroups is chosen on the first solve of a set of
+ * shapes by timing candidate splits (a small autotuner).
+ *   ops, g, lambda, precs, d, infos : host arrays of n entries. precs may be NULL (plain CG for
+ *   all), or entries with U == NULL are plain CG. Returns NGD_ERR_NOT_CONVERGED / BREAKDOWN if any
+ *   member did; infos holds each member's outcome. Synchronises `stream`.
+ */
+ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const double* const* g,
+                               const double* lambda, const ngd_precond* precs, double rtol, int64_t maxit,
+                               double* const* d, ngd_pcg_info* infos, void* stream);
+
+/*
  * Kernel timers (measurement support, not part of the method). When enabled, the library records a
  * HIP event pair on the call's stream around every launch of the timed kernels and accumulates the
  * elapsed times, so a benchmark can read the average duration of, e.g., the one-pass Gramian matvec

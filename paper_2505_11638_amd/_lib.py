@@ -64,6 +64,16 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.c_void_p]),
     "ngd_line_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                   C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_void_p)]),
+    "ngd_batch_destroy": (C.c_int, [C.c_void_p]),
+    "ngd_batch_size": (C.c_int32, [C.c_void_p]),
+    "ngd_batch_problem": (C.c_void_p, [C.c_void_p, C.c_int32]),
+    "ngd_batch_residual_jacobian": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                              C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_void_p),
+                                              C.POINTER(C.c_void_p), C.c_void_p]),
+    "ngd_batch_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.POINTER(C.c_void_p), C.POINTER(C.c_double),
+                                      C.POINTER(Precond), C.c_double, C.c_int64, C.POINTER(C.c_void_p),
+                                      C.POINTER(PcgInfo), C.c_void_p]),
     "ngd_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ngd_timing_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }

@@ -65,7 +65,8 @@ class Problem:
     `data` needs attributes widths, pde, X (N x d), w, f, g, kind (as in `workloads.Problem`); they are
     copied to the device in the working precision `dtype` ("f64" or "f32")."""
 
-    def __init__(self, data, dtype: Optional[str] = None, max_ell: Optional[int] = None, device="cuda"):
+    def __init__(self, data, dtype: Optional[str] = None, max_ell: Optional[int] = None, device="cuda",
+                 _batch=None):
         self.lib = L.load()
         self.dtype_name = dtype or data.dtype
         self.dtype = _DTYPE[self.dtype_name]
@@ -81,18 +82,25 @@ class Problem:
         self.kind = to(data.kind, torch.int8)
         self.N = int(self.X.shape[0])
         self._widths_c = (C.c_int32 * len(self.widths))(*self.widths)
-        desc = L.ProblemDesc(len(self.widths) - 1, self._widths_c, self.pde, self.dtype, self.N,
-                             self.X.data_ptr(), self.w.data_ptr(), self.f.data_ptr(), self.g.data_ptr(),
-                             self.kind.data_ptr(), int(max_ell or getattr(data, "ell", 1)))
+        self.desc = L.ProblemDesc(len(self.widths) - 1, self._widths_c, self.pde, self.dtype, self.N,
+                                  self.X.data_ptr(), self.w.data_ptr(), self.f.data_ptr(), self.g.data_ptr(),
+                                  self.kind.data_ptr(), int(max_ell or getattr(data, "ell", 1)))
+        self._owned = _batch is None
+        if _batch is not None:  # a batch member: the batch creates and owns the handle
+            return
         h = C.c_void_p()
-        L.check(self.lib.ngd_problem_create(C.byref(desc), C.byref(h)), "ngd_problem_create")
+        L.check(self.lib.ngd_problem_create(C.byref(self.desc), C.byref(h)), "ngd_problem_create")
+        self._bind(h)
+
+    def _bind(self, h):
         self.h = h
         self.P = int(self.lib.ngd_num_params(h))
         self.ld = int(self.lib.ngd_recommended_ld(h))
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.ngd_problem_destroy(self.h)
+            if self._owned:
+                self.lib.ngd_problem_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -230,3 +238,77 @@ class Problem:
                                          int(max_halvings), _ptr(theta_out), C.byref(a), C.byref(ln), _stream()),
                 "ngd_line_search")
         return theta_out, a.value, ln.value
+
+
+class Batch:
+    """Several independent problems (one dtype) bound to one libngd batch. `members[i]` is a `Problem`
+    view of member i's handle (for its sketch, line search, ...); `residual_jacobian` and `pcg_solve`
+    run all members together through the batched entry points."""
+
+    def __init__(self, datas, dtype: Optional[str] = None, device="cuda"):
+        self.lib = L.load()
+        self.members = [Problem(d, dtype=dtype, device=device, _batch=self) for d in datas]
+        descs = (L.ProblemDesc * len(self.members))(*[m.desc for m in self.members])
+        b = C.c_void_p()
+        L.check(self.lib.ngd_batch_create(descs, len(self.members), C.byref(b)), "ngd_batch_create")
+        self.b = b
+        for i, m in enumerate(self.members):
+            m._bind(C.c_void_p(self.lib.ngd_batch_problem(b, i)))
+
+    def __len__(self):
+        return len(self.members)
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.h = None
+            self.lib.ngd_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptrs(ts):
+        return (C.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
+
+    def residual_jacobian(self, thetas, Js, want_grad=True, want_loss=True):
+        """ngd_batch_residual_jacobian: returns lists (r_w, grad or None, loss or None) per member."""
+        n = len(self.members)
+        rs = [torch.empty(m.N, dtype=m.tdtype, device=m.device) for m in self.members]
+        grads = [torch.empty(m.P, dtype=torch.float64, device=m.device) if want_grad else None for m in self.members]
+        losses = [torch.empty(1, dtype=torch.float64, device=m.device) if want_loss else None for m in self.members]
+        for m, t, J in zip(self.members, thetas, Js):
+            _need(t, m.tdtype, "theta")
+            _need(J, m.tdtype, "J")
+        lds = (C.c_int64 * n)(*[J.stride(0) for J in Js])
+        L.check(self.lib.ngd_batch_residual_jacobian(self.b, self._ptrs(thetas), self._ptrs(rs), self._ptrs(Js), lds,
+                                                     self._ptrs(grads) if want_grad else None,
+                                                     self._ptrs(losses) if want_loss else None, _stream()),
+                "ngd_batch_residual_jacobian")
+        return rs, grads, losses
+
+    def pcg_solve(self, Js, gs, lams, precs=None, rtol=1e-6, maxit=1000):
+        """ngd_batch_pcg_solve: precs is None or a list of NystromResult / None per member."""
+        n = len(self.members)
+        ops = (L.Operator * n)(*[m._op(J) for m, J in zip(self.members, Js)])
+        ds = [torch.empty(m.P, dtype=torch.float64, device=m.device) for m in self.members]
+        lam = (C.c_double * n)(*[float(v) for v in lams])
+        pcs = None
+        if precs is not None:
+            pcs = (L.Precond * n)(*[L.Precond(p.U.data_ptr(), p.U.stride(0), p.lam_hat.data_ptr(), p.lam_hat.numel())
+                                    if p is not None else L.Precond(None, 0, None, 0) for p in precs])
+        infos = (L.PcgInfo * n)()
+        for m, gv in zip(self.members, gs):
+            _need(gv, torch.float64, "g")
+        st = self.lib.ngd_batch_pcg_solve(self.b, ops, self._ptrs(gs), lam, pcs, float(rtol), int(maxit),
+                                          self._ptrs(ds), infos, _stream())
+        L.check(st, "ngd_batch_pcg_solve", (L.NGD_ERR_NOT_CONVERGED, L.NGD_ERR_BREAKDOWN))
+        return [PcgResult(d, int(i.iters), float(i.rel_res), bool(i.converged), bool(i.breakdown), st)
+                for d, i in zip(ds, infos)]

@@ -60,6 +60,7 @@ struct ngd_problem {
   double* F;         // ell x ell
   double* evals;     // ell
   double* gemm_work; // split-K partials of the ell x ell Gram products (8 ell^2)
+  double* cholblk;   // the Cholesky's diagonal-block factors (ceil(ell / 32) x 32 x 32)
   void* eigw;        // eig workspace
   void* trial;       // kTrials x ldP, dtype (line search)
   double* alphas;    // kTrials
@@ -291,6 +292,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->evals, sizeof(double) * (size_t)L});
   plan.push_back({(void**)&h->gemm_work, sizeof(double) * 8 * (size_t)L * L});
+  plan.push_back({(void**)&h->cholblk, sizeof(double) * 1024 * (size_t)((L + 31) / 32)});
   plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
   plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
   plan.push_back({(void**)&h->nvec[0], sizeof(double) * (size_t)N});
@@ -497,7 +499,7 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     NGD_TRY(launch_gemm(g2, s));
     // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
     NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
-                                    reinterpret_cast<int*>(h->scal + 210), s));
+                                    reinterpret_cast<int*>(h->scal + 210), h->cholblk, s));
     NGD_TRY(launch_cast(T, h->Z, NGD_F64, h->Q, N * L, s));
     return launch_trsm_right_lt(h->M, (int)L, (double*)h->Q, L, N, s);
   }));
@@ -738,6 +740,324 @@ ngd_status ngd_timing_read(ngd_problem* h, int32_t id, int64_t* launches, double
   *launches = h->t_n[id];
   *total_ms = h->t_ms[id];
   return NGD_OK;
+}
+
+// ================= batched problems =================
+
+struct ngd_batch {
+  std::vector<ngd_problem*> inst;
+  int dtype = NGD_F32;
+  BatchResidualItem* d_res = nullptr;
+  BatchResidualItem* h_res = nullptr;
+  PcgBatchItem* d_pcg = nullptr;
+  PcgBatchItem* h_pcg = nullptr;
+  PcgState* d_states = nullptr;
+  PcgState* h_states = nullptr;
+  hipStream_t capture = nullptr;      // stream on which the PCG iteration is captured
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> graph_key;     // launch shapes the captured graph was built for
+  int rows_target = 0;                // autotuned rows per matvec workgroup (0: not tuned yet)
+  std::vector<int64_t> tuned_for;     // problem shapes the tuning applies to
+  int64_t last_iters = 4;
+};
+
+namespace {
+
+void batch_release(ngd_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  (void)hipFree(b->d_res);
+  (void)hipFree(b->d_pcg);
+  (void)hipFree(b->d_states);
+  (void)hipHostFree(b->h_res);
+  (void)hipHostFree(b->h_pcg);
+  (void)hipHostFree(b->h_states);
+  for (ngd_problem* h : b->inst) ngd_problem_destroy(h);
+  delete b;
+}
+
+// per-problem matvec workgroups for a target number of rows per workgroup
+int batch_nwg(const ngd_problem* h, int rows_target) {
+  int64_t w = rows_target > 0 ? (h->N + rows_target - 1) / rows_target : h->nwg;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(w, h->nwg));
+}
+
+}  // namespace
+
+ngd_status ngd_batch_create(const ngd_problem_desc* descs, int32_t n, ngd_batch** out) {
+  NGD_CHECK(descs != nullptr && out != nullptr, "NULL argument");
+  NGD_CHECK(n >= 1 && n <= 4096, "batch size out of range [1, 4096]");
+  *out = nullptr;
+  ngd_batch* b = new ngd_batch();
+  b->dtype = descs[0].dtype;
+  for (int i = 0; i < n; ++i) {
+    if (descs[i].dtype != b->dtype) {
+      batch_release(b);
+      set_error("all problems of a batch must share one dtype");
+      return NGD_ERR_INVALID;
+    }
+    ngd_problem* h = nullptr;
+    ngd_status st = ngd_problem_create(&descs[i], &h);
+    if (st != NGD_OK) {
+      batch_release(b);
+      return st;
+    }
+    b->inst.push_back(h);
+  }
+  bool ok = hipMalloc(&b->d_res, sizeof(BatchResidualItem) * n) == hipSuccess &&
+            hipMalloc(&b->d_pcg, sizeof(PcgBatchItem) * n) == hipSuccess &&
+            hipMalloc(&b->d_states, sizeof(PcgState) * n) == hipSuccess &&
+            hipHostMalloc(&b->h_res, sizeof(BatchResidualItem) * n, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_pcg, sizeof(PcgBatchItem) * n, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_states, sizeof(PcgState) * n, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    batch_release(b);
+    set_error("batch allocation failed");
+    return NGD_ERR_OOM;
+  }
+  *out = b;
+  return NGD_OK;
+}
+
+ngd_status ngd_batch_destroy(ngd_batch* b) {
+  if (b != nullptr) batch_release(b);
+  return NGD_OK;
+}
+
+int32_t ngd_batch_size(const ngd_batch* b) { return b ? (int32_t)b->inst.size() : -1; }
+
+ngd_problem* ngd_batch_problem(ngd_batch* b, int32_t i) {
+  return (b != nullptr && i >= 0 && i < (int32_t)b->inst.size()) ? b->inst[i] : nullptr;
+}
+
+ngd_status ngd_batch_residual_jacobian(ngd_batch* b, const void* const* theta, void* const* r_w, void* const* J_w,
+                                       const int64_t* ldJ, double* const* grad, double* const* loss, void* stream) {
+  NGD_CHECK(b != nullptr && theta != nullptr && r_w != nullptr && J_w != nullptr && ldJ != nullptr, "NULL argument");
+  hipStream_t s = S(stream);
+  const int n = (int)b->inst.size();
+  // the host table is reused by every call: wait until the previous call's copy has been consumed
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  int64_t tiles = 0;
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    NGD_CHECK(theta[i] != nullptr && r_w[i] != nullptr && J_w[i] != nullptr, "NULL problem pointer");
+    NGD_CHECK(ldJ[i] >= h->P, "ldJ < P");
+    int tp = 0;
+    lds = std::max(lds, residual_lds_bytes(h->net, h->dtype, &tp));
+    BatchResidualItem& it = b->h_res[i];
+    it.net = h->net;
+    it.theta = theta[i];
+    it.X = h->X;
+    it.w = h->w;
+    it.f = h->f;
+    it.g = h->g;
+    it.kind = h->kind;
+    it.r_w = r_w[i];
+    it.J = J_w[i];
+    it.ldJ = ldJ[i];
+    it.N = h->N;
+    it.first_tile = tiles;
+    it.TP = tp;
+    it.loss_part = h->loss_part;
+    tiles += (h->N + tp - 1) / tp;
+  }
+  NGD_HIP_TRY(hipMemcpyAsync(b->d_res, b->h_res, sizeof(BatchResidualItem) * n, hipMemcpyHostToDevice, s));
+  NGD_TRY(launch_batch_residual_jacobian(b->dtype, b->d_res, n, tiles, lds, s));
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    const int nt = (int)((h->N + b->h_res[i].TP - 1) / b->h_res[i].TP);
+    if (loss != nullptr && loss[i] != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, nt, 1, 0.5, loss[i], s));
+    if (grad != nullptr && grad[i] != nullptr) {
+      const ngd_operator op{theta[i], J_w[i], ldJ[i]};
+      NGD_TRY(check_op(h, &op));
+      NGD_TRY(launch_grad_rows(h->dtype, J_w[i], ldJ[i], h->N, r_w[i], h->partial, h->nwg, s));
+      NGD_TRY(launch_gram_reduce(h->dtype, h->partial, h->nwg, ldJ[i], h->P, nullptr, 0.0, grad[i], s));
+    }
+  }
+  return NGD_OK;
+}
+
+namespace {
+
+// item numbering of the batched PCG launches for the current per-problem workgroup counts
+void batch_pcg_items(ngd_batch* b, int* rows, int* upd, int* dots, int* elem, int* apply) {
+  *rows = *upd = *dots = *elem = *apply = 0;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    PcgBatchItem& it = b->h_pcg[i];
+    it.nwg = batch_nwg(b->inst[i], b->rows_target);
+    it.item0_rows = *rows;
+    it.item0_upd = *upd;
+    it.item0_dots = *dots;
+    it.item0_elem = *elem;
+    it.item0_apply = *apply;
+    *rows += it.nwg;
+    *upd += (int)((it.P + 31) / 32);
+    *elem += (int)((it.P + 255) / 256);
+    if (!it.plain) {
+      *dots += it.ell;
+      *apply += (int)((it.P + 255) / 256);
+    }
+  }
+}
+
+}  // namespace
+
+ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const double* const* g, const double* lambda,
+                               const ngd_precond* precs, double rtol, int64_t maxit, double* const* d,
+                               ngd_pcg_info* infos, void* stream) {
+  NGD_CHECK(b != nullptr && ops != nullptr && g != nullptr && lambda != nullptr && d != nullptr && infos != nullptr,
+            "NULL argument");
+  NGD_CHECK(rtol >= 0.0 && maxit >= 0, "rtol >= 0 and maxit >= 0 required");
+  hipStream_t s = S(stream);
+  const int n = (int)b->inst.size();
+  NGD_HIP_TRY(hipStreamSynchronize(s));  // the host tables are reused by every call
+  int64_t max_ld = 0;
+  int max_ell = 1;
+  std::vector<int64_t> shape;
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    NGD_CHECK(ops[i].J != nullptr, "the batched solve needs stored Jacobians");
+    NGD_TRY(check_op(h, &ops[i]));
+    NGD_CHECK(lambda[i] > 0.0 && std::isfinite(lambda[i]), "lambda must be > 0");
+    NGD_CHECK(g[i] != nullptr && d[i] != nullptr, "NULL problem pointer");
+    const ngd_precond* pc = (precs != nullptr && precs[i].U != nullptr) ? &precs[i] : nullptr;
+    if (pc != nullptr) {
+      NGD_CHECK(pc->lam_hat != nullptr, "preconditioner pointers are NULL");
+      NGD_CHECK(pc->ell >= 1 && pc->ell <= h->max_ell && pc->ldU >= h->P, "bad preconditioner ell / ldU");
+    }
+    PcgBatchItem& it = b->h_pcg[i];
+    it.J = ops[i].J;
+    it.ldJ = ops[i].ldJ;
+    it.N = h->N;
+    it.P = h->P;
+    it.g = g[i];
+    it.x = d[i];
+    it.r = h->pcg_r;
+    it.z = h->pcg_z;
+    it.p0 = h->pcg_p[0];
+    it.p1 = h->pcg_p[1];
+    it.s = h->pcg_s;
+    it.part = h->pcg_part;
+    it.partial = h->partial;
+    it.tsq = h->tsq;
+    it.st = b->d_states + i;
+    it.U = pc ? pc->U : nullptr;
+    it.ldU = pc ? pc->ldU : 0;
+    it.lam = pc ? pc->lam_hat : nullptr;
+    it.mu = lambda[i];
+    it.rtol = rtol;
+    it.ell = pc ? (int)pc->ell : 0;
+    it.plain = pc == nullptr;
+    max_ld = std::max(max_ld, ops[i].ldJ);
+    max_ell = std::max(max_ell, it.ell);
+    shape.push_back(h->N);
+    shape.push_back(ops[i].ldJ);
+    PcgState& st = b->h_states[i];
+    std::memset(&st, 0, sizeof(PcgState));
+    st.lambda = lambda[i];
+    st.maxit = maxit;
+  }
+  NGD_TRY(pcg_batch_prepare(b->dtype, max_ld, max_ell));
+  int rows, upd, dots, elem, apply;
+  // autotune the split of each problem's rows over matvec workgroups (once per set of shapes): time
+  // one batched matvec launch per candidate on this solve's first direction; that launch only writes
+  // buffers the first iteration rewrites
+  const bool tune = b->rows_target == 0 || b->tuned_for != shape;
+  if (tune) b->rows_target = 0;
+  batch_pcg_items(b, &rows, &upd, &dots, &elem, &apply);
+  NGD_HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(PcgState) * n, hipMemcpyHostToDevice, s));
+  NGD_HIP_TRY(hipMemcpyAsync(b->d_pcg, b->h_pcg, sizeof(PcgBatchItem) * n, hipMemcpyHostToDevice, s));
+  NGD_TRY(pcg_batch_launch_init(b->dtype, b->d_pcg, n, elem, s));
+  NGD_TRY(pcg_batch_launch_precond(b->dtype, b->d_pcg, n, dots, apply, max_ell, s));
+  if (tune) {
+    const int cand[4] = {8, 16, 32, 64};
+    float best = 1e30f;
+    int best_t = 16;
+    hipEvent_t e0, e1;
+    NGD_HIP_TRY(hipEventCreate(&e0));
+    NGD_HIP_TRY(hipEventCreate(&e1));
+    for (int t : cand) {
+      b->rows_target = t;
+      batch_pcg_items(b, &rows, &upd, &dots, &elem, &apply);
+      NGD_HIP_TRY(hipStreamSynchronize(s));
+      NGD_HIP_TRY(hipMemcpyAsync(b->d_pcg, b->h_pcg, sizeof(PcgBatchItem) * n, hipMemcpyHostToDevice, s));
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        NGD_HIP_TRY(hipEventRecord(e0, s));
+        NGD_TRY(pcg_batch_launch_rows(b->dtype, b->d_pcg, n, rows, max_ld, s));
+        NGD_HIP_TRY(hipEventRecord(e1, s));
+        NGD_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        NGD_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms_best = std::min(ms_best, ms);
+      }
+      if (ms_best < best) {
+        best = ms_best;
+        best_t = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->rows_target = best_t;
+    b->tuned_for = shape;
+    batch_pcg_items(b, &rows, &upd, &dots, &elem, &apply);
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    NGD_HIP_TRY(hipMemcpyAsync(b->d_pcg, b->h_pcg, sizeof(PcgBatchItem) * n, hipMemcpyHostToDevice, s));
+  }
+  // one PCG iteration of every problem = 2 (plain CG) or 4 batched launches, captured once as a graph
+  std::vector<int64_t> key = {rows, upd, dots, apply, max_ld, max_ell, b->dtype};
+  if (b->exec == nullptr || b->graph_key != key) {
+    if (b->exec) NGD_HIP_TRY(hipGraphExecDestroy(b->exec));
+    if (b->graph) NGD_HIP_TRY(hipGraphDestroy(b->graph));
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (b->capture == nullptr) NGD_HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    NGD_HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed));
+    ngd_status st = pcg_batch_launch_rows(b->dtype, b->d_pcg, n, rows, max_ld, b->capture);
+    if (st == NGD_OK) st = pcg_batch_launch_update(b->dtype, b->d_pcg, n, upd, b->capture);
+    if (st == NGD_OK) st = pcg_batch_launch_precond(b->dtype, b->d_pcg, n, dots, apply, max_ell, b->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->capture, &graph);
+    if (st != NGD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    NGD_HIP_TRY(ce);
+    b->graph = graph;
+    NGD_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_key = key;
+  }
+  int64_t k = 0;
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(64, b->last_iters));
+  while (true) {
+    const int64_t upto = std::min<int64_t>(maxit, k + chunk);
+    for (; k < upto; ++k) NGD_HIP_TRY(hipGraphLaunch(b->exec, s));
+    NGD_HIP_TRY(hipMemcpyAsync(b->h_states, b->d_states, sizeof(PcgState) * n, hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    bool all_done = true;
+    for (int i = 0; i < n; ++i) all_done = all_done && (b->h_states[i].done != 0);
+    if (all_done || k >= maxit) break;
+    chunk = std::min<int64_t>(chunk * 2, 64);
+  }
+  ngd_status ret = NGD_OK;
+  int64_t most = 0;
+  for (int i = 0; i < n; ++i) {
+    const PcgState& st = b->h_states[i];
+    infos[i].iters = st.iters;
+    infos[i].rel_res = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
+    infos[i].converged = st.converged;
+    infos[i].breakdown = st.breakdown;
+    most = std::max<int64_t>(most, st.iters);
+    if (st.breakdown) ret = NGD_ERR_BREAKDOWN;
+    else if (!st.converged && ret == NGD_OK) ret = NGD_ERR_NOT_CONVERGED;
+  }
+  b->last_iters = std::max<int64_t>(1, most);
+  if (ret == NGD_ERR_BREAKDOWN) set_error("batched PCG: breakdown in at least one problem");
+  else if (ret == NGD_ERR_NOT_CONVERGED) set_error("batched PCG: at least one problem reached maxit");
+  return ret;
 }
 
 }  // extern "C"

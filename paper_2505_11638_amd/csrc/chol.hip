@@ -18,8 +18,8 @@ namespace {
 constexpr int kNb = 32;
 constexpr int kLd = kNb + 1;  // LDS row pitch of a staged block
 
-// factor the nb x nb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, kNb x kLd), one
-// wave: lane r % 32 owns row r, the two half-waves split the columns of the trailing update
+// factor the nb x nb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, kNb x kLd): thread t
+// owns row t % 32, and the blockDim / 32 thread groups split the columns of the trailing update
 __device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb, double floor, double null_thresh,
                             double* Ls, int* nmod) {
   const int t = threadIdx.x;
@@ -28,7 +28,7 @@ __device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb,
     Ls[r * kLd + c] = (r < nb && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
   }
   __syncthreads();
-  const int r = t & 31, half = t >> 5;
+  const int r = t & 31, half = t >> 5, halves = (int)blockDim.x >> 5;
   for (int c = 0; c < nb; ++c) {
     if (t == 0) {
       double a = Ls[c * kLd + c];
@@ -42,7 +42,7 @@ __device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb,
     __syncthreads();
     if (r > c && r < nb) {
       const double lrc = Ls[r * kLd + c];
-      for (int q = c + 1 + half; q <= r; q += 2) Ls[r * kLd + q] -= lrc * Ls[q * kLd + c];
+      for (int q = c + 1 + half; q <= r; q += halves) Ls[r * kLd + q] -= lrc * Ls[q * kLd + c];
     }
     __syncthreads();
   }
@@ -69,19 +69,45 @@ __device__ __forceinline__ void solve_row(double* __restrict__ x, const double* 
     if (j < nb) x[j] = v[j];
 }
 
-// Cholesky of the diagonal block of panel j0, written back in place (one wave)
-__global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, int n, int j0, int nb,
-                                                       const double* __restrict__ floor_p, int* __restrict__ nmod) {
+// One Cholesky panel: every workgroup factors the diagonal block of panel j0 in LDS (workgroup 0
+// also stores the factor in Lblk and counts the null pivots), then solves its share of the rows
+// below, L21 = A21 L11^{-T}, one row per thread. Fusing the two saves a launch and a dependency per
+// panel; the factor goes to Lblk, not back into A, because the other workgroups are still reading
+// A's diagonal block (copy_diag_blocks_kernel moves all factors into place at the end).
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int n, int j0, int nb,
+                                                         const double* __restrict__ floor_p, int* __restrict__ nmod,
+                                                         double* __restrict__ Lblk) {
   __shared__ double Ls[kNb * kLd];
+  __shared__ double rdiag[kNb];
   __shared__ int local_mod;
   if (threadIdx.x == 0) local_mod = 0;
   __syncthreads();
   factor_diag(A, n, j0, nb, floor_p[0], floor_p[2], Ls, &local_mod);
+  if (blockIdx.x == 0) {
+    double* dst = Lblk + (int64_t)(j0 / kNb) * kNb * kNb;
+    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+      const int r = e >> 5, c = e & 31;
+      dst[e] = (r < nb && c <= r) ? Ls[r * kLd + c] : 0.0;
+    }
+    if (threadIdx.x == 0) *nmod += local_mod;
+  }
+  if (threadIdx.x < kNb) rdiag[threadIdx.x] = threadIdx.x < nb ? 1.0 / Ls[threadIdx.x * kLd + threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t below = n - j0 - nb;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < below) solve_row(A + (j0 + nb + r) * (int64_t)n + j0, Ls, rdiag, nb);
+}
+
+// the diagonal factors from Lblk into A's diagonal blocks (upper part of each block zeroed)
+__global__ __launch_bounds__(256) void copy_diag_blocks_kernel(double* __restrict__ A, int n,
+                                                               const double* __restrict__ Lblk) {
+  const int j0 = blockIdx.x * kNb;
+  const int nb = min(kNb, n - j0);
+  const double* src = Lblk + (int64_t)blockIdx.x * kNb * kNb;
   for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
     const int r = e >> 5, c = e & 31;
-    if (r < nb && c < nb) A[(int64_t)(j0 + r) * n + j0 + c] = c <= r ? Ls[r * kLd + c] : 0.0;
+    if (r < nb && c < nb) A[(int64_t)(j0 + r) * n + j0 + c] = src[e];
   }
-  if (threadIdx.x == 0) *nmod += local_mod;
 }
 
 // rows of X (FP64, ld ldx): X[r, j0:j0+nb] <- X[r, j0:j0+nb] L_JJ^{-T}, L read from the factor
@@ -119,23 +145,21 @@ __global__ void shift_kernel(double* __restrict__ M, int n, double shift_rel, do
 
 }  // namespace
 
-// L (lower, in place of M) with L L^T = M + nu I, nu = shift_rel tr(M). `scal` holds 2 doubles
-// (floor, nu) and `nmod` the count of floored pivots (both device).
+// L (lower, in place of M) with L L^T = M + nu I, nu = shift_rel tr(M). `scal` holds 3 doubles
+// (floor, nu, null threshold) and `nmod` the count of null pivots (both device); Lblk holds
+// ceil(n / 32) 32 x 32 blocks of scratch.
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
-                                   hipStream_t s) {
+                                   double* Lblk, hipStream_t s) {
   hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(256), 0, s, M, n, shift_rel, floor_rel, scal, nmod);
   NGD_HIP_TRY(hipGetLastError());
   for (int j0 = 0; j0 < n; j0 += kNb) {
     const int nb = std::min(kNb, n - j0);
     const int below = n - j0 - nb;
-    // a single wave: its barriers are nearly free, and the block is small
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, s, M, n, j0, nb, scal, nmod);
+    // L11 and L21 = A21 L11^{-T} in one launch
+    const unsigned wgs = (unsigned)std::max(1, (below + 255) / 256);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(wgs), dim3(256), 0, s, M, n, j0, nb, scal, nmod, Lblk);
     NGD_HIP_TRY(hipGetLastError());
     if (below > 0) {
-      // L21 = A21 L11^{-T}, row by row
-      hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, s, M, n, j0, nb,
-                         M + (int64_t)(j0 + nb) * n, (int64_t)n, (int64_t)below);
-      NGD_HIP_TRY(hipGetLastError());
       // A22 -= L21 L21^T
       const int t0 = j0 + nb;
       GemmArgs g{below, below, nb, M + (int64_t)t0 * n + j0, n, true, M + (int64_t)t0 * n + j0, n, true,
@@ -144,6 +168,8 @@ ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double fl
       if (st != NGD_OK) return st;
     }
   }
+  hipLaunchKernelGGL(copy_diag_blocks_kernel, dim3((unsigned)((n + kNb - 1) / kNb)), dim3(256), 0, s, M, n, Lblk);
+  NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
 

@@ -246,7 +246,7 @@ size_t residual_lds_bytes(const NetDesc& net, int dtype, int* tp);
 
 // chol.hip: blocked shifted Cholesky of the core and the right triangular solve X <- X L^{-T}
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
-                                   hipStream_t s);
+                                   double* Lblk, hipStream_t s);
 ngd_status launch_trsm_right_lt(const double* L, int n, double* X, int64_t ldx, int64_t nrows, hipStream_t s);
 
 // nystrom helpers (misc.hip)

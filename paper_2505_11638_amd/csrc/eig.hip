@@ -455,6 +455,7 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
   double* Ys = zc + (size_t)kNC * n;                 // wy x n
   __shared__ double W[kWy][kNC];
   __shared__ double S[kWy][kNC];
+  __shared__ double Ts[kWy * kWy];
   const int c0 = blockIdx.x * kNC;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int c = 0; c < kNC; ++c)
@@ -465,8 +466,16 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
     const int k0 = b * wy;
     const int m = min(wy, nref - k0);
     __syncthreads();
-    for (int i = 0; i < m; ++i)
-      for (int j = threadIdx.x; j < n; j += blockDim.x) Ys[i * n + j] = V[(int64_t)(k0 + i) * n + j];
+    // the block's reflectors and T factor into LDS (all loads of a thread issued before its stores)
+    for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Ts[e] = Tall[(int64_t)b * kWy * kWy + e];
+    for (int j0 = threadIdx.x; j0 < n; j0 += blockDim.x) {
+      double yv[kWy];
+#pragma unroll
+      for (int i = 0; i < kWy; ++i) yv[i] = i < m ? V[(int64_t)(k0 + i) * n + j0] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kWy; ++i)
+        if (i < m) Ys[i * n + j0] = yv[i];
+    }
     __syncthreads();
     // W = Y^T Z (one wave per (reflector, column) pair); v_k is zero at and above row k
     for (int q = wid; q < wy * kNC; q += nw) {
@@ -482,10 +491,9 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
     // S = T W
     if (threadIdx.x < wy * kNC) {
       const int i = threadIdx.x / kNC, c = threadIdx.x % kNC;
-      const double* T = Tall + (int64_t)b * kWy * kWy;
       double acc = 0.0;
       if (i < m)
-        for (int a = i; a < m; ++a) acc += T[i * kWy + a] * W[a][c];
+        for (int a = i; a < m; ++a) acc += Ts[i * kWy + a] * W[a][c];
       S[i][c] = acc;
     }
     __syncthreads();

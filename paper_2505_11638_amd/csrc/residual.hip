@@ -25,6 +25,10 @@ struct Lds {
   T* red;   // reduction scratch
 };
 
+// Row pitch of the per-channel buffers (h, abar, zbar): the widest layer plus one, so that the 16 rows
+// an MFMA operand read touches at one k fall in distinct LDS banks.
+__host__ __device__ inline int chan_pitch(const NetDesc& net) { return net.max_width + 1; }
+
 __host__ __device__ inline int64_t pre_offset(const NetDesc& net, int layer, int TP) {
   // start of hidden layer `layer` (affine index, < n_layers-1) in the pre buffer
   int64_t off = 0;
@@ -32,14 +36,14 @@ __host__ __device__ inline int64_t pre_offset(const NetDesc& net, int layer, int
   return off;
 }
 
-__host__ inline size_t lds_elems(const NetDesc& net, int TP) {
+__host__ __device__ inline size_t lds_elems(const NetDesc& net, int TP) {
   size_t ws = 0;
   for (int l = 0; l < net.n_layers; ++l) {
     size_t s = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
     ws = s > ws ? s : ws;
   }
   size_t pre = (size_t)pre_offset(net, net.n_layers - 1, TP);
-  size_t buf = (size_t)TP * net.C * net.max_width;
+  size_t buf = (size_t)TP * net.C * chan_pitch(net);
   return ws + pre + 3 * buf + (size_t)TP * kMaxChan + 32;
 }
 
@@ -70,10 +74,118 @@ __device__ void load_weights(const NetDesc& net, const T* theta, int l, T* Ws) {
   }
 }
 
+// ---- 16 x 16 MFMA tiles for the per-point products ----
+// One wave computes C = sum_k A(m, k) B(k, n) for a 16 x 16 tile with v_mfma_f32_16x16x4f32 (or the
+// FP64 form): in each K-step of 4, lane l supplies A(l % 16, k0 + l / 16) and B(k0 + l / 16, l % 16).
+// The operands come from LDS through the functors (which return 0 outside the problem's extents);
+// `store(row, col, value)` receives the lane's four results. The accumulator layout is row
+// 4 (l / 16) + r for the FP32 form and l / 16 + 4 r for the FP64 form, column l % 16.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+template <typename T, typename FA, typename FB, typename FS>
+__device__ __forceinline__ void mfma_tile(int K, FA&& a, FB&& b, FS&& store) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  if constexpr (sizeof(T) == 8) {
+    md4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(r16, k0 + kq), b(k0 + kq, r16), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(kq + 4 * r, r16, acc[r]);
+  } else {
+    mf4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a(r16, k0 + kq), b(k0 + kq, r16), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(4 * kq + r, r16, acc[r]);
+  }
+}
+
+// Two products summed in one tile: C = A1 B1 + A2 B2 (the tangent of a layer product)
+template <typename T, typename FA1, typename FB1, typename FA2, typename FB2, typename FS>
+__device__ __forceinline__ void mfma_tile2(int K, FA1&& a1, FB1&& b1, FA2&& a2, FB2&& b2, FS&& store) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  if constexpr (sizeof(T) == 8) {
+    md4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1(r16, k0 + kq), b1(k0 + kq, r16), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2(r16, k0 + kq), b2(k0 + kq, r16), acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(kq + 4 * r, r16, acc[r]);
+  } else {
+    mf4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1(r16, k0 + kq), b1(k0 + kq, r16), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2(r16, k0 + kq), b2(k0 + kq, r16), acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(4 * kq + r, r16, acc[r]);
+  }
+}
+
+// pre[pc][o] = sum_i W[o][i] h[pc][i] (+ b[o] on value channels) for pc < npc, o < n_out (row pitch ldo)
+template <typename T>
+__device__ __forceinline__ void mfma_forward(const T* Ws, int n_in, int n_out, const T* hb, int nm, int npc, int C,
+                                             const T* __restrict__ b, T* pre, int ldo = 0) {
+  if (ldo == 0) ldo = n_out;
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tm = (npc + 15) / 16, tn = (n_out + 15) / 16;
+  for (int t = wid; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    mfma_tile<T>(
+        n_in, [&](int r, int k) { const int pc = m0 + r; return (pc < npc && k < n_in) ? hb[pc * nm + k] : T(0); },
+        [&](int k, int c) { const int o = n0 + c; return (o < n_out && k < n_in) ? Ws[o * (n_in + 1) + k] : T(0); },
+        [&](int r, int c, T v) {
+          const int pc = m0 + r, o = n0 + c;
+          if (pc < npc && o < n_out) pre[pc * ldo + o] = v + (pc % C == 0 ? b[o] : T(0));
+        });
+  }
+}
+
+// the tangent of mfma_forward: zd[pc][o] = sum_i W[o][i] hd[pc][i] + Wd[o][i] h[pc][i] (+ bd[o])
+template <typename T>
+__device__ __forceinline__ void mfma_forward_tangent(const T* Ws, const T* Wd, int n_in, int n_out, const T* hb,
+                                                     const T* hd, int nm, int npc, int C, const T* __restrict__ bd,
+                                                     T* zd) {
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tm = (npc + 15) / 16, tn = (n_out + 15) / 16;
+  for (int t = wid; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    auto w_of = [&](const T* Wm) {
+      return [=](int k, int c) { const int o = n0 + c; return (o < n_out && k < n_in) ? Wm[o * (n_in + 1) + k] : T(0); };
+    };
+    auto h_of = [&](const T* Hm) {
+      return [=](int r, int k) { const int pc = m0 + r; return (pc < npc && k < n_in) ? Hm[pc * nm + k] : T(0); };
+    };
+    mfma_tile2<T>(n_in, h_of(hd), w_of(Ws), h_of(hb), w_of(Wd), [&](int r, int c, T v) {
+      const int pc = m0 + r, o = n0 + c;
+      if (pc < npc && o < n_out) zd[pc * nm + o] = v + (pc % C == 0 ? bd[o] : T(0));
+    });
+  }
+}
+
+// ab[pc][i] = sum_o W[o][i] zb[pc][o] for pc < npc, i < n_in (the adjoint product W^T z)
+template <typename T>
+__device__ __forceinline__ void mfma_adjoint(const T* Ws, int n_in, int n_out, const T* zb, int nm, int npc, T* ab) {
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int tm = (npc + 15) / 16, tn = (n_in + 15) / 16;
+  for (int t = wid; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    mfma_tile<T>(
+        n_out, [&](int r, int k) { const int pc = m0 + r; return (pc < npc && k < n_out) ? zb[pc * nm + k] : T(0); },
+        [&](int k, int c) { const int i = n0 + c; return (i < n_in && k < n_out) ? Ws[k * (n_in + 1) + i] : T(0); },
+        [&](int r, int c, T v) {
+          const int pc = m0 + r, i = n0 + c;
+          if (pc < npc && i < n_in) ab[pc * nm + i] = v;
+        });
+  }
+}
+
 // input channels of layer 0 for the tile
 template <typename T>
 __device__ void input_channels(const NetDesc& net, const T* X, int64_t row0, int64_t N, int TP, T* hb) {
-  const int d = net.d, C = net.C, nm = net.max_width;
+  const int d = net.d, C = net.C, nm = chan_pitch(net);
   for (int e = threadIdx.x; e < TP * C * d; e += blockDim.x) {
     int i = e % d, pc = e / d, c = pc % C, p = pc / C;
     int64_t row = row0 + p;
@@ -94,7 +206,7 @@ __device__ void input_channels(const NetDesc& net, const T* X, int64_t row0, int
 // post-activation channels of hidden layer `l` (affine index) from its pre-activations
 template <typename T>
 __device__ void activate(const NetDesc& net, const T* pre_l, int n, int TP, T* hb) {
-  const int C = net.C, nS = net.nS, nm = net.max_width;
+  const int C = net.C, nS = net.nS, nm = chan_pitch(net);
   for (int e = threadIdx.x; e < TP * n; e += blockDim.x) {
     int p = e / n, i = e - p * n;
     const T* z = pre_l + (int64_t)p * C * n;
@@ -129,10 +241,11 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
                               const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g,
                               const int8_t* __restrict__ kind, T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ,
                               int TP, int64_t tile_first, int64_t tile_step, const double* __restrict__ wv,
-                              int64_t wv_stride, bool write_r, double* loss_slot, T* part_row, double* tsq_slot) {
+                              int64_t wv_stride, bool write_r, double* loss_slot, T* part_row, double* tsq_slot,
+                              bool acc_in_lds = false) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
+  const int C = net.C, nS = net.nS, nm = chan_pitch(net), L = net.n_layers;
   const int64_t ntiles = (N + TP - 1) / TP;
   double tsq_acc = 0.0;
   bool first = true;
@@ -164,15 +277,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     __syncthreads();
     T* pre_l = s.pre + pre_offset(net, l, TP);
     const T* b = theta + net.boff[l];
-    for (int e = threadIdx.x; e < TP * C * n_out; e += blockDim.x) {
-      int o = e % n_out, pc = e / n_out;
-      const T* wrow = s.Ws + o * (n_in + 1);
-      const T* h = s.hb + pc * nm;
-      T acc = 0;
-      for (int i = 0; i < n_in; ++i) acc += wrow[i] * h[i];
-      if (pc % C == 0) acc += b[o];
-      pre_l[(int64_t)pc * n_out + o] = acc;
-    }
+    mfma_forward(s.Ws, n_in, n_out, s.hb, nm, TP * C, C, b, pre_l);
     __syncthreads();
     activate(net, pre_l, n_out, TP, s.hb);
   }
@@ -233,9 +338,11 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     if (J == nullptr) return;
   }
   __syncthreads();
-  // accumulate into this workgroup's partial row (kVjp); a thread always owns the same entries
+  // accumulate into this workgroup's partial row (kVjp), in LDS past the tile buffers when it fits
+  // there (written out once after the last tile); a thread always owns the same entries
+  T* acc_lds = (MODE == kVjp && acc_in_lds) ? smem + lds_elems(net, TP) : nullptr;
   auto put = [&](int64_t idx, T v) {
-    T* q = part_row + idx;
+    T* q = acc_lds != nullptr ? acc_lds + idx : part_row + idx;
     *q = first ? v : *q + v;
   };
   (void)put;
@@ -268,7 +375,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
       for (int p = 0; p < nvalid; ++p) acc += s.ub[p * kMaxChan];
       put(net.boff[L - 1], acc);
     }
-    if (first)
+    if (first && acc_lds == nullptr)
       for (int64_t j = P + threadIdx.x; j < ldJ; j += blockDim.x) part_row[j] = 0;
   }
   // adjoint of the last hidden layer outputs: ab = W_out^T seed
@@ -318,50 +425,45 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     // Jacobian segments of W_l and b_l
     const int64_t wo = net.woff[l], bo = net.boff[l];
     const int nel = n_out * n_in;
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int tmo = (n_out + 15) / 16, tni = (n_in + 15) / 16;
     if constexpr (MODE == kVjp) {
-      for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-        const int o = e / n_in, i = e - o * n_in;
-        T acc = 0;
-        for (int p = 0; p < nvalid; ++p) {
-          const T* zbp = s.zb + (int64_t)p * C * nm;
-          const T* hbp = s.hb + (int64_t)p * C * nm;
-          for (int c = 0; c < C; ++c) acc += zbp[c * nm + o] * hbp[c * nm + i];
-        }
-        put(wo + e, acc);
+      // dW[o][i] = sum over the tile's points and channels of zbar[pc][o] h[pc][i]: one contraction
+      // with K = nvalid C (seeds of rows past N are zero)
+      const int kk = nvalid * C;
+      for (int t = wid; t < tmo * tni; t += nw) {
+        const int o0 = (t / tni) * 16, i0 = (t % tni) * 16;
+        mfma_tile<T>(
+            kk, [&](int r, int k) { const int o = o0 + r; return (o < n_out && k < kk) ? s.zb[k * nm + o] : T(0); },
+            [&](int k, int c) { const int i = i0 + c; return (i < n_in && k < kk) ? s.hb[k * nm + i] : T(0); },
+            [&](int r, int c, T v) {
+              const int o = o0 + r, i = i0 + c;
+              if (o < n_out && i < n_in) put(wo + o * n_in + i, v);
+            });
       }
+      (void)nel;
       for (int o = threadIdx.x; o < n_out; o += blockDim.x) {
         T acc = 0;
         for (int p = 0; p < nvalid; ++p) acc += s.zb[(int64_t)p * C * nm + o];
         put(bo + o, acc);
       }
-    } else if ((int)blockDim.x % n_in == 0) {
-      const int i = threadIdx.x % n_in, ostep = blockDim.x / n_in, o0 = threadIdx.x / n_in;
-      for (int p = 0; p < nvalid; ++p) {
-        T hreg[kMaxChan];
-#pragma unroll
-        for (int c = 0; c < kMaxChan; ++c) hreg[c] = c < C ? s.hb[(p * C + c) * nm + i] : T(0);
-        T* Jrow = J + (row0 + p) * ldJ + wo;
-        const T* zbp = s.zb + (int64_t)p * C * nm;
-        for (int o = o0; o < n_out; o += ostep) {
-          T acc = 0;
-#pragma unroll
-          for (int c = 0; c < kMaxChan; ++c)
-            if (c < C) acc += zbp[c * nm + o] * hreg[c];
-          Jrow[o * n_in + i] = acc;
-        }
-      }
     } else {
-      for (int p = 0; p < nvalid; ++p) {
-        T* Jrow = J + (row0 + p) * ldJ + wo;
+      // per point p: the W_l block of J_p is zbar_p (n_out x C) times h_p^T (C x n_in), K = C
+      for (int t = wid; t < nvalid * tmo * tni; t += nw) {
+        const int p = t / (tmo * tni), tt = t - p * (tmo * tni);
+        const int o0 = (tt / tni) * 16, i0 = (tt % tni) * 16;
         const T* zbp = s.zb + (int64_t)p * C * nm;
         const T* hbp = s.hb + (int64_t)p * C * nm;
-        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
-          int o = e / n_in, i = e - o * n_in;
-          T acc = 0;
-          for (int c = 0; c < C; ++c) acc += zbp[c * nm + o] * hbp[c * nm + i];
-          Jrow[e] = acc;
-        }
+        T* Jrow = J + (row0 + p) * ldJ + wo;
+        mfma_tile<T>(
+            C, [&](int r, int k) { const int o = o0 + r; return (o < n_out && k < C) ? zbp[k * nm + o] : T(0); },
+            [&](int k, int c) { const int i = i0 + c; return (i < n_in && k < C) ? hbp[k * nm + i] : T(0); },
+            [&](int r, int c, T v) {
+              const int o = o0 + r, i = i0 + c;
+              if (o < n_out && i < n_in) Jrow[o * n_in + i] = v;
+            });
       }
+      (void)nel;
     }
     if constexpr (MODE == kJacobian) {
       for (int p = 0; p < nvalid; ++p) {
@@ -374,13 +476,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     __syncthreads();
     load_weights(net, theta, l, s.Ws);
     __syncthreads();
-    for (int e = threadIdx.x; e < TP * C * n_in; e += blockDim.x) {
-      int i = e % n_in, pc = e / n_in;
-      const T* zc = s.zb + pc * nm;
-      T acc = 0;
-      for (int o = 0; o < n_out; ++o) acc += s.Ws[o * (n_in + 1) + i] * zc[o];
-      s.ab[pc * nm + i] = acc;
-    }
+    mfma_adjoint(s.Ws, n_in, n_out, s.zb, nm, TP * C, s.ab);
   }
   __syncthreads();
   }  // tile loop
@@ -388,6 +484,10 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     __shared__ double red_t[4];
     const double t = block_sum(tsq_acc, red_t);
     if (threadIdx.x == 0 && tsq_slot != nullptr) *tsq_slot = t;
+    if (acc_in_lds) {
+      const T* acc = smem + lds_elems(net, TP);
+      for (int64_t j = threadIdx.x; j < ldJ; j += blockDim.x) part_row[j] = j < net.P ? acc[j] : T(0);
+    }
   }
 }
 
@@ -396,7 +496,7 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
     NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
     const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
     T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
-    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out) {
+    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out, int acc_in_lds) {
   const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
   const int64_t ntiles = (N + TP - 1) / TP;
   const int64_t tile_step = MODE == kVjp ? (int64_t)gridDim.x : ntiles;
@@ -405,7 +505,7 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
   T* part_row = MODE == kVjp ? J + (int64_t)blockIdx.x * ldJ : nullptr;
   double* tsq_slot = tsq_out != nullptr ? tsq_out + blockIdx.x : nullptr;
   residual_body<T, MODE>(net, theta, N, X, w, f, g, kind, r_w, J, ldJ, TP, blockIdx.x, tile_step, wv, wv_stride,
-                         blockIdx.y == 0, loss_slot, part_row, tsq_slot);
+                         blockIdx.y == 0, loss_slot, part_row, tsq_slot, acc_in_lds != 0);
 }
 
 // Several problems in one launch: work item i is tile (i - first_tile[q]) of the problem q whose
@@ -443,7 +543,7 @@ __global__ __launch_bounds__(256) void jvp_kernel(NetDesc net, const T* __restri
                                                   TO* __restrict__ out, int64_t ldo, int64_t cs, int TP) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const int C = net.C, nS = net.nS, nm = net.max_width, L = net.n_layers;
+  const int C = net.C, nS = net.nS, nm = chan_pitch(net), L = net.n_layers;
   const int64_t row0 = (int64_t)blockIdx.x * TP;
   const T* dth = U + (int64_t)blockIdx.y * ldU;
   size_t ws = 0;
@@ -470,24 +570,8 @@ __global__ __launch_bounds__(256) void jvp_kernel(NetDesc net, const T* __restri
     __syncthreads();
     const T* b = theta + net.boff[l];
     const T* bd = dth + net.boff[l];
-    for (int e = threadIdx.x; e < TP * C * n_out; e += blockDim.x) {
-      const int o = e % n_out, pc = e / n_out;
-      const T* wr = Ws + o * (n_in + 1);
-      const T* wdr = Wd + o * (n_in + 1);
-      const T* h = hb + pc * nm;
-      const T* hdt = hd + pc * nm;
-      T acc = 0, dacc = 0;
-      for (int i = 0; i < n_in; ++i) {
-        acc += wr[i] * h[i];
-        dacc += wr[i] * hdt[i] + wdr[i] * h[i];
-      }
-      if (pc % C == 0) {
-        acc += b[o];
-        dacc += bd[o];
-      }
-      zb[pc * nm + o] = acc;
-      zd[pc * nm + o] = dacc;
-    }
+    mfma_forward(Ws, n_in, n_out, hb, nm, TP * C, C, b, zb, nm);
+    mfma_forward_tangent(Ws, Wd, n_in, n_out, hb, hd, nm, TP * C, C, bd, zd);
     __syncthreads();
     for (int e = threadIdx.x; e < TP * n_out; e += blockDim.x) {
       const int p = e / n_out, o = e - p * n_out;
@@ -556,7 +640,7 @@ __host__ inline size_t jvp_lds_elems(const NetDesc& net, int TP) {
     size_t s = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
     ws = s > ws ? s : ws;
   }
-  return 2 * ws + 4 * (size_t)TP * net.C * net.max_width + (size_t)TP * kMaxChan;
+  return 2 * ws + 4 * (size_t)TP * net.C * chan_pitch(net) + (size_t)TP * kMaxChan;
 }
 
 // sum of n_per partials for each of n_sets sets, scaled: out[s] = scale * sum_i partial[s*n_per + i]
@@ -628,13 +712,13 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const double*)theta, theta_stride, N, (const double*)X,
                        (const double*)w, (const double*)f, (const double*)g, kind, (double*)r_w, (double*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0);
   } else {
     auto k = residual_jacobian_kernel<float, kJacobian>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const float*)theta, theta_stride, N, (const float*)X,
                        (const float*)w, (const float*)f, (const float*)g, kind, (float*)r_w, (float*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0);
   }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
@@ -658,18 +742,22 @@ ngd_status launch_vjp(const NetDesc& net, int dtype, const void* theta, int64_t 
     set_error("vjp: workgroup count out of range");
     return NGD_ERR_INVALID;
   }
+  // the workgroup's P accumulators in LDS too when they fit beside the tile buffers
+  const size_t with_acc = (bytes + 15) / 16 * 16 + (size_t)net.P * elem;
+  const int acc_in_lds = with_acc <= 150 * 1024 && bytes % elem == 0 ? 1 : 0;
+  if (acc_in_lds) bytes = (size_t)(lds_elems(net, tp) + net.P) * elem;
   if (dtype == NGD_F64) {
     auto k = residual_jacobian_kernel<double, kVjp>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const double*)theta, (int64_t)0, N, (const double*)X,
                        (const double*)w, (const double*)f, (const double*)g, kind, nullptr, (double*)partial, ld,
-                       nullptr, tp, wv, wv_stride, tsq);
+                       nullptr, tp, wv, wv_stride, tsq, acc_in_lds);
   } else {
     auto k = residual_jacobian_kernel<float, kVjp>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const float*)theta, (int64_t)0, N, (const float*)X,
                        (const float*)w, (const float*)f, (const float*)g, kind, nullptr, (float*)partial, ld, nullptr,
-                       tp, wv, wv_stride, tsq);
+                       tp, wv, wv_stride, tsq, acc_in_lds);
   }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;

@@ -17,7 +17,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .api import Problem, Recompute
+from .api import Batch, Problem, Recompute
 
 EPS = {"f64": 2.0 ** -52, "f32": 2.0 ** -23}
 
@@ -80,3 +80,43 @@ class NGD:
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
         return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
+
+
+class BatchNGD:
+    """NGD (Alg. 1) on many independent problems at once: residuals and Jacobians of all problems in
+    one batched launch, each problem's own Nystrom sketch (Alg. 4/6, its own ell) and damping, one
+    batched PCG solve for all, and each problem's Armijo step."""
+
+    def __init__(self, datas, thetas0, *, solver="nystrom", rtol=1e-6, gamma=10.0, seed=0):
+        self.batch = Batch(datas, dtype="f32")
+        self.solver = solver
+        self.rtol = rtol
+        self.gamma = gamma
+        self.seed = seed
+        self.eps = EPS["f32"]
+        self.ells = [min(int(d.ell), m.P) for d, m in zip(datas, self.batch.members)]
+        self.thetas = [m.theta(t) for m, t in zip(self.batch.members, thetas0)]
+        self.Js = [m.new_jacobian() for m in self.batch.members]
+        self.k = 0
+
+    def step(self):
+        b = self.batch
+        _, grads, losses = b.residual_jacobian(self.thetas, self.Js)
+        L0 = torch.cat(losses).cpu().numpy()
+        pcs = None
+        if self.solver == "nystrom":
+            pcs = [m.nystrom_sketch(J, ell, seed=self.seed, counter=self.k, sketch_dtype="f32", want_info=True)
+                   for m, J, ell in zip(b.members, self.Js, self.ells)]
+            lam1 = [p.info["lam1"] for p in pcs]
+        else:
+            lam1 = [m.power_lambda_max(J, torch.ones(m.P, dtype=torch.float64, device=m.device), 4)
+                    for m, J in zip(b.members, self.Js)]
+        mus = [max(self.gamma * self.eps * l1, 1e-4 * float(l0) ** 2) for l1, l0 in zip(lam1, L0)]
+        maxit = 1000 if self.solver == "nystrom" else max(m.P for m in b.members)
+        outs = b.pcg_solve(self.Js, grads, mus, pcs, rtol=self.rtol, maxit=maxit)
+        news = []
+        for m, th, o, g, l0 in zip(b.members, self.thetas, outs, grads, L0):
+            _, alpha, l1 = m.line_search(th, o.d, g, float(l0), theta_out=th)
+            news.append(l1)
+        self.k += 1
+        return L0, np.array(news), outs

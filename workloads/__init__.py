@@ -27,7 +27,7 @@ PDE_POISSON = 0     # interior res = Laplace(u) + f      (-Laplace(u) = f)
 PDE_HEAT = 1        # interior res = u_t - Laplace_x(u) - f (last input coordinate is time)
 
 # purposes for independent random streams
-_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE = range(6)
+_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE, _P_SHAPES = range(7)
 
 
 @dataclasses.dataclass
@@ -214,6 +214,26 @@ def config(name: str, seed: int = 0) -> Problem:
     if name == "c4":
         return dataclasses.replace(heat2d(seed=seed), recompute=True)
     raise KeyError(name)
+
+
+def batch_instances(n=32, seed=0, widths=(32, 48, 64, 96), depths=(2, 3, 4), n_min=1024, n_max=8192,
+                    ells=(50, 100, 200, 400), dims=(2, 3)) -> list:
+    """The batched workload: n independent Poisson problems on [0,1]^d (d from `dims`) with
+    u* = prod sin(pi x_i); per problem a hidden width from `widths` (all hidden layers alike), a depth
+    from `depths`, N_int uniform in [n_min, n_max] plus N_int // 8 boundary points, and ell from `ells`,
+    all drawn from one seeded stream; FP32. Problem i uses data seed 1000 * seed + i."""
+    rng = _rng(seed, _P_SHAPES)
+    out = []
+    for i in range(n):
+        d = int(rng.choice(dims))
+        wdt = int(rng.choice(widths))
+        depth = int(rng.choice(depths))
+        n_int = int(rng.integers(n_min, n_max + 1))
+        ell = int(rng.choice(ells))
+        prob = poisson_random(d=d, widths=(d,) + (wdt,) * depth + (1,), n_interior=n_int, n_boundary=n_int // 8,
+                              seed=1000 * seed + i, dtype="f32", ell=ell, sketch_dtype="f32")
+        out.append(dataclasses.replace(prob, name=f"batch{i}"))
+    return out
 
 
 def small_problem(pde=PDE_POISSON, d=2, widths=(2, 8, 8, 1), n_interior=24, n_boundary=12, seed=0,
