@@ -155,12 +155,6 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
     }                                 \
   } while (0)
 
-#define NGD_TRY(expr)                 \
-  do {                                \
-    ngd_status st_ = (expr);          \
-    if (st_ != NGD_OK) return st_;    \
-  } while (0)
-
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 ngd_status check_op(const ngd_problem* h, const ngd_operator* op) {

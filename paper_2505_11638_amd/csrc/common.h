@@ -61,6 +61,13 @@ void set_error(const std::string& msg);
     }                                                                            \
   } while (0)
 
+// propagate a non-OK status
+#define NGD_TRY(expr)                 \
+  do {                                \
+    ngd_status st_ = (expr);          \
+    if (st_ != NGD_OK) return st_;    \
+  } while (0)
+
 // ---- device helpers -----------------------------------------------------------------------------
 
 template <typename T>

@@ -28,7 +28,8 @@ struct TriArgs {
   double* e;       // off-diagonal of T (n-1)
   double* V;       // Householder vectors, row k = v_k (support k+1..n-1, v_k[k+1] = 1)
   double* tau;     // Householder scalars
-  double* p;       // n: p = tau A v of the current step
+  double* p;       // 2 n: p = tau A v of the current step (double-buffered by step parity, so that
+                   // a workgroup that runs ahead never overwrites values another still has to read)
   unsigned* flags; // one barrier flag per workgroup
   int* err;
 };
@@ -140,14 +141,14 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
         if (publish) next_pivot[j] = x;
       }
       acc = wave_sum(acc);
-      if (lane == 0) a.p[i] = tau * acc;
+      if (lane == 0) a.p[(int64_t)(k & 1) * n + i] = tau * acc;
     }
     if (!grid_sync(a.flags, (unsigned)k, a.err)) return;
     // p and the next pivot row are read together; w = p - (tau/2)(p . v) v is kept by every
     // workgroup as the pending update
     double pv = 0.0;
     for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double pj = a.p[j];
+      const double pj = a.p[(int64_t)(k & 1) * n + j];
       const double nx = next_pivot[j];
       wprev[j] = pj;
       pivl[j] = nx;
@@ -183,6 +184,236 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
         a.d[0] = row[0];
       }
     }
+  }
+}
+
+// ---- register-resident tridiagonalisation (n <= kTrMaxN) ----
+// The same Householder recurrence with the trailing matrix held in registers: 8 waves per
+// workgroup, each owning up to four of the workgroup's rows, lane l holding columns l, l + 64, ...
+// Only the per-column vectors go through LDS (thread t handles columns t and t + 512), so few
+// workgroups (about n / 32) suffice and the grid barrier, whose latency bounds this kernel, is as
+// cheap as it gets. The vectors the workgroups exchange (p and the next pivot row) are written and
+// read with device-coherent (sc1) accesses, double-buffered by step parity, so the barrier needs no
+// cache write-back or invalidate: each thread waits for its own stores to complete before the
+// workgroup publishes its flag.
+constexpr int kTrWaves = 8;
+constexpr int kTrThreads = 64 * kTrWaves;
+constexpr int kTrRows = 4;  // rows per wave
+constexpr int kTrMaxN = 1024;
+constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column vector entries per thread
+
+__device__ __forceinline__ void st_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coherent(double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier number `epoch` for data exchanged only through st_coherent / ld_coherent. The flags of up
+// to 64 workgroups are polled by wave 0 (one per lane). The wait is bounded; on timeout the error
+// word is raised and false is returned to the whole workgroup.
+__device__ bool grid_sync_coherent(unsigned* flags, unsigned epoch, int* err, int* timed_out) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const unsigned target = epoch + 1u;
+    if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (true) {
+      const int g = threadIdx.x;
+      const bool ok = g >= (int)gridDim.x ||
+                      __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+      if (__all(ok)) break;
+      if (++spins > (1L << 24)) {  // seconds: give up instead of hanging
+        if (threadIdx.x == 0) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          *timed_out = 1;
+        }
+        break;
+      }
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  return *timed_out == 0;
+}
+
+template <int QN>
+__global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
+  // the three per-column vectors in one array, so that one base address serves all of them
+  __shared__ double vecs[3 * kTrMaxN];
+  double* vprev = vecs;
+  double* wprev = vecs + kTrMaxN;
+  double* vcur = vecs + 2 * kTrMaxN;
+  __shared__ double red[kTrWaves];
+  __shared__ int timed_out;
+  const int n = a.n, G = gridDim.x, g = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) timed_out = 0;
+  double rows[kTrRows][QN];
+#pragma unroll
+  for (int s = 0; s < kTrRows; ++s) {
+    const int i = g + G * (wid + kTrWaves * s);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      const int c = lane + 64 * q;
+      rows[s][q] = (i < n && c < n) ? a.A0[(int64_t)i * n + c] : 0.0;
+    }
+  }
+  // per-column state of columns j_t = threadIdx.x + kTrThreads t: pivot row entry (row 0, nothing
+  // pending) and the pending rank-2 update
+  double piv[kTrCols], vp[kTrCols], wp[kTrCols], vj[kTrCols];
+#pragma unroll
+  for (int t = 0; t < kTrCols; ++t) {
+    const int j = threadIdx.x + kTrThreads * t;
+    piv[t] = j < n ? a.A0[j] : 0.0;
+    vp[t] = wp[t] = 0.0;
+    vprev[j] = 0.0;
+    wprev[j] = 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    // column k of A^(k) below the diagonal: the pivot row with the pending update applied
+    const double vk = vprev[k], wk = wprev[k];
+    double x[kTrCols], tail = 0.0;
+#pragma unroll
+    for (int t = 0; t < kTrCols; ++t) {
+      const int j = threadIdx.x + kTrThreads * t;
+      x[t] = (j > k && j < n) ? piv[t] - vk * wp[t] - wk * vp[t] : 0.0;
+      vcur[j] = x[t];
+      if (j > k + 1) tail += x[t] * x[t];
+    }
+    tail = block_sum(tail, red);
+    const double alpha = vcur[k + 1];
+    double tau, beta, scale;
+    if (tail == 0.0) {
+      tau = 0.0;
+      beta = alpha;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + tail);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read vcur[k + 1]
+#pragma unroll
+    for (int t = 0; t < kTrCols; ++t) {
+      const int j = threadIdx.x + kTrThreads * t;
+      vj[t] = j == k + 1 ? 1.0 : (j > k + 1 ? x[t] * scale : 0.0);
+      vcur[j] = vj[t];
+      if (g == 0) {
+        if (j == k) a.d[k] = piv[t] - 2.0 * vk * wk;
+        if (j < n) a.V[(int64_t)k * n + j] = vj[t];
+      }
+    }
+    if (g == 0 && threadIdx.x == 0) {
+      a.e[k] = beta;
+      a.tau[k] = tau;
+    }
+    __syncthreads();
+    // owned rows i > k: the pending update in place, p_i = tau * row . v. The column vectors are
+    // read from LDS four columns at a time for all rows (one wait per chunk); columns c <= k and
+    // c >= n need no predicate: v is zero there, and the entries they change are never read again.
+    double* next_pivot = a.A1 + (int64_t)((k + 1) & 1) * n;
+    double* pk = a.p + (int64_t)(k & 1) * n;
+    double vi[kTrRows], wi[kTrRows], acc[kTrRows];
+    bool live[kTrRows];
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) {
+      const int i = g + G * (wid + kTrWaves * s);
+      live[s] = i > k && i < n;
+      vi[s] = live[s] ? vprev[i] : 0.0;
+      wi[s] = live[s] ? wprev[i] : 0.0;
+      acc[s] = 0.0;
+    }
+#pragma unroll
+    for (int q0 = 0; q0 < QN; q0 += 4) {
+      double wq[4], vq[4], uq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = lane + 64 * (q0 + u);
+        if (q0 + u < QN) {
+          wq[u] = wprev[c];
+          vq[u] = vprev[c];
+          uq[u] = vcur[c];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < kTrRows; ++s) {
+        if (!live[s]) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (q0 + u < QN) {
+            const double y = rows[s][q0 + u] - vi[s] * wq[u] - wi[s] * vq[u];
+            rows[s][q0 + u] = y;
+            acc[s] += y * uq[u];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) acc[s] = wave_sum(acc[s]);
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) {
+      const int i = g + G * (wid + kTrWaves * s);
+      if (!live[s]) continue;
+      if (lane == 0) st_coherent(pk + i, tau * acc[s]);
+      if (i == k + 1) {  // the next pivot row, updated
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+          const int c = lane + 64 * q;
+          if (c > k && c < n) st_coherent(next_pivot + c, rows[s][q]);
+        }
+      }
+    }
+    if (!grid_sync_coherent(a.flags, (unsigned)k, a.err, &timed_out)) return;
+    // p and the next pivot row; w = p - (tau/2)(p . v) v becomes the pending update
+    double pj[kTrCols], pvs = 0.0;
+#pragma unroll
+    for (int t = 0; t < kTrCols; ++t) {
+      const int j = threadIdx.x + kTrThreads * t;
+      pj[t] = 0.0;
+      if (j > k && j < n) {
+        pj[t] = ld_coherent(pk + j);
+        piv[t] = ld_coherent(next_pivot + j);
+      }
+      pvs += pj[t] * vj[t];
+    }
+    const double c = 0.5 * tau * block_sum(pvs, red);
+#pragma unroll
+    for (int t = 0; t < kTrCols; ++t) {
+      const int j = threadIdx.x + kTrThreads * t;
+      const bool live = j > k && j < n;
+      wp[t] = live ? pj[t] - c * vj[t] : 0.0;
+      vp[t] = live ? vj[t] : 0.0;
+      vprev[j] = vp[t];
+      wprev[j] = wp[t];
+    }
+    __syncthreads();
+  }
+  // last 2 x 2 (or 1 x 1) block: rows n-2 (the pivot) and n-1 with the pending update
+  const int m = n >= 2 ? n - 2 : 0;
+#pragma unroll
+  for (int t = 0; t < kTrCols; ++t) {
+    const int j = threadIdx.x + kTrThreads * t;
+    if (g != 0) break;
+    if (n == 1) {
+      if (j == 0) a.d[0] = piv[t];
+    } else {
+      if (j == m) a.d[m] = piv[t] - 2.0 * vprev[m] * wprev[m];
+      if (j == m + 1) a.e[m] = piv[t] - vprev[m] * wprev[m + 1] - wprev[m] * vprev[m + 1];
+    }
+  }
+  if (n == 1) return;
+#pragma unroll
+  for (int s = 0; s < kTrRows; ++s) {
+    const int i = g + G * (wid + kTrWaves * s);
+    if (i != m + 1) continue;
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      if (lane + 64 * q == m + 1) a.d[m + 1] = rows[s][q] - 2.0 * vprev[m + 1] * wprev[m + 1];
   }
 }
 
@@ -523,8 +754,134 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
   }
 }
 
-// Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau, p, e2,
-// lam (n each), tnorm (8), the per-workgroup barrier flags (256 unsigned) and the error word, then
+// The same back-transformation on the FP64 matrix cores, for n <= kBtMaxN. A workgroup owns 16
+// columns of Z, held in registers as 16 x 16 accumulator tiles (tile t = rows 16t .. 16t+15, tiles
+// dealt round-robin to the waves). Per block of kWy reflectors, staged in LDS:
+//   W = Y^T Z   (each wave over its tiles, partial sums reduced through LDS),
+//   S = T W     (every wave, redundantly: four MFMAs),
+//   Z -= Y S    (each wave on its tiles).
+// In v_mfma_f64_16x16x4f64 lane l supplies A(l % 16, k + l / 16) and B(k + l / 16, l % 16) and
+// holds C(l / 16 + 4 r, l % 16) in accumulator element r; element r of a tile is therefore exactly
+// the B operand of the K-step that covers rows 4 r .. 4 r + 3 of it, so Z and S are fed to the
+// next product without any data movement. Tiles wholly at or above the block's first reflector
+// row are left alone (Y is zero there).
+typedef double bt_d4 __attribute__((ext_vector_type(4)));
+constexpr int kBtWaves = 16;
+constexpr int kBtTiles = 4;  // tiles per wave
+constexpr int kBtMaxN = 16 * kBtWaves * kBtTiles;
+static_assert(kBtMaxN == 64 * kBtWaves, "one reflector column per thread");
+
+__device__ __forceinline__ bt_d4 mfma64(double a, double b, bt_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
+    const double* __restrict__ Z, const double* __restrict__ V, const double* __restrict__ Tall,
+    const double* __restrict__ lam_asc, int n, const double* __restrict__ tnorm, double drop_rel,
+    double* __restrict__ evals_desc, double* __restrict__ evec_rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nt = (n + 15) / 16;
+  const int ldy = nt * 16 + 1;  // odd pitch: the 16 reflector rows fall in distinct LDS banks
+  double* Ys = reinterpret_cast<double*>(smem_raw);  // kWy x ldy
+  double* Wp = Ys + (size_t)kWy * ldy;              // kBtWaves x 256 partial W
+  __shared__ double Ts[kWy * kWy];
+  __shared__ double Ws[256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int c0 = blockIdx.x * 16;
+  const int col = c0 + lr;
+
+  bt_d4 acc[kBtTiles];
+#pragma unroll
+  for (int i = 0; i < kBtTiles; ++i) {
+    const int t = wid + i * kBtWaves;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + lq + 4 * r;
+      acc[i][r] = (t < nt && row < n && col < n) ? Z[(int64_t)row * n + col] : 0.0;
+    }
+  }
+  const int nref = n - 2;
+  const int nblk = nref > 0 ? (nref + kWy - 1) / kWy : 0;
+  // a block's reflectors and T factor are fetched into registers one block ahead, so that their
+  // loads are in flight while the previous block is applied
+  // thread t fetches column t of the block's kWy reflectors (kBtMaxN = blockDim.x >= n)
+  const int jt = threadIdx.x;
+  double ypf[kWy], tpf = 0.0;
+  auto prefetch = [&](int b) {
+    const int k0 = b * kWy;
+    const int m = min(kWy, nref - k0);
+#pragma unroll
+    for (int u = 0; u < kWy; ++u) ypf[u] = (u < m && jt < n) ? V[(int64_t)(k0 + u) * n + jt] : 0.0;
+    if (threadIdx.x < kWy * kWy) tpf = Tall[(int64_t)b * kWy * kWy + threadIdx.x];
+  };
+  if (nblk > 0) prefetch(nblk - 1);
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * kWy;
+    __syncthreads();
+    if (jt < nt * 16) {
+#pragma unroll
+      for (int u = 0; u < kWy; ++u) Ys[u * ldy + jt] = ypf[u];
+    }
+    if (threadIdx.x < kWy * kWy) Ts[threadIdx.x] = tpf;
+    __syncthreads();
+    if (b > 0) prefetch(b - 1);
+    // W = Y^T Z over this wave's tiles (rows <= k0 of Y are zero)
+    bt_d4 w = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < kBtTiles; ++i) {
+      const int t = wid + i * kBtWaves;
+      if (t < nt && 16 * t + 15 > k0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w = mfma64(Ys[lr * ldy + 16 * t + 4 * r + lq], acc[i][r], w);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wp[wid * 256 + (lq + 4 * r) * 16 + lr] = w[r];
+    __syncthreads();
+    // W summed over the waves in a fixed order, each entry by one thread
+    if (threadIdx.x < 256) {
+      double wsum = 0.0;
+      for (int q = 0; q < kBtWaves; ++q) wsum += Wp[q * 256 + threadIdx.x];
+      Ws[threadIdx.x] = wsum;
+    }
+    __syncthreads();
+    // S = T W
+    bt_d4 sacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a = 4 * s + lq;
+      sacc = mfma64(Ts[lr * kWy + a], Ws[a * 16 + lr], sacc);
+    }
+    // Z -= Y S
+#pragma unroll
+    for (int i = 0; i < kBtTiles; ++i) {
+      const int t = wid + i * kBtWaves;
+      if (t < nt && 16 * t + 15 > k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[i] = mfma64(-Ys[(4 * s + lq) * ldy + 16 * t + lr], sacc[s], acc[i]);
+      }
+    }
+  }
+  // eigenvector rows in descending eigenvalue order; dropped pairs as (0, zero vector)
+  const double drop = drop_rel * (*tnorm);
+  const bool keep = col < n && lam_asc[col] >= drop;
+  if (wid == 0 && lq == 0 && col < n) evals_desc[n - 1 - col] = keep ? lam_asc[col] : 0.0;
+  if (col < n) {
+#pragma unroll
+    for (int i = 0; i < kBtTiles; ++i) {
+      const int t = wid + i * kBtWaves;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * t + lq + 4 * r;
+        if (t < nt && row < n) evec_rows[(int64_t)(n - 1 - col) * n + row] = keep ? acc[i][r] : 0.0;
+      }
+    }
+  }
+}
+
+// Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau (n each),
+// p (2 n), e2, lam (n each), tnorm (8), the per-workgroup barrier flags (256 unsigned) and the error word, then
 // the T factors of the reflector blocks.
 struct EigWs {
   double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *pbuf, *e2, *lam, *tnorm, *Tall;
@@ -542,7 +899,7 @@ struct EigWs {
     evec = dvec + n;
     tau = evec + n;
     pbuf = tau + n;
-    e2 = pbuf + n;
+    e2 = pbuf + 2 * n;
     lam = e2 + n;
     tnorm = lam + n;
     flags = reinterpret_cast<unsigned*>(tnorm + 8);
@@ -552,6 +909,71 @@ struct EigWs {
     bytes = (size_t)((Tall + nblk * kWy * kWy) - w) * sizeof(double);
   }
 };
+
+// The grid barriers need every workgroup resident at once: the grids below are far smaller than
+// the device's CU count, and the occupancy is checked; every barrier wait is bounded (it raises the
+// error word instead of spinning forever).
+ngd_status check_coresident(const void* kernel, int threads, size_t lds, int blocks) {
+  int dev = 0, cus = 0, per_cu = 0;
+  NGD_HIP_TRY(hipGetDevice(&dev));
+  NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  NGD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds));
+  if ((int64_t)cus * per_cu < blocks) {
+    set_error("tridiagonalisation grid cannot be co-resident");
+    return NGD_ERR_HIP;
+  }
+  return NGD_OK;
+}
+
+template <int QN>
+ngd_status launch_tridiag_reg(const TriArgs& ta, hipStream_t s) {
+  // as few workgroups as hold the rows (at most kTrWaves * kTrRows each): the barrier's cost grows
+  // with the number of workgroups
+  const int per = kTrWaves * kTrRows;
+  const int blocks = (ta.n + per - 1) / per;
+  NGD_TRY(check_coresident((const void*)tridiag_reg_kernel<QN>, kTrThreads, 0, blocks));
+  hipLaunchKernelGGL(tridiag_reg_kernel<QN>, dim3(blocks), dim3(kTrThreads), 0, s, ta);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_tridiag(const TriArgs& ta, hipStream_t s) {
+  const int n = ta.n;
+  if (n <= kTrMaxN) {
+    switch ((n + 63) / 64) {
+      case 1: return launch_tridiag_reg<1>(ta, s);
+      case 2: return launch_tridiag_reg<2>(ta, s);
+      case 3: return launch_tridiag_reg<3>(ta, s);
+      case 4: return launch_tridiag_reg<4>(ta, s);
+      case 5: return launch_tridiag_reg<5>(ta, s);
+      case 6: return launch_tridiag_reg<6>(ta, s);
+      case 7: return launch_tridiag_reg<7>(ta, s);
+      case 8: return launch_tridiag_reg<8>(ta, s);
+      case 9: return launch_tridiag_reg<9>(ta, s);
+      case 10: return launch_tridiag_reg<10>(ta, s);
+      case 11: return launch_tridiag_reg<11>(ta, s);
+      case 12: return launch_tridiag_reg<12>(ta, s);
+      case 13: return launch_tridiag_reg<13>(ta, s);
+      case 14: return launch_tridiag_reg<14>(ta, s);
+      case 15: return launch_tridiag_reg<15>(ta, s);
+      default: return launch_tridiag_reg<16>(ta, s);
+    }
+  }
+  // larger n: rows in LDS, enough workgroups that each one's rows fit next to four n-vectors
+  int blocks = kTriBlocks;
+  auto lds_for = [&](int G) { return sizeof(double) * ((size_t)((n + G - 1) / G) * n + 4 * (size_t)n); };
+  while (lds_for(blocks) > 144 * 1024 && blocks < 256) blocks *= 2;
+  const size_t lds = lds_for(blocks);
+  if (lds > 144 * 1024) {
+    set_error("ell too large for the LDS-resident tridiagonalisation");
+    return NGD_ERR_INVALID;
+  }
+  NGD_HIP_TRY(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  NGD_TRY(check_coresident((const void*)tridiag_kernel, kTriThreads, lds, blocks));
+  hipLaunchKernelGGL(tridiag_kernel, dim3(blocks), dim3(kTriThreads), lds, s, ta);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
 
 }  // namespace
 
@@ -581,30 +1003,7 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
     if (st != NGD_OK) return st;
   }
   TriArgs ta{A, A1, n, dvec, evec, V, tau, pbuf, bar, err};
-  // workgroups: enough that each one's rows fit in LDS next to three n-vectors
-  int blocks = n < kTriBlocks ? (n < 1 ? 1 : n) : kTriBlocks;
-  auto lds_for = [&](int G) { return sizeof(double) * ((size_t)((n + G - 1) / G) * n + 4 * (size_t)n); };
-  while (lds_for(blocks) > 144 * 1024 && blocks < 256) blocks *= 2;
-  size_t lds = lds_for(blocks);
-  if (lds > 144 * 1024) {
-    set_error("ell too large for the LDS-resident tridiagonalisation");
-    return NGD_ERR_INVALID;
-  }
-  NGD_HIP_TRY(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  // The grid barrier needs every workgroup resident at once: `blocks` (<= 64) is far below the
-  // device's CU count, and the check below confirms the occupancy; the barrier's wait is bounded
-  // (it sets the error flag instead of spinning forever).
-  {
-    int dev = 0, cus = 0, per_cu = 0;
-    NGD_HIP_TRY(hipGetDevice(&dev));
-    NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    NGD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)tridiag_kernel, kTriThreads, lds));
-    if ((int64_t)cus * per_cu < blocks) {
-      set_error("tridiagonalisation grid cannot be co-resident");
-      return NGD_ERR_HIP;
-    }
-  }
-  hipLaunchKernelGGL(tridiag_kernel, dim3(blocks), dim3(kTriThreads), lds, s, ta);
+  NGD_TRY(launch_tridiag(ta, s));
   const int tb = 256;
   hipLaunchKernelGGL(bisect_kernel, dim3((n + 3) / 4), dim3(tb), 2 * sizeof(double) * n, s, dvec, evec, n, e2,
                      lam, tnorm);
@@ -645,6 +1044,18 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   }
   // T factors of the reflector blocks (written over the multipliers of inverse iteration, free now)
   double* Tall = ws.Tall;
+  if (n <= kBtMaxN) {
+    const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
+    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, kWy, Tall);
+    const int nt = (n + 15) / 16;
+    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kBtWaves * 256);
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_mfma_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(backtransform_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, s, Z, V, Tall, lam, n, tnorm,
+                       drop_rel, evals_desc, evec_rows);
+    NGD_HIP_TRY(hipGetLastError());
+    return NGD_OK;
+  }
   // reflectors per block: as many as fit in LDS beside the kNC columns
   int wy = kWy;
   while (wy > 1 && (size_t)(kNC + wy) * n * sizeof(double) > 150 * 1024) wy >>= 1;
