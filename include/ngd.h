@@ -67,7 +67,8 @@ typedef struct {
   const void* f;           /* device, N, dtype: source on interior rows */
   const void* g;           /* device, N, dtype: target on boundary / initial rows */
   const int8_t* row_kind;  /* device, N: ngd_row_kind */
-  int32_t max_ell;         /* largest sketch size that will be used with this handle (>= 1) */
+  int32_t max_ell;         /* largest sketch size that will be used with this handle, 1 .. 1024
+                              (the FP64 ell x ell core kernels keep their operands in registers) */
 } ngd_problem_desc;
 
 typedef struct ngd_problem ngd_problem;  /* opaque; owns device workspace only */

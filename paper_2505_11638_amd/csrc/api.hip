@@ -209,6 +209,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   NGD_CHECK(d->n_rows >= 1, "n_rows must be >= 1");
   NGD_CHECK(d->X && d->w && d->f && d->g && d->row_kind, "problem data pointer is NULL");
   NGD_CHECK(d->max_ell >= 1, "max_ell must be >= 1");
+  NGD_CHECK(d->max_ell <= kMaxEll, "max_ell must be <= 1024");
   NetDesc net{};
   net.n_layers = d->n_layers;
   int64_t off = 0;
@@ -489,19 +490,16 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
     GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-                h->gemm_work, 8 * L * L};
+                h->gemm_work, 8 * L * L, 1};
     NGD_TRY(launch_gemm(g2, s));
     // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
     NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
                                     reinterpret_cast<int*>(h->scal + 210), h->cholblk, s));
-    NGD_TRY(launch_cast(T, h->Z, NGD_F64, h->Q, N * L, s));
-    return launch_trsm_right_lt(h->M, (int)L, (double*)h->Q, L, N, s);
+    // one launch: Q in FP64 where a product reads it, Q^T in the compute type on the NT path
+    return launch_trsm_q(h->M, (int)L, T, h->Z, N, nt ? nullptr : (double*)h->Q, et, nt ? h->Qt : nullptr, h->ldN,
+                         s);
   }));
   // B^T = Q^T J (ell x P); on the NT path as (J^T Q)^T with Q^T in the compute type
-  if (nt)
-    NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, s, [&] {
-      return launch_transpose_cast(NGD_F64, h->Q, L, N, L, et, h->Qt, h->ldN, s);
-    }));
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
     if (rec) {
       for (int64_t j = 0; j < L; ++j) {
@@ -520,7 +518,7 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
     GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-                h->gemm_work, 8 * L * L};
+                h->gemm_work, 8 * L * L, 1};
     NGD_TRY(launch_gemm(g5, s));
     // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
     // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
@@ -537,7 +535,7 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     NGD_HIP_TRY(hipMemcpyAsync(&err, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
     if (err) {
-      set_error("grid barrier of the tridiagonalisation timed out");
+      set_error("exchange between the workgroups of the tridiagonalisation timed out");
       return NGD_ERR_HIP;
     }
     int nmod = 0;

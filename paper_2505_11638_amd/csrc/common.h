@@ -14,6 +14,7 @@ namespace ngd {
 constexpr int kMaxLayers = 8;   // affine layers
 constexpr int kMaxDim = 6;      // input dimension d
 constexpr int kMaxWidth = 256;
+constexpr int kMaxEll = 1024;   // sketch size: the ell x ell core kernels hold their operands in registers
 constexpr int kMaxChan = 8;     // value + |S| gradient + Laplacian + time <= 1 + 5 + 1 + 1
 
 // Network and PDE description passed by value to the kernels.
@@ -75,6 +76,48 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Wave-wide sum by DPP row operations (quad permutes, row mirrors, then row broadcasts 15 and 31;
+// the total lands in lane 63 and is read from there): a few VALU cycles per step instead of an LDS
+// permute. Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane63(float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63)); }
+__device__ __forceinline__ double lane63(double x) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                          __builtin_amdgcn_readlane(__double2loint(x), 63));
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T x) {
+  x += dpp_move<0xb1>(x);         // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4e>(x);         // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x141>(x);        // row_half_mirror
+  x += dpp_move<0x140>(x);        // row_mirror: every lane holds its row's sum
+  x += dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return lane63(x);
+}
+
+// Block sum with wave_sum_dpp (every lane of every wave active)
+template <typename T>
+__device__ __forceinline__ T block_sum_dpp(T v, T* red) {
+  v = wave_sum_dpp(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
 }
 
 // Block-wide sum; `red` must hold blockDim.x/64 elements. Result is returned to every thread.
@@ -159,6 +202,9 @@ struct GemmArgs {
   double alpha, beta;
   double* work = nullptr;                      // optional split-K workspace (FP64)
   int64_t work_elems = 0;                      // its size in doubles
+  // C = A B with B = A^T (M == N), FP64 compute only: 1 = only the tiles on and below the diagonal
+  // are formed and mirrored, 2 = only those tiles are formed (the upper part of C is left untouched)
+  int sym = 0;
 };
 ngd_status launch_gemm(const GemmArgs& a, hipStream_t s);
 
@@ -254,7 +300,8 @@ size_t residual_lds_bytes(const NetDesc& net, int dtype, int* tp);
 // chol.hip: blocked shifted Cholesky of the core and the right triangular solve X <- X L^{-T}
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
                                    double* Lblk, hipStream_t s);
-ngd_status launch_trsm_right_lt(const double* L, int n, double* X, int64_t ldx, int64_t nrows, hipStream_t s);
+ngd_status launch_trsm_q(const double* L, int ell, int z_type, const void* Z, int64_t N, double* Q, int qt_type,
+                         void* Qt, int64_t ldqt, hipStream_t s);
 
 // nystrom helpers (misc.hip)
 ngd_status launch_whitening(const double* evals, const double* evec_rows, int ell, double* F, hipStream_t s);

@@ -4,12 +4,15 @@
 // singular values are the eigenpairs of the ell x ell Gram matrix B^T B, computed here in FP64:
 //  1. Householder tridiagonalisation Q^T A Q = T in one launch whose workgroups meet at a grid
 //     barrier once per column. The trailing matrix is row-distributed over the workgroups and kept
-//     in LDS; each step applies the previous step's rank-2 update lazily while forming p = tau A v.
+//     in registers; each step applies the previous step's rank-2 update lazily while forming
+//     p = tau A v.
 //  2. Eigenvalues of T by multisection on Sturm counts (one wave per eigenvalue).
 //  3. Eigenvectors of T by inverse iteration with partial-pivoting LU of T - lambda I (one thread
 //     per eigenvector), modified Gram-Schmidt inside clusters of (nearly) equal eigenvalues, and two
 //     Newton-Schulz steps that restore orthonormality to working precision.
-//  4. Back-transformation V = H_0 H_1 ... H_{n-3} Z (one workgroup per group of columns).
+//  4. Back-transformation V = H_0 H_1 ... H_{n-3} Z in compact WY blocks on the FP64 matrix cores
+//     (one workgroup per 16 columns).
+// n <= 1024.
 // Eigenpairs whose eigenvalue is below drop_rel * (Gershgorin bound of T) are returned as
 // (0, zero vector).
 #include "common.h"
@@ -17,190 +20,39 @@
 namespace ngd {
 namespace {
 
-constexpr int kTriBlocks = 64;
-constexpr int kTriThreads = 256;
-
 struct TriArgs {
   double* A0;      // input matrix (n x n, ld n), read once
-  double* A1;      // two pivot-row buffers (2 n)
+  double* PV;      // 2 n: the next pivot row, double-buffered by the parity of its index
   int n;
   double* d;       // diagonal of T
   double* e;       // off-diagonal of T (n-1)
   double* V;       // Householder vectors, row k = v_k (support k+1..n-1, v_k[k+1] = 1)
   double* tau;     // Householder scalars
-  double* p;       // 2 n: p = tau A v of the current step (double-buffered by step parity, so that
-                   // a workgroup that runs ahead never overwrites values another still has to read)
-  unsigned* flags; // one barrier flag per workgroup
+  double* P;       // 2 n: p = tau A v of the current step, double-buffered by step parity
+  unsigned* flags; // one barrier flag per workgroup, zero at launch
   int* err;
 };
 
-// Grid barrier number `epoch` (0, 1, 2, ...): workgroup g publishes epoch + 1 in its own flag (no
-// contended atomic) and wave 0 polls all flags. One agent-scope release fence before publishing and
-// one acquire fence after the wait (each is an L2 write-back or invalidate on this GPU, so they are
-// kept to the minimum). The wait is bounded: on timeout it raises `err`.
-__device__ bool grid_sync(unsigned* flags, unsigned epoch, int* err) {
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const unsigned target = epoch + 1u;
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    long spins = 0;
-    while (true) {
-      int ok = 1;
-      for (int g = threadIdx.x; g < (int)gridDim.x; g += 64)
-        ok &= __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
-      if (__all(ok)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1L << 24)) {  // seconds: give up instead of hanging
-        if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-}
-
-// One Householder step per column k, rows of the trailing matrix resident in LDS: workgroup g owns
-// rows i = g, g + G, g + 2G, ... Each step applies the previous step's rank-2 update (v, w) to the
-// owned rows in place, forms p_i = tau A_i . v, and the owner of row k+1 publishes that updated row
-// (the next pivot row) to global memory. After one grid barrier every workgroup reads p and the
-// pivot row together, forms w = p - (tau/2)(p . v) v and, from the pivot row, the next Householder
-// vector.
-__global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = a.n, G = gridDim.x, g = blockIdx.x;
-  const int R = (n + G - 1) / G;  // rows per workgroup
-  double* rows = reinterpret_cast<double*>(smem_raw);   // R x n
-  double* vprev = rows + (size_t)R * n;
-  double* wprev = vprev + n;
-  double* v = wprev + n;
-  double* pivl = v + n;  // the current pivot row
-  __shared__ double red[8];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int r = 0; r < R; ++r) {
-    const int i = g + r * G;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) rows[(size_t)r * n + j] = i < n ? a.A0[(int64_t)i * n + j] : 0.0;
-  }
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    vprev[j] = wprev[j] = 0.0;
-    pivl[j] = a.A0[j];  // step 0: row 0 of A, no pending update
-  }
-  __syncthreads();
-  for (int k = 0; k + 2 < n; ++k) {
-    // column k of A^(k) below the diagonal = pivot row k with the pending update applied
-    double tail = 0.0;
-    const double vk = vprev[k], wk = wprev[k];
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double x = pivl[j] - vk * wprev[j] - wk * vprev[j];
-      v[j] = x;
-      if (j > k + 1) tail += x * x;
-    }
-    const double dk = pivl[k] - 2.0 * vk * wk;
-    tail = block_sum(tail, red);
-    const double alpha = v[k + 1];
-    double tau, beta, scale;
-    if (tail == 0.0) {
-      tau = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      const double nrm = sqrt(alpha * alpha + tail);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();
-    for (int j = k + 2 + threadIdx.x; j < n; j += blockDim.x) v[j] *= scale;
-    if (threadIdx.x == 0) v[k + 1] = 1.0;
-    __syncthreads();
-    if (g == 0) {
-      if (threadIdx.x == 0) {
-        a.d[k] = dk;
-        a.e[k] = beta;
-        a.tau[k] = tau;
-      }
-      for (int j = threadIdx.x; j < n; j += blockDim.x) a.V[(int64_t)k * n + j] = j > k ? v[j] : 0.0;
-    }
-    // owned rows i > k: pending update in place, p_i = tau * row . v (one wave per row)
-    double* next_pivot = a.A1 + (int64_t)((k + 1) & 1) * n;
-    for (int r = wid; r < R; r += nw) {
-      const int i = g + r * G;
-      if (i <= k || i >= n) continue;
-      double* row = rows + (size_t)r * n;
-      const double vi = vprev[i], wi = wprev[i];
-      const bool publish = (i == k + 1);
-      double acc = 0.0;
-      for (int j = k + 1 + lane; j < n; j += 64) {
-        const double x = row[j] - vi * wprev[j] - wi * vprev[j];
-        row[j] = x;
-        acc += x * v[j];
-        if (publish) next_pivot[j] = x;
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) a.p[(int64_t)(k & 1) * n + i] = tau * acc;
-    }
-    if (!grid_sync(a.flags, (unsigned)k, a.err)) return;
-    // p and the next pivot row are read together; w = p - (tau/2)(p . v) v is kept by every
-    // workgroup as the pending update
-    double pv = 0.0;
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      const double pj = a.p[(int64_t)(k & 1) * n + j];
-      const double nx = next_pivot[j];
-      wprev[j] = pj;
-      pivl[j] = nx;
-      pv += pj * v[j];
-    }
-    pv = block_sum(pv, red);
-    const double c = 0.5 * tau * pv;
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      if (j > k) {
-        wprev[j] = wprev[j] - c * v[j];
-        vprev[j] = v[j];
-      } else {
-        wprev[j] = 0.0;
-        vprev[j] = 0.0;
-      }
-    }
-    __syncthreads();
-  }
-  // last 2 x 2 (or 1 x 1) block, from the owners' rows with the pending update
-  if (threadIdx.x == 0) {
-    const int m = n >= 2 ? n - 2 : 0;
-    for (int r = 0; r < R; ++r) {
-      const int i = g + r * G;
-      if (i < m || i >= n) continue;
-      const double* row = rows + (size_t)r * n;
-      if (i == m && n >= 2) {
-        a.d[m] = row[m] - 2.0 * vprev[m] * wprev[m];
-        a.e[m] = row[m + 1] - vprev[m] * wprev[m + 1] - wprev[m] * vprev[m + 1];
-      } else if (i == m + 1) {
-        a.d[m + 1] = row[m + 1] - 2.0 * vprev[m + 1] * wprev[m + 1];
-      } else if (n == 1) {
-        a.d[0] = row[0];
-      }
-    }
-  }
-}
-
 // ---- register-resident tridiagonalisation (n <= kTrMaxN) ----
-// The same Householder recurrence with the trailing matrix held in registers: 8 waves per
-// workgroup, each owning up to four of the workgroup's rows, lane l holding columns l, l + 64, ...
-// Only the per-column vectors go through LDS (thread t handles columns t and t + 512), so few
-// workgroups (about n / 32) suffice and the grid barrier, whose latency bounds this kernel, is as
-// cheap as it gets. The vectors the workgroups exchange (p and the next pivot row) are written and
-// read with device-coherent (sc1) accesses, double-buffered by step parity, so the barrier needs no
-// cache write-back or invalidate: each thread waits for its own stores to complete before the
-// workgroup publishes its flag.
+// The Householder recurrence with the trailing matrix in registers: 8 waves per workgroup, each
+// owning up to four of the workgroup's rows, lane l holding columns l, l + 64, ... Per column k:
+//  (A) wave 0 forms the Householder vector v_k from the pivot row (with the pending rank-2 update of
+//      step k-1 applied) while every wave applies that pending update to its rows;
+//  (C) each row's p_i = tau_k row_i . v_k, and the owner of row k+1 publishes that row;
+//  (D) one grid barrier;
+//  (E) p_k and the next pivot row are read into LDS;
+//  (F) every wave forms c_k = (tau_k / 2) p_k . v_k and the new pending update w_k = p_k - c_k v_k at
+//      its own columns, in registers.
+// All reductions are within a wave (DPP), so a step has two workgroup barriers besides the grid
+// barrier. The exchanged vectors are written and read with device-coherent (sc1) accesses, so the
+// grid barrier needs no cache write-back or invalidate: each thread waits for its own stores to
+// complete before the workgroup publishes its flag.
 constexpr int kTrWaves = 8;
 constexpr int kTrThreads = 64 * kTrWaves;
-constexpr int kTrRows = 4;  // rows per wave
+// rows per wave: four, or three where four would not fit in registers with 16 columns per lane
+constexpr int tr_rows(int qn) { return qn <= 13 ? 4 : 3; }
 constexpr int kTrMaxN = 1024;
-constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column vector entries per thread
+constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column LDS entries per thread
 
 __device__ __forceinline__ void st_coherent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -239,14 +91,27 @@ __device__ bool grid_sync_coherent(unsigned* flags, unsigned epoch, int* err, in
   return *timed_out == 0;
 }
 
-template <int QN>
+// entry j of a vector held as x[q] at column lane + 64 q (j wave-uniform): select the register,
+// then read it from lane j % 64
+__device__ __forceinline__ double read_lane(double t, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(t), l),
+                          __builtin_amdgcn_readlane(__double2loint(t), l));
+}
+#define NGD_LANE_VALUE(out, x, QN, j)                  \
+  do {                                                 \
+    const int q_ = (j) >> 6;                           \
+    double t_ = (x)[0];                                \
+    _Pragma("unroll") for (int u_ = 1; u_ < (QN); ++u_) \
+      if (q_ == u_) t_ = (x)[u_];                      \
+    (out) = read_lane(t_, (j) & 63);                   \
+  } while (0)
+
+template <int QN, int kTrRows>
 __global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
-  // the three per-column vectors in one array, so that one base address serves all of them
-  __shared__ double vecs[3 * kTrMaxN];
-  double* vprev = vecs;
-  double* wprev = vecs + kTrMaxN;
-  double* vcur = vecs + 2 * kTrMaxN;
-  __shared__ double red[kTrWaves];
+  __shared__ double vbuf[2][kTrMaxN];  // v of this step and of the previous one (by parity)
+  __shared__ double pbuf[kTrMaxN];     // p of the previous step
+  __shared__ double pivl[kTrMaxN];     // the pivot row (before the pending update)
+  __shared__ double tau_s;
   __shared__ int timed_out;
   const int n = a.n, G = gridDim.x, g = blockIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -261,159 +126,160 @@ __global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
       rows[s][q] = (i < n && c < n) ? a.A0[(int64_t)i * n + c] : 0.0;
     }
   }
-  // per-column state of columns j_t = threadIdx.x + kTrThreads t: pivot row entry (row 0, nothing
-  // pending) and the pending rank-2 update
-  double piv[kTrCols], vp[kTrCols], wp[kTrCols], vj[kTrCols];
+  // the pending rank-2 update (v, w) at this lane's columns; c of the step that made it
+  double vq[QN], wq[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) vq[q] = wq[q] = 0.0;
+  double cprev = 0.0;
 #pragma unroll
   for (int t = 0; t < kTrCols; ++t) {
     const int j = threadIdx.x + kTrThreads * t;
-    piv[t] = j < n ? a.A0[j] : 0.0;
-    vp[t] = wp[t] = 0.0;
-    vprev[j] = 0.0;
-    wprev[j] = 0.0;
+    pivl[j] = j < n ? a.A0[j] : 0.0;  // row 0, nothing pending
+    vbuf[0][j] = 0.0;
+    vbuf[1][j] = 0.0;
+    pbuf[j] = 0.0;
   }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
-    // column k of A^(k) below the diagonal: the pivot row with the pending update applied
-    const double vk = vprev[k], wk = wprev[k];
-    double x[kTrCols], tail = 0.0;
+    double* vnew = vbuf[k & 1];
+    const double* vold = vbuf[(k & 1) ^ 1];
+    // (A) wave 0: v_k from column k of A^(k) = the pivot row with the pending update applied
+    if (wid == 0) {
+      const double vk = vold[k];
+      double wk;
+      NGD_LANE_VALUE(wk, wq, QN, k);
+      double x[QN], tail = 0.0;
 #pragma unroll
-    for (int t = 0; t < kTrCols; ++t) {
-      const int j = threadIdx.x + kTrThreads * t;
-      x[t] = (j > k && j < n) ? piv[t] - vk * wp[t] - wk * vp[t] : 0.0;
-      vcur[j] = x[t];
-      if (j > k + 1) tail += x[t] * x[t];
-    }
-    tail = block_sum(tail, red);
-    const double alpha = vcur[k + 1];
-    double tau, beta, scale;
-    if (tail == 0.0) {
-      tau = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      const double nrm = sqrt(alpha * alpha + tail);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();  // every thread has read vcur[k + 1]
+      for (int q = 0; q < QN; ++q) {  // unconditional LDS reads, so that they issue together
+        const int c = lane + 64 * q;
+        const double pl = pivl[c];
+        x[q] = (c > k && c < n) ? pl - vk * wq[q] - wk * vq[q] : 0.0;
+        if (c > k + 1) tail += x[q] * x[q];
+      }
+      tail = wave_sum_dpp(tail);
+      double alpha;
+      NGD_LANE_VALUE(alpha, x, QN, k + 1);
+      double tau, beta, scale;
+      if (tail == 0.0) {
+        tau = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + tail);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
 #pragma unroll
-    for (int t = 0; t < kTrCols; ++t) {
-      const int j = threadIdx.x + kTrThreads * t;
-      vj[t] = j == k + 1 ? 1.0 : (j > k + 1 ? x[t] * scale : 0.0);
-      vcur[j] = vj[t];
-      if (g == 0) {
-        if (j == k) a.d[k] = piv[t] - 2.0 * vk * wk;
-        if (j < n) a.V[(int64_t)k * n + j] = vj[t];
+      for (int q = 0; q < QN; ++q) {
+        const int c = lane + 64 * q;
+        const double v = c == k + 1 ? 1.0 : (c > k + 1 ? x[q] * scale : 0.0);
+        vnew[c] = v;
+        if (g == 0 && c < n) a.V[(int64_t)k * n + c] = v;
+      }
+      if (lane == 0) {
+        tau_s = tau;
+        if (g == 0) {
+          a.d[k] = pivl[k] - 2.0 * vk * wk;
+          a.e[k] = beta;
+          a.tau[k] = tau;
+        }
       }
     }
-    if (g == 0 && threadIdx.x == 0) {
-      a.e[k] = beta;
-      a.tau[k] = tau;
+    // (A) every wave: the pending update of its live rows, A_ic -= v_i w_c + w_i v_c
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) {
+      const int i = g + G * (wid + kTrWaves * s);
+      if (i <= k || i >= n) continue;
+      const double vi = vold[i], wi = pbuf[i] - cprev * vi;
+#pragma unroll
+      for (int q = 0; q < QN; ++q) rows[s][q] -= vi * wq[q] + wi * vq[q];
     }
     __syncthreads();
-    // owned rows i > k: the pending update in place, p_i = tau * row . v. The column vectors are
-    // read from LDS four columns at a time for all rows (one wait per chunk); columns c <= k and
-    // c >= n need no predicate: v is zero there, and the entries they change are never read again.
-    double* next_pivot = a.A1 + (int64_t)((k + 1) & 1) * n;
-    double* pk = a.p + (int64_t)(k & 1) * n;
-    double vi[kTrRows], wi[kTrRows], acc[kTrRows];
-    bool live[kTrRows];
+    // (C) p_i = tau_k row_i . v_k; the owner of row k+1 publishes it
+    const double tk = tau_s;
+    double* pk = a.P + (int64_t)(k & 1) * n;
+    double* nextp = a.PV + (int64_t)((k + 1) & 1) * n;
+    double acc[kTrRows];
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) acc[s] = 0.0;
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      const double u = vnew[lane + 64 * q];
+#pragma unroll
+      for (int s = 0; s < kTrRows; ++s) acc[s] += rows[s][q] * u;
+    }
+#pragma unroll
+    for (int s = 0; s < kTrRows; ++s) acc[s] = wave_sum_dpp(acc[s]);
 #pragma unroll
     for (int s = 0; s < kTrRows; ++s) {
       const int i = g + G * (wid + kTrWaves * s);
-      live[s] = i > k && i < n;
-      vi[s] = live[s] ? vprev[i] : 0.0;
-      wi[s] = live[s] ? wprev[i] : 0.0;
-      acc[s] = 0.0;
-    }
-#pragma unroll
-    for (int q0 = 0; q0 < QN; q0 += 4) {
-      double wq[4], vq[4], uq[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = lane + 64 * (q0 + u);
-        if (q0 + u < QN) {
-          wq[u] = wprev[c];
-          vq[u] = vprev[c];
-          uq[u] = vcur[c];
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < kTrRows; ++s) {
-        if (!live[s]) continue;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (q0 + u < QN) {
-            const double y = rows[s][q0 + u] - vi[s] * wq[u] - wi[s] * vq[u];
-            rows[s][q0 + u] = y;
-            acc[s] += y * uq[u];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < kTrRows; ++s) acc[s] = wave_sum(acc[s]);
-#pragma unroll
-    for (int s = 0; s < kTrRows; ++s) {
-      const int i = g + G * (wid + kTrWaves * s);
-      if (!live[s]) continue;
-      if (lane == 0) st_coherent(pk + i, tau * acc[s]);
-      if (i == k + 1) {  // the next pivot row, updated
+      if (i <= k || i >= n) continue;
+      if (lane == 0) st_coherent(pk + i, tk * acc[s]);
+      if (i == k + 1) {
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
           const int c = lane + 64 * q;
-          if (c > k && c < n) st_coherent(next_pivot + c, rows[s][q]);
+          if (c > k && c < n) st_coherent(nextp + c, rows[s][q]);
         }
       }
     }
+    // (D)
     if (!grid_sync_coherent(a.flags, (unsigned)k, a.err, &timed_out)) return;
-    // p and the next pivot row; w = p - (tau/2)(p . v) v becomes the pending update
-    double pj[kTrCols], pvs = 0.0;
+    // (E) p_k and pivot row k+1
+    double pl[kTrCols], nl[kTrCols];
 #pragma unroll
-    for (int t = 0; t < kTrCols; ++t) {
-      const int j = threadIdx.x + kTrThreads * t;
-      pj[t] = 0.0;
-      if (j > k && j < n) {
-        pj[t] = ld_coherent(pk + j);
-        piv[t] = ld_coherent(next_pivot + j);
-      }
-      pvs += pj[t] * vj[t];
+    for (int t = 0; t < kTrCols; ++t) {  // unconditional (clamped) loads, so that they issue together
+      const int jc = min((int)threadIdx.x + kTrThreads * t, n - 1);
+      pl[t] = ld_coherent(pk + jc);
+      nl[t] = ld_coherent(nextp + jc);
     }
-    const double c = 0.5 * tau * block_sum(pvs, red);
 #pragma unroll
     for (int t = 0; t < kTrCols; ++t) {
       const int j = threadIdx.x + kTrThreads * t;
       const bool live = j > k && j < n;
-      wp[t] = live ? pj[t] - c * vj[t] : 0.0;
-      vp[t] = live ? vj[t] : 0.0;
-      vprev[j] = vp[t];
-      wprev[j] = wp[t];
+      pbuf[j] = live ? pl[t] : 0.0;
+      pivl[j] = live ? nl[t] : 0.0;
     }
     __syncthreads();
-  }
-  // last 2 x 2 (or 1 x 1) block: rows n-2 (the pivot) and n-1 with the pending update
-  const int m = n >= 2 ? n - 2 : 0;
+    // (F) c_k and the new pending update at this lane's columns (every wave)
+    double pv = 0.0;
 #pragma unroll
-  for (int t = 0; t < kTrCols; ++t) {
-    const int j = threadIdx.x + kTrThreads * t;
-    if (g != 0) break;
-    if (n == 1) {
-      if (j == 0) a.d[0] = piv[t];
-    } else {
-      if (j == m) a.d[m] = piv[t] - 2.0 * vprev[m] * wprev[m];
-      if (j == m + 1) a.e[m] = piv[t] - vprev[m] * wprev[m + 1] - wprev[m] * vprev[m + 1];
+    for (int q = 0; q < QN; ++q) {
+      const int c = lane + 64 * q;
+      pv += pbuf[c] * vnew[c];
     }
+    const double ck = 0.5 * tk * wave_sum_dpp(pv);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      const int c = lane + 64 * q;
+      vq[q] = vnew[c];
+      wq[q] = pbuf[c] - ck * vq[q];
+    }
+    cprev = ck;
   }
-  if (n == 1) return;
+  // the last 2 x 2 (or 1 x 1) block: pivot row n-2 and row n-1 with the pending update
+  const int m = n >= 2 ? n - 2 : 0;
+  if (n == 1) {
+    if (g == 0 && threadIdx.x == 0) a.d[0] = pivl[0];
+    return;
+  }
+  double vm, wm, vm1, wm1;
+  NGD_LANE_VALUE(vm, vq, QN, m);
+  NGD_LANE_VALUE(wm, wq, QN, m);
+  NGD_LANE_VALUE(vm1, vq, QN, m + 1);
+  NGD_LANE_VALUE(wm1, wq, QN, m + 1);
+  if (g == 0 && threadIdx.x == 0) {
+    a.d[m] = pivl[m] - 2.0 * vm * wm;
+    a.e[m] = pivl[m + 1] - vm * wm1 - wm * vm1;
+  }
 #pragma unroll
   for (int s = 0; s < kTrRows; ++s) {
     const int i = g + G * (wid + kTrWaves * s);
     if (i != m + 1) continue;
 #pragma unroll
     for (int q = 0; q < QN; ++q)
-      if (lane + 64 * q == m + 1) a.d[m + 1] = rows[s][q] - 2.0 * vprev[m + 1] * wprev[m + 1];
+      if (lane + 64 * q == m + 1) a.d[m + 1] = rows[s][q] - 2.0 * vm1 * wm1;
   }
 }
 
@@ -491,110 +357,159 @@ __global__ void bisect_kernel(const double* __restrict__ d, const double* __rest
 }
 
 // inverse iteration for eigenvalue i: solve (T - lam I) x = b by LU with partial pivoting
-// (tridiagonal; the U factor has two superdiagonals). A workgroup of `tpw` threads handles tpw
-// eigenvalues; d, e and the per-thread factor arrays live in LDS (interleaved by thread), so the
-// sequential recurrences wait on LDS rather than global-memory latency.
-constexpr int kInvArrays = 6;
+// (tridiagonal; the U factor has two superdiagonals), two sweeps. One thread per eigenvalue, 64
+// eigenvalues per wave: the factors live in a global workspace laid out [array][j][i] (consecutive
+// eigenvalues adjacent, so every access is coalesced), and the sequential recurrences read them in
+// chunks of sixteen that are loaded before they are used. Quotients are a hardware reciprocal refined
+// by one Newton step.
+constexpr int kInvChunk = 16;
+
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
-                                                   const double* __restrict__ lam_asc,
-                                                   const double* __restrict__ tnorm, double drop_rel,
-                                                   double* __restrict__ Z) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sd = reinterpret_cast<double*>(smem_raw);
-  double* se = sd + n;
-  double* arr = se + n;
-  const int tpw = blockDim.x;
-  for (int j = threadIdx.x; j < n; j += tpw) {
-    sd[j] = d[j];
-    se[j] = j < n - 1 ? e[j] : 0.0;
-  }
-  __syncthreads();
-  const int t = threadIdx.x;
-  const int i = blockIdx.x * tpw + t;
+                                                    const double* __restrict__ lam_asc,
+                                                    const double* __restrict__ tnorm, double drop_rel,
+                                                    double* __restrict__ ML, double* __restrict__ SW,
+                                                    double* __restrict__ U1, double* __restrict__ U2,
+                                                    double* __restrict__ RI, double* __restrict__ Y,
+                                                    double* __restrict__ Z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double lam = lam_asc[i];
   const double drop = drop_rel * (*tnorm);
-#define W(k, j) arr[((int64_t)(k) * n + (j)) * tpw + t]
-  enum { RINV = 0, U1 = 1, U2 = 2, ML = 3, Y = 4, SWP = 5 };
   if (lam < drop) {
     for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = 0.0;
     return;
   }
   const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
-  // factorisation of T - lam I
-  double a = sd[0] - lam, b = n > 1 ? se[0] : 0.0;
-  for (int j = 0; j < n - 1; ++j) {
-    const double c = se[j], dn = sd[j + 1] - lam, en = se[j + 1];
-    double piv, m;
-    if (fabs(a) >= fabs(c)) {
-      piv = a;
-      m = a != 0.0 ? c / a : 0.0;
-      W(U1, j) = b;
-      W(U2, j) = 0.0;
-      W(ML, j) = m;
-      a = dn - m * b;
-      b = en;
-      W(SWP, j) = 0.0;
-    } else {
-      piv = c;
-      m = a / c;
-      W(U1, j) = dn;
-      W(U2, j) = en;
-      W(ML, j) = m;
-      a = b - m * dn;
-      b = -m * en;
-      W(SWP, j) = 1.0;
+  auto at = [&](int j) { return (int64_t)j * n + i; };
+  // factorisation of T - lam I fused with the first forward sweep (start vector: deterministic
+  // pseudo-random entries in [0.5, 1.5))
+  unsigned h = 2166136261u ^ ((unsigned)i * 16777619u);
+  h = (h ^ 0u) * 16777619u + 0x9E3779B9u;
+  double carry = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
+  double a = d[0] - lam, b = n > 1 ? e[0] : 0.0;
+  for (int j0 = 0; j0 < n - 1; j0 += kInvChunk) {
+    double cj[kInvChunk], dj[kInvChunk], ej[kInvChunk];
+#pragma unroll
+    for (int u = 0; u < kInvChunk; ++u) {
+      const int j = min(j0 + u, n - 2);
+      cj[u] = e[j];
+      dj[u] = d[j + 1];
+      ej[u] = j + 1 < n - 1 ? e[j + 1] : 0.0;
     }
-    if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
-    W(RINV, j) = 1.0 / piv;
+#pragma unroll
+    for (int u = 0; u < kInvChunk; ++u) {
+      const int j = j0 + u;
+      if (j < n - 1) {
+        const double c = cj[u], dn = dj[u] - lam, en = ej[u];
+        h = (h ^ (unsigned)(j + 1)) * 16777619u + 0x9E3779B9u;
+        const double nxt = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
+        double piv, m, x0, x1;
+        if (fabs(a) >= fabs(c)) {
+          piv = a;
+          m = a != 0.0 ? c * recip(a) : 0.0;
+          U1[at(j)] = b;
+          U2[at(j)] = 0.0;
+          SW[at(j)] = 0.0;
+          a = dn - m * b;
+          b = en;
+          x0 = carry;
+          x1 = nxt;
+        } else {
+          piv = c;
+          m = a * recip(c);
+          U1[at(j)] = dn;
+          U2[at(j)] = en;
+          SW[at(j)] = 1.0;
+          a = b - m * dn;
+          b = -m * en;
+          x0 = nxt;
+          x1 = carry;
+        }
+        ML[at(j)] = m;
+        if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
+        RI[at(j)] = recip(piv);
+        Y[at(j)] = x0;
+        carry = x1 - m * x0;
+      }
+    }
   }
   if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-  W(RINV, n - 1) = 1.0 / a;
-  // start vector: deterministic pseudo-random entries in [0.5, 1.5)
-  unsigned h = 2166136261u ^ ((unsigned)i * 16777619u);
-  double scale = 1.0;
+  RI[at(n - 1)] = recip(a);
+  U1[at(n - 1)] = 0.0;
+  U2[at(n - 1)] = 0.0;
+  Y[at(n - 1)] = carry;
+  double scale = 1.0, ss = 0.0;
   for (int it = 0; it < 2; ++it) {
-    // forward sweep (interchanges + multipliers) writes y; carry the running entry in a register
-    double carry;
-    if (it == 0) {
-      h = (h ^ 0u) * 16777619u + 0x9E3779B9u;
-      carry = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
-    } else {
-      carry = W(Y, 0) * scale;
-    }
-    for (int j = 0; j < n - 1; ++j) {
-      double nxt;
-      if (it == 0) {
-        h = (h ^ (unsigned)(j + 1)) * 16777619u + 0x9E3779B9u;
-        nxt = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
-      } else {
-        nxt = W(Y, j + 1) * scale;
+    if (it == 1) {
+      // forward sweep with the stored interchanges and multipliers on the scaled previous solution
+      carry = Y[at(0)] * scale;
+      for (int j0 = 0; j0 < n - 1; j0 += kInvChunk) {
+        double ml[kInvChunk], sw[kInvChunk], yn[kInvChunk];
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) {
+          const int j = min(j0 + u, n - 2);
+          ml[u] = ML[at(j)];
+          sw[u] = SW[at(j)];
+          yn[u] = Y[at(j + 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kInvChunk; ++u) {
+          const int j = j0 + u;
+          if (j < n - 1) {
+            const double nxt = yn[u] * scale;
+            const bool swp = sw[u] != 0.0;
+            const double x0 = swp ? nxt : carry, x1 = swp ? carry : nxt;
+            Y[at(j)] = x0;
+            carry = x1 - ml[u] * x0;
+          }
+        }
       }
-      const bool swp = W(SWP, j) != 0.0;
-      const double x0 = swp ? nxt : carry, x1 = swp ? carry : nxt;
-      W(Y, j) = x0;
-      carry = x1 - W(ML, j) * x0;
+      Y[at(n - 1)] = carry;
     }
-    W(Y, n - 1) = carry;
-    // backward substitution with U, in place on y; track the max-norm for scaling
+    // backward substitution with U, in place on y; the max-norm for scaling (and, on the last sweep,
+    // the sum of squares for the final normalisation)
     double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-    for (int j = n - 1; j >= 0; --j) {
-      const double x = (W(Y, j) - W(U1, j) * x1 - W(U2, j) * x2) * W(RINV, j);
-      W(Y, j) = x;
-      x2 = x1;
-      x1 = x;
-      nrm = fmax(nrm, fabs(x));
+    ss = 0.0;
+    for (int j0 = n - 1; j0 >= 0; j0 -= kInvChunk) {
+      double yv[kInvChunk], u1[kInvChunk], u2[kInvChunk], ri[kInvChunk];
+#pragma unroll
+      for (int u = 0; u < kInvChunk; ++u) {
+        const int j = max(j0 - u, 0);
+        yv[u] = Y[at(j)];
+        u1[u] = U1[at(j)];
+        u2[u] = U2[at(j)];
+        ri[u] = RI[at(j)];
+      }
+#pragma unroll
+      for (int u = 0; u < kInvChunk; ++u) {
+        const int j = j0 - u;
+        if (j >= 0) {
+          const double x = (yv[u] - u1[u] * x1 - u2[u] * x2) * ri[u];
+          Y[at(j)] = x;
+          x2 = x1;
+          x1 = x;
+          nrm = fmax(nrm, fabs(x));
+          ss += x * x;
+        }
+      }
     }
     scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
   }
-  double nrm2 = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double v = W(Y, j) * scale;
-    nrm2 += v * v;
+  // unit 2-norm: ss is the sum of squares of the unscaled last solution
+  const double s2 = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  for (int j0 = 0; j0 < n; j0 += kInvChunk) {
+    double yv[kInvChunk];
+#pragma unroll
+    for (int u = 0; u < kInvChunk; ++u) yv[u] = Y[at(min(j0 + u, n - 1))];
+#pragma unroll
+    for (int u = 0; u < kInvChunk; ++u)
+      if (j0 + u < n) Z[at(j0 + u)] = yv[u] * s2;
   }
-  const double s2 = nrm2 > 0.0 ? scale / sqrt(nrm2) : 0.0;
-  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = W(Y, j) * s2;
-#undef W
 }
 
 // modified Gram-Schmidt within each cluster of close eigenvalues (one workgroup per cluster start)
@@ -630,7 +545,6 @@ __global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, co
 // WY form: H_k0 ... H_k1 = I - Y T Y^T (Y = [v_k0 .. v_k1], T upper triangular, built as in the
 // forward-accumulation recurrence T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[:, 0:i]^T v_i).
 constexpr int kWy = 16;   // reflectors per block
-constexpr int kNC = 8;    // eigenvector columns per workgroup
 
 // T of every block of wy (<= kWy) reflectors (one workgroup per block), stored kWy x kWy per block
 __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V, const double* __restrict__ tau, int n,
@@ -669,89 +583,6 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V,
   }
   __syncthreads();
   for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Tall[(int64_t)blockIdx.x * kWy * kWy + e] = (&Ts[0][0])[e];
-}
-
-// kNC columns of Z per workgroup: for each block of wy reflectors from the last, the block's
-// reflectors are staged in LDS and Z <- Z - Y (T (Y^T Z)); then the columns are written as
-// eigenvector rows in descending eigenvalue order (dropped pairs as zeros)
-__global__ __launch_bounds__(256) void backtransform_kernel(const double* __restrict__ Z, const double* __restrict__ V,
-                                                            const double* __restrict__ Tall, int wy,
-                                                            const double* __restrict__ lam_asc, int n,
-                                                            const double* __restrict__ tnorm, double drop_rel,
-                                                            double* __restrict__ evals_desc,
-                                                            double* __restrict__ evec_rows) {
-  const double drop = drop_rel * (*tnorm);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* zc = reinterpret_cast<double*>(smem_raw);  // kNC x n
-  double* Ys = zc + (size_t)kNC * n;                 // wy x n
-  __shared__ double W[kWy][kNC];
-  __shared__ double S[kWy][kNC];
-  __shared__ double Ts[kWy * kWy];
-  const int c0 = blockIdx.x * kNC;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int c = 0; c < kNC; ++c)
-    for (int j = threadIdx.x; j < n; j += blockDim.x) zc[c * n + j] = (c0 + c < n) ? Z[(int64_t)j * n + c0 + c] : 0.0;
-  const int nref = n - 2;
-  const int nblk = nref > 0 ? (nref + wy - 1) / wy : 0;
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int k0 = b * wy;
-    const int m = min(wy, nref - k0);
-    __syncthreads();
-    // the block's reflectors and T factor into LDS (all loads of a thread issued before its stores)
-    for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Ts[e] = Tall[(int64_t)b * kWy * kWy + e];
-    for (int j0 = threadIdx.x; j0 < n; j0 += blockDim.x) {
-      double yv[kWy];
-#pragma unroll
-      for (int i = 0; i < kWy; ++i) yv[i] = i < m ? V[(int64_t)(k0 + i) * n + j0] : 0.0;
-#pragma unroll
-      for (int i = 0; i < kWy; ++i)
-        if (i < m) Ys[i * n + j0] = yv[i];
-    }
-    __syncthreads();
-    // W = Y^T Z (one wave per (reflector, column) pair); v_k is zero at and above row k
-    for (int q = wid; q < wy * kNC; q += nw) {
-      const int i = q / kNC, c = q % kNC;
-      double acc = 0.0;
-      if (i < m) {
-        for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += Ys[i * n + j] * zc[c * n + j];
-        acc = wave_sum(acc);
-      }
-      if (lane == 0) W[i][c] = acc;
-    }
-    __syncthreads();
-    // S = T W
-    if (threadIdx.x < wy * kNC) {
-      const int i = threadIdx.x / kNC, c = threadIdx.x % kNC;
-      double acc = 0.0;
-      if (i < m)
-        for (int a = i; a < m; ++a) acc += Ts[i * kWy + a] * W[a][c];
-      S[i][c] = acc;
-    }
-    __syncthreads();
-    // Z -= Y S
-    for (int j = k0 + 1 + threadIdx.x; j < n; j += blockDim.x) {
-      double acc[kNC];
-#pragma unroll
-      for (int c = 0; c < kNC; ++c) acc[c] = 0.0;
-      for (int i = 0; i < m; ++i) {
-        const double y = j > k0 + i ? Ys[i * n + j] : 0.0;
-#pragma unroll
-        for (int c = 0; c < kNC; ++c) acc[c] += y * S[i][c];
-      }
-#pragma unroll
-      for (int c = 0; c < kNC; ++c) zc[c * n + j] -= acc[c];
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < kNC; ++c) {
-    const int col = c0 + c;
-    if (col >= n) break;
-    const int out = n - 1 - col;  // descending order
-    const double lam = lam_asc[col];
-    const bool keep = lam >= drop;
-    if (threadIdx.x == 0) evals_desc[out] = keep ? lam : 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) evec_rows[(int64_t)out * n + j] = keep ? zc[c * n + j] : 0.0;
-  }
 }
 
 // The same back-transformation on the FP64 matrix cores, for n <= kBtMaxN. A workgroup owns 16
@@ -880,11 +711,11 @@ __global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
   }
 }
 
-// Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau (n each),
-// p (2 n), e2, lam (n each), tnorm (8), the per-workgroup barrier flags (256 unsigned) and the error word, then
+// Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau, e2, lam
+// (n each), tnorm (8), the barrier flags (256 unsigned) and the error word (in a 1 KiB slot), then
 // the T factors of the reflector blocks.
 struct EigWs {
-  double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *pbuf, *e2, *lam, *tnorm, *Tall;
+  double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *e2, *lam, *tnorm, *Tall;
   unsigned* flags;
   int* err;
   size_t bytes;
@@ -898,13 +729,12 @@ struct EigWs {
     dvec = wk + 5 * nn;
     evec = dvec + n;
     tau = evec + n;
-    pbuf = tau + n;
-    e2 = pbuf + 2 * n;
+    e2 = tau + n;
     lam = e2 + n;
     tnorm = lam + n;
     flags = reinterpret_cast<unsigned*>(tnorm + 8);
-    err = reinterpret_cast<int*>(flags + 256);
-    Tall = tnorm + 8 + 130;  // 256 unsigned + err word, rounded up to doubles
+    err = reinterpret_cast<int*>(flags + 248);
+    Tall = tnorm + 8 + 128;  // the 1 KiB slot of the flags and the error word
     const size_t nblk = (size_t)n + 1;  // blocks of as few as one reflector
     bytes = (size_t)((Tall + nblk * kWy * kWy) - w) * sizeof(double);
   }
@@ -927,12 +757,12 @@ ngd_status check_coresident(const void* kernel, int threads, size_t lds, int blo
 
 template <int QN>
 ngd_status launch_tridiag_reg(const TriArgs& ta, hipStream_t s) {
-  // as few workgroups as hold the rows (at most kTrWaves * kTrRows each): the barrier's cost grows
-  // with the number of workgroups
-  const int per = kTrWaves * kTrRows;
+  // as few workgroups as hold the rows: the barrier's cost grows with the number of workgroups
+  constexpr int RW = tr_rows(QN);
+  const int per = kTrWaves * RW;
   const int blocks = (ta.n + per - 1) / per;
-  NGD_TRY(check_coresident((const void*)tridiag_reg_kernel<QN>, kTrThreads, 0, blocks));
-  hipLaunchKernelGGL(tridiag_reg_kernel<QN>, dim3(blocks), dim3(kTrThreads), 0, s, ta);
+  NGD_TRY(check_coresident((const void*)tridiag_reg_kernel<QN, RW>, kTrThreads, 0, blocks));
+  hipLaunchKernelGGL((tridiag_reg_kernel<QN, RW>), dim3(blocks), dim3(kTrThreads), 0, s, ta);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
@@ -959,20 +789,8 @@ ngd_status launch_tridiag(const TriArgs& ta, hipStream_t s) {
       default: return launch_tridiag_reg<16>(ta, s);
     }
   }
-  // larger n: rows in LDS, enough workgroups that each one's rows fit next to four n-vectors
-  int blocks = kTriBlocks;
-  auto lds_for = [&](int G) { return sizeof(double) * ((size_t)((n + G - 1) / G) * n + 4 * (size_t)n); };
-  while (lds_for(blocks) > 144 * 1024 && blocks < 256) blocks *= 2;
-  const size_t lds = lds_for(blocks);
-  if (lds > 144 * 1024) {
-    set_error("ell too large for the LDS-resident tridiagonalisation");
-    return NGD_ERR_INVALID;
-  }
-  NGD_HIP_TRY(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  NGD_TRY(check_coresident((const void*)tridiag_kernel, kTriThreads, lds, blocks));
-  hipLaunchKernelGGL(tridiag_kernel, dim3(blocks), dim3(kTriThreads), lds, s, ta);
-  NGD_HIP_TRY(hipGetLastError());
-  return NGD_OK;
+  set_error("tridiagonalisation: n above 1024");
+  return NGD_ERR_INVALID;
 }
 
 }  // namespace
@@ -990,35 +808,29 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   double* dvec = ws.dvec;
   double* evec = ws.evec;
   double* tau = ws.tau;
-  double* pbuf = ws.pbuf;
   double* e2 = ws.e2;
   double* lam = ws.lam;
   double* tnorm = ws.tnorm;
-  unsigned* bar = ws.flags;
   int* err = ws.err;
   {
-    ngd_status st = launch_zero(bar, 256 * sizeof(unsigned) + sizeof(int), s);
+    ngd_status st = launch_zero(ws.flags, 1024, s);
     if (st != NGD_OK) return st;
     st = launch_zero(tau, sizeof(double) * n, s);
     if (st != NGD_OK) return st;
   }
-  TriArgs ta{A, A1, n, dvec, evec, V, tau, pbuf, bar, err};
+  // exchange buffers of the tridiagonalisation (2 n each): PV in A1, P in wk (both free until it is done)
+  TriArgs ta{A, A1, n, dvec, evec, V, tau, wk, ws.flags, err};
   NGD_TRY(launch_tridiag(ta, s));
   const int tb = 256;
   hipLaunchKernelGGL(bisect_kernel, dim3((n + 3) / 4), dim3(tb), 2 * sizeof(double) * n, s, dvec, evec, n, e2,
                      lam, tnorm);
   {
-    // as many eigenvalues per workgroup as fit: (2 + 6 tpw) n doubles of LDS
-    int tpw = (int)((150 * 1024 / sizeof(double) - 2 * (size_t)n) / ((size_t)kInvArrays * n));
-    tpw = tpw > 64 ? 64 : tpw;
-    if (tpw < 1) {
-      set_error("ell too large for inverse iteration in LDS");
-      return NGD_ERR_INVALID;
-    }
-    const size_t lds = sizeof(double) * ((size_t)2 * n + (size_t)kInvArrays * n * tpw);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(invit_kernel, dim3((n + tpw - 1) / tpw), dim3(tpw), lds, s, dvec, evec, n, lam, tnorm,
-                       drop_rel, Z);
+    // the factors of inverse iteration: five n x n arrays in wk, the interchanges in A1 (both free
+    // after the tridiagonalisation)
+    const size_t nn = (size_t)n * n;
+    hipLaunchKernelGGL(invit_kernel, dim3((n + 63) / 64), dim3(64), 0, s, dvec, evec, n, lam, tnorm, drop_rel,
+                       wk, A1, wk + nn, wk + 2 * nn, wk + 3 * nn, wk + 4 * nn, Z);
+    NGD_HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(cluster_mgs_kernel, dim3(n), dim3(256), 0, s, lam, n, tnorm, drop_rel, Z);
   NGD_HIP_TRY(hipGetLastError());
@@ -1029,7 +841,7 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   double* nswork = wk + (size_t)n * n;  // split-K partials of the n x n products (4 n^2)
   for (int ns = 0; ns < 2; ++ns) {
     GemmArgs e{n, n, n, Z, n, false, Z, n, false, E, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
-               nswork, 4 * (int64_t)n * n};
+               nswork, 4 * (int64_t)n * n, 1};
     ngd_status st = launch_gemm(e, s);
     if (st != NGD_OK) return st;
     st = launch_cast(NGD_F64, Z, NGD_F64, Z2, (int64_t)n * n, s);
@@ -1056,22 +868,8 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
     NGD_HIP_TRY(hipGetLastError());
     return NGD_OK;
   }
-  // reflectors per block: as many as fit in LDS beside the kNC columns
-  int wy = kWy;
-  while (wy > 1 && (size_t)(kNC + wy) * n * sizeof(double) > 150 * 1024) wy >>= 1;
-  const size_t bt_lds = (size_t)(kNC + wy) * n * sizeof(double);
-  if (bt_lds > 150 * 1024) {
-    set_error("ell too large for the back-transformation's LDS budget");
-    return NGD_ERR_INVALID;
-  }
-  const int nblk = n > 2 ? (n - 2 + wy - 1) / wy : 0;
-  if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, wy, Tall);
-  NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bt_lds));
-  hipLaunchKernelGGL(backtransform_kernel, dim3((n + kNC - 1) / kNC), dim3(256), bt_lds, s, Z, V, Tall, wy, lam, n,
-                     tnorm, drop_rel, evals_desc, evec_rows);
-  NGD_HIP_TRY(hipGetLastError());
-  return NGD_OK;
+  set_error("back-transformation: n above 1024");
+  return NGD_ERR_INVALID;
 }
 
 const int* eig_error_flag(void* work, int n) { return EigWs(work, n).err; }

@@ -10,7 +10,8 @@
 // Tiling: 256 threads = 4 wave64s in a 2 x 2 arrangement; workgroup tile BM x BN = 64 x 64, each
 // wave a 32 x 32 block of 2 x 2 MFMA tiles. The next K-slab is fetched into registers while the
 // current one is multiplied out of LDS. Blocks that share an A row-panel are adjacent in launch
-// order so the panel is reused from L2.
+// order so the panel is reused from L2. FP64 compute has its own kernel (dgemm_kernel: double-
+// buffered LDS, vector loads, and a symmetric mode for the Gram matrices of the core).
 #include "common.h"
 
 namespace ngd {
@@ -23,7 +24,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int BM = 64, BN = 64, NT = 256;
 
 template <typename E> struct Cfg;
-template <> struct Cfg<double> { static constexpr int BK = 16; };
 template <> struct Cfg<float> { static constexpr int BK = 16; };
 template <> struct Cfg<__bf16> { static constexpr int BK = 32; };
 
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
   constexpr int B_ELEMS = IS_BF ? BN * (BK + 8) : BK * (BN + 4);
   __shared__ __align__(16) E As[A_ELEMS];
   __shared__ __align__(16) E Bs[B_ELEMS];
-  using Acc = typename std::conditional<sizeof(E) == 8, d4, f4>::type;
+  using Acc = f4;
 
   const int tile = blockIdx.x;
   const int64_t m0 = (int64_t)(tile / n_tiles_n) * BM;
@@ -131,24 +131,19 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            if constexpr (sizeof(E) == 8)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
   }
-  // epilogue: lane holds column lane % 16 of each 16 x 16 tile, rows 4*(lane/16) + r for the FP32
-  // accumulating instructions and lane/16 + 4*r for v_mfma_f64_16x16x4f64 (measured lane layouts)
+  // epilogue: lane holds column lane % 16 of each 16 x 16 tile, rows 4*(lane/16) + r (the lane
+  // layout of the FP32-accumulating instructions)
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row_in_tile = sizeof(E) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int row_in_tile = 4 * (lane >> 4) + r;
         const int64_t gm = m0 + wm + i * 16 + row_in_tile;
         const int64_t gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
@@ -175,6 +170,218 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ work, int ks, in
   double v = alpha * acc;
   if (beta != 0.0) v += beta * (double)C[m * ldc + n];
   C[m * ldc + n] = (TC)v;
+}
+
+// ---- FP64 compute (v_mfma_f64_16x16x4f64) ----
+// Same tiling (64 x 64 per workgroup, 32 x 32 per wave), with K-slabs of 16 double-buffered in LDS
+// (one barrier per slab), operands fetched four consecutive elements at a time (one vector load
+// where the layout and alignment allow it) and converted to FP64 on the way into LDS. With `sym`,
+// only the tiles on and below the diagonal of C = A A^T are formed.
+constexpr int kDK = 16, kDPad = 4, kDLd = BM + kDPad;
+
+template <typename TS>
+struct DStage {
+  double v[4];
+  int r, k;
+  __device__ __forceinline__ void setup(bool kmajor) {
+    const int t = threadIdx.x;
+    if (kmajor) { r = t >> 2; k = (t & 3) * 4; }   // 4 consecutive k of one row
+    else { k = t >> 4; r = (t & 15) * 4; }         // 4 consecutive rows at one k
+  }
+  __device__ __forceinline__ void load(const TS* __restrict__ X, int64_t ld, bool kmajor, bool vec, int64_t row0,
+                                       int64_t nrows, int64_t k0, int64_t kend) {
+    const int64_t gr = row0 + r, gk = k0 + k;
+    if (kmajor) {
+      const TS* p = X + gr * ld + gk;
+      if (vec && gr < nrows && gk + 3 < kend) {
+        if constexpr (sizeof(TS) == 4) {
+          const float4 q = *reinterpret_cast<const float4*>(p);
+          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+          const double2 q0 = *reinterpret_cast<const double2*>(p), q1 = *reinterpret_cast<const double2*>(p + 2);
+          v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (gr < nrows && gk + j < kend) ? (double)p[j] : 0.0;
+      }
+    } else {
+      const TS* p = X + gk * ld + gr;
+      if (vec && gk < kend && gr + 3 < nrows) {
+        if constexpr (sizeof(TS) == 4) {
+          const float4 q = *reinterpret_cast<const float4*>(p);
+          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+          const double2 q0 = *reinterpret_cast<const double2*>(p), q1 = *reinterpret_cast<const double2*>(p + 2);
+          v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (gk < kend && gr + j < nrows) ? (double)p[j] : 0.0;
+      }
+    }
+  }
+  // LDS tile [k][row] (pitch kDLd)
+  __device__ __forceinline__ void store(double* lds, bool kmajor) const {
+    if (kmajor) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lds[(k + j) * kDLd + r] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lds[k * kDLd + r + j] = v[j];
+    }
+  }
+};
+
+// lower tile t (row-major over the lower triangle) -> (tile row, tile column)
+__device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
+  int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((m + 1) * (m + 2) / 2 <= t) ++m;
+  while (m * (m + 1) / 2 > t) --m;
+  tm = m;
+  tn = t - m * (m + 1) / 2;
+}
+
+template <typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(NT) void dgemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
+                                                   int64_t lda, int a_kmajor, int a_vec, const TB* __restrict__ B,
+                                                   int64_t ldb, int b_kmajor, int b_vec, TC* __restrict__ C,
+                                                   int64_t ldc, double alpha, double beta, int n_tiles_n, int sym,
+                                                   int64_t kchunk, double* __restrict__ work) {
+  __shared__ __align__(16) double As[2][kDK * kDLd];
+  __shared__ __align__(16) double Bs[2][kDK * kDLd];
+  int tm, tn;
+  if (sym) lower_tile((int)blockIdx.x, tm, tn);
+  else { tm = (int)blockIdx.x / n_tiles_n; tn = (int)blockIdx.x % n_tiles_n; }
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  DStage<TA> sa;
+  DStage<TB> sb;
+  sa.setup(a_kmajor);
+  sb.setup(b_kmajor);
+  const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+  const int64_t kend = (kbeg + kchunk) < K ? (kbeg + kchunk) : K;
+  sa.load(A, lda, a_kmajor, a_vec, m0, M, kbeg, kend);
+  sb.load(B, ldb, b_kmajor, b_vec, n0, N, kbeg, kend);
+  sa.store(As[0], a_kmajor);
+  sb.store(Bs[0], b_kmajor);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kDK) {
+    const bool more = k0 + kDK < kend;
+    if (more) {
+      sa.load(A, lda, a_kmajor, a_vec, m0, M, k0 + kDK, kend);
+      sb.load(B, ldb, b_kmajor, b_vec, n0, N, k0 + kDK, kend);
+    }
+    const double* as = As[buf];
+    const double* bs = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < kDK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[i] = as[kr * kDLd + wm + i * 16 + (lane & 15)];
+        b[i] = bs[kr * kDLd + wn + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      sa.store(As[buf ^ 1], a_kmajor);
+      sb.store(Bs[buf ^ 1], b_kmajor);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane holds column lane % 16 of each 16 x 16 tile, rows lane / 16 + 4 r
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int64_t gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          if (work != nullptr) {
+            work[((int64_t)blockIdx.y * M + gm) * N + gn] = acc[i][j][r];
+          } else {
+            double v = alpha * acc[i][j][r];
+            if (beta != 0.0) v += beta * (double)C[gm * ldc + gn];
+            C[gm * ldc + gn] = (TC)v;
+            if (sym == 1 && tm != tn) {
+              double w = alpha * acc[i][j][r];
+              if (beta != 0.0) w += beta * (double)C[gn * ldc + gm];
+              C[gn * ldc + gm] = (TC)w;
+            }
+          }
+        }
+      }
+}
+
+// split-K reduction of a symmetric product: tiles above the diagonal read their mirror (sym == 1)
+// or are skipped (sym == 2)
+template <typename TC>
+__global__ void splitk_reduce_sym_kernel(const double* __restrict__ work, int ks, int64_t M, TC* __restrict__ C,
+                                         int64_t ldc, double alpha, double beta, int sym) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * M) return;
+  const int64_t m = idx / M, n = idx - m * M;
+  const bool lower = m / BM >= n / BN;
+  if (!lower && sym == 2) return;
+  const int64_t src = lower ? idx : n * M + m;
+  double acc = 0.0;
+  for (int s = 0; s < ks; ++s) acc += work[(int64_t)s * M * M + src];
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * (double)C[m * ldc + n];
+  C[m * ldc + n] = (TC)v;
+}
+
+template <typename TS>
+bool vec_ok(const void* p, int64_t ld) {
+  const int per = sizeof(TS) == 4 ? 4 : 2;
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && ld % per == 0;
+}
+
+template <typename TA, typename TB, typename TC>
+ngd_status run_f64(const GemmArgs& g, hipStream_t s) {
+  const int tn = (int)((g.N + BN - 1) / BN), tm = (int)((g.M + BM - 1) / BM);
+  if (g.sym && (g.M != g.N || tm != tn)) {
+    set_error("gemm: a symmetric product must be square");
+    return NGD_ERR_INVALID;
+  }
+  const int64_t tiles = g.sym ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tn * tm;
+  if (tiles == 0) return NGD_OK;
+  int ks = 1;
+  if (g.work != nullptr && g.work_elems > 0) {
+    while (tiles * ks * 2 <= 1024 && g.K / (ks * 2) >= 8 * kDK && (int64_t)ks * 2 * g.M * g.N <= g.work_elems) ks *= 2;
+  }
+  const int64_t kchunk = ks == 1 ? g.K : ((g.K + ks - 1) / ks + kDK - 1) / kDK * kDK;
+  const int av = vec_ok<TA>(g.A, g.lda), bv = vec_ok<TB>(g.B, g.ldb);
+  hipLaunchKernelGGL((dgemm_kernel<TA, TB, TC>), dim3((unsigned)tiles, (unsigned)ks), dim3(NT), 0, s, g.M, g.N, g.K,
+                     (const TA*)g.A, g.lda, (int)g.a_kmajor, av, (const TB*)g.B, g.ldb, (int)g.b_kmajor, bv,
+                     (TC*)g.C, g.ldc, g.alpha, g.beta, tn, g.sym, kchunk, ks > 1 ? g.work : nullptr);
+  NGD_HIP_TRY(hipGetLastError());
+  if (ks > 1) {
+    const int64_t mn = g.M * g.N;
+    if (g.sym)
+      hipLaunchKernelGGL(splitk_reduce_sym_kernel<TC>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.work, ks,
+                         g.M, (TC*)g.C, g.ldc, g.alpha, g.beta, g.sym);
+    else
+      hipLaunchKernelGGL(splitk_reduce_kernel<TC>, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.work, ks,
+                         g.M, g.N, (TC*)g.C, g.ldc, g.alpha, g.beta);
+    NGD_HIP_TRY(hipGetLastError());
+  }
+  return NGD_OK;
 }
 
 template <typename TA, typename TB, typename TC, typename E>
@@ -205,14 +412,29 @@ ngd_status run(const GemmArgs& g, hipStream_t s) {
 template <typename E>
 ngd_status dispatch_types(const GemmArgs& g, hipStream_t s) {
   const bool a64 = g.a_type == NGD_F64, b64 = g.b_type == NGD_F64, c64 = g.c_type == NGD_F64;
-  if (a64 && b64 && c64) return run<double, double, double, E>(g, s);
-  if (!a64 && !b64 && !c64) return run<float, float, float, E>(g, s);
-  if (!a64 && !b64 && c64) return run<float, float, double, E>(g, s);
-  if (!a64 && b64 && c64) return run<float, double, double, E>(g, s);
-  if (!a64 && b64 && !c64) return run<float, double, float, E>(g, s);
-  if (a64 && !b64 && !c64) return run<double, float, float, E>(g, s);
-  if (a64 && !b64 && c64) return run<double, float, double, E>(g, s);
-  return run<double, double, float, E>(g, s);
+  if constexpr (sizeof(E) == 8) {
+    if (a64 && b64 && c64) return run_f64<double, double, double>(g, s);
+    if (!a64 && !b64 && !c64) return run_f64<float, float, float>(g, s);
+    if (!a64 && !b64 && c64) return run_f64<float, float, double>(g, s);
+    if (!a64 && b64 && c64) return run_f64<float, double, double>(g, s);
+    if (!a64 && b64 && !c64) return run_f64<float, double, float>(g, s);
+    if (a64 && !b64 && !c64) return run_f64<double, float, float>(g, s);
+    if (a64 && !b64 && c64) return run_f64<double, float, double>(g, s);
+    return run_f64<double, double, float>(g, s);
+  } else {
+    if (g.sym) {
+      set_error("gemm: symmetric products need FP64 compute");
+      return NGD_ERR_INVALID;
+    }
+    if (a64 && b64 && c64) return run<double, double, double, E>(g, s);
+    if (!a64 && !b64 && !c64) return run<float, float, float, E>(g, s);
+    if (!a64 && !b64 && c64) return run<float, float, double, E>(g, s);
+    if (!a64 && b64 && c64) return run<float, double, double, E>(g, s);
+    if (!a64 && b64 && !c64) return run<float, double, float, E>(g, s);
+    if (a64 && !b64 && !c64) return run<double, float, float, E>(g, s);
+    if (a64 && !b64 && c64) return run<double, float, double, E>(g, s);
+    return run<double, double, float, E>(g, s);
+  }
 }
 
 }  // namespace

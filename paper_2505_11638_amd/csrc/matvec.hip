@@ -147,7 +147,7 @@ __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, 
         int64_t c = threadIdx.x + (int64_t)k * blockDim.x;
         if (c < nchunk) dot[q] += dot_vec<T>(cur[q][k], vs + c * VN);
       }
-      dot[q] = wave_sum(dot[q]);
+      dot[q] = wave_sum_dpp(dot[q]);
     }
     if (lane == 0)
 #pragma unroll
