@@ -60,13 +60,18 @@ struct ngd_problem {
   double* F;         // ell x ell
   double* evals;     // ell
   double* gemm_work; // split-K partials of the ell x ell Gram products (8 ell^2)
-  double* cholblk;   // the Cholesky's diagonal-block factors (ceil(ell / 32) x 32 x 32)
+  unsigned* cholsync;  // the Cholesky's row-block flags (2 x 64) and error word
+  unsigned chol_epoch = 0;
   void* eigw;        // eig workspace
   void* trial;       // kTrials x ldP, dtype (line search)
   double* alphas;    // kTrials
   double* losses;    // kTrials
   // pinned host staging
   void* host;
+  // a second stream (default priority) for sketch work that is independent of the FP64 core, and
+  // the events that fork it from and join it to the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // kernel timers
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -287,7 +292,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->evals, sizeof(double) * (size_t)L});
   plan.push_back({(void**)&h->gemm_work, sizeof(double) * 8 * (size_t)L * L});
-  plan.push_back({(void**)&h->cholblk, sizeof(double) * 1024 * (size_t)((L + 31) / 32)});
+  plan.push_back({(void**)&h->cholsync, sizeof(unsigned) * 256});
   plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
   plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
   plan.push_back({(void**)&h->nvec[0], sizeof(double) * (size_t)N});
@@ -316,7 +321,20 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   }
   h->base = base;
   h->bytes = total;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->side) (void)hipStreamDestroy(h->side);
+    (void)hipFree(h->base);
+    delete h;
+    set_error("hipStreamCreate / hipEventCreate failed");
+    return NGD_ERR_HIP;
+  }
   if (hipHostMalloc(&h->host, 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipEventDestroy(h->ev_join);
+    (void)hipEventDestroy(h->ev_fork);
+    (void)hipStreamDestroy(h->side);
     (void)hipFree(base);
     delete h;
     set_error("hipHostMalloc failed");
@@ -330,6 +348,12 @@ ngd_status ngd_problem_destroy(ngd_problem* h) {
   if (h == nullptr) return NGD_OK;
   (void)flush_timers(h);
   for (hipEvent_t e : h->ev_free) (void)hipEventDestroy(e);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   (void)hipFree(h->base);
   (void)hipHostFree(h->host);
   delete h;
@@ -481,11 +505,16 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
     return launch_gemm(g1, s);
   }));
-  // J^T in the compute type for the second product; independent of the core below
-  if (nt)
-    NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, s, [&] {
-      return launch_transpose_cast(NGD_F32, op->J, op->ldJ, N, P, et, h->Jt, h->ldN, s);
+  // J^T in the compute type for the second product, on the side stream: it overlaps the
+  // latency-bound FP64 core below and is joined before the product that reads it
+  if (nt) {
+    NGD_HIP_TRY(hipEventRecord(h->ev_fork, s));
+    NGD_HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, h->side, [&] {
+      return launch_transpose_cast(NGD_F32, op->J, op->ldJ, N, P, et, h->Jt, h->ldN, h->side);
     }));
+    NGD_HIP_TRY(hipEventRecord(h->ev_join, h->side));
+  }
   // M = Z^T Z (FP64), eigenpairs, whitening F = V_M D^{-1/2} (pseudo-inverse of the core), and
   // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
@@ -494,12 +523,13 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     NGD_TRY(launch_gemm(g2, s));
     // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
     NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
-                                    reinterpret_cast<int*>(h->scal + 210), h->cholblk, s));
+                                    reinterpret_cast<int*>(h->scal + 210), h->cholsync, ++h->chol_epoch, s));
     // one launch: Q in FP64 where a product reads it, Q^T in the compute type on the NT path
     return launch_trsm_q(h->M, (int)L, T, h->Z, N, nt ? nullptr : (double*)h->Q, et, nt ? h->Qt : nullptr, h->ldN,
                          s);
   }));
   // B^T = Q^T J (ell x P); on the NT path as (J^T Q)^T with Q^T in the compute type
+  if (nt) NGD_HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
     if (rec) {
       for (int64_t j = 0; j < L; ++j) {
@@ -531,11 +561,16 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     std::vector<double> lh(L), core(16);
     NGD_HIP_TRY(hipMemcpyAsync(lh.data(), lam_hat, sizeof(double) * L, hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipMemcpyAsync(core.data(), h->scal + 200, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
-    int err = 0;
+    int err = 0, cerr = 0;
     NGD_HIP_TRY(hipMemcpyAsync(&err, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipMemcpyAsync(&cerr, h->cholsync + 128, sizeof(int), hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
     if (err) {
       set_error("exchange between the workgroups of the tridiagonalisation timed out");
+      return NGD_ERR_HIP;
+    }
+    if (cerr) {
+      set_error("exchange between the workgroups of the Cholesky factorisation timed out");
       return NGD_ERR_HIP;
     }
     int nmod = 0;

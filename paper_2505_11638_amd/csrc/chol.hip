@@ -1,9 +1,9 @@
 // Shifted Cholesky of the ell x ell core M + nu I = L L^T and the triangular solve Q = Z L^{-T}
-// (Alg. 6: C = chol(Omega^T Y_nu), B = Y_nu / C):
-//  * Cholesky, by panels of kNb columns: one workgroup factors the kNb x kNb diagonal block in LDS,
-//    the rows below are solved, L21 = A21 L11^{-T}, one row per thread, and the trailing matrix is
-//    updated with one MFMA GEMM, A22 -= L21 L21^T.
-//  * Triangular solve: one launch, 16 rows of Z per workgroup (trsm_q_kernel below).
+// (Alg. 6: C = chol(Omega^T Y_nu), B = Y_nu / C), one launch each, both by 16-row blocks on the
+// FP64 matrix cores:
+//  * Cholesky: left-looking, one workgroup per row block, row blocks exchanged through flags
+//    (chol_rows_kernel).
+//  * Triangular solve: 16 rows of Z per workgroup (trsm_q_kernel).
 // A pivot that is not safely positive is replaced by a floor (pivot^2 = `floor`), so the
 // factorisation never fails; the directions involved are left shrunk in Q (the effect of the
 // shift nu in Alg. 6). Their count is reported as a rank deficit.
@@ -13,127 +13,6 @@
 
 namespace ngd {
 namespace {
-
-constexpr int kNb = 32;
-constexpr int kLd = kNb + 1;  // LDS row pitch of a staged block
-
-// factor the nb x nb diagonal block at (j0, j0) of A (ld n) into Ls (LDS, lower, kNb x kLd). The block
-// is factored by wave 0 alone, in registers: lane l holds row l % 32, columns l / 32, l / 32 + 2, ...
-// Per column c the pivot is read from its lane, the column is scaled by the lanes that hold it and
-// published through LDS, and every lane applies the rank-1 update to its 16 entries; a wave needs no
-// workgroup barrier for any of this.
-__device__ void factor_diag(const double* __restrict__ A, int n, int j0, int nb, double floor, double null_thresh,
-                            double* Ls, int* nmod) {
-  __shared__ double col[kNb];
-  const int t = threadIdx.x;
-  if (t < 64) {
-    const int r = t & 31, h = t >> 5;
-    double a[kNb / 2];
-#pragma unroll
-    for (int i = 0; i < kNb / 2; ++i) {
-      const int c = h + 2 * i;
-      a[i] = (r < nb && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : 0.0;
-    }
-    int nulls = 0;
-#pragma unroll
-    for (int c = 0; c < kNb; ++c) {
-      if (c < nb) {
-        const int owner = c + 32 * (c & 1);
-        double piv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(a[c >> 1]), owner),
-                                      __builtin_amdgcn_readlane(__double2loint(a[c >> 1]), owner));
-        if (!(piv > null_thresh)) ++nulls;  // direction at the level of the shift: numerically null
-        if (!(piv > floor)) piv = floor;
-        const double d = sqrt(piv), rd = 1.0 / d;
-        if (h == (c & 1)) {
-          if (r == c) a[c >> 1] = d;
-          else if (r > c && r < nb) a[c >> 1] *= rd;
-          col[r] = (r > c && r < nb) ? a[c >> 1] : 0.0;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double lr = col[r];
-#pragma unroll
-        for (int i = 0; i < kNb / 2; ++i) {
-          const int q = h + 2 * i;
-          if (q > c && q <= r) a[i] -= lr * col[q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kNb / 2; ++i) {
-      const int c = h + 2 * i;
-      Ls[r * kLd + c] = (r < nb && c <= r) ? a[i] : 0.0;
-    }
-    if (t == 0 && nmod) *nmod += nulls;
-  }
-  __syncthreads();
-}
-
-// one row x (nb values) of X: solve x L^T = x in place; L lower in LDS (pitch kLd), rdiag its
-// reciprocal diagonal
-__device__ __forceinline__ void solve_row(double* __restrict__ x, const double* Ls, const double* rdiag, int nb) {
-  double v[kNb];
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) v[j] = j < nb ? x[j] : 0.0;
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    if (j < nb) {
-      double s = v[j];
-#pragma unroll
-      for (int k = 0; k < kNb; ++k)
-        if (k < j) s -= v[k] * Ls[j * kLd + k];
-      v[j] = s * rdiag[j];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kNb; ++j)
-    if (j < nb) x[j] = v[j];
-}
-
-// One Cholesky panel: every workgroup factors the diagonal block of panel j0 in LDS (workgroup 0
-// also stores the factor in Lblk and counts the null pivots), then solves its share of the rows
-// below, L21 = A21 L11^{-T}, one row per thread. Fusing the two saves a launch and a dependency per
-// panel; the factor goes to Lblk, not back into A, because the other workgroups are still reading
-// A's diagonal block (copy_diag_blocks_kernel moves all factors into place at the end).
-__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int n, int j0, int nb,
-                                                         const double* __restrict__ floor_p, int* __restrict__ nmod,
-                                                         double* __restrict__ Lblk) {
-  __shared__ double Ls[kNb * kLd];
-  __shared__ double rdiag[kNb];
-  __shared__ int local_mod;
-  if (threadIdx.x == 0) local_mod = 0;
-  __syncthreads();
-  factor_diag(A, n, j0, nb, floor_p[0], floor_p[2], Ls, &local_mod);
-  if (blockIdx.x == 0) {
-    double* dst = Lblk + (int64_t)(j0 / kNb) * kNb * kNb;
-    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
-      const int r = e >> 5, c = e & 31;
-      dst[e] = (r < nb && c <= r) ? Ls[r * kLd + c] : 0.0;
-    }
-    if (threadIdx.x == 0) *nmod += local_mod;
-  }
-  if (threadIdx.x < kNb) rdiag[threadIdx.x] = threadIdx.x < nb ? 1.0 / Ls[threadIdx.x * kLd + threadIdx.x] : 0.0;
-  __syncthreads();
-  const int64_t below = n - j0 - nb;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < below) solve_row(A + (j0 + nb + r) * (int64_t)n + j0, Ls, rdiag, nb);
-}
-
-// the diagonal factors from Lblk into A's diagonal blocks (upper part of each block zeroed)
-__global__ __launch_bounds__(256) void copy_diag_blocks_kernel(double* __restrict__ A, int n,
-                                                               const double* __restrict__ Lblk) {
-  const int j0 = blockIdx.x * kNb;
-  const int nb = min(kNb, n - j0);
-  const double* src = Lblk + (int64_t)blockIdx.x * kNb * kNb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
-    const int r = e >> 5, c = e & 31;
-    if (r < nb && c < nb) A[(int64_t)(j0 + r) * n + j0 + c] = src[e];
-  }
-}
 
 // ---- Q = Z L^{-T} in one launch (FP64 matrix cores) ----
 // A workgroup (4 or 8 waves) owns 16 rows of Z and sweeps the ell columns in 16-column panels J:
@@ -281,6 +160,208 @@ ngd_status run_trsm_q(const double* L, int ell, const void* Z, int64_t N, double
   return NGD_OK;
 }
 
+// ---- Shifted Cholesky in one launch ----
+// Left-looking by 16-row blocks: workgroup R owns rows 16R .. 16R+15 and forms, panel by panel,
+//   L_RJ = (M_RJ - L_R,<J L_J,<J^T) L_JJ^{-T}   (J < R, as in trsm_q_kernel),
+//   L_RR = chol(M_RR - L_R,<R L_R,<R^T)         (the owner wave, in registers),
+// storing L over M. Row block J is read only after workgroup J has published it: the workgroup
+// stores its rows with device-coherent (sc1) stores, waits for them to complete and then sets a
+// flag to this call's epoch, one for L_J,<J (the products with it can start) and one, after the
+// diagonal factorisation, for L_JJ; readers poll the flags (one lane per wave) and read the rows
+// with device-coherent loads. All ceil(n / 16) workgroups are resident at once (checked), every wait is
+// bounded, and workgroup R depends only on lower-numbered ones.
+__device__ __forceinline__ void st_co(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_co(double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// flags: [0, 64) off-diagonal part of row block R final (A), [64, 128) diagonal block final (B)
+constexpr int kCholFlagsB = 64;
+
+__device__ __forceinline__ void wait_flag(unsigned* f, unsigned epoch, int* err) {
+  long spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    if (++spins > (1L << 24)) {  // seconds: give up instead of hanging
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+}
+
+template <int MAXS, int W>
+__global__ __launch_bounds__(64 * W) void chol_rows_kernel(double* __restrict__ M, int n,
+                                                           const double* __restrict__ fl, int* __restrict__ nmod,
+                                                           unsigned* __restrict__ flags, unsigned epoch,
+                                                           int* __restrict__ err) {
+  __shared__ double Sp[2][W][256];
+  __shared__ double Ld[2][16][17];
+  __shared__ double Rd[2][16];
+  __shared__ double col[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int R = blockIdx.x, r0 = 16 * R;
+  const int row = r0 + lr;
+  const double floor = fl[0], null_thresh = fl[2];
+  tq_d4 X[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) X[s] = tq_d4{0.0, 0.0, 0.0, 0.0};
+  for (int J = 0; J <= R; ++J) {
+    const int j0 = 16 * J, par = J & 1, owner = J % W;
+    const bool own = wid == owner, diag = J == R;
+    // the owner's block of M (row lr, columns j0 + 4 lq + r), independent of the other workgroups
+    double zv[4], ldv[4], rdv = 0.0;
+    if (own) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = j0 + 4 * lq + r;
+        zv[r] = (row < n && c < n && c <= row) ? M[(int64_t)row * n + c] : 0.0;
+      }
+    }
+    if (!diag && lane == 0) wait_flag(flags + J, epoch, err);  // L_J,<J is final
+    // this wave's share of S^T = L_J,<J L_R,<J^T over the tiles t < J held here (t % W == wid); the
+    // rows of L_J come from workgroup J, or are this workgroup's own tiles when J == R
+    // (all loads issued before the first product, so that their latencies overlap)
+    tq_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const bool lrow = j0 + lr < n;
+    double* Lrow = M + (int64_t)(j0 + lr) * n + 4 * lq;
+    double a[MAXS][4];
+    if (!diag) {
+#pragma unroll
+      for (int s = 0; s < MAXS; ++s) {
+        const int t = wid + W * s;
+        if (t < J && lrow) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[s][r] = ld_co(Lrow + 16 * t + r);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      const int t = wid + W * s;
+      if (t < J) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double av = diag ? X[s][r] : (lrow ? a[s][r] : 0.0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, X[s][r], acc, 0, 0, 0);
+        }
+      }
+    }
+    if (own && !diag) {
+      if (lane == 0) wait_flag(flags + kCholFlagsB + J, epoch, err);  // L_JJ is final
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u, ra = e >> 4, cb = e & 15;
+        ldv[u] = (j0 + ra < n && cb <= ra) ? ld_co(M + (int64_t)(j0 + ra) * n + j0 + cb) : 0.0;
+      }
+      if (lane < 16 && j0 + lane < n) rdv = ld_co(M + (int64_t)(j0 + lane) * n + j0 + lane);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u;
+        Ld[par][e >> 4][e & 15] = ldv[u];
+      }
+      if (lane < 16) Rd[par][lane] = rdv != 0.0 ? 1.0 / rdv : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Sp[par][wid][(lq + 4 * r) * 16 + lr] = acc[r];
+    __syncthreads();
+    if (diag) {
+      // every wave's stores of L_R,<R complete, then flag A: the later row blocks can form their
+      // products with L_R,<R while the owner factors L_RR
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(flags + R, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!own) break;
+    } else if (!own) {
+      continue;
+    }
+    double b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 4 * lq + r;
+      double sv = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) sv += Sp[par][w][c * 16 + lr];
+      b[r] = zv[r] - sv;
+    }
+    if (!diag) {
+      // L_RJ = b L_JJ^{-T} by forward substitution over the 16 columns
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double xc = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * lq + r == c) xc = b[r] * Rd[par][c];
+        xc = __shfl(xc, lr + 16 * (c >> 2), 64);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cc = 4 * lq + r;
+          if (cc == c) b[r] = xc;
+          else if (cc > c) b[r] -= xc * Ld[par][cc][c];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < MAXS; ++s)
+        if (owner + W * s == J) X[s] = tq_d4{b[0], b[1], b[2], b[3]};
+      if (row < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = j0 + 4 * lq + r;
+          if (c < n) st_co(M + (int64_t)row * n + c, b[r]);
+        }
+      }
+    } else {
+      // L_RR = chol(b): column by column, the pivot from its lane, the column published through LDS
+      int nulls = 0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (j0 + c < n) {
+          const int src = c + 16 * (c >> 2);
+          double piv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(b[c & 3]), src),
+                                        __builtin_amdgcn_readlane(__double2loint(b[c & 3]), src));
+          if (!(piv > null_thresh)) ++nulls;  // direction at the level of the shift: numerically null
+          if (!(piv > floor)) piv = floor;
+          // 1 / sqrt(piv) from the hardware estimate and two Newton steps; sqrt(piv) = piv / sqrt(piv)
+          double rd = __builtin_amdgcn_rsq(piv);
+          rd = rd * fma(-0.5 * piv * rd, rd, 1.5);
+          rd = rd * fma(-0.5 * piv * rd, rd, 1.5);
+          const double d = piv * rd;
+          if (lq == (c >> 2)) {
+            if (lr == c) b[c & 3] = d;
+            else if (lr > c) b[c & 3] *= rd;
+            col[lr] = lr > c ? b[c & 3] : 0.0;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const double l_r = col[lr];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = 4 * lq + r;
+            if (q > c && q <= lr) b[r] -= l_r * col[q];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+      if (row < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = j0 + 4 * lq + r;
+          if (c < n) st_co(M + (int64_t)row * n + c, c <= row ? b[r] : 0.0);
+        }
+      }
+      if (lane == 0 && nulls) atomicAdd(nmod, nulls);
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) __hip_atomic_store(flags + kCholFlagsB + R, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // nu = shift_rel * trace(M) added to the diagonal; floor = floor_rel * trace(M)
 __global__ void shift_kernel(double* __restrict__ M, int n, double shift_rel, double floor_rel,
                              double* __restrict__ floor_out, int* __restrict__ nmod) {
@@ -300,30 +381,39 @@ __global__ void shift_kernel(double* __restrict__ M, int n, double shift_rel, do
 
 }  // namespace
 
-// L (lower, in place of M) with L L^T = M + nu I, nu = shift_rel tr(M). `scal` holds 3 doubles
-// (floor, nu, null threshold) and `nmod` the count of null pivots (both device); Lblk holds
-// ceil(n / 32) 32 x 32 blocks of scratch.
+// L (lower, in place of M; the upper part of the diagonal blocks zeroed) with L L^T = M + nu I,
+// nu = shift_rel tr(M). `scal` holds 3 doubles (floor, nu, null threshold) and `nmod` the count of
+// null pivots (both device). `sync` is the device word block of the launch (two sets of 64 flags and
+// the error word at index 128), `epoch` a value that differs from every earlier call's.
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
-                                   double* Lblk, hipStream_t s) {
+                                   unsigned* sync, unsigned epoch, hipStream_t s) {
+  if (n <= 0) return NGD_OK;
+  if (n > kMaxEll) {
+    set_error("cholesky: n above 1024");
+    return NGD_ERR_INVALID;
+  }
   hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(256), 0, s, M, n, shift_rel, floor_rel, scal, nmod);
   NGD_HIP_TRY(hipGetLastError());
-  for (int j0 = 0; j0 < n; j0 += kNb) {
-    const int nb = std::min(kNb, n - j0);
-    const int below = n - j0 - nb;
-    // L11 and L21 = A21 L11^{-T} in one launch
-    const unsigned wgs = (unsigned)std::max(1, (below + 255) / 256);
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(wgs), dim3(256), 0, s, M, n, j0, nb, scal, nmod, Lblk);
-    NGD_HIP_TRY(hipGetLastError());
-    if (below > 0) {
-      // A22 -= L21 L21^T
-      const int t0 = j0 + nb;
-      GemmArgs g{below, below, nb, M + (int64_t)t0 * n + j0, n, true, M + (int64_t)t0 * n + j0, n, true,
-                 M + (int64_t)t0 * n + t0, n, NGD_F64, NGD_F64, NGD_F64, G_F64, -1.0, 1.0, nullptr, 0, 2};
-      ngd_status st = launch_gemm(g, s);
-      if (st != NGD_OK) return st;
-    }
+  const int ntile = (n + 15) / 16;
+  int* err = reinterpret_cast<int*>(sync + 2 * kCholFlagsB);
+  int dev = 0, cus = 0;
+  NGD_HIP_TRY(hipGetDevice(&dev));
+  NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (ntile > cus) {
+    set_error("cholesky grid cannot be co-resident");
+    return NGD_ERR_HIP;
   }
-  hipLaunchKernelGGL(copy_diag_blocks_kernel, dim3((unsigned)((n + kNb - 1) / kNb)), dim3(256), 0, s, M, n, Lblk);
+#define NGD_CH(S, W)                                                                                        \
+  hipLaunchKernelGGL((chol_rows_kernel<S, W>), dim3(ntile), dim3(64 * W), 0, s, M, n, (const double*)scal, nmod, \
+                     sync, epoch, err)
+  // eight waves beyond eight row blocks: fewer tiles per wave leaves registers for the loads
+  const int s4 = (ntile + 3) / 4, s8 = (ntile + 7) / 8;
+  if (s4 <= 2) NGD_CH(2, 4);
+  else if (s8 <= 2) NGD_CH(2, 8);
+  else if (s8 <= 4) NGD_CH(4, 8);
+  else if (s8 <= 6) NGD_CH(6, 8);
+  else NGD_CH(8, 8);
+#undef NGD_CH
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

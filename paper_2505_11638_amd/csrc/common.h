@@ -299,7 +299,7 @@ size_t residual_lds_bytes(const NetDesc& net, int dtype, int* tp);
 
 // chol.hip: blocked shifted Cholesky of the core and the right triangular solve X <- X L^{-T}
 ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double floor_rel, double* scal, int* nmod,
-                                   double* Lblk, hipStream_t s);
+                                   unsigned* sync, unsigned epoch, hipStream_t s);
 ngd_status launch_trsm_q(const double* L, int ell, int z_type, const void* Z, int64_t N, double* Q, int qt_type,
                          void* Qt, int64_t ldqt, hipStream_t s);
 

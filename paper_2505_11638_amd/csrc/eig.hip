@@ -541,48 +541,65 @@ __global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, co
   }
 }
 
-// Back-transformation V = H_0 H_1 ... H_{n-3} Z with the reflectors taken kNb at a time in compact
+// Back-transformation V = H_0 H_1 ... H_{n-3} Z with the reflectors taken kWy at a time in compact
 // WY form: H_k0 ... H_k1 = I - Y T Y^T (Y = [v_k0 .. v_k1], T upper triangular, built as in the
 // forward-accumulation recurrence T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] Y[:, 0:i]^T v_i).
 constexpr int kWy = 16;   // reflectors per block
 
-// T of every block of wy (<= kWy) reflectors (one workgroup per block), stored kWy x kWy per block
+// T of every block of kWy reflectors (one workgroup per block), stored kWy x kWy per block. The
+// Gram matrix G = Y^T Y of the block's reflectors is one 16 x 16 FP64 MFMA product over n (the four
+// waves split n; with the contraction index of K-step r taken as 4 (l / 16) + r, the same four
+// doubles of a lane are its A and its B operand); then T column by column, the rows of a column in
+// parallel: T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].
+typedef double wy_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V, const double* __restrict__ tau, int n,
-                                                   int wy, double* __restrict__ Tall) {
+                                                   double* __restrict__ Tall) {
   const int nref = n - 2;
-  const int k0 = blockIdx.x * wy;
-  const int m = min(wy, nref - k0);
-  __shared__ double Gm[kWy][kWy];
-  __shared__ double Ts[kWy][kWy];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  // Gm[a][i] = v_{k0+a} . v_{k0+i} for a < i (one wave per pair)
-  for (int q = wid; q < kWy * kWy; q += nw) {
-    const int a = q / kWy, i = q % kWy;
-    double acc = 0.0;
-    if (a < i && i < m) {
-      const double* va = V + (int64_t)(k0 + a) * n;
-      const double* vi = V + (int64_t)(k0 + i) * n;
-      for (int j = k0 + i + 1 + lane; j < n; j += 64) acc += va[j] * vi[j];
-      acc = wave_sum(acc);
+  const int k0 = blockIdx.x * kWy;
+  const int m = min(kWy, nref - k0);
+  __shared__ double Gp[4][256];
+  __shared__ double Gm[kWy][kWy + 1];
+  __shared__ double Ts[kWy][kWy + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const bool rv = lr < m;
+  const double* vrow = V + (int64_t)(k0 + (rv ? lr : 0)) * n;
+  const int nslab = (n + 15) / 16;
+  wy_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int sl = wid; sl < nslab; sl += 4) {
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * sl + 4 * lq + r;
+      v[r] = (rv && j < n) ? vrow[j] : 0.0;
     }
-    if (lane == 0) Gm[a][i] = acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r], v[r], acc, 0, 0, 0);
+  }
+  // accumulator element r: G(lq + 4 r, lr)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Gp[wid][(lq + 4 * r) * 16 + lr] = acc[r];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int a = threadIdx.x >> 4, i = threadIdx.x & 15;
+    Gm[a][i] = Gp[0][threadIdx.x] + Gp[1][threadIdx.x] + Gp[2][threadIdx.x] + Gp[3][threadIdx.x];
+    Ts[a][i] = 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < kWy; ++i)
-      for (int a = 0; a < kWy; ++a) Ts[a][i] = 0.0;
-    for (int i = 0; i < m; ++i) {
-      const double t = tau[k0 + i];
-      for (int a = 0; a < i; ++a) {
-        double acc = 0.0;
-        for (int b = a; b < i; ++b) acc += Ts[a][b] * Gm[b][i];
-        Ts[a][i] = -t * acc;
-      }
+  for (int i = 0; i < m; ++i) {
+    const double t = tau[k0 + i];
+    const int a = threadIdx.x;
+    if (a < i) {
+      double sum = 0.0;
+      for (int b = a; b < i; ++b) sum += Ts[a][b] * Gm[b][i];
+      Ts[a][i] = -t * sum;
+    } else if (a == i) {
       Ts[i][i] = t;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x) Tall[(int64_t)blockIdx.x * kWy * kWy + e] = (&Ts[0][0])[e];
+  for (int e = threadIdx.x; e < kWy * kWy; e += blockDim.x)
+    Tall[(int64_t)blockIdx.x * kWy * kWy + e] = Ts[e / kWy][e % kWy];
 }
 
 // The same back-transformation on the FP64 matrix cores, for n <= kBtMaxN. A workgroup owns 16
@@ -858,7 +875,7 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   double* Tall = ws.Tall;
   if (n <= kBtMaxN) {
     const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
-    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, kWy, Tall);
+    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, Tall);
     const int nt = (n + 15) / 16;
     const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kBtWaves * 256);
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_mfma_kernel,

@@ -14,6 +14,8 @@
 // workgroup's MFMA work covers this one's load latency). Tiles are numbered so that the workgroups that share an A
 // row panel run on the same XCD (workgroups are dealt to the 8 XCDs round-robin), where the panel
 // is then read from that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 
 namespace ngd {
@@ -108,10 +110,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const T* base, int64
                                            (int)((rows * ld - kbeg) * (int64_t)sizeof(T)), 0x00020000);
 }
 
-// Multiply one staged slab: acc[i][j] (16 x 16 tiles) += A_slab(wave rows) B_slab(wave cols)^T
-template <typename E>
+// Multiply one staged slab: acc[i][j] (16 x 16 tiles) += A_slab(wave rows) B_slab(wave cols)^T, for
+// the tiles i < imax, j < jmax that hold rows and columns of C (wave-uniform bounds: the MFMAs of
+// tiles wholly past the end of C are skipped, which frees the matrix core for the other waves)
+template <typename E, bool FULL>
 __device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigned char* Bs, int wm, int wn,
-                                          f4 (&acc)[8][4]) {
+                                          int imax, int jmax, f4 (&acc)[8][4]) {
   const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, kq = lane >> 4;
   u4 b[4];
@@ -119,9 +123,11 @@ __device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigne
   for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const u4*>(Bs + (wn + 16 * j + r16) * kPitch + 16 * kq);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
+    if (!FULL && i >= imax) break;
     const u4 a = *reinterpret_cast<const u4*>(As + (wm + 16 * i + r16) * kPitch + 16 * kq);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      if (!FULL && j >= jmax) break;
       if constexpr (sizeof(E) == 2) {
         // lane holds k = 8 kq .. 8 kq + 7 of row r16 for both operands
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b[j]),
@@ -173,24 +179,39 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = (K + BK - 1) / BK;
+  const int imax = (int)((M - m0 - wm + 15) / 16), jmax = (int)((N - n0 - wn + 15) / 16);
+  // (FP32 only: the BF16 instantiations are large enough that a second copy of the loop costs more
+  // in instruction fetch than the skipped edge tiles save)
+  const bool full = sizeof(E) == 2 || (imax >= 8 && jmax >= 4);
   la.load(ra, lda, 0, K);
   lb.load(rb, ldb, 0, K);
   la.store(As[0]);
   lb.store(Bs[0]);
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    const bool more = kt + 1 < nk;
-    if (more) {
-      la.load(ra, lda, (kt + 1) * BK, K);
-      lb.load(rb, ldb, (kt + 1) * BK, K);
+  // the K loop, with the tile bounds checked only in workgroups that hold an edge of C (the branch
+  // is taken once, outside the loop, so the loads in flight across iterations are not waited for)
+  auto kloop = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = (int)(kt & 1);
+      const bool more = kt + 1 < nk;
+      if (more) {
+        la.load(ra, lda, (kt + 1) * BK, K);
+        lb.load(rb, ldb, (kt + 1) * BK, K);
+      }
+      slab_mfma<E, FULL>(As[cur], Bs[cur], wm, wn, imax, jmax, acc);
+      if (more) {
+        la.store(As[cur ^ 1]);
+        lb.store(Bs[cur ^ 1]);
+      }
+      __syncthreads();
     }
-    slab_mfma<E>(As[cur], Bs[cur], wm, wn, acc);
-    if (more) {
-      la.store(As[cur ^ 1]);
-      lb.store(Bs[cur ^ 1]);
-    }
-    __syncthreads();
+  };
+  if constexpr (sizeof(E) == 2) {
+    kloop(std::true_type{});
+  } else {
+    if (full) kloop(std::true_type{});
+    else kloop(std::false_type{});
   }
 
   // epilogue: lane holds column lane % 16 and rows 4 (lane / 16) + r of each 16 x 16 tile
@@ -265,11 +286,28 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
   if (tiles == 0) return NGD_OK;
   const int64_t per = (tiles + kXcd - 1) / kXcd;
   constexpr int BK = Slab<E>::BK;
-  // split K when the tiles alone leave most CUs idle, keeping at least 8 slabs per slice
+  // split K so that the workgroups fill the resident slots (two per CU) in as few rounds as
+  // possible: the time is about (rounds) x (slabs per slice); at least 8 slabs per slice, and the
+  // slices' partial products must fit the workspace
   int ks = 1;
-  if (work != nullptr && tiles < 384) {
+  if (work != nullptr) {
+    static int slots = 0;
+    if (slots == 0) {
+      int dev = 0, cus = 0;
+      NGD_HIP_TRY(hipGetDevice(&dev));
+      NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      slots = 2 * (cus > 0 ? cus : 1);
+    }
     const int64_t nk = (K + BK - 1) / BK;
-    while (tiles * ks * 2 <= 768 && nk / (ks * 2) >= 8 && (int64_t)ks * 2 * M * N <= work_elems) ks *= 2;
+    int64_t best = ((tiles + slots - 1) / slots) * nk;
+    for (int q = 2; q <= 16; ++q) {
+      if (nk / q < 8 || (int64_t)q * M * N > work_elems) break;
+      const int64_t cost = ((tiles * q + slots - 1) / slots) * ((nk + q - 1) / q);
+      if (cost < best) {
+        best = cost;
+        ks = q;
+      }
+    }
   }
   const int64_t kchunk = ks == 1 ? K : ((K + ks - 1) / ks + BK - 1) / BK * BK;
   if (ks == 1) {
