@@ -276,6 +276,10 @@ typedef enum {
 
 /* enable != 0 turns timing on and resets all counters; enable == 0 turns it off. */
 ngd_status ngd_timing_enable(ngd_problem* h, int32_t enable);
+/* As ngd_timing_enable, for the timers whose bit (1u << id) is set in mask only (0: off). The
+ * matvec timer stamps the kernel's own dispatch and adds no work to the stream; the others bracket
+ * their kernel sequences with event records, which the device executes as extra packets. */
+ngd_status ngd_timing_enable_mask(ngd_problem* h, uint32_t mask);
 /* Launch count and total milliseconds of timer `id`; waits for the recorded events. */
 ngd_status ngd_timing_read(ngd_problem* h, int32_t id, int64_t* launches, double* total_ms);
 

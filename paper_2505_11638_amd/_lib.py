@@ -75,6 +75,7 @@ SIGNATURES = {
                                       C.POINTER(Precond), C.c_double, C.c_int64, C.POINTER(C.c_void_p),
                                       C.POINTER(PcgInfo), C.c_void_p]),
     "ngd_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ngd_timing_enable_mask": (C.c_int, [C.c_void_p, C.c_uint32]),
     "ngd_timing_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
 

@@ -218,8 +218,15 @@ class Problem:
                                               _stream()), "ngd_power_lambda_max")
         return out.value
 
-    def timing(self, enable: bool):
-        L.check(self.lib.ngd_timing_enable(self.h, 1 if enable else 0), "ngd_timing_enable")
+    def timing(self, enable: bool, only=None):
+        """Turn the kernel timers on (all, or only the named ones) or off; resets the counters."""
+        if enable and only is not None:
+            mask = 0
+            for name in only:
+                mask |= 1 << L.TIMERS[name]
+            L.check(self.lib.ngd_timing_enable_mask(self.h, mask), "ngd_timing_enable_mask")
+        else:
+            L.check(self.lib.ngd_timing_enable(self.h, 1 if enable else 0), "ngd_timing_enable")
 
     def timers(self) -> dict:
         """{name: (launches, total_ms)} of the library's kernel timers."""

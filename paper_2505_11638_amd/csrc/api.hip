@@ -73,13 +73,18 @@ struct ngd_problem {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // kernel timers
-  bool timing = false;
+  uint32_t timing = 0;  // bit id set: timer id records
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double t_ms[NGD_NUM_TIMERS] = {};
   int64_t t_n[NGD_NUM_TIMERS] = {};
   // iterations of the previous solve (index: plain CG), used to size the first launch chunk
   int64_t last_iters[2] = {4, 4};
+  // line-search trials per launch (set at creation from the residual kernel's occupancy), and in the
+  // first launch of the next search: 1 while the full step keeps being accepted, ls_batch after a
+  // search that had to halve (the same step is chosen either way)
+  int ls_batch = 1;
+  int ls_first_batch = 1;
 };
 
 namespace {
@@ -125,7 +130,7 @@ void drop_tail(ngd_problem* h, int id, int64_t count) {
 // Run `fn` (which enqueues one kernel sequence on s); when timing is on, bracket it with events.
 template <typename F>
 ngd_status timed(ngd_problem* h, int id, hipStream_t s, F&& fn) {
-  if (!h->timing || id < 0) return fn();
+  if (id < 0 || !((h->timing >> id) & 1u)) return fn();
   if (h->ev_pending.size() > 4096) {
     ngd_status st = flush_timers(h);
     if (st != NGD_OK) return st;
@@ -139,6 +144,25 @@ ngd_status timed(ngd_problem* h, int id, hipStream_t s, F&& fn) {
   ngd_status st = fn();
   NGD_HIP_TRY(hipEventRecord(b, s));
   h->ev_pending.push_back({id, {a, b}});
+  return st;
+}
+
+// As timed(), for a launcher that starts exactly one kernel: the events are handed to the launch and
+// stamped with that kernel's own start and end, so the timer holds kernel time without marker overhead.
+template <typename F>
+ngd_status timed_kernel(ngd_problem* h, int id, F&& fn) {
+  if (id < 0 || !((h->timing >> id) & 1u)) return fn(LaunchEvents{});
+  if (h->ev_pending.size() > 4096) {
+    ngd_status st = flush_timers(h);
+    if (st != NGD_OK) return st;
+  }
+  LaunchEvents ev{take_event(h), take_event(h)};
+  if (!ev.start || !ev.stop) {
+    set_error("hipEventCreate failed");
+    return NGD_ERR_HIP;
+  }
+  ngd_status st = fn(ev);
+  h->ev_pending.push_back({id, {ev.start, ev.stop}});
   return st;
 }
 
@@ -192,8 +216,8 @@ ngd_status gram_apply(ngd_problem* h, const ngd_operator* op, const double* v, d
     NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] { return recompute_rows(h, op, h->pt, s); }));
     return launch_gram_reduce(h->dtype, h->partial, h->nwg_vjp, h->ldP, h->P, v, lambda, y, s);
   }
-  NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
-    return launch_gram_rows(h->dtype, op->J, op->ldJ, h->N, h->P, v, h->partial, h->tsq, h->nwg, s);
+  NGD_TRY(timed_kernel(h, NGD_TIMER_MATVEC_ROWS, [&](LaunchEvents ev) {
+    return launch_gram_rows(h->dtype, op->J, op->ldJ, h->N, h->P, v, h->partial, h->tsq, h->nwg, s, ev);
   }));
   return launch_gram_reduce(h->dtype, h->partial, h->nwg, op->ldJ, h->P, v, lambda, y, s);
 }
@@ -256,6 +280,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   h->elem = d->dtype == NGD_F64 ? 8 : 4;
   h->tp = residual_block_rows(net, d->dtype);
   h->res_blocks = (int)((h->N + h->tp - 1) / h->tp);
+  h->ls_batch = residual_trials_per_launch(net, d->dtype, h->N, kTrials);
   h->nwg = gram_rows_grid(d->dtype, h->N, h->P);
   h->nwg_vjp = vjp_grid(net, d->dtype, h->N, h->nwg);
 
@@ -370,11 +395,14 @@ ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, v
 
   if (J_w != nullptr) NGD_CHECK(ldJ >= h->P, "ldJ < P");
   hipStream_t s = S(stream);
+  // residual workgroups of this launch (fewer without the Jacobian), each with one loss partial
+  const int nb = residual_blocks(h->net, h->dtype, h->N, J_w != nullptr);
+  NGD_CHECK(nb <= h->res_blocks, "residual launch exceeds its loss-partial buffer");
   NGD_TRY(timed(h, J_w ? NGD_TIMER_RESIDUAL_JACOBIAN : -1, s, [&] {
     return launch_residual_jacobian(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, r_w, J_w, ldJ,
                                     h->loss_part, 0, 1, s, nullptr);
   }));
-  if (loss != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, 1, 0.5, loss, s));
+  if (loss != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, nb, 1, 0.5, loss, s));
   if (grad != nullptr && J_w != nullptr) {
     // one pass over J_w when its rows suit the one-pass kernel, else the column-sum kernel
     const ngd_operator gop{theta, J_w, ldJ};
@@ -558,28 +586,25 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     return launch_gemm(g6, s);
   }));
   if (info != nullptr) {
-    std::vector<double> lh(L), core(16);
-    NGD_HIP_TRY(hipMemcpyAsync(lh.data(), lam_hat, sizeof(double) * L, hipMemcpyDeviceToHost, s));
-    NGD_HIP_TRY(hipMemcpyAsync(core.data(), h->scal + 200, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
-    int err = 0, cerr = 0;
-    NGD_HIP_TRY(hipMemcpyAsync(&err, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
-    NGD_HIP_TRY(hipMemcpyAsync(&cerr, h->cholsync + 128, sizeof(int), hipMemcpyDeviceToHost, s));
+    // one gather kernel and one copy into pinned memory: a single host round trip
+    double* hv = reinterpret_cast<double*>(h->host);
+    NGD_TRY(launch_sketch_info(lam_hat, (int)L, h->scal + 200, eig_error_flag(h->eigw, (int)L),
+                               reinterpret_cast<const int*>(h->cholsync + 128), h->scal + 240, s));
+    NGD_HIP_TRY(hipMemcpyAsync(hv, h->scal + 240, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
-    if (err) {
+    if (hv[5] != 0.0) {
       set_error("exchange between the workgroups of the tridiagonalisation timed out");
       return NGD_ERR_HIP;
     }
-    if (cerr) {
+    if (hv[6] != 0.0) {
       set_error("exchange between the workgroups of the Cholesky factorisation timed out");
       return NGD_ERR_HIP;
     }
-    int nmod = 0;
-    std::memcpy(&nmod, &core[10], sizeof(int));
-    info->nu = core[1];
-    info->lam1 = lh[0];
-    info->lam_ell = lh[L - 1];
-    info->rank = (int32_t)std::count_if(lh.begin(), lh.end(), [](double v) { return v > 0.0; });
-    info->rank_z = (int32_t)(L - nmod);
+    info->nu = hv[3];
+    info->lam1 = hv[0];
+    info->lam_ell = hv[1];
+    info->rank = (int32_t)hv[2];
+    info->rank_z = (int32_t)(L - (int64_t)hv[4]);
   }
   return NGD_OK;
 }
@@ -621,9 +646,9 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
       double* pprev = h->pcg_p[k & 1];
       double* pcur = h->pcg_p[(k + 1) & 1];
       if (op->J != nullptr) {
-        NGD_TRY(timed(h, NGD_TIMER_MATVEC_ROWS, s, [&] {
+        NGD_TRY(timed_kernel(h, NGD_TIMER_MATVEC_ROWS, [&](LaunchEvents ev) {
           return pcg_launch_rows(h->dtype, op->J, op->ldJ, h->N, P, zsrc, pprev, pcur, h->pcg_st, h->partial, h->tsq,
-                                 h->nwg, s);
+                                 h->nwg, s, ev);
         }));
         NGD_TRY(pcg_launch_update(h->dtype, h->partial, h->nwg, op->ldJ, P, pcur, h->tsq, d, h->pcg_r, h->pcg_part,
                                   h->pcg_st, plain, s));
@@ -709,40 +734,43 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
   hipStream_t s = S(stream);
   const int64_t P = h->P;
   double* hv = reinterpret_cast<double*>(h->host);  // [0] slope, [8..15] alphas, [16..23] losses
+  // the slope comes back with the first batch of trial losses (the trial steps do not depend on it)
   NGD_TRY(launch_dot(grad, d, P, h->scal + 8, h->scal + 0, s));
   NGD_HIP_TRY(hipMemcpyAsync(hv, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
-  NGD_HIP_TRY(hipStreamSynchronize(s));
-  const double slope = hv[0];
   int tried = 0;
   double accepted = 0.0, acc_loss = loss0;
   bool found = false;
-  int batch = 1;
+  int accepted_index = -1;
+  int batch = h->ls_first_batch;
   while (!found && tried <= max_halvings) {
     const int nt = std::min(batch, max_halvings + 1 - tried);
     for (int t = 0; t < nt; ++t) hv[8 + t] = std::ldexp(1.0, -(tried + t));
     NGD_HIP_TRY(hipMemcpyAsync(h->alphas, hv + 8, sizeof(double) * nt, hipMemcpyHostToDevice, s));
     NGD_TRY(launch_axpy_theta(h->dtype, theta, d, h->alphas, nt, P, h->trial, h->ldP, s));
+    const int nb = residual_blocks(h->net, h->dtype, h->N, false);
+    NGD_CHECK(nb <= h->res_blocks, "residual launch exceeds its loss-partial buffer");
     NGD_TRY(launch_residual_jacobian(h->net, h->dtype, h->trial, h->N, h->X, h->w, h->f, h->g, h->kind, nullptr,
                                      nullptr, 0, h->loss_part, h->ldP, nt, s, nullptr));
-    NGD_TRY(launch_reduce_sum(h->loss_part, h->res_blocks, nt, 0.5, h->losses, s));
+    NGD_TRY(launch_reduce_sum(h->loss_part, nb, nt, 0.5, h->losses, s));
     NGD_HIP_TRY(hipMemcpyAsync(hv + 16, h->losses, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
+    const double slope = hv[0];
     for (int t = 0; t < nt; ++t) {
       const double a = hv[8 + t], Lt = hv[16 + t];
       if (Lt <= loss0 - c1 * a * slope) {
         accepted = a;
         acc_loss = Lt;
         found = true;
+        accepted_index = tried + t;
         break;
       }
     }
     tried += nt;
-    batch = kTrials;
+    batch = h->ls_batch;
   }
-  // theta_out = theta - alpha d (alpha = 0 copies theta)
-  hv[8] = accepted;
-  NGD_HIP_TRY(hipMemcpyAsync(h->alphas, hv + 8, sizeof(double), hipMemcpyHostToDevice, s));
-  NGD_TRY(launch_axpy_theta(h->dtype, theta, d, h->alphas, 1, P, theta_out, h->ldP, s));
+  h->ls_first_batch = accepted_index == 0 ? 1 : h->ls_batch;
+  // theta_out = theta - alpha d (alpha = 0 copies theta), alpha passed by value
+  NGD_TRY(launch_axpy_theta(h->dtype, theta, d, nullptr, 1, P, theta_out, h->ldP, s, accepted));
   NGD_HIP_TRY(hipStreamSynchronize(s));
   *alpha = accepted;
   *loss_new = acc_loss;
@@ -750,9 +778,13 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
 }
 
 ngd_status ngd_timing_enable(ngd_problem* h, int32_t enable) {
+  return ngd_timing_enable_mask(h, enable != 0 ? (1u << NGD_NUM_TIMERS) - 1u : 0u);
+}
+
+ngd_status ngd_timing_enable_mask(ngd_problem* h, uint32_t mask) {
   NGD_CHECK(h != nullptr, "NULL handle");
   NGD_TRY(flush_timers(h));
-  h->timing = enable != 0;
+  h->timing = mask & ((1u << NGD_NUM_TIMERS) - 1u);
   for (int i = 0; i < NGD_NUM_TIMERS; ++i) {
     h->t_ms[i] = 0.0;
     h->t_n[i] = 0;

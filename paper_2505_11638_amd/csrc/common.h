@@ -1,6 +1,7 @@
 // Internal declarations shared by the libngd HIP sources (not part of the public ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -181,10 +182,16 @@ ngd_status launch_gradient(int dtype, const void* J, int64_t ldJ, int64_t N, int
                            double* work, double* grad, hipStream_t s);
 int gradient_chunks(int64_t N);
 
+// Events that, when set, the runtime stamps with the start and end of one kernel's own dispatch
+// (hipExtLaunchKernel), so that a timer measures the kernel and not the markers around it.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // matvec.hip
 int gram_rows_grid(int dtype, int64_t N, int64_t P);
 ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* v,
-                            void* partial, double* tsq, int nwg, hipStream_t s);
+                            void* partial, double* tsq, int nwg, hipStream_t s, LaunchEvents ev = {});
 ngd_status launch_grad_rows(int dtype, const void* J, int64_t ldJ, int64_t N, const void* r, void* partial, int nwg,
                             hipStream_t s);
 ngd_status launch_gram_reduce(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* v,
@@ -231,8 +238,12 @@ const int* eig_error_flag(void* work, int n);
 ngd_status launch_gaussian_omega(int dtype, uint64_t seed, uint64_t counter, int64_t P, int64_t ell, void* out,
                                  int64_t ld, hipStream_t s);
 ngd_status launch_cast(int src_type, const void* src, int dst_type, void* dst, int64_t n, hipStream_t s);
+// out[t * out_stride + j] = theta[j] - alpha_t d[j], alpha_t = alphas[t] (device), or alpha0 when
+// alphas is NULL
 ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, const double* alphas, int n_alpha,
-                             int64_t P, void* out, int64_t out_stride, hipStream_t s);
+                             int64_t P, void* out, int64_t out_stride, hipStream_t s, double alpha0 = 0.0);
+ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
+                              double* out, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // matvec.hip (continued)
@@ -243,7 +254,7 @@ ngd_status pcg_launch_init(const double* g, int64_t P, double* x, double* r, dou
                            PcgState* st, double rtol, int plain, hipStream_t s);
 ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* z,
                            const double* p_prev, double* p_cur, PcgState* st, void* partial, double* tsq, int nwg,
-                           hipStream_t s);
+                           hipStream_t s, LaunchEvents ev = {});
 ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,
                              const double* tsq, double* x, double* r, double* rr_part, PcgState* st, int plain,
                              hipStream_t s);
@@ -308,5 +319,10 @@ ngd_status launch_whitening(const double* evals, const double* evec_rows, int el
 ngd_status launch_add_scaled(int dtype, const void* X, int64_t ldx, double a, void* Y, int64_t ldy, int64_t rows,
                              int64_t cols, hipStream_t s);
 int residual_block_rows(const NetDesc& net, int dtype);
+// workgroups (one loss partial each) of a residual launch over N points, with or without the Jacobian
+int residual_blocks(const NetDesc& net, int dtype, int64_t N, bool with_jacobian);
+// line-search trials (residual-only sweeps) per launch: as many as occupy the device about as long as
+// one (1 when a single trial already fills it), at most max_trials
+int residual_trials_per_launch(const NetDesc& net, int dtype, int64_t N, int max_trials);
 
 }  // namespace ngd

@@ -175,7 +175,6 @@ __global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
         const int c = lane + 64 * q;
         const double v = c == k + 1 ? 1.0 : (c > k + 1 ? x[q] * scale : 0.0);
         vnew[c] = v;
-        if (g == 0 && c < n) a.V[(int64_t)k * n + c] = v;
       }
       if (lane == 0) {
         tau_s = tau;
@@ -250,6 +249,14 @@ __global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
       pv += pbuf[c] * vnew[c];
     }
     const double ck = 0.5 * tk * wave_sum_dpp(pv);
+    // v_k to V, off the path to the next barrier (only later kernels read V)
+    if (g == 0 && wid == 0) {
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const int c = lane + 64 * q;
+        if (c < n) a.V[(int64_t)k * n + c] = vnew[c];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
       const int c = lane + 64 * q;

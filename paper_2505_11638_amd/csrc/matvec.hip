@@ -654,7 +654,7 @@ bool gram_rows_supported(int dtype, int64_t ldJ) {
 
 template <typename T>
 static ngd_status gram_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, const double* v, T* partial,
-                              double* tsq, int nwg, hipStream_t s) {
+                              double* tsq, int nwg, hipStream_t s, LaunchEvents ev) {
   RowsCfg c;
   if (!rows_cfg(sizeof(T) == 8 ? NGD_F64 : NGD_F32, ldJ, &c)) {
     set_error("Jacobian row too long for the one-pass matvec");
@@ -665,7 +665,8 @@ static ngd_status gram_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, con
   case ID: {                                                                                            \
     auto k = gram_rows_kernel<T, NK, R, B>;                                                             \
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    hipLaunchKernelGGL(k, dim3(nwg), dim3(B), lds, s, J, ldJ, N, P, v, partial, tsq);                  \
+    hipExtLaunchKernelGGL(k, dim3(nwg), dim3(B), (uint32_t)lds, s, ev.start, ev.stop, 0u, J, ldJ, N, P, v,  \
+                          partial, tsq);                                                                \
     break;                                                                                              \
   }
   NGD_CFG_DISPATCH(c.id, NGD_CALL)
@@ -699,10 +700,10 @@ ngd_status launch_grad_rows(int dtype, const void* J, int64_t ldJ, int64_t N, co
 }
 
 ngd_status launch_gram_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* v,
-                            void* partial, double* tsq, int nwg, hipStream_t s) {
+                            void* partial, double* tsq, int nwg, hipStream_t s, LaunchEvents ev) {
   if (dtype == NGD_F64)
-    return gram_rows_t<double>((const double*)J, ldJ, N, P, v, (double*)partial, tsq, nwg, s);
-  return gram_rows_t<float>((const float*)J, ldJ, N, P, v, (float*)partial, tsq, nwg, s);
+    return gram_rows_t<double>((const double*)J, ldJ, N, P, v, (double*)partial, tsq, nwg, s, ev);
+  return gram_rows_t<float>((const float*)J, ldJ, N, P, v, (float*)partial, tsq, nwg, s, ev);
 }
 
 ngd_status launch_gram_reduce(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* v,
@@ -777,7 +778,8 @@ ngd_status pcg_launch_init(const double* g, int64_t P, double* x, double* r, dou
 
 template <typename T>
 static ngd_status pcg_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, const double* z, const double* p_prev,
-                             double* p_cur, PcgState* st, T* partial, double* tsq, int nwg, hipStream_t s) {
+                             double* p_cur, PcgState* st, T* partial, double* tsq, int nwg, hipStream_t s,
+                             LaunchEvents ev) {
   RowsCfg c;
   if (!rows_cfg(sizeof(T) == 8 ? NGD_F64 : NGD_F32, ldJ, &c)) {
     set_error("Jacobian row too long for the one-pass matvec");
@@ -788,7 +790,8 @@ static ngd_status pcg_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, cons
   case ID: {                                                                                            \
     auto k = pcg_rows_kernel<T, NK, R, B>;                                                              \
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    hipLaunchKernelGGL(k, dim3(nwg), dim3(B), lds, s, J, ldJ, N, P, z, p_prev, p_cur, st, partial, tsq); \
+    hipExtLaunchKernelGGL(k, dim3(nwg), dim3(B), (uint32_t)lds, s, ev.start, ev.stop, 0u, J, ldJ, N, P, z, \
+                          p_prev, p_cur, st, partial, tsq);                                             \
     break;                                                                                              \
   }
   NGD_CFG_DISPATCH(c.id, NGD_CALL)
@@ -799,10 +802,10 @@ static ngd_status pcg_rows_t(const T* J, int64_t ldJ, int64_t N, int64_t P, cons
 
 ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, const double* z,
                            const double* p_prev, double* p_cur, PcgState* st, void* partial, double* tsq, int nwg,
-                           hipStream_t s) {
+                           hipStream_t s, LaunchEvents ev) {
   if (dtype == NGD_F64)
-    return pcg_rows_t<double>((const double*)J, ldJ, N, P, z, p_prev, p_cur, st, (double*)partial, tsq, nwg, s);
-  return pcg_rows_t<float>((const float*)J, ldJ, N, P, z, p_prev, p_cur, st, (float*)partial, tsq, nwg, s);
+    return pcg_rows_t<double>((const double*)J, ldJ, N, P, z, p_prev, p_cur, st, (double*)partial, tsq, nwg, s, ev);
+  return pcg_rows_t<float>((const float*)J, ldJ, N, P, z, p_prev, p_cur, st, (float*)partial, tsq, nwg, s, ev);
 }
 
 ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,

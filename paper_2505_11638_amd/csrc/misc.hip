@@ -58,10 +58,36 @@ __global__ void cast_kernel(const S* __restrict__ s, D* __restrict__ d, int64_t 
 
 template <typename T>
 __global__ void theta_trial_kernel(const T* __restrict__ theta, const double* __restrict__ d,
-                                   const double* __restrict__ alphas, int64_t P, T* __restrict__ out, int64_t stride) {
+                                   const double* __restrict__ alphas, double alpha0, int64_t P, T* __restrict__ out,
+                                   int64_t stride) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
-  if (j < P) out[t * stride + j] = (T)((double)theta[j] - alphas[t] * d[j]);
+  const double a = alphas != nullptr ? alphas[t] : alpha0;
+  if (j < P) out[t * stride + j] = (T)((double)theta[j] - a * d[j]);
+}
+
+// The sketch's summary for the host, gathered so that one copy brings it back:
+// out[0] = lam[0], out[1] = lam[L-1], out[2] = #{lam > 0}, out[3] = core[1] (the shift nu),
+// out[4] = the modified-pivot count (an int stored at core[10]), out[5], out[6] = the error words.
+__global__ __launch_bounds__(256) void sketch_info_kernel(const double* __restrict__ lam, int L,
+                                                          const double* __restrict__ core,
+                                                          const int* __restrict__ eig_err,
+                                                          const int* __restrict__ chol_err, double* __restrict__ out) {
+  __shared__ double red[4];
+  double c = 0.0;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) c += lam[i] > 0.0 ? 1.0 : 0.0;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    int nmod = 0;
+    __builtin_memcpy(&nmod, core + 10, sizeof(int));
+    out[0] = lam[0];
+    out[1] = lam[L - 1];
+    out[2] = c;
+    out[3] = core[1];
+    out[4] = (double)nmod;
+    out[5] = (double)*eig_err;
+    out[6] = (double)*chol_err;
+  }
 }
 
 // F[k][i] = V[i][k] / sqrt(lam_i) for lam_i > 0, else 0 (rows of V are eigenvectors)
@@ -116,14 +142,21 @@ ngd_status launch_cast(int st, const void* src, int dt, void* dst, int64_t n, hi
 }
 
 ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, const double* alphas, int n_alpha,
-                             int64_t P, void* out, int64_t out_stride, hipStream_t s) {
+                             int64_t P, void* out, int64_t out_stride, hipStream_t s, double alpha0) {
   dim3 grid((unsigned)((P + 255) / 256), (unsigned)n_alpha);
   if (dtype == NGD_F64)
-    hipLaunchKernelGGL(theta_trial_kernel<double>, grid, dim3(256), 0, s, (const double*)theta, d, alphas, P,
+    hipLaunchKernelGGL(theta_trial_kernel<double>, grid, dim3(256), 0, s, (const double*)theta, d, alphas, alpha0, P,
                        (double*)out, out_stride);
   else
-    hipLaunchKernelGGL(theta_trial_kernel<float>, grid, dim3(256), 0, s, (const float*)theta, d, alphas, P,
+    hipLaunchKernelGGL(theta_trial_kernel<float>, grid, dim3(256), 0, s, (const float*)theta, d, alphas, alpha0, P,
                        (float*)out, out_stride);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
+                              double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sketch_info_kernel, dim3(1), dim3(256), 0, s, lam, L, core, eig_err, chol_err, out);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

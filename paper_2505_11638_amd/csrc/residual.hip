@@ -47,6 +47,17 @@ __host__ __device__ inline size_t lds_elems(const NetDesc& net, int TP) {
   return ws + pre + 3 * buf + (size_t)TP * kMaxChan + 32;
 }
 
+// Residuals only (no Jacobian): the forward sweep needs one layer's pre-activations at a time and no
+// adjoint buffers, so more points fit per workgroup.
+__host__ __device__ inline size_t lds_elems_fwd(const NetDesc& net, int TP) {
+  size_t ws = 0;
+  for (int l = 0; l < net.n_layers; ++l) {
+    size_t s = (size_t)net.widths[l + 1] * (net.widths[l] + 1);
+    ws = s > ws ? s : ws;
+  }
+  return ws + (size_t)TP * net.C * net.max_width + (size_t)TP * net.C * chan_pitch(net) + (size_t)TP * kMaxChan + 32;
+}
+
 // Stage W_l (n_out x n_in, row-major in theta) into LDS with a padded row pitch n_in + 1. Each thread
 // issues its loads in batches of kLoadBatch before storing any, so a batch costs one L2 round trip.
 constexpr int kLoadBatch = 16;
@@ -242,7 +253,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
                               const int8_t* __restrict__ kind, T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ,
                               int TP, int64_t tile_first, int64_t tile_step, const double* __restrict__ wv,
                               int64_t wv_stride, bool write_r, double* loss_slot, T* part_row, double* tsq_slot,
-                              bool acc_in_lds = false) {
+                              bool acc_in_lds = false, bool fwd_only = false) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const int C = net.C, nS = net.nS, nm = chan_pitch(net), L = net.n_layers;
@@ -261,10 +272,16 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     }
     s.Ws = smem;
     s.pre = s.Ws + ws;
-    s.hb = s.pre + pre_offset(net, L - 1, TP);
-    s.ab = s.hb + (size_t)TP * C * nm;
-    s.zb = s.ab + (size_t)TP * C * nm;
-    s.ub = s.zb + (size_t)TP * C * nm;
+    if (fwd_only) {  // residuals only: one layer of pre-activations, no adjoint buffers
+      s.hb = s.pre + (size_t)TP * C * net.max_width;
+      s.ab = s.zb = nullptr;
+      s.ub = s.hb + (size_t)TP * C * nm;
+    } else {
+      s.hb = s.pre + pre_offset(net, L - 1, TP);
+      s.ab = s.hb + (size_t)TP * C * nm;
+      s.zb = s.ab + (size_t)TP * C * nm;
+      s.ub = s.zb + (size_t)TP * C * nm;
+    }
     s.red = s.ub + TP * kMaxChan;
   }
 
@@ -275,7 +292,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     __syncthreads();
     load_weights(net, theta, l, s.Ws);
     __syncthreads();
-    T* pre_l = s.pre + pre_offset(net, l, TP);
+    T* pre_l = s.pre + (fwd_only ? 0 : pre_offset(net, l, TP));
     const T* b = theta + net.boff[l];
     mfma_forward(s.Ws, n_in, n_out, s.hb, nm, TP * C, C, b, pre_l);
     __syncthreads();
@@ -496,7 +513,8 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
     NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
     const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
     T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
-    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out, int acc_in_lds) {
+    const double* __restrict__ wv, int64_t wv_stride, double* __restrict__ tsq_out, int acc_in_lds,
+    int fwd_only) {
   const T* theta = theta0 + (int64_t)blockIdx.y * theta_stride;
   const int64_t ntiles = (N + TP - 1) / TP;
   const int64_t tile_step = MODE == kVjp ? (int64_t)gridDim.x : ntiles;
@@ -505,7 +523,8 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
   T* part_row = MODE == kVjp ? J + (int64_t)blockIdx.x * ldJ : nullptr;
   double* tsq_slot = tsq_out != nullptr ? tsq_out + blockIdx.x : nullptr;
   residual_body<T, MODE>(net, theta, N, X, w, f, g, kind, r_w, J, ldJ, TP, blockIdx.x, tile_step, wv, wv_stride,
-                         blockIdx.y == 0, loss_slot, part_row, tsq_slot, acc_in_lds != 0);
+                         blockIdx.y == 0, loss_slot, part_row, tsq_slot, acc_in_lds != 0,
+                         MODE == kJacobian && fwd_only != 0 && J == nullptr);
 }
 
 // Several problems in one launch: work item i is tile (i - first_tile[q]) of the problem q whose
@@ -678,19 +697,43 @@ __global__ void colsum_stage2(const double* __restrict__ work, int nchunk, int64
 
 }  // namespace
 
-static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes);
+static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes, bool fwd_only = false);
 
 int residual_block_rows(const NetDesc& net, int dtype) {
   size_t b = 0;
   return choose_tp(net, dtype == NGD_F64 ? 8 : 4, &b);
 }
 
-static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes) {
+int residual_trials_per_launch(const NetDesc& net, int dtype, int64_t N, int max_trials) {
+  size_t bytes = 0;
+  const int tp = choose_tp(net, dtype == NGD_F64 ? 8 : 4, &bytes, true);
+  const int64_t per_trial = (N + tp - 1) / tp;
+  int dev = 0, cus = 0, per_cu = 0;
+  const void* k = dtype == NGD_F64 ? (const void*)residual_jacobian_kernel<double, kJacobian>
+                                   : (const void*)residual_jacobian_kernel<float, kJacobian>;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, bytes) != hipSuccess || per_cu < 1)
+    return 1;
+  // trials that run in about four rounds of resident workgroups cost little more than one
+  const int64_t fit = 4 * (int64_t)cus * per_cu / (per_trial > 0 ? per_trial : 1);
+  return (int)(fit < 1 ? 1 : (fit > max_trials ? max_trials : fit));
+}
+
+int residual_blocks(const NetDesc& net, int dtype, int64_t N, bool with_jacobian) {
+  size_t b = 0;
+  const int tp = choose_tp(net, dtype == NGD_F64 ? 8 : 4, &b, !with_jacobian);
+  return (int)((N + tp - 1) / tp);
+}
+
+static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes, bool fwd_only) {
+  auto need = [&](int t) { return (fwd_only ? lds_elems_fwd(net, t) : lds_elems(net, t)) * elem; };
   int tp = 16;
-  while (tp > 1 && lds_elems(net, tp) * elem > 96 * 1024) tp >>= 1;
+  while (tp > 1 && need(tp) > 96 * 1024) tp >>= 1;
   // wide layers: trade occupancy for more points per staged weight matrix
-  while (tp < 4 && lds_elems(net, 2 * tp) * elem <= 150 * 1024) tp <<= 1;
-  *bytes = lds_elems(net, tp) * elem;
+  while (tp < 4 && need(2 * tp) <= 150 * 1024) tp <<= 1;
+  *bytes = need(tp);
   return tp;
 }
 
@@ -700,7 +743,8 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
                                     hipStream_t s, int* n_blocks_out) {
   size_t elem = dtype == NGD_F64 ? 8 : 4;
   size_t bytes = 0;
-  int tp = choose_tp(net, elem, &bytes);
+  const int fwd_only = J == nullptr ? 1 : 0;
+  int tp = choose_tp(net, elem, &bytes, fwd_only != 0);
   if (bytes > 160 * 1024) {
     set_error("network too wide for the residual kernel's LDS budget");
     return NGD_ERR_INVALID;
@@ -712,13 +756,13 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const double*)theta, theta_stride, N, (const double*)X,
                        (const double*)w, (const double*)f, (const double*)g, kind, (double*)r_w, (double*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0, fwd_only);
   } else {
     auto k = residual_jacobian_kernel<float, kJacobian>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const float*)theta, theta_stride, N, (const float*)X,
                        (const float*)w, (const float*)f, (const float*)g, kind, (float*)r_w, (float*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0);
+                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0, fwd_only);
   }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
@@ -751,13 +795,13 @@ ngd_status launch_vjp(const NetDesc& net, int dtype, const void* theta, int64_t 
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const double*)theta, (int64_t)0, N, (const double*)X,
                        (const double*)w, (const double*)f, (const double*)g, kind, nullptr, (double*)partial, ld,
-                       nullptr, tp, wv, wv_stride, tsq, acc_in_lds);
+                       nullptr, tp, wv, wv_stride, tsq, acc_in_lds, 0);
   } else {
     auto k = residual_jacobian_kernel<float, kVjp>;
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     hipLaunchKernelGGL(k, dim3(nwg), dim3(256), bytes, s, net, (const float*)theta, (int64_t)0, N, (const float*)X,
                        (const float*)w, (const float*)f, (const float*)g, kind, nullptr, (float*)partial, ld, nullptr,
-                       tp, wv, wv_stride, tsq, acc_in_lds);
+                       tp, wv, wv_stride, tsq, acc_in_lds, 0);
   }
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;

@@ -59,6 +59,8 @@ class NGD:
         if power_v0 is None:
             power_v0 = np.random.default_rng(np.random.SeedSequence([seed, 99])).standard_normal(gp.P)
         self.v0 = torch.as_tensor(power_v0, dtype=torch.float64, device=gp.device)
+        # pinned landing slot of the loss: its copy rides the stream and is read after the next sync
+        self.loss_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.k = 0
 
     def step(self) -> StepReport:
@@ -66,15 +68,18 @@ class NGD:
         r, J, grad, loss = gp.residual_jacobian(self.theta, self.J)
         if self.recompute:
             J = Recompute(self.theta)
-        L0 = float(loss.item())
         pc = None
         rank = -1
+        # the loss comes back by an asynchronous copy on the same stream; the sketch (or the power
+        # iteration) synchronises that stream, after which the pinned slot holds it
+        self.loss_host.copy_(loss, non_blocking=True)
         if self.solver == "nystrom":
             pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype)
             lam1 = pc.info["lam1"]
             rank = pc.info["rank"]
         else:
             lam1 = gp.power_lambda_max(J, self.v0, 4)
+        L0 = float(self.loss_host[0])
         mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
         out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
@@ -102,7 +107,6 @@ class BatchNGD:
     def step(self):
         b = self.batch
         _, grads, losses = b.residual_jacobian(self.thetas, self.Js)
-        L0 = torch.cat(losses).cpu().numpy()
         pcs = None
         if self.solver == "nystrom":
             pcs = [m.nystrom_sketch(J, ell, seed=self.seed, counter=self.k, sketch_dtype="f32", want_info=True)
@@ -111,6 +115,7 @@ class BatchNGD:
         else:
             lam1 = [m.power_lambda_max(J, torch.ones(m.P, dtype=torch.float64, device=m.device), 4)
                     for m, J in zip(b.members, self.Js)]
+        L0 = torch.cat(losses).cpu().numpy()
         mus = [max(self.gamma * self.eps * l1, 1e-4 * float(l0) ** 2) for l1, l0 in zip(lam1, L0)]
         maxit = 1000 if self.solver == "nystrom" else max(m.P for m in b.members)
         outs = b.pcg_solve(self.Js, grads, mus, pcs, rtol=self.rtol, maxit=maxit)
