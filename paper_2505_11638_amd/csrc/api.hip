@@ -39,7 +39,7 @@ struct ngd_problem {
   double* pcg_r;
   double* pcg_z;
   double* pcg_p[2];
-  double* pcg_s;     // max_ell
+  double* pcg_s;     // kDotChunksMax x max_ell: column-chunk partials of the preconditioner dots
   double* pcg_part;  // block partials (P / 256)
   PcgState* pcg_st;
   void* omega;       // max_ell x ldP, dtype
@@ -297,7 +297,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->pcg_z, sizeof(double) * ldP});
   plan.push_back({(void**)&h->pcg_p[0], sizeof(double) * ldP});
   plan.push_back({(void**)&h->pcg_p[1], sizeof(double) * ldP});
-  plan.push_back({(void**)&h->pcg_s, sizeof(double) * (size_t)L});
+  plan.push_back({(void**)&h->pcg_s, sizeof(double) * (size_t)L * kDotChunksMax});
   plan.push_back({(void**)&h->pcg_part, sizeof(double) * (size_t)((P + 31) / 32 + 64)});
   plan.push_back({(void**)&h->pcg_st, sizeof(PcgState)});
   plan.push_back({&h->omega, (size_t)L * ldP * e});

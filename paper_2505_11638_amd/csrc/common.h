@@ -142,22 +142,30 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ a, 
   return block_sum(s, red);
 }
 
-// Last-block detection for deterministic two-stage reductions inside one launch: every block
-// publishes its partial, then the block that arrives last sees all partials.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
+// Deterministic two-stage reduction inside one launch. Block `bid` publishes its partial v (the same
+// value in every thread) to part[bid] with a device-coherent (sc1) store, waits for that store to
+// complete, and counts itself in; the block that arrives last reads all partials with
+// device-coherent loads and returns true with their fixed-order sum in *total (every thread), then
+// re-arms the counter for the next launch. No L2 write-back or invalidate is involved.
+__device__ __forceinline__ bool publish_and_reduce(double v, double* part, int bid, unsigned* counter,
+                                                   unsigned nblocks, double* red, double* total) {
   __shared__ int last;
-  __threadfence();
-  __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == nblocks - 1);
+    __hip_atomic_store(part + bid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == nblocks - 1;
   }
   __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0u;
-  }
-  return last != 0;
+  if (!last) return false;
+  double s = 0;
+  for (int i = threadIdx.x; i < (int)nblocks; i += blockDim.x)
+    s += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *total = block_sum(s, red);
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
 }
 
 // ---- launchers (defined in the .hip files) ------------------------------------------------------
@@ -262,6 +270,9 @@ ngd_status launch_partials_to_row(int dtype, const void* partial, int nwg, int64
                                   hipStream_t s);
 ngd_status pcg_launch_direction(int dtype, const double* z, const double* p_prev, int64_t P, double* p_cur, void* p_t,
                                 double* part, PcgState* st, hipStream_t s);
+// column chunks of the preconditioner dots (the partial buffer holds kDotChunksMax x ell doubles)
+constexpr int kDotChunksMax = 16;
+int precond_dot_chunks(int64_t P, int ell);
 ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
 

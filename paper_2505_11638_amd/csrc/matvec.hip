@@ -295,9 +295,8 @@ __global__ __launch_bounds__(256) void pcg_direction_kernel(const double* __rest
     pp = pj * pj;
   }
   pp = block_sum(pp, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = pp;
-  if (!arrive_last(&st->counter, gridDim.x)) return;
-  const double tot = block_sum_array(part, (int)gridDim.x, red);
+  double tot;
+  if (!publish_and_reduce(pp, part, (int)blockIdx.x, &st->counter, (unsigned)(gridDim.x), red, &tot)) return;
   if (threadIdx.x == 0) st->pp = tot;
 }
 
@@ -372,9 +371,8 @@ __device__ __forceinline__ void pcg_update_body(const T* __restrict__ partial, i
     rr = rj * rj;
   }
   rr = block_sum(rr, red);
-  if (threadIdx.x == 0) rr_part[bid] = rr;
-  if (!arrive_last(&st->counter, nb)) return;
-  const double tot = block_sum_array(rr_part, nb, red);
+  double tot;
+  if (!publish_and_reduce(rr, rr_part, (int)bid, &st->counter, (unsigned)(nb), red, &tot)) return;
   if (threadIdx.x == 0) {
     if (bad) {
       st->breakdown = 1;
@@ -423,11 +421,43 @@ __device__ __forceinline__ void precond_dots_body(const T* __restrict__ U, int64
   if (threadIdx.x == 0) s[bid] = acc;
 }
 
+// (C) for one problem: workgroup (g, c) forms the dots of preconditioner rows kDotRows g ..
+// kDotRows g + kDotRows - 1 with r over column chunk c, into part[c * ell + i]; the apply kernel adds
+// the chunks in a fixed order. r is read once per kDotRows rows, and the grid has rows x chunks
+// workgroups instead of one per row.
+constexpr int kDotRows = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256) void precond_dots_kernel(const T* __restrict__ U, int64_t ldU, int64_t P,
-                                                           const double* __restrict__ r, double* __restrict__ s,
-                                                           const PcgState* __restrict__ st) {
-  precond_dots_body<T>(U, ldU, P, r, s, st, blockIdx.x);
+__global__ __launch_bounds__(256) void precond_dots_chunk_kernel(const T* __restrict__ U, int64_t ldU, int64_t P,
+                                                                 int ell, int64_t chunk,
+                                                                 const double* __restrict__ r,
+                                                                 double* __restrict__ part,
+                                                                 const PcgState* __restrict__ st) {
+  if (st != nullptr && st->done) return;
+  __shared__ double red[kDotRows][4];
+  const int i0 = blockIdx.x * kDotRows;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = j0 + chunk < P ? j0 + chunk : P;
+  double acc[kDotRows];
+#pragma unroll
+  for (int q = 0; q < kDotRows; ++q) acc[q] = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const double rj = r[j];
+#pragma unroll
+    for (int q = 0; q < kDotRows; ++q)
+      if (i0 + q < ell) acc[q] += (double)U[(int64_t)(i0 + q) * ldU + j] * rj;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kDotRows; ++q) acc[q] = wave_sum_dpp(acc[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < kDotRows; ++q) red[q][wid] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < kDotRows && i0 + (int)threadIdx.x < ell) {
+    const int q = threadIdx.x;
+    part[(int64_t)blockIdx.y * ell + i0 + q] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+  }
 }
 
 // (D) z = c r + sum_i (1/(lam_i + mu) - c) s_i U_i (eq. nystrom_inverse); rz = r^T z; beta
@@ -455,9 +485,8 @@ __device__ __forceinline__ void precond_apply_body(const T* __restrict__ U, int6
   }
   if (st == nullptr) return;
   rz = block_sum(rz, red);
-  if (threadIdx.x == 0) rz_part[bid] = rz;
-  if (!arrive_last(&st->counter, nb)) return;
-  const double tot = block_sum_array(rz_part, nb, red);
+  double tot;
+  if (!publish_and_reduce(rz, rz_part, (int)bid, &st->counter, (unsigned)(nb), red, &tot)) return;
   if (threadIdx.x == 0) {
     if (st->iters == 0 && st->beta == 0.0) {
       st->rz = tot;                       // initial z_0 = P^{-1} r_0
@@ -472,13 +501,86 @@ __device__ __forceinline__ void precond_apply_body(const T* __restrict__ U, int6
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void precond_apply_kernel(const T* __restrict__ U, int64_t ldU, int64_t P, int ell,
-                                                            const double* __restrict__ lam, double mu,
-                                                            const double* __restrict__ s, const double* __restrict__ r,
-                                                            double* __restrict__ z, double* __restrict__ rz_part,
-                                                            PcgState* __restrict__ st) {
-  precond_apply_body<T>(U, ldU, P, ell, lam, mu, s, r, z, rz_part, st, blockIdx.x, gridDim.x);
+// (D) for one problem: a workgroup of kApWaves waves owns kApCols columns; wave w adds the rows
+// w, w + kApWaves, ... of U (two adjacent columns per lane, read as one 2-element vector when VEC),
+// the waves' sums meet in LDS. The coefficients are (1/(lam_i + mu) - c) s_i with s_i the sum of the
+// dot chunks. Then z, r^T z and beta as in the batched form.
+constexpr int kApWaves = 8, kApCols = 128;
+
+template <typename T> struct Pair;
+template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(64 * kApWaves) void precond_apply_cols_kernel(
+    const T* __restrict__ U, int64_t ldU, int64_t P, int ell, const double* __restrict__ lam, double mu,
+    const double* __restrict__ part, int nchunk, const double* __restrict__ r, double* __restrict__ z,
+    double* __restrict__ rz_part, PcgState* __restrict__ st) {
+  if (st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* coef = reinterpret_cast<double*>(smem_raw);
+  __shared__ double wsum[kApWaves][kApCols];
+  __shared__ double red[kApWaves];
+  const double c = 1.0 / (lam[ell - 1] + mu);
+  for (int i = threadIdx.x; i < ell; i += blockDim.x) {
+    double si = 0.0;
+    for (int q = 0; q < nchunk; ++q) si += part[(int64_t)q * ell + i];
+    coef[i] = (1.0 / (lam[i] + mu) - c) * si;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * kApCols + 2 * lane;  // this lane's columns j, j + 1
+  double a0 = 0.0, a1 = 0.0;
+  if (j < P) {
+    if constexpr (VEC) {  // j even and ldU even: the pair is aligned and j + 1 < ldU
+      using V2 = typename Pair<T>::type;
+#pragma unroll 8
+      for (int i = w; i < ell; i += kApWaves) {
+        const V2 u = *reinterpret_cast<const V2*>(U + (int64_t)i * ldU + j);
+        a0 += coef[i] * (double)u.x;
+        a1 += coef[i] * (double)u.y;
+      }
+    } else {
+      const bool two = j + 1 < P;
+#pragma unroll 8
+      for (int i = w; i < ell; i += kApWaves) {
+        const T* u = U + (int64_t)i * ldU + j;
+        a0 += coef[i] * (double)u[0];
+        if (two) a1 += coef[i] * (double)u[1];
+      }
+    }
+  }
+  wsum[w][2 * lane] = a0;
+  wsum[w][2 * lane + 1] = a1;
+  __syncthreads();
+  double rz = 0.0;
+  if (threadIdx.x < kApCols) {
+    const int64_t jj = (int64_t)blockIdx.x * kApCols + threadIdx.x;
+    if (jj < P) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kApWaves; ++q) acc += wsum[q][threadIdx.x];
+      const double zj = c * r[jj] + acc;
+      z[jj] = zj;
+      rz = zj * r[jj];
+    }
+  }
+  rz = block_sum(rz, red);
+  const int nb = (int)gridDim.x;
+  double tot;
+  if (!publish_and_reduce(rz, rz_part, (int)blockIdx.x, &st->counter, (unsigned)(nb), red, &tot)) return;
+  if (threadIdx.x == 0) {
+    if (st->iters == 0 && st->beta == 0.0) {
+      st->rz = tot;  // initial z_0 = P^{-1} r_0
+    } else {
+      st->beta = tot / st->rz;
+      st->rz = tot;
+    }
+    if (!isfinite(tot) || !(tot > 0.0)) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
 }
 
 // initial state: x = 0, r = g, p_prev = 0; ||g||^2 and the stopping threshold
@@ -497,9 +599,8 @@ __device__ __forceinline__ void pcg_init_body(const double* __restrict__ g, int6
     gg = gj * gj;
   }
   gg = block_sum(gg, red);
-  if (threadIdx.x == 0) part[bid] = gg;
-  if (!arrive_last(&st->counter, nb)) return;
-  const double tot = block_sum_array(part, nb, red);
+  double tot;
+  if (!publish_and_reduce(gg, part, (int)bid, &st->counter, (unsigned)(nb), red, &tot)) return;
   if (threadIdx.x == 0) {
     st->bnorm2 = tot;
     st->rr = tot;
@@ -535,9 +636,8 @@ __global__ void dot_stage_kernel(const double* __restrict__ a, const double* __r
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
     acc += a[j] * b[j];
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
-  if (!arrive_last(counter, gridDim.x)) return;
-  const double tot = block_sum_array(part, (int)gridDim.x, red);
+  double tot;
+  if (!publish_and_reduce(acc, part, (int)blockIdx.x, counter, (unsigned)(gridDim.x), red, &tot)) return;
   if (threadIdx.x == 0) *out = tot;
 }
 
@@ -822,23 +922,46 @@ ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld
   return NGD_OK;
 }
 
+// column chunks of the preconditioner dots: enough workgroups to cover the device, chunks of at
+// least 1024 columns, at most kDotChunksMax (the size of the partial buffer, kDotChunksMax x ell)
+int precond_dot_chunks(int64_t P, int ell) {
+  const int64_t rowblocks = (ell + kDotRows - 1) / kDotRows;
+  int64_t nc = (1024 + rowblocks - 1) / rowblocks;
+  if (nc > P / 1024) nc = P / 1024;
+  if (nc > kDotChunksMax) nc = kDotChunksMax;
+  return (int)(nc < 1 ? 1 : nc);
+}
+
 ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s) {
-  const size_t lds = (size_t)ell * sizeof(double);
-  dim3 grid((unsigned)((P + 255) / 256));
-  if (dtype == NGD_F64) {
-    hipLaunchKernelGGL(precond_dots_kernel<double>, dim3(ell), dim3(256), 0, s, (const double*)U, ldU, P, r, sbuf, st);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)precond_apply_kernel<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(precond_apply_kernel<double>, grid, dim3(256), lds, s, (const double*)U, ldU, P, ell, lam, mu,
-                       sbuf, r, z, rz_part, st);
-  } else {
-    hipLaunchKernelGGL(precond_dots_kernel<float>, dim3(ell), dim3(256), 0, s, (const float*)U, ldU, P, r, sbuf, st);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)precond_apply_kernel<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(precond_apply_kernel<float>, grid, dim3(256), lds, s, (const float*)U, ldU, P, ell, lam, mu,
-                       sbuf, r, z, rz_part, st);
+  if (ell < 1 || P < 1) {
+    set_error("preconditioner with no rows or no columns");
+    return NGD_ERR_INVALID;
   }
+  const size_t lds = (size_t)ell * sizeof(double);
+  const int nchunk = precond_dot_chunks(P, ell);
+  const int64_t chunk = (P + nchunk - 1) / nchunk;
+  const dim3 dgrid((unsigned)((ell + kDotRows - 1) / kDotRows), (unsigned)nchunk);
+  const dim3 agrid((unsigned)((P + kApCols - 1) / kApCols));
+  const size_t esz = dtype == NGD_F64 ? 8 : 4;
+  const bool vec = ldU % 2 == 0 && (reinterpret_cast<uintptr_t>(U) % (2 * esz)) == 0;
+#define NGD_APPLY(TT, VV)                                                                                      \
+  do {                                                                                                         \
+    auto k = precond_apply_cols_kernel<TT, VV>;                                                                \
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
+    hipLaunchKernelGGL(k, agrid, dim3(64 * kApWaves), lds, s, (const TT*)U, ldU, P, ell, lam, mu, sbuf, nchunk, \
+                       r, z, rz_part, st);                                                                     \
+  } while (0)
+  if (dtype == NGD_F64) {
+    hipLaunchKernelGGL(precond_dots_chunk_kernel<double>, dgrid, dim3(256), 0, s, (const double*)U, ldU, P, ell, chunk,
+                       r, sbuf, st);
+    if (vec) NGD_APPLY(double, true); else NGD_APPLY(double, false);
+  } else {
+    hipLaunchKernelGGL(precond_dots_chunk_kernel<float>, dgrid, dim3(256), 0, s, (const float*)U, ldU, P, ell, chunk,
+                       r, sbuf, st);
+    if (vec) NGD_APPLY(float, true); else NGD_APPLY(float, false);
+  }
+#undef NGD_APPLY
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
