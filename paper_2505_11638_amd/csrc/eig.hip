@@ -392,6 +392,7 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
     return;
   }
   const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
+  const double inv_tiny = recip(tiny);
   auto at = [&](int j) { return (int64_t)j * n + i; };
   // factorisation of T - lam I fused with the first forward sweep (start vector: deterministic
   // pseudo-random entries in [0.5, 1.5))
@@ -415,31 +416,22 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
         const double c = cj[u], dn = dj[u] - lam, en = ej[u];
         h = (h ^ (unsigned)(j + 1)) * 16777619u + 0x9E3779B9u;
         const double nxt = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
-        double piv, m, x0, x1;
-        if (fabs(a) >= fabs(c)) {
-          piv = a;
-          m = a != 0.0 ? c * recip(a) : 0.0;
-          U1[at(j)] = b;
-          U2[at(j)] = 0.0;
-          SW[at(j)] = 0.0;
-          a = dn - m * b;
-          b = en;
-          x0 = carry;
-          x1 = nxt;
-        } else {
-          piv = c;
-          m = a * recip(c);
-          U1[at(j)] = dn;
-          U2[at(j)] = en;
-          SW[at(j)] = 1.0;
-          a = b - m * dn;
-          b = -m * en;
-          x0 = nxt;
-          x1 = carry;
-        }
+        // partial pivoting between rows j (a, b) and j + 1 (c, dn, en), without branches (the lanes
+        // of a wave pivot differently) and with one reciprocal: the pivot's serves the multiplier
+        // and, unless the pivot is below `tiny` (then replaced by +-tiny), the stored 1/pivot
+        const bool sw = !(fabs(a) >= fabs(c));
+        const double piv = sw ? c : a, oth = sw ? a : c;
+        const double rp = recip(piv);
+        const double m = piv != 0.0 ? oth * rp : 0.0;
+        U1[at(j)] = sw ? dn : b;
+        U2[at(j)] = sw ? en : 0.0;
+        SW[at(j)] = sw ? 1.0 : 0.0;
+        const double an = (sw ? b : dn) - m * (sw ? dn : b);
+        b = sw ? -m * en : en;
+        a = an;
+        const double x0 = sw ? nxt : carry, x1 = sw ? carry : nxt;
         ML[at(j)] = m;
-        if (fabs(piv) < tiny) piv = piv < 0.0 ? -tiny : tiny;
-        RI[at(j)] = recip(piv);
+        RI[at(j)] = fabs(piv) < tiny ? (piv < 0.0 ? -inv_tiny : inv_tiny) : rp;
         Y[at(j)] = x0;
         carry = x1 - m * x0;
       }
