@@ -49,8 +49,10 @@ struct TriArgs {
 // complete before the workgroup publishes its flag.
 constexpr int kTrWaves = 8;
 constexpr int kTrThreads = 64 * kTrWaves;
-// rows per wave: four, or three where four would not fit in registers with 16 columns per lane
-constexpr int tr_rows(int qn) { return qn <= 13 ? 4 : 3; }
+// rows per wave: four up to 8 columns per lane; from there more workgroups with fewer rows each
+// measured faster (two rows up to 13 columns per lane, three beyond, where four would not fit in
+// registers with 16 columns per lane)
+constexpr int tr_rows(int qn) { return qn <= 8 ? 4 : (qn <= 13 ? 2 : 3); }
 constexpr int kTrMaxN = 1024;
 constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column LDS entries per thread
 
