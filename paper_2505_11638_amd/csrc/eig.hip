@@ -311,58 +311,79 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
-// eigenvalue index i (ascending) of T by bisection; also prepares e^2
-__global__ void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
-                              double* __restrict__ e2, double* __restrict__ lam_asc, double* __restrict__ tnorm) {
+// eigenvalue index i (ascending) of T by multisection on Sturm counts; also prepares e^2
+// wpe (1 or 2) waves per eigenvalue, 4 / wpe eigenvalues per 256-thread workgroup: their 64 wpe lanes
+// evaluate 64 wpe interior points of the current interval and the first point whose count exceeds i
+// bounds eigenvalue i from above, so each round shrinks the interval (64 wpe + 1)-fold. Two waves per
+// eigenvalue pay off while they still find a SIMD of their own. Every eigenvalue starts from the same
+// Gershgorin interval and every round divides its width by the same factor, so the number of rounds
+// is the same for all of them and is fixed up front (workgroup barriers stay uniform).
+__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                     int n, int wpe, double* __restrict__ e2,
+                                                     double* __restrict__ lam_asc, double* __restrict__ tnorm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sd = reinterpret_cast<double*>(smem_raw);
   double* se2 = sd + n;
-  __shared__ double lo_s, hi_s;
+  __shared__ double red_lo[4], red_hi[4];
+  __shared__ unsigned long long mask[2][4];
+  // the tridiagonal in LDS, and the Gershgorin interval by a workgroup reduction
+  double glo = 1e300, ghi = -1e300;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    sd[j] = d[j];
-    if (j < n - 1) se2[j] = e[j] * e[j];
+    const double dj = d[j];
+    const double ej = j < n - 1 ? e[j] : 0.0;
+    sd[j] = dj;
+    if (j < n - 1) {
+      se2[j] = ej * ej;
+      if (blockIdx.x == 0) e2[j] = ej * ej;
+    }
+    const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + fabs(ej);
+    glo = fmin(glo, dj - r);
+    ghi = fmax(ghi, dj + r);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    glo = fmin(glo, __shfl_xor(glo, o, 64));
+    ghi = fmax(ghi, __shfl_xor(ghi, o, 64));
+  }
+  if (lane == 0) {
+    red_lo[wid] = glo;
+    red_hi[wid] = ghi;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double lo = 1e300, hi = -1e300;
-    for (int j = 0; j < n; ++j) {
-      double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < n - 1 ? fabs(e[j]) : 0.0);
-      lo = fmin(lo, sd[j] - r);
-      hi = fmax(hi, sd[j] + r);
-    }
-    lo_s = lo;
-    hi_s = hi;
-    if (blockIdx.x == 0) {
-      *tnorm = fmax(fabs(lo), fabs(hi));
-      for (int j = 0; j < n - 1; ++j) e2[j] = se2[j];
-    }
-  }
-  __syncthreads();
-  // multisection: one wave per eigenvalue; its 64 lanes evaluate 64 interior points of the current
-  // interval, the first point whose Sturm count exceeds i bounds eigenvalue i from above. Each round
-  // shrinks the interval 65-fold; stop at an absolute width of a few ulps of ||T||.
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const double tn = fmax(fabs(lo_s), fabs(hi_s));
+  glo = fmin(fmin(red_lo[0], red_lo[1]), fmin(red_lo[2], red_lo[3]));
+  ghi = fmax(fmax(red_hi[0], red_hi[1]), fmax(red_hi[2], red_hi[3]));
+  const double tn = fmax(fabs(glo), fabs(ghi));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tnorm = tn;
   const double pivmin = fmax(1e-300, 2.2250738585072014e-308 * fmax(1.0, tn * tn));
-  double lo = lo_s - 1e-14 * tn - pivmin, hi = hi_s + 1e-14 * tn + pivmin;
+  double lo = glo - 1e-14 * tn - pivmin, hi = ghi + 1e-14 * tn + pivmin;
   const double tol = 4.0 * 2.220446049250313e-16 * tn + pivmin;
-  for (int it = 0; it < 16 && hi - lo > tol; ++it) {
-    const double h = (hi - lo) / 65.0;
-    const double x = lo + h * (lane + 1);
-    const bool above = sturm_count(sd, se2, n, x, pivmin) > i;
+  // rounds until the width (hi - lo) / (64 wpe + 1)^r is at most tol (at most 16)
+  const double div = 64.0 * wpe + 1.0;
+  int rounds = 0;
+  for (double w = hi - lo; w > tol && rounds < 16; w /= div) ++rounds;
+  const int pair = wid / wpe, half = wid - pair * wpe;
+  const int i = blockIdx.x * (4 / wpe) + pair;
+  const int ic = i < n ? i : n - 1;  // waves past the end follow a valid eigenvalue and store nothing
+  for (int it = 0; it < rounds; ++it) {
+    const double h = (hi - lo) / div;
+    const double x = lo + h * (64 * half + lane + 1);
+    const bool above = sturm_count(sd, se2, n, x, pivmin) > ic;
     const unsigned long long m = __ballot(above);
-    if (m == 0ull) {
-      lo = lo + h * 64.0;
+    if (lane == 0) mask[it & 1][wid] = m;
+    __syncthreads();
+    const unsigned long long m0 = mask[it & 1][wpe * pair];
+    const unsigned long long m1 = wpe == 2 ? mask[it & 1][wpe * pair + 1] : 0ull;
+    if (m0 == 0ull && m1 == 0ull) {
+      lo = lo + h * (64.0 * wpe);
     } else {
-      const int first = __ffsll((long long)m) - 1;
+      const int first = m0 != 0ull ? __ffsll((long long)m0) - 1 : 64 + __ffsll((long long)m1) - 1;
       const double nhi = lo + h * (first + 1);
       lo = first == 0 ? lo : lo + h * first;
       hi = nhi;
     }
   }
-  if (lane == 0) lam_asc[i] = 0.5 * (lo + hi);
+  if (i < n && half == 0 && lane == 0) lam_asc[i] = 0.5 * (lo + hi);
 }
 
 // inverse iteration for eigenvalue i: solve (T - lam I) x = b by LU with partial pivoting
@@ -840,8 +861,16 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   TriArgs ta{A, A1, n, dvec, evec, V, tau, wk, ws.flags, err};
   NGD_TRY(launch_tridiag(ta, s));
   const int tb = 256;
-  hipLaunchKernelGGL(bisect_kernel, dim3((n + 3) / 4), dim3(tb), 2 * sizeof(double) * n, s, dvec, evec, n, e2,
-                     lam, tnorm);
+  {
+    // two waves per eigenvalue while the 2n waves find a SIMD each, else one
+    int dev = 0, cus = 0;
+    NGD_HIP_TRY(hipGetDevice(&dev));
+    NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int wpe = 2 * n <= 4 * cus ? 2 : 1;
+    const int per_block = 4 / wpe;
+    hipLaunchKernelGGL(bisect_kernel, dim3((n + per_block - 1) / per_block), dim3(tb), 2 * sizeof(double) * n, s, dvec,
+                       evec, n, wpe, e2, lam, tnorm);
+  }
   {
     // the factors of inverse iteration: five n x n arrays in wk, the interchanges in A1 (both free
     // after the tridiagonalisation)
