@@ -165,7 +165,10 @@ typedef struct {
  *   U             : device, ell x ldU, dtype, out: row i = eigenvector i (unit norm, orthogonal),
  *                   rows for dropped (zero) eigenvalues are zero. ldU >= P.
  *   lam_hat       : device, ell doubles, out: eigenvalues, descending, >= 0.
- *   info          : host, nullable. If non-NULL the call synchronises `stream` and fills it.
+ *   info          : host, nullable. If non-NULL the call synchronises `stream`, fills it and
+ *                   reports a timed-out exchange inside the FP64 core. If NULL the call does not
+ *                   synchronise, and the next ngd_pcg_solve / ngd_pcg_solve_damped with this
+ *                   preconditioner (same ell) reports that error instead.
  */
 ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed,
                               uint64_t counter, const void* omega, int64_t ldO, int32_t sketch_dtype,
@@ -200,6 +203,21 @@ typedef struct {
 ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
                          const ngd_precond* prec, double rtol, int64_t maxit, double* d,
                          ngd_pcg_info* info, void* stream);
+
+/*
+ * ngd_pcg_solve with the damping chosen on the device by the rule of Section 4.3,
+ *   lambda = max(c_lam * prec->lam_hat[0], c_loss * loss[0]^2)
+ * (lam_hat[0] = lambda_hat_1 of the sketch; with c_lam = gamma eps and c_loss = 1e-4 this is the
+ * paper's mu), so that the call can follow ngd_nystrom_sketch(..., info = NULL) without the host
+ * reading lambda_hat_1 first: the sketch and the solve then share one host round trip.
+ *   c_lam, c_loss : >= 0, not both 0. loss : device, 1 double (as written by ngd_residual_jacobian).
+ *   prec          : required. lambda_used : host, nullable, out: the lambda of the solve.
+ * Everything else, including the synchronisation and the errors, is as for ngd_pcg_solve.
+ */
+ngd_status ngd_pcg_solve_damped(ngd_problem* h, const ngd_operator* op, const double* g, double c_lam,
+                                double c_loss, const double* loss, const ngd_precond* prec, double rtol,
+                                int64_t maxit, double* d, ngd_pcg_info* info, double* lambda_used,
+                                void* stream);
 
 /*
  * Largest-eigenvalue estimate of J_w^T J_w by the power method (Section 4.3: 2-4 iterations):

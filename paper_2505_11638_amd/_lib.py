@@ -60,6 +60,9 @@ SIGNATURES = {
                                      C.POINTER(NystromInfo), C.c_void_p]),
     "ngd_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_double, C.POINTER(Precond),
                                 C.c_double, C.c_int64, C.c_void_p, C.POINTER(PcgInfo), C.c_void_p]),
+    "ngd_pcg_solve_damped": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_double, C.c_double,
+                                       C.c_void_p, C.POINTER(Precond), C.c_double, C.c_int64, C.c_void_p,
+                                       C.POINTER(PcgInfo), C.POINTER(C.c_double), C.c_void_p]),
     "ngd_power_lambda_max": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int32,
                                        C.POINTER(C.c_double), C.c_void_p]),
     "ngd_line_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,

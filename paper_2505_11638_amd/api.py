@@ -49,6 +49,7 @@ class PcgResult:
     converged: bool
     breakdown: bool
     status: int
+    mu: Optional[float] = None  # the damping of the solve (set when the device chose it)
 
 
 class Recompute:
@@ -196,7 +197,9 @@ class Problem:
         return NystromResult(U, lam, d)
 
     def pcg_solve(self, J: torch.Tensor, g: torch.Tensor, lam: float, precond: Optional[NystromResult] = None,
-                  rtol: float = 1e-6, maxit: int = 1000, raise_on_fail=False) -> PcgResult:
+                  rtol: float = 1e-6, maxit: int = 1000, raise_on_fail=False, damping=None) -> PcgResult:
+        """ngd_pcg_solve with damping lam; or, with damping = (c_lam, c_loss, loss tensor) and a
+        preconditioner, ngd_pcg_solve_damped: lam = max(c_lam lam_hat[0], c_loss loss^2) on the device."""
         _need(g, torch.float64, "g")
         d = torch.empty(self.P, dtype=torch.float64, device=self.device)
         info = L.PcgInfo()
@@ -204,12 +207,27 @@ class Problem:
         if precond is not None:
             pc = L.Precond(precond.U.data_ptr(), precond.U.stride(0), precond.lam_hat.data_ptr(),
                            precond.lam_hat.numel())
-        st = self.lib.ngd_pcg_solve(self.h, C.byref(self._op(J)), _ptr(g), float(lam),
-                                    C.byref(pc) if pc is not None else None, float(rtol), int(maxit), _ptr(d),
-                                    C.byref(info), _stream())
+        mu = None
+        if damping is not None:
+            if pc is None:
+                raise ValueError("the device damping rule needs a preconditioner")
+            c_lam, c_loss, loss = damping
+            _need(loss, torch.float64, "loss")
+            lam_used = C.c_double()
+            st = self.lib.ngd_pcg_solve_damped(self.h, C.byref(self._op(J)), _ptr(g), float(c_lam), float(c_loss),
+                                               _ptr(loss), C.byref(pc), float(rtol), int(maxit), _ptr(d),
+                                               C.byref(info), C.byref(lam_used), _stream())
+            mu = float(lam_used.value)
+            where = "ngd_pcg_solve_damped"
+        else:
+            st = self.lib.ngd_pcg_solve(self.h, C.byref(self._op(J)), _ptr(g), float(lam),
+                                        C.byref(pc) if pc is not None else None, float(rtol), int(maxit), _ptr(d),
+                                        C.byref(info), _stream())
+            where = "ngd_pcg_solve"
         allow = () if raise_on_fail else (L.NGD_ERR_NOT_CONVERGED, L.NGD_ERR_BREAKDOWN)
-        L.check(st, "ngd_pcg_solve", allow)
-        return PcgResult(d, int(info.iters), float(info.rel_res), bool(info.converged), bool(info.breakdown), st)
+        L.check(st, where, allow)
+        return PcgResult(d, int(info.iters), float(info.rel_res), bool(info.converged), bool(info.breakdown), st,
+                         mu)
 
     def power_lambda_max(self, J: torch.Tensor, v0: torch.Tensor, iters: int = 4) -> float:
         _need(v0, torch.float64, "v0")

@@ -85,6 +85,8 @@ struct ngd_problem {
   // search that had to halve (the same step is chosen either way)
   int ls_batch = 1;
   int ls_first_batch = 1;
+  // ell of the last sketch taken without its summary (its core's error words not read yet), or 0
+  int64_t unchecked_ell = 0;
 };
 
 namespace {
@@ -585,6 +587,9 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
     return launch_gemm(g6, s);
   }));
+  // without a summary the call does not synchronise; the next PCG solve with this preconditioner
+  // reads the core's error words instead
+  h->unchecked_ell = info == nullptr ? L : 0;
   if (info != nullptr) {
     // one gather kernel and one copy into pinned memory: a single host round trip
     double* hv = reinterpret_cast<double*>(h->host);
@@ -609,12 +614,22 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   return NGD_OK;
 }
 
-ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
-                         const ngd_precond* prec, double rtol, int64_t maxit, double* d, ngd_pcg_info* info,
-                         void* stream) {
+namespace {
+
+// The PCG solve behind ngd_pcg_solve (lambda given) and ngd_pcg_solve_damped (rule != NULL: lambda
+// = max(c_lam lam_hat[0], c_loss loss^2) on the device). When the handle's last sketch was taken
+// without its summary, its core's error words travel with the PCG state and are checked here.
+struct DampingRule {
+  double c_lam, c_loss;
+  const double* loss;
+};
+
+ngd_status pcg_solve_impl(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
+                          const DampingRule* rule, const ngd_precond* prec, double rtol, int64_t maxit, double* d,
+                          ngd_pcg_info* info, double* lambda_used, void* stream) {
   NGD_CHECK(h != nullptr && g != nullptr && d != nullptr && info != nullptr, "NULL argument");
   NGD_TRY(check_op(h, op));
-  NGD_CHECK(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
+  if (rule == nullptr) NGD_CHECK(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
   NGD_CHECK(rtol >= 0.0 && maxit >= 0, "rtol >= 0 and maxit >= 0 required");
   if (prec != nullptr) {
     NGD_CHECK(prec->U != nullptr && prec->lam_hat != nullptr, "preconditioner pointers are NULL");
@@ -625,13 +640,21 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
   const int plain = prec == nullptr;
   PcgState* hs = reinterpret_cast<PcgState*>(h->host);
   std::memset(hs, 0, sizeof(PcgState));
-  hs->lambda = lambda;
+  hs->lambda = rule != nullptr ? 0.0 : lambda;
   hs->maxit = maxit;
   NGD_HIP_TRY(hipMemcpyAsync(h->pcg_st, hs, sizeof(PcgState), hipMemcpyHostToDevice, s));
+  const bool check_sketch = prec != nullptr && h->unchecked_ell > 0 && prec->ell == h->unchecked_ell;
+  if (rule != nullptr || check_sketch) {
+    NGD_TRY(pcg_launch_setup(h->pcg_st, rule != nullptr ? prec->lam_hat : nullptr, rule != nullptr ? rule->c_lam : 0.0,
+                             rule != nullptr ? rule->loss : nullptr, rule != nullptr ? rule->c_loss : 0.0,
+                             check_sketch ? eig_error_flag(h->eigw, (int)prec->ell) : nullptr,
+                             check_sketch ? h->cholsync + 128 : nullptr, s));
+  }
+  if (check_sketch) h->unchecked_ell = 0;
   NGD_TRY(pcg_launch_init(g, P, d, h->pcg_r, h->pcg_p[0], h->pcg_part, h->pcg_st, rtol, plain, s));
   double* zsrc = h->pcg_r;
   if (!plain) {
-    NGD_TRY(pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, lambda, h->pcg_s,
+    NGD_TRY(pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, h->pcg_s,
                                h->pcg_r, h->pcg_z, h->pcg_part, h->pcg_st, s));
     zsrc = h->pcg_z;
   }
@@ -661,7 +684,7 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
       }
       if (!plain)
         NGD_TRY(timed(h, NGD_TIMER_PRECOND, s, [&] {
-          return pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, lambda, h->pcg_s,
+          return pcg_launch_precond(h->dtype, prec->U, prec->ldU, P, (int)prec->ell, prec->lam_hat, h->pcg_s,
                                     h->pcg_r, h->pcg_z, h->pcg_part, h->pcg_st, s);
         }));
     }
@@ -690,6 +713,15 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
   info->rel_res = hs->bnorm2 > 0 ? std::sqrt(hs->rr / hs->bnorm2) : 0.0;
   info->converged = hs->converged;
   info->breakdown = hs->breakdown;
+  if (lambda_used != nullptr) *lambda_used = hs->lambda;
+  if (hs->sketch_err & 1) {
+    set_error("exchange between the workgroups of the sketch's tridiagonalisation timed out");
+    return NGD_ERR_HIP;
+  }
+  if (hs->sketch_err & 2) {
+    set_error("exchange between the workgroups of the sketch's Cholesky factorisation timed out");
+    return NGD_ERR_HIP;
+  }
   if (hs->breakdown) {
     set_error("PCG breakdown (non-positive curvature or non-finite value)");
     return NGD_ERR_BREAKDOWN;
@@ -699,6 +731,23 @@ ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g
     return NGD_ERR_NOT_CONVERGED;
   }
   return NGD_OK;
+}
+
+}  // namespace
+
+ngd_status ngd_pcg_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda,
+                         const ngd_precond* prec, double rtol, int64_t maxit, double* d, ngd_pcg_info* info,
+                         void* stream) {
+  return pcg_solve_impl(h, op, g, lambda, nullptr, prec, rtol, maxit, d, info, nullptr, stream);
+}
+
+ngd_status ngd_pcg_solve_damped(ngd_problem* h, const ngd_operator* op, const double* g, double c_lam,
+                                double c_loss, const double* loss, const ngd_precond* prec, double rtol,
+                                int64_t maxit, double* d, ngd_pcg_info* info, double* lambda_used, void* stream) {
+  NGD_CHECK(prec != nullptr && loss != nullptr, "the damping rule needs the preconditioner and the loss");
+  NGD_CHECK(c_lam >= 0.0 && c_loss >= 0.0 && (c_lam > 0.0 || c_loss > 0.0), "c_lam, c_loss >= 0, not both 0");
+  const DampingRule rule{c_lam, c_loss, loss};
+  return pcg_solve_impl(h, op, g, 0.0, &rule, prec, rtol, maxit, d, info, lambda_used, stream);
 }
 
 ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const double* v0, int32_t iters, double* lam1,

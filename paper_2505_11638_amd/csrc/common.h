@@ -50,6 +50,7 @@ struct PcgState {
   int converged;
   int breakdown;
   unsigned counter; // arrival counter for last-block reductions
+  int sketch_err;   // the core of the sketch behind the preconditioner timed out (checked when asked)
 };
 
 void set_error(const std::string& msg);
@@ -273,7 +274,11 @@ ngd_status pcg_launch_direction(int dtype, const double* z, const double* p_prev
 // column chunks of the preconditioner dots (the partial buffer holds kDotChunksMax x ell doubles)
 constexpr int kDotChunksMax = 16;
 int precond_dot_chunks(int64_t P, int ell);
-ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
+// before PCG initialisation: lambda from the damping rule max(c_lam lam_hat[0], c_loss loss^2) when
+// lam_hat != NULL, and the sketch's error words (either pointer may be NULL) into st->sketch_err
+ngd_status pcg_launch_setup(PcgState* st, const double* lam_hat, double c_lam, const double* loss, double c_loss,
+                            const int* eig_err, const unsigned* chol_err, hipStream_t s);
+ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s);
 
 // Batched PCG (several independent problems per launch): one entry per problem, in device memory.

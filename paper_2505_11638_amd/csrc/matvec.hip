@@ -513,10 +513,11 @@ template <> struct Pair<double> { typedef double type __attribute__((ext_vector_
 
 template <typename T, bool VEC>
 __global__ __launch_bounds__(64 * kApWaves) void precond_apply_cols_kernel(
-    const T* __restrict__ U, int64_t ldU, int64_t P, int ell, const double* __restrict__ lam, double mu,
+    const T* __restrict__ U, int64_t ldU, int64_t P, int ell, const double* __restrict__ lam,
     const double* __restrict__ part, int nchunk, const double* __restrict__ r, double* __restrict__ z,
     double* __restrict__ rz_part, PcgState* __restrict__ st) {
   if (st->done) return;
+  const double mu = st->lambda;  // the solve's damping (set on the device by the damping rule)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* coef = reinterpret_cast<double*>(smem_raw);
   __shared__ double wsum[kApWaves][kApCols];
@@ -700,9 +701,27 @@ __global__ __launch_bounds__(256) void pcg_batch_apply_kernel(const PcgBatchItem
                         it - b.item0_apply, (int)((b.P + 255) / 256));
 }
 
+// one thread: the damping rule of Section 4.3 evaluated on the device, and the sketch's error words
+__global__ void pcg_setup_kernel(PcgState* __restrict__ st, const double* __restrict__ lam_hat, double c_lam,
+                                 const double* __restrict__ loss, double c_loss, const int* __restrict__ eig_err,
+                                 const unsigned* __restrict__ chol_err) {
+  if (lam_hat != nullptr) st->lambda = fmax(c_lam * lam_hat[0], c_loss * (loss[0] * loss[0]));
+  int e = 0;
+  if (eig_err != nullptr && *eig_err != 0) e |= 1;
+  if (chol_err != nullptr && *chol_err != 0u) e |= 2;
+  st->sketch_err = e;
+}
+
 }  // namespace
 
 // ---------------- host launchers ----------------
+
+ngd_status pcg_launch_setup(PcgState* st, const double* lam_hat, double c_lam, const double* loss, double c_loss,
+                            const int* eig_err, const unsigned* chol_err, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_setup_kernel, dim3(1), dim3(1), 0, s, st, lam_hat, c_lam, loss, c_loss, eig_err, chol_err);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
 
 // One-pass configurations (block, NK, R): a workgroup per CU, so a lane may hold 256 VGPRs; R rows
 // per step are chosen so that the 2R row buffers and the accumulator, (2R + 1) NK 16-byte chunks,
@@ -932,7 +951,7 @@ int precond_dot_chunks(int64_t P, int ell) {
   return (int)(nc < 1 ? 1 : nc);
 }
 
-ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam, double mu,
+ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, int ell, const double* lam,
                               double* sbuf, const double* r, double* z, double* rz_part, PcgState* st, hipStream_t s) {
   if (ell < 1 || P < 1) {
     set_error("preconditioner with no rows or no columns");
@@ -949,7 +968,7 @@ ngd_status pcg_launch_precond(int dtype, const void* U, int64_t ldU, int64_t P, 
   do {                                                                                                         \
     auto k = precond_apply_cols_kernel<TT, VV>;                                                                \
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));   \
-    hipLaunchKernelGGL(k, agrid, dim3(64 * kApWaves), lds, s, (const TT*)U, ldU, P, ell, lam, mu, sbuf, nchunk, \
+    hipLaunchKernelGGL(k, agrid, dim3(64 * kApWaves), lds, s, (const TT*)U, ldU, P, ell, lam, sbuf, nchunk,     \
                        r, z, rz_part, st);                                                                     \
   } while (0)
   if (dtype == NGD_F64) {

@@ -59,8 +59,10 @@ class NGD:
         if power_v0 is None:
             power_v0 = np.random.default_rng(np.random.SeedSequence([seed, 99])).standard_normal(gp.P)
         self.v0 = torch.as_tensor(power_v0, dtype=torch.float64, device=gp.device)
-        # pinned landing slot of the loss: its copy rides the stream and is read after the next sync
+        # pinned landing slots of the loss and of lambda_hat_1: their copies ride the stream and are
+        # read after the next synchronisation (the power iteration's or the solve's)
         self.loss_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
+        self.lam1_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.k = 0
 
     def step(self) -> StepReport:
@@ -68,23 +70,30 @@ class NGD:
         r, J, grad, loss = gp.residual_jacobian(self.theta, self.J)
         if self.recompute:
             J = Recompute(self.theta)
-        pc = None
-        rank = -1
-        # the loss comes back by an asynchronous copy on the same stream; the sketch (or the power
-        # iteration) synchronises that stream, after which the pinned slot holds it
         self.loss_host.copy_(loss, non_blocking=True)
         if self.solver == "nystrom":
-            pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype)
-            lam1 = pc.info["lam1"]
-            rank = pc.info["rank"]
+            # sketch, damping (Section 4.3) and solve with no host round trip in between: the sketch
+            # returns no summary and the solve takes mu on the device
+            pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype,
+                                   want_info=False)
+            self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
+            if self.lam is not None:
+                out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit)
+                mu = self.lam
+            else:
+                out = gp.pcg_solve(J, grad, None, precond=pc, rtol=self.rtol, maxit=self.maxit,
+                                   damping=(self.gamma * self.eps, 1e-4, loss))
+                mu = out.mu
+            lam1 = float(self.lam1_host[0])
+            L0 = float(self.loss_host[0])
         else:
             lam1 = gp.power_lambda_max(J, self.v0, 4)
-        L0 = float(self.loss_host[0])
-        mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
-        out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit)
+            L0 = float(self.loss_host[0])
+            mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
+            out = gp.pcg_solve(J, grad, mu, precond=None, rtol=self.rtol, maxit=self.maxit)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
-        return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
+        return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1)
 
 
 class BatchNGD:

@@ -198,6 +198,29 @@ def test_pcg_solve_matches_direct_solve(name, precond):
         assert out.iters <= 3 * ref.iters + 10
 
 
+@pytest.mark.parametrize("name", ["poisson2d_f64", "poisson2d_f32"])
+def test_pcg_solve_damped_matches_host_damping(name):
+    """The damping rule of Section 4.3 taken on the device (after a sketch that returns no summary)
+    gives the lambda the host rule gives from the same lambda_hat_1 and loss, and then the same solve
+    bit for bit; the rule's two branches are both exercised."""
+    prob, th, gp = _setup(name)
+    theta = gp.theta(th)
+    J = gp.new_jacobian()
+    r, J, grad, loss = gp.residual_jacobian(theta, J)
+    pc = gp.nystrom_sketch(J, prob.ell, seed=5, want_info=False)
+    lam1 = float(pc.lam_hat[0].item())
+    L0 = float(loss.item())
+    for c_lam, c_loss in [(1e-3, 1e-4), (1e-12, 1.0)]:
+        mu = max(c_lam * lam1, c_loss * (L0 * L0))
+        ref = gp.pcg_solve(J, grad, mu, precond=pc, rtol=1e-6, maxit=1000)
+        out = gp.pcg_solve(J, grad, None, precond=pc, rtol=1e-6, maxit=1000, damping=(c_lam, c_loss, loss))
+        assert out.mu == mu
+        assert out.iters == ref.iters and out.converged == ref.converged
+        assert torch.equal(out.d, ref.d)
+    with pytest.raises(ValueError):
+        gp.pcg_solve(J, grad, None, precond=None, damping=(1e-3, 1e-4, loss))
+
+
 def test_pcg_edge_cases():
     prob, th, gp = _setup("poisson2d_f64")
     theta = gp.theta(th)
