@@ -23,7 +23,13 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+_RAW_STREAM = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream():
+    """The current stream of the current device, as the void* the ABI takes."""
+    if _RAW_STREAM is not None:
+        return C.c_void_p(_RAW_STREAM(torch.cuda.current_device()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -131,12 +137,18 @@ class Problem:
 
     # -- entry points -------------------------------------------------------------------------------
     def residual_jacobian(self, theta: torch.Tensor, J: Optional[torch.Tensor] = None, want_grad=True,
-                          want_loss=True):
-        """ngd_residual_jacobian: returns (r_w, J or None, grad or None, loss tensor or None)."""
+                          want_loss=True, out=None):
+        """ngd_residual_jacobian: returns (r_w, J or None, grad or None, loss tensor or None). `out`, if
+        given, is an (r_w, grad, loss) triple of buffers from a previous call to write into."""
         _need(theta, self.tdtype, "theta")
-        r = torch.empty(self.N, dtype=self.tdtype, device=self.device)
-        grad = torch.empty(self.P, dtype=torch.float64, device=self.device) if want_grad else None
-        loss = torch.empty(1, dtype=torch.float64, device=self.device) if want_loss else None
+        if out is not None:
+            r, grad, loss = out
+            grad = grad if want_grad else None
+            loss = loss if want_loss else None
+        else:
+            r = torch.empty(self.N, dtype=self.tdtype, device=self.device)
+            grad = torch.empty(self.P, dtype=torch.float64, device=self.device) if want_grad else None
+            loss = torch.empty(1, dtype=torch.float64, device=self.device) if want_loss else None
         ldJ = J.stride(0) if J is not None else 0
         if J is not None:
             _need(J, self.tdtype, "J")
@@ -181,10 +193,14 @@ class Problem:
 
     def nystrom_sketch(self, J: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
                        omega: Optional[torch.Tensor] = None, sketch_dtype: Optional[str] = None,
-                       want_info=True) -> NystromResult:
+                       want_info=True, out: Optional[NystromResult] = None) -> NystromResult:
+        """ngd_nystrom_sketch; `out`, if given, is a previous result of the same ell to write into."""
         sd = _DTYPE[sketch_dtype or ("f64" if self.dtype == L.NGD_F64 else "f32")]
-        U = torch.empty((ell, self.ld), dtype=self.tdtype, device=self.device)
-        lam = torch.empty(ell, dtype=torch.float64, device=self.device)
+        if out is not None and out.lam_hat.numel() == ell:
+            U, lam = out.U, out.lam_hat
+        else:
+            U = torch.empty((ell, self.ld), dtype=self.tdtype, device=self.device)
+            lam = torch.empty(ell, dtype=torch.float64, device=self.device)
         info = L.NystromInfo()
         ldO = 0
         if omega is not None:
@@ -197,11 +213,15 @@ class Problem:
         return NystromResult(U, lam, d)
 
     def pcg_solve(self, J: torch.Tensor, g: torch.Tensor, lam: float, precond: Optional[NystromResult] = None,
-                  rtol: float = 1e-6, maxit: int = 1000, raise_on_fail=False, damping=None) -> PcgResult:
+                  rtol: float = 1e-6, maxit: int = 1000, raise_on_fail=False, damping=None,
+                  out: Optional[torch.Tensor] = None) -> PcgResult:
         """ngd_pcg_solve with damping lam; or, with damping = (c_lam, c_loss, loss tensor) and a
-        preconditioner, ngd_pcg_solve_damped: lam = max(c_lam lam_hat[0], c_loss loss^2) on the device."""
+        preconditioner, ngd_pcg_solve_damped: lam = max(c_lam lam_hat[0], c_loss loss^2) on the device.
+        `out`, if given, is a P-double device buffer for d."""
         _need(g, torch.float64, "g")
-        d = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        d = torch.empty(self.P, dtype=torch.float64, device=self.device) if out is None else out
+        if d.numel() != self.P or d.dtype != torch.float64 or not d.is_contiguous():
+            raise ValueError("out must be a contiguous P-double tensor")
         info = L.PcgInfo()
         pc = None
         if precond is not None:

@@ -63,11 +63,17 @@ class NGD:
         # read after the next synchronisation (the power iteration's or the solve's)
         self.loss_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.lam1_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
+        self.loss_np, self.lam1_np = self.loss_host.numpy(), self.lam1_host.numpy()
+        # per-step device buffers, reused: residuals, gradient, loss and the search direction
+        self.bufs = None
+        self.pc = None
+        self.d = torch.empty(gp.P, dtype=torch.float64, device=gp.device)
         self.k = 0
 
     def step(self) -> StepReport:
         gp = self.gp
-        r, J, grad, loss = gp.residual_jacobian(self.theta, self.J)
+        r, J, grad, loss = gp.residual_jacobian(self.theta, self.J, out=self.bufs)
+        self.bufs = (r, grad, loss)
         if self.recompute:
             J = Recompute(self.theta)
         self.loss_host.copy_(loss, non_blocking=True)
@@ -75,22 +81,23 @@ class NGD:
             # sketch, damping (Section 4.3) and solve with no host round trip in between: the sketch
             # returns no summary and the solve takes mu on the device
             pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype,
-                                   want_info=False)
+                                   want_info=False, out=self.pc)
+            self.pc = pc
             self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
             if self.lam is not None:
-                out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit)
+                out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
                 mu = self.lam
             else:
                 out = gp.pcg_solve(J, grad, None, precond=pc, rtol=self.rtol, maxit=self.maxit,
-                                   damping=(self.gamma * self.eps, 1e-4, loss))
+                                   damping=(self.gamma * self.eps, 1e-4, loss), out=self.d)
                 mu = out.mu
-            lam1 = float(self.lam1_host[0])
-            L0 = float(self.loss_host[0])
+            lam1 = float(self.lam1_np[0])
+            L0 = float(self.loss_np[0])
         else:
             lam1 = gp.power_lambda_max(J, self.v0, 4)
-            L0 = float(self.loss_host[0])
+            L0 = float(self.loss_np[0])
             mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
-            out = gp.pcg_solve(J, grad, mu, precond=None, rtol=self.rtol, maxit=self.maxit)
+            out = gp.pcg_solve(J, grad, mu, precond=None, rtol=self.rtol, maxit=self.maxit, out=self.d)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
         return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1)
