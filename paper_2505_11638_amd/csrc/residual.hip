@@ -729,7 +729,9 @@ int residual_blocks(const NetDesc& net, int dtype, int64_t N, bool with_jacobian
 
 static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes, bool fwd_only) {
   auto need = [&](int t) { return (fwd_only ? lds_elems_fwd(net, t) : lds_elems(net, t)) * elem; };
-  int tp = 16;
+  // small tiles (more workgroups, several per CU) measured fastest; the residual-only layout starts
+  // from the same size, so that both sweeps group the loss partials alike (bitwise the same loss)
+  int tp = 4;
   while (tp > 1 && need(tp) > 96 * 1024) tp >>= 1;
   // wide layers: trade occupancy for more points per staged weight matrix
   while (tp < 4 && need(2 * tp) <= 150 * 1024) tp <<= 1;
