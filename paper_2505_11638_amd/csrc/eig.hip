@@ -34,8 +34,9 @@ struct TriArgs {
 };
 
 // ---- register-resident tridiagonalisation (n <= kTrMaxN) ----
-// The Householder recurrence with the trailing matrix in registers: 8 waves per workgroup, each
-// owning up to four of the workgroup's rows, lane l holding columns l, l + 64, ... Per column k:
+// The Householder recurrence with the trailing matrix in registers: 8 or 16 waves per workgroup,
+// each owning two or three of the workgroup's rows, lane l holding columns l, l + 64, ... Per
+// column k:
 //  (A) wave 0 forms the Householder vector v_k from the pivot row (with the pending rank-2 update of
 //      step k-1 applied) while every wave applies that pending update to its rows;
 //  (C) each row's p_i = tau_k row_i . v_k, and the owner of row k+1 publishes that row;
@@ -47,14 +48,12 @@ struct TriArgs {
 // barrier. The exchanged vectors are written and read with device-coherent (sc1) accesses, so the
 // grid barrier needs no cache write-back or invalidate: each thread waits for its own stores to
 // complete before the workgroup publishes its flag.
-constexpr int kTrWaves = 8;
-constexpr int kTrThreads = 64 * kTrWaves;
-// rows per wave: four up to 8 columns per lane; from there more workgroups with fewer rows each
-// measured faster (two rows up to 13 columns per lane, three beyond, where four would not fit in
-// registers with 16 columns per lane)
-constexpr int tr_rows(int qn) { return qn <= 8 ? 4 : (qn <= 13 ? 2 : 3); }
+// waves per workgroup and rows per wave: 16 x 2 up to 7 columns per lane, 8 x 2 up to 13 and 8 x 3
+// beyond (where more rows would not fit in registers with 16 columns per lane); these measured
+// fastest among the shapes that keep the workgroup count at or below 64
+constexpr int tr_waves(int qn) { return qn <= 7 ? 16 : 8; }
+constexpr int tr_rows(int qn) { return qn <= 13 ? 2 : 3; }
 constexpr int kTrMaxN = 1024;
-constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column LDS entries per thread
 
 __device__ __forceinline__ void st_coherent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -108,8 +107,10 @@ __device__ __forceinline__ double read_lane(double t, int l) {
     (out) = read_lane(t_, (j) & 63);                   \
   } while (0)
 
-template <int QN, int kTrRows>
-__global__ __launch_bounds__(kTrThreads) void tridiag_reg_kernel(TriArgs a) {
+template <int QN, int kTrRows, int kTrWaves>
+__global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
+  constexpr int kTrThreads = 64 * kTrWaves;
+  constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column LDS entries per thread
   __shared__ double vbuf[2][kTrMaxN];  // v of this step and of the previous one (by parity)
   __shared__ double pbuf[kTrMaxN];     // p of the previous step
   __shared__ double pivl[kTrMaxN];     // the pivot row (before the pending update)
@@ -390,9 +391,9 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
 // (tridiagonal; the U factor has two superdiagonals), two sweeps. One thread per eigenvalue, 64
 // eigenvalues per wave: the factors live in a global workspace laid out [array][j][i] (consecutive
 // eigenvalues adjacent, so every access is coalesced), and the sequential recurrences read them in
-// chunks of sixteen that are loaded before they are used. Quotients are a hardware reciprocal refined
+// chunks of 32 that are loaded before they are used. Quotients are a hardware reciprocal refined
 // by one Newton step.
-constexpr int kInvChunk = 16;
+constexpr int kInvChunk = 32;
 
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -797,11 +798,15 @@ ngd_status check_coresident(const void* kernel, int threads, size_t lds, int blo
 template <int QN>
 ngd_status launch_tridiag_reg(const TriArgs& ta, hipStream_t s) {
   // as few workgroups as hold the rows: the barrier's cost grows with the number of workgroups
-  constexpr int RW = tr_rows(QN);
-  const int per = kTrWaves * RW;
+  constexpr int RW = tr_rows(QN), WV = tr_waves(QN);
+  const int per = WV * RW;
   const int blocks = (ta.n + per - 1) / per;
-  NGD_TRY(check_coresident((const void*)tridiag_reg_kernel<QN, RW>, kTrThreads, 0, blocks));
-  hipLaunchKernelGGL((tridiag_reg_kernel<QN, RW>), dim3(blocks), dim3(kTrThreads), 0, s, ta);
+  if (blocks > 64) {  // the barrier polls one flag per lane of one wave
+    set_error("tridiagonalisation: more than 64 workgroups");
+    return NGD_ERR_INVALID;
+  }
+  NGD_TRY(check_coresident((const void*)tridiag_reg_kernel<QN, RW, WV>, 64 * WV, 0, blocks));
+  hipLaunchKernelGGL((tridiag_reg_kernel<QN, RW, WV>), dim3(blocks), dim3(64 * WV), 0, s, ta);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
