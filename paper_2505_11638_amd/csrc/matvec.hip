@@ -73,8 +73,8 @@ __device__ __forceinline__ void axpy_vec<double>(double t, const vd2& a, vd2& y)
 // ones are reduced and accumulated, so that about 2R rows per CU are in flight against HBM.
 // `stage` fills vs (and does any other per-launch set-up), followed by a workgroup barrier; for
 // short rows it runs after the first rows' loads have been issued, so its own reads overlap them.
-// With `wts` non-null the row coefficients are given (t_r = wts[r], no dot products and no
-// reductions): acc = sum_r wts[r] J_r, the one-pass form of the gradient J_w^T r_w.
+// With `wts` non-null the row coefficients are given (t_r = wts[r - r0]: wts points at row r0's, no
+// dot products and no reductions): acc = sum_r t_r J_r, the one-pass form of the gradient J_w^T r_w.
 template <typename T, int NK, int R, typename Stage>
 __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, int64_t r0, int64_t r1,
                                           const T* vs, RowRegs<T, NK>& acc, double& tsq, Stage&& stage,
@@ -128,7 +128,7 @@ __device__ __forceinline__ void rows_pass(const T* __restrict__ J, int64_t ldJ, 
     if (wts != nullptr) {  // given coefficients: accumulate and move on
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const T tt = base + q < nrows ? wts[r0 + base + q] : T(0);
+        const T tt = base + q < nrows ? wts[base + q] : T(0);
 #pragma unroll
         for (int k = 0; k < NK; ++k) axpy_vec<T>(tt, cur[q][k], acc.c[k]);
       }
@@ -218,12 +218,22 @@ __global__ __launch_bounds__(B) void gram_rows_kernel(const T* __restrict__ J, i
 // partials of the gradient J^T r (r in the Jacobian's dtype): rows weighted by r, no reductions
 template <typename T, int NK, int R, int B>
 __global__ __launch_bounds__(B) void grad_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N,
-                                                      const T* __restrict__ r, T* __restrict__ partial) {
+                                                      const T* __restrict__ r, T* __restrict__ partial,
+                                                      int max_staged) {
   int64_t r0, r1;
   row_range(N, &r0, &r1, blockIdx.x, gridDim.x);
   RowRegs<T, NK> acc;
   double tsq = 0;
-  rows_pass<T, NK, R>(J, ldJ, r0, r1, nullptr, acc, tsq, [] {}, r);
+  // the workgroup's row coefficients in LDS when they fit (launched with that much dynamic LDS), so
+  // that no global load waits inside the row loop
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ws = reinterpret_cast<T*>(smem_raw);
+  const int nr = (int)(r1 - r0);
+  const bool staged = nr <= max_staged;
+  if (staged)
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) ws[i] = r[r0 + i];
+  __syncthreads();
+  rows_pass<T, NK, R>(J, ldJ, r0, r1, nullptr, acc, tsq, [] {}, staged ? ws : r + r0);
   store_partial<T, NK>(partial, ldJ, acc, blockIdx.x);
 }
 
@@ -801,9 +811,14 @@ static ngd_status grad_rows_t(const T* J, int64_t ldJ, int64_t N, const T* r, T*
     set_error("Jacobian row too long for the one-pass gradient");
     return NGD_ERR_INVALID;
   }
+  // rows per workgroup (the balanced split of row_range), staged in LDS up to 16 KB
+  const int64_t per = (N + nwg - 1) / nwg;
+  const int max_staged = per * (int64_t)sizeof(T) <= 16 * 1024 ? (int)per : 0;
+  const size_t lds = (size_t)max_staged * sizeof(T);
 #define NGD_CALL(ID, B, NK, R)                                                            \
   case ID: {                                                                              \
-    hipLaunchKernelGGL((grad_rows_kernel<T, NK, R, B>), dim3(nwg), dim3(B), 0, s, J, ldJ, N, r, partial); \
+    hipLaunchKernelGGL((grad_rows_kernel<T, NK, R, B>), dim3(nwg), dim3(B), lds, s, J, ldJ, N, r, partial,      \
+                       max_staged);                                                       \
     break;                                                                                \
   }
   NGD_CFG_DISPATCH(c.id, NGD_CALL)
