@@ -75,9 +75,10 @@ typedef struct ngd_problem ngd_problem;  /* opaque; owns device workspace only *
 
 /* The linear operator J_w at a fixed theta. Either J is the stored Jacobian (N x P, leading
  * dimension ldJ >= P, dtype) produced by ngd_residual_jacobian for `theta`, or J is NULL: the
- * recompute mode, where every product with J_w or J_w^T is formed from theta by the forward-
- * tangent (ngd_jvp) and adjoint (ngd_vjp) kernels and J_w is never stored (for N x P beyond memory;
- * "Recompute Jacobian" of Section 4.1.2). */
+ * recompute mode, where J_w is never stored whole (for N x P beyond memory; "Recompute Jacobian" of
+ * Section 4.1.2). Its matvecs are formed from theta by the forward-tangent (ngd_jvp) and adjoint
+ * (ngd_vjp) kernels; its sketch recomputes J_w a block of rows at a time into a scratch buffer of at
+ * most 128 MB, allocated by the handle on the first recompute-mode sketch. */
 typedef struct {
   const void* theta;       /* device, P, dtype (read only in the recompute mode) */
   const void* J;           /* device, N x ldJ, dtype, or NULL (recompute mode) */

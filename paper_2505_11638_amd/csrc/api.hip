@@ -50,6 +50,8 @@ struct ngd_problem {
   void* Jt;          // P x ldN, J_w^T in the sketch compute type (FP32 problems)
   void* Qt;          // max_ell x ldN, Q^T in the sketch compute type (FP32 problems)
   void* Ob;          // max_ell x ldP, Omega^T in BF16 (FP32 problems)
+  void* Jc = nullptr;  // recompute-mode sketch: a block of rows of J_w (jc_rows x ldP, dtype), on first use
+  int64_t jc_rows = 0;
   double* nvec[2];   // N-vectors (FP64): recompute-mode J v and adjoint weights
   void* pt;          // ldP, dtype: the current CG direction for the recompute-mode JVP
   int nwg_vjp;       // workgroups of the recompute-mode adjoint product
@@ -381,6 +383,7 @@ ngd_status ngd_problem_destroy(ngd_problem* h) {
   }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->Jc) (void)hipFree(h->Jc);
   (void)hipFree(h->base);
   (void)hipHostFree(h->host);
   delete h;
@@ -485,6 +488,36 @@ ngd_status ngd_gaussian_omega(ngd_problem* h, uint64_t seed, uint64_t counter, i
   return launch_gaussian_omega(h->dtype, seed, counter, h->P, ell, omega, ld, S(stream));
 }
 
+namespace {
+
+// Recompute mode: rows [r0, r0 + rows) of J_w at theta into the handle's row-block buffer (allocated on
+// first use, at most 128 MB), by the residual/Jacobian kernel on that slice of the points.
+ngd_status jc_ensure(ngd_problem* h) {
+  if (h->Jc != nullptr) return NGD_OK;
+  const int64_t row_bytes = h->ldP * (int64_t)h->elem;
+  int64_t rows = std::max<int64_t>(64, (int64_t)(128ll << 20) / row_bytes);
+  rows = std::min<int64_t>(rows, h->N);
+  if (hipMalloc(&h->Jc, (size_t)rows * row_bytes) != hipSuccess) {
+    h->Jc = nullptr;
+    set_error("hipMalloc of the recompute-mode row block failed");
+    return NGD_ERR_OOM;
+  }
+  h->jc_rows = rows;
+  return NGD_OK;
+}
+
+ngd_status jc_rows_at(ngd_problem* h, const void* theta, int64_t r0, int64_t rows, hipStream_t s) {
+  const size_t e = h->elem;
+  const char* X = static_cast<const char*>(h->X) + (size_t)r0 * h->net.d * e;
+  const char* w = static_cast<const char*>(h->w) + (size_t)r0 * e;
+  const char* f = static_cast<const char*>(h->f) + (size_t)r0 * e;
+  const char* g = static_cast<const char*>(h->g) + (size_t)r0 * e;
+  return launch_residual_jacobian(h->net, h->dtype, theta, rows, X, w, f, g, h->kind + r0, nullptr, h->Jc, h->ldP,
+                                  h->loss_part, 0, 1, s, nullptr);
+}
+
+}  // namespace
+
 ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
                               const void* omega, int64_t ldO, int32_t sketch_dtype, void* U, int64_t ldU,
                               double* lam_hat, ngd_nystrom_info* info, void* stream) {
@@ -509,9 +542,14 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     omega = h->omega;
     ldO = h->ldP;
   }
-  // recompute mode: the ell columns of Z = J_w Omega by the JVP kernel, the rows of B^T = Q^T J_w by
-  // the adjoint kernel (one launch per column of Q); the products run in the problem's dtype
+  // recompute mode: J_w is never stored whole. Each product is formed a block of rows at a time: the
+  // residual/Jacobian kernel recomputes the block into a scratch buffer and the block's share of
+  // Z = J_w Omega (its rows) or of B^T = Q^T J_w (a rank-`rows` update) follows with the same GEMM
+  // kernels as the stored path. Every row of J_w is formed twice per sketch instead of swept ell times
+  // by the tangent and adjoint kernels.
   const bool rec = op->J == nullptr;
+  if (rec) NGD_TRY(jc_ensure(h));
+  const bool nt_rec = rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, h->jc_rows, L, P, h->ldP, ldO);
   // the NT kernel (large tiles, both operands K-contiguous) serves the FP32 / BF16 sketch
   const int et = gt == G_BF16 ? NGD_BF16 : NGD_F32;
   const bool nt = !rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
@@ -520,7 +558,7 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   const void* om_nt = omega;
   int64_t ld_nt = ldO;
   int om_type = NGD_F32;
-  if (nt && gt == G_BF16) {
+  if ((nt || nt_rec) && gt == G_BF16) {
     NGD_TRY(launch_cast_rows(NGD_F32, omega, ldO, L, P, NGD_BF16, h->Ob, h->ldP, s));
     om_nt = h->Ob;
     ld_nt = h->ldP;
@@ -528,8 +566,21 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   }
   // Z = J Omega (N x ell)
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] {
-    if (rec)
-      return launch_jvp(h->net, T, op->theta, omega, ldO, L, N, h->X, h->w, h->kind, T, h->Z, L, 1, s);
+    if (rec) {
+      for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
+        const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);
+        NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+        void* Zr = static_cast<char*>(h->Z) + (size_t)r0 * L * h->elem;
+        if (nt_rec) {
+          NGD_TRY(launch_nt_gemm(NGD_F32, h->Jc, h->ldP, om_type, om_nt, ld_nt, gt, rows, L, P, NGD_F32, Zr, L, false,
+                                 1.0, h->sk_work, h->sk_work_elems, s));
+        } else {
+          GemmArgs g1{rows, L, P, h->Jc, h->ldP, true, omega, ldO, true, Zr, L, T, T, T, gt, 1.0, 0.0};
+          NGD_TRY(launch_gemm(g1, s));
+        }
+      }
+      return NGD_OK;
+    }
     if (nt) return launch_nt_gemm(NGD_F32, op->J, op->ldJ, om_type, om_nt, ld_nt, gt, N, L, P, NGD_F32, h->Z, L,
                                   false, 1.0, h->sk_work, h->sk_work_elems, s);
     GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
@@ -562,11 +613,12 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   if (nt) NGD_HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
     if (rec) {
-      for (int64_t j = 0; j < L; ++j) {
-        NGD_TRY(launch_vjp(h->net, T, op->theta, N, h->X, h->w, h->f, h->g, h->kind, (const double*)h->Q + j, L,
-                           h->partial, h->ldP, h->tsq, h->nwg_vjp, s));
-        NGD_TRY(launch_partials_to_row(T, h->partial, h->nwg_vjp, h->ldP, P,
-                                       static_cast<char*>(h->Bt) + (size_t)j * h->ldP * h->elem, s));
+      for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
+        const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);
+        NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+        GemmArgs g4{L, P, rows, (const double*)h->Q + r0 * L, L, false, h->Jc, h->ldP, false, h->Bt, h->ldP,
+                    NGD_F64, T, T, gt, 1.0, r0 == 0 ? 0.0 : 1.0};
+        NGD_TRY(launch_gemm(g4, s));
       }
       return NGD_OK;
     }

@@ -267,8 +267,6 @@ ngd_status pcg_launch_rows(int dtype, const void* J, int64_t ldJ, int64_t N, int
 ngd_status pcg_launch_update(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, const double* p,
                              const double* tsq, double* x, double* r, double* rr_part, PcgState* st, int plain,
                              hipStream_t s);
-ngd_status launch_partials_to_row(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, void* out,
-                                  hipStream_t s);
 ngd_status pcg_launch_direction(int dtype, const double* z, const double* p_prev, int64_t P, double* p_cur, void* p_t,
                                 double* part, PcgState* st, hipStream_t s);
 // column chunks of the preconditioner dots (the partial buffer holds kDotChunksMax x ell doubles)

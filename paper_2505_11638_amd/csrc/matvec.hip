@@ -278,16 +278,6 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
   if (threadIdx.x < kRedCols && j < P) y[j] = lambda != 0.0 ? acc + lambda * v[j] : acc;
 }
 
-// out[j] = sum of the partial rows (FP32 / FP64 storage), for one row of B^T in recompute mode
-template <typename T>
-__global__ __launch_bounds__(256) void partials_to_row_kernel(const T* __restrict__ partial, int nwg, int64_t ld,
-                                                              int64_t P, T* __restrict__ out) {
-  __shared__ double buf[kRedGroups][kRedCols];
-  int64_t j;
-  const double acc = sum_partials(partial, nwg, ld, P, buf, &j, blockIdx.x);
-  if (threadIdx.x < kRedCols && j < P) out[j] = (T)acc;
-}
-
 // recompute-mode CG direction: p = z + beta p_prev (FP64 and a dtype copy for the JVP), pp = p.p
 template <typename T>
 __global__ __launch_bounds__(256) void pcg_direction_kernel(const double* __restrict__ z,
@@ -865,19 +855,6 @@ ngd_status launch_dot(const double* a, const double* b, int64_t n, double* work,
 
 ngd_status launch_scale_rsqrt(const double* w, const double* ww, int64_t n, double* v, hipStream_t s) {
   hipLaunchKernelGGL(scale_by_rsqrt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, ww, n, v);
-  NGD_HIP_TRY(hipGetLastError());
-  return NGD_OK;
-}
-
-ngd_status launch_partials_to_row(int dtype, const void* partial, int nwg, int64_t ld, int64_t P, void* out,
-                                  hipStream_t s) {
-  dim3 grid((unsigned)((P + kRedCols - 1) / kRedCols));
-  if (dtype == NGD_F64)
-    hipLaunchKernelGGL(partials_to_row_kernel<double>, grid, dim3(256), 0, s, (const double*)partial, nwg, ld, P,
-                       (double*)out);
-  else
-    hipLaunchKernelGGL(partials_to_row_kernel<float>, grid, dim3(256), 0, s, (const float*)partial, nwg, ld, P,
-                       (float*)out);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
