@@ -634,7 +634,7 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
     NGD_TRY(launch_gemm(g5, s));
     // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
     // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
-    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s));
+    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
     NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
     GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
     return launch_gemm(g6, s);

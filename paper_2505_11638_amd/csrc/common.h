@@ -239,8 +239,10 @@ ngd_status launch_transpose_cast(int src_type, const void* src, int64_t ld_s, in
 // eig.hip: symmetric eigendecomposition of an n x n FP64 matrix (row-major, ld = n), in place.
 // Eigenpairs below drop_rel * ||T|| (Gershgorin bound) are returned as zeros. A is overwritten.
 size_t eig_workspace_bytes(int n);
+// side, fork, join: a second stream and two events for the part that overlaps (side may be NULL)
 ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
-                          hipStream_t s);
+                          hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
+                          hipEvent_t join = nullptr);
 const int* eig_error_flag(void* work, int n);
 
 // misc.hip

@@ -10,8 +10,10 @@
 //  3. Eigenvectors of T by inverse iteration with partial-pivoting LU of T - lambda I (one thread
 //     per eigenvector), modified Gram-Schmidt inside clusters of (nearly) equal eigenvalues, and two
 //     Newton-Schulz steps that restore orthonormality to working precision.
-//  4. Back-transformation V = H_0 H_1 ... H_{n-3} Z in compact WY blocks on the FP64 matrix cores
-//     (one workgroup per 16 columns).
+//  4. Back-transformation V = Q Z. Q = H_0 H_1 ... H_{n-3} is formed explicitly from the compact
+//     WY blocks on the FP64 matrix cores (one workgroup per 16 columns) as soon as step 1 is done,
+//     on a second stream where one is given, so that it runs beside steps 2 and 3; V is then a
+//     single FP64 product.
 // n <= 1024.
 // Eigenpairs whose eigenvalue is below drop_rel * (Gershgorin bound of T) are returned as
 // (0, zero vector).
@@ -625,8 +627,8 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double* __restrict__ V,
     Tall[(int64_t)blockIdx.x * kWy * kWy + e] = Ts[e / kWy][e % kWy];
 }
 
-// The same back-transformation on the FP64 matrix cores, for n <= kBtMaxN. A workgroup owns 16
-// columns of Z, held in registers as 16 x 16 accumulator tiles (tile t = rows 16t .. 16t+15, tiles
+// Forming Q on the FP64 matrix cores, for n <= kBtMaxN. A workgroup owns 16 columns of Z (the
+// identity at the start, Q at the end), held in registers as 16 x 16 accumulator tiles (tile t = rows 16t .. 16t+15, tiles
 // dealt round-robin to the waves). Per block of kWy reflectors, staged in LDS:
 //   W = Y^T Z   (each wave over its tiles, partial sums reduced through LDS),
 //   S = T W     (every wave, redundantly: four MFMAs),
@@ -646,10 +648,12 @@ __device__ __forceinline__ bt_d4 mfma64(double a, double b, bt_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
-    const double* __restrict__ Z, const double* __restrict__ V, const double* __restrict__ Tall,
-    const double* __restrict__ lam_asc, int n, const double* __restrict__ tnorm, double drop_rel,
-    double* __restrict__ evals_desc, double* __restrict__ evec_rows) {
+// Q = H_0 H_1 ... H_{n-3} applied to the identity, written row-major (n x n) to Qm. Each
+// workgroup owns 16 columns, held in MFMA accumulators over all row tiles; the reflector blocks are
+// applied from the last to the first as I - Y T Y^T (compact WY form).
+__global__ __launch_bounds__(64 * kBtWaves) void form_q_mfma_kernel(const double* __restrict__ V,
+                                                                    const double* __restrict__ Tall, int n,
+                                                                    double* __restrict__ Qm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nt = (n + 15) / 16;
   const int ldy = nt * 16 + 1;  // odd pitch: the 16 reflector rows fall in distinct LDS banks
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * t + lq + 4 * r;
-      acc[i][r] = (t < nt && row < n && col < n) ? Z[(int64_t)row * n + col] : 0.0;
+      acc[i][r] = (t < nt && row < n && row == col) ? 1.0 : 0.0;
     }
   }
   const int nref = n - 2;
@@ -734,10 +738,6 @@ __global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
       }
     }
   }
-  // eigenvector rows in descending eigenvalue order; dropped pairs as (0, zero vector)
-  const double drop = drop_rel * (*tnorm);
-  const bool keep = col < n && lam_asc[col] >= drop;
-  if (wid == 0 && lq == 0 && col < n) evals_desc[n - 1 - col] = keep ? lam_asc[col] : 0.0;
   if (col < n) {
 #pragma unroll
     for (int i = 0; i < kBtTiles; ++i) {
@@ -745,17 +745,30 @@ __global__ __launch_bounds__(64 * kBtWaves) void backtransform_mfma_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * t + lq + 4 * r;
-        if (t < nt && row < n) evec_rows[(int64_t)(n - 1 - col) * n + row] = keep ? acc[i][r] : 0.0;
+        if (t < nt && row < n) Qm[(int64_t)row * n + col] = acc[i][r];
       }
     }
   }
 }
 
+// Eigenvector rows in descending eigenvalue order from Xt = (Q Z)^T (row c = eigenvector of the c-th
+// smallest eigenvalue); pairs below the drop threshold become (0, zero vector)
+__global__ void eig_finalize_kernel(const double* __restrict__ Xt, const double* __restrict__ lam_asc, int n,
+                                    const double* __restrict__ tnorm, double drop_rel,
+                                    double* __restrict__ evals_desc, double* __restrict__ evec_rows) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;  // component
+  const int col = blockIdx.y;                             // eigenvector (ascending)
+  const double drop = drop_rel * (*tnorm);
+  const bool keep = lam_asc[col] >= drop;
+  if (row == 0) evals_desc[n - 1 - col] = keep ? lam_asc[col] : 0.0;
+  if (row < n) evec_rows[(int64_t)(n - 1 - col) * n + row] = keep ? Xt[(int64_t)col * n + row] : 0.0;
+}
+
 // Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau, e2, lam
-// (n each), tnorm (8), the barrier flags (256 unsigned) and the error word (in a 1 KiB slot), then
-// the T factors of the reflector blocks.
+// (n each), tnorm (8), the barrier flags (256 unsigned) and the error word (in a 1 KiB slot), the
+// T factors of the reflector blocks, then Qm (n^2, the explicit product of the reflectors).
 struct EigWs {
-  double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *e2, *lam, *tnorm, *Tall;
+  double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *e2, *lam, *tnorm, *Tall, *Qm;
   unsigned* flags;
   int* err;
   size_t bytes;
@@ -776,7 +789,8 @@ struct EigWs {
     err = reinterpret_cast<int*>(flags + 248);
     Tall = tnorm + 8 + 128;  // the 1 KiB slot of the flags and the error word
     const size_t nblk = (size_t)n + 1;  // blocks of as few as one reflector
-    bytes = (size_t)((Tall + nblk * kWy * kWy) - w) * sizeof(double);
+    Qm = Tall + nblk * kWy * kWy;
+    bytes = (size_t)((Qm + nn) - w) * sizeof(double);
   }
 };
 
@@ -842,8 +856,12 @@ ngd_status launch_tridiag(const TriArgs& ta, hipStream_t s) {
 size_t eig_workspace_bytes(int n) { return EigWs(nullptr, n).bytes; }
 
 ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
-                               hipStream_t s) {
+                               hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
   if (n <= 0) return NGD_OK;
+  if (n > kBtMaxN) {
+    set_error("symmetric eigensolver: n above 1024");
+    return NGD_ERR_INVALID;
+  }
   EigWs ws(work, n);
   double* A1 = ws.A1;
   double* V = ws.V;
@@ -865,6 +883,25 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   // exchange buffers of the tridiagonalisation (2 n each): PV in A1, P in wk (both free until it is done)
   TriArgs ta{A, A1, n, dvec, evec, V, tau, wk, ws.flags, err};
   NGD_TRY(launch_tridiag(ta, s));
+  // The explicit Q = H_0 ... H_{n-3} needs only the reflectors: on the side stream (when given) it
+  // overlaps the eigenvalues, the eigenvectors of T and their orthogonalisation below, and the
+  // back-transformation becomes one product Q Z at the end.
+  hipStream_t qs = side != nullptr ? side : s;
+  if (side != nullptr) {
+    NGD_HIP_TRY(hipEventRecord(fork, s));
+    NGD_HIP_TRY(hipStreamWaitEvent(side, fork, 0));
+  }
+  {
+    const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
+    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, qs, V, tau, n, ws.Tall);
+    const int nt = (n + 15) / 16;
+    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kBtWaves * 256);
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)form_q_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    hipLaunchKernelGGL(form_q_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, qs, V, ws.Tall, n, ws.Qm);
+    NGD_HIP_TRY(hipGetLastError());
+  }
+  if (side != nullptr) NGD_HIP_TRY(hipEventRecord(join, side));
   const int tb = 256;
   {
     // two waves per eigenvalue while the 2n waves find a SIMD each, else one
@@ -906,22 +943,16 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
     Z = Z2;
     Z2 = t;
   }
-  // T factors of the reflector blocks (written over the multipliers of inverse iteration, free now)
-  double* Tall = ws.Tall;
-  if (n <= kBtMaxN) {
-    const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
-    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, V, tau, n, Tall);
-    const int nt = (n + 15) / 16;
-    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kBtWaves * 256);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)backtransform_mfma_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(backtransform_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, s, Z, V, Tall, lam, n, tnorm,
-                       drop_rel, evals_desc, evec_rows);
-    NGD_HIP_TRY(hipGetLastError());
-    return NGD_OK;
-  }
-  set_error("back-transformation: n above 1024");
-  return NGD_ERR_INVALID;
+  // (Q Z)^T = Z^T Q^T once Q is there, then the eigenvector rows in descending order
+  if (side != nullptr) NGD_HIP_TRY(hipStreamWaitEvent(s, join, 0));
+  double* Xt = wk;  // free after the Newton-Schulz steps (Z is back in its own buffer)
+  GemmArgs q{n, n, n, Z, n, false, ws.Qm, n, true, Xt, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
+             wk + (size_t)n * n, 4 * (int64_t)n * n};
+  NGD_TRY(launch_gemm(q, s));
+  hipLaunchKernelGGL(eig_finalize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, Xt, lam, n, tnorm, drop_rel,
+                     evals_desc, evec_rows);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
 }
 
 const int* eig_error_flag(void* work, int n) { return EigWs(work, n).err; }
