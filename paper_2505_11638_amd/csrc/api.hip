@@ -313,7 +313,9 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
     plan.push_back({&h->Jt, (size_t)P * h->ldN * 4});
     plan.push_back({&h->Qt, (size_t)L * h->ldN * 4});
     plan.push_back({&h->Ob, (size_t)L * ldP * 2});
-    h->sk_work_elems = (int64_t)16 << 20;  // 64 MB
+    // room for up to 16 slices of the larger sketch product, between 64 and 256 MB
+    h->sk_work_elems = std::min<int64_t>((int64_t)64 << 20,
+                                         std::max<int64_t>((int64_t)16 << 20, 16 * L * std::max(N, P)));
     plan.push_back({(void**)&h->sk_work, (size_t)h->sk_work_elems * 4});
   }
   plan.push_back({(void**)&h->M, sizeof(double) * (size_t)L * L});

@@ -14,6 +14,8 @@
 // workgroup's MFMA work covers this one's load latency). Tiles are numbered so that the workgroups that share an A
 // row panel run on the same XCD (workgroups are dealt to the 8 XCDs round-robin), where the panel
 // is then read from that XCD's L2.
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -278,6 +280,74 @@ __global__ void splitk_sum_kernel(const float* __restrict__ work, int ks, int64_
   out[r * ld_out + c] = alpha * acc;
 }
 
+// Split-K choice from a small model of the launch. Workgroups are dealt to the XCDs round-robin in
+// launch order (x fastest), and each XCD starts its next workgroup in the first of its resident
+// slots (two per CU) that comes free. A workgroup lasts (its slabs) x (one slab's time with two
+// workgroups per CU) x (its tile's weight): 1 for a full tile, less for an edge tile, whose MFMAs
+// outside C are skipped but whose loads and barriers are not. Slices add their partial products'
+// round trip through HBM (written by the GEMM, read by the ordered sum). The slab times are those
+// measured on MI355X for the two compute types (FP32 runs near 78% of the MFMA peak, BF16 is bound
+// by the L2 -> CU traffic of its FP32 operand).
+constexpr double kSlabUsF32 = 4.4, kSlabUsBf16 = 1.5;
+constexpr double kSumBytesPerUs = 5.0e6;  // 5 TB/s
+constexpr int kXcdSlotsMax = 256;
+
+double tile_weight(int64_t M, int64_t N, int64_t t, int64_t tiles_n) {
+  const int64_t m0 = (t / tiles_n) * kBM, n0 = (t % tiles_n) * kBN;
+  const double fm = (double)std::min<int64_t>(kBM, M - m0) / kBM, fn = (double)std::min<int64_t>(kBN, N - n0) / kBN;
+  return 0.35 + 0.65 * fm * fn;
+}
+
+double predict_us(int64_t M, int64_t N, int64_t nk, int q, double slab_us, int64_t tiles_n, int64_t tiles,
+                  int64_t per, int slots) {
+  const int per_xcd_slots = std::max(1, std::min(kXcdSlotsMax, slots / kXcd));
+  const int64_t slabs = (nk + q - 1) / q;
+  double worst = 0.0;
+  double free_at[kXcdSlotsMax];
+  for (int x = 0; x < kXcd; ++x) {
+    for (int i = 0; i < per_xcd_slots; ++i) free_at[i] = 0.0;
+    for (int y = 0; y < q; ++y)
+      for (int64_t j = 0; j < per; ++j) {
+        const int64_t t = (int64_t)x * per + j;
+        if (t >= tiles) break;
+        int best = 0;
+        for (int i = 1; i < per_xcd_slots; ++i)
+          if (free_at[i] < free_at[best]) best = i;
+        free_at[best] += (double)slabs * slab_us * tile_weight(M, N, t, tiles_n);
+      }
+    for (int i = 0; i < per_xcd_slots; ++i) worst = std::max(worst, free_at[i]);
+  }
+  if (q > 1) worst += (double)q * M * N * 8.0 / kSumBytesPerUs;
+  return worst;
+}
+
+int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_t tiles_n, int64_t tiles, int64_t per,
+                 int slots, int64_t work_elems) {
+  struct Entry { int64_t M, N, K, work; int BK, slots, ks; };
+  static Entry cache[16];
+  static int used = 0;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < used; ++i)
+    if (cache[i].M == M && cache[i].N == N && cache[i].K == K && cache[i].work == work_elems && cache[i].BK == BK &&
+        cache[i].slots == slots)
+      return cache[i].ks;
+  const int64_t nk = (K + BK - 1) / BK;
+  int ks = 1;
+  double best = predict_us(M, N, nk, 1, slab_us, tiles_n, tiles, per, slots);
+  for (int q = 2; q <= 16; ++q) {
+    if (nk / q < 8 || (int64_t)q * M * N > work_elems) break;
+    const double c = predict_us(M, N, nk, q, slab_us, tiles_n, tiles, per, slots);
+    if (c < best) {
+      best = c;
+      ks = q;
+    }
+  }
+  cache[used % 16] = Entry{M, N, K, work_elems, BK, slots, ks};
+  if (used < 16) ++used;
+  return ks;
+}
+
 template <typename TA, typename TB, typename E, typename TC>
 ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                   int64_t ldc, bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s) {
@@ -286,9 +356,7 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
   if (tiles == 0) return NGD_OK;
   const int64_t per = (tiles + kXcd - 1) / kXcd;
   constexpr int BK = Slab<E>::BK;
-  // split K so that the workgroups fill the resident slots (two per CU) in as few rounds as
-  // possible: the time is about (rounds) x (slabs per slice); at least 8 slabs per slice, and the
-  // slices' partial products must fit the workspace
+  // split K by the count of slices with the shortest predicted time (kept per shape)
   int ks = 1;
   if (work != nullptr) {
     static int slots = 0;
@@ -298,16 +366,7 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
       NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
       slots = 2 * (cus > 0 ? cus : 1);
     }
-    const int64_t nk = (K + BK - 1) / BK;
-    int64_t best = ((tiles + slots - 1) / slots) * nk;
-    for (int q = 2; q <= 16; ++q) {
-      if (nk / q < 8 || (int64_t)q * M * N > work_elems) break;
-      const int64_t cost = ((tiles * q + slots - 1) / slots) * ((nk + q - 1) / q);
-      if (cost < best) {
-        best = cost;
-        ks = q;
-      }
-    }
+    ks = choose_split(M, N, K, BK, sizeof(E) == 2 ? kSlabUsBf16 : kSlabUsF32, tn, tiles, per, slots, work_elems);
   }
   const int64_t kchunk = ks == 1 ? K : ((K + ks - 1) / ks + BK - 1) / BK * BK;
   if (ks == 1) {
