@@ -40,7 +40,72 @@ WORKLOADS = {
 WORKLOADS["c5"] = ("32 independent 2D/3D Poisson PINNs, hidden widths from {32,48,64,96}, depth 2-4 (P 1,185-28,417), "
                     "N_int 1,024-8,192 + N_int/8 boundary points, ell from {50,100,200,400}, FP32; batched residual/"
                     "Jacobian launch, per-problem Nystrom sketch, batched graph-replayed PCG, per-problem Armijo")
+WORKLOADS["paper3d"] = ("the paper's 3D Poisson PINN: 3-64-64-64-1 tanh (P=8,641), 10,000 + 1,000 random points, FP64, "
+                         "u* = sin(pi x) sin(pi y) sin(pi z); Nystrom NGD with adaptive sketch size (ell from 20 in "
+                         "steps of 20 up to 500), at most 20 PCG iterations at rtol 1e-6, mu = max(10 eps lam1_hat, "
+                         "1e-4 L^2), Armijo; relative H1 error on 100,000 random points")
+# The paper's Nystrom NGD on this problem: 66.8 s to its plateau error over at most 1,000 iterations on
+# one RTX 4090 in FP64, so at most 15.0 NGD steps/s (a derived upper bound on its rate).
+PAPER3D_BASELINE_SPS = 1000.0 / 66.8
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def bench_paper(a):
+    """The paper's own 3D Poisson setup with the full Nystrom NGD of Alg. 1 + Alg. 4 (adaptive rank)."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2505_11638_amd.driver import NGD
+
+    prob = wl.config("paper3d", seed=a.seed)
+    theta0 = wl.glorot_theta(prob.widths, a.seed)
+    P, N = prob.n_params, prob.n_rows
+    ngd = NGD(prob, theta0, solver="nystrom", rtol=1e-6, seed=a.seed)
+    gp = ngd.gp
+    Xe, ue, ge = wl.evaluation_set(prob, 100_000, seed=a.seed)
+    _, h1_start, sums = gp.solution_error(ngd.theta, Xe, ue, ge)
+    for _ in range(a.warmup):
+        ngd.step()
+    gp.timing(True, only=["matvec_rows"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [ngd.step() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_mv, ms_mv = gp.timers()["matvec_rows"]
+    gp.timing(False)
+    l2_end, h1_end, _ = gp.solution_error(ngd.theta, Xe, ue, ge, sums=sums)
+    avg_ms = ms_mv / max(n_mv, 1)
+    alg_bytes = N * P * 8 + 2 * P * 8
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    sps = a.steps / dt
+    ranks = [r.rank for r in reps]
+    line = {
+        "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
+        "value": sps, "unit": "NGD steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": sps / PAPER3D_BASELINE_SPS,
+        "baseline": {"value": PAPER3D_BASELINE_SPS, "unit": "NGD steps/s",
+                     "kind": "the paper's Nystrom NGD on this problem, RTX 4090, FP64: 66.8 s to its plateau "
+                             "over at most 1,000 iterations (an upper bound on its rate)"},
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"paper3d: {WORKLOADS['paper3d']}; {a.warmup} + {a.steps} NGD steps from a "
+                               f"Glorot start (the last {a.steps} timed)", "P": P, "N": N,
+                   "ell0": prob.ell, "ell_max": prob.ell_max, "dell": prob.dell, "maxit": prob.maxit},
+        "ell_first_last_max": [ranks[0], ranks[-1], max(ranks)],
+        "ell_trajectory": ranks,
+        "mean_pcg_iters": float(np.mean([r.iters for r in reps])),
+        "loss_first_last": [reps[0].loss, reps[-1].loss_new],
+        "rel_h1_error_start_end": [h1_start, h1_end], "rel_l2_error_end": l2_end,
+        "roofline": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v)), FP64", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": n_mv},
+    }
+    torch.cuda.synchronize()
+    gp.close()
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def bench_batch(a):
@@ -170,6 +235,8 @@ def main(argv=None):
 
     if a.config == "c5":
         return bench_batch(a)
+    if a.config == "paper3d":
+        return bench_paper(a)
 
     import numpy as np
     import torch

@@ -239,6 +239,23 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
                            double* alpha, double* loss_new, void* stream);
 
 /*
+ * Accuracy of u_theta against a reference solution on n evaluation points, the measure by which the
+ * experiments of Section 5 are compared (relative errors in L2 and H1, estimated by Monte Carlo on
+ * uniform random points as in the appendix's table of discretisations). Writes four FP64 sums:
+ *   sums[0] = sum_i (u(x_i) - u_ref_i)^2,          sums[1] = sum_i |grad u(x_i) - grad_u_ref_i|^2,
+ *   sums[2] = sum_i u_ref_i^2,                     sums[3] = sum_i |grad_u_ref_i|^2,
+ * with grad over all d inputs; then rel. L2 = sqrt(sums[0] / sums[2]) and
+ * rel. H1 = sqrt((sums[0] + sums[1]) / (sums[2] + sums[3])). Evaluation only, not part of a step.
+ *   theta : device, P values of the problem's dtype.  X : device, n x d row-major, problem dtype.
+ *   u_ref : device, n values; grad_u_ref : device, n x d row-major (both the problem's dtype).
+ *   sums  : device, 4 doubles, out (zeros for n = 0). The arithmetic is FP64 and its order is fixed.
+ * Asynchronous on `stream`. NGD_ERR_INVALID for n < 0 or NULL pointers (any pointer may be NULL
+ * when n = 0 except sums).
+ */
+ngd_status ngd_solution_error(ngd_problem* h, const void* theta, const void* X, int64_t n, const void* u_ref,
+                              const void* grad_u_ref, double* sums, void* stream);
+
+/*
  * Batches: many independent PINN problems (uneven P, N, ell; one dtype) driven together. Each batch
  * member is a full problem handle (ngd_batch_problem) usable with every single-problem entry point,
  * e.g. for its Nystrom sketch and line search; the two calls below treat all members at once.

@@ -194,3 +194,25 @@ def gradient(theta, prob) -> np.ndarray:
     """Euclidean gradient of the loss: grad L = J_w^T r_w (Alg. 1, first step)."""
     r, J = residual_and_jacobian(theta, prob)
     return J.T @ r
+
+
+def solution_error_sums(theta, widths, X, u_ref, grad_ref) -> np.ndarray:
+    """The four sums behind the relative L2 and H1 errors of u_theta against a reference solution on
+    evaluation points X (n x d), the accuracy measure of the experiments of Section 5 (Monte Carlo over
+    uniform random points): [sum (u - u_ref)^2, sum |grad u - grad u_ref|^2, sum u_ref^2,
+    sum |grad u_ref|^2], with grad over all d inputs."""
+    X = np.asarray(X, dtype=np.float64)
+    if X.shape[0] == 0:
+        return np.zeros(4)
+    # with every input a Laplacian coordinate, the forward sweep's gradient channel is grad_x u
+    u, grad, _, _, _ = taylor_forward(theta, widths, X, PDE_POISSON)
+    u_ref = np.asarray(u_ref, dtype=np.float64)
+    grad_ref = np.asarray(grad_ref, dtype=np.float64)
+    return np.array([np.sum((u - u_ref) ** 2), np.sum((grad - grad_ref) ** 2), np.sum(u_ref ** 2),
+                     np.sum(grad_ref ** 2)])
+
+
+def relative_errors(sums) -> tuple:
+    """(relative L2 error, relative H1 error) from the four sums of solution_error_sums."""
+    s = np.asarray(sums, dtype=np.float64)
+    return float(np.sqrt(s[0] / s[2])), float(np.sqrt((s[0] + s[1]) / (s[2] + s[3])))

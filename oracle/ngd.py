@@ -10,6 +10,9 @@ Readings of points the paper leaves open:
   (Rayleigh quotient of the last normalised iterate) started from a given vector.
 * Armijo (Section 4.4): alpha_0 = 1, halve until L(theta - alpha d) <= L(theta) - c1 alpha g^T d,
   c1 = 1e-4, at most 30 halvings; alpha = 0 if none is accepted.
+* adaptive sketch size (Alg. 4, Section 4.3, experimental setup of Section 5): the next rank from
+  lam_hat_ell / mu against 10, growing by dell = 20 up to ell_max = 500, shrinking to the first index
+  below the threshold plus an offset of 1; the initial rank is not stated and is taken as dell.
 * the sketch is of the undamped Gramian (Alg. 4 sketches G_fun and forms mu afterwards); the CG
   operator is G + mu I and the preconditioner uses the same mu (Alg. 3, Alg. 4).
 """
@@ -30,6 +33,23 @@ def damping(lam1_hat: float, loss_value: float, eps: float, gamma: float = 10.0,
             c: float = 1e-4) -> float:
     """mu = max(gamma * eps * lam1_hat, c * L^2)."""
     return max(gamma * eps * lam1_hat, c * loss_value ** 2)
+
+
+def next_rank(lam_hat, mu: float, ell: int, ell_max: int, dell: int, offset: int = 1) -> int:
+    """Sketch size for the next NGD step (Alg. 4, after the preconditioner is built; Section 4.3).
+
+    lam_hat holds the ell Nystrom eigenvalues in descending order. If the smallest, lam_hat_ell, is
+    above 10 mu the rank grows by dell (capped at ell_max). Otherwise it becomes the first (1-based)
+    index i with lam_hat_i < 10 mu plus `offset`, capped at ell_max. When no eigenvalue lies strictly
+    below 10 mu (lam_hat_ell equal to 10 mu) the rank is kept."""
+    lam = np.asarray(lam_hat, dtype=np.float64)[:ell]
+    thresh = 10.0 * mu
+    if lam[ell - 1] > thresh:
+        return min(ell + dell, ell_max)
+    below = np.nonzero(lam < thresh)[0]
+    if below.size == 0:
+        return min(ell, ell_max)
+    return min(int(below[0]) + 1 + offset, ell_max)
 
 
 def power_method(G_fun, v0: np.ndarray, iters: int = 4) -> float:

@@ -284,6 +284,24 @@ class Problem:
                 "ngd_line_search")
         return theta_out, a.value, ln.value
 
+    def solution_error(self, theta: torch.Tensor, X, u_ref, grad_u_ref, sums: Optional[torch.Tensor] = None):
+        """Relative L2 and H1 errors of u_theta against (u_ref, grad u_ref) on the points X (n x d), the
+        accuracy measure of Section 5 (Monte Carlo over the evaluation set). Returns
+        (rel_l2, rel_h1, sums) with the four FP64 device sums of the entry point; synchronises."""
+        to = lambda a: torch.as_tensor(np.asarray(a), dtype=self.tdtype, device=self.device).contiguous()
+        X, u_ref, grad_u_ref = to(X), to(u_ref), to(grad_u_ref)
+        n = int(X.shape[0]) if X.ndim == 2 else 0
+        if X.ndim != 2 or X.shape[1] != self.widths[0] or u_ref.shape != (n,) or grad_u_ref.shape != X.shape:
+            raise ValueError("solution_error: X must be n x d, u_ref n, grad_u_ref n x d")
+        _need(theta, self.tdtype, "theta")
+        sums = torch.empty(4, dtype=torch.float64, device=self.device) if sums is None else sums
+        L.check(self.lib.ngd_solution_error(self.h, _ptr(theta), _ptr(X), n, _ptr(u_ref), _ptr(grad_u_ref),
+                                            _ptr(sums), _stream()), "ngd_solution_error")
+        s = sums.cpu().numpy()
+        rel_l2 = float(np.sqrt(s[0] / s[2])) if s[2] > 0 else float("nan")
+        rel_h1 = float(np.sqrt((s[0] + s[1]) / (s[2] + s[3]))) if s[2] + s[3] > 0 else float("nan")
+        return rel_l2, rel_h1, sums
+
 
 class Batch:
     """Several independent problems (one dtype) bound to one libngd batch. `members[i]` is a `Problem`

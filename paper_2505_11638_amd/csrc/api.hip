@@ -33,6 +33,7 @@ struct ngd_problem {
   void* partial;     // nwg x ldP, dtype
   double* tsq;       // nwg
   double* loss_part; // res_blocks * kTrials
+  double* err_part;  // 4 * kEvalBlocks partial sums of the solution error
   double* grad_work; // gradient_chunks(N) x P
   double* vtmp[4];   // P-vectors (FP64)
   double* scal;      // small scalars / dot workspace (128 doubles)
@@ -294,6 +295,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({&h->partial, (size_t)h->nwg * ldP * e});
   plan.push_back({(void**)&h->tsq, sizeof(double) * 1024});
   plan.push_back({(void**)&h->loss_part, sizeof(double) * (size_t)h->res_blocks * kTrials});
+  plan.push_back({(void**)&h->err_part, sizeof(double) * 4 * (size_t)kEvalBlocks});
   plan.push_back({(void**)&h->grad_work, sizeof(double) * (size_t)gradient_chunks(N) * P});
   for (int i = 0; i < 4; ++i) plan.push_back({(void**)&h->vtmp[i], sizeof(double) * ldP});
   plan.push_back({(void**)&h->scal, sizeof(double) * 256});
@@ -827,6 +829,14 @@ ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const do
   NGD_HIP_TRY(hipStreamSynchronize(s));
   *lam1 = hv[0];
   return NGD_OK;
+}
+
+ngd_status ngd_solution_error(ngd_problem* h, const void* theta, const void* X, int64_t n, const void* u_ref,
+                              const void* grad_u_ref, double* sums, void* stream) {
+  NGD_CHECK(h != nullptr && sums != nullptr, "NULL argument");
+  NGD_CHECK(n >= 0, "n must be >= 0");
+  NGD_CHECK(n == 0 || (theta && X && u_ref && grad_u_ref), "NULL argument");
+  return launch_solution_error(h->net, h->dtype, theta, X, n, u_ref, grad_u_ref, h->err_part, sums, S(stream));
 }
 
 ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, const double* grad, double loss0,

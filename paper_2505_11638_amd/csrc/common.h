@@ -257,6 +257,14 @@ ngd_status launch_sketch_info(const double* lam, int L, const double* core, cons
                               double* out, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
 
+// eval.hip: the four sums of the relative L2 / H1 error of u_theta against (u_ref, grad u_ref) at n
+// points: sum (u - u_ref)^2, sum |grad u - grad u_ref|^2, sum u_ref^2, sum |grad u_ref|^2 (FP64,
+// device). `part` holds 4 * kEvalBlocks doubles of workgroup partial sums.
+constexpr int kEvalBlocks = 1024;
+ngd_status launch_solution_error(const NetDesc& net, int dtype, const void* theta, const void* X, int64_t n,
+                                 const void* u_ref, const void* grad_u_ref, double* part, double* sums,
+                                 hipStream_t s);
+
 // matvec.hip (continued)
 bool gram_rows_supported(int dtype, int64_t ldJ);
 ngd_status launch_dot(const double* a, const double* b, int64_t n, double* work, double* out, hipStream_t s);

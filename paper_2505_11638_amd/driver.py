@@ -8,6 +8,10 @@ and the update. Every numerical operation is a libngd call; the host only moves 
 Damping (Section 4.3 and the experimental setup of Section 5): mu = max(gamma eps lam1_hat, 1e-4 L^2)
 with gamma = 10 and eps the unit roundoff of the working precision, unless a fixed mu is given.
 Plain CG takes lam1_hat from 4 power iterations.
+
+Sketch size: fixed, or adaptive as in Alg. 4 (Section 4.3) when a maximum is given: after each step
+the next size grows by dell while lam_hat_ell > 10 mu, else drops to the first index with
+lam_hat_i < 10 mu plus one, never above ell_max.
 """
 from __future__ import annotations
 
@@ -37,15 +41,24 @@ class StepReport:
 
 class NGD:
     def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
-                 maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None):
-        self.gp = Problem(data, dtype=dtype, max_ell=ell or getattr(data, "ell", 1))
+                 maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None,
+                 ell_max=None, dell=None, rank_offset=1):
+        # adaptive sketch size when a maximum is given (here or by the problem)
+        self.ell_max = ell_max if ell_max is not None else getattr(data, "ell_max", None)
+        self.dell = int(dell if dell is not None else getattr(data, "dell", 20))
+        self.rank_offset = int(rank_offset)
+        self.gp = Problem(data, dtype=dtype, max_ell=self.ell_max or ell or getattr(data, "ell", 1))
         gp = self.gp
         self.solver = solver
-        self.ell = min(int(ell or data.ell), gp.P)
+        if self.ell_max is not None:
+            self.ell_max = min(int(self.ell_max), gp.P)
+        self.ell = min(int(ell or data.ell), gp.P, self.ell_max or gp.P)
         self.sketch_dtype = sketch_dtype or getattr(data, "sketch_dtype", None)
         if gp.dtype_name == "f64":
             self.sketch_dtype = "f64"
         self.rtol = rtol
+        if maxit is None:
+            maxit = getattr(data, "maxit", None)
         self.maxit = maxit if maxit is not None else (1000 if solver == "nystrom" else gp.P)
         self.lam = lam if lam is not None else getattr(data, "lam", None)
         self.gamma = gamma
@@ -64,6 +77,9 @@ class NGD:
         self.loss_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.lam1_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.loss_np, self.lam1_np = self.loss_host.numpy(), self.lam1_host.numpy()
+        # all of lam_hat when the sketch size adapts (read after the solve's synchronisation)
+        self.lam_host = (torch.empty(self.ell_max, dtype=torch.float64, pin_memory=True)
+                         if self.ell_max is not None and solver == "nystrom" else None)
         # per-step device buffers, reused: residuals, gradient, loss and the search direction
         self.bufs = None
         self.pc = None
@@ -80,10 +96,13 @@ class NGD:
         if self.solver == "nystrom":
             # sketch, damping (Section 4.3) and solve with no host round trip in between: the sketch
             # returns no summary and the solve takes mu on the device
-            pc = gp.nystrom_sketch(J, self.ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype,
+            ell = self.ell
+            pc = gp.nystrom_sketch(J, ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype,
                                    want_info=False, out=self.pc)
             self.pc = pc
             self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
+            if self.lam_host is not None:
+                self.lam_host[:ell].copy_(pc.lam_hat[:ell], non_blocking=True)
             if self.lam is not None:
                 out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
                 mu = self.lam
@@ -93,6 +112,8 @@ class NGD:
                 mu = out.mu
             lam1 = float(self.lam1_np[0])
             L0 = float(self.loss_np[0])
+            if self.lam_host is not None:
+                self.ell = self.next_rank(self.lam_host.numpy()[:ell], mu, ell)
         else:
             lam1 = gp.power_lambda_max(J, self.v0, 4)
             L0 = float(self.loss_np[0])
@@ -100,7 +121,18 @@ class NGD:
             out = gp.pcg_solve(J, grad, mu, precond=None, rtol=self.rtol, maxit=self.maxit, out=self.d)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
-        return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1)
+        rank = ell if self.solver == "nystrom" else -1
+        return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
+
+    def next_rank(self, lam_hat, mu: float, ell: int) -> int:
+        """Alg. 4's update of the sketch size from the descending eigenvalue estimates of this step."""
+        thresh = 10.0 * mu
+        if lam_hat[ell - 1] > thresh:
+            return min(ell + self.dell, self.ell_max)
+        for i in range(ell):
+            if lam_hat[i] < thresh:
+                return min(i + 1 + self.rank_offset, self.ell_max)
+        return min(ell, self.ell_max)
 
 
 class BatchNGD:

@@ -1,0 +1,107 @@
+"""GPU parity of the accuracy measure (relative L2 / H1 errors of Section 5) and of the adaptive
+sketch size of Alg. 4 as the NGD driver applies it (MI355X).
+
+The four error sums are FP64 on both sides, so they agree to 1e-12 relative on the same inputs (FP32
+problems: the oracle runs on the FP32-rounded theta, points and reference values)."""
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_helpers import make
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import mlp, ngd as ongd  # noqa: E402
+from paper_2505_11638_amd.api import Problem  # noqa: E402
+from paper_2505_11638_amd.driver import NGD  # noqa: E402
+
+CASES = {
+    "poisson2d_f64": lambda: wl.small_problem(widths=(2, 32, 32, 1), n_interior=40, n_boundary=12, seed=1),
+    "poisson3d_f64_paper_widths": lambda: wl.small_problem(d=3, widths=(3, 64, 64, 64, 1), n_interior=30,
+                                                           n_boundary=10, seed=2),
+    "poisson5d_f32": lambda: wl.small_problem(d=5, widths=(5, 48, 40, 1), n_interior=30, n_boundary=10, seed=3,
+                                              dtype="f32"),
+    "heat_f32_wide": lambda: wl.small_problem(pde=wl.PDE_HEAT, widths=(3, 128, 96, 1), n_interior=30, n_boundary=10,
+                                              seed=4, dtype="f32"),
+}
+
+
+def _round(a, dtype):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64) if dtype == "f32" else np.asarray(a)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("n", [1, 37, 1000, 40001])
+def test_solution_error_matches_oracle(name, n):
+    prob, th = make(CASES[name]())
+    gp = Problem(prob, dtype=prob.dtype, max_ell=4)
+    rng = np.random.default_rng(n)
+    X = _round(rng.uniform(0, 1, (n, prob.d)), prob.dtype)
+    u_ref = _round(rng.standard_normal(n), prob.dtype)
+    g_ref = _round(rng.standard_normal((n, prob.d)), prob.dtype)
+    l2, h1, sums = gp.solution_error(gp.theta(th), X, u_ref, g_ref)
+    want = mlp.solution_error_sums(th, prob.widths, X, u_ref, g_ref)
+    got = sums.cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    wl2, wh1 = mlp.relative_errors(want)
+    assert abs(l2 - wl2) <= 1e-12 * wl2 and abs(h1 - wh1) <= 1e-12 * wh1
+    gp.close()
+
+
+def test_solution_error_empty_and_invalid():
+    prob, th = make(CASES["poisson2d_f64"]())
+    gp = Problem(prob, dtype=prob.dtype, max_ell=4)
+    sums = torch.full((4,), 7.0, dtype=torch.float64, device="cuda")
+    gp.solution_error(gp.theta(th), np.zeros((0, 2)), np.zeros(0), np.zeros((0, 2)), sums=sums)
+    assert np.all(sums.cpu().numpy() == 0.0)
+    # n < 0 and NULL inputs are refused on the host, before any launch
+    st = gp.lib.ngd_solution_error(gp.h, None, None, -1, None, None, C.c_void_p(sums.data_ptr()), None)
+    assert st != 0
+    st = gp.lib.ngd_solution_error(gp.h, None, None, 5, None, None, C.c_void_p(sums.data_ptr()), None)
+    assert st != 0
+    with pytest.raises(ValueError):
+        gp.solution_error(gp.theta(th), np.zeros((3, 3)), np.zeros(3), np.zeros((3, 3)))
+    gp.close()
+
+
+def test_solution_error_of_the_exact_network():
+    """Against the network's own values and gradients (from the oracle) both errors vanish."""
+    prob, th = make(CASES["poisson3d_f64_paper_widths"]())
+    gp = Problem(prob, dtype=prob.dtype, max_ell=4)
+    X = np.random.default_rng(9).uniform(0, 1, (500, 3))
+    u, g, _, _, _ = mlp.taylor_forward(th, prob.widths, X, wl.PDE_POISSON)
+    l2, h1, _ = gp.solution_error(gp.theta(th), X, u, g)
+    assert l2 < 1e-13 and h1 < 1e-13
+    gp.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adaptive_rank_follows_alg4(dtype):
+    """Every step's next sketch size is Alg. 4's rule applied to that step's own eigenvalue estimates
+    and damping (re-derived here with the oracle's rule), the size actually sketched at each step is
+    the one chosen before it, and the rank reaches both branches of the rule."""
+    prob = wl.poisson_random(d=3, widths=(3, 24, 24, 1), n_interior=400, n_boundary=80, seed=5, dtype=dtype,
+                             ell=8, sketch_dtype=dtype)
+    prob = dataclasses.replace(prob, ell_max=48, dell=8, maxit=20)
+    ngd = NGD(prob, wl.glorot_theta(prob.widths, 5), solver="nystrom", seed=5)
+    expect = prob.ell
+    grew = shrank = False
+    for _ in range(12):
+        rep = ngd.step()
+        assert rep.rank == expect
+        lam = ngd.lam_host.numpy()[:rep.rank].copy()
+        assert np.all(np.diff(lam) <= 0)
+        expect = ongd.next_rank(lam, rep.mu, rep.rank, prob.ell_max, prob.dell)
+        assert ngd.ell == expect
+        grew |= expect > rep.rank
+        shrank |= expect < rep.rank
+        assert rep.loss_new <= rep.loss
+    assert grew
+    ngd.gp.close()

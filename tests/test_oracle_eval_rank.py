@@ -1,0 +1,140 @@
+"""Pins of the oracle's adaptive sketch-size rule (Alg. 4), its accuracy measure (relative L2 / H1
+errors, Section 5) and the paper's 3D Poisson workload; plus the driver's own rank rule against the
+oracle's (host logic, CPU only)."""
+import types
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp, ngd
+
+
+# ---- Alg. 4: the next sketch size ----
+
+def test_next_rank_grows_while_smallest_estimate_exceeds_ten_mu():
+    # lam_hat_3 = 2 > 10 mu = 1: grow by dell, capped at ell_max
+    assert ngd.next_rank([10.0, 5.0, 2.0], 0.1, 3, 500, 20) == 23
+    assert ngd.next_rank([10.0, 5.0, 2.0], 0.1, 3, 10, 20) == 10
+
+
+def test_next_rank_shrinks_to_first_index_below_threshold_plus_offset():
+    # 1-based first index with lam_hat_i < 1 is 3; plus the offset 1
+    assert ngd.next_rank([10.0, 5.0, 0.5, 0.1], 0.1, 4, 500, 20) == 4
+    assert ngd.next_rank([10.0, 5.0, 0.5, 0.1, 0.0, 0.0], 0.1, 6, 500, 20) == 4
+    assert ngd.next_rank([0.5, 0.1, 0.0], 0.1, 3, 500, 20) == 2
+    assert ngd.next_rank([10.0, 5.0, 0.5, 0.1], 0.1, 4, 500, 20, offset=2) == 5
+    # the shrunk rank never exceeds ell_max
+    assert ngd.next_rank([10.0, 5.0, 2.0, 0.5], 0.1, 4, 4, 20) == 4
+
+
+def test_next_rank_boundary_of_the_threshold():
+    # lam_hat_ell equal to 10 mu does not grow the rank, and no estimate lies strictly below: keep ell
+    assert ngd.next_rank([5.0, 1.0], 0.1, 2, 500, 20) == 2
+    # just above the threshold grows it
+    assert ngd.next_rank([5.0, 1.0 + 1e-12], 0.1, 2, 500, 20) == 22
+
+
+def test_driver_rank_rule_matches_oracle():
+    torch = pytest.importorskip("torch")  # noqa: F841 - the driver module imports torch
+    from paper_2505_11638_amd.driver import NGD
+
+    rng = np.random.default_rng(0)
+    for trial in range(400):
+        ell = int(rng.integers(1, 60))
+        ell_max = int(rng.integers(ell, 120))
+        dell = int(rng.integers(1, 30))
+        off = int(rng.integers(1, 3))
+        lam = np.sort(10.0 ** rng.uniform(-8, 2, ell))[::-1]
+        if trial % 5 == 0:
+            lam[rng.integers(0, ell):] = 0.0  # dropped pairs are reported as zeros
+        mu = float(10.0 ** rng.uniform(-7, 0))
+        if trial % 7 == 0:
+            mu = float(lam[ell - 1]) / 10.0  # on the threshold
+        me = types.SimpleNamespace(dell=dell, ell_max=ell_max, rank_offset=off)
+        assert NGD.next_rank(me, lam, mu, ell) == ngd.next_rank(lam, mu, ell, ell_max, dell, off)
+
+
+# ---- accuracy measure: relative L2 and H1 errors ----
+
+def _glorot(widths, seed):
+    return wl.glorot_theta(widths, seed) + 0.1 * np.random.default_rng(seed).standard_normal(wl.num_params(widths))
+
+
+def test_solution_error_sums_linear_network_closed_form():
+    """widths (d, 1): u = w . x + b exactly, grad u = w."""
+    rng = np.random.default_rng(1)
+    d, n = 3, 50
+    w, b = rng.standard_normal(d), 0.7
+    theta = np.concatenate([w, [b]])
+    X = rng.uniform(0, 1, (n, d))
+    u_ref, g_ref = rng.standard_normal(n), rng.standard_normal((n, d))
+    s = mlp.solution_error_sums(theta, (d, 1), X, u_ref, g_ref)
+    u = X @ w + b
+    want = [np.sum((u - u_ref) ** 2), np.sum((w[None, :] - g_ref) ** 2), np.sum(u_ref ** 2), np.sum(g_ref ** 2)]
+    np.testing.assert_allclose(s, want, rtol=1e-13)
+
+
+def test_solution_error_sums_constant_network():
+    """All weights zero: u is the output bias everywhere and its gradient vanishes."""
+    widths = (2, 5, 4, 1)
+    theta = np.zeros(wl.num_params(widths))
+    theta[-1] = -1.25
+    rng = np.random.default_rng(2)
+    X = rng.uniform(0, 1, (20, 2))
+    u_ref, g_ref = rng.standard_normal(20), rng.standard_normal((20, 2))
+    s = mlp.solution_error_sums(theta, widths, X, u_ref, g_ref)
+    np.testing.assert_allclose(s, [np.sum((-1.25 - u_ref) ** 2), np.sum(g_ref ** 2), np.sum(u_ref ** 2),
+                                   np.sum(g_ref ** 2)], rtol=1e-14)
+
+
+def test_solution_error_gradient_matches_finite_differences():
+    """The gradient term uses grad_x u; compare with central differences of u (error O(h^2))."""
+    widths = (3, 12, 9, 1)
+    theta = _glorot(widths, 3)
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 1, (15, 3))
+    h = 1e-5
+    fd = np.stack([(mlp.taylor_forward(theta, widths, X + h * e, wl.PDE_POISSON)[0]
+                    - mlp.taylor_forward(theta, widths, X - h * e, wl.PDE_POISSON)[0]) / (2 * h)
+                   for e in np.eye(3)], axis=1)
+    zeros = np.zeros(15)
+    s = mlp.solution_error_sums(theta, widths, X, zeros, np.zeros((15, 3)))
+    assert abs(s[1] - np.sum(fd ** 2)) <= 1e-8 * np.sum(fd ** 2)
+    # against the exact gradient itself the gradient term vanishes up to the FD error
+    s2 = mlp.solution_error_sums(theta, widths, X, zeros, fd)
+    assert s2[1] <= 1e-16 * np.sum(fd ** 2) + 1e-18
+
+
+def test_relative_errors_and_empty_set():
+    assert mlp.relative_errors([1.0, 3.0, 4.0, 12.0]) == (0.5, 0.5)
+    np.testing.assert_array_equal(mlp.solution_error_sums(np.zeros(4), (2, 1), np.zeros((0, 2)), [], np.zeros((0, 2))),
+                                  np.zeros(4))
+
+
+# ---- the paper's 3D Poisson setup ----
+
+def test_paper3d_workload_shape():
+    p = wl.config("paper3d")
+    assert p.widths == (3, 64, 64, 64, 1) and p.n_params == 8641  # the paper's p
+    assert (p.kind == wl.KIND_INTERIOR).sum() == 10000 and (p.kind == wl.KIND_BOUNDARY).sum() == 1000
+    assert p.dtype == "f64" and p.ell_max == 500 and p.dell == 20 and p.maxit == 20 and p.ell == 20
+    X, u, g = wl.evaluation_set(p, 1000)
+    assert X.shape == (1000, 3) and np.all((X >= 0) & (X <= 1))
+
+
+@pytest.mark.parametrize("solution,d", [("sinprod", 3), ("sinsum", 5), ("heat", 3)])
+def test_exact_solution_gradients(solution, d):
+    X = np.random.default_rng(4).uniform(0, 1, (6, d))
+    u, g = wl.exact_solution(solution, X)
+    h = 1e-6
+    fd = np.stack([(wl.exact_solution(solution, X + h * e)[0] - wl.exact_solution(solution, X - h * e)[0]) / (2 * h)
+                   for e in np.eye(d)], axis=1)
+    np.testing.assert_allclose(g, fd, atol=1e-8)
+
+
+def test_exact_solution_special_points():
+    u, g = wl.exact_solution("sinprod", np.full((1, 3), 0.5))
+    assert abs(u[0] - 1.0) < 1e-15 and np.abs(g).max() < 1e-15
+    u, g = wl.exact_solution("sinsum", np.zeros((1, 5)))
+    assert u[0] == 0.0 and np.allclose(g, np.pi)

@@ -27,7 +27,7 @@ PDE_POISSON = 0     # interior res = Laplace(u) + f      (-Laplace(u) = f)
 PDE_HEAT = 1        # interior res = u_t - Laplace_x(u) - f (last input coordinate is time)
 
 # purposes for independent random streams
-_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE, _P_SHAPES = range(7)
+_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE, _P_SHAPES, _P_EVAL = range(8)
 
 
 @dataclasses.dataclass
@@ -48,6 +48,10 @@ class Problem:
     sketch_dtype: str = "f64"     # "f64" | "f32" | "bf16"
     seed: int = 0
     recompute: bool = False       # products with J_w recomputed from theta instead of a stored J_w
+    ell_max: Optional[int] = None # adaptive sketch size up to ell_max (None: ell fixed)
+    dell: int = 20                # rank increase of the adaptive rule
+    maxit: Optional[int] = None   # PCG iteration cap (None: the driver's default)
+    solution: str = ""            # manufactured solution ("sinprod", "sinsum", "heat") for evaluation
 
     @property
     def n_rows(self) -> int:
@@ -151,7 +155,7 @@ def poisson2d_grid(widths=(2, 32, 32, 1), n_side=30, seed=0, dtype="f64", ell=10
     blocks = [(Xi, KIND_INTERIOR, 1.0 / ni, 2 * np.pi ** 2 * _sinprod(Xi), np.zeros(ni)),
               (Xb, KIND_BOUNDARY, 4.0 / nb, np.zeros(nb), np.zeros(nb))]
     return _assemble("poisson2d_grid", PDE_POISSON, widths, blocks, dtype=dtype, ell=ell, lam=lam,
-                     sketch_dtype=sketch_dtype, seed=seed)
+                     sketch_dtype=sketch_dtype, seed=seed, solution="sinprod")
 
 
 def poisson_random(d=2, widths=(2, 64, 64, 64, 1), n_interior=4096, n_boundary=512, seed=0,
@@ -172,7 +176,7 @@ def poisson_random(d=2, widths=(2, 64, 64, 64, 1), n_interior=4096, n_boundary=5
     blocks = [(Xi, KIND_INTERIOR, 1.0 / n_interior, fi, np.zeros(n_interior)),
               (Xb, KIND_BOUNDARY, 2.0 * d / n_boundary, np.zeros(n_boundary), gb)]
     return _assemble(f"poisson{d}d_random", PDE_POISSON, widths, blocks, dtype=dtype, ell=ell,
-                     lam=lam, sketch_dtype=sketch_dtype, seed=seed)
+                     lam=lam, sketch_dtype=sketch_dtype, seed=seed, solution=solution)
 
 
 def heat2d(widths=(3, 64, 64, 64, 64, 1), n_interior=8192, n_lateral=1024, n_initial=1024, seed=0,
@@ -188,7 +192,38 @@ def heat2d(widths=(3, 64, 64, 64, 64, 1), n_interior=8192, n_lateral=1024, n_ini
               (Xl, KIND_BOUNDARY, 4.0 / n_lateral, np.zeros(n_lateral), np.zeros(n_lateral)),
               (X0, KIND_INITIAL, 1.0 / n_initial, np.zeros(n_initial), _sinprod(X0[:, :2]))]
     return _assemble("heat2d", PDE_HEAT, widths, blocks, dtype=dtype, ell=ell, lam=lam,
-                     sketch_dtype=sketch_dtype, seed=seed)
+                     sketch_dtype=sketch_dtype, seed=seed, solution="heat")
+
+
+def exact_solution(solution: str, X: np.ndarray) -> tuple:
+    """Value and gradient (over all inputs) of a manufactured solution at the points X (n x d)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    s, c = np.sin(np.pi * X), np.cos(np.pi * X)
+    if solution == "sinprod":
+        u = np.prod(s, axis=1)
+        grad = np.empty((n, d))
+        for j in range(d):
+            grad[:, j] = np.pi * c[:, j] * np.prod(np.delete(s, j, axis=1), axis=1)
+        return u, grad
+    if solution == "sinsum":
+        return np.sum(s, axis=1), np.pi * c
+    if solution == "heat":  # exp(-2 pi^2 t) sin(pi x) sin(pi y), inputs (x, y, t)
+        e = np.exp(-2.0 * np.pi ** 2 * X[:, 2])
+        u = e * s[:, 0] * s[:, 1]
+        grad = np.stack([np.pi * e * c[:, 0] * s[:, 1], np.pi * e * s[:, 0] * c[:, 1],
+                         -2.0 * np.pi ** 2 * u], axis=1)
+        return u, grad
+    raise ValueError(solution)
+
+
+def evaluation_set(prob: Problem, n: int = 100_000, seed: int = 0) -> tuple:
+    """n uniform random points of the problem's domain [0,1]^d (the paper's evaluation sets: 100,000
+    random points, appendix table of discretisations) with the exact solution and its gradient there:
+    (X, u, grad u)."""
+    X = _rng(seed, _P_EVAL).uniform(0.0, 1.0, size=(n, prob.d))
+    u, grad = exact_solution(prob.solution, X)
+    return X, u, grad
 
 
 # ----------------------------------------------------------------------------------------------
@@ -203,7 +238,14 @@ def config(name: str, seed: int = 0) -> Problem:
     c3: 5D Poisson (u* = sum sin), 5-128-128-128-1, 16,384 + 2,048 points, BF16 sketch, ell = 800.
     c4: 2+1D heat, 3-64-64-64-64-1, 8,192 + 1,024 lateral + 1,024 initial points, FP32, ell = 400,
         J_w recomputed (never stored).
+    paper3d: the paper's 3D Poisson setup (Section 5.1.1 and the experimental setup of Section 5):
+        3-64-64-64-1 tanh (P = 8,641), 10,000 + 1,000 random points, FP64, u* = prod sin(pi x_i),
+        adaptive sketch size from 20 in steps of 20 up to 500, at most 20 PCG iterations.
     """
+    if name == "paper3d":
+        prob = poisson_random(d=3, widths=(3, 64, 64, 64, 1), n_interior=10000, n_boundary=1000, seed=seed,
+                              dtype="f64", ell=20, sketch_dtype="f64", solution="sinprod")
+        return dataclasses.replace(prob, name="paper3d", ell_max=500, dell=20, maxit=20)
     if name == "c1":
         return poisson2d_grid(seed=seed)
     if name == "c2":
