@@ -176,6 +176,42 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
                               void* U, int64_t ldU, double* lam_hat, ngd_nystrom_info* info,
                               void* stream);
 
+/*
+ * The same Nystrom builder with a sampling test matrix (the "sampling" variant of the experiments of
+ * Section 5): Omega = [e_{cols[0]}, ..., e_{cols[ell-1]}], columns of the identity, so Z = J_w Omega
+ * is a gather of ell columns of J_w and the rest is as in ngd_nystrom_sketch. Repeated indices are
+ * allowed (range(Omega) is what matters; the extra directions come out as dropped pairs).
+ *   cols : device, ell int64 indices in [0, P) (a negative index stands for a zero column), e.g. from
+ *          ngd_sample_pivots. Other arguments and the synchronisation rule as for ngd_nystrom_sketch.
+ */
+ngd_status ngd_nystrom_sketch_columns(ngd_problem* h, const ngd_operator* op, int64_t ell, const int64_t* cols,
+                                      int32_t sketch_dtype, void* U, int64_t ldU, double* lam_hat,
+                                      ngd_nystrom_info* info, void* stream);
+
+/*
+ * diag(G) = diag(J_w^T J_w), the column sums of squares of J_w (eq. gram_diagonal, with the
+ * quadrature weights folded into J_w): one pass over a stored J_w, or over its rows recomputed a
+ * block at a time (op->J == NULL). FP64 sums in a fixed order.
+ *   diag : device, P doubles, out. Asynchronous on `stream`.
+ */
+ngd_status ngd_gramian_diagonal(ngd_problem* h, const ngd_operator* op, double* diag, void* stream);
+
+/*
+ * n_samples indices drawn i.i.d. from [0, P) with probability max(w_j, 0) / sum_k max(w_k, 0): the
+ * pivot sampling of RPCholesky (Section 4.2.2, s ~ d) and of the sampling test matrix (Section 5).
+ * Sample k of `substream` q takes the uniform u = ((x0 >> 5) 2^26 + (x1 >> 6) + 1/2) 2^-53 from the
+ * first two words of Philox4x32-10 at counter (k, 2^31 + q, counter_lo, counter_hi), key (seed_lo,
+ * seed_hi), and returns the first index whose running weight sum exceeds u * total.
+ *   weights : device, P doubles. unique : nonzero = sort the samples and drop repeats.
+ *   idx     : device, n_samples int64, out (the first *count entries are valid).
+ *   count   : device, 1 int32, out: n_samples, the number of distinct indices (unique), or 0 if
+ *             every weight is <= 0 (idx is then -1).
+ * 0 <= n_samples <= 4096, substream < 2^31. Asynchronous on `stream`.
+ */
+ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_samples, uint64_t seed,
+                             uint64_t counter, uint32_t substream, int32_t unique, int64_t* idx, int32_t* count,
+                             void* stream);
+
 /* Nystrom preconditioner of eq. nystrom_inverse for G + mu I with mu = the solve's lambda:
  * P^{-1} v = U (Lambda + mu I)^{-1} U^T v + (lam_hat[ell-1] + mu)^{-1} (v - U U^T v). */
 typedef struct {

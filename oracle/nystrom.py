@@ -38,6 +38,18 @@ def nystrom_definition(G: np.ndarray, Omega: np.ndarray) -> np.ndarray:
     return Y @ np.linalg.pinv(core, rcond=1e-13, hermitian=True) @ Y.T
 
 
+def nystrom_shifted(G: np.ndarray, Omega: np.ndarray, nu: float) -> np.ndarray:
+    """The Nystrom approximation with its core shifted and the shift kept: (G Omega)(Omega^T G Omega +
+    nu I)^{-1} (G Omega)^T. It tends to eq. nystrom_approx as nu -> 0 and lies below it in the PSD
+    order; Alg. 6 shifts the core in the same way for stability and then subtracts nu from the
+    eigenvalues."""
+    Y = G @ Omega
+    core = Omega.T @ Y
+    core = 0.5 * (core + core.T) + nu * np.eye(core.shape[0])
+    out = Y @ np.linalg.solve(core, Y.T)
+    return 0.5 * (out + out.T)
+
+
 def precond_apply(U: np.ndarray, lam_hat: np.ndarray, mu: float, V: np.ndarray) -> np.ndarray:
     """eq. nystrom_inverse: P^{-1} v = U (Lambda + mu I)^{-1} U^T v + (lam_ell + mu)^{-1} (v - U U^T v),
     with lam_ell the smallest of the ell Nystrom eigenvalues."""

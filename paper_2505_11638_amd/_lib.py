@@ -67,6 +67,11 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.c_void_p]),
     "ngd_line_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                   C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_nystrom_sketch_columns": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_int64, C.c_void_p, C.c_int32,
+                                             C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(NystromInfo), C.c_void_p]),
+    "ngd_gramian_diagonal": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_void_p]),
+    "ngd_sample_pivots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
     "ngd_solution_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
     "ngd_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_void_p)]),

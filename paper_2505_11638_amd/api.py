@@ -193,8 +193,11 @@ class Problem:
 
     def nystrom_sketch(self, J: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
                        omega: Optional[torch.Tensor] = None, sketch_dtype: Optional[str] = None,
-                       want_info=True, out: Optional[NystromResult] = None) -> NystromResult:
-        """ngd_nystrom_sketch; `out`, if given, is a previous result of the same ell to write into."""
+                       want_info=True, out: Optional[NystromResult] = None,
+                       cols: Optional[torch.Tensor] = None) -> NystromResult:
+        """ngd_nystrom_sketch (Gaussian test matrix), or ngd_nystrom_sketch_columns when `cols` (device
+        int64 indices) gives a sampling test matrix; `out`, if given, is a previous result of the same
+        ell to write into."""
         sd = _DTYPE[sketch_dtype or ("f64" if self.dtype == L.NGD_F64 else "f32")]
         if out is not None and out.lam_hat.numel() == ell:
             U, lam = out.U, out.lam_hat
@@ -206,9 +209,16 @@ class Problem:
         if omega is not None:
             _need(omega, self.tdtype, "omega")
             ldO = omega.stride(0)
-        L.check(self.lib.ngd_nystrom_sketch(self.h, C.byref(self._op(J)), ell, seed, counter, _ptr(omega), ldO, sd,
-                                            _ptr(U), U.stride(0), _ptr(lam), C.byref(info) if want_info else None,
-                                            _stream()), "ngd_nystrom_sketch")
+        if cols is not None:
+            if not (cols.is_cuda and cols.dtype == torch.int64 and cols.numel() >= ell and cols.is_contiguous()):
+                raise ValueError("cols must be a contiguous device int64 tensor of at least ell indices")
+            L.check(self.lib.ngd_nystrom_sketch_columns(self.h, C.byref(self._op(J)), ell, _ptr(cols), sd, _ptr(U),
+                                                        U.stride(0), _ptr(lam), C.byref(info) if want_info else None,
+                                                        _stream()), "ngd_nystrom_sketch_columns")
+        else:
+            L.check(self.lib.ngd_nystrom_sketch(self.h, C.byref(self._op(J)), ell, seed, counter, _ptr(omega), ldO,
+                                                sd, _ptr(U), U.stride(0), _ptr(lam),
+                                                C.byref(info) if want_info else None, _stream()), "ngd_nystrom_sketch")
         d = {k: getattr(info, k) for k, _ in L.NystromInfo._fields_} if want_info else {}
         return NystromResult(U, lam, d)
 
@@ -283,6 +293,24 @@ class Problem:
                                          int(max_halvings), _ptr(theta_out), C.byref(a), C.byref(ln), _stream()),
                 "ngd_line_search")
         return theta_out, a.value, ln.value
+
+    def gramian_diagonal(self, J, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """diag(J_w^T J_w) (eq. gram_diagonal), P doubles on the device."""
+        out = torch.empty(self.P, dtype=torch.float64, device=self.device) if out is None else out
+        L.check(self.lib.ngd_gramian_diagonal(self.h, C.byref(self._op(J)), _ptr(out), _stream()),
+                "ngd_gramian_diagonal")
+        return out
+
+    def sample_pivots(self, weights: torch.Tensor, n: int, seed: int = 0, counter: int = 0, substream: int = 0,
+                      unique: bool = False, out: Optional[torch.Tensor] = None):
+        """n indices drawn with probability proportional to max(weights, 0) (ngd_sample_pivots):
+        (idx device int64 tensor, count device int32 tensor)."""
+        _need(weights, torch.float64, "weights")
+        idx = torch.empty(max(int(n), 1), dtype=torch.int64, device=self.device) if out is None else out
+        cnt = torch.empty(1, dtype=torch.int32, device=self.device)
+        L.check(self.lib.ngd_sample_pivots(self.h, _ptr(weights), int(n), int(seed), int(counter), int(substream),
+                                           1 if unique else 0, _ptr(idx), _ptr(cnt), _stream()), "ngd_sample_pivots")
+        return idx, cnt
 
     def solution_error(self, theta: torch.Tensor, X, u_ref, grad_u_ref, sums: Optional[torch.Tensor] = None):
         """Relative L2 and H1 errors of u_theta against (u_ref, grad u_ref) on the points X (n x d), the

@@ -34,6 +34,7 @@ struct ngd_problem {
   double* tsq;       // nwg
   double* loss_part; // res_blocks * kTrials
   double* err_part;  // 4 * kEvalBlocks partial sums of the solution error
+  double* diag_work; // kDiagChunks * ldP partial column sums of squares (Gramian diagonal)
   double* grad_work; // gradient_chunks(N) x P
   double* vtmp[4];   // P-vectors (FP64)
   double* scal;      // small scalars / dot workspace (128 doubles)
@@ -296,6 +297,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->tsq, sizeof(double) * 1024});
   plan.push_back({(void**)&h->loss_part, sizeof(double) * (size_t)h->res_blocks * kTrials});
   plan.push_back({(void**)&h->err_part, sizeof(double) * 4 * (size_t)kEvalBlocks});
+  plan.push_back({(void**)&h->diag_work, sizeof(double) * (size_t)kDiagChunks * ldP});
   plan.push_back({(void**)&h->grad_work, sizeof(double) * (size_t)gradient_chunks(N) * P});
   for (int i = 0; i < 4; ++i) plan.push_back({(void**)&h->vtmp[i], sizeof(double) * ldP});
   plan.push_back({(void**)&h->scal, sizeof(double) * 256});
@@ -522,9 +524,55 @@ ngd_status jc_rows_at(ngd_problem* h, const void* theta, int64_t r0, int64_t row
 
 }  // namespace
 
+// The sketch with a Gaussian test matrix (omega, or generated from seed/counter), or, when `cols` is
+// given, with Omega = the identity's columns at those indices, so that Z = J_w Omega is a gather of
+// J_w's columns.
+ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
+                       const void* omega, int64_t ldO, const int64_t* cols, int32_t sketch_dtype, void* U, int64_t ldU,
+                       double* lam_hat, ngd_nystrom_info* info, void* stream);
+
 ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
                               const void* omega, int64_t ldO, int32_t sketch_dtype, void* U, int64_t ldU,
                               double* lam_hat, ngd_nystrom_info* info, void* stream) {
+  return sketch_impl(h, op, ell, seed, counter, omega, ldO, nullptr, sketch_dtype, U, ldU, lam_hat, info, stream);
+}
+
+ngd_status ngd_nystrom_sketch_columns(ngd_problem* h, const ngd_operator* op, int64_t ell, const int64_t* cols,
+                                      int32_t sketch_dtype, void* U, int64_t ldU, double* lam_hat,
+                                      ngd_nystrom_info* info, void* stream) {
+  NGD_CHECK(cols != nullptr, "NULL argument");
+  return sketch_impl(h, op, ell, 0, 0, nullptr, 0, cols, sketch_dtype, U, ldU, lam_hat, info, stream);
+}
+
+ngd_status ngd_gramian_diagonal(ngd_problem* h, const ngd_operator* op, double* diag, void* stream) {
+  NGD_CHECK(h != nullptr && diag != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  hipStream_t s = S(stream);
+  const int64_t dw = kDiagChunks * h->ldP;
+  if (op->J != nullptr) return launch_colsq(h->dtype, op->J, op->ldJ, h->N, h->P, h->diag_work, dw, 0, diag, s);
+  // recompute mode: the rows of J_w a block at a time, each block's squares added in
+  NGD_TRY(jc_ensure(h));
+  if (h->N == 0) return launch_colsq(h->dtype, nullptr, h->ldP, 0, h->P, h->diag_work, dw, 0, diag, s);
+  for (int64_t r0 = 0; r0 < h->N; r0 += h->jc_rows) {
+    const int64_t rows = std::min<int64_t>(h->jc_rows, h->N - r0);
+    NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+    NGD_TRY(launch_colsq(h->dtype, h->Jc, h->ldP, rows, h->P, h->diag_work, dw, r0 > 0 ? 1 : 0, diag, s));
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_samples, uint64_t seed, uint64_t counter,
+                             uint32_t substream, int32_t unique, int64_t* idx, int32_t* count, void* stream) {
+  NGD_CHECK(h != nullptr && weights != nullptr && idx != nullptr && count != nullptr, "NULL argument");
+  NGD_CHECK(n_samples >= 0 && n_samples <= kMaxSamples, "n_samples must be in [0, 4096]");
+  NGD_CHECK(substream < 0x80000000u, "substream must be below 2^31");
+  return launch_sample_pivots(weights, h->P, seed, counter, substream, n_samples, unique ? 1 : 0, idx, count,
+                              S(stream));
+}
+
+ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
+                       const void* omega, int64_t ldO, const int64_t* cols, int32_t sketch_dtype, void* U, int64_t ldU,
+                       double* lam_hat, ngd_nystrom_info* info, void* stream) {
   NGD_CHECK(h != nullptr && U != nullptr && lam_hat != nullptr, "NULL argument");
   NGD_TRY(check_op(h, op));
   NGD_CHECK(ell >= 1 && ell <= h->max_ell, "ell must be in [1, min(max_ell, P)]");
@@ -541,11 +589,12 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   hipStream_t s = S(stream);
   const int64_t N = h->N, P = h->P, L = ell;
   const int T = h->dtype;
-  if (omega == nullptr) {
+  if (omega == nullptr && cols == nullptr) {
     NGD_TRY(launch_gaussian_omega(T, seed, counter, P, L, h->omega, h->ldP, s));
     omega = h->omega;
     ldO = h->ldP;
   }
+  if (cols != nullptr) ldO = h->ldP;  // (no Omega is read; keeps the NT-path checks below well defined)
   // recompute mode: J_w is never stored whole. Each product is formed a block of rows at a time: the
   // residual/Jacobian kernel recomputes the block into a scratch buffer and the block's share of
   // Z = J_w Omega (its rows) or of B^T = Q^T J_w (a rank-`rows` update) follows with the same GEMM
@@ -570,6 +619,16 @@ ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t el
   }
   // Z = J Omega (N x ell)
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_Z, s, [&] {
+    if (cols != nullptr) {  // Omega = columns of the identity: Z is a gather of J's columns
+      if (!rec) return launch_gather_cols(T, op->J, op->ldJ, N, cols, L, h->Z, L, s);
+      for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
+        const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);
+        NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+        void* Zr = static_cast<char*>(h->Z) + (size_t)r0 * L * h->elem;
+        NGD_TRY(launch_gather_cols(T, h->Jc, h->ldP, rows, cols, L, Zr, L, s));
+      }
+      return NGD_OK;
+    }
     if (rec) {
       for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
         const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);

@@ -33,6 +33,33 @@ struct NetDesc {
   int64_t P;
 };
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplications,
+// word recombination with the key, and a Weyl increment of the key between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  const uint64_t v = ((uint64_t)(a >> 5) << 26) + (uint64_t)(b >> 6);
+  return ((double)v + 0.5) * 1.1102230246251565e-16;  // 2^-53
+}
+
 // Device-side solver state of one PCG solve (FP64 scalars).
 struct PcgState {
   double rz;        // r^T z of the current iterate
@@ -256,6 +283,18 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
 ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
                               double* out, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// pivots.hip: out (+)= column sums of squares of J (N x P, ldJ) through `work` (work_elems doubles);
+// ns samples of indices in [0, P) with probability proportional to max(w, 0) (Philox substream q;
+// sorted and without duplicates when `unique`; count on the device); gather of columns.
+constexpr int kDiagChunks = 64;
+constexpr int64_t kMaxSamples = 4096;
+ngd_status launch_colsq(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, double* work,
+                        int64_t work_elems, int accumulate, double* out, hipStream_t s);
+ngd_status launch_sample_pivots(const double* w, int64_t P, uint64_t seed, uint64_t counter, uint32_t q, int64_t ns,
+                                int unique, int64_t* idx, int* count, hipStream_t s);
+ngd_status launch_gather_cols(int dtype, const void* J, int64_t ldJ, int64_t rows, const int64_t* cols, int64_t ncol,
+                              void* out, int64_t ld_out, hipStream_t s);
 
 // eval.hip: the four sums of the relative L2 / H1 error of u_theta against (u_ref, grad u_ref) at n
 // points: sum (u - u_ref)^2, sum |grad u - grad u_ref|^2, sum u_ref^2, sum |grad u_ref|^2 (FP64,

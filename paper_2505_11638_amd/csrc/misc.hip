@@ -5,33 +5,6 @@
 namespace ngd {
 namespace {
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplications,
-// word recombination with the key, and a Weyl increment of the key between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += W0;
-      k1 += W1;
-    }
-    const uint64_t p0 = (uint64_t)M0 * c[0];
-    const uint64_t p1 = (uint64_t)M1 * c[2];
-    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-  }
-}
-
-__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
-  const uint64_t v = ((uint64_t)(a >> 5) << 26) + (uint64_t)(b >> 6);
-  return ((double)v + 0.5) * 1.1102230246251565e-16;  // 2^-53
-}
-
 // Omega^T row j (column j of the p x ell test matrix), entries 2m and 2m+1 from counter (m, j, c)
 template <typename T>
 __global__ void omega_kernel(uint64_t seed, uint64_t counter, int64_t P, int64_t ell, T* __restrict__ out,

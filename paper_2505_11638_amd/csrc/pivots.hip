@@ -1,0 +1,184 @@
+// Diagonal of the Gramian, pivot sampling proportional to a weight vector, and column gathers: the
+// pieces of the sampling test matrix of the Nystrom approximation (Omega = columns of the identity at
+// indices drawn with probability proportional to diag(G); Section 5, the "sampling" variant) and of
+// RPCholesky (Section 4.2.2, its block algorithm in the appendix).
+#include "common.h"
+
+namespace ngd {
+namespace {
+
+// ---- diag(G) = column sums of squares of J_w (eq. gram_diagonal with the weights folded into J_w) ----
+// stage 1: work[c * P + j] = sum over rows of chunk c of J[i, j]^2 (threads along j: coalesced rows)
+template <typename T>
+__global__ __launch_bounds__(256) void colsq_stage1_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N,
+                                                           int64_t P, int64_t rows_per, double* __restrict__ work) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = (r0 + rows_per) < N ? (r0 + rows_per) : N;
+  double acc = 0.0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const double v = (double)J[i * ldJ + j];
+    acc = fma(v, v, acc);
+  }
+  work[(int64_t)blockIdx.y * P + j] = acc;
+}
+
+// stage 2: out[j] (+)= sum over chunks in chunk order
+__global__ void colsq_stage2_kernel(const double* __restrict__ work, int nchunk, int64_t P, int accumulate,
+                                    double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  double acc = accumulate ? out[j] : 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += work[(int64_t)c * P + j];
+  out[j] = acc;
+}
+
+// ---- sampling proportional to weights ----
+// Sample k of substream q draws u = u53 of the first two words of Philox4x32-10 at the counter
+// (k, 2^31 + q, counter_lo, counter_hi) with the key (seed_lo, seed_hi): a counter range that the
+// Gaussian test matrix (second word < 2^31) never reaches.
+__device__ double sample_uniform(uint64_t k, uint32_t q, uint64_t seed, uint64_t counter) {
+  uint32_t c[4] = {(uint32_t)k, 0x80000000u | q, (uint32_t)counter, (uint32_t)(counter >> 32)};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return u53(c[0], c[1]);
+}
+
+constexpr int kSampThreads = 1024;
+
+// One workgroup. Chunk sums of max(w, 0) (thread t: entries t*chunk .. in order), their running sum
+// (one thread, in order), then per sample k the inverse CDF at u_k * total: the first chunk whose
+// running sum exceeds the target, then the first index inside it whose running sum exceeds it.
+// unique: the picks are sorted and duplicates removed. count = number of indices written (0 when all
+// weights vanish).
+__global__ __launch_bounds__(kSampThreads) void sample_pivots_kernel(const double* __restrict__ w, int64_t P,
+                                                                     uint64_t seed, uint64_t counter, uint32_t q,
+                                                                     int64_t ns, int unique, int64_t* __restrict__ idx,
+                                                                     int* __restrict__ count) {
+  __shared__ double csum[kSampThreads];
+  const int t = threadIdx.x;
+  const int64_t chunk = (P + kSampThreads - 1) / kSampThreads;
+  {
+    const int64_t j0 = (int64_t)t * chunk, j1 = (j0 + chunk) < P ? (j0 + chunk) : P;
+    double s = 0.0;
+    for (int64_t j = j0; j < j1; ++j) s += fmax(w[j], 0.0);
+    csum[t] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0;
+    for (int i = 0; i < kSampThreads; ++i) {
+      a += csum[i];
+      csum[i] = a;
+    }
+  }
+  __syncthreads();
+  const double total = csum[kSampThreads - 1];
+  for (int64_t k = t; k < ns; k += kSampThreads) {
+    int64_t pick = -1;
+    if (total > 0.0) {
+      const double target = sample_uniform((uint64_t)k, q, seed, counter) * total;
+      int lo = 0, hi = kSampThreads - 1;  // first chunk with csum > target (csum[last] = total > target)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (csum[mid] > target) hi = mid;
+        else lo = mid + 1;
+      }
+      const int64_t j0 = (int64_t)lo * chunk, j1 = (j0 + chunk) < P ? (j0 + chunk) : P;
+      double a = lo > 0 ? csum[lo - 1] : 0.0;
+      int64_t last_pos = -1;
+      for (int64_t j = j0; j < j1; ++j) {
+        const double wj = fmax(w[j], 0.0);
+        if (wj > 0.0) last_pos = j;
+        a += wj;
+        if (a > target && wj > 0.0) {
+          pick = j;
+          break;
+        }
+      }
+      if (pick < 0) pick = last_pos;  // the in-chunk running sum rounded below the target
+    }
+    idx[k] = pick;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (total <= 0.0) {
+      *count = 0;
+      return;
+    }
+    int64_t n = ns;
+    if (unique) {
+      for (int64_t i = 1; i < ns; ++i) {  // insertion sort (ns is a block size)
+        const int64_t v = idx[i];
+        int64_t j = i - 1;
+        while (j >= 0 && idx[j] > v) {
+          idx[j + 1] = idx[j];
+          --j;
+        }
+        idx[j + 1] = v;
+      }
+      n = ns > 0 ? 1 : 0;
+      for (int64_t i = 1; i < ns; ++i)
+        if (idx[i] != idx[n - 1]) idx[n++] = idx[i];
+    }
+    *count = (int)n;
+  }
+}
+
+// out[i * ld_out + c] = J[i * ldJ + cols[c]] for rows i < rows, c < ncol (zero for a negative index)
+template <typename T>
+__global__ void gather_cols_kernel(const T* __restrict__ J, int64_t ldJ, int64_t rows, const int64_t* __restrict__ cols,
+                                   int64_t ncol, T* __restrict__ out, int64_t ld_out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int64_t col = cols[c];
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) out[i * ld_out + c] = col >= 0 ? J[i * ldJ + col] : T(0);
+}
+
+}  // namespace
+
+ngd_status launch_colsq(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, double* work,
+                        int64_t work_elems, int accumulate, double* out, hipStream_t s) {
+  if (P <= 0) return NGD_OK;
+  const int64_t col_blocks = (P + 255) / 256;
+  int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(work_elems / P, (2048 + col_blocks - 1) / col_blocks));
+  nchunk = (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, N));
+  const int64_t rows_per = (N + nchunk - 1) / std::max(nchunk, 1);
+  if (N > 0) {
+    if (dtype == NGD_F64)
+      hipLaunchKernelGGL(colsq_stage1_kernel<double>, dim3((unsigned)col_blocks, (unsigned)nchunk), dim3(256), 0, s,
+                         (const double*)J, ldJ, N, P, rows_per, work);
+    else
+      hipLaunchKernelGGL(colsq_stage1_kernel<float>, dim3((unsigned)col_blocks, (unsigned)nchunk), dim3(256), 0, s,
+                         (const float*)J, ldJ, N, P, rows_per, work);
+    NGD_HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(colsq_stage2_kernel, dim3((unsigned)col_blocks), dim3(256), 0, s, work, N > 0 ? nchunk : 0, P,
+                     accumulate, out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_sample_pivots(const double* w, int64_t P, uint64_t seed, uint64_t counter, uint32_t q, int64_t ns,
+                                int unique, int64_t* idx, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(sample_pivots_kernel, dim3(1), dim3(kSampThreads), 0, s, w, P, seed, counter, q, ns, unique,
+                     idx, count);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_gather_cols(int dtype, const void* J, int64_t ldJ, int64_t rows, const int64_t* cols, int64_t ncol,
+                              void* out, int64_t ld_out, hipStream_t s) {
+  if (rows <= 0 || ncol <= 0) return NGD_OK;
+  const dim3 grid((unsigned)((ncol + 127) / 128), (unsigned)std::min<int64_t>(rows, 4096));
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(gather_cols_kernel<double>, grid, dim3(128), 0, s, (const double*)J, ldJ, rows, cols, ncol,
+                       (double*)out, ld_out);
+  else
+    hipLaunchKernelGGL(gather_cols_kernel<float>, grid, dim3(128), 0, s, (const float*)J, ldJ, rows, cols, ncol,
+                       (float*)out, ld_out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+}  // namespace ngd

@@ -42,7 +42,7 @@ class StepReport:
 class NGD:
     def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
                  maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None,
-                 ell_max=None, dell=None, rank_offset=1):
+                 ell_max=None, dell=None, rank_offset=1, test_matrix="gaussian"):
         # adaptive sketch size when a maximum is given (here or by the problem)
         self.ell_max = ell_max if ell_max is not None else getattr(data, "ell_max", None)
         self.dell = int(dell if dell is not None else getattr(data, "dell", 20))
@@ -50,6 +50,11 @@ class NGD:
         self.gp = Problem(data, dtype=dtype, max_ell=self.ell_max or ell or getattr(data, "ell", 1))
         gp = self.gp
         self.solver = solver
+        if test_matrix not in ("gaussian", "sampling"):
+            raise ValueError("test_matrix must be 'gaussian' or 'sampling'")
+        # sampling: Omega = identity columns drawn with probability proportional to diag(G) (Section 5)
+        self.test_matrix = test_matrix
+        self.diag = None
         if self.ell_max is not None:
             self.ell_max = min(int(self.ell_max), gp.P)
         self.ell = min(int(ell or data.ell), gp.P, self.ell_max or gp.P)
@@ -97,8 +102,12 @@ class NGD:
             # sketch, damping (Section 4.3) and solve with no host round trip in between: the sketch
             # returns no summary and the solve takes mu on the device
             ell = self.ell
+            cols = None
+            if self.test_matrix == "sampling":
+                self.diag = gp.gramian_diagonal(J, out=self.diag)
+                cols, _ = gp.sample_pivots(self.diag, ell, seed=self.seed, counter=self.k)
             pc = gp.nystrom_sketch(J, ell, seed=self.seed, counter=self.k, sketch_dtype=self.sketch_dtype,
-                                   want_info=False, out=self.pc)
+                                   want_info=False, out=self.pc, cols=cols)
             self.pc = pc
             self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
             if self.lam_host is not None:

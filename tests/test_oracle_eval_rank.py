@@ -138,3 +138,73 @@ def test_exact_solution_special_points():
     assert abs(u[0] - 1.0) < 1e-15 and np.abs(g).max() < 1e-15
     u, g = wl.exact_solution("sinsum", np.zeros((1, 5)))
     assert u[0] == 0.0 and np.allclose(g, np.pi)
+
+
+# ---- Gramian diagonal, pivot sampling, sampling test matrix ----
+
+def test_gram_diagonal_is_diag_of_product():
+    from oracle import sampling
+    J = np.random.default_rng(5).standard_normal((30, 12))
+    np.testing.assert_allclose(sampling.gram_diagonal(J), np.diag(J.T @ J), rtol=1e-14)
+
+
+def test_sample_pivots_frequencies_follow_weights():
+    """s ~ d: empirical frequencies within 5 standard deviations of d_j / sum d; zero and negative
+    weights are never drawn."""
+    from oracle import sampling
+    w = np.array([0.0, 1.0, 0.0, 3.0, -1.0, 0.0, 6.0, 0.5])
+    n = 200_000
+    s = sampling.sample_pivots(w, n, seed=3, counter=1)
+    p = np.maximum(w, 0) / np.maximum(w, 0).sum()
+    freq = np.bincount(s, minlength=w.size) / n
+    assert np.all(freq[p == 0] == 0)
+    assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / n) + 1e-12)
+
+
+def test_sample_pivots_special_cases():
+    from oracle import sampling
+    w = np.zeros(9)
+    assert sampling.sample_pivots(w, 5, 1, 0).size == 0
+    w[4] = 2.5
+    assert np.all(sampling.sample_pivots(w, 50, 1, 0) == 4)
+    u = sampling.sample_uniforms(1000, 7, 2, 3)
+    assert np.all((u > 0) & (u < 1))
+    # substreams and counters give different draws
+    assert not np.array_equal(u, sampling.sample_uniforms(1000, 7, 2, 4))
+    assert not np.array_equal(u, sampling.sample_uniforms(1000, 7, 3, 3))
+    s = sampling.sample_pivots(np.arange(1.0, 31.0), 40, 1, 0, unique=True)
+    assert np.all(np.diff(s) > 0)
+
+
+def test_column_test_matrix_nystrom_is_column_form():
+    """With Omega = I[:, S] the Nystrom approximation is G[:, S] G[S, S]^+ G[S, :]; it is exact once the
+    sampled columns span range(G)."""
+    from oracle import nystrom, sampling
+    rng = np.random.default_rng(6)
+    B = rng.standard_normal((5, 14))
+    G = B.T @ B  # rank 5
+    S = np.array([0, 3, 7, 9])
+    Om = sampling.column_test_matrix(14, S)
+    Gn = nystrom.nystrom_definition(G, Om)
+    np.testing.assert_allclose(Gn, G[:, S] @ np.linalg.pinv(G[np.ix_(S, S)]) @ G[S, :], atol=1e-10)
+    S6 = np.array([0, 2, 3, 7, 9, 11])
+    np.testing.assert_allclose(nystrom.nystrom_definition(G, sampling.column_test_matrix(14, S6)), G, atol=1e-9)
+    # Alg. 6 with the column test matrix agrees with the definition
+    U, lam, _ = nystrom.nystrom_alg6(lambda V: G @ V, Om)
+    np.testing.assert_allclose(U @ np.diag(lam) @ U.T, Gn, atol=1e-9 * np.abs(G).max())
+
+
+def test_shifted_nystrom_limits_and_order():
+    """nu -> 0 recovers eq. nystrom_approx (well-conditioned core); a positive shift lowers the
+    approximation in the PSD order, by at most nu-scaled terms."""
+    from oracle import nystrom
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((9, 20))
+    G = B.T @ B
+    Om = rng.standard_normal((20, 6))
+    G0 = nystrom.nystrom_definition(G, Om)
+    np.testing.assert_allclose(nystrom.nystrom_shifted(G, Om, 0.0), G0, atol=1e-10)
+    Gs = nystrom.nystrom_shifted(G, Om, 1e-3)
+    ev = np.linalg.eigvalsh(G0 - Gs)
+    assert ev.min() >= -1e-10 and ev.max() > 0
+    assert np.linalg.norm(G0 - nystrom.nystrom_shifted(G, Om, 1e-9)) <= 1e-6 * np.linalg.norm(G0)
