@@ -46,8 +46,8 @@ WORKLOADS["paper3d"] = ("the paper's 3D Poisson PINN: 3-64-64-64-1 tanh (P=8,641
                          "1e-4 L^2), Armijo; relative H1 error on 100,000 random points")
 # The paper's Nystrom NGD on this problem: 66.8 s to its plateau error over at most 1,000 iterations on
 # one RTX 4090 in FP64, so at most 15.0 NGD steps/s (a derived upper bound on its rate).
-PAPER3D_BASELINE_SPS = {"gaussian": 1000.0 / 66.8, "sampling": 1000.0 / 81.2}
-PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2}
+PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1}
+PAPER3D_BASELINE_SPS = {k: 1000.0 / v for k, v in PAPER3D_BASELINE_S.items()}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
@@ -62,7 +62,11 @@ def bench_paper(a):
     prob = wl.config("paper3d", seed=a.seed)
     theta0 = wl.glorot_theta(prob.widths, a.seed)
     P, N = prob.n_params, prob.n_rows
-    ngd = NGD(prob, theta0, solver="nystrom", rtol=1e-6, seed=a.seed, test_matrix=a.test_matrix)
+    variant = "rpchol" if a.solver == "rpchol" else a.test_matrix
+    if a.solver == "rpchol":  # RPCholNGD (Alg. 5): block size 20, rank up to 500
+        ngd = NGD(prob, theta0, solver="rpchol", rtol=1e-6, seed=a.seed, ell_max=prob.ell_max)
+    else:
+        ngd = NGD(prob, theta0, solver="nystrom", rtol=1e-6, seed=a.seed, test_matrix=a.test_matrix)
     gp = ngd.gp
     Xe, ue, ge = wl.evaluation_set(prob, 100_000, seed=a.seed)
     _, h1_start, sums = gp.solution_error(ngd.theta, Xe, ue, ge)
@@ -86,16 +90,16 @@ def bench_paper(a):
         "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
         "value": sps, "unit": "NGD steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": sps / PAPER3D_BASELINE_SPS[a.test_matrix],
-        "baseline": {"value": PAPER3D_BASELINE_SPS[a.test_matrix], "unit": "NGD steps/s",
-                     "kind": f"the paper's Nystrom NGD ({a.test_matrix} test matrix) on this problem, RTX 4090, "
-                             f"FP64: {PAPER3D_BASELINE_S[a.test_matrix]} s to its plateau over at most 1,000 "
-                             "iterations (an upper bound on its rate)"},
+        "vs_baseline": sps / PAPER3D_BASELINE_SPS[variant],
+        "baseline": {"value": PAPER3D_BASELINE_SPS[variant], "unit": "NGD steps/s",
+                     "kind": f"the paper's {'RPCholNGD' if variant == 'rpchol' else 'Nystrom NGD (' + variant + ' test matrix)'}"
+                             f" on this problem, RTX 4090, FP64: {PAPER3D_BASELINE_S[variant]} s to its plateau over "
+                             "at most 1,000 iterations (an upper bound on its rate)"},
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"paper3d: {WORKLOADS['paper3d']}; {a.warmup} + {a.steps} NGD steps from a "
                                f"Glorot start (the last {a.steps} timed)", "P": P, "N": N,
                    "ell0": prob.ell, "ell_max": prob.ell_max, "dell": prob.dell, "maxit": prob.maxit,
-                   "test_matrix": a.test_matrix},
+                   "preconditioner": variant},
         "ell_first_last_max": [ranks[0], ranks[-1], max(ranks)],
         "ell_trajectory": ranks,
         "mean_pcg_iters": float(np.mean([r.iters for r in reps])),
@@ -229,6 +233,8 @@ def main(argv=None):
     ap.add_argument("--no-cg", action="store_true", help="skip the plain-CG comparison loop")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="further Nystrom steps, after the timed ones, with every phase timer on")
+    ap.add_argument("--solver", default="nystrom", choices=["nystrom", "rpchol"],
+                    help="paper3d: Nystrom NGD or RPCholNGD")
     ap.add_argument("--test-matrix", default="gaussian", choices=["gaussian", "sampling"],
                     help="paper3d: Gaussian test matrix or identity columns sampled proportionally to diag(G)")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -212,6 +212,38 @@ ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_sa
                              uint64_t counter, uint32_t substream, int32_t unique, int64_t* idx, int32_t* count,
                              void* stream);
 
+/*
+ * Block RPCholesky of G = J_w^T J_w (Section 4.2.2; the block algorithm of the appendix): G ~ F F^T
+ * with F (P x r) built a block of pivots at a time. Round i (i < ceil(ell_max / block)) draws `block`
+ * pivots ~ d (ngd_sample_pivots with substream i, sorted, repeats dropped), forms the residual
+ * columns C = G[:, S'] - F F[S', :]^T from J_w, factors C[S', S'] = R^T R, appends C R^{-1} to F and
+ * downdates d by its squared rows; it stops once the trace of the residual, sum(d), is below eps
+ * (or F is full). A pivot whose residual diagonal is not safely positive (<= 1e-13 of the block's
+ * largest: a direction F already holds) is dropped with its column.
+ *   diag  : device, P doubles: d^(0) = diag(G) (ngd_gramian_diagonal); not modified.
+ *   Ft    : device, ell_max x ldF doubles, out: row k = column k of F (rows >= rank are zero).
+ *   rank  : host, out: r. trace : host, nullable, out: sum(d) at the end.
+ * 1 <= block <= 64, 1 <= ell_max <= min(1024, P), ldF >= P, eps >= 0. Needs the stored J_w
+ * (op->J != NULL). Synchronises `stream`.
+ */
+ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* diag, int64_t ell_max,
+                          int32_t block, uint64_t seed, uint64_t counter, double eps, double* Ft, int64_t ldF,
+                          int64_t* rank, double* trace, void* stream);
+
+/*
+ * The RPCholesky preconditioner P = F F^T + mu I (Section 4.2.2) in the form ngd_pcg_solve takes:
+ * with the thin SVD F = U Sigma V^T (from the FP64 eigenpairs of F^T F),
+ * P^{-1} = U (Sigma^2 + mu I)^{-1} U^T + mu^{-1} (I - U U^T) (eq. rpchol_svdprecond, the same P^{-1}
+ * as the Woodbury form eq. rpchol_precond), which is mu^{-1} times eq. nystrom_inverse evaluated with
+ * the eigenpairs of F F^T and a trailing zero pair. So U gets rank + 1 rows (the last one zero) and
+ * lam_hat rank + 1 values (the last one 0); pass ell = rank + 1 to ngd_pcg_solve.
+ *   Ft : device, rank x ldF doubles (from ngd_rpcholesky). U : device, (rank + 1) x ldU, dtype, out.
+ *   lam_hat : device, rank + 1 doubles, out, descending.
+ * rank + 1 <= max_ell. Synchronises `stream` (checks the eigensolver's exchanges).
+ */
+ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int64_t rank, void* U, int64_t ldU,
+                              double* lam_hat, void* stream);
+
 /* Nystrom preconditioner of eq. nystrom_inverse for G + mu I with mu = the solve's lambda:
  * P^{-1} v = U (Lambda + mu I)^{-1} U^T v + (lam_hat[ell-1] + mu)^{-1} (v - U U^T v). */
 typedef struct {

@@ -54,3 +54,60 @@ def column_test_matrix(p: int, cols) -> np.ndarray:
     Om = np.zeros((p, cols.size))
     Om[cols, np.arange(cols.size)] = 1.0
     return Om
+
+
+def block_rpcholesky(G_cols, d0, ell_max: int, block: int, seed: int, counter: int, eps: float):
+    """Block RPCholesky (Section 4.2.2, the block algorithm of the appendix) on a PSD matrix given by
+    column access G_cols(S) -> G[:, S] and its diagonal d0. Round i draws `block` pivots ~ d (substream
+    i, sorted, repeats dropped), forms C = G[:, S'] - F F[S', :]^T, factors C[S', S'] = R^T R and
+    appends C R^{-1} to F, downdates d by the squared rows and stops once sum(d) < eps or F is full.
+    Reading: a pivot whose residual diagonal in the block's elimination is not above 1e-13 of the
+    block's largest is dropped with its column (a direction F already holds).
+    Returns (F (p x r), pivots kept, trace sum(d))."""
+    d = np.array(d0, dtype=np.float64)
+    p = d.size
+    F = np.zeros((p, ell_max))
+    r = 0
+    kept_all = []
+    rounds = -(-ell_max // block)
+    done = False
+    for i in range(rounds):
+        if done:
+            break
+        S = sample_pivots(d, block, seed, counter, substream=i, unique=True)
+        if S.size == 0:
+            break
+        C = G_cols(S) - F[:, :r] @ F[S, :r].T
+        A = C[S, :].T.copy()  # the pivot block (symmetric up to rounding); lower part used
+        dmax = max(float(np.max(np.diag(A))), 0.0)
+        keep = []
+        for j in range(S.size):  # right-looking elimination deciding which pivots stay
+            pj = A[j, j]
+            if not (pj > 1e-13 * dmax) or r + len(keep) >= ell_max:
+                continue
+            rj = np.sqrt(pj)
+            A[j, j] = rj
+            A[j + 1:, j] /= rj
+            for m in range(j + 1, S.size):
+                A[m, j + 1:m + 1] -= A[m, j] * A[j + 1:m + 1, j]
+            keep.append(j)
+        if keep:
+            k = np.array(keep)
+            Lk = A[np.ix_(k, k)]
+            Lk = np.tril(Lk)
+            Fn = np.linalg.solve(Lk, C[:, k].T).T  # C[:, k] R^{-1} with R = Lk^T
+            F[:, r:r + k.size] = Fn
+            d -= np.sum(Fn * Fn, axis=1)
+            r += k.size
+            kept_all.extend(S[k].tolist())
+        tr = float(np.sum(d))
+        if tr < eps or r + 1 > ell_max:
+            done = True
+    return F[:, :r], np.array(kept_all, dtype=np.int64), float(np.sum(d))
+
+
+def rpchol_precond_apply(F: np.ndarray, mu: float, V: np.ndarray) -> np.ndarray:
+    """eq. rpchol_precond: P^{-1} v = mu^{-1} (v - F R^{-1} R^{-T} F^T v) with R^T R = F^T F + mu I."""
+    R = np.linalg.cholesky(F.T @ F + mu * np.eye(F.shape[1])).T
+    W = np.linalg.solve(R, np.linalg.solve(R.T, F.T @ V))
+    return (V - F @ W) / mu

@@ -72,6 +72,11 @@ SIGNATURES = {
     "ngd_gramian_diagonal": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_void_p]),
     "ngd_sample_pivots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ngd_rpcholesky": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int64, C.c_int32, C.c_uint64,
+                                 C.c_uint64, C.c_double, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_rpchol_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p]),
     "ngd_solution_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
     "ngd_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_void_p)]),

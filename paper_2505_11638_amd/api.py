@@ -312,6 +312,26 @@ class Problem:
                                            1 if unique else 0, _ptr(idx), _ptr(cnt), _stream()), "ngd_sample_pivots")
         return idx, cnt
 
+    def rpcholesky(self, J, diag: torch.Tensor, ell_max: int, block: int = 20, seed: int = 0, counter: int = 0,
+                   eps: float = 0.0, Ft: Optional[torch.Tensor] = None):
+        """Block RPCholesky (ngd_rpcholesky): (Ft (ell_max x ld) float64 device tensor, rank, trace)."""
+        _need(diag, torch.float64, "diag")
+        Ft = torch.empty((ell_max, self.ld), dtype=torch.float64, device=self.device) if Ft is None else Ft
+        r, tr = C.c_int64(), C.c_double()
+        L.check(self.lib.ngd_rpcholesky(self.h, C.byref(self._op(J)), _ptr(diag), int(ell_max), int(block), int(seed),
+                                        int(counter), float(eps), _ptr(Ft), Ft.stride(0), C.byref(r), C.byref(tr),
+                                        _stream()), "ngd_rpcholesky")
+        return Ft, int(r.value), float(tr.value)
+
+    def rpchol_precond(self, Ft: torch.Tensor, rank: int) -> NystromResult:
+        """The RPCholesky preconditioner as (U, lam_hat) with a trailing zero pair (ngd_rpchol_precond);
+        use it as `precond` of pcg_solve."""
+        U = torch.empty((rank + 1, self.ld), dtype=self.tdtype, device=self.device)
+        lam = torch.empty(rank + 1, dtype=torch.float64, device=self.device)
+        L.check(self.lib.ngd_rpchol_precond(self.h, _ptr(Ft), Ft.stride(0), int(rank), _ptr(U), U.stride(0), _ptr(lam),
+                                            _stream()), "ngd_rpchol_precond")
+        return NystromResult(U, lam, {"rank": rank})
+
     def solution_error(self, theta: torch.Tensor, X, u_ref, grad_u_ref, sums: Optional[torch.Tensor] = None):
         """Relative L2 and H1 errors of u_theta against (u_ref, grad u_ref) on the points X (n x d), the
         accuracy measure of Section 5 (Monte Carlo over the evaluation set). Returns

@@ -35,6 +35,14 @@ struct ngd_problem {
   double* loss_part; // res_blocks * kTrials
   double* err_part;  // 4 * kEvalBlocks partial sums of the solution error
   double* diag_work; // kDiagChunks * ldP partial column sums of squares (Gramian diagonal)
+  // block RPCholesky workspace (allocated on first use): downdated diagonal, pivots, their count,
+  // state {rank, done, kept}, C^T (64 x ldP), F[S', :] (64 x 1024), gathered columns of J (N x 64),
+  // the pivot block's factor, kept-row map, block partial sums, residual trace
+  void* rp_blob = nullptr;
+  double *rp_d, *rp_Ct, *rp_W, *rp_Rt, *rp_part, *rp_trace;
+  int64_t *rp_idx, *rp_st;
+  int *rp_cnt, *rp_keep;
+  void* rp_Jcols;
   double* grad_work; // gradient_chunks(N) x P
   double* vtmp[4];   // P-vectors (FP64)
   double* scal;      // small scalars / dot workspace (128 doubles)
@@ -390,6 +398,7 @@ ngd_status ngd_problem_destroy(ngd_problem* h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->Jc) (void)hipFree(h->Jc);
+  if (h->rp_blob) (void)hipFree(h->rp_blob);
   (void)hipFree(h->base);
   (void)hipHostFree(h->host);
   delete h;
@@ -561,6 +570,86 @@ ngd_status ngd_gramian_diagonal(ngd_problem* h, const ngd_operator* op, double* 
   return NGD_OK;
 }
 
+ngd_status rp_ensure(ngd_problem* h);
+
+ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* diag, int64_t ell_max, int32_t block,
+                          uint64_t seed, uint64_t counter, double eps, double* Ft, int64_t ldF, int64_t* rank,
+                          double* trace, void* stream) {
+  NGD_CHECK(h != nullptr && op != nullptr && diag != nullptr && Ft != nullptr && rank != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(op->J != nullptr, "rpcholesky needs the stored J_w (the recompute mode is not supported)");
+  NGD_CHECK(block >= 1 && block <= kRpBlockMax, "block must be in [1, 64]");
+  NGD_CHECK(ell_max >= 1 && ell_max <= std::min<int64_t>(kMaxEll, h->P), "ell_max must be in [1, min(1024, P)]");
+  NGD_CHECK(ldF >= h->P, "ldF < P");
+  NGD_CHECK(eps >= 0.0, "eps must be >= 0");
+  NGD_TRY(rp_ensure(h));
+  hipStream_t s = S(stream);
+  const int64_t P = h->P, N = h->N;
+  const int T = h->dtype;
+  const int b = block;
+  NGD_HIP_TRY(hipMemcpyAsync(h->rp_d, diag, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
+  NGD_TRY(launch_zero(Ft, sizeof(double) * (size_t)ell_max * ldF, s));
+  NGD_TRY(launch_zero(h->rp_st, sizeof(int64_t) * 4, s));
+  const int64_t rounds = (ell_max + b - 1) / b;
+  for (int64_t i = 0; i < rounds; ++i) {
+    // S' = Unique(b draws ~ d); C^T = (G[:, S'] - F F[S', :]^T)^T = J[:, S']^T J - F[S', :] F^T
+    NGD_TRY(launch_sample_pivots(h->rp_d, P, seed, counter, (uint32_t)i, b, 1, h->rp_idx, h->rp_cnt, s, h->rp_st + 1));
+    NGD_TRY(launch_gather_cols(T, op->J, op->ldJ, N, h->rp_idx, b, h->rp_Jcols, b, s));
+    GemmArgs g1{b, P, N, h->rp_Jcols, b, false, op->J, op->ldJ, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64, 1.0,
+                0.0};
+    NGD_TRY(launch_gemm(g1, s));
+    const int64_t kmax = std::min<int64_t>(i * b, ell_max);
+    if (kmax > 0) {
+      NGD_TRY(launch_rp_gather_f(Ft, ldF, h->rp_idx, b, kmax, h->rp_W, kmax, s));
+      GemmArgs g2{b, P, kmax, h->rp_W, kmax, true, Ft, ldF, false, h->rp_Ct, h->ldP, NGD_F64, NGD_F64, NGD_F64, G_F64,
+                  -1.0, 1.0};
+      NGD_TRY(launch_gemm(g2, s));
+    }
+    // R = chol(C[S', S']), F[:, r : r + kept] = C R^{-1}, d -= squared row norms; stop on trace < eps
+    NGD_TRY(launch_rp_block(h->rp_Ct, h->ldP, h->rp_idx, h->rp_cnt, h->rp_st, ell_max, h->rp_Rt, h->rp_keep, P, Ft,
+                            ldF, h->rp_d, h->rp_part, eps, b, h->rp_trace, s));
+  }
+  double* hv = reinterpret_cast<double*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, h->rp_st, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipMemcpyAsync(hv + 1, h->rp_trace, sizeof(double), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  int64_t r = 0;
+  std::memcpy(&r, hv, sizeof(r));
+  *rank = r;
+  if (trace != nullptr) *trace = hv[1];
+  return NGD_OK;
+}
+
+ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int64_t rank, void* U, int64_t ldU,
+                              double* lam_hat, void* stream) {
+  NGD_CHECK(h != nullptr && Ft != nullptr && U != nullptr && lam_hat != nullptr, "NULL argument");
+  NGD_CHECK(rank >= 0 && rank + 1 <= h->max_ell, "rank + 1 must be <= max_ell");
+  NGD_CHECK(ldF >= h->P && ldU >= h->P, "ldF and ldU must be >= P");
+  hipStream_t s = S(stream);
+  const int64_t P = h->P, L = rank;
+  const int T = h->dtype;
+  NGD_TRY(launch_zero(static_cast<char*>(U) + (size_t)L * ldU * h->elem, (size_t)ldU * h->elem, s));
+  NGD_TRY(launch_zero(lam_hat + L, sizeof(double), s));
+  if (L == 0) return NGD_OK;
+  // the thin SVD of F through the eigenpairs of F^T F (FP64): U = F V Sigma^{-1}, lam = sigma^2
+  NGD_TRY(launch_cast_rows(NGD_F64, Ft, ldF, L, P, T, h->Bt, h->ldP, s));
+  GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
+              h->gemm_work, 8 * L * L, 1};
+  NGD_TRY(launch_gemm(g5, s));
+  NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
+  NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
+  GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
+  NGD_TRY(launch_gemm(g6, s));
+  int* hv = reinterpret_cast<int*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  if (hv[0] != 0) {
+    set_error("exchange between the workgroups of the tridiagonalisation timed out");
+    return NGD_ERR_HIP;
+  }
+  return NGD_OK;
+}
+
 ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_samples, uint64_t seed, uint64_t counter,
                              uint32_t substream, int32_t unique, int64_t* idx, int32_t* count, void* stream) {
   NGD_CHECK(h != nullptr && weights != nullptr && idx != nullptr && count != nullptr, "NULL argument");
@@ -568,6 +657,38 @@ ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_sa
   NGD_CHECK(substream < 0x80000000u, "substream must be below 2^31");
   return launch_sample_pivots(weights, h->P, seed, counter, substream, n_samples, unique ? 1 : 0, idx, count,
                               S(stream));
+}
+
+// ---- block RPCholesky (Section 4.2.2; block algorithm of the appendix) and its preconditioner ----
+ngd_status rp_ensure(ngd_problem* h) {
+  if (h->rp_blob != nullptr) return NGD_OK;
+  const size_t P = (size_t)h->P, ldP = (size_t)h->ldP, N = (size_t)h->N;
+  const size_t nb = (P + 255) / 256;
+  std::vector<std::pair<void**, size_t>> plan = {
+      {(void**)&h->rp_d, 8 * P},
+      {(void**)&h->rp_Ct, 8 * kRpBlockMax * ldP},
+      {(void**)&h->rp_W, 8 * (size_t)kRpBlockMax * kMaxEll},
+      {(void**)&h->rp_Rt, 8 * (size_t)kRpBlockMax * kRpBlockMax},
+      {(void**)&h->rp_part, 8 * nb},
+      {(void**)&h->rp_trace, 8},
+      {(void**)&h->rp_idx, 8 * (size_t)kRpBlockMax},
+      {(void**)&h->rp_st, 8 * 4},
+      {(void**)&h->rp_cnt, 4 * 4},
+      {(void**)&h->rp_keep, 4 * (size_t)kRpBlockMax},
+      {&h->rp_Jcols, (size_t)h->elem * N * kRpBlockMax}};
+  size_t total = 0;
+  for (auto& e : plan) total += align_up(e.second, 256);
+  if (hipMalloc(&h->rp_blob, total) != hipSuccess) {
+    h->rp_blob = nullptr;
+    set_error("hipMalloc of the RPCholesky workspace failed");
+    return NGD_ERR_OOM;
+  }
+  char* q = static_cast<char*>(h->rp_blob);
+  for (auto& e : plan) {
+    *e.first = q;
+    q += align_up(e.second, 256);
+  }
+  return NGD_OK;
 }
 
 ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,

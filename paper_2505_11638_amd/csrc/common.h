@@ -288,11 +288,20 @@ ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
 // ns samples of indices in [0, P) with probability proportional to max(w, 0) (Philox substream q;
 // sorted and without duplicates when `unique`; count on the device); gather of columns.
 constexpr int kDiagChunks = 64;
+constexpr int kRpBlockMax = 64;  // largest RPCholesky block
 constexpr int64_t kMaxSamples = 4096;
 ngd_status launch_colsq(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, double* work,
                         int64_t work_elems, int accumulate, double* out, hipStream_t s);
 ngd_status launch_sample_pivots(const double* w, int64_t P, uint64_t seed, uint64_t counter, uint32_t q, int64_t ns,
-                                int unique, int64_t* idx, int* count, hipStream_t s);
+                                int unique, int64_t* idx, int* count, hipStream_t s, const int64_t* done = nullptr);
+// block RPCholesky pieces: W = F[idx, :kmax] (b x ldw) from the rows of F^T; the pivot block's
+// Cholesky with dependent pivots dropped, the new rows of F^T, the diagonal downdate and the
+// stopping rule. st = {rank, done, kept} (device int64), part = ceil(P/256) doubles.
+ngd_status launch_rp_gather_f(const double* Ft, int64_t ldF, const int64_t* idx, int b, int64_t kmax, double* W,
+                              int64_t ldw, hipStream_t s);
+ngd_status launch_rp_block(const double* Ct, int64_t ldc, const int64_t* idx, const int* count, int64_t* st,
+                           int64_t cap, double* Rt, int* keep_rows, int64_t P, double* Ft, int64_t ldF, double* d,
+                           double* part, double eps, int b, double* trace_out, hipStream_t s);
 ngd_status launch_gather_cols(int dtype, const void* J, int64_t ldJ, int64_t rows, const int64_t* cols, int64_t ncol,
                               void* out, int64_t ld_out, hipStream_t s);
 

@@ -54,9 +54,15 @@ constexpr int kSampThreads = 1024;
 __global__ __launch_bounds__(kSampThreads) void sample_pivots_kernel(const double* __restrict__ w, int64_t P,
                                                                      uint64_t seed, uint64_t counter, uint32_t q,
                                                                      int64_t ns, int unique, int64_t* __restrict__ idx,
-                                                                     int* __restrict__ count) {
+                                                                     int* __restrict__ count,
+                                                                     const int64_t* __restrict__ done) {
   __shared__ double csum[kSampThreads];
   const int t = threadIdx.x;
+  if (done != nullptr && *done) {  // a finished factorisation draws nothing
+    for (int64_t k = t; k < ns; k += kSampThreads) idx[k] = -1;
+    if (t == 0) *count = 0;
+    return;
+  }
   const int64_t chunk = (P + kSampThreads - 1) / kSampThreads;
   {
     const int64_t j0 = (int64_t)t * chunk, j1 = (j0 + chunk) < P ? (j0 + chunk) : P;
@@ -120,6 +126,7 @@ __global__ __launch_bounds__(kSampThreads) void sample_pivots_kernel(const doubl
       n = ns > 0 ? 1 : 0;
       for (int64_t i = 1; i < ns; ++i)
         if (idx[i] != idx[n - 1]) idx[n++] = idx[i];
+      for (int64_t i = n; i < ns; ++i) idx[i] = -1;
     }
     *count = (int)n;
   }
@@ -135,7 +142,153 @@ __global__ void gather_cols_kernel(const T* __restrict__ J, int64_t ldJ, int64_t
   for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) out[i * ld_out + c] = col >= 0 ? J[i * ldJ + col] : T(0);
 }
 
+// ---- block RPCholesky (Section 4.2.2; the block algorithm of the appendix) ----
+// Device state of one factorisation: [0] rank r so far, [1] done flag, [2] kept columns of the
+// current block; sums of the downdated diagonal in `dsum`.
+constexpr int kRpMaxBlock = kRpBlockMax;
+
+// W[m * ldw + k] = F[idx[m], k] = Ft[k * ldF + idx[m]] for k < kmax (zero rows for idx < 0)
+__global__ void rp_gather_f_kernel(const double* __restrict__ Ft, int64_t ldF, const int64_t* __restrict__ idx,
+                                   int b, int64_t kmax, double* __restrict__ W, int64_t ldw) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (k >= kmax || m >= b) return;
+  const int64_t s = idx[m];
+  W[(int64_t)m * ldw + k] = s >= 0 ? Ft[k * ldF + s] : 0.0;
+}
+
+// One workgroup: the pivot block C[S', S'] (from the rows of C^T at the pivots), its Cholesky
+// factor R (C[S',S'] = R^T R) column by column; a pivot that is not safely positive (<= 1e-13 of the
+// block's largest diagonal entry: a direction the earlier columns already hold) is dropped together
+// with its column. Writes R^T rows of the kept pivots, packed, to Rt (kRpMaxBlock x kRpMaxBlock) and
+// their count to st[2] (capped so that r + kept <= cap).
+__global__ __launch_bounds__(64) void rp_block_chol_kernel(const double* __restrict__ Ct, int64_t ldc,
+                                                           const int64_t* __restrict__ idx,
+                                                           const int* __restrict__ count, int64_t* __restrict__ st,
+                                                           int64_t cap, double* __restrict__ Rt,
+                                                           int* __restrict__ keep_rows) {
+  __shared__ double A[kRpMaxBlock][kRpMaxBlock + 1];
+  __shared__ int keep[kRpMaxBlock];
+  const int c = *count;
+  const int t = threadIdx.x;
+  for (int e = t; e < c * c; e += blockDim.x) {
+    const int m = e / c, n = e - m * c;
+    A[m][n] = Ct[(int64_t)m * ldc + idx[n]];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double dmax = 0.0;
+    for (int m = 0; m < c; ++m) dmax = fmax(dmax, A[m][m]);
+    const int64_t r = st[0];
+    int kept = 0;
+    // right-looking: column j's pivot, scaled column, rank-1 update of the rest (symmetric, lower)
+    for (int j = 0; j < c; ++j) {
+      const double pj = A[j][j];
+      keep[j] = 0;
+      if (st[1] || !(pj > 1e-13 * dmax) || r + kept >= cap) continue;
+      const double rj = sqrt(pj);
+      A[j][j] = rj;
+      for (int m = j + 1; m < c; ++m) A[m][j] /= rj;
+      for (int m = j + 1; m < c; ++m)
+        for (int n = j + 1; n <= m; ++n) A[m][n] -= A[m][j] * A[n][j];
+      keep[j] = 1;
+      ++kept;
+    }
+    st[2] = kept;
+  }
+  __syncthreads();
+  // packed lower factor of the kept pivots: Rt[a][b'] = L(kept a, kept b'), L = R^T
+  if (t == 0) {
+    int a = 0;
+    for (int m = 0; m < c; ++m) {
+      if (!keep[m]) continue;
+      int bb = 0;
+      for (int n = 0; n <= m; ++n) {
+        if (!keep[n]) continue;
+        Rt[a * kRpMaxBlock + bb] = A[m][n];
+        ++bb;
+      }
+      keep_rows[a] = m;
+      ++a;
+    }
+  }
+}
+
+// Per parameter p: x = L^{-1} C[p, kept] (the row p of C R^{-1}, by forward substitution with the
+// packed factor), written as rows r .. r + kept - 1 of Ft; the diagonal downdated by |x|^2. Block
+// partial sums of the downdated diagonal go to part[blockIdx.x].
+__global__ __launch_bounds__(256) void rp_update_kernel(const double* __restrict__ Ct, int64_t ldc,
+                                                        const double* __restrict__ Rt,
+                                                        const int* __restrict__ keep_rows,
+                                                        const int64_t* __restrict__ st, int64_t P,
+                                                        double* __restrict__ Ft, int64_t ldF, double* __restrict__ d,
+                                                        double* __restrict__ part) {
+  __shared__ double Ls[kRpMaxBlock * kRpMaxBlock];
+  __shared__ double red[16];
+  const int kept = (int)st[2];
+  const int64_t r = st[0];
+  for (int e = threadIdx.x; e < kept * kRpMaxBlock; e += blockDim.x) Ls[e] = Rt[e];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dv = 0.0;
+  if (p < P) {
+    double x[kRpMaxBlock];
+    double dd = d[p];
+    for (int a = 0; a < kept; ++a) {
+      double v = Ct[(int64_t)keep_rows[a] * ldc + p];
+      for (int bb = 0; bb < a; ++bb) v -= Ls[a * kRpMaxBlock + bb] * x[bb];
+      x[a] = v / Ls[a * kRpMaxBlock + a];
+      Ft[(r + a) * ldF + p] = x[a];
+      dd -= x[a] * x[a];
+    }
+    d[p] = dd;
+    dv = dd;
+  }
+  dv = block_sum(dv, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = dv;
+}
+
+// One thread: the rank grows by the kept columns; the factorisation is done once the trace of the
+// residual (the downdated diagonal's sum, in block order) is below eps, or no room is left.
+__global__ void rp_finish_kernel(const double* __restrict__ part, int nb, double eps, int64_t cap, int b,
+                                 int64_t* __restrict__ st, double* __restrict__ trace_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tr = 0.0;
+  for (int i = 0; i < nb; ++i) tr += part[i];
+  st[0] += st[2];
+  st[2] = 0;
+  *trace_out = tr;
+  if (tr < eps || st[0] + 1 > cap) st[1] = 1;
+}
+
 }  // namespace
+
+ngd_status launch_rp_gather_f(const double* Ft, int64_t ldF, const int64_t* idx, int b, int64_t kmax, double* W,
+                              int64_t ldw, hipStream_t s) {
+  if (kmax <= 0 || b <= 0) return NGD_OK;
+  hipLaunchKernelGGL(rp_gather_f_kernel, dim3((unsigned)((kmax + 255) / 256), (unsigned)b), dim3(256), 0, s, Ft, ldF,
+                     idx, b, kmax, W, ldw);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_rp_block(const double* Ct, int64_t ldc, const int64_t* idx, const int* count, int64_t* st,
+                           int64_t cap, double* Rt, int* keep_rows, int64_t P, double* Ft, int64_t ldF, double* d,
+                           double* part, double eps, int b, double* trace_out, hipStream_t s) {
+  if (b > kRpMaxBlock) {
+    set_error("rpcholesky: block size above 64");
+    return NGD_ERR_INVALID;
+  }
+  hipLaunchKernelGGL(rp_block_chol_kernel, dim3(1), dim3(64), 0, s, Ct, ldc, idx, count, st, cap, Rt, keep_rows);
+  NGD_HIP_TRY(hipGetLastError());
+  const int nb = (int)((P + 255) / 256);
+  hipLaunchKernelGGL(rp_update_kernel, dim3((unsigned)nb), dim3(256), 0, s, Ct, ldc, Rt, keep_rows, st, P, Ft, ldF, d,
+                     part);
+  NGD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(rp_finish_kernel, dim3(1), dim3(64), 0, s, part, nb, eps, cap, b, st, trace_out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
 
 ngd_status launch_colsq(int dtype, const void* J, int64_t ldJ, int64_t N, int64_t P, double* work,
                         int64_t work_elems, int accumulate, double* out, hipStream_t s) {
@@ -160,9 +313,9 @@ ngd_status launch_colsq(int dtype, const void* J, int64_t ldJ, int64_t N, int64_
 }
 
 ngd_status launch_sample_pivots(const double* w, int64_t P, uint64_t seed, uint64_t counter, uint32_t q, int64_t ns,
-                                int unique, int64_t* idx, int* count, hipStream_t s) {
+                                int unique, int64_t* idx, int* count, hipStream_t s, const int64_t* done) {
   hipLaunchKernelGGL(sample_pivots_kernel, dim3(1), dim3(kSampThreads), 0, s, w, P, seed, counter, q, ns, unique,
-                     idx, count);
+                     idx, count, done);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -438,6 +438,12 @@ ngd_status launch_cast_rows(int src_type, const void* src, int64_t ld_s, int64_t
   if (src_type == NGD_F32 && dst_type == NGD_BF16)
     hipLaunchKernelGGL((cast_rows_kernel<float, __bf16>), grid, dim3(256), 0, s, (const float*)src, ld_s, rows, cols,
                        (__bf16*)dst, ld_d);
+  else if (src_type == NGD_F64 && dst_type == NGD_F32)
+    hipLaunchKernelGGL((cast_rows_kernel<double, float>), grid, dim3(256), 0, s, (const double*)src, ld_s, rows, cols,
+                       (float*)dst, ld_d);
+  else if (src_type == NGD_F64 && dst_type == NGD_F64)
+    hipLaunchKernelGGL((cast_rows_kernel<double, double>), grid, dim3(256), 0, s, (const double*)src, ld_s, rows,
+                       cols, (double*)dst, ld_d);
   else {
     set_error("cast_rows: unsupported types");
     return NGD_ERR_INVALID;

@@ -47,7 +47,12 @@ class NGD:
         self.ell_max = ell_max if ell_max is not None else getattr(data, "ell_max", None)
         self.dell = int(dell if dell is not None else getattr(data, "dell", 20))
         self.rank_offset = int(rank_offset)
-        self.gp = Problem(data, dtype=dtype, max_ell=self.ell_max or ell or getattr(data, "ell", 1))
+        # RPCholNGD (Alg. 5) keeps one more row for the preconditioner's trailing zero pair
+        max_ell = self.ell_max or ell or getattr(data, "ell", 1)
+        if solver == "rpchol":
+            self.ell_max = int(self.ell_max or ell or getattr(data, "ell", 1))
+            max_ell = self.ell_max + 1
+        self.gp = Problem(data, dtype=dtype, max_ell=max_ell)
         gp = self.gp
         self.solver = solver
         if test_matrix not in ("gaussian", "sampling"):
@@ -56,7 +61,9 @@ class NGD:
         self.test_matrix = test_matrix
         self.diag = None
         if self.ell_max is not None:
-            self.ell_max = min(int(self.ell_max), gp.P)
+            self.ell_max = min(int(self.ell_max), gp.P - (1 if solver == "rpchol" else 0))
+        self.rp_block = 20  # block size of the block RPCholesky (experimental setup of Section 5)
+        self.Ft = None
         self.ell = min(int(ell or data.ell), gp.P, self.ell_max or gp.P)
         self.sketch_dtype = sketch_dtype or getattr(data, "sketch_dtype", None)
         if gp.dtype_name == "f64":
@@ -64,7 +71,7 @@ class NGD:
         self.rtol = rtol
         if maxit is None:
             maxit = getattr(data, "maxit", None)
-        self.maxit = maxit if maxit is not None else (1000 if solver == "nystrom" else gp.P)
+        self.maxit = maxit if maxit is not None else (gp.P if solver == "cg" else 1000)
         self.lam = lam if lam is not None else getattr(data, "lam", None)
         self.gamma = gamma
         self.seed = seed
@@ -85,6 +92,8 @@ class NGD:
         # all of lam_hat when the sketch size adapts (read after the solve's synchronisation)
         self.lam_host = (torch.empty(self.ell_max, dtype=torch.float64, pin_memory=True)
                          if self.ell_max is not None and solver == "nystrom" else None)
+        if solver not in ("nystrom", "cg", "rpchol"):
+            raise ValueError("solver must be 'nystrom', 'cg' or 'rpchol'")
         # per-step device buffers, reused: residuals, gradient, loss and the search direction
         self.bufs = None
         self.pc = None
@@ -124,13 +133,22 @@ class NGD:
             if self.lam_host is not None:
                 self.ell = self.next_rank(self.lam_host.numpy()[:ell], mu, ell)
         else:
+            # plain CG, or RPCholNGD (Alg. 5): lambda_1 from 4 power iterations, then the damping rule
             lam1 = gp.power_lambda_max(J, self.v0, 4)
             L0 = float(self.loss_np[0])
             mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
-            out = gp.pcg_solve(J, grad, mu, precond=None, rtol=self.rtol, maxit=self.maxit, out=self.d)
+            pc = None
+            if self.solver == "rpchol":
+                # F with G ~ F F^T until the residual trace is below mu p; P = F F^T + mu I
+                self.diag = gp.gramian_diagonal(J, out=self.diag)
+                self.Ft, rank, _ = gp.rpcholesky(J, self.diag, self.ell_max, self.rp_block, seed=self.seed,
+                                                 counter=self.k, eps=mu * gp.P, Ft=self.Ft)
+                pc = gp.rpchol_precond(self.Ft, rank)
+                self.last_rank = rank
+            out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
-        rank = ell if self.solver == "nystrom" else -1
+        rank = ell if self.solver == "nystrom" else (self.last_rank if self.solver == "rpchol" else -1)
         return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
 
     def next_rank(self, lam_hat, mu: float, ell: int) -> int:

@@ -150,3 +150,90 @@ def test_ngd_with_sampling_test_matrix_decreases_loss():
 
 def ngd_first_loss(prob):
     return mlp.loss(wl.glorot_theta(prob.widths, 5), prob)
+
+
+# ---- block RPCholesky and RPCholNGD ----
+
+@pytest.mark.parametrize("name", ["poisson2d_f64", "poisson2d_f32"])
+@pytest.mark.parametrize("ell_max,block,frac", [(40, 20, 0.0), (37, 8, 1e-3), (12, 5, 0.0)])
+def test_rpcholesky_matches_oracle(name, ell_max, block, frac):
+    """F against the oracle's block RPCholesky on the same diagonal and Gramian (columns of G from the
+    GPU's own J in FP64); the rank, the residual trace and F F^T on probes agree."""
+    prob, th, gp, theta, J = _setup(name)
+    Jg = J.cpu().numpy().astype(np.float64)[:, :gp.P]
+    G = Jg.T @ Jg
+    d = gp.gramian_diagonal(J)
+    eps = frac * float(np.trace(G))
+    gp2 = Problem(prob, dtype=prob.dtype, max_ell=ell_max + 1)
+    Ft, r, tr = gp2.rpcholesky(J, d, ell_max, block, seed=4, counter=3, eps=eps)
+    Fo, piv, tro = sampling.block_rpcholesky(lambda S: G[:, S], d.cpu().numpy(), ell_max, block, 4, 3, eps)
+    assert r == Fo.shape[1]
+    F = Ft.cpu().numpy()[:r, :gp.P].T
+    assert np.all(Ft.cpu().numpy()[r:, :gp.P] == 0)
+    # the columns of the first block (a well-conditioned pivot block) agree entry by entry; later
+    # columns come from nearly dependent pivots and carry the conditioning of their pivot blocks, so
+    # the approximation F F^T is compared instead
+    k0 = min(r, block)
+    np.testing.assert_allclose(F[:, :k0], Fo[:, :k0], rtol=0, atol=1e-10 * np.abs(Fo).max())
+    np.testing.assert_allclose(F @ F.T, Fo @ Fo.T, rtol=0, atol=1e-10 * np.abs(G).max())
+    assert abs(tr - tro) <= 1e-9 * np.trace(G)
+    X = wl.probe_vectors(gp.P, 4, seed=1)
+    assert np.linalg.norm(F @ (F.T @ X) - Fo @ (Fo.T @ X)) <= 1e-9 * np.linalg.norm(G) * np.linalg.norm(X)
+    gp2.close()
+    gp.close()
+
+
+@pytest.mark.parametrize("name", ["poisson2d_f64", "poisson2d_f32"])
+def test_rpchol_preconditioner_and_solve(name):
+    """(U, lam_hat) reproduce F F^T with a trailing zero pair, and PCG with it solves (G + mu I) d = g
+    in about as many iterations as the oracle's PCG with the Woodbury form eq. rpchol_precond."""
+    from oracle import cg, linalg
+    prob, th, gp0, theta, J = _setup(name)
+    gp0.close()
+    ell_max = 30
+    gp = Problem(prob, dtype=prob.dtype, max_ell=ell_max + 1)
+    theta = gp.theta(th)
+    J = gp.new_jacobian()
+    r_, J, grad, loss = gp.residual_jacobian(theta, J)
+    Jg = J.cpu().numpy().astype(np.float64)[:, :gp.P]
+    G = Jg.T @ Jg
+    mu = prob.lam
+    d = gp.gramian_diagonal(J)
+    Ft, r, _ = gp.rpcholesky(J, d, ell_max, 10, seed=1, counter=0, eps=mu * gp.P)
+    pc = gp.rpchol_precond(Ft, r)
+    U = pc.U.cpu().numpy().astype(np.float64)[:, :gp.P]
+    lam = pc.lam_hat.cpu().numpy()
+    assert lam.size == r + 1 and lam[-1] == 0 and np.all(U[-1] == 0) and np.all(np.diff(lam) <= 0)
+    F = Ft.cpu().numpy()[:r, :gp.P].T
+    X = wl.probe_vectors(gp.P, 4, seed=2)
+    tol = 1e-10 if prob.dtype == "f64" else 1e-5
+    assert np.linalg.norm(U.T @ (lam[:, None] * (U @ X)) - F @ (F.T @ X)) <= tol * lam[0] * np.linalg.norm(X)
+    g = grad.cpu().numpy()
+    rtol = 1e-8 if prob.dtype == "f64" else 1e-6
+    out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=rtol, maxit=2000)
+    assert out.converged
+    dstar = linalg.solve_cholesky(G, g, mu)
+    res = np.linalg.norm(g - G @ out.d.cpu().numpy() - mu * out.d.cpu().numpy())
+    assert res <= 10 * rtol * np.linalg.norm(g)
+    assert np.linalg.norm(out.d.cpu().numpy() - dstar) <= res / mu * (1 + 1e-6) + 1e-12 * np.linalg.norm(dstar)
+    ref = cg.pcg(lambda v: G @ v + mu * v, g, rtol, 2000, lambda v: sampling.rpchol_precond_apply(F, mu, v))
+    assert ref.converged
+    if prob.dtype == "f64":
+        assert abs(out.iters - ref.iters) <= max(3, 0.25 * ref.iters)
+    else:
+        # rtol 1e-6 sits a few units above FP32 roundoff: the FP32 matvec needs a few more iterations
+        assert ref.iters - 3 <= out.iters <= ref.iters + max(6, 0.5 * ref.iters)
+    gp.close()
+
+
+def test_rpchol_ngd_steps():
+    prob = wl.poisson_random(d=3, widths=(3, 24, 24, 1), n_interior=400, n_boundary=80, seed=6, dtype="f64",
+                             ell=40, sketch_dtype="f64")
+    ngd = NGD(prob, wl.glorot_theta(prob.widths, 6), solver="rpchol", seed=6, ell_max=60, maxit=20)
+    L0 = None
+    for _ in range(5):
+        rep = ngd.step()
+        L0 = rep.loss if L0 is None else L0
+        assert rep.loss_new <= rep.loss and 1 <= rep.rank <= 60
+    assert rep.loss_new < 0.5 * L0
+    ngd.gp.close()

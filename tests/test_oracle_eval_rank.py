@@ -208,3 +208,47 @@ def test_shifted_nystrom_limits_and_order():
     ev = np.linalg.eigvalsh(G0 - Gs)
     assert ev.min() >= -1e-10 and ev.max() > 0
     assert np.linalg.norm(G0 - nystrom.nystrom_shifted(G, Om, 1e-9)) <= 1e-6 * np.linalg.norm(G0)
+
+
+# ---- block RPCholesky and its preconditioner ----
+
+def _psd(rank, p, seed):
+    B = np.random.default_rng(seed).standard_normal((rank, p)) * np.logspace(0, -3, rank)[:, None]
+    return B.T @ B
+
+
+def test_rpcholesky_exact_for_low_rank_and_trace_identity():
+    from oracle import sampling
+    G = _psd(7, 30, 1)
+    F, piv, tr = sampling.block_rpcholesky(lambda S: G[:, S], np.diag(G).copy(), 20, 4, seed=1, counter=0,
+                                           eps=1e-12 * np.trace(G))
+    assert F.shape[1] <= 20
+    np.testing.assert_allclose(F @ F.T, G, atol=1e-9 * np.abs(G).max())
+    assert abs(tr - np.trace(G - F @ F.T)) <= 1e-12 * np.trace(G)
+
+
+def test_rpcholesky_interpolates_pivot_columns_and_stops_on_trace():
+    from oracle import sampling
+    G = _psd(25, 40, 2)
+    eps = 0.05 * np.trace(G)
+    F, piv, tr = sampling.block_rpcholesky(lambda S: G[:, S], np.diag(G).copy(), 24, 5, seed=3, counter=2, eps=eps)
+    # partial Cholesky reproduces the selected columns exactly and leaves a PSD residual
+    np.testing.assert_allclose((F @ F.T)[:, piv], G[:, piv], atol=1e-10 * np.abs(G).max())
+    assert np.linalg.eigvalsh(G - F @ F.T).min() >= -1e-10 * np.abs(G).max()
+    assert abs(tr - np.trace(G - F @ F.T)) <= 1e-10 * np.trace(G)
+    # it stopped at the first round whose residual trace fell below eps (or ran out of room)
+    assert tr < eps or F.shape[1] + 1 > 24
+
+
+def test_rpchol_preconditioner_is_the_inverse_of_FFt_plus_mu():
+    from oracle import sampling
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((25, 6))
+    mu = 0.3
+    V = rng.standard_normal((25, 3))
+    want = np.linalg.solve(F @ F.T + mu * np.eye(25), V)
+    np.testing.assert_allclose(sampling.rpchol_precond_apply(F, mu, V), want, rtol=1e-12, atol=1e-12)
+    # the SVD form of the same inverse
+    U, s, _ = np.linalg.svd(F, full_matrices=False)
+    svd_form = U @ ((U.T @ V) / (s[:, None] ** 2 + mu)) + (V - U @ (U.T @ V)) / mu
+    np.testing.assert_allclose(svd_form, want, rtol=1e-12, atol=1e-12)
