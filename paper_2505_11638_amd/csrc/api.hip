@@ -595,8 +595,9 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
     // S' = Unique(b draws ~ d); C^T = (G[:, S'] - F F[S', :]^T)^T = J[:, S']^T J - F[S', :] F^T
     NGD_TRY(launch_sample_pivots(h->rp_d, P, seed, counter, (uint32_t)i, b, 1, h->rp_idx, h->rp_cnt, s, h->rp_st + 1));
     NGD_TRY(launch_gather_cols(T, op->J, op->ldJ, N, h->rp_idx, b, h->rp_Jcols, b, s));
+    // (a b x P output over K = N: split K through the core's GEMM workspace, idle here)
     GemmArgs g1{b, P, N, h->rp_Jcols, b, false, op->J, op->ldJ, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64, 1.0,
-                0.0};
+                0.0, h->gemm_work, 8 * (int64_t)h->max_ell * h->max_ell};
     NGD_TRY(launch_gemm(g1, s));
     const int64_t kmax = std::min<int64_t>(i * b, ell_max);
     if (kmax > 0) {
