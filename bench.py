@@ -44,6 +44,9 @@ WORKLOADS["paper3d"] = ("the paper's 3D Poisson PINN: 3-64-64-64-1 tanh (P=8,641
                          "u* = sin(pi x) sin(pi y) sin(pi z); Nystrom NGD with adaptive sketch size (ell from 20 in "
                          "steps of 20 up to 500), at most 20 PCG iterations at rtol 1e-6, mu = max(10 eps lam1_hat, "
                          "1e-4 L^2), Armijo; relative H1 error on 100,000 random points")
+WORKLOADS["paper_heat"] = ("the paper's heat equation in 3+1D: 4-64-64-64-1 tanh (P=8,705), 10,000 + 1,000 random "
+                            "points, FP64, u* = (cos(pi x) + cos(pi y) + cos(pi z)) exp(-pi^2 t / 4); the paper3d "
+                            "solver settings; relative H1 error (space-time gradient) on 100,000 random points")
 # The paper's Nystrom NGD on this problem: 66.8 s to its plateau error over at most 1,000 iterations on
 # one RTX 4090 in FP64, so at most 15.0 NGD steps/s (a derived upper bound on its rate).
 PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1}
@@ -59,7 +62,7 @@ def bench_paper(a):
     import workloads as wl
     from paper_2505_11638_amd.driver import NGD
 
-    prob = wl.config("paper3d", seed=a.seed)
+    prob = wl.config(a.config, seed=a.seed)
     theta0 = wl.glorot_theta(prob.widths, a.seed)
     P, N = prob.n_params, prob.n_rows
     variant = "rpchol" if a.solver == "rpchol" else a.test_matrix
@@ -90,13 +93,13 @@ def bench_paper(a):
         "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
         "value": sps, "unit": "NGD steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": sps / PAPER3D_BASELINE_SPS[variant],
-        "baseline": {"value": PAPER3D_BASELINE_SPS[variant], "unit": "NGD steps/s",
+        "vs_baseline": sps / PAPER3D_BASELINE_SPS[variant] if a.config == "paper3d" else None,
+        "baseline": None if a.config != "paper3d" else {"value": PAPER3D_BASELINE_SPS[variant], "unit": "NGD steps/s",
                      "kind": f"the paper's {'RPCholNGD' if variant == 'rpchol' else 'Nystrom NGD (' + variant + ' test matrix)'}"
                              f" on this problem, RTX 4090, FP64: {PAPER3D_BASELINE_S[variant]} s to its plateau over "
                              "at most 1,000 iterations (an upper bound on its rate)"},
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"paper3d: {WORKLOADS['paper3d']}; {a.warmup} + {a.steps} NGD steps from a "
+        "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}; {a.warmup} + {a.steps} NGD steps from a "
                                f"Glorot start (the last {a.steps} timed)", "P": P, "N": N,
                    "ell0": prob.ell, "ell_max": prob.ell_max, "dell": prob.dell, "maxit": prob.maxit,
                    "preconditioner": variant},
@@ -246,7 +249,7 @@ def main(argv=None):
 
     if a.config == "c5":
         return bench_batch(a)
-    if a.config == "paper3d":
+    if a.config in ("paper3d", "paper_heat"):
         return bench_paper(a)
 
     import numpy as np

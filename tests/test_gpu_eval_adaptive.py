@@ -105,3 +105,31 @@ def test_adaptive_rank_follows_alg4(dtype):
         assert rep.loss_new <= rep.loss
     assert grew
     ngd.gp.close()
+
+
+def test_heat3d_paper_shape_parity_and_steps():
+    """The heat equation in 3+1D (four inputs, three Laplacian coordinates, time last): residuals,
+    Jacobian and gradient against the oracle, the error sums against the oracle's, and adaptive Nystrom
+    NGD steps that decrease the loss."""
+    prob = wl.heat3d_paper(widths=(4, 24, 20, 1), n_interior=70, n_boundary=35, seed=7, ell=8)
+    prob = dataclasses.replace(prob, ell_max=40, dell=8, maxit=20)
+    th = wl.glorot_theta(prob.widths, 7)
+    gp = Problem(prob, dtype="f64", max_ell=40)
+    theta = gp.theta(th)
+    r, J, grad, loss = gp.residual_jacobian(theta, gp.new_jacobian())
+    r_o, J_o = mlp.residual_and_jacobian(th, prob)
+    assert np.linalg.norm(r.cpu().numpy() - r_o) <= 1e-10 * np.linalg.norm(r_o)
+    assert np.linalg.norm(J.cpu().numpy()[:, :gp.P] - J_o) <= 1e-10 * np.linalg.norm(J_o)
+    assert np.linalg.norm(grad.cpu().numpy() - J_o.T @ r_o) <= 1e-10 * np.linalg.norm(J_o.T @ r_o)
+    X, u, g = wl.evaluation_set(prob, 3000, seed=1)
+    _, _, sums = gp.solution_error(theta, X, u, g)
+    np.testing.assert_allclose(sums.cpu().numpy(), mlp.solution_error_sums(th, prob.widths, X, u, g), rtol=1e-12)
+    gp.close()
+    ngd = NGD(prob, th, solver="nystrom", seed=7)
+    L0 = None
+    for _ in range(4):
+        rep = ngd.step()
+        L0 = rep.loss if L0 is None else L0
+        assert rep.loss_new <= rep.loss
+    assert rep.loss_new < L0
+    ngd.gp.close()

@@ -252,3 +252,27 @@ def test_rpchol_preconditioner_is_the_inverse_of_FFt_plus_mu():
     U, s, _ = np.linalg.svd(F, full_matrices=False)
     svd_form = U @ ((U.T @ V) / (s[:, None] ** 2 + mu)) + (V - U @ (U.T @ V)) / mu
     np.testing.assert_allclose(svd_form, want, rtol=1e-12, atol=1e-12)
+
+
+def test_paper_heat_workload_and_source():
+    """The heat 3+1D setup: shapes, and f = u_t - Laplace u of the exact solution (central differences)."""
+    p = wl.config("paper_heat")
+    assert p.widths == (4, 64, 64, 64, 1) and p.n_params == 8705 and p.pde == wl.PDE_HEAT
+    n_i = int((p.kind == wl.KIND_INTERIOR).sum())
+    assert n_i == 10000 and p.n_rows == 11000 and (p.kind == wl.KIND_INITIAL).sum() == 143
+    assert np.all(p.X[p.kind == wl.KIND_INITIAL, 3] == 0)
+    lat = p.X[p.kind == wl.KIND_BOUNDARY, :3]
+    assert np.all(np.any((lat == 0) | (lat == 1), axis=1))
+    X = p.X[:20][p.kind[:20] == wl.KIND_INTERIOR]
+    h = 1e-4
+    u = lambda Y: wl.exact_solution("heatcos", Y)[0]
+    E = np.eye(4)
+    lap = sum((u(X + h * E[j]) - 2 * u(X) + u(X - h * E[j])) / h ** 2 for j in range(3))
+    ut = (u(X + h * E[3]) - u(X - h * E[3])) / (2 * h)
+    np.testing.assert_allclose(p.f[:20][p.kind[:20] == wl.KIND_INTERIOR], ut - lap, rtol=1e-5, atol=1e-6)
+    g0 = p.g[p.kind == wl.KIND_INITIAL]
+    np.testing.assert_allclose(g0, u(p.X[p.kind == wl.KIND_INITIAL]), rtol=1e-14)
+    # the oracle's residual at the exact solution's values: u - g vanishes on boundary rows by construction
+    _, grad = wl.exact_solution("heatcos", X)
+    fd = np.stack([(u(X + 1e-6 * e) - u(X - 1e-6 * e)) / 2e-6 for e in E], axis=1)
+    np.testing.assert_allclose(grad, fd, atol=1e-7)

@@ -208,6 +208,12 @@ def exact_solution(solution: str, X: np.ndarray) -> tuple:
         return u, grad
     if solution == "sinsum":
         return np.sum(s, axis=1), np.pi * c
+    if solution == "heatcos":  # (cos(pi x) + cos(pi y) + cos(pi z)) exp(-pi^2 t / 4), inputs (x, y, z, t)
+        e = np.exp(-np.pi ** 2 * X[:, 3] / 4.0)
+        u = (c[:, 0] + c[:, 1] + c[:, 2]) * e
+        grad = np.stack([-np.pi * s[:, 0] * e, -np.pi * s[:, 1] * e, -np.pi * s[:, 2] * e,
+                         -np.pi ** 2 / 4.0 * u], axis=1)
+        return u, grad
     if solution == "heat":  # exp(-2 pi^2 t) sin(pi x) sin(pi y), inputs (x, y, t)
         e = np.exp(-2.0 * np.pi ** 2 * X[:, 2])
         u = e * s[:, 0] * s[:, 1]
@@ -226,6 +232,30 @@ def evaluation_set(prob: Problem, n: int = 100_000, seed: int = 0) -> tuple:
     return X, u, grad
 
 
+def heat3d_paper(widths=(4, 64, 64, 64, 1), n_interior=10000, n_boundary=1000, seed=0, dtype="f64", ell=20,
+                 sketch_dtype="f64") -> Problem:
+    """The paper's heat equation in 3+1D (Section 5.1.2): u_t - Laplace u = f on (0,1)^3 x (0,1) with
+    u* = (cos(pi x) + cos(pi y) + cos(pi z)) exp(-pi^2 t / 4), so f = 3 pi^2 / 4 u*; Dirichlet data
+    g = u* on the lateral boundary and the initial value u*(., 0). Inputs (x, y, z, t).
+
+    The n_boundary random boundary points are split between the lateral boundary and t = 0 in
+    proportion to their measures (6 : 1); weights are measure / count as elsewhere."""
+    rng_i, rng_b, rng_0 = _rng(seed, _P_INTERIOR), _rng(seed, _P_BOUNDARY), _rng(seed, _P_INITIAL)
+    n_init = int(round(n_boundary / 7.0))
+    n_lat = n_boundary - n_init
+    Xi = rng_i.uniform(0.0, 1.0, size=(n_interior, 4))
+    Xl = np.concatenate([_box_boundary(rng_b, n_lat, 3), rng_b.uniform(0, 1, (n_lat, 1))], 1)
+    X0 = np.concatenate([rng_0.uniform(0, 1, (n_init, 3)), np.zeros((n_init, 1))], 1)
+    ui, _ = exact_solution("heatcos", Xi)
+    ul, _ = exact_solution("heatcos", Xl)
+    u0, _ = exact_solution("heatcos", X0)
+    blocks = [(Xi, KIND_INTERIOR, 1.0 / n_interior, 0.75 * np.pi ** 2 * ui, np.zeros(n_interior)),
+              (Xl, KIND_BOUNDARY, 6.0 / n_lat, np.zeros(n_lat), ul),
+              (X0, KIND_INITIAL, 1.0 / n_init, np.zeros(n_init), u0)]
+    return _assemble("heat3d_paper", PDE_HEAT, widths, blocks, dtype=dtype, ell=ell, lam=None,
+                     sketch_dtype=sketch_dtype, seed=seed, solution="heatcos")
+
+
 # ----------------------------------------------------------------------------------------------
 # named configurations
 # ----------------------------------------------------------------------------------------------
@@ -241,7 +271,11 @@ def config(name: str, seed: int = 0) -> Problem:
     paper3d: the paper's 3D Poisson setup (Section 5.1.1 and the experimental setup of Section 5):
         3-64-64-64-1 tanh (P = 8,641), 10,000 + 1,000 random points, FP64, u* = prod sin(pi x_i),
         adaptive sketch size from 20 in steps of 20 up to 500, at most 20 PCG iterations.
+    paper_heat: the paper's heat equation in 3+1D (Section 5.1.2), 4-64-64-64-1 tanh (P = 8,705), 10,000 +
+        1,000 random points, FP64, the same solver settings as paper3d.
     """
+    if name == "paper_heat":
+        return dataclasses.replace(heat3d_paper(seed=seed), name="paper_heat", ell_max=500, dell=20, maxit=20)
     if name == "paper3d":
         prob = poisson_random(d=3, widths=(3, 64, 64, 64, 1), n_interior=10000, n_boundary=1000, seed=seed,
                               dtype="f64", ell=20, sketch_dtype="f64", solution="sinprod")
