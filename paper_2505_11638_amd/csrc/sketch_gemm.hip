@@ -323,8 +323,11 @@ double predict_us(int64_t M, int64_t N, int64_t nk, int q, double slab_us, int64
 
 int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_t tiles_n, int64_t tiles, int64_t per,
                  int slots, int64_t work_elems) {
+  // the prediction costs up to a few ms of host time for large grids, so it is made once per shape (a
+  // batch of uneven problems brings two shapes per member)
+  constexpr int kCache = 512;
   struct Entry { int64_t M, N, K, work; int BK, slots, ks; };
-  static Entry cache[16];
+  static Entry cache[kCache];
   static int used = 0;
   static std::mutex mu;
   std::lock_guard<std::mutex> lock(mu);
@@ -343,8 +346,8 @@ int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_
       ks = q;
     }
   }
-  cache[used % 16] = Entry{M, N, K, work_elems, BK, slots, ks};
-  if (used < 16) ++used;
+  cache[used % kCache] = Entry{M, N, K, work_elems, BK, slots, ks};
+  if (used < kCache) ++used;
   return ks;
 }
 
