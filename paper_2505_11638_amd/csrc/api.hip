@@ -609,6 +609,14 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
     // R = chol(C[S', S']), F[:, r : r + kept] = C R^{-1}, d -= squared row norms; stop on trace < eps
     NGD_TRY(launch_rp_block(h->rp_Ct, h->ldP, h->rp_idx, h->rp_cnt, h->rp_st, ell_max, h->rp_Rt, h->rp_keep, P, Ft,
                             ldF, h->rp_d, h->rp_part, eps, b, h->rp_trace, s));
+    // rounds after the stop draw nothing and add nothing, but their products with J_w still run: look
+    // at the flag every fourth round, so that at most three such rounds are enqueued
+    if (i % 4 == 3 && i + 1 < rounds) {
+      int64_t* hd = reinterpret_cast<int64_t*>(h->host);
+      NGD_HIP_TRY(hipMemcpyAsync(hd, h->rp_st + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      NGD_HIP_TRY(hipStreamSynchronize(s));
+      if (hd[0] != 0) break;
+    }
   }
   double* hv = reinterpret_cast<double*>(h->host);
   NGD_HIP_TRY(hipMemcpyAsync(hv, h->rp_st, sizeof(int64_t), hipMemcpyDeviceToHost, s));
