@@ -157,11 +157,13 @@ __global__ void rp_gather_f_kernel(const double* __restrict__ Ft, int64_t ldF, c
   W[(int64_t)m * ldw + k] = s >= 0 ? Ft[k * ldF + s] : 0.0;
 }
 
-// One workgroup: the pivot block C[S', S'] (from the rows of C^T at the pivots), its Cholesky
-// factor R (C[S',S'] = R^T R) column by column; a pivot that is not safely positive (<= 1e-13 of the
-// block's largest diagonal entry: a direction the earlier columns already hold) is dropped together
-// with its column. Writes R^T rows of the kept pivots, packed, to Rt (kRpMaxBlock x kRpMaxBlock) and
-// their count to st[2] (capped so that r + kept <= cap).
+// One wave: the pivot block C[S', S'] (from the rows of C^T at the pivots), its Cholesky factor
+// (C[S',S'] = R^T R) column by column, the lanes sharing each column's scaling and the rank-1 update
+// of the trailing block (every entry is updated with the same operands in the same order as a
+// sequential elimination). A pivot that is not safely positive (<= 1e-13 of the block's largest
+// diagonal entry: a direction the earlier columns already hold) is dropped together with its column.
+// Writes the lower factor of the kept pivots, packed, to Rt (kRpMaxBlock x kRpMaxBlock) and their
+// count to st[2] (capped so that r + kept <= cap).
 __global__ __launch_bounds__(64) void rp_block_chol_kernel(const double* __restrict__ Ct, int64_t ldc,
                                                            const int64_t* __restrict__ idx,
                                                            const int* __restrict__ count, int64_t* __restrict__ st,
@@ -176,27 +178,31 @@ __global__ __launch_bounds__(64) void rp_block_chol_kernel(const double* __restr
     A[m][n] = Ct[(int64_t)m * ldc + idx[n]];
   }
   __syncthreads();
-  if (t == 0) {
-    double dmax = 0.0;
-    for (int m = 0; m < c; ++m) dmax = fmax(dmax, A[m][m]);
-    const int64_t r = st[0];
-    int kept = 0;
-    // right-looking: column j's pivot, scaled column, rank-1 update of the rest (symmetric, lower)
-    for (int j = 0; j < c; ++j) {
-      const double pj = A[j][j];
-      keep[j] = 0;
-      if (st[1] || !(pj > 1e-13 * dmax) || r + kept >= cap) continue;
-      const double rj = sqrt(pj);
-      A[j][j] = rj;
-      for (int m = j + 1; m < c; ++m) A[m][j] /= rj;
-      for (int m = j + 1; m < c; ++m)
-        for (int n = j + 1; n <= m; ++n) A[m][n] -= A[m][j] * A[n][j];
-      keep[j] = 1;
-      ++kept;
+  double dmax = 0.0;
+  for (int m = 0; m < c; ++m) dmax = fmax(dmax, A[m][m]);
+  const int64_t r = st[0];
+  const bool done = st[1] != 0;
+  int kept = 0;
+  for (int j = 0; j < c; ++j) {
+    const double pj = A[j][j];
+    const bool ok = !done && pj > 1e-13 * dmax && r + kept < cap;
+    if (t == 0) keep[j] = ok ? 1 : 0;
+    if (!ok) continue;  // uniform: every lane sees the same pivot
+    const double rj = sqrt(pj);
+    __syncthreads();
+    if (t == 0) A[j][j] = rj;
+    for (int m = j + 1 + t; m < c; m += blockDim.x) A[m][j] /= rj;
+    __syncthreads();
+    const int w = c - j - 1;
+    for (int e = t; e < w * w; e += blockDim.x) {
+      const int m = j + 1 + e / w, n = j + 1 + e % w;
+      if (n <= m) A[m][n] -= A[m][j] * A[n][j];
     }
-    st[2] = kept;
+    __syncthreads();
+    ++kept;
   }
   __syncthreads();
+  if (t == 0) st[2] = kept;
   // packed lower factor of the kept pivots: Rt[a][b'] = L(kept a, kept b'), L = R^T
   if (t == 0) {
     int a = 0;
