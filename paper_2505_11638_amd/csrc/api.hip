@@ -71,7 +71,8 @@ struct ngd_problem {
   double* Ev;        // ell x ell eigenvectors (rows)
   double* F;         // ell x ell
   double* evals;     // ell
-  double* gemm_work; // split-K partials of the ell x ell Gram products (8 ell^2)
+  double* gemm_work; // split-K partials of the ell x ell Gram products
+  int64_t gemm_work_elems;  // 32 max_ell^2: room for 16 slices, enough to fill the chip with the Gram tiles
   unsigned* cholsync;  // the Cholesky's row-block flags (2 x 64) and error word
   unsigned chol_epoch = 0;
   void* eigw;        // eig workspace
@@ -334,7 +335,8 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({(void**)&h->Ev, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->F, sizeof(double) * (size_t)L * L});
   plan.push_back({(void**)&h->evals, sizeof(double) * (size_t)L});
-  plan.push_back({(void**)&h->gemm_work, sizeof(double) * 8 * (size_t)L * L});
+  h->gemm_work_elems = 32 * (int64_t)L * L;
+  plan.push_back({(void**)&h->gemm_work, sizeof(double) * (size_t)h->gemm_work_elems});
   plan.push_back({(void**)&h->cholsync, sizeof(unsigned) * 256});
   plan.push_back({&h->eigw, eig_workspace_bytes((int)L)});
   plan.push_back({&h->trial, (size_t)kTrials * ldP * e});
@@ -597,7 +599,7 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
     NGD_TRY(launch_gather_cols(T, op->J, op->ldJ, N, h->rp_idx, b, h->rp_Jcols, b, s));
     // (a b x P output over K = N: split K through the core's GEMM workspace, idle here)
     GemmArgs g1{b, P, N, h->rp_Jcols, b, false, op->J, op->ldJ, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64, 1.0,
-                0.0, h->gemm_work, 8 * (int64_t)h->max_ell * h->max_ell};
+                0.0, h->gemm_work, h->gemm_work_elems};
     NGD_TRY(launch_gemm(g1, s));
     const int64_t kmax = std::min<int64_t>(i * b, ell_max);
     if (kmax > 0) {
@@ -643,7 +645,7 @@ ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int
   // the thin SVD of F through the eigenpairs of F^T F (FP64): U = F V Sigma^{-1}, lam = sigma^2
   NGD_TRY(launch_cast_rows(NGD_F64, Ft, ldF, L, P, T, h->Bt, h->ldP, s));
   GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-              h->gemm_work, 8 * L * L, 1};
+              h->gemm_work, h->gemm_work_elems, 1};
   NGD_TRY(launch_gemm(g5, s));
   NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
   NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
@@ -793,7 +795,7 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
   // Q = Z F (orthonormal basis of range(Z)) with FP64 accumulation
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
     GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-                h->gemm_work, 8 * L * L, 1};
+                h->gemm_work, h->gemm_work_elems, 1};
     NGD_TRY(launch_gemm(g2, s));
     // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
     NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
@@ -823,7 +825,7 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
     GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-                h->gemm_work, 8 * L * L, 1};
+                h->gemm_work, h->gemm_work_elems, 1};
     NGD_TRY(launch_gemm(g5, s));
     // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
     // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
