@@ -237,3 +237,26 @@ def test_rpchol_ngd_steps():
         assert rep.loss_new <= rep.loss and 1 <= rep.rank <= 60
     assert rep.loss_new < 0.5 * L0
     ngd.gp.close()
+
+
+def test_rpcholesky_and_sampling_reject_bad_arguments():
+    """Argument errors are refused on the host before any launch, with a message."""
+    from paper_2505_11638_amd import _lib as L
+    prob, th, gp, theta, J = _setup("poisson2d_f64")
+    d = gp.gramian_diagonal(J)
+    for kw in [dict(block=0), dict(block=65), dict(ell_max=0), dict(ell_max=gp.P + 1), dict(eps=-1.0)]:
+        args = dict(ell_max=10, block=5, eps=0.0)
+        args.update(kw)
+        with pytest.raises(Exception):
+            gp.rpcholesky(J, d, args["ell_max"], args["block"], eps=args["eps"])
+    with pytest.raises(Exception):  # the recompute mode has no stored J_w
+        gp.rpcholesky(Recompute(theta), d, 10, 5)
+    with pytest.raises(Exception):
+        gp.sample_pivots(d, 4097)
+    with pytest.raises(Exception):
+        gp.sample_pivots(d, 4, substream=2 ** 31)
+    assert "substream" in L.load().ngd_last_error().decode()
+    # the handle still works after refused calls
+    Ft, r, _ = gp.rpcholesky(J, d, 10, 5)
+    assert 1 <= r <= 10
+    gp.close()
