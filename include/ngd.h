@@ -164,7 +164,9 @@ typedef struct {
  *                   (dtype F32) or NGD_BF16 (dtype F32; BF16 inputs, FP32 accumulation). The
  *                   ell x ell core always runs in FP64.
  *   U             : device, ell x ldU, dtype, out: row i = eigenvector i (unit norm, orthogonal),
- *                   rows for dropped (zero) eigenvalues are zero. ldU >= P.
+ *                   rows for dropped (zero) eigenvalues are zero. ldU >= P. Columns P..ldU-1 are not
+ *                   written; the preconditioner kernels may read column P when P is odd and discard
+ *                   it, so the caller keeps that padding finite (e.g. zero-initialised).
  *   lam_hat       : device, ell doubles, out: eigenvalues, descending, >= 0.
  *   info          : host, nullable. If non-NULL the call synchronises `stream`, fills it and
  *                   reports a timed-out exchange inside the FP64 core. If NULL the call does not

@@ -202,7 +202,8 @@ class Problem:
         if out is not None and out.lam_hat.numel() == ell:
             U, lam = out.U, out.lam_hat
         else:
-            U = torch.empty((ell, self.ld), dtype=self.tdtype, device=self.device)
+            # zeros: the library writes columns 0..P-1 only, so the padding stays defined
+            U = torch.zeros((ell, self.ld), dtype=self.tdtype, device=self.device)
             lam = torch.empty(ell, dtype=torch.float64, device=self.device)
         info = L.NystromInfo()
         ldO = 0
@@ -326,7 +327,7 @@ class Problem:
     def rpchol_precond(self, Ft: torch.Tensor, rank: int) -> NystromResult:
         """The RPCholesky preconditioner as (U, lam_hat) with a trailing zero pair (ngd_rpchol_precond);
         use it as `precond` of pcg_solve."""
-        U = torch.empty((rank + 1, self.ld), dtype=self.tdtype, device=self.device)
+        U = torch.zeros((rank + 1, self.ld), dtype=self.tdtype, device=self.device)
         lam = torch.empty(rank + 1, dtype=torch.float64, device=self.device)
         L.check(self.lib.ngd_rpchol_precond(self.h, _ptr(Ft), Ft.stride(0), int(rank), _ptr(U), U.stride(0), _ptr(lam),
                                             _stream()), "ngd_rpchol_precond")

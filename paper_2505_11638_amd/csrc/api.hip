@@ -739,11 +739,12 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
   const int et = gt == G_BF16 ? NGD_BF16 : NGD_F32;
   const bool nt = !rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
                   nt_gemm_supported(et, et, gt, P, L, N, h->ldN, h->ldN);
-  // Omega^T in the compute type (BF16: a rounded copy, read at half the bytes)
+  // Omega^T in the compute type (BF16: a rounded copy, read at half the bytes). A column test matrix
+  // has no Omega to read: its Z is a gather.
   const void* om_nt = omega;
   int64_t ld_nt = ldO;
   int om_type = NGD_F32;
-  if ((nt || nt_rec) && gt == G_BF16) {
+  if ((nt || nt_rec) && gt == G_BF16 && cols == nullptr) {
     NGD_TRY(launch_cast_rows(NGD_F32, omega, ldO, L, P, NGD_BF16, h->Ob, h->ldP, s));
     om_nt = h->Ob;
     ld_nt = h->ldP;

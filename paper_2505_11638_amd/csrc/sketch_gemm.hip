@@ -329,6 +329,7 @@ int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_
   struct Entry { int64_t M, N, K, work; int BK, slots, ks; };
   static Entry cache[kCache];
   static int used = 0;
+  static int next = 0;  // round-robin slot for a new shape once the table is full
   static std::mutex mu;
   std::lock_guard<std::mutex> lock(mu);
   for (int i = 0; i < used; ++i)
@@ -346,8 +347,12 @@ int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_
       ks = q;
     }
   }
-  cache[used % kCache] = Entry{M, N, K, work_elems, BK, slots, ks};
-  if (used < kCache) ++used;
+  if (used < kCache) {
+    cache[used++] = Entry{M, N, K, work_elems, BK, slots, ks};
+  } else {
+    cache[next] = Entry{M, N, K, work_elems, BK, slots, ks};
+    next = (next + 1) % kCache;
+  }
   return ks;
 }
 
@@ -362,12 +367,17 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
   // split K by the count of slices with the shortest predicted time (kept per shape)
   int ks = 1;
   if (work != nullptr) {
-    static int slots = 0;
-    if (slots == 0) {
+    // two resident workgroups per compute unit (initialised once, thread-safe)
+    static const int slots = [] {
       int dev = 0, cus = 0;
-      NGD_HIP_TRY(hipGetDevice(&dev));
-      NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      slots = 2 * (cus > 0 ? cus : 1);
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+      return 2 * (cus > 0 ? cus : 1);
+    }();
+    if (slots == 0) {
+      set_error("hipDeviceGetAttribute (compute unit count) failed");
+      return NGD_ERR_HIP;
     }
     ks = choose_split(M, N, K, BK, sizeof(E) == 2 ? kSlabUsBf16 : kSlabUsF32, tn, tiles, per, slots, work_elems);
   }

@@ -134,6 +134,38 @@ def test_nystrom_sketch_columns_matches_alg6(name, unique):
     gp.close()
 
 
+@pytest.mark.parametrize("name", ["poisson2d_f32", "heat_f32"])
+def test_nystrom_sketch_columns_bf16(name):
+    """A BF16 sketch with a sampling test matrix: Z is a gather of J's columns (no Omega is cast or
+    read), only the product B^T = Q^T J runs in BF16. Eigenvalues and G_nys on probe vectors against
+    the shifted Nystrom definition on the same columns, at the BF16 sketch tolerance (2e-2 of lam_1),
+    and the padding columns of U stay zero."""
+    prob, th, gp, theta, J = _setup(name)
+    Jg = J.cpu().numpy().astype(np.float64)[:, :gp.P]
+    cols = sampling.sample_pivots(sampling.gram_diagonal(Jg), prob.ell, seed=4, counter=2, unique=True)
+    ell = cols.size
+    cdev = torch.as_tensor(cols, dtype=torch.int64, device="cuda")
+    res = gp.nystrom_sketch(J, ell, cols=cdev, sketch_dtype="bf16")
+    torch.cuda.synchronize()
+    Uf = res.U.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(Uf)) and np.all(Uf[:, gp.P:] == 0.0)
+    U, lam = Uf[:, :gp.P], res.lam_hat.cpu().numpy()
+    G = Jg.T @ Jg
+    Om = sampling.column_test_matrix(gp.P, cols)
+    Z = Jg @ Om
+    Gs = nystrom.nystrom_shifted(G, Om, 10 * 2.0 ** -52 * np.trace(Z.T @ Z))
+    ls = np.sort(np.linalg.eigvalsh(Gs))[::-1][:ell]
+    assert np.all(np.diff(lam) <= 0) and np.all(lam >= 0)
+    assert np.max(np.abs(lam - ls)) <= 2e-2 * ls[0]
+    X = wl.probe_vectors(gp.P, 5, seed=3)
+    Gg = U.T @ (lam[:, None] * (U @ X))
+    assert np.linalg.norm(Gg - Gs @ X) <= 2e-2 * ls[0] * np.linalg.norm(X)
+    # the FP32 column sketch of the same columns agrees to the same bound
+    r32 = gp.nystrom_sketch(J, ell, cols=cdev, sketch_dtype="f32")
+    assert np.max(np.abs(r32.lam_hat.cpu().numpy() - lam)) <= 2e-2 * ls[0]
+    gp.close()
+
+
 def test_ngd_with_sampling_test_matrix_decreases_loss():
     prob = wl.poisson_random(d=3, widths=(3, 24, 24, 1), n_interior=400, n_boundary=80, seed=5, dtype="f64",
                              ell=30, sketch_dtype="f64")
