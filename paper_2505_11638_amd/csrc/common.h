@@ -87,6 +87,7 @@ void set_error(const std::string& msg);
     hipError_t e_ = (expr);                                                      \
     if (e_ != hipSuccess) {                                                      \
       ::ngd::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      (void)hipGetLastError(); /* leave no stale error for the caller's checks */ \
       return NGD_ERR_HIP;                                                        \
     }                                                                            \
   } while (0)

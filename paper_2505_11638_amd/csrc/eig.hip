@@ -643,6 +643,10 @@ constexpr int kBtWaves = 16;
 constexpr int kBtTiles = 4;  // tiles per wave
 constexpr int kBtMaxN = 16 * kBtWaves * kBtTiles;
 static_assert(kBtMaxN == 64 * kBtWaves, "one reflector column per thread");
+// slots of the per-wave partial W in LDS: half the waves, so that the Y block (kWy x (n + 1)
+// doubles) and the partials fit in 160 KB at n = 1024 with the static arrays
+constexpr int kWpSlots = kBtWaves / 2;
+static_assert(kBtWaves % 2 == 0, "pairwise hand-over of the partial W");
 
 __device__ __forceinline__ bt_d4 mfma64(double a, double b, bt_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(64 * kBtWaves) void form_q_mfma_kernel(const double
   const int nt = (n + 15) / 16;
   const int ldy = nt * 16 + 1;  // odd pitch: the 16 reflector rows fall in distinct LDS banks
   double* Ys = reinterpret_cast<double*>(smem_raw);  // kWy x ldy
-  double* Wp = Ys + (size_t)kWy * ldy;              // kBtWaves x 256 partial W
+  double* Wp = Ys + (size_t)kWy * ldy;              // kWpSlots x 256 partial W
   __shared__ double Ts[kWy * kWy];
   __shared__ double Ws[256];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -711,13 +715,24 @@ __global__ __launch_bounds__(64 * kBtWaves) void form_q_mfma_kernel(const double
         for (int r = 0; r < 4; ++r) w = mfma64(Ys[lr * ldy + 16 * t + 4 * r + lq], acc[i][r], w);
       }
     }
+    // W summed over the waves in a fixed order: the upper half of the waves hands its partials to
+    // the lower half (pairwise), then each entry's kWpSlots partials are added by one thread
+    if (wid >= kWpSlots) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Wp[wid * 256 + (lq + 4 * r) * 16 + lr] = w[r];
+      for (int r = 0; r < 4; ++r) Wp[(wid - kWpSlots) * 256 + (lq + 4 * r) * 16 + lr] = w[r];
+    }
     __syncthreads();
-    // W summed over the waves in a fixed order, each entry by one thread
+    if (wid < kWpSlots) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* slot = Wp + wid * 256 + (lq + 4 * r) * 16 + lr;
+        *slot = w[r] + *slot;
+      }
+    }
+    __syncthreads();
     if (threadIdx.x < 256) {
       double wsum = 0.0;
-      for (int q = 0; q < kBtWaves; ++q) wsum += Wp[q * 256 + threadIdx.x];
+      for (int q = 0; q < kWpSlots; ++q) wsum += Wp[q * 256 + threadIdx.x];
       Ws[threadIdx.x] = wsum;
     }
     __syncthreads();
@@ -895,7 +910,7 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
     const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
     if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, qs, V, tau, n, ws.Tall);
     const int nt = (n + 15) / 16;
-    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kBtWaves * 256);
+    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kWpSlots * 256);
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)form_q_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds));
     hipLaunchKernelGGL(form_q_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, qs, V, ws.Tall, n, ws.Qm);
