@@ -139,6 +139,28 @@ ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void
                               int64_t k, double lambda, void* Y, int64_t ldY, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the conjugate-gradient product of ngd_gramian_matvec
+ * (k = 1, stored J_w) without a problem handle and without any allocation,
+ *   y = (J_w^T J_w + lambda I) v,
+ * computed by the same one-pass kernels, so the result equals ngd_gramian_matvec's for the same
+ * inputs. Its scratch (workgroup partials, FP64 copies of v and y) is a static device array of
+ * NGD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; its address is looked up once
+ * per device on the first call there. Every size the one-pass matvec accepts fits
+ * (ldJ * element size <= 150 KB); a size that would need more is refused with NGD_ERR_INVALID.
+ * Calls that overlap on one GPU (two streams, two threads) share that scratch and race: serialise
+ * them. No workspace word needs clearing between calls.
+ *   dtype  : NGD_F64 or NGD_F32 (of J, v and y).
+ *   J      : device, n_rows x ldJ, dtype, row-major, 16-byte aligned; ldJ >= n_params, ldJ a
+ *            multiple of 16 bytes / element size.
+ *   v, y   : device, n_params, dtype; y is written, must not alias v or J. lambda >= 0.
+ */
+#define NGD_NOALLOC_SCRATCH_BYTES (40 * 1024 * 1024)
+ngd_status ngd_gramian_matvec_noalloc(int32_t dtype, const void* J, int64_t ldJ, int64_t n_rows,
+                                      int64_t n_params, const void* v, double lambda, void* y,
+                                      void* stream);
+
+/*
  * Counter-based standard normal test matrix (Philox4x32-10 of Salmon et al. SC'11 with Box-Muller):
  * row j of `omega` (j < ell) is column j of the P x ell matrix Omega of eq. nystrom_approx.
  *   omega : device, ell x ld, dtype, out. ld >= P.

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libngd.so")
 NGD_OK, NGD_ERR_INVALID, NGD_ERR_OOM, NGD_ERR_NOT_PD, NGD_ERR_BREAKDOWN, NGD_ERR_NOT_CONVERGED, NGD_ERR_HIP = range(7)
 NGD_F64, NGD_F32, NGD_BF16 = 0, 1, 2
 NGD_PDE_POISSON, NGD_PDE_HEAT = 0, 1
+NGD_NOALLOC_SCRATCH_BYTES = 40 * 1024 * 1024
 
 STATUS_NAMES = {0: "NGD_OK", 1: "NGD_ERR_INVALID", 2: "NGD_ERR_OOM", 3: "NGD_ERR_NOT_PD", 4: "NGD_ERR_BREAKDOWN",
                 5: "NGD_ERR_NOT_CONVERGED", 6: "NGD_ERR_HIP"}
@@ -50,6 +51,8 @@ SIGNATURES = {
                                         C.c_void_p, C.c_void_p]),
     "ngd_gramian_matvec": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int64, C.c_int64, C.c_double,
                                      C.c_void_p, C.c_int64, C.c_void_p]),
+    "ngd_gramian_matvec_noalloc": (C.c_int, [C.c_int32, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                             C.c_double, C.c_void_p, C.c_void_p]),
     "ngd_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
                           C.c_void_p]),
     "ngd_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
