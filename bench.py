@@ -49,8 +49,9 @@ WORKLOADS["paper_heat"] = ("the paper's heat equation in 3+1D: 4-64-64-64-1 tanh
                             "solver settings; relative H1 error (space-time gradient) on 100,000 random points")
 # The paper's Nystrom NGD on this problem: 66.8 s to its plateau error over at most 1,000 iterations on
 # one RTX 4090 in FP64, so at most 15.0 NGD steps/s (a derived upper bound on its rate).
-PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1}
+PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1, "direct": 317.7}
 PAPER3D_BASELINE_SPS = {k: 1000.0 / v for k, v in PAPER3D_BASELINE_S.items()}
+_VARIANT_NAME = {"rpchol": "RPCholNGD", "direct": "NGD full (direct Cholesky)"}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
@@ -65,9 +66,11 @@ def bench_paper(a):
     prob = wl.config(a.config, seed=a.seed)
     theta0 = wl.glorot_theta(prob.widths, a.seed)
     P, N = prob.n_params, prob.n_rows
-    variant = "rpchol" if a.solver == "rpchol" else a.test_matrix
+    variant = a.solver if a.solver in ("rpchol", "direct") else a.test_matrix
     if a.solver == "rpchol":  # RPCholNGD (Alg. 5): block size 20, rank up to 500
         ngd = NGD(prob, theta0, solver="rpchol", rtol=1e-6, seed=a.seed, ell_max=prob.ell_max)
+    elif a.solver == "direct":  # NGD full (Alg. 2): explicit FP64 Gramian and its Cholesky factor
+        ngd = NGD(prob, theta0, solver="direct", seed=a.seed)
     else:
         ngd = NGD(prob, theta0, solver="nystrom", rtol=1e-6, seed=a.seed, test_matrix=a.test_matrix)
     gp = ngd.gp
@@ -95,7 +98,7 @@ def bench_paper(a):
         "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": sps / PAPER3D_BASELINE_SPS[variant] if a.config == "paper3d" else None,
         "baseline": None if a.config != "paper3d" else {"value": PAPER3D_BASELINE_SPS[variant], "unit": "NGD steps/s",
-                     "kind": f"the paper's {'RPCholNGD' if variant == 'rpchol' else 'Nystrom NGD (' + variant + ' test matrix)'}"
+                     "kind": f"the paper's {_VARIANT_NAME.get(variant, 'Nystrom NGD (' + variant + ' test matrix)')}"
                              f" on this problem, RTX 4090, FP64: {PAPER3D_BASELINE_S[variant]} s to its plateau over "
                              "at most 1,000 iterations (an upper bound on its rate)"},
         "dtype": "f64", "data": "synthetic",
@@ -236,8 +239,8 @@ def main(argv=None):
     ap.add_argument("--no-cg", action="store_true", help="skip the plain-CG comparison loop")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="further Nystrom steps, after the timed ones, with every phase timer on")
-    ap.add_argument("--solver", default="nystrom", choices=["nystrom", "rpchol"],
-                    help="paper3d: Nystrom NGD or RPCholNGD")
+    ap.add_argument("--solver", default="nystrom", choices=["nystrom", "rpchol", "direct"],
+                    help="paper3d: Nystrom NGD, RPCholNGD or NGD full")
     ap.add_argument("--test-matrix", default="gaussian", choices=["gaussian", "sampling"],
                     help="paper3d: Gaussian test matrix or identity columns sampled proportionally to diag(G)")
     ap.add_argument("--calibrate-copy", action="store_true",

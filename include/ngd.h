@@ -237,6 +237,20 @@ ngd_status ngd_sample_pivots(ngd_problem* h, const double* weights, int64_t n_sa
                              void* stream);
 
 /*
+ * NGD with the full Gramian (Alg. 2; Section 4.1.1, "Computing the full Gramian"): the direction
+ * d = (J_w^T J_w + lambda I)^{-1} g by forming G = J_w^T J_w explicitly in FP64 (the tiles on and
+ * below the diagonal, O(N P^2) on the matrix cores), the Cholesky factor G + lambda I = L L^T
+ * (right-looking, panels of 128 columns) and the substitutions L y = g, L^T d = y.
+ *   g : device, P doubles. d : device, P doubles, out (may alias g).
+ *   lambda > 0. Stored J_w, or the recompute mode (op->J == NULL: G summed over row blocks of J_w).
+ * The handle allocates P x ngd_recommended_ld doubles for G on the first call and keeps them
+ * (NGD_ERR_OOM if that fails). Synchronises `stream`; a non-positive pivot (G + lambda I not
+ * numerically positive definite) returns NGD_ERR_NOT_PD, d then undefined.
+ */
+ngd_status ngd_direct_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda, double* d,
+                            void* stream);
+
+/*
  * Block RPCholesky of G = J_w^T J_w (Section 4.2.2; the block algorithm of the appendix): G ~ F F^T
  * with F (P x r) built a block of pivots at a time. Round i (i < ceil(ell_max / block)) draws `block`
  * pivots ~ d (ngd_sample_pivots with substream i, sorted, repeats dropped), forms the residual
@@ -315,10 +329,37 @@ ngd_status ngd_pcg_solve_damped(ngd_problem* h, const ngd_operator* op, const do
 /*
  * Largest-eigenvalue estimate of J_w^T J_w by the power method (Section 4.3: 2-4 iterations):
  * v <- G v / ||G v||, returning the Rayleigh quotient v^T G v of the last normalised iterate.
- *   v0 : device, P doubles (nonzero start vector; not modified). lam1 : host, out. Synchronises.
+ *   v0 : device, P doubles (nonzero start vector; not modified). lam1 : host, out.
+ *   lam1_dev : device double, nullable, out: the same estimate, for ngd_damping. Synchronises.
  */
 ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const double* v0, int32_t iters,
-                                double* lam1, void* stream);
+                                double* lam1, double* lam1_dev, void* stream);
+
+/*
+ * The damping rule of Section 4.3 (the experimental setup of Section 5) on the device:
+ * mu = max(c_lam * lam1, c_loss * loss^2), with c_lam = gamma * eps (gamma = 10, eps the unit
+ * roundoff of the working precision) and c_loss = 1e-4 in the paper's runs.
+ *   lam1 : device double (lam_hat[0] of a sketch, or lam1_dev of ngd_power_lambda_max).
+ *   loss : device double, nullable (then 0): the loss 1/2 ||r_w||^2 of ngd_residual_jacobian.
+ *   mu   : device double, out. mu_host : host double, nullable: when given, the call synchronises
+ *          and stores mu there too; otherwise it is asynchronous.
+ * c_lam, c_loss finite and >= 0.
+ */
+ngd_status ngd_damping(ngd_problem* h, const double* lam1, const double* loss, double c_lam, double c_loss,
+                       double* mu, double* mu_host, void* stream);
+
+/*
+ * Alg. 4's update of the sketch size (Section 4.3) from one step's eigenvalue estimates:
+ * ell + dell while lam_hat[ell - 1] > 10 mu; otherwise the first 1-based index i with
+ * lam_hat[i] < 10 mu plus `offset` (the text allows 1 or 2); ell if no estimate lies strictly below
+ * (lam_hat[ell - 1] = 10 mu exactly); never above min(ell_max, P).
+ *   lam_hat : device, ell doubles, descending (as written by ngd_nystrom_sketch).
+ *   mu      : the step's damping (e.g. lambda_used of ngd_pcg_solve_damped, or mu_host of
+ *             ngd_damping). next_ell : host, out. Synchronises.
+ * ell >= 1, dell >= 0, offset >= 0, ell_max >= 1, mu >= 0.
+ */
+ngd_status ngd_next_rank(ngd_problem* h, const double* lam_hat, int64_t ell, double mu, int64_t dell,
+                         int64_t offset, int64_t ell_max, int64_t* next_ell, void* stream);
 
 /*
  * Armijo backtracking along theta - alpha d (Alg. 1, Linesearch; Section 4.4): alpha = 1, 1/2, ...

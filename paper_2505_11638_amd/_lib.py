@@ -67,7 +67,11 @@ SIGNATURES = {
                                        C.c_void_p, C.POINTER(Precond), C.c_double, C.c_int64, C.c_void_p,
                                        C.POINTER(PcgInfo), C.POINTER(C.c_double), C.c_void_p]),
     "ngd_power_lambda_max": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int32,
-                                       C.POINTER(C.c_double), C.c_void_p]),
+                                       C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "ngd_damping": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                              C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_next_rank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int64, C.c_int64, C.c_int64,
+                                C.POINTER(C.c_int64), C.c_void_p]),
     "ngd_line_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                   C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "ngd_nystrom_sketch_columns": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_int64, C.c_void_p, C.c_int32,
@@ -75,6 +79,7 @@ SIGNATURES = {
     "ngd_gramian_diagonal": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_void_p]),
     "ngd_sample_pivots": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ngd_direct_solve": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "ngd_rpcholesky": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_int64, C.c_int32, C.c_uint64,
                                  C.c_uint64, C.c_double, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_double), C.c_void_p]),

@@ -260,12 +260,42 @@ class Problem:
         return PcgResult(d, int(info.iters), float(info.rel_res), bool(info.converged), bool(info.breakdown), st,
                          mu)
 
-    def power_lambda_max(self, J: torch.Tensor, v0: torch.Tensor, iters: int = 4) -> float:
+    def direct_solve(self, J, g: torch.Tensor, lam: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """ngd_direct_solve (Alg. 2): d = (J_w^T J_w + lam I)^{-1} g through the explicit FP64 Gramian and
+        its Cholesky factor; synchronises."""
+        _need(g, torch.float64, "g")
+        d = torch.empty(self.P, dtype=torch.float64, device=self.device) if out is None else out
+        L.check(self.lib.ngd_direct_solve(self.h, C.byref(self._op(J)), _ptr(g), float(lam), _ptr(d), _stream()),
+                "ngd_direct_solve")
+        return d
+
+    def power_lambda_max(self, J: torch.Tensor, v0: torch.Tensor, iters: int = 4,
+                         out: Optional[torch.Tensor] = None) -> float:
+        """ngd_power_lambda_max: the estimate on the host; also into `out` (a device double) when given."""
         _need(v0, torch.float64, "v0")
-        out = C.c_double()
-        L.check(self.lib.ngd_power_lambda_max(self.h, C.byref(self._op(J)), _ptr(v0), iters, C.byref(out),
-                                              _stream()), "ngd_power_lambda_max")
-        return out.value
+        res = C.c_double()
+        L.check(self.lib.ngd_power_lambda_max(self.h, C.byref(self._op(J)), _ptr(v0), iters, C.byref(res),
+                                              _ptr(out), _stream()), "ngd_power_lambda_max")
+        return res.value
+
+    def damping(self, lam1: torch.Tensor, loss: Optional[torch.Tensor], c_lam: float, c_loss: float,
+                out: Optional[torch.Tensor] = None, host: bool = True):
+        """ngd_damping (the rule of Section 4.3) on device doubles: returns (mu device tensor, mu on the host
+        or None when host=False)."""
+        _need(lam1, torch.float64, "lam1")
+        mu = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        mh = C.c_double()
+        L.check(self.lib.ngd_damping(self.h, _ptr(lam1), _ptr(loss), float(c_lam), float(c_loss), _ptr(mu),
+                                     C.byref(mh) if host else None, _stream()), "ngd_damping")
+        return mu, (mh.value if host else None)
+
+    def next_rank(self, lam_hat: torch.Tensor, ell: int, mu: float, dell: int, offset: int, ell_max: int) -> int:
+        """ngd_next_rank: Alg. 4's next sketch size from lam_hat[:ell] and the step's damping mu."""
+        _need(lam_hat, torch.float64, "lam_hat")
+        out = C.c_int64()
+        L.check(self.lib.ngd_next_rank(self.h, _ptr(lam_hat), int(ell), float(mu), int(dell), int(offset),
+                                       int(ell_max), C.byref(out), _stream()), "ngd_next_rank")
+        return int(out.value)
 
     def timing(self, enable: bool, only=None):
         """Turn the kernel timers on (all, or only the named ones) or off; resets the counters."""

@@ -43,6 +43,11 @@ struct ngd_problem {
   int64_t *rp_idx, *rp_st;
   int *rp_cnt, *rp_keep;
   void* rp_Jcols;
+  // full-Gramian solve workspace (allocated on first use): G / its factor (P x ldP), the panels'
+  // inverse diagonal blocks, the panel staging rows, substitution partials, y, the pivot word
+  void* dr_blob = nullptr;
+  double *dr_G, *dr_Linv, *dr_stage, *dr_part, *dr_y;
+  int* dr_info;
   double* grad_work; // gradient_chunks(N) x P
   double* vtmp[4];   // P-vectors (FP64)
   double* scal;      // small scalars / dot workspace (128 doubles)
@@ -401,6 +406,7 @@ ngd_status ngd_problem_destroy(ngd_problem* h) {
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->Jc) (void)hipFree(h->Jc);
   if (h->rp_blob) (void)hipFree(h->rp_blob);
+  if (h->dr_blob) (void)hipFree(h->dr_blob);
   (void)hipFree(h->base);
   (void)hipHostFree(h->host);
   delete h;
@@ -573,6 +579,72 @@ ngd_status ngd_gramian_diagonal(ngd_problem* h, const ngd_operator* op, double* 
 }
 
 ngd_status rp_ensure(ngd_problem* h);
+
+namespace {
+
+ngd_status dr_ensure(ngd_problem* h) {
+  if (h->dr_blob != nullptr) return NGD_OK;
+  const size_t P = (size_t)h->P, ldP = (size_t)h->ldP;
+  std::vector<std::pair<void**, size_t>> plan = {{(void**)&h->dr_G, 8 * P * ldP},
+                                                 {(void**)&h->dr_Linv, direct_panel_inverse_bytes(h->P)},
+                                                 {(void**)&h->dr_stage, direct_stage_bytes(h->P)},
+                                                 {(void**)&h->dr_part, direct_part_bytes(h->P)},
+                                                 {(void**)&h->dr_y, 8 * ldP},
+                                                 {(void**)&h->dr_info, 256}};
+  size_t total = 0;
+  for (auto& e : plan) total += align_up(e.second, 256);
+  if (hipMalloc(&h->dr_blob, total) != hipSuccess) {
+    (void)hipGetLastError();
+    h->dr_blob = nullptr;
+    set_error("hipMalloc of the full-Gramian workspace failed (" + std::to_string(total) + " bytes)");
+    return NGD_ERR_OOM;
+  }
+  char* q = static_cast<char*>(h->dr_blob);
+  for (auto& e : plan) {
+    *e.first = q;
+    q += align_up(e.second, 256);
+  }
+  return NGD_OK;
+}
+
+}  // namespace
+
+// NGD full (Alg. 2): G = J_w^T J_w (FP64, lower tiles), G + lambda I = L L^T, d = L^{-T} L^{-1} g.
+ngd_status ngd_direct_solve(ngd_problem* h, const ngd_operator* op, const double* g, double lambda, double* d,
+                            void* stream) {
+  NGD_CHECK(h != nullptr && g != nullptr && d != nullptr, "NULL argument");
+  NGD_TRY(check_op(h, op));
+  NGD_CHECK(lambda > 0.0 && std::isfinite(lambda), "lambda must be > 0");
+  NGD_TRY(dr_ensure(h));
+  hipStream_t s = S(stream);
+  const int64_t P = h->P, N = h->N, ldG = h->ldP;
+  const int T = h->dtype;
+  if (op->J != nullptr) {
+    GemmArgs gg{P, P, N, op->J, op->ldJ, false, op->J, op->ldJ, false, h->dr_G, ldG, T, T, NGD_F64, G_F64, 1.0, 0.0,
+                nullptr, 0, 2};
+    NGD_TRY(launch_gemm(gg, s));
+  } else {  // recompute mode: the Gramian summed over row blocks of J_w formed from theta
+    NGD_TRY(jc_ensure(h));
+    for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
+      const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);
+      NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+      GemmArgs gg{P, P, rows, h->Jc, h->ldP, false, h->Jc, h->ldP, false, h->dr_G, ldG, T, T, NGD_F64, G_F64, 1.0,
+                  r0 == 0 ? 0.0 : 1.0, nullptr, 0, 2};
+      NGD_TRY(launch_gemm(gg, s));
+    }
+  }
+  NGD_TRY(launch_add_diag(h->dr_G, ldG, P, lambda, s));
+  NGD_TRY(launch_blocked_cholesky(h->dr_G, ldG, P, h->dr_Linv, h->dr_stage, h->dr_info, s));
+  NGD_TRY(launch_cholesky_solve(h->dr_G, ldG, P, h->dr_Linv, g, h->dr_y, h->dr_part, d, s));
+  int* hv = reinterpret_cast<int*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, h->dr_info, sizeof(int), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  if (hv[0] != 0) {
+    set_error("Cholesky factorisation of G + lambda I met a non-positive pivot at index " + std::to_string(hv[0] - 1));
+    return NGD_ERR_NOT_PD;
+  }
+  return NGD_OK;
+}
 
 ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* diag, int64_t ell_max, int32_t block,
                           uint64_t seed, uint64_t counter, double eps, double* Ft, int64_t ldF, int64_t* rank,
@@ -999,7 +1071,7 @@ ngd_status ngd_pcg_solve_damped(ngd_problem* h, const ngd_operator* op, const do
 }
 
 ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const double* v0, int32_t iters, double* lam1,
-                                void* stream) {
+                                double* lam1_dev, void* stream) {
   NGD_CHECK(h != nullptr && v0 != nullptr && lam1 != nullptr, "NULL argument");
   NGD_TRY(check_op(h, op));
   NGD_CHECK(iters >= 1, "iters must be >= 1");
@@ -1016,10 +1088,42 @@ ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const do
     NGD_TRY(launch_dot(w, w, P, sc + 8, sc + 1, s));
     NGD_TRY(launch_scale_rsqrt(w, sc + 1, P, v, s));
   }
+  if (lam1_dev != nullptr) NGD_HIP_TRY(hipMemcpyAsync(lam1_dev, sc, sizeof(double), hipMemcpyDeviceToDevice, s));
   double* hv = reinterpret_cast<double*>(h->host);
   NGD_HIP_TRY(hipMemcpyAsync(hv, sc, sizeof(double), hipMemcpyDeviceToHost, s));
   NGD_HIP_TRY(hipStreamSynchronize(s));
   *lam1 = hv[0];
+  return NGD_OK;
+}
+
+ngd_status ngd_damping(ngd_problem* h, const double* lam1, const double* loss, double c_lam, double c_loss,
+                       double* mu, double* mu_host, void* stream) {
+  NGD_CHECK(h != nullptr && lam1 != nullptr && mu != nullptr, "NULL argument");
+  NGD_CHECK(c_lam >= 0.0 && c_loss >= 0.0 && std::isfinite(c_lam) && std::isfinite(c_loss),
+            "c_lam and c_loss must be finite and >= 0");
+  hipStream_t s = S(stream);
+  NGD_TRY(launch_damping1(lam1, loss, c_lam, c_loss, mu, s));
+  if (mu_host != nullptr) {
+    double* hv = reinterpret_cast<double*>(h->host);
+    NGD_HIP_TRY(hipMemcpyAsync(hv, mu, sizeof(double), hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    *mu_host = hv[0];
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_next_rank(ngd_problem* h, const double* lam_hat, int64_t ell, double mu, int64_t dell,
+                         int64_t offset, int64_t ell_max, int64_t* next_ell, void* stream) {
+  NGD_CHECK(h != nullptr && lam_hat != nullptr && next_ell != nullptr, "NULL argument");
+  NGD_CHECK(ell >= 1 && dell >= 0 && offset >= 0 && ell_max >= 1, "ell >= 1, dell >= 0, offset >= 0, ell_max >= 1");
+  NGD_CHECK(mu >= 0.0 && std::isfinite(mu), "mu must be finite and >= 0");
+  hipStream_t s = S(stream);
+  int64_t* slot = reinterpret_cast<int64_t*>(h->scal + 250);
+  NGD_TRY(launch_next_rank(lam_hat, ell, mu, dell, offset, std::min<int64_t>(ell_max, h->P), slot, s));
+  int64_t* hv = reinterpret_cast<int64_t*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, slot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  *next_ell = hv[0];
   return NGD_OK;
 }
 

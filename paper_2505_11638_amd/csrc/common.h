@@ -284,6 +284,14 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
 ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
                               double* out, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
+// the damping rule of Section 4.3 for n problems (pointer tables in device memory), and Alg. 4's
+// sketch-size update (out: device int64)
+ngd_status launch_damping1(const double* lam1, const double* loss, double c_lam, double c_loss, double* mu,
+                           hipStream_t s);
+ngd_status launch_damping(const double* const* lam1, const double* const* loss, double c_lam, double c_loss,
+                          double* const* mu, int n, hipStream_t s);
+ngd_status launch_next_rank(const double* lam, int64_t ell, double mu, int64_t dell, int64_t offset,
+                            int64_t ell_max, int64_t* out, hipStream_t s);
 
 // pivots.hip: out (+)= column sums of squares of J (N x P, ldJ) through `work` (work_elems doubles);
 // ns samples of indices in [0, P) with probability proportional to max(w, 0) (Philox substream q;
@@ -389,6 +397,17 @@ ngd_status launch_trsm_q(const double* L, int ell, int z_type, const void* Z, in
 
 // nystrom helpers (misc.hip)
 ngd_status launch_whitening(const double* evals, const double* evec_rows, int ell, double* F, hipStream_t s);
+
+// direct.hip: the full-Gramian solve (Alg. 2): blocked Cholesky of a P x P FP64 matrix and the two
+// substitutions with it.
+size_t direct_panel_inverse_bytes(int64_t P);
+size_t direct_stage_bytes(int64_t P);
+size_t direct_part_bytes(int64_t P);
+ngd_status launch_add_diag(double* A, int64_t ld, int64_t n, double mu, hipStream_t s);
+ngd_status launch_blocked_cholesky(double* A, int64_t ld, int64_t P, double* Linv, double* stage, int* info,
+                                   hipStream_t s);
+ngd_status launch_cholesky_solve(const double* L, int64_t ld, int64_t P, const double* Linv, const double* g,
+                                 double* y, double* part, double* d, hipStream_t s);
 ngd_status launch_add_scaled(int dtype, const void* X, int64_t ldx, double a, void* Y, int64_t ldy, int64_t rows,
                              int64_t cols, hipStream_t s);
 int residual_block_rows(const NetDesc& net, int dtype);

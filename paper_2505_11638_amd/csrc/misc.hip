@@ -86,6 +86,46 @@ __global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n_words) {
   if (i < n_words) p[i] = 0u;
 }
 
+// The damping rule of Section 4.3 for n problems: mu_i = max(c_lam lam1_i, c_loss loss_i^2), with the
+// inputs and the output behind per-problem device pointers (a null loss pointer counts as 0)
+__global__ void damping_kernel(const double* const* __restrict__ lam1, const double* const* __restrict__ loss,
+                               double c_lam, double c_loss, double* const* __restrict__ mu, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double l = loss[i] != nullptr ? *loss[i] : 0.0;
+  *mu[i] = fmax(c_lam * *lam1[i], c_loss * l * l);
+}
+
+__global__ void damping1_kernel(const double* __restrict__ lam1, const double* __restrict__ loss, double c_lam,
+                                double c_loss, double* __restrict__ mu) {
+  const double l = loss != nullptr ? *loss : 0.0;
+  *mu = fmax(c_lam * *lam1, c_loss * l * l);
+}
+
+// Alg. 4's update of the sketch size from the descending eigenvalue estimates lam[0 .. ell) and the
+// damping mu: ell + dell while lam[ell - 1] > 10 mu, else the first (1-based) index with lam_i < 10 mu
+// plus `offset`, else ell (lam_ell = 10 mu exactly); never above ell_max. One wave: the first index
+// below the threshold is the smallest lane hit, reduced over chunks of 64.
+__global__ __launch_bounds__(64) void next_rank_kernel(const double* __restrict__ lam, int64_t ell, double mu,
+                                                       int64_t dell, int64_t offset,
+                                                       int64_t ell_max, int64_t* __restrict__ out) {
+  const double thresh = 10.0 * mu;
+  int64_t next;
+  if (lam[ell - 1] > thresh) {
+    next = ell + dell;
+  } else {
+    int64_t first = ell;
+    for (int64_t c = 0; c < ell && first == ell; c += 64) {
+      const int64_t i = c + threadIdx.x;
+      const bool hit = i < ell && lam[i] < thresh;
+      const unsigned long long m = __ballot(hit);
+      if (m != 0ull) first = c + (int64_t)__builtin_ctzll(m);
+    }
+    next = first < ell ? first + 1 + offset : ell;
+  }
+  if (threadIdx.x == 0) *out = next < ell_max ? next : ell_max;
+}
+
 }  // namespace
 
 ngd_status launch_gaussian_omega(int dtype, uint64_t seed, uint64_t counter, int64_t P, int64_t ell, void* out,
@@ -157,6 +197,28 @@ ngd_status launch_zero(void* p, size_t bytes, hipStream_t s) {
   const int64_t words = (int64_t)(bytes / 4);
   if (words <= 0) return NGD_OK;
   hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, words);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_damping1(const double* lam1, const double* loss, double c_lam, double c_loss, double* mu,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(damping1_kernel, dim3(1), dim3(1), 0, s, lam1, loss, c_lam, c_loss, mu);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_damping(const double* const* lam1, const double* const* loss, double c_lam, double c_loss,
+                          double* const* mu, int n, hipStream_t s) {
+  if (n <= 0) return NGD_OK;
+  hipLaunchKernelGGL(damping_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, lam1, loss, c_lam, c_loss, mu, n);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_next_rank(const double* lam, int64_t ell, double mu, int64_t dell, int64_t offset,
+                            int64_t ell_max, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(next_rank_kernel, dim3(1), dim3(64), 0, s, lam, ell, mu, dell, offset, ell_max, out);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -6,16 +6,21 @@ and the update. Every numerical operation is a libngd call; the host only moves 
 (loss, largest eigenvalue estimate, Armijo decisions).
 
 Damping (Section 4.3 and the experimental setup of Section 5): mu = max(gamma eps lam1_hat, 1e-4 L^2)
-with gamma = 10 and eps the unit roundoff of the working precision, unless a fixed mu is given.
-Plain CG takes lam1_hat from 4 power iterations.
+with gamma = 10 and eps the unit roundoff of the working precision, unless a fixed mu is given; the
+rule runs in the library (ngd_pcg_solve_damped, ngd_damping). Plain CG, RPCholNGD and NGD full take
+lam1_hat from 4 power iterations.
 
 Sketch size: fixed, or adaptive as in Alg. 4 (Section 4.3) when a maximum is given: after each step
-the next size grows by dell while lam_hat_ell > 10 mu, else drops to the first index with
-lam_hat_i < 10 mu plus one, never above ell_max.
+ngd_next_rank gives the next size (grow by dell while lam_hat_ell > 10 mu, else the first index with
+lam_hat_i < 10 mu plus one, never above ell_max).
+
+Solvers: "nystrom" (Alg. 3 with the Nystrom preconditioner of Alg. 4), "cg" (no preconditioner),
+"rpchol" (Alg. 5) and "direct" (NGD full, Alg. 2: the explicit Gramian and its Cholesky factor).
 """
 from __future__ import annotations
 
 import dataclasses
+import types
 from typing import Optional
 
 import numpy as np
@@ -89,11 +94,11 @@ class NGD:
         self.loss_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.lam1_host = torch.empty(1, dtype=torch.float64, pin_memory=True)
         self.loss_np, self.lam1_np = self.loss_host.numpy(), self.lam1_host.numpy()
-        # all of lam_hat when the sketch size adapts (read after the solve's synchronisation)
-        self.lam_host = (torch.empty(self.ell_max, dtype=torch.float64, pin_memory=True)
-                         if self.ell_max is not None and solver == "nystrom" else None)
-        if solver not in ("nystrom", "cg", "rpchol"):
-            raise ValueError("solver must be 'nystrom', 'cg' or 'rpchol'")
+        # device slots of the power method's estimate and of the damping (plain CG, RPCholNGD, NGD full)
+        self.lam1_dev = torch.zeros(1, dtype=torch.float64, device=gp.device)
+        self.mu_dev = torch.zeros(1, dtype=torch.float64, device=gp.device)
+        if solver not in ("nystrom", "cg", "rpchol", "direct"):
+            raise ValueError("solver must be 'nystrom', 'cg', 'rpchol' or 'direct'")
         # per-step device buffers, reused: residuals, gradient, loss and the search direction
         self.bufs = None
         self.pc = None
@@ -119,8 +124,6 @@ class NGD:
                                    want_info=False, out=self.pc, cols=cols)
             self.pc = pc
             self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
-            if self.lam_host is not None:
-                self.lam_host[:ell].copy_(pc.lam_hat[:ell], non_blocking=True)
             if self.lam is not None:
                 out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
                 mu = self.lam
@@ -130,13 +133,17 @@ class NGD:
                 mu = out.mu
             lam1 = float(self.lam1_np[0])
             L0 = float(self.loss_np[0])
-            if self.lam_host is not None:
-                self.ell = self.next_rank(self.lam_host.numpy()[:ell], mu, ell)
+            if self.ell_max is not None:  # Alg. 4's next sketch size, evaluated by the library
+                self.ell = gp.next_rank(pc.lam_hat, ell, mu, self.dell, self.rank_offset, self.ell_max)
         else:
-            # plain CG, or RPCholNGD (Alg. 5): lambda_1 from 4 power iterations, then the damping rule
-            lam1 = gp.power_lambda_max(J, self.v0, 4)
+            # plain CG, RPCholNGD (Alg. 5) or NGD full (Alg. 2): lambda_1 from 4 power iterations, then the
+            # damping rule on the device
+            lam1 = gp.power_lambda_max(J, self.v0, 4, out=self.lam1_dev)
             L0 = float(self.loss_np[0])
-            mu = self.lam if self.lam is not None else max(self.gamma * self.eps * lam1, 1e-4 * L0 ** 2)
+            if self.lam is not None:
+                mu = self.lam
+            else:
+                _, mu = gp.damping(self.lam1_dev, loss, self.gamma * self.eps, 1e-4, out=self.mu_dev)
             pc = None
             if self.solver == "rpchol":
                 # F with G ~ F F^T until the residual trace is below mu p; P = F F^T + mu I
@@ -145,21 +152,16 @@ class NGD:
                                                  counter=self.k, eps=mu * gp.P, Ft=self.Ft)
                 pc = gp.rpchol_precond(self.Ft, rank)
                 self.last_rank = rank
-            out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
+            if self.solver == "direct":
+                d = gp.direct_solve(J, grad, mu, out=self.d)
+                out = types.SimpleNamespace(d=d, iters=0, rel_res=0.0, converged=True)
+            else:
+                out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
         self.k += 1
         rank = ell if self.solver == "nystrom" else (self.last_rank if self.solver == "rpchol" else -1)
         return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)
 
-    def next_rank(self, lam_hat, mu: float, ell: int) -> int:
-        """Alg. 4's update of the sketch size from the descending eigenvalue estimates of this step."""
-        thresh = 10.0 * mu
-        if lam_hat[ell - 1] > thresh:
-            return min(ell + self.dell, self.ell_max)
-        for i in range(ell):
-            if lam_hat[i] < thresh:
-                return min(i + 1 + self.rank_offset, self.ell_max)
-        return min(ell, self.ell_max)
 
 
 class BatchNGD:

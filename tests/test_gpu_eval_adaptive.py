@@ -96,7 +96,7 @@ def test_adaptive_rank_follows_alg4(dtype):
     for _ in range(12):
         rep = ngd.step()
         assert rep.rank == expect
-        lam = ngd.lam_host.numpy()[:rep.rank].copy()
+        lam = ngd.pc.lam_hat.cpu().numpy()[:rep.rank].copy()
         assert np.all(np.diff(lam) <= 0)
         expect = ongd.next_rank(lam, rep.mu, rep.rank, prob.ell_max, prob.dell)
         assert ngd.ell == expect
@@ -133,3 +133,34 @@ def test_heat3d_paper_shape_parity_and_steps():
         assert rep.loss_new <= rep.loss
     assert rep.loss_new < L0
     ngd.gp.close()
+
+
+def test_library_rank_rule_and_damping_match_oracle():
+    """ngd_next_rank (Alg. 4's update) against the oracle's rule on 400 random cases (both branches, the
+    threshold itself, zeros of dropped pairs, the cap), and ngd_damping (Section 4.3) against the
+    rule written out, both branches, with and without a loss."""
+    prob = wl.small_problem(widths=(2, 32, 32, 1), n_interior=61, n_boundary=22, seed=1, ell=24)
+    gp = Problem(prob, dtype="f64", max_ell=24)
+    rng = np.random.default_rng(0)
+    for trial in range(400):
+        ell = int(rng.integers(1, 60))
+        ell_max = int(rng.integers(ell, 120))
+        dell = int(rng.integers(1, 30))
+        off = int(rng.integers(1, 3))
+        lam = np.sort(10.0 ** rng.uniform(-8, 2, ell))[::-1]
+        if trial % 5 == 0:
+            lam[rng.integers(0, ell):] = 0.0  # dropped pairs are reported as zeros
+        mu = float(10.0 ** rng.uniform(-7, 0))
+        if trial % 7 == 0:
+            mu = float(lam[ell - 1]) / 10.0  # on the threshold
+        lam_dev = torch.as_tensor(lam.copy(), dtype=torch.float64, device="cuda")
+        got = gp.next_rank(lam_dev, ell, mu, dell, off, ell_max)
+        assert got == min(ongd.next_rank(lam, mu, ell, ell_max, dell, off), gp.P), (trial, got)
+    for lam1, loss in [(3.0, 1e-2), (3.0, 10.0), (1e-9, None)]:
+        l1 = torch.tensor([lam1], dtype=torch.float64, device="cuda")
+        lt = None if loss is None else torch.tensor([loss], dtype=torch.float64, device="cuda")
+        mu_dev, mu = gp.damping(l1, lt, 10 * 2.0 ** -52, 1e-4)
+        want = max(10 * 2.0 ** -52 * lam1, 1e-4 * (loss or 0.0) ** 2)
+        assert mu == want and mu_dev.item() == want
+    gp.close()
+
