@@ -578,6 +578,64 @@ ngd_status ngd_gramian_diagonal(ngd_problem* h, const ngd_operator* op, double* 
   return NGD_OK;
 }
 
+namespace {
+
+// Eigenpairs of B^T B below this fraction of the largest (by the Gershgorin bound of its tridiagonal
+// form) come out of the first eigendecomposition as zeros: their vectors carry errors of order
+// eps sigma_1 / sigma there.
+constexpr double kDropRel = 1e-11;
+// FP64 problems resolve every pair below kSplitRel lam_1 a second time, from B projected off the
+// pairs above: the projected Gram matrix holds only the small part of the spectrum, so its
+// eigendecomposition is accurate relative to that part instead of to lam_1 (forming B^T B squares
+// sigma; the projection keeps the small singular values accurate to about eps sigma_1 / sigma).
+// Pairs of the second level below kNoiseRel lam_1 are rounding noise of the projection and are
+// returned as zeros.
+constexpr double kSplitRel = 1e-8;
+constexpr double kNoiseRel = 1e-18;
+
+// The thin SVD of B (P x L, given as Bt = B^T, L rows of the working type, ld = ldP; overwritten in
+// the FP64 case) through the eigenpairs of B^T B (Alg. 6, svd(B)): lam_hat = sigma^2 descending and
+// U = B V Sigma^{-1} as rows. Uses the handle's core buffers M, Ev, F, evals, the eigensolver's
+// workspace, vtmp[2] and (FP64) the Omega buffer.
+ngd_status core_svd(ngd_problem* h, void* Bt, int64_t L, void* U, int64_t ldU, double* lam_hat, hipStream_t s) {
+  const int64_t P = h->P, ldP = h->ldP;
+  const int T = h->dtype;
+  GemmArgs g5{L, L, P, Bt, ldP, true, Bt, ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
+              h->gemm_work, h->gemm_work_elems, 1};
+  NGD_TRY(launch_gemm(g5, s));
+  NGD_TRY(launch_sym_eig(h->M, (int)L, kDropRel, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
+  if (T != NGD_F64) {
+    NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
+    GemmArgs g6{L, P, L, h->F, L, false, Bt, ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
+    return launch_gemm(g6, s);
+  }
+  double* lam_t = h->vtmp[2];
+  double* Evt = h->M;  // free: the eigensolver consumed it
+  double* X = static_cast<double*>(h->omega);
+  // the resolved pairs (lam >= kSplitRel lam_1) give their rows of U directly
+  NGD_TRY(launch_split_top(lam_hat, h->Ev, (int)L, kSplitRel, lam_t, Evt, s));
+  NGD_TRY(launch_whitening(lam_t, h->Ev, (int)L, h->F, s));
+  GemmArgs g6{L, P, L, h->F, L, false, Bt, ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
+  NGD_TRY(launch_gemm(g6, s));
+  // B_c^T = (I - V_t V_t^T) B^T: X = V_t^T B^T, then B^T -= V_t X
+  GemmArgs gx{L, P, L, Evt, L, true, Bt, ldP, false, X, ldP, NGD_F64, T, NGD_F64, G_F64, 1.0, 0.0};
+  NGD_TRY(launch_gemm(gx, s));
+  GemmArgs gp{L, P, L, Evt, L, false, X, ldP, false, Bt, ldP, NGD_F64, NGD_F64, T, G_F64, -1.0, 1.0};
+  NGD_TRY(launch_gemm(gp, s));
+  // the small pairs from the eigendecomposition of B_c^T B_c, and their rows of U = B_c y / sqrt(mu)
+  GemmArgs g7{L, L, P, Bt, ldP, true, Bt, ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
+              h->gemm_work, h->gemm_work_elems, 1};
+  NGD_TRY(launch_gemm(g7, s));
+  NGD_TRY(launch_sym_eig(h->M, (int)L, kDropRel, h->evals, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join,
+                         true));
+  NGD_TRY(launch_whitening(h->evals, h->Ev, (int)L, h->F, s));
+  GemmArgs g8{L, P, L, h->F, L, false, Bt, ldP, false, X, ldP, NGD_F64, T, NGD_F64, G_F64, 1.0, 0.0};
+  NGD_TRY(launch_gemm(g8, s));
+  return launch_merge_small(T, lam_t, h->evals, X, ldP, (int)L, P, kNoiseRel, U, ldU, lam_hat, s);
+}
+
+}  // namespace
+
 ngd_status rp_ensure(ngd_problem* h);
 
 namespace {
@@ -716,13 +774,7 @@ ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int
   if (L == 0) return NGD_OK;
   // the thin SVD of F through the eigenpairs of F^T F (FP64): U = F V Sigma^{-1}, lam = sigma^2
   NGD_TRY(launch_cast_rows(NGD_F64, Ft, ldF, L, P, T, h->Bt, h->ldP, s));
-  GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-              h->gemm_work, h->gemm_work_elems, 1};
-  NGD_TRY(launch_gemm(g5, s));
-  NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
-  NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
-  GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
-  NGD_TRY(launch_gemm(g6, s));
+  NGD_TRY(core_svd(h, h->Bt, L, U, ldU, lam_hat, s));
   int* hv = reinterpret_cast<int*>(h->host);
   NGD_HIP_TRY(hipMemcpyAsync(hv, eig_error_flag(h->eigw, (int)L), sizeof(int), hipMemcpyDeviceToHost, s));
   NGD_HIP_TRY(hipStreamSynchronize(s));
@@ -870,8 +922,10 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
     GemmArgs g2{L, L, N, h->Z, L, false, h->Z, L, false, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
                 h->gemm_work, h->gemm_work_elems, 1};
     NGD_TRY(launch_gemm(g2, s));
-    // L L^T = M + nu I with nu = 10 eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64
-    NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 10.0 * 2.220446049250313e-16, 1e-15, h->scal + 200,
+    // L L^T = M + nu I with nu = c eps tr(M) (the shift of Alg. 6), then Q = Z L^{-T} in FP64; c = 1
+    // for FP64 Jacobians (the shift bounds how small an eigenvalue the core resolves), 10 for FP32
+    const double shift_rel = (T == NGD_F64 ? 1.0 : 10.0) * 2.220446049250313e-16;
+    NGD_TRY(launch_shifted_cholesky(h->M, (int)L, shift_rel, 1e-15, h->scal + 200,
                                     reinterpret_cast<int*>(h->scal + 210), h->cholsync, ++h->chol_epoch, s));
     // one launch: Q in FP64 where a product reads it, Q^T in the compute type on the NT path
     return launch_trsm_q(h->M, (int)L, T, h->Z, N, nt ? nullptr : (double*)h->Q, et, nt ? h->Qt : nullptr, h->ldN,
@@ -895,18 +949,9 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
     GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
     return launch_gemm(g4, s);
   }));
-  // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T
-  NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] {
-    GemmArgs g5{L, L, P, h->Bt, h->ldP, true, h->Bt, h->ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-                h->gemm_work, h->gemm_work_elems, 1};
-    NGD_TRY(launch_gemm(g5, s));
-    // eigenvalues below 1e-11 lam_1 are reported as 0: their vectors B v / sigma carry errors of
-    // order eps * sigma_1 / sigma_i, and 1e-11 lies below the FP64 parity tolerance of 1e-10 lam_1
-    NGD_TRY(launch_sym_eig(h->M, (int)L, 1e-11, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
-    NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
-    GemmArgs g6{L, P, L, h->F, L, false, h->Bt, h->ldP, false, U, ldU, NGD_F64, T, T, G_F64, 1.0, 0.0};
-    return launch_gemm(g6, s);
-  }));
+  // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T (FP64
+  // problems: the small pairs a second time, from B projected off the resolved ones)
+  NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] { return core_svd(h, h->Bt, L, U, ldU, lam_hat, s); }));
   // without a summary the call does not synchronise; the next PCG solve with this preconditioner
   // reads the core's error words instead
   h->unchecked_ell = info == nullptr ? L : 0;

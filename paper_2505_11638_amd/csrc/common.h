@@ -266,11 +266,13 @@ ngd_status launch_transpose_cast(int src_type, const void* src, int64_t ld_s, in
 
 // eig.hip: symmetric eigendecomposition of an n x n FP64 matrix (row-major, ld = n), in place.
 // Eigenpairs below drop_rel * ||T|| (Gershgorin bound) are returned as zeros. A is overwritten.
+// keep_err: leave the error word of an earlier call on the same workspace as it is (its flags are
+// cleared either way).
 size_t eig_workspace_bytes(int n);
 // side, fork, join: a second stream and two events for the part that overlaps (side may be NULL)
 ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
                           hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
-                          hipEvent_t join = nullptr);
+                          hipEvent_t join = nullptr, bool keep_err = false);
 const int* eig_error_flag(void* work, int n);
 
 // misc.hip
@@ -286,6 +288,12 @@ ngd_status launch_sketch_info(const double* lam, int L, const double* core, cons
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
 // the damping rule of Section 4.3 for n problems (pointer tables in device memory), and Alg. 4's
 // sketch-size update (out: device int64)
+// the two-level eigendecomposition of the Nystrom core (FP64 problems): split off the pairs that the
+// first level resolves, and merge the ones recomputed from the projected B
+ngd_status launch_split_top(const double* lam, const double* Ev, int L, double tau, double* lam_t, double* Evt,
+                            hipStream_t s);
+ngd_status launch_merge_small(int dtype, const double* lam_t, const double* mu, const void* U2, int64_t ld2, int L,
+                              int64_t P, double floor_rel, void* U, int64_t ldU, double* lam_hat, hipStream_t s);
 ngd_status launch_damping1(const double* lam1, const double* loss, double c_lam, double c_loss, double* mu,
                            hipStream_t s);
 ngd_status launch_damping(const double* const* lam1, const double* const* loss, double c_lam, double c_loss,

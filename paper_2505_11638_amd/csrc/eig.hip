@@ -871,7 +871,7 @@ ngd_status launch_tridiag(const TriArgs& ta, hipStream_t s) {
 size_t eig_workspace_bytes(int n) { return EigWs(nullptr, n).bytes; }
 
 ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
-                               hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+                               hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join, bool keep_err) {
   if (n <= 0) return NGD_OK;
   if (n > kBtMaxN) {
     set_error("symmetric eigensolver: n above 1024");
@@ -890,7 +890,8 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   double* tnorm = ws.tnorm;
   int* err = ws.err;
   {
-    ngd_status st = launch_zero(ws.flags, 1024, s);
+    // the barrier flags, and the error word unless an earlier call's must survive (it lies after them)
+    ngd_status st = launch_zero(ws.flags, keep_err ? sizeof(unsigned) * 248 : 1024, s);
     if (st != NGD_OK) return st;
     st = launch_zero(tau, sizeof(double) * n, s);
     if (st != NGD_OK) return st;

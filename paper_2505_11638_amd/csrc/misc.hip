@@ -1,5 +1,7 @@
 // Small kernels: counter-based Gaussian test matrix, precision casts, trial parameters for the
 // line search, zero fill (a kernel rather than hipMemsetAsync so the work can be graph-captured).
+#include <algorithm>
+
 #include "common.h"
 
 namespace ngd {
@@ -94,6 +96,45 @@ __global__ void damping_kernel(const double* const* __restrict__ lam1, const dou
   if (i >= n) return;
   const double l = loss[i] != nullptr ? *loss[i] : 0.0;
   *mu[i] = fmax(c_lam * *lam1[i], c_loss * l * l);
+}
+
+// The split of the first eigendecomposition of B^T B: pairs with lam >= tau lam_0 (and > 0) are kept
+// as they are (lam_t, and their eigenvector rows in Evt); the others are zeroed in both, to be
+// recomputed from B projected off the kept ones.
+__global__ void split_top_kernel(const double* __restrict__ lam, const double* __restrict__ Ev, int L, double tau,
+                                 double* __restrict__ lam_t, double* __restrict__ Evt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // column
+  const int k = blockIdx.y;                             // pair
+  const bool keep = lam[k] > 0.0 && lam[k] >= tau * lam[0];
+  if (i == 0) lam_t[k] = keep ? lam[k] : 0.0;
+  if (i < L) Evt[(int64_t)k * L + i] = keep ? Ev[(int64_t)k * L + i] : 0.0;
+}
+
+// Rows r.. of U and lam_hat from the second, projected eigendecomposition: r = the number of kept pairs
+// of the first (the leading nonzeros of lam_t); destination row j >= r takes pair j - r of the second
+// (eigenvalue mu, vector row U2) when mu is above the noise floor floor_rel * lam_t[0], else zeros.
+// The value is capped at lam_t[r - 1] so that the order stays descending across the seam (the two
+// differ there by rounding only).
+template <typename T>
+__global__ void merge_small_kernel(const double* __restrict__ lam_t, const double* __restrict__ mu,
+                                   const T* __restrict__ U2, int64_t ld2, int L, int64_t P, double floor_rel,
+                                   T* __restrict__ U, int64_t ldU, double* __restrict__ lam_hat) {
+  __shared__ int r_s;
+  if (threadIdx.x == 0) {
+    int r = 0;
+    while (r < L && lam_t[r] > 0.0) ++r;
+    r_s = r;
+  }
+  __syncthreads();
+  const int r = r_s;
+  const int j = blockIdx.y;
+  if (j < r) return;
+  const int src = j - r;
+  const double m = mu[src];
+  const bool keep = r > 0 && m > 0.0 && m >= floor_rel * lam_t[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) lam_hat[j] = keep ? fmin(m, lam_t[r - 1]) : 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P; c += (int64_t)gridDim.x * blockDim.x)
+    U[(int64_t)j * ldU + c] = keep ? U2[(int64_t)src * ld2 + c] : T(0);
 }
 
 __global__ void damping1_kernel(const double* __restrict__ lam1, const double* __restrict__ loss, double c_lam,
@@ -219,6 +260,29 @@ ngd_status launch_damping(const double* const* lam1, const double* const* loss, 
 ngd_status launch_next_rank(const double* lam, int64_t ell, double mu, int64_t dell, int64_t offset,
                             int64_t ell_max, int64_t* out, hipStream_t s) {
   hipLaunchKernelGGL(next_rank_kernel, dim3(1), dim3(64), 0, s, lam, ell, mu, dell, offset, ell_max, out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_split_top(const double* lam, const double* Ev, int L, double tau, double* lam_t, double* Evt,
+                            hipStream_t s) {
+  if (L <= 0) return NGD_OK;
+  hipLaunchKernelGGL(split_top_kernel, dim3((unsigned)((L + 255) / 256), (unsigned)L), dim3(256), 0, s, lam, Ev, L, tau,
+                     lam_t, Evt);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_merge_small(int dtype, const double* lam_t, const double* mu, const void* U2, int64_t ld2, int L,
+                              int64_t P, double floor_rel, void* U, int64_t ldU, double* lam_hat, hipStream_t s) {
+  if (L <= 0) return NGD_OK;
+  dim3 grid((unsigned)std::min<int64_t>((P + 255) / 256, 64), (unsigned)L);
+  if (dtype == NGD_F64)
+    hipLaunchKernelGGL(merge_small_kernel<double>, grid, dim3(256), 0, s, lam_t, mu, (const double*)U2, ld2, L, P,
+                       floor_rel, (double*)U, ldU, lam_hat);
+  else
+    hipLaunchKernelGGL(merge_small_kernel<float>, grid, dim3(256), 0, s, lam_t, mu, (const float*)U2, ld2, L, P,
+                       floor_rel, (float*)U, ldU, lam_hat);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -160,7 +160,7 @@ def test_library_rank_rule_and_damping_match_oracle():
         l1 = torch.tensor([lam1], dtype=torch.float64, device="cuda")
         lt = None if loss is None else torch.tensor([loss], dtype=torch.float64, device="cuda")
         mu_dev, mu = gp.damping(l1, lt, 10 * 2.0 ** -52, 1e-4)
-        want = max(10 * 2.0 ** -52 * lam1, 1e-4 * (loss or 0.0) ** 2)
+        want = max(10 * 2.0 ** -52 * lam1, 1e-4 * (loss or 0.0) * (loss or 0.0))
         assert mu == want and mu_dev.item() == want
     gp.close()
 

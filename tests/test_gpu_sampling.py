@@ -97,7 +97,8 @@ def test_sample_pivots_unique_and_degenerate():
 @pytest.mark.parametrize("unique", [True, False])
 def test_nystrom_sketch_columns_matches_alg6(name, unique):
     """The sampling test matrix: GPU eigenpairs and G_nys on probe vectors against the Nystrom
-    approximation with the core shift the GPU keeps (nu = 10 eps tr(Omega^T G Omega)), on the distinct
+    approximation with the core shift the GPU keeps (nu = c eps tr(Omega^T G Omega), c = 1 for FP64 and
+    10 for FP32 Jacobians), on the distinct
     sampled columns (repeats leave range(Omega) unchanged; their extra directions come out as ~0
     pairs). Against Alg. 6, which removes its shift, the difference is the shift's effect, amplified by
     the conditioning of G[S, S] (about 1e-10 lam_1 here); it is bounded below as well."""
@@ -115,7 +116,7 @@ def test_nystrom_sketch_columns_matches_alg6(name, unique):
     Om_all = sampling.column_test_matrix(gp.P, cols)
     G = Jg.T @ Jg
     Z = Jg @ Om_all
-    nu = 10 * 2.0 ** -52 * np.trace(Z.T @ Z)
+    nu = (1 if prob.dtype == "f64" else 10) * 2.0 ** -52 * np.trace(Z.T @ Z)  # the core's shift
     Gs = nystrom.nystrom_shifted(G, Om_all, nu)
     ls = np.sort(np.linalg.eigvalsh(Gs))[::-1]
     assert np.all(np.diff(lam) <= 0) and np.all(lam >= 0)
