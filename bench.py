@@ -144,6 +144,11 @@ def bench_batch(a):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n = len(probs)
+    # roofline of the batched one-pass matvec (every member's J_w read once per PCG iteration), timed
+    # with HIP events on the stream it runs on, on the directions of the last solve
+    mv_ms = ngd.batch.matvec_time(20)
+    alg_bytes = sum(p.n_rows * p.n_params * 4 + 2 * p.n_params * 8 for p in probs)
+    achieved = alg_bytes / (mv_ms * 1e-3) / 1e9
     line = {
         "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
         "value": n * a.steps / dt, "unit": "problem NGD steps/s (sum over the batch)", "n_gpus": 1,
@@ -153,10 +158,35 @@ def bench_batch(a):
                    "P": [p.n_params for p in probs], "N": [p.n_rows for p in probs], "ell": [p.ell for p in probs],
                    },
         "nystrom_mean_pcg_iters": float(np.mean(iters)), "nystrom_converged": conv,
+        "roofline": {"bound": "hbm", "kernel": "pcg_batch_rows_kernel (one pass over all 32 J_w)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": mv_ms, "launches": 20},
     }
     ngd.batch.close()
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(probs, thetas, a.seed, max(1, min(a.cpu_steps, 4)))
     print(json.dumps(line), flush=True)
     return 0
+
+
+def cpu_baseline_batch(probs, thetas, seed: int, members: int):
+    """The FP64 NumPy oracle's NGD step on the first `members` problems of the batch (bounded sample)."""
+    import numpy as np
+
+    from oracle import ngd as ongd
+    import workloads as wl
+
+    t0 = time.perf_counter()
+    for i in range(members):
+        p = probs[i]
+        p64 = p.cast(p.dtype)
+        th = thetas[i].astype(np.float32).astype(np.float64)
+        Om = wl.gaussian_omega(p.n_params, p.ell, seed=seed, counter=i)
+        ongd.ngd_step(th, p64, solver="nystrom", Omega=Om, rtol=1e-6, maxit=1000)
+    dt = time.perf_counter() - t0
+    return {"value": members / dt, "unit": "problem NGD steps/s", "cores": _cpu_threads(), "kind": "oracle",
+            "sample": f"one Nystrom-PCG NGD step of each of the first {members} problems of workload c5 (same data, "
+                      f"their own ell, rtol 1e-6) in the FP64 NumPy oracle, {dt:.1f} s"}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pcg_rows_kernel_c2_c3_hbm_traffic.md")

@@ -427,6 +427,40 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
                                double* const* d, ngd_pcg_info* infos, void* stream);
 
 /*
+ * ngd_pcg_solve_damped for every member: as ngd_batch_pcg_solve, with member i's damping from the
+ * rule of Section 4.3 on the device, lambda_i = max(c_lam lam_hat_i[0], c_loss loss_i^2), from its
+ * preconditioner's eigenvalues and its loss (no host round trip between the members' sketches and
+ * the solve). Every member needs a preconditioner. A member's sketch taken without its summary has
+ * its core's error words checked here (NGD_ERR_HIP if one timed out).
+ *   loss        : host array of n device pointers (an entry may be NULL: loss 0), or NULL (all 0).
+ *   lambda_used : host array of n doubles, nullable, out: each member's damping. Synchronises.
+ */
+ngd_status ngd_batch_pcg_solve_damped(ngd_batch* b, const ngd_operator* ops, const double* const* g,
+                                      double c_lam, double c_loss, const double* const* loss,
+                                      const ngd_precond* precs, double rtol, int64_t maxit, double* const* d,
+                                      ngd_pcg_info* infos, double* lambda_used, void* stream);
+
+/*
+ * ngd_nystrom_sketch (Gaussian test matrix, Alg. 6 on each member's J_w) for every member, without a
+ * host round trip: the members run side by side on four streams of the batch (largest ell P (N + ell)
+ * first), forked from and joined back to `stream`. Member i draws Omega from (seed, counter + i 2^32),
+ * so that no two members share test-matrix entries. The summaries are not returned; the core error
+ * words are checked by the next batched or single solve with these preconditioners.
+ *   ops, ells, U, ldU, lam_hat : host arrays of n entries (device pointers as for ngd_nystrom_sketch).
+ * Asynchronous on `stream`.
+ */
+ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const int64_t* ells, uint64_t seed,
+                                    uint64_t counter, int32_t sketch_dtype, void* const* U, const int64_t* ldU,
+                                    double* const* lam_hat, void* stream);
+
+/*
+ * Measurement: the average duration of one batched matvec launch (the PCG iteration's single pass
+ * over every member's J_w) on the directions of the last batched solve, from HIP events around `reps`
+ * launches on `stream` (they rewrite only the solve's scratch directions). Synchronises.
+ */
+ngd_status ngd_batch_matvec_time(ngd_batch* b, int32_t reps, double* avg_ms, void* stream);
+
+/*
  * Kernel timers (measurement support, not part of the method). When enabled, the library records a
  * HIP event pair on the call's stream around every launch of the timed kernels and accumulates the
  * elapsed times, so a benchmark can read the average duration of, e.g., the one-pass Gramian matvec

@@ -97,6 +97,14 @@ SIGNATURES = {
     "ngd_batch_pcg_solve": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.POINTER(C.c_void_p), C.POINTER(C.c_double),
                                       C.POINTER(Precond), C.c_double, C.c_int64, C.POINTER(C.c_void_p),
                                       C.POINTER(PcgInfo), C.c_void_p]),
+    "ngd_batch_pcg_solve_damped": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.POINTER(C.c_void_p), C.c_double,
+                                             C.c_double, C.POINTER(C.c_void_p), C.POINTER(Precond), C.c_double,
+                                             C.c_int64, C.POINTER(C.c_void_p), C.POINTER(PcgInfo),
+                                             C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_batch_nystrom_sketch": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.POINTER(C.c_int64), C.c_uint64,
+                                           C.c_uint64, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_void_p), C.c_void_p]),
+    "ngd_batch_matvec_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
     "ngd_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ngd_timing_enable_mask": (C.c_int, [C.c_void_p, C.c_uint32]),
     "ngd_timing_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),

@@ -436,6 +436,53 @@ class Batch:
                 "ngd_batch_residual_jacobian")
         return rs, grads, losses
 
+    def nystrom_sketch(self, Js, ells, seed=0, counter=0, sketch_dtype="f32", outs=None):
+        """ngd_batch_nystrom_sketch: every member's Gaussian sketch side by side, no host round trip.
+        Returns a NystromResult per member (info empty); `outs`, if given, are previous results of the
+        same ells to write into."""
+        n = len(self.members)
+        res = []
+        for i, (m, ell) in enumerate(zip(self.members, ells)):
+            o = outs[i] if outs is not None else None
+            if o is not None and o.lam_hat.numel() == ell:
+                res.append(o)
+            else:
+                res.append(NystromResult(torch.zeros((ell, m.ld), dtype=m.tdtype, device=m.device),
+                                         torch.empty(ell, dtype=torch.float64, device=m.device), {}))
+        ops = (L.Operator * n)(*[m._op(J) for m, J in zip(self.members, Js)])
+        ell_a = (C.c_int64 * n)(*[int(e) for e in ells])
+        ld_a = (C.c_int64 * n)(*[r.U.stride(0) for r in res])
+        L.check(self.lib.ngd_batch_nystrom_sketch(self.b, ops, ell_a, int(seed), int(counter), _DTYPE[sketch_dtype],
+                                                  self._ptrs([r.U for r in res]), ld_a,
+                                                  self._ptrs([r.lam_hat for r in res]), _stream()),
+                "ngd_batch_nystrom_sketch")
+        return res
+
+    def pcg_solve_damped(self, Js, gs, c_lam, c_loss, losses, precs, rtol=1e-6, maxit=1000):
+        """ngd_batch_pcg_solve_damped: the damping rule on the device per member. Returns the PcgResults
+        (with mu set)."""
+        n = len(self.members)
+        ops = (L.Operator * n)(*[m._op(J) for m, J in zip(self.members, Js)])
+        ds = [torch.empty(m.P, dtype=torch.float64, device=m.device) for m in self.members]
+        pcs = (L.Precond * n)(*[L.Precond(p.U.data_ptr(), p.U.stride(0), p.lam_hat.data_ptr(), p.lam_hat.numel())
+                                for p in precs])
+        infos = (L.PcgInfo * n)()
+        used = (C.c_double * n)()
+        for m, gv in zip(self.members, gs):
+            _need(gv, torch.float64, "g")
+        st = self.lib.ngd_batch_pcg_solve_damped(self.b, ops, self._ptrs(gs), float(c_lam), float(c_loss),
+                                                 self._ptrs(losses) if losses is not None else None, pcs,
+                                                 float(rtol), int(maxit), self._ptrs(ds), infos, used, _stream())
+        L.check(st, "ngd_batch_pcg_solve_damped", (L.NGD_ERR_NOT_CONVERGED, L.NGD_ERR_BREAKDOWN))
+        return [PcgResult(d, int(i.iters), float(i.rel_res), bool(i.converged), bool(i.breakdown), st, float(u))
+                for d, i, u in zip(ds, infos, used)]
+
+    def matvec_time(self, reps: int = 10) -> float:
+        """ngd_batch_matvec_time: average ms of one batched matvec launch (after a batched solve)."""
+        out = C.c_double()
+        L.check(self.lib.ngd_batch_matvec_time(self.b, int(reps), C.byref(out), _stream()), "ngd_batch_matvec_time")
+        return out.value
+
     def pcg_solve(self, Js, gs, lams, precs=None, rtol=1e-6, maxit=1000):
         """ngd_batch_pcg_solve: precs is None or a list of NystromResult / None per member."""
         n = len(self.members)

@@ -1273,11 +1273,26 @@ struct ngd_batch {
   int rows_target = 0;                // autotuned rows per matvec workgroup (0: not tuned yet)
   std::vector<int64_t> tuned_for;     // problem shapes the tuning applies to
   int64_t last_iters = 4;
+  // streams (default priority) over which the members' sketches run side by side, and the events
+  // that fork them from and join them to the caller's stream; created on first use
+  static constexpr int kSketchStreams = 4;
+  hipStream_t sk_stream[kSketchStreams] = {};
+  hipEvent_t sk_fork = nullptr, sk_join[kSketchStreams] = {};
+  int* h_err = nullptr;               // pinned: two error words per member (sketch core checks)
 };
 
 namespace {
 
 void batch_release(ngd_batch* b) {
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+    if (b->sk_stream[q]) {
+      (void)hipStreamSynchronize(b->sk_stream[q]);
+      (void)hipStreamDestroy(b->sk_stream[q]);
+    }
+    if (b->sk_join[q]) (void)hipEventDestroy(b->sk_join[q]);
+  }
+  if (b->sk_fork) (void)hipEventDestroy(b->sk_fork);
+  if (b->h_err) (void)hipHostFree(b->h_err);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -1324,7 +1339,8 @@ ngd_status ngd_batch_create(const ngd_problem_desc* descs, int32_t n, ngd_batch*
             hipMalloc(&b->d_states, sizeof(PcgState) * n) == hipSuccess &&
             hipHostMalloc(&b->h_res, sizeof(BatchResidualItem) * n, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&b->h_pcg, sizeof(PcgBatchItem) * n, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc(&b->h_states, sizeof(PcgState) * n, hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(&b->h_states, sizeof(PcgState) * n, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_err, sizeof(int) * 2 * n, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     batch_release(b);
     set_error("batch allocation failed");
@@ -1418,11 +1434,18 @@ void batch_pcg_items(ngd_batch* b, int* rows, int* upd, int* dots, int* elem, in
 
 }  // namespace
 
-ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const double* const* g, const double* lambda,
-                               const ngd_precond* precs, double rtol, int64_t maxit, double* const* d,
-                               ngd_pcg_info* infos, void* stream) {
-  NGD_CHECK(b != nullptr && ops != nullptr && g != nullptr && lambda != nullptr && d != nullptr && infos != nullptr,
-            "NULL argument");
+namespace {
+
+// The batched PCG solve behind ngd_batch_pcg_solve (lambda given per problem) and
+// ngd_batch_pcg_solve_damped (lambda == NULL: the damping rule on the device from each problem's
+// lam_hat[0] and loss).
+ngd_status batch_pcg_impl(ngd_batch* b, const ngd_operator* ops, const double* const* g, const double* lambda,
+                          const double* const* loss, double c_lam, double c_loss, const ngd_precond* precs,
+                          double rtol, int64_t maxit, double* const* d, ngd_pcg_info* infos, double* lambda_used,
+                          void* stream) {
+  NGD_CHECK(b != nullptr && ops != nullptr && g != nullptr && d != nullptr && infos != nullptr, "NULL argument");
+  const bool rule = lambda == nullptr;
+  if (rule) NGD_CHECK(precs != nullptr, "the device damping rule needs every problem's preconditioner");
   NGD_CHECK(rtol >= 0.0 && maxit >= 0, "rtol >= 0 and maxit >= 0 required");
   hipStream_t s = S(stream);
   const int n = (int)b->inst.size();
@@ -1434,9 +1457,10 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
     ngd_problem* h = b->inst[i];
     NGD_CHECK(ops[i].J != nullptr, "the batched solve needs stored Jacobians");
     NGD_TRY(check_op(h, &ops[i]));
-    NGD_CHECK(lambda[i] > 0.0 && std::isfinite(lambda[i]), "lambda must be > 0");
+    if (!rule) NGD_CHECK(lambda[i] > 0.0 && std::isfinite(lambda[i]), "lambda must be > 0");
     NGD_CHECK(g[i] != nullptr && d[i] != nullptr, "NULL problem pointer");
     const ngd_precond* pc = (precs != nullptr && precs[i].U != nullptr) ? &precs[i] : nullptr;
+    if (rule) NGD_CHECK(pc != nullptr, "the device damping rule needs every problem's preconditioner");
     if (pc != nullptr) {
       NGD_CHECK(pc->lam_hat != nullptr, "preconditioner pointers are NULL");
       NGD_CHECK(pc->ell >= 1 && pc->ell <= h->max_ell && pc->ldU >= h->P, "bad preconditioner ell / ldU");
@@ -1460,7 +1484,8 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
     it.U = pc ? pc->U : nullptr;
     it.ldU = pc ? pc->ldU : 0;
     it.lam = pc ? pc->lam_hat : nullptr;
-    it.mu = lambda[i];
+    it.loss = rule && loss != nullptr ? loss[i] : nullptr;
+    it.mu = rule ? 0.0 : lambda[i];
     it.rtol = rtol;
     it.ell = pc ? (int)pc->ell : 0;
     it.plain = pc == nullptr;
@@ -1470,8 +1495,20 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
     shape.push_back(ops[i].ldJ);
     PcgState& st = b->h_states[i];
     std::memset(&st, 0, sizeof(PcgState));
-    st.lambda = lambda[i];
+    st.lambda = rule ? 0.0 : lambda[i];
     st.maxit = maxit;
+  }
+  // the core error words of sketches taken without their summary, read back with the solve's state
+  std::vector<int> checked;
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    const ngd_precond* pc = (precs != nullptr && precs[i].U != nullptr) ? &precs[i] : nullptr;
+    if (pc == nullptr || h->unchecked_ell == 0 || pc->ell != h->unchecked_ell) continue;
+    NGD_HIP_TRY(hipMemcpyAsync(b->h_err + 2 * i, eig_error_flag(h->eigw, (int)pc->ell), sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+    NGD_HIP_TRY(hipMemcpyAsync(b->h_err + 2 * i + 1, h->cholsync + 128, sizeof(int), hipMemcpyDeviceToHost, s));
+    h->unchecked_ell = 0;
+    checked.push_back(i);
   }
   NGD_TRY(pcg_batch_prepare(b->dtype, max_ld, max_ell));
   int rows, upd, dots, elem, apply;
@@ -1483,6 +1520,7 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
   batch_pcg_items(b, &rows, &upd, &dots, &elem, &apply);
   NGD_HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(PcgState) * n, hipMemcpyHostToDevice, s));
   NGD_HIP_TRY(hipMemcpyAsync(b->d_pcg, b->h_pcg, sizeof(PcgBatchItem) * n, hipMemcpyHostToDevice, s));
+  if (rule) NGD_TRY(pcg_batch_launch_damping(b->d_pcg, b->d_states, n, c_lam, c_loss, s));
   NGD_TRY(pcg_batch_launch_init(b->dtype, b->d_pcg, n, elem, s));
   NGD_TRY(pcg_batch_launch_precond(b->dtype, b->d_pcg, n, dots, apply, max_ell, s));
   if (tune) {
@@ -1555,10 +1593,18 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
     if (all_done || k >= maxit) break;
     chunk = std::min<int64_t>(chunk * 2, 64);
   }
+  for (int i : checked) {
+    if (b->h_err[2 * i] != 0 || b->h_err[2 * i + 1] != 0) {
+      set_error("exchange between the workgroups of a member's sketch core timed out (problem " + std::to_string(i) +
+                ")");
+      return NGD_ERR_HIP;
+    }
+  }
   ngd_status ret = NGD_OK;
   int64_t most = 0;
   for (int i = 0; i < n; ++i) {
     const PcgState& st = b->h_states[i];
+    if (lambda_used != nullptr) lambda_used[i] = st.lambda;
     infos[i].iters = st.iters;
     infos[i].rel_res = st.bnorm2 > 0 ? std::sqrt(st.rr / st.bnorm2) : 0.0;
     infos[i].converged = st.converged;
@@ -1572,5 +1618,105 @@ ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const doub
   else if (ret == NGD_ERR_NOT_CONVERGED) set_error("batched PCG: at least one problem reached maxit");
   return ret;
 }
+
+}  // namespace
+
+ngd_status ngd_batch_pcg_solve(ngd_batch* b, const ngd_operator* ops, const double* const* g, const double* lambda,
+                               const ngd_precond* precs, double rtol, int64_t maxit, double* const* d,
+                               ngd_pcg_info* infos, void* stream) {
+  NGD_CHECK(lambda != nullptr, "NULL argument");
+  return batch_pcg_impl(b, ops, g, lambda, nullptr, 0.0, 0.0, precs, rtol, maxit, d, infos, nullptr, stream);
+}
+
+ngd_status ngd_batch_pcg_solve_damped(ngd_batch* b, const ngd_operator* ops, const double* const* g,
+                                      double c_lam, double c_loss, const double* const* loss,
+                                      const ngd_precond* precs, double rtol, int64_t maxit, double* const* d,
+                                      ngd_pcg_info* infos, double* lambda_used, void* stream) {
+  NGD_CHECK(std::isfinite(c_lam) && std::isfinite(c_loss) && c_lam >= 0.0 && c_loss >= 0.0,
+            "c_lam and c_loss must be finite and >= 0");
+  return batch_pcg_impl(b, ops, g, nullptr, loss, c_lam, c_loss, precs, rtol, maxit, d, infos, lambda_used, stream);
+}
+
+// The members' Nystrom sketches side by side: member i (largest cost first) on pool stream
+// i % kSketchStreams, forked from and joined back to the caller's stream; no host round trip.
+ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const int64_t* ells, uint64_t seed,
+                                    uint64_t counter, int32_t sketch_dtype, void* const* U, const int64_t* ldU,
+                                    double* const* lam_hat, void* stream) {
+  NGD_CHECK(b != nullptr && ops != nullptr && ells != nullptr && U != nullptr && ldU != nullptr && lam_hat != nullptr,
+            "NULL argument");
+  const int n = (int)b->inst.size();
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    NGD_TRY(check_op(h, &ops[i]));
+    NGD_CHECK(ells[i] >= 1 && ells[i] <= h->max_ell, "ell must be in [1, min(max_ell, P)] for every problem");
+    NGD_CHECK(U[i] != nullptr && lam_hat[i] != nullptr && ldU[i] >= h->P, "bad output of a problem");
+  }
+  if (b->sk_fork == nullptr) {
+    NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_fork, hipEventDisableTiming));
+    for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+      NGD_HIP_TRY(hipStreamCreateWithFlags(&b->sk_stream[q], hipStreamNonBlocking));
+      NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_join[q], hipEventDisableTiming));
+    }
+  }
+  hipStream_t s = S(stream);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) { return (double)ells[i] * (double)b->inst[i]->P * (double)(b->inst[i]->N + ells[i]); };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  NGD_HIP_TRY(hipEventRecord(b->sk_fork, s));
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) NGD_HIP_TRY(hipStreamWaitEvent(b->sk_stream[q], b->sk_fork, 0));
+  for (int k = 0; k < n; ++k) {
+    const int i = order[k];
+    hipStream_t qs = b->sk_stream[k % ngd_batch::kSketchStreams];
+    // member i's test matrix from its own counter range (counter, i)
+    NGD_TRY(sketch_impl(b->inst[i], &ops[i], ells[i], seed, counter + ((uint64_t)i << 32), nullptr, 0, nullptr,
+                        sketch_dtype, U[i], ldU[i], lam_hat[i], nullptr, qs));
+  }
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+    NGD_HIP_TRY(hipEventRecord(b->sk_join[q], b->sk_stream[q]));
+    NGD_HIP_TRY(hipStreamWaitEvent(s, b->sk_join[q], 0));
+  }
+  return NGD_OK;
+}
+
+// Average time of one batched matvec launch (the PCG iteration's one pass over every J_w) on the
+// directions of the last batched solve, from HIP events around `reps` launches on `stream`.
+ngd_status ngd_batch_matvec_time(ngd_batch* b, int32_t reps, double* avg_ms, void* stream) {
+  NGD_CHECK(b != nullptr && avg_ms != nullptr && reps >= 1, "NULL argument or reps < 1");
+  NGD_CHECK(b->rows_target != 0, "no batched solve has run yet");
+  hipStream_t s = S(stream);
+  int rows, upd, dots, elem, apply;
+  batch_pcg_items(b, &rows, &upd, &dots, &elem, &apply);
+  int64_t max_ld = 0;
+  for (size_t i = 0; i < b->inst.size(); ++i) max_ld = std::max<int64_t>(max_ld, b->h_pcg[i].ldJ);
+  const int n = (int)b->inst.size();
+  // the solve left every state done, and a done state skips its rows: clear the flags for the timed
+  // launches (they rewrite only the direction slot, its norm and the partial sums, which the next
+  // solve initialises again) and restore them afterwards
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int> done(n);
+  for (int i = 0; i < n; ++i) {
+    done[i] = b->h_states[i].done;
+    b->h_states[i].done = 0;
+  }
+  NGD_HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(PcgState) * n, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  NGD_HIP_TRY(hipEventCreate(&e0));
+  NGD_HIP_TRY(hipEventCreate(&e1));
+  NGD_HIP_TRY(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) NGD_TRY(pcg_batch_launch_rows(b->dtype, b->d_pcg, n, rows, max_ld, s));
+  NGD_HIP_TRY(hipEventRecord(e1, s));
+  NGD_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  NGD_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int i = 0; i < n; ++i) b->h_states[i].done = done[i];
+  NGD_HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(PcgState) * n, hipMemcpyHostToDevice, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  *avg_ms = ms / reps;
+  return NGD_OK;
+}
+
 
 }  // extern "C"

@@ -369,6 +369,7 @@ struct PcgBatchItem {
   const void* U;  // NULL: plain CG
   int64_t ldU;
   const double* lam;
+  const double* loss;  // the problem's loss (device) for the damping rule, or NULL
   double mu;
   double rtol;
   int ell, nwg, plain;
@@ -382,6 +383,10 @@ ngd_status pcg_batch_launch_rows(int dtype, const PcgBatchItem* items, int n, in
 ngd_status pcg_batch_launch_update(int dtype, const PcgBatchItem* items, int n, int total_upd, hipStream_t s);
 // make the kernels of a batched launch ready for stream capture (function attributes set up front)
 ngd_status pcg_batch_prepare(int dtype, int64_t max_ldJ, int max_ell);
+// the damping rule of Section 4.3 for every problem of a batch: states[i].lambda =
+// max(c_lam items[i].lam[0], c_loss items[i].loss[0]^2)
+ngd_status pcg_batch_launch_damping(const PcgBatchItem* items, PcgState* states, int n, double c_lam, double c_loss,
+                                    hipStream_t s);
 
 // residual.hip: several problems' residuals, Jacobians and loss partials in one launch
 struct BatchResidualItem {

@@ -697,8 +697,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void pcg_batch_apply_kernel(const PcgBatchItem* __restrict__ items, int n) {
   const int it = blockIdx.x;
   const PcgBatchItem& b = items[find_problem(n, it, [&](int q) { return items[q].item0_apply; })];
-  precond_apply_body<T>((const T*)b.U, b.ldU, b.P, b.ell, b.lam, b.mu, b.s, b.r, b.z, b.part, b.st,
+  precond_apply_body<T>((const T*)b.U, b.ldU, b.P, b.ell, b.lam, b.st->lambda, b.s, b.r, b.z, b.part, b.st,
                         it - b.item0_apply, (int)((b.P + 255) / 256));
+}
+
+// the damping rule of Section 4.3 for every problem of a batch (one thread per problem)
+__global__ void pcg_batch_damping_kernel(const PcgBatchItem* __restrict__ items, PcgState* __restrict__ states, int n,
+                                         double c_lam, double c_loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double l = items[i].loss != nullptr ? items[i].loss[0] : 0.0;
+  states[i].lambda = fmax(c_lam * items[i].lam[0], c_loss * (l * l));
 }
 
 // one thread: the damping rule of Section 4.3 evaluated on the device, and the sketch's error words
@@ -983,6 +992,15 @@ ngd_status pcg_batch_launch_init(int dtype, const PcgBatchItem* items, int n, in
   (void)dtype;
   if (total_elem <= 0) return NGD_OK;
   hipLaunchKernelGGL(pcg_batch_init_kernel, dim3((unsigned)total_elem), dim3(256), 0, s, items, n);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status pcg_batch_launch_damping(const PcgBatchItem* items, PcgState* states, int n, double c_lam, double c_loss,
+                                    hipStream_t s) {
+  if (n <= 0) return NGD_OK;
+  hipLaunchKernelGGL(pcg_batch_damping_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, items, states, n, c_lam,
+                     c_loss);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -166,8 +166,9 @@ class NGD:
 
 class BatchNGD:
     """NGD (Alg. 1) on many independent problems at once: residuals and Jacobians of all problems in
-    one batched launch, each problem's own Nystrom sketch (Alg. 4/6, its own ell) and damping, one
-    batched PCG solve for all, and each problem's Armijo step."""
+    one batched launch, every problem's Nystrom sketch (Alg. 4/6, its own ell) side by side with no host
+    round trip, each problem's damping on the device and one batched PCG solve for all, then each
+    problem's Armijo step. Plain CG ("cg") takes each problem's lam1_hat from 4 power iterations."""
 
     def __init__(self, datas, thetas0, *, solver="nystrom", rtol=1e-6, gamma=10.0, seed=0):
         self.batch = Batch(datas, dtype="f32")
@@ -179,23 +180,25 @@ class BatchNGD:
         self.ells = [min(int(d.ell), m.P) for d, m in zip(datas, self.batch.members)]
         self.thetas = [m.theta(t) for m, t in zip(self.batch.members, thetas0)]
         self.Js = [m.new_jacobian() for m in self.batch.members]
+        self.pcs = None
         self.k = 0
 
     def step(self):
         b = self.batch
         _, grads, losses = b.residual_jacobian(self.thetas, self.Js)
-        pcs = None
         if self.solver == "nystrom":
-            pcs = [m.nystrom_sketch(J, ell, seed=self.seed, counter=self.k, sketch_dtype="f32", want_info=True)
-                   for m, J, ell in zip(b.members, self.Js, self.ells)]
-            lam1 = [p.info["lam1"] for p in pcs]
+            self.pcs = b.nystrom_sketch(self.Js, self.ells, seed=self.seed, counter=self.k, sketch_dtype="f32",
+                                        outs=self.pcs)
+            outs = b.pcg_solve_damped(self.Js, grads, self.gamma * self.eps, 1e-4, losses, self.pcs, rtol=self.rtol,
+                                      maxit=1000)
         else:
-            lam1 = [m.power_lambda_max(J, torch.ones(m.P, dtype=torch.float64, device=m.device), 4)
-                    for m, J in zip(b.members, self.Js)]
+            mus = []
+            for m, J, loss in zip(b.members, self.Js, losses):
+                l1 = torch.empty(1, dtype=torch.float64, device=m.device)
+                m.power_lambda_max(J, torch.ones(m.P, dtype=torch.float64, device=m.device), 4, out=l1)
+                mus.append(m.damping(l1, loss, self.gamma * self.eps, 1e-4)[1])
+            outs = b.pcg_solve(self.Js, grads, mus, None, rtol=self.rtol, maxit=max(m.P for m in b.members))
         L0 = torch.cat(losses).cpu().numpy()
-        mus = [max(self.gamma * self.eps * l1, 1e-4 * float(l0) ** 2) for l1, l0 in zip(lam1, L0)]
-        maxit = 1000 if self.solver == "nystrom" else max(m.P for m in b.members)
-        outs = b.pcg_solve(self.Js, grads, mus, pcs, rtol=self.rtol, maxit=maxit)
         news = []
         for m, th, o, g, l0 in zip(b.members, self.thetas, outs, grads, L0):
             _, alpha, l1 = m.line_search(th, o.d, g, float(l0), theta_out=th)

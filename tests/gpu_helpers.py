@@ -27,3 +27,28 @@ def make(prob, seed=0):
     theta = theta + 0.05 * np.random.default_rng(seed + 1).standard_normal(theta.size)
     th = rounded_theta(theta, prob.dtype)
     return prob.cast(prob.dtype), th
+
+
+U32 = 2.0 ** -24
+
+
+def jt_mul(J32, V, chunk=2048):
+    """FP64 J^T (J V) with J a host copy of an FP32 Jacobian, in row chunks (V a vector or a block)."""
+    out = np.zeros((J32.shape[1],) + np.shape(V)[1:])
+    for s in range(0, J32.shape[0], chunk):
+        Jc = J32[s:s + chunk].astype(np.float64)
+        out += Jc.T @ (Jc @ V)
+    return out
+
+
+def check_fp32_solve(J32, g, d, mu, rtol):
+    """True residual of a solve on an FP32 Jacobian promoted to FP64, against the PCG tolerance plus the
+    rounding bound of the FP32 operator the solver applies (a sqrt(P) u dot-product bound)."""
+    absd = np.zeros(J32.shape[1])
+    for s in range(0, J32.shape[0], 2048):
+        Jc = np.abs(J32[s:s + 2048].astype(np.float64))
+        absd += Jc.T @ (Jc @ np.abs(d))
+    res = np.linalg.norm(g - jt_mul(J32, d) - mu * d) / np.linalg.norm(g)
+    bound = 10 * rtol + np.sqrt(J32.shape[1]) * U32 * np.linalg.norm(absd) / np.linalg.norm(g)
+    assert res <= bound, (res, bound)
+    return res

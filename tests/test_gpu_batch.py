@@ -86,3 +86,64 @@ def test_batch_ngd_steps_decrease_loss():
         assert np.all(L1 <= L0 + 1e-12)
         assert all(o.converged for o in outs)
     ngd.batch.close()
+
+
+@pytest.mark.timeout(900)
+def test_c5_workload_members_against_oracle():
+    """The batched workload itself (32 problems, hidden widths 32-96, depths 2-4, N 1,152-9,216, ell up to
+    400, FP32) through the batched entry points: residual/Jacobian launch, the side-by-side sketches and
+    the graph-replayed solve with the damping rule on the device. Members that cover both dimensions,
+    every depth and the largest and smallest P and ell are checked against the oracle: sampled Jacobian
+    rows and all residuals; the gradient, Alg. 6's eigenvalues (same Omega) and the solve's true residual
+    in FP64 on the member's own FP32 Jacobian; the damping against the rule."""
+    from oracle import nystrom
+    from gpu_helpers import check_fp32_solve, jt_mul, rowwise_rel
+    probs = wl.batch_instances(seed=0)
+    b = Batch(probs, dtype="f32")
+    ths = [wl.glorot_theta(p.widths, i) for i, p in enumerate(probs)]
+    ths = [t.astype(np.float32).astype(np.float64) for t in ths]
+    thetas = [m.theta(t) for m, t in zip(b.members, ths)]
+    Js = [m.new_jacobian() for m in b.members]
+    rs, grads, losses = b.residual_jacobian(thetas, Js)
+    ells = [p.ell for p in probs]
+    pcs = b.nystrom_sketch(Js, ells, seed=3, counter=1)
+    eps32 = 2.0 ** -23
+    outs = b.pcg_solve_damped(Js, grads, 10 * eps32, 1e-4, losses, pcs, rtol=1e-6, maxit=1000)
+    torch.cuda.synchronize()
+    assert all(o.converged for o in outs)
+    P = [m.P for m in b.members]
+    pick = {int(np.argmax(P)), int(np.argmin(P)), int(np.argmax(ells)), int(np.argmin(ells))}
+    for key in (lambda p: p.d, lambda p: len(p.widths)):
+        seen = {}
+        for i, p in enumerate(probs):
+            seen.setdefault(key(p), i)
+        pick |= set(seen.values())
+    for i in sorted(pick):
+        p, m = probs[i], b.members[i]
+        p64 = p.cast("f32")
+        print(f"c5 member {i}: d={p.d} widths={p.widths} N={m.N} P={m.P} ell={ells[i]}", flush=True)
+        rng = np.random.default_rng(i)
+        rows = np.unique(np.concatenate([rng.choice(m.N, 10, replace=False), [0, m.N - 1]]))
+        J32 = Js[i].cpu().numpy()[:, :m.P]
+        assert rowwise_rel(J32[rows], mlp.jacobian(ths[i], p64, rows)) <= 1e-5
+        r_o = mlp.weighted_residual(ths[i], p64)
+        assert np.linalg.norm(rs[i].cpu().numpy() - r_o) <= 1e-5 * np.linalg.norm(r_o)
+        r32 = rs[i].cpu().numpy().astype(np.float64)
+        g_ref = np.zeros(m.P)
+        for s in range(0, m.N, 2048):
+            g_ref += J32[s:s + 2048].astype(np.float64).T @ r32[s:s + 2048]
+        assert np.linalg.norm(grads[i].cpu().numpy() - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+        # Alg. 6 on the member's own FP32 Jacobian with the test matrix it drew, (3, 1 + i 2^32)
+        om = m.gaussian_omega(3, 1 + (i << 32), ells[i]).cpu().numpy()[:, :m.P].T.astype(np.float64)
+        _, lo, _ = nystrom.nystrom_alg6(lambda V: jt_mul(J32, V), om)
+        lam = pcs[i].lam_hat.cpu().numpy()
+        top = lo >= 1e-6 * lo[0]
+        err = np.max(np.abs(lam[top] - lo[top])) / lo[0]
+        L0 = float(losses[i].item())
+        mu = max(10 * eps32 * lam[0], 1e-4 * (L0 * L0))
+        assert outs[i].mu == mu
+        res = check_fp32_solve(J32, grads[i].cpu().numpy(), outs[i].d.cpu().numpy(), mu, 1e-6)
+        print(f"  Alg. 6 max |lam - lam_o| / lam_1 (lam >= 1e-6 lam_1) {err:.1e}; mu {mu:.3e}; "
+              f"PCG {outs[i].iters} its, true residual {res:.1e}", flush=True)
+        assert err <= 1e-5
+    b.close()
