@@ -29,7 +29,7 @@ MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 WORKLOADS = {
     "c1": "2D Poisson 2-32-32-1 tanh (P=1,185), 30x30 grid + 120 boundary points, FP64, ell=100, "
-          "lambda=1e-6, PCG rtol 1e-6",
+          "lambda=1e-6, PCG rtol 1e-8",
     "c2": "2D Poisson 2-64-64-64-1 tanh (P=8,577), 4,096 + 512 random points, FP32 (FP64 CG scalars), "
           "ell=400, PCG rtol 1e-6",
     "c3": "5D Poisson 5-128-128-128-1 tanh (P=33,921), 16,384 + 2,048 points, FP32 Jacobian, BF16 sketch, "
@@ -52,7 +52,10 @@ WORKLOADS["paper_heat"] = ("the paper's heat equation in 3+1D: 4-64-64-64-1 tanh
 PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1, "direct": 317.7}
 PAPER3D_BASELINE_SPS = {k: 1000.0 / v for k, v in PAPER3D_BASELINE_S.items()}
 _VARIANT_NAME = {"rpchol": "RPCholNGD", "direct": "NGD full (direct Cholesky)"}
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 vector peak without packed FP32 instructions (which this build leaves out): 256 CUs x 128 FLOP
+# per clock (4 SIMDs x 16 lanes x an FMA) x 2.4 GHz = 78.6 TFLOP/s; the 157.3 of the data sheet counts
+# packed FP32
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def bench_paper(a):
@@ -245,14 +248,102 @@ def cpu_baseline(cfg: str, seed: int, steps: int = 1):
     theta = wl.glorot_theta(prob.widths, seed)
     prob64 = prob.cast(prob.dtype)
     th = theta.astype(np.float32).astype(np.float64) if prob.dtype == "f32" else theta
+    rtol = 1e-8 if cfg == "c1" else 1e-6
     t0 = time.perf_counter()
     for k in range(steps):
         Om = wl.gaussian_omega(prob.n_params, prob.ell, seed=seed, counter=k)
-        th, _ = ongd.ngd_step(th, prob64, solver="nystrom", Omega=Om, rtol=1e-6, maxit=1000)
+        th, _ = ongd.ngd_step(th, prob64, solver="nystrom", Omega=Om, rtol=rtol, maxit=1000)
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "NGD steps/s", "cores": _cpu_threads(), "kind": "oracle",
             "sample": f"{steps} Nystrom-PCG NGD step(s) of workload {cfg} (same data, ell={prob.ell}, "
-                      f"rtol 1e-6) in the FP64 NumPy oracle, {dt:.1f} s"}
+                      f"rtol {rtol:g}) in the FP64 NumPy oracle, {dt:.1f} s"}
+
+
+def time_to_rtol(cfg: str, seed: int, at_steps=(0, 10, 49), reps: int = 3, cg_maxit: int = 2000):
+    """Single solves to rtol 1e-6 at fixed theta (the iterates after `at_steps` Nystrom NGD steps from the
+    Glorot start) and fixed lambda (the damping rule's value there): Nystrom = sketch + FP64 core + PCG,
+    plain CG = CG alone (capped at `cg_maxit` iterations). Median wall time of `reps` runs each."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2505_11638_amd.driver import EPS, NGD
+
+    prob = wl.config(cfg, seed=seed)
+    ngd = NGD(prob, wl.glorot_theta(prob.widths, seed), solver="nystrom", rtol=1e-6, seed=seed)
+    gp = ngd.gp
+    out = []
+    for k in range(max(at_steps) + 1):
+        if k in at_steps:
+            theta = ngd.theta.clone()
+            r, J, grad, loss = gp.residual_jacobian(theta, ngd.J)
+            pc = gp.nystrom_sketch(J, ngd.ell, seed=seed, counter=10_000 + k, sketch_dtype=ngd.sketch_dtype)
+            _, mu = gp.damping(pc.lam_hat[:1], loss, 10.0 * EPS[gp.dtype_name], 1e-4)
+            row = {"step": k, "lambda": mu}
+            for name in ("nystrom", "cg"):
+                times, its, conv = [], 0, True
+                for rep in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    if name == "nystrom":
+                        pc = gp.nystrom_sketch(J, ngd.ell, seed=seed, counter=20_000 + 10 * k + rep,
+                                               sketch_dtype=ngd.sketch_dtype, want_info=False, out=pc)
+                        o = gp.pcg_solve(J, grad, mu, precond=pc, rtol=1e-6, maxit=1000)
+                    else:
+                        o = gp.pcg_solve(J, grad, mu, rtol=1e-6, maxit=cg_maxit)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    its, conv = o.iters, o.converged
+                row[name] = {"ms": 1000.0 * float(np.median(times)), "iters": its, "converged": conv}
+            row["speedup_nystrom_vs_cg"] = row["cg"]["ms"] / row["nystrom"]["ms"]
+            out.append(row)
+        if k < max(at_steps):
+            ngd.step()
+    torch.cuda.synchronize()
+    gp.close()
+    return {"workload": cfg, "rtol": 1e-6, "ell": prob.ell, "sketch_dtype": prob.sketch_dtype,
+            "cg_maxit": cg_maxit, "reps": reps, "solves": out}
+
+
+def c3_subrun(seed: int, steps: int = 3):
+    """A short run of the 5D workload (BF16 sketch, ell = 800): the one-pass matvec's HBM roofline and the
+    sketch contractions' MFMA roofline, timed with HIP events over `steps` Nystrom NGD steps."""
+    import torch
+
+    import workloads as wl
+    from paper_2505_11638_amd.driver import NGD
+
+    prob = wl.config("c3", seed=seed)
+    ngd = NGD(prob, wl.glorot_theta(prob.widths, seed), solver="nystrom", rtol=1e-6, seed=seed)
+    gp = ngd.gp
+    ngd.step()
+    gp.timing(True, only=["matvec_rows", "sketch_z", "sketch_w"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ngd.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t = gp.timers()
+    gp.timing(False)
+    gp.close()
+    P, N = prob.n_params, prob.n_rows
+    n_mv, ms_mv = t["matvec_rows"]
+    mv_ms = ms_mv / max(n_mv, 1)
+    mv_bytes = N * P * 4 + 2 * P * 8
+    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    n_sk = t["sketch_z"][0] + t["sketch_w"][0]
+    sk_ms = (t["sketch_z"][1] + t["sketch_w"][1]) / max(n_sk, 1)
+    sk_flops = 2.0 * N * P * prob.ell
+    sk_tf = sk_flops / (sk_ms * 1e-3) / 1e12
+    return {"workload": f"c3: {WORKLOADS['c3']}; 1 + {steps} NGD steps", "steps_per_s": steps / dt,
+            "roofline_matvec": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v))", "achieved": mv_gbs,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": mv_gbs / HBM_PEAK_GBS,
+                                "alg_bytes_per_launch": mv_bytes, "avg_launch_ms": mv_ms, "launches": n_mv},
+            "roofline_sketch": {"bound": "mfma", "kernel": "nt_gemm_kernel (Z = J Omega and B^T = Q^T J), BF16",
+                                "achieved": sk_tf, "peak": MFMA_PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                                "frac": sk_tf / MFMA_PEAK_TFLOPS["bf16"], "alg_flops_per_launch": sk_flops,
+                                "avg_launch_ms": sk_ms, "launches": n_sk}}
 
 
 def main(argv=None):
@@ -275,6 +366,8 @@ def main(argv=None):
                     help="paper3d: Gaussian test matrix or identity columns sampled proportionally to diag(G)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (known bytes) to calibrate the HBM traffic counters")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c2: skip the time-to-rtol solves and the 5D sub-run")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -294,7 +387,7 @@ def main(argv=None):
     prob = wl.config(a.config, seed=a.seed)
     theta0 = wl.glorot_theta(prob.widths, a.seed)
     P, N = prob.n_params, prob.n_rows
-    rtol = 1e-6
+    rtol = 1e-8 if a.config == "c1" else 1e-6
 
     # ---- Nystrom-PCG NGD ----
     nys = NGD(prob, theta0, solver="nystrom", rtol=rtol, seed=a.seed)
@@ -400,7 +493,7 @@ def main(argv=None):
                       "achieved": achieved_tf, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                       "alg_flops_per_launch": mv_flops, "avg_launch_ms": avg_ms, "launches": n_mv}),
-        "roofline_sketch": {"bound": "mfma", "kernel": "gemm_kernel (Z = J Omega and B^T = Q^T J)",
+        "roofline_sketch": {"bound": "mfma", "kernel": "nt_gemm_kernel (Z = J Omega and B^T = Q^T J)",
                             "achieved": sk_achieved, "peak": sk_peak, "unit": "TFLOP/s",
                             "frac": sk_achieved / sk_peak, "compute_dtype": prob.sketch_dtype,
                             "alg_flops_per_launch": sk_flops, "avg_launch_ms": sk_ms / max(sk_n, 1),
@@ -411,6 +504,11 @@ def main(argv=None):
     nys.gp.close()
     if cg is not None:
         cg.gp.close()
+    # time-to-rtol 1e-6 at fixed theta and lambda (Nystrom: sketch + core + PCG; plain CG: CG alone) for
+    # this workload and the 5D one, and the 5D workload's matvec and BF16-sketch rooflines
+    if a.config == "c2" and not a.no_extras:
+        line["time_to_rtol"] = [time_to_rtol("c2", a.seed), time_to_rtol("c3", a.seed, at_steps=(0, 10, 49), reps=2)]
+        line["c3_subrun"] = c3_subrun(a.seed)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(a.config, a.seed, a.cpu_steps)
     print(json.dumps(line), flush=True)
