@@ -353,9 +353,10 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   size_t total = 0;
   for (auto& p : plan) total += align_up(p.second, 256);
   void* base = nullptr;
-  if (hipMalloc(&base, total) != hipSuccess) {
+  if (const hipError_t e = hipMalloc(&base, total); e != hipSuccess) {
+    (void)hipGetLastError();
     delete h;
-    set_error("hipMalloc of the workspace failed");
+    set_error("hipMalloc of the workspace failed (" + std::to_string(total) + " bytes): " + hipGetErrorString(e));
     return NGD_ERR_OOM;
   }
   if (hipMemset(base, 0, total) != hipSuccess) {

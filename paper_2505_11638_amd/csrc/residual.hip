@@ -349,7 +349,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
     for (int c = 0; c < kMaxChan; ++c) s.ub[p * kMaxChan + c] = seed[c];
   }
   if constexpr (MODE == kJacobian) {
-    __shared__ double red_d[4];
+    __shared__ double red_d[16];
     double tot = block_sum<double>((double)lsum, red_d);
     if (threadIdx.x == 0 && loss_slot != nullptr) *loss_slot = tot;
     if (J == nullptr) return;
@@ -498,7 +498,7 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
   __syncthreads();
   }  // tile loop
   if constexpr (MODE == kVjp) {
-    __shared__ double red_t[4];
+    __shared__ double red_t[16];
     const double t = block_sum(tsq_acc, red_t);
     if (threadIdx.x == 0 && tsq_slot != nullptr) *tsq_slot = t;
     if (acc_in_lds) {
@@ -508,8 +508,8 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
   }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void residual_jacobian_kernel(
+template <typename T, int MODE, int NT = 256>
+__global__ __launch_bounds__(NT) void residual_jacobian_kernel(
     NetDesc net, const T* __restrict__ theta0, int64_t theta_stride, int64_t N, const T* __restrict__ X,
     const T* __restrict__ w, const T* __restrict__ f, const T* __restrict__ g, const int8_t* __restrict__ kind,
     T* __restrict__ r_w, T* __restrict__ J, int64_t ldJ, double* __restrict__ loss_partial, int TP,
@@ -530,8 +530,8 @@ __global__ __launch_bounds__(256) void residual_jacobian_kernel(
 // Several problems in one launch: work item i is tile (i - first_tile[q]) of the problem q whose
 // tile range holds i; workgroups stride over the items (a persistent grid). loss_part has one slot
 // per tile of the problem.
-template <typename T>
-__global__ __launch_bounds__(256) void batch_residual_jacobian_kernel(const BatchResidualItem* __restrict__ items,
+template <typename T, int NT = 256>
+__global__ __launch_bounds__(NT) void batch_residual_jacobian_kernel(const BatchResidualItem* __restrict__ items,
                                                                       int n_prob, int64_t total_tiles) {
   for (int64_t it = blockIdx.x; it < total_tiles; it += gridDim.x) {
     int lo = 0, hi = n_prob - 1;  // last problem whose first tile is <= it
@@ -739,6 +739,14 @@ static int choose_tp(const NetDesc& net, size_t elem, size_t* bytes, bool fwd_on
   return tp;
 }
 
+// Threads per workgroup of the Jacobian sweep: the tile's LDS decides how many workgroups share a CU;
+// where that is one or two, wider workgroups (1,024 or 512 threads) keep more waves in flight for the
+// row stores and the per-point products (every loop of the sweep strides over the workgroup).
+static int jacobian_threads(size_t lds_bytes) {
+  const size_t per_cu = lds_bytes > 0 ? (160 * 1024) / lds_bytes : 8;
+  return per_cu <= 1 ? 1024 : (per_cu <= 3 ? 512 : 256);
+}
+
 ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* theta, int64_t N, const void* X,
                                     const void* w, const void* f, const void* g, const int8_t* kind, void* r_w,
                                     void* J, int64_t ldJ, double* loss_partial, int64_t theta_stride, int n_theta,
@@ -753,19 +761,26 @@ ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* t
   }
   dim3 grid((unsigned)((N + tp - 1) / tp), (unsigned)n_theta);
   if (n_blocks_out) *n_blocks_out = (int)grid.x;
+  const int nt = fwd_only ? 256 : jacobian_threads(bytes);
+  auto go = [&](auto k, auto tag) -> ngd_status {
+    using T = decltype(tag);
+    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    hipLaunchKernelGGL(k, grid, dim3(nt), bytes, s, net, (const T*)theta, theta_stride, N, (const T*)X, (const T*)w,
+                       (const T*)f, (const T*)g, kind, (T*)r_w, (T*)J, ldJ, loss_partial, tp, nullptr, (int64_t)0,
+                       nullptr, 0, fwd_only);
+    return NGD_OK;
+  };
+  ngd_status st;
   if (dtype == NGD_F64) {
-    auto k = residual_jacobian_kernel<double, kJacobian>;
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const double*)theta, theta_stride, N, (const double*)X,
-                       (const double*)w, (const double*)f, (const double*)g, kind, (double*)r_w, (double*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0, fwd_only);
+    st = nt == 1024 ? go(residual_jacobian_kernel<double, kJacobian, 1024>, 0.0)
+                    : (nt == 512 ? go(residual_jacobian_kernel<double, kJacobian, 512>, 0.0)
+                                 : go(residual_jacobian_kernel<double, kJacobian>, 0.0));
   } else {
-    auto k = residual_jacobian_kernel<float, kJacobian>;
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    hipLaunchKernelGGL(k, grid, dim3(256), bytes, s, net, (const float*)theta, theta_stride, N, (const float*)X,
-                       (const float*)w, (const float*)f, (const float*)g, kind, (float*)r_w, (float*)J, ldJ,
-                       loss_partial, tp, nullptr, (int64_t)0, nullptr, 0, fwd_only);
+    st = nt == 1024 ? go(residual_jacobian_kernel<float, kJacobian, 1024>, 0.f)
+                    : (nt == 512 ? go(residual_jacobian_kernel<float, kJacobian, 512>, 0.f)
+                                 : go(residual_jacobian_kernel<float, kJacobian>, 0.f));
   }
+  NGD_TRY(st);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }
@@ -856,15 +871,20 @@ ngd_status launch_batch_residual_jacobian(int dtype, const BatchResidualItem* it
   }
   // a persistent grid: a few workgroups per CU, striding over all tiles of all problems
   const int64_t grid = total_tiles < 2048 ? total_tiles : 2048;
-  if (dtype == NGD_F64) {
-    auto k = batch_residual_jacobian_kernel<double>;
+  const int nt = jacobian_threads(lds_bytes);
+  auto go = [&](auto k) -> ngd_status {
     NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds_bytes, s, items, n, total_tiles);
-  } else {
-    auto k = batch_residual_jacobian_kernel<float>;
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(256), lds_bytes, s, items, n, total_tiles);
-  }
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(nt), lds_bytes, s, items, n, total_tiles);
+    return NGD_OK;
+  };
+  ngd_status st;
+  if (dtype == NGD_F64)
+    st = nt == 1024 ? go(batch_residual_jacobian_kernel<double, 1024>)
+                    : (nt == 512 ? go(batch_residual_jacobian_kernel<double, 512>) : go(batch_residual_jacobian_kernel<double>));
+  else
+    st = nt == 1024 ? go(batch_residual_jacobian_kernel<float, 1024>)
+                    : (nt == 512 ? go(batch_residual_jacobian_kernel<float, 512>) : go(batch_residual_jacobian_kernel<float>));
+  NGD_TRY(st);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -172,8 +172,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   K = (K - kbeg) < kchunk ? (K - kbeg) : kchunk;
   const __amdgpu_buffer_rsrc_t ra = tile_rsrc(A, m0, M, kBM, lda, kbeg);
   const __amdgpu_buffer_rsrc_t rb = tile_rsrc(B, n0, N, kBN, ldb, kbeg);
-  SlabLoader<TA, E, kBM> la;
-  SlabLoader<TB, E, kBN> lb;
+  // two register sets per operand: the slab after next is loaded while the next one waits in
+  // registers for its LDS buffer, so two slabs of global loads are in flight behind the MFMAs
+  SlabLoader<TA, E, kBM> la0, la1;
+  SlabLoader<TB, E, kBN> lb0, lb1;
   f4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -185,28 +187,36 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   // (FP32 only: the BF16 instantiations are large enough that a second copy of the loop costs more
   // in instruction fetch than the skipped edge tiles save)
   const bool full = sizeof(E) == 2 || (imax >= 8 && jmax >= 4);
-  la.load(ra, lda, 0, K);
-  lb.load(rb, ldb, 0, K);
-  la.store(As[0]);
-  lb.store(Bs[0]);
+  la0.load(ra, lda, 0, K);
+  lb0.load(rb, ldb, 0, K);
+  if (nk > 1) {
+    la1.load(ra, lda, BK, K);
+    lb1.load(rb, ldb, BK, K);
+  }
+  la0.store(As[0]);
+  lb0.store(Bs[0]);
   __syncthreads();
   // the K loop, with the tile bounds checked only in workgroups that hold an edge of C (the branch
-  // is taken once, outside the loop, so the loads in flight across iterations are not waited for)
+  // is taken once, outside the loop, so the loads in flight across iterations are not waited for).
+  // Step kt multiplies LDS buffer kt % 2; the register set that held slab kt is free and takes
+  // slab kt + 2; the other set holds slab kt + 1 and goes to the other LDS buffer.
   auto kloop = [&](auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
-    for (int64_t kt = 0; kt < nk; ++kt) {
-      const int cur = (int)(kt & 1);
-      const bool more = kt + 1 < nk;
-      if (more) {
-        la.load(ra, lda, (kt + 1) * BK, K);
-        lb.load(rb, ldb, (kt + 1) * BK, K);
+    auto step = [&](int64_t kt, int cur, auto& la_free, auto& lb_free, auto& la_next, auto& lb_next) {
+      if (kt + 2 < nk) {
+        la_free.load(ra, lda, (kt + 2) * BK, K);
+        lb_free.load(rb, ldb, (kt + 2) * BK, K);
       }
       slab_mfma<E, FULL>(As[cur], Bs[cur], wm, wn, imax, jmax, acc);
-      if (more) {
-        la.store(As[cur ^ 1]);
-        lb.store(Bs[cur ^ 1]);
+      if (kt + 1 < nk) {
+        la_next.store(As[cur ^ 1]);
+        lb_next.store(Bs[cur ^ 1]);
       }
       __syncthreads();
+    };
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      step(kt, 0, la0, lb0, la1, lb1);
+      if (kt + 1 < nk) step(kt + 1, 1, la1, lb1, la0, lb0);
     }
   };
   if constexpr (sizeof(E) == 2) {
