@@ -193,7 +193,7 @@ __device__ __forceinline__ void row_range(int64_t N, int64_t* r0, int64_t* r1, i
 
 // y partials of J^T (J v) for an FP64 input vector
 template <typename T, int NK, int R, int B>
-__global__ __launch_bounds__(B) void gram_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+__global__ __launch_bounds__(B, (NK * R <= 10 ? 4 : 1)) void gram_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
                                                          const double* __restrict__ v, T* __restrict__ partial,
                                                          double* __restrict__ tsq_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -338,7 +338,7 @@ __device__ __forceinline__ void pcg_rows_body(const T* __restrict__ J, int64_t l
 }
 
 template <typename T, int NK, int R, int B>
-__global__ __launch_bounds__(B) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
+__global__ __launch_bounds__(B, (NK * R <= 10 ? 4 : 1)) void pcg_rows_kernel(const T* __restrict__ J, int64_t ldJ, int64_t N, int64_t P,
                                                      const double* __restrict__ z, const double* __restrict__ p_prev,
                                                      double* __restrict__ p_cur, PcgState* __restrict__ st,
                                                      T* __restrict__ partial, double* __restrict__ tsq_out) {
@@ -739,7 +739,7 @@ ngd_status pcg_launch_setup(PcgState* st, const double* lam_hat, double c_lam, c
   X(0, 256, 1, 4) X(1, 256, 2, 4) X(2, 256, 3, 4) X(3, 256, 4, 4) X(4, 512, 2, 4) X(5, 512, 3, 4) \
   X(6, 512, 4, 4) X(7, 512, 5, 4) X(8, 512, 6, 2) X(9, 512, 7, 2) X(10, 512, 8, 2)              \
   X(11, 512, 9, 2) X(12, 512, 10, 2) X(13, 512, 12, 1) X(14, 512, 14, 1) X(15, 512, 16, 1)     \
-  X(16, 512, 17, 1) X(17, 512, 18, 1)
+  X(16, 512, 17, 1) X(17, 512, 18, 1) X(18, 512, 5, 2)
 
 struct RowsCfg {
   int id, block, nk, r;
@@ -753,6 +753,13 @@ static bool rows_cfg(int dtype, int64_t ldJ, RowsCfg* c) {
       NGD_ROWS_CONFIGS(NGD_ROW)
 #undef NGD_ROW
   };
+  // FP32 rows of 2,049 - 2,560 chunks (P about 8.2k - 10.2k): five chunks per thread and two rows per
+  // step, few enough registers for two workgroups per CU (measured faster than four rows per step
+  // with one workgroup per CU)
+  if (dtype == NGD_F32 && nchunk > 2048 && nchunk <= 2560) {
+    *c = table[18];
+    return true;
+  }
   for (const RowsCfg& t : table) {
     if ((int64_t)t.block * t.nk >= nchunk && (t.block == 512 || nchunk <= 256 * 4)) {
       *c = t;
@@ -763,9 +770,11 @@ static bool rows_cfg(int dtype, int64_t ldJ, RowsCfg* c) {
 }
 
 int gram_rows_grid(int dtype, int64_t N, int64_t P) {
-  (void)dtype;
-  (void)P;
-  int64_t g = N < 256 ? N : 256;
+  // one workgroup per CU, or two where the row configuration leaves registers for two
+  RowsCfg c;
+  const int64_t ld = (P + 63) / 64 * 64;
+  const int64_t cap = rows_cfg(dtype, ld, &c) && c.nk * c.r <= 10 && c.block == 512 ? 512 : 256;
+  int64_t g = N < cap ? N : cap;
   return (int)(g < 1 ? 1 : g);
 }
 
