@@ -403,8 +403,9 @@ int32_t ngd_batch_size(const ngd_batch* b);
 ngd_problem* ngd_batch_problem(ngd_batch* b, int32_t i);
 
 /*
- * ngd_residual_jacobian for every member in one launch: a persistent kernel whose workgroups stride
- * over all members' point tiles. All arrays are host arrays of n entries holding device pointers as
+ * ngd_residual_jacobian for every member: persistent launches whose workgroups stride over the
+ * members' point tiles, one launch per group of members whose tiles need a like amount of LDS (at
+ * most three), so that narrow members are not held to the widest member's occupancy. All arrays are host arrays of n entries holding device pointers as
  * for ngd_residual_jacobian (J_w[i] with ldJ[i]; grad and loss may be NULL, or hold NULL entries).
  * Synchronises `stream` on entry (the call reuses its host-side work table).
  */

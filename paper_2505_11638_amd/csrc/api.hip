@@ -1369,36 +1369,54 @@ ngd_status ngd_batch_residual_jacobian(ngd_batch* b, const void* const* theta, v
   const int n = (int)b->inst.size();
   // the host table is reused by every call: wait until the previous call's copy has been consumed
   NGD_HIP_TRY(hipStreamSynchronize(s));
-  int64_t tiles = 0;
-  size_t lds = 0;
+  // Members are grouped by the LDS their tiles need (how many workgroups share a CU: four or more, two
+  // or three, one), and each group is one persistent launch with its own LDS size: a single launch
+  // would reserve the widest member's LDS for every tile and hold the narrow ones to its occupancy.
+  std::vector<int> tps(n), cls(n);
+  std::vector<size_t> ldsb(n);
   for (int i = 0; i < n; ++i) {
     ngd_problem* h = b->inst[i];
     NGD_CHECK(theta[i] != nullptr && r_w[i] != nullptr && J_w[i] != nullptr, "NULL problem pointer");
     NGD_CHECK(ldJ[i] >= h->P, "ldJ < P");
-    int tp = 0;
-    lds = std::max(lds, residual_lds_bytes(h->net, h->dtype, &tp));
-    BatchResidualItem& it = b->h_res[i];
-    it.net = h->net;
-    it.theta = theta[i];
-    it.X = h->X;
-    it.w = h->w;
-    it.f = h->f;
-    it.g = h->g;
-    it.kind = h->kind;
-    it.r_w = r_w[i];
-    it.J = J_w[i];
-    it.ldJ = ldJ[i];
-    it.N = h->N;
-    it.first_tile = tiles;
-    it.TP = tp;
-    it.loss_part = h->loss_part;
-    tiles += (h->N + tp - 1) / tp;
+    ldsb[i] = residual_lds_bytes(h->net, h->dtype, &tps[i]);
+    const size_t per_cu = ldsb[i] > 0 ? (160 * 1024) / ldsb[i] : 8;
+    cls[i] = per_cu >= 4 ? 0 : (per_cu >= 2 ? 1 : 2);
+  }
+  int slot = 0;
+  struct Group { int first, count; int64_t tiles; size_t lds; };
+  std::vector<Group> groups;
+  for (int c = 0; c < 3; ++c) {
+    Group gr{slot, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+      if (cls[i] != c) continue;
+      ngd_problem* h = b->inst[i];
+      BatchResidualItem& it = b->h_res[slot++];
+      it.net = h->net;
+      it.theta = theta[i];
+      it.X = h->X;
+      it.w = h->w;
+      it.f = h->f;
+      it.g = h->g;
+      it.kind = h->kind;
+      it.r_w = r_w[i];
+      it.J = J_w[i];
+      it.ldJ = ldJ[i];
+      it.N = h->N;
+      it.first_tile = gr.tiles;
+      it.TP = tps[i];
+      it.loss_part = h->loss_part;
+      gr.tiles += (h->N + tps[i] - 1) / tps[i];
+      gr.lds = std::max(gr.lds, ldsb[i]);
+      ++gr.count;
+    }
+    if (gr.count > 0) groups.push_back(gr);
   }
   NGD_HIP_TRY(hipMemcpyAsync(b->d_res, b->h_res, sizeof(BatchResidualItem) * n, hipMemcpyHostToDevice, s));
-  NGD_TRY(launch_batch_residual_jacobian(b->dtype, b->d_res, n, tiles, lds, s));
+  for (const Group& gr : groups)
+    NGD_TRY(launch_batch_residual_jacobian(b->dtype, b->d_res + gr.first, gr.count, gr.tiles, gr.lds, s));
   for (int i = 0; i < n; ++i) {
     ngd_problem* h = b->inst[i];
-    const int nt = (int)((h->N + b->h_res[i].TP - 1) / b->h_res[i].TP);
+    const int nt = (int)((h->N + tps[i] - 1) / tps[i]);
     if (loss != nullptr && loss[i] != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, nt, 1, 0.5, loss[i], s));
     if (grad != nullptr && grad[i] != nullptr) {
       const ngd_operator op{theta[i], J_w[i], ldJ[i]};
