@@ -474,7 +474,7 @@ typedef enum {
   NGD_TIMER_SKETCH_W = 3,         /* J_w^T Q contraction */
   NGD_TIMER_CORE = 4,             /* FP64 ell x ell core (both eigendecompositions and small products) */
   NGD_TIMER_PRECOND = 5,          /* preconditioner application inside PCG */
-  NGD_TIMER_SKETCH_PREP = 6,      /* transposed copies of J_w and Q feeding the second sketch product */
+  NGD_TIMER_SKETCH_PREP = 6,      /* BF16 transposed copy of J_w for the second BF16 sketch product */
   NGD_NUM_TIMERS = 7
 } ngd_timer_id;
 

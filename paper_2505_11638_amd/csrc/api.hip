@@ -62,7 +62,7 @@ struct ngd_problem {
   void* Q;           // N x max_ell, FP64 (orthonormal basis of range(Z))
   void* Bt;          // max_ell x ldP, dtype
   int64_t ldN;       // row stride of the transposed sketch operands (N rounded up to 64)
-  void* Jt;          // P x ldN, J_w^T in the sketch compute type (FP32 problems)
+  void* Jt;          // P x ldN, J_w^T in BF16 for the BF16 sketch (FP32 problems)
   void* Qt;          // max_ell x ldN, Q^T in the sketch compute type (FP32 problems)
   void* Ob;          // max_ell x ldP, Omega^T in BF16 (FP32 problems)
   void* Jc = nullptr;  // recompute-mode sketch: a block of rows of J_w (jc_rows x ldP, dtype), on first use
@@ -328,7 +328,7 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   plan.push_back({&h->Bt, (size_t)L * ldP * e});
   h->ldN = (int64_t)align_up((size_t)N, 64);
   if (d->dtype == NGD_F32) {  // sized for FP32, which also holds the BF16 copies
-    plan.push_back({&h->Jt, (size_t)P * h->ldN * 4});
+    plan.push_back({&h->Jt, (size_t)P * h->ldN * 2});
     plan.push_back({&h->Qt, (size_t)L * h->ldN * 4});
     plan.push_back({&h->Ob, (size_t)L * ldP * 2});
     // room for up to 16 slices of the larger sketch product, between 64 and 256 MB
@@ -862,8 +862,14 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
   const bool nt_rec = rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, h->jc_rows, L, P, h->ldP, ldO);
   // the NT kernel (large tiles, both operands K-contiguous) serves the FP32 / BF16 sketch
   const int et = gt == G_BF16 ? NGD_BF16 : NGD_F32;
+  // The second product reads J in place as a K-major operand in FP32; in BF16 it reads a transposed
+  // BF16 copy of J instead (made on the side stream beside the core): with the FP32 operand the BF16
+  // product is held to the rate at which its tiles' FP32 rows reach the CUs, and it ran slower than
+  // the copy and the product together.
+  const bool w_kmajor = et == NGD_F32;
   const bool nt = !rec && T == NGD_F32 && nt_gemm_supported(NGD_F32, NGD_F32, gt, N, L, P, op->ldJ, ldO) &&
-                  nt_gemm_supported(et, et, gt, P, L, N, h->ldN, h->ldN);
+                  (w_kmajor ? nt_gemm_supported(NGD_F32, et, gt, P, L, N, op->ldJ, h->ldN, true)
+                            : nt_gemm_supported(et, et, gt, P, L, N, h->ldN, h->ldN));
   // Omega^T in the compute type (BF16: a rounded copy, read at half the bytes). A column test matrix
   // has no Omega to read: its Z is a gather.
   const void* om_nt = omega;
@@ -907,9 +913,10 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
     GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
     return launch_gemm(g1, s);
   }));
-  // J^T in the compute type for the second product, on the side stream: it overlaps the
-  // latency-bound FP64 core below and is joined before the product that reads it
-  if (nt) {
+  // J^T in BF16 for the second product, on the side stream: it overlaps the latency-bound FP64 core
+  // below and is joined before the product that reads it
+  const bool w_copy = nt && !w_kmajor;
+  if (w_copy) {
     NGD_HIP_TRY(hipEventRecord(h->ev_fork, s));
     NGD_HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
     NGD_TRY(timed(h, NGD_TIMER_SKETCH_PREP, h->side, [&] {
@@ -932,8 +939,9 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
     return launch_trsm_q(h->M, (int)L, T, h->Z, N, nt ? nullptr : (double*)h->Q, et, nt ? h->Qt : nullptr, h->ldN,
                          s);
   }));
-  // B^T = Q^T J (ell x P); on the NT path as (J^T Q)^T with Q^T in the compute type
-  if (nt) NGD_HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
+  // B^T = Q^T J (ell x P); on the NT path as (J^T Q)^T with Q^T in the compute type and J^T read in
+  // place from the stored J (FP32, K-major operand) or from its BF16 copy
+  if (w_copy) NGD_HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   NGD_TRY(timed(h, NGD_TIMER_SKETCH_W, s, [&] {
     if (rec) {
       for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
@@ -945,6 +953,9 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
       }
       return NGD_OK;
     }
+    if (nt && w_kmajor)
+      return launch_nt_gemm(NGD_F32, op->J, op->ldJ, et, h->Qt, h->ldN, gt, P, L, N, NGD_F32, h->Bt, h->ldP, true,
+                            1.0, h->sk_work, h->sk_work_elems, s, true);
     if (nt) return launch_nt_gemm(et, h->Jt, h->ldN, et, h->Qt, h->ldN, gt, P, L, N, NGD_F32, h->Bt, h->ldP, true,
                                   1.0, h->sk_work, h->sk_work_elems, s);
     GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};

@@ -253,12 +253,14 @@ struct GemmArgs {
 ngd_status launch_gemm(const GemmArgs& a, hipStream_t s);
 
 // sketch_gemm.hip: C = alpha A B^T with A (M x K) and B (N x K) K-contiguous (FP32 or BF16 storage),
-// FP32 output, C^T stored when trans_c; and transposed precision copies.
+// FP32 output, C^T stored when trans_c; a_kmajor: A is given as an FP32 K x M matrix (A[m][k] at
+// k lda + m) and read without a transposed copy. Also transposed precision copies.
 bool nt_gemm_supported(int a_type, int b_type, int compute, int64_t M, int64_t N, int64_t K, int64_t lda,
-                       int64_t ldb);
+                       int64_t ldb, bool a_kmajor = false);
 ngd_status launch_nt_gemm(int a_type, const void* A, int64_t lda, int b_type, const void* B, int64_t ldb,
                           int compute, int64_t M, int64_t N, int64_t K, int c_type, void* C, int64_t ldc,
-                          bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s);
+                          bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s,
+                          bool a_kmajor = false);
 ngd_status launch_cast_rows(int src_type, const void* src, int64_t ld_s, int64_t rows, int64_t cols, int dst_type,
                             void* dst, int64_t ld_d, hipStream_t s);
 ngd_status launch_transpose_cast(int src_type, const void* src, int64_t ld_s, int64_t rows, int64_t cols,

@@ -4,6 +4,9 @@
 // second product B^T = Q^T J_w of the structured Alg. 6 runs as (J_w^T Q)^T with A = J_w^T and
 // B = Q^T, both transposed copies in the compute type, and the result written transposed. These
 // are the ell simultaneous Gramian matvecs of the sketch (Section 4.1.2, Table tab:matvec_costs).
+// The second product can also take A = J_w^T straight from the stored J_w (A "K-major": A[m][k] at
+// k lda + m), so that no transposed copy of J_w is made: the loader then reads 16-byte runs along m
+// from four K-rows and writes them to LDS as 4-k chunks of one m in a chunk-major layout.
 //
 // Tiling for gfx950: a 256 x 128 workgroup tile, 4 wave64s in a 2 x 2 arrangement, so each wave
 // owns a 128 x 64 block of 8 x 4 MFMA tiles (v_mfma_f32_16x16x32_bf16 for BF16, or
@@ -102,6 +105,54 @@ struct SlabLoader {
   }
 };
 
+// LDS layout of a K-major A slab: 16-byte chunk (kc, m) holds compute values k = kc CE .. kc CE + CE - 1
+// of row m at kc * kKcStride + 16 m. The stride is 16 (256 + 1) bytes, so the 16 lanes that the LDS
+// serves together (chunks kc + 4 i, m = 4 j + e in the writes; kc, m0 + r16 in the MFMA reads) fall
+// in 16 distinct 16-byte bank groups.
+constexpr int kKcStride = 16 * (kBM + 1);
+
+// Registers holding this thread's part of one BK x 256 slab of a K-major operand (m contiguous in
+// memory): lane l of wave w covers k-chunk kc = l % 4 and columns m = 4 (16 w + l / 4) .. + 3, that
+// is CE rows of 16 bytes (4 source values along m) each, converted to CE-value chunks along k.
+template <typename TS, typename E>
+struct KMajorLoader {
+  static_assert(sizeof(TS) == 4, "K-major operands are stored in FP32");
+  static constexpr int CE = 16 / (int)sizeof(E);  // compute values per chunk = source rows per thread
+  u4 raw[CE];
+
+  // The resource covers this slab's rows only (k0 .. min(k0 + BK, K) - 1 from column m0 on), so rows
+  // at or past K read as zero; columns past the operand's M hold values that only reach rows of C
+  // that are not stored.
+  __device__ __forceinline__ void load(const TS* tile, int64_t lda, int64_t k0, int64_t K) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kc = lane & 3, mq = 16 * w + (lane >> 2);
+    constexpr int BK = Slab<E>::BK;
+    const int64_t rows = K - k0 < BK ? K - k0 : BK;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(tile + k0 * lda), (short)0, (int)(rows * lda * (int64_t)sizeof(TS)), 0x00020000);
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+      const uint32_t off = (uint32_t)(((int64_t)(kc * CE + e) * lda + 4 * mq) * (int64_t)sizeof(TS));
+      raw[e] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    }
+  }
+  __device__ __forceinline__ void store(unsigned char* lds) const {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kc = lane & 3, mq = 16 * w + (lane >> 2);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // column m = 4 mq + j: the CE values of k-chunk kc
+      u4 o;
+      if constexpr (sizeof(E) == 4) {
+        o = u4{raw[0][j], raw[1][j], raw[2][j], raw[3][j]};
+      } else {  // the 8 FP32 values of k-chunk kc, rounded as the row loader rounds them
+        const u4 two[2] = {u4{raw[0][j], raw[1][j], raw[2][j], raw[3][j]}, u4{raw[4][j], raw[5][j], raw[6][j], raw[7][j]}};
+        o = Chunk<float, __bf16>::convert(two);
+      }
+      *reinterpret_cast<u4*>(lds + kc * kKcStride + 16 * (4 * mq + j)) = o;
+    }
+  }
+};
+
 // Buffer resource over the tile's rows of an operand whose pointer has been advanced by `kbeg`
 // columns (a split-K slice): the extent ends where the operand's last row of the tile ends.
 template <typename T>
@@ -115,7 +166,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const T* base, int64
 // Multiply one staged slab: acc[i][j] (16 x 16 tiles) += A_slab(wave rows) B_slab(wave cols)^T, for
 // the tiles i < imax, j < jmax that hold rows and columns of C (wave-uniform bounds: the MFMAs of
 // tiles wholly past the end of C are skipped, which frees the matrix core for the other waves)
-template <typename E, bool FULL>
+template <typename E, bool FULL, bool AK>
 __device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigned char* Bs, int wm, int wn,
                                           int imax, int jmax, f4 (&acc)[8][4]) {
   const int lane = threadIdx.x & 63;
@@ -126,7 +177,8 @@ __device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigne
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     if (!FULL && i >= imax) break;
-    const u4 a = *reinterpret_cast<const u4*>(As + (wm + 16 * i + r16) * kPitch + 16 * kq);
+    const u4 a = AK ? *reinterpret_cast<const u4*>(As + kq * kKcStride + 16 * (wm + 16 * i + r16))
+                    : *reinterpret_cast<const u4*>(As + (wm + 16 * i + r16) * kPitch + 16 * kq);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (!FULL && j >= jmax) break;
@@ -148,7 +200,7 @@ __device__ __forceinline__ void slab_mfma(const unsigned char* As, const unsigne
 
 // C (M x N, ldc) = alpha A B^T, or C^T stored (C[n * ldc + m]) when trans_c. With split K
 // (gridDim.y slices of kchunk), slice s writes its partial product to C + s * slice_stride.
-template <typename TA, typename TB, typename E, typename TC>
+template <typename TA, typename TB, typename E, typename TC, bool AK>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void nt_gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A,
                                                            int64_t lda, const TB* __restrict__ B, int64_t ldb,
                                                            TC* __restrict__ C, int64_t ldc, int trans_c, float alpha,
@@ -166,15 +218,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 
   // this slice's K range: the operands are offset to its start, K becomes its length
   const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
-  A += kbeg;
+  A += AK ? kbeg * lda : kbeg;
   B += kbeg;
   C += (int64_t)blockIdx.y * slice_stride;
   K = (K - kbeg) < kchunk ? (K - kbeg) : kchunk;
-  const __amdgpu_buffer_rsrc_t ra = tile_rsrc(A, m0, M, kBM, lda, kbeg);
+  // a K-major A is addressed per slab from the tile's first column
+  const TA* const at = A + m0;
   const __amdgpu_buffer_rsrc_t rb = tile_rsrc(B, n0, N, kBN, ldb, kbeg);
+  const __amdgpu_buffer_rsrc_t ra = AK ? rb : tile_rsrc(A, m0, M, kBM, lda, kbeg);  // (unused when AK)
   // two register sets per operand: the slab after next is loaded while the next one waits in
   // registers for its LDS buffer, so two slabs of global loads are in flight behind the MFMAs
-  SlabLoader<TA, E, kBM> la0, la1;
+  typename std::conditional<AK, KMajorLoader<TA, E>, SlabLoader<TA, E, kBM>>::type la0, la1;
   SlabLoader<TB, E, kBN> lb0, lb1;
   f4 acc[8][4];
 #pragma unroll
@@ -187,10 +241,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   // (FP32 only: the BF16 instantiations are large enough that a second copy of the loop costs more
   // in instruction fetch than the skipped edge tiles save)
   const bool full = sizeof(E) == 2 || (imax >= 8 && jmax >= 4);
-  la0.load(ra, lda, 0, K);
+  auto load_a = [&](auto& la, int64_t k0) {
+    if constexpr (AK) la.load(at, lda, k0, K);
+    else la.load(ra, lda, k0, K);
+  };
+  load_a(la0, 0);
   lb0.load(rb, ldb, 0, K);
   if (nk > 1) {
-    la1.load(ra, lda, BK, K);
+    load_a(la1, BK);
     lb1.load(rb, ldb, BK, K);
   }
   la0.store(As[0]);
@@ -204,10 +262,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     constexpr bool FULL = decltype(full_tag)::value;
     auto step = [&](int64_t kt, int cur, auto& la_free, auto& lb_free, auto& la_next, auto& lb_next) {
       if (kt + 2 < nk) {
-        la_free.load(ra, lda, (kt + 2) * BK, K);
+        load_a(la_free, (kt + 2) * BK);
         lb_free.load(rb, ldb, (kt + 2) * BK, K);
       }
-      slab_mfma<E, FULL>(As[cur], Bs[cur], wm, wn, imax, jmax, acc);
+      slab_mfma<E, FULL, AK>(As[cur], Bs[cur], wm, wn, imax, jmax, acc);
       if (kt + 1 < nk) {
         la_next.store(As[cur ^ 1]);
         lb_next.store(Bs[cur ^ 1]);
@@ -366,7 +424,7 @@ int choose_split(int64_t M, int64_t N, int64_t K, int BK, double slab_us, int64_
   return ks;
 }
 
-template <typename TA, typename TB, typename E, typename TC>
+template <typename TA, typename TB, typename E, typename TC, bool AK = false>
 ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                   int64_t ldc, bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s) {
   const int64_t tm = (M + kBM - 1) / kBM, tn = (N + kBN - 1) / kBN;
@@ -393,7 +451,7 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
   }
   const int64_t kchunk = ks == 1 ? K : ((K + ks - 1) / ks + BK - 1) / BK * BK;
   if (ks == 1) {
-    hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, TC>), dim3((unsigned)(per * kXcd), 1), dim3(kThreads), 0, s, M, N,
+    hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, TC, AK>), dim3((unsigned)(per * kXcd), 1), dim3(kThreads), 0, s, M, N,
                        K, (const TA*)A, lda, (const TB*)B, ldb, (TC*)C, ldc, (int)trans_c, (float)alpha, (int)tn,
                        (int)tiles, (int)per, kchunk, (int64_t)0);
     NGD_HIP_TRY(hipGetLastError());
@@ -401,7 +459,7 @@ ngd_status run_nt(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, c
   }
   // slices in the output's own orientation (rows x cols packed), then one ordered sum
   const int64_t rows = trans_c ? N : M, cols = trans_c ? M : N;
-  hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, float>), dim3((unsigned)(per * kXcd), (unsigned)ks), dim3(kThreads), 0,
+  hipLaunchKernelGGL((nt_gemm_kernel<TA, TB, E, float, AK>), dim3((unsigned)(per * kXcd), (unsigned)ks), dim3(kThreads), 0,
                      s, M, N, K, (const TA*)A, lda, (const TB*)B, ldb, work, cols, (int)trans_c, 1.0f, (int)tn,
                      (int)tiles, (int)per, kchunk, rows * cols);
   NGD_HIP_TRY(hipGetLastError());
@@ -422,14 +480,17 @@ __global__ void cast_rows_kernel(const TS* __restrict__ src, int64_t ld_s, int64
 }  // namespace
 
 bool nt_gemm_supported(int a_type, int b_type, int compute, int64_t M, int64_t N, int64_t K, int64_t lda,
-                       int64_t ldb) {
+                       int64_t ldb, bool a_kmajor) {
   auto sz = [](int t) { return t == NGD_BF16 ? 2 : (t == NGD_F32 ? 4 : 8); };
   if (compute == G_F64 || a_type == NGD_F64 || b_type == NGD_F64) return false;
   if (compute == G_F32 && (a_type != NGD_F32 || b_type != NGD_F32)) return false;
-  // 16-byte aligned rows, and 32-bit byte offsets within one tile's rows
+  if (a_kmajor && a_type != NGD_F32) return false;
+  // 16-byte aligned rows, and 32-bit byte offsets within one tile's rows (one slab's rows for a
+  // K-major A, whose rows are M long)
   if ((lda * sz(a_type)) % 16 != 0 || (ldb * sz(b_type)) % 16 != 0) return false;
-  if (lda < K || ldb < K) return false;
-  if ((int64_t)kBM * lda * sz(a_type) >= (int64_t)1 << 31 || (int64_t)kBN * ldb * sz(b_type) >= (int64_t)1 << 31)
+  if ((a_kmajor ? lda < M : lda < K) || ldb < K) return false;
+  const int64_t a_rows = a_kmajor ? 32 : kBM;
+  if (a_rows * lda * sz(a_type) >= (int64_t)1 << 31 || (int64_t)kBN * ldb * sz(b_type) >= (int64_t)1 << 31)
     return false;
   const int64_t tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
   return tiles > 0 && tiles < ((int64_t)1 << 30);
@@ -437,10 +498,20 @@ bool nt_gemm_supported(int a_type, int b_type, int compute, int64_t M, int64_t N
 
 ngd_status launch_nt_gemm(int a_type, const void* A, int64_t lda, int b_type, const void* B, int64_t ldb,
                           int compute, int64_t M, int64_t N, int64_t K, int c_type, void* C, int64_t ldc,
-                          bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s) {
-  if (!nt_gemm_supported(a_type, b_type, compute, M, N, K, lda, ldb) || c_type != NGD_F32 ||
+                          bool trans_c, double alpha, float* work, int64_t work_elems, hipStream_t s, bool a_kmajor) {
+  if (!nt_gemm_supported(a_type, b_type, compute, M, N, K, lda, ldb, a_kmajor) || c_type != NGD_F32 ||
       (trans_c ? (ldc < M || ldc % 4 != 0) : ldc < N)) {
     set_error("nt_gemm: unsupported operand types or layout");
+    return NGD_ERR_INVALID;
+  }
+  if (a_kmajor) {  // A = an FP32 matrix read K-major (no transposed copy)
+    if (compute == G_F32)
+      return run_nt<float, float, float, float, true>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work,
+                                                      work_elems, s);
+    if (b_type == NGD_BF16)
+      return run_nt<float, __bf16, __bf16, float, true>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work,
+                                                        work_elems, s);
+    set_error("nt_gemm: unsupported operand types for a K-major A");
     return NGD_ERR_INVALID;
   }
   if (compute == G_F32) return run_nt<float, float, float, float>(M, N, K, A, lda, B, ldb, C, ldc, trans_c, alpha, work, work_elems, s);
