@@ -547,7 +547,7 @@ ngd_status jc_rows_at(ngd_problem* h, const void* theta, int64_t r0, int64_t row
 // J_w's columns.
 ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
                        const void* omega, int64_t ldO, const int64_t* cols, int32_t sketch_dtype, void* U, int64_t ldU,
-                       double* lam_hat, ngd_nystrom_info* info, void* stream);
+                       double* lam_hat, ngd_nystrom_info* info, void* stream, bool defer_eig = false);
 
 ngd_status ngd_nystrom_sketch(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
                               const void* omega, int64_t ldO, int32_t sketch_dtype, void* U, int64_t ldU,
@@ -598,12 +598,26 @@ constexpr double kNoiseRel = 1e-18;
 // the FP64 case) through the eigenpairs of B^T B (Alg. 6, svd(B)): lam_hat = sigma^2 descending and
 // U = B V Sigma^{-1} as rows. Uses the handle's core buffers M, Ev, F, evals, the eigensolver's
 // workspace, vtmp[2] and (FP64) the Omega buffer.
+// the Gram matrix B^T B of the core in h->M (FP64)
+ngd_status core_gram(ngd_problem* h, void* Bt, int64_t L, hipStream_t s) {
+  GemmArgs g5{L, L, h->P, Bt, h->ldP, true, Bt, h->ldP, true, h->M, L, h->dtype, h->dtype, NGD_F64, G_F64, 1.0, 0.0,
+              h->gemm_work, h->gemm_work_elems, 1};
+  return launch_gemm(g5, s);
+}
+
+// non-FP64 problems, once h->M has been tridiagonalised: the rest of the eigensolver, then
+// U^T = (V Sigma^{-1})^T B^T
+ngd_status core_svd_finish(ngd_problem* h, void* Bt, int64_t L, void* U, int64_t ldU, double* lam_hat, hipStream_t s) {
+  NGD_TRY(launch_sym_eig_finish((int)L, kDropRel, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
+  NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
+  GemmArgs g6{L, h->P, L, h->F, L, false, Bt, h->ldP, false, U, ldU, NGD_F64, h->dtype, h->dtype, G_F64, 1.0, 0.0};
+  return launch_gemm(g6, s);
+}
+
 ngd_status core_svd(ngd_problem* h, void* Bt, int64_t L, void* U, int64_t ldU, double* lam_hat, hipStream_t s) {
   const int64_t P = h->P, ldP = h->ldP;
   const int T = h->dtype;
-  GemmArgs g5{L, L, P, Bt, ldP, true, Bt, ldP, true, h->M, L, T, T, NGD_F64, G_F64, 1.0, 0.0,
-              h->gemm_work, h->gemm_work_elems, 1};
-  NGD_TRY(launch_gemm(g5, s));
+  NGD_TRY(core_gram(h, Bt, L, s));
   NGD_TRY(launch_sym_eig(h->M, (int)L, kDropRel, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
   if (T != NGD_F64) {
     NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
@@ -829,7 +843,7 @@ ngd_status rp_ensure(ngd_problem* h) {
 
 ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint64_t seed, uint64_t counter,
                        const void* omega, int64_t ldO, const int64_t* cols, int32_t sketch_dtype, void* U, int64_t ldU,
-                       double* lam_hat, ngd_nystrom_info* info, void* stream) {
+                       double* lam_hat, ngd_nystrom_info* info, void* stream, bool defer_eig) {
   NGD_CHECK(h != nullptr && U != nullptr && lam_hat != nullptr, "NULL argument");
   NGD_TRY(check_op(h, op));
   NGD_CHECK(ell >= 1 && ell <= h->max_ell, "ell must be in [1, min(max_ell, P)]");
@@ -963,6 +977,13 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
   }));
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T (FP64
   // problems: the small pairs a second time, from B projected off the resolved ones)
+  // defer_eig (FP32 problems, no summary): stop after the Gram matrix B B^T in h->M; the caller
+  // tridiagonalises it with other problems' and completes the core with core_svd_finish
+  if (defer_eig && h->dtype != NGD_F64 && info == nullptr) {
+    NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] { return core_gram(h, h->Bt, L, s); }));
+    h->unchecked_ell = L;
+    return NGD_OK;
+  }
   NGD_TRY(timed(h, NGD_TIMER_CORE, s, [&] { return core_svd(h, h->Bt, L, U, ldU, lam_hat, s); }));
   // without a summary the call does not synchronise; the next PCG solve with this preconditioner
   // reads the core's error words instead
@@ -1693,20 +1714,45 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
   for (int i = 0; i < n; ++i) order[i] = i;
   auto cost = [&](int i) { return (double)ells[i] * (double)b->inst[i]->P * (double)(b->inst[i]->N + ells[i]); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-  NGD_HIP_TRY(hipEventRecord(b->sk_fork, s));
-  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) NGD_HIP_TRY(hipStreamWaitEvent(b->sk_stream[q], b->sk_fork, 0));
+  // FP32 members: each sketch up to its core's Gram matrix side by side, then every core's
+  // tridiagonalisation in batched launches on the caller's stream (a member's is a chain of grid
+  // barriers on a few CUs; side by side on four streams most of the device idled), then the rest of
+  // each core side by side again
+  bool batch_eig = true;
+  for (int i = 0; i < n; ++i) batch_eig = batch_eig && b->inst[i]->dtype != NGD_F64;
+  auto fork = [&] {
+    NGD_HIP_TRY(hipEventRecord(b->sk_fork, s));
+    for (int q = 0; q < ngd_batch::kSketchStreams; ++q)
+      NGD_HIP_TRY(hipStreamWaitEvent(b->sk_stream[q], b->sk_fork, 0));
+    return NGD_OK;
+  };
+  auto join = [&] {
+    for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+      NGD_HIP_TRY(hipEventRecord(b->sk_join[q], b->sk_stream[q]));
+      NGD_HIP_TRY(hipStreamWaitEvent(s, b->sk_join[q], 0));
+    }
+    return NGD_OK;
+  };
+  NGD_TRY(fork());
   for (int k = 0; k < n; ++k) {
     const int i = order[k];
     hipStream_t qs = b->sk_stream[k % ngd_batch::kSketchStreams];
     // member i's test matrix from its own counter range (counter, i)
     NGD_TRY(sketch_impl(b->inst[i], &ops[i], ells[i], seed, counter + ((uint64_t)i << 32), nullptr, 0, nullptr,
-                        sketch_dtype, U[i], ldU[i], lam_hat[i], nullptr, qs));
+                        sketch_dtype, U[i], ldU[i], lam_hat[i], nullptr, qs, batch_eig));
   }
-  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
-    NGD_HIP_TRY(hipEventRecord(b->sk_join[q], b->sk_stream[q]));
-    NGD_HIP_TRY(hipStreamWaitEvent(s, b->sk_join[q], 0));
+  NGD_TRY(join());
+  if (!batch_eig) return NGD_OK;
+  std::vector<EigJob> jobs(n);
+  for (int i = 0; i < n; ++i) jobs[i] = EigJob{static_cast<double*>(b->inst[i]->M), (int)ells[i], b->inst[i]->eigw, false};
+  NGD_TRY(launch_sym_eig_tridiag_batch(jobs.data(), n, s));
+  NGD_TRY(fork());
+  for (int k = 0; k < n; ++k) {
+    const int i = order[k];
+    hipStream_t qs = b->sk_stream[k % ngd_batch::kSketchStreams];
+    NGD_TRY(core_svd_finish(b->inst[i], b->inst[i]->Bt, ells[i], U[i], ldU[i], lam_hat[i], qs));
   }
-  return NGD_OK;
+  return join();
 }
 
 // Average time of one batched matvec launch (the PCG iteration's one pass over every J_w) on the

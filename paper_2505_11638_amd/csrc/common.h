@@ -276,6 +276,21 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
                           hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
                           hipEvent_t join = nullptr, bool keep_err = false);
 const int* eig_error_flag(void* work, int n);
+// The same eigensolver for several matrices: launch_sym_eig_tridiag_batch clears each job's words and
+// tridiagonalises every matrix in batched launches on s (one per register shape, the workgroups of
+// each matrix meeting only among themselves); launch_sym_eig_finish then completes one job (after
+// its tridiagonalisation, on any stream ordered after s). Together they compute what launch_sym_eig
+// computes, bitwise.
+struct EigJob {
+  double* A;
+  int n;
+  void* work;
+  bool keep_err;
+};
+ngd_status launch_sym_eig_tridiag_batch(const EigJob* jobs, int n, hipStream_t s);
+ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
+                                 hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
+                                 hipEvent_t join = nullptr);
 
 // misc.hip
 ngd_status launch_gaussian_omega(int dtype, uint64_t seed, uint64_t counter, int64_t P, int64_t ell, void* out,

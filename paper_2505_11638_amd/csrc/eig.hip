@@ -17,6 +17,9 @@
 // n <= 1024.
 // Eigenpairs whose eigenvalue is below drop_rel * (Gershgorin bound of T) are returned as
 // (0, zero vector).
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 
 namespace ngd {
@@ -64,21 +67,21 @@ __device__ __forceinline__ double ld_coherent(double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier number `epoch` for data exchanged only through st_coherent / ld_coherent. The flags of up
-// to 64 workgroups are polled by wave 0 (one per lane). The wait is bounded; on timeout the error
-// word is raised and false is returned to the whole workgroup.
-__device__ bool grid_sync_coherent(unsigned* flags, unsigned epoch, int* err, int* timed_out) {
+// Barrier number `epoch` among the G workgroups of one matrix (this one is number gme) for data
+// exchanged only through st_coherent / ld_coherent. The flags of up to 64 workgroups are polled by
+// wave 0 (one per lane). The wait is bounded; on timeout the error word is raised and false is
+// returned to the whole workgroup.
+__device__ bool grid_sync_coherent(unsigned* flags, unsigned epoch, int* err, int* timed_out, int gme, int G) {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   if (threadIdx.x < 64) {
     const unsigned target = epoch + 1u;
-    if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(flags + gme, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     while (true) {
       const int g = threadIdx.x;
-      const bool ok = g >= (int)gridDim.x ||
-                      __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+      const bool ok = g >= G || __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
       if (__all(ok)) break;
       if (++spins > (1L << 24)) {  // seconds: give up instead of hanging
         if (threadIdx.x == 0) {
@@ -109,8 +112,9 @@ __device__ __forceinline__ double read_lane(double t, int l) {
     (out) = read_lane(t_, (j) & 63);                   \
   } while (0)
 
+// The tridiagonalisation of one matrix by workgroup g of its G workgroups.
 template <int QN, int kTrRows, int kTrWaves>
-__global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
+__device__ __forceinline__ void tridiag_body(const TriArgs& a, const int g, const int G) {
   constexpr int kTrThreads = 64 * kTrWaves;
   constexpr int kTrCols = kTrMaxN / kTrThreads;  // per-column LDS entries per thread
   __shared__ double vbuf[2][kTrMaxN];  // v of this step and of the previous one (by parity)
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
   __shared__ double pivl[kTrMaxN];     // the pivot row (before the pending update)
   __shared__ double tau_s;
   __shared__ int timed_out;
-  const int n = a.n, G = gridDim.x, g = blockIdx.x;
+  const int n = a.n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (threadIdx.x == 0) timed_out = 0;
   double rows[kTrRows][QN];
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
       }
     }
     // (D)
-    if (!grid_sync_coherent(a.flags, (unsigned)k, a.err, &timed_out)) return;
+    if (!grid_sync_coherent(a.flags, (unsigned)k, a.err, &timed_out, g, G)) return;
     // (E) p_k and pivot row k+1
     double pl[kTrCols], nl[kTrCols];
 #pragma unroll
@@ -293,6 +297,27 @@ __global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
     for (int q = 0; q < QN; ++q)
       if (lane + 64 * q == m + 1) a.d[m + 1] = rows[s][q] - 2.0 * vm1 * wm1;
   }
+}
+
+template <int QN, int kTrRows, int kTrWaves>
+__global__ __launch_bounds__(64 * kTrWaves) void tridiag_reg_kernel(TriArgs a) {
+  tridiag_body<QN, kTrRows, kTrWaves>(a, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Several matrices of one register shape in one launch: matrix m has workgroups first[m] ..
+// first[m + 1] - 1, which meet only among themselves. The arguments travel by value.
+constexpr int kTriBatchMax = 24;
+struct TriBatch {
+  TriArgs a[kTriBatchMax];
+  int first[kTriBatchMax + 1];
+  int n;
+};
+
+template <int QN, int kTrRows, int kTrWaves>
+__global__ __launch_bounds__(64 * kTrWaves) void tridiag_batch_kernel(TriBatch tb) {
+  int m = 0;
+  while (m + 1 < tb.n && (int)blockIdx.x >= tb.first[m + 1]) ++m;
+  tridiag_body<QN, kTrRows, kTrWaves>(tb.a[m], (int)blockIdx.x - tb.first[m], tb.first[m + 1] - tb.first[m]);
 }
 
 // Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots of T - x I). The pivot
@@ -866,6 +891,76 @@ ngd_status launch_tridiag(const TriArgs& ta, hipStream_t s) {
   return NGD_ERR_INVALID;
 }
 
+template <int QN>
+ngd_status launch_tridiag_batch_qn(const TriArgs* items, int n, hipStream_t s) {
+  constexpr int RW = tr_rows(QN), WV = tr_waves(QN);
+  const int per = WV * RW;
+  for (int c0 = 0; c0 < n; c0 += kTriBatchMax) {
+    TriBatch tb{};
+    tb.n = std::min(kTriBatchMax, n - c0);
+    int total = 0;
+    for (int m = 0; m < tb.n; ++m) {
+      tb.a[m] = items[c0 + m];
+      tb.first[m] = total;
+      const int blocks = (tb.a[m].n + per - 1) / per;
+      if (blocks > 64) {
+        set_error("tridiagonalisation: more than 64 workgroups");
+        return NGD_ERR_INVALID;
+      }
+      total += blocks;
+    }
+    tb.first[tb.n] = total;
+    NGD_TRY(check_coresident((const void*)tridiag_batch_kernel<QN, RW, WV>, 64 * WV, 0, total));
+    hipLaunchKernelGGL((tridiag_batch_kernel<QN, RW, WV>), dim3(total), dim3(64 * WV), 0, s, tb);
+    NGD_HIP_TRY(hipGetLastError());
+  }
+  return NGD_OK;
+}
+
+// the matrices of each register shape (ceil(n / 64) columns per lane) in launches of their own
+ngd_status launch_tridiag_batch(const TriArgs* items, int n, hipStream_t s) {
+  std::vector<TriArgs> cls;
+  for (int q = 1; q <= kTrMaxN / 64; ++q) {
+    cls.clear();
+    for (int i = 0; i < n; ++i)
+      if (items[i].n >= 1 && (items[i].n + 63) / 64 == q) cls.push_back(items[i]);
+    if (cls.empty()) continue;
+    const int m = (int)cls.size();
+    switch (q) {
+      case 1: NGD_TRY(launch_tridiag_batch_qn<1>(cls.data(), m, s)); break;
+      case 2: NGD_TRY(launch_tridiag_batch_qn<2>(cls.data(), m, s)); break;
+      case 3: NGD_TRY(launch_tridiag_batch_qn<3>(cls.data(), m, s)); break;
+      case 4: NGD_TRY(launch_tridiag_batch_qn<4>(cls.data(), m, s)); break;
+      case 5: NGD_TRY(launch_tridiag_batch_qn<5>(cls.data(), m, s)); break;
+      case 6: NGD_TRY(launch_tridiag_batch_qn<6>(cls.data(), m, s)); break;
+      case 7: NGD_TRY(launch_tridiag_batch_qn<7>(cls.data(), m, s)); break;
+      case 8: NGD_TRY(launch_tridiag_batch_qn<8>(cls.data(), m, s)); break;
+      case 9: NGD_TRY(launch_tridiag_batch_qn<9>(cls.data(), m, s)); break;
+      case 10: NGD_TRY(launch_tridiag_batch_qn<10>(cls.data(), m, s)); break;
+      case 11: NGD_TRY(launch_tridiag_batch_qn<11>(cls.data(), m, s)); break;
+      case 12: NGD_TRY(launch_tridiag_batch_qn<12>(cls.data(), m, s)); break;
+      case 13: NGD_TRY(launch_tridiag_batch_qn<13>(cls.data(), m, s)); break;
+      case 14: NGD_TRY(launch_tridiag_batch_qn<14>(cls.data(), m, s)); break;
+      case 15: NGD_TRY(launch_tridiag_batch_qn<15>(cls.data(), m, s)); break;
+      default: NGD_TRY(launch_tridiag_batch_qn<16>(cls.data(), m, s)); break;
+    }
+  }
+  return NGD_OK;
+}
+
+// Zero the words a call must start from and fill the tridiagonalisation's arguments.
+ngd_status sym_eig_prepare(double* A, int n, void* work, hipStream_t s, bool keep_err, TriArgs* ta) {
+  EigWs ws(work, n);
+  // the barrier flags, and the error word unless an earlier call's must survive (it lies after them)
+  ngd_status st = launch_zero(ws.flags, keep_err ? sizeof(unsigned) * 248 : 1024, s);
+  if (st != NGD_OK) return st;
+  st = launch_zero(ws.tau, sizeof(double) * n, s);
+  if (st != NGD_OK) return st;
+  // exchange buffers of the tridiagonalisation (2 n each): PV in A1, P in wk (both free until it is done)
+  *ta = TriArgs{A, ws.A1, n, ws.dvec, ws.evec, ws.V, ws.tau, ws.wk, ws.flags, ws.err};
+  return NGD_OK;
+}
+
 }  // namespace
 
 size_t eig_workspace_bytes(int n) { return EigWs(nullptr, n).bytes; }
@@ -877,6 +972,30 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
     set_error("symmetric eigensolver: n above 1024");
     return NGD_ERR_INVALID;
   }
+  TriArgs ta;
+  NGD_TRY(sym_eig_prepare(A, n, work, s, keep_err, &ta));
+  NGD_TRY(launch_tridiag(ta, s));
+  return launch_sym_eig_finish(n, drop_rel, evals_desc, evec_rows, work, s, side, fork, join);
+}
+
+ngd_status launch_sym_eig_tridiag_batch(const EigJob* jobs, int n, hipStream_t s) {
+  std::vector<TriArgs> items;
+  for (int i = 0; i < n; ++i) {
+    if (jobs[i].n <= 0) continue;
+    if (jobs[i].n > kBtMaxN) {
+      set_error("symmetric eigensolver: n above 1024");
+      return NGD_ERR_INVALID;
+    }
+    TriArgs ta;
+    NGD_TRY(sym_eig_prepare(jobs[i].A, jobs[i].n, jobs[i].work, s, jobs[i].keep_err, &ta));
+    items.push_back(ta);
+  }
+  return launch_tridiag_batch(items.data(), (int)items.size(), s);
+}
+
+ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
+                                 hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+  if (n <= 0) return NGD_OK;
   EigWs ws(work, n);
   double* A1 = ws.A1;
   double* V = ws.V;
@@ -888,17 +1007,6 @@ ngd_status launch_sym_eig(double* A, int n, double drop_rel, double* evals_desc,
   double* e2 = ws.e2;
   double* lam = ws.lam;
   double* tnorm = ws.tnorm;
-  int* err = ws.err;
-  {
-    // the barrier flags, and the error word unless an earlier call's must survive (it lies after them)
-    ngd_status st = launch_zero(ws.flags, keep_err ? sizeof(unsigned) * 248 : 1024, s);
-    if (st != NGD_OK) return st;
-    st = launch_zero(tau, sizeof(double) * n, s);
-    if (st != NGD_OK) return st;
-  }
-  // exchange buffers of the tridiagonalisation (2 n each): PV in A1, P in wk (both free until it is done)
-  TriArgs ta{A, A1, n, dvec, evec, V, tau, wk, ws.flags, err};
-  NGD_TRY(launch_tridiag(ta, s));
   // The explicit Q = H_0 ... H_{n-3} needs only the reflectors: on the side stream (when given) it
   // overlaps the eigenvalues, the eigenvectors of T and their orthogonalisation below, and the
   // back-transformation becomes one product Q Z at the end.

@@ -147,3 +147,25 @@ def test_c5_workload_members_against_oracle():
               f"PCG {outs[i].iters} its, true residual {res:.1e}", flush=True)
         assert err <= 1e-5
     b.close()
+
+
+def test_batch_sketch_equals_member_sketches():
+    """The batched sketch (each member's core tridiagonalised in batched launches, one per register
+    shape, with the rest of each core side by side) against every member's own single-problem sketch
+    with the same test matrix: the same arithmetic, so U and the eigenvalues agree bitwise. The c5
+    members span ell = 50-400, i.e. four register shapes, and several matrices share each launch."""
+    probs = wl.batch_instances(seed=0)
+    b = Batch(probs, dtype="f32")
+    ths = [wl.glorot_theta(p.widths, i) for i, p in enumerate(probs)]
+    thetas = [m.theta(t) for m, t in zip(b.members, ths)]
+    Js = [m.new_jacobian() for m in b.members]
+    b.residual_jacobian(thetas, Js)
+    ells = [p.ell for p in probs]
+    pcs = b.nystrom_sketch(Js, ells, seed=5, counter=2)
+    torch.cuda.synchronize()
+    print(f"batched sketch of {len(probs)} members, ell in {sorted(set(ells))}", flush=True)
+    for i, (m, J) in enumerate(zip(b.members, Js)):
+        one = m.nystrom_sketch(J, ells[i], seed=5, counter=2 + (i << 32), sketch_dtype="f32")
+        assert torch.equal(one.lam_hat, pcs[i].lam_hat), f"member {i}: eigenvalues differ"
+        assert torch.equal(one.U[:, :m.P], pcs[i].U[:, :m.P]), f"member {i}: U differs"
+    b.close()
