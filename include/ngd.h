@@ -455,6 +455,20 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
                                     double* const* lam_hat, void* stream);
 
 /*
+ * ngd_line_search for every member (Armijo backtracking, Alg. 1's line search, Section 4.4), with the
+ * acceptance test of each trial step on the device: every round evaluates the next trial steps of all
+ * members still searching, side by side on the batch's streams, and brings back one decision per
+ * member, so the host waits once per round (usually once) instead of once per member. Member i's
+ * accepted step, new loss and theta_out are those ngd_line_search returns for it.
+ *   theta, d, grad, theta_out : host arrays of n device pointers (as for ngd_line_search; theta_out[i]
+ *                               may alias theta[i]). loss0 : host, n doubles (finite).
+ *   alpha, loss_new : host, n doubles, out. Synchronises.
+ */
+ngd_status ngd_batch_line_search(ngd_batch* b, void* const* theta, double* const* d, double* const* grad,
+                                 const double* loss0, double c1, int32_t max_halvings, void* const* theta_out,
+                                 double* alpha, double* loss_new, void* stream);
+
+/*
  * Measurement: the average duration of one batched matvec launch (the PCG iteration's single pass
  * over every member's J_w) on the directions of the last batched solve, from HIP events around `reps`
  * launches on `stream` (they rewrite only the solve's scratch directions). Synchronises.

@@ -105,6 +105,10 @@ SIGNATURES = {
                                            C.c_uint64, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                            C.POINTER(C.c_void_p), C.c_void_p]),
     "ngd_batch_matvec_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
+    "ngd_batch_line_search": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.c_double, C.c_int32,
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.c_void_p]),
     "ngd_timing_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ngd_timing_enable_mask": (C.c_int, [C.c_void_p, C.c_uint32]),
     "ngd_timing_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),

@@ -458,6 +458,18 @@ class Batch:
                 "ngd_batch_nystrom_sketch")
         return res
 
+    def line_search(self, thetas, ds, grads, loss0, c1=1e-4, max_halvings=30, theta_outs=None):
+        """ngd_batch_line_search: every member's Armijo step with the decisions on the device. loss0:
+        host floats. Returns (theta_outs, alphas, new losses) as lists."""
+        n = len(self.members)
+        theta_outs = [torch.empty_like(t) for t in thetas] if theta_outs is None else theta_outs
+        l0 = (C.c_double * n)(*[float(x) for x in loss0])
+        a, ln = (C.c_double * n)(), (C.c_double * n)()
+        L.check(self.lib.ngd_batch_line_search(self.b, self._ptrs(thetas), self._ptrs(ds), self._ptrs(grads), l0,
+                                               float(c1), int(max_halvings), self._ptrs(theta_outs), a, ln,
+                                               _stream()), "ngd_batch_line_search")
+        return theta_outs, list(a), list(ln)
+
     def pcg_solve_damped(self, Js, gs, c_lam, c_loss, losses, precs, rtol=1e-6, maxit=1000):
         """ngd_batch_pcg_solve_damped: the damping rule on the device per member. Returns the PcgResults
         (with mu set)."""

@@ -1312,6 +1312,7 @@ struct ngd_batch {
   hipStream_t sk_stream[kSketchStreams] = {};
   hipEvent_t sk_fork = nullptr, sk_join[kSketchStreams] = {};
   int* h_err = nullptr;               // pinned: two error words per member (sketch core checks)
+  double* h_ls = nullptr;             // pinned: the line search's decision per member (4 doubles)
 };
 
 namespace {
@@ -1326,6 +1327,7 @@ void batch_release(ngd_batch* b) {
   }
   if (b->sk_fork) (void)hipEventDestroy(b->sk_fork);
   if (b->h_err) (void)hipHostFree(b->h_err);
+  if (b->h_ls) (void)hipHostFree(b->h_ls);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -1373,7 +1375,8 @@ ngd_status ngd_batch_create(const ngd_problem_desc* descs, int32_t n, ngd_batch*
             hipHostMalloc(&b->h_res, sizeof(BatchResidualItem) * n, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&b->h_pcg, sizeof(PcgBatchItem) * n, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(&b->h_states, sizeof(PcgState) * n, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc(&b->h_err, sizeof(int) * 2 * n, hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(&b->h_err, sizeof(int) * 2 * n, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_ls, sizeof(double) * 4 * n, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     batch_release(b);
     set_error("batch allocation failed");
@@ -1688,6 +1691,17 @@ ngd_status ngd_batch_pcg_solve_damped(ngd_batch* b, const ngd_operator* ops, con
   return batch_pcg_impl(b, ops, g, nullptr, loss, c_lam, c_loss, precs, rtol, maxit, d, infos, lambda_used, stream);
 }
 
+// the batch's pool streams and their fork / join events, created on first use
+ngd_status batch_streams(ngd_batch* b) {
+  if (b->sk_fork != nullptr) return NGD_OK;
+  NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_fork, hipEventDisableTiming));
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+    NGD_HIP_TRY(hipStreamCreateWithFlags(&b->sk_stream[q], hipStreamNonBlocking));
+    NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_join[q], hipEventDisableTiming));
+  }
+  return NGD_OK;
+}
+
 // The members' Nystrom sketches side by side: member i (largest cost first) on pool stream
 // i % kSketchStreams, forked from and joined back to the caller's stream; no host round trip.
 ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const int64_t* ells, uint64_t seed,
@@ -1702,13 +1716,7 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
     NGD_CHECK(ells[i] >= 1 && ells[i] <= h->max_ell, "ell must be in [1, min(max_ell, P)] for every problem");
     NGD_CHECK(U[i] != nullptr && lam_hat[i] != nullptr && ldU[i] >= h->P, "bad output of a problem");
   }
-  if (b->sk_fork == nullptr) {
-    NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_fork, hipEventDisableTiming));
-    for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
-      NGD_HIP_TRY(hipStreamCreateWithFlags(&b->sk_stream[q], hipStreamNonBlocking));
-      NGD_HIP_TRY(hipEventCreateWithFlags(&b->sk_join[q], hipEventDisableTiming));
-    }
-  }
+  NGD_TRY(batch_streams(b));
   hipStream_t s = S(stream);
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -1753,6 +1761,88 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
     NGD_TRY(core_svd_finish(b->inst[i], b->inst[i]->Bt, ells[i], U[i], ldU[i], lam_hat[i], qs));
   }
   return join();
+}
+
+// Every member's Armijo line search (as ngd_line_search) with the decisions on the device: each round
+// evaluates the next trial steps of every member still searching (side by side on the batch's
+// streams) and the host reads back only which members are done, once per round for all of them.
+ngd_status ngd_batch_line_search(ngd_batch* b, void* const* theta, double* const* d, double* const* grad,
+                                 const double* loss0, double c1, int32_t max_halvings, void* const* theta_out,
+                                 double* alpha, double* loss_new, void* stream) {
+  NGD_CHECK(b != nullptr && theta && d && grad && loss0 && theta_out && alpha && loss_new, "NULL argument");
+  NGD_CHECK(max_halvings >= 0 && c1 >= 0.0, "max_halvings >= 0 and c1 >= 0 required");
+  const int n = (int)b->inst.size();
+  for (int i = 0; i < n; ++i)
+    NGD_CHECK(theta[i] && d[i] && grad[i] && theta_out[i] && std::isfinite(loss0[i]), "bad argument of a problem");
+  NGD_TRY(batch_streams(b));
+  hipStream_t s = S(stream);
+  auto fork = [&] {
+    NGD_HIP_TRY(hipEventRecord(b->sk_fork, s));
+    for (int q = 0; q < ngd_batch::kSketchStreams; ++q)
+      NGD_HIP_TRY(hipStreamWaitEvent(b->sk_stream[q], b->sk_fork, 0));
+    return NGD_OK;
+  };
+  auto join = [&] {
+    for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+      NGD_HIP_TRY(hipEventRecord(b->sk_join[q], b->sk_stream[q]));
+      NGD_HIP_TRY(hipStreamWaitEvent(s, b->sk_join[q], 0));
+    }
+    return NGD_OK;
+  };
+  // per member: the slope grad^T d, a cleared decision [found, alpha, loss, index] at scal + 100
+  NGD_TRY(fork());
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    hipStream_t qs = b->sk_stream[i % ngd_batch::kSketchStreams];
+    NGD_TRY(launch_dot(grad[i], d[i], h->P, h->scal + 8, h->scal + 0, qs));
+    NGD_TRY(launch_zero(h->scal + 100, sizeof(double) * 4, qs));
+  }
+  std::vector<int> tried(n, 0), active(n);
+  for (int i = 0; i < n; ++i) active[i] = i;
+  double* hst = b->h_ls;
+  bool first = true;
+  while (!active.empty()) {
+    for (int i : active) {
+      ngd_problem* h = b->inst[i];
+      hipStream_t qs = b->sk_stream[i % ngd_batch::kSketchStreams];
+      const int batch = first ? h->ls_first_batch : h->ls_batch;
+      const int nt = std::min(batch, max_halvings + 1 - tried[i]);
+      double* ha = reinterpret_cast<double*>(h->host) + 8;  // this member's pinned staging of the steps
+      for (int t = 0; t < nt; ++t) ha[t] = std::ldexp(1.0, -(tried[i] + t));
+      NGD_HIP_TRY(hipMemcpyAsync(h->alphas, ha, sizeof(double) * nt, hipMemcpyHostToDevice, qs));
+      NGD_TRY(launch_axpy_theta(h->dtype, theta[i], d[i], h->alphas, nt, h->P, h->trial, h->ldP, qs));
+      const int nb = residual_blocks(h->net, h->dtype, h->N, false);
+      NGD_CHECK(nb <= h->res_blocks, "residual launch exceeds its loss-partial buffer");
+      NGD_TRY(launch_residual_jacobian(h->net, h->dtype, h->trial, h->N, h->X, h->w, h->f, h->g, h->kind, nullptr,
+                                       nullptr, 0, h->loss_part, h->ldP, nt, qs, nullptr));
+      NGD_TRY(launch_reduce_sum(h->loss_part, nb, nt, 0.5, h->losses, qs));
+      NGD_TRY(launch_armijo(h->alphas, h->losses, h->scal + 0, loss0[i], c1, nt, tried[i], h->scal + 100, qs));
+      NGD_HIP_TRY(hipMemcpyAsync(hst + 4 * (size_t)i, h->scal + 100, sizeof(double) * 4, hipMemcpyDeviceToHost, qs));
+      tried[i] += nt;
+    }
+    NGD_TRY(join());
+    NGD_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int i : active)
+      if (hst[4 * (size_t)i] == 0.0 && tried[i] <= max_halvings) next.push_back(i);
+    active.swap(next);
+    first = false;
+    if (!active.empty()) NGD_TRY(fork());
+  }
+  // theta_out = theta - alpha d with the accepted alpha (0 when none was: theta_out = theta)
+  NGD_TRY(fork());
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    hipStream_t qs = b->sk_stream[i % ngd_batch::kSketchStreams];
+    const bool found = hst[4 * (size_t)i] != 0.0;
+    alpha[i] = found ? hst[4 * (size_t)i + 1] : 0.0;
+    loss_new[i] = found ? hst[4 * (size_t)i + 2] : loss0[i];
+    h->ls_first_batch = found && hst[4 * (size_t)i + 3] == 0.0 ? 1 : h->ls_batch;
+    NGD_TRY(launch_axpy_theta(h->dtype, theta[i], d[i], nullptr, 1, h->P, theta_out[i], h->ldP, qs, alpha[i]));
+  }
+  NGD_TRY(join());
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  return NGD_OK;
 }
 
 // Average time of one batched matvec launch (the PCG iteration's one pass over every J_w) on the

@@ -302,6 +302,9 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
                              int64_t P, void* out, int64_t out_stride, hipStream_t s, double alpha0 = 0.0);
 ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
                               double* out, hipStream_t s);
+// Armijo decision for nt trials on the device: st = [found, alpha, loss, index] (left as it is once found)
+ngd_status launch_armijo(const double* alphas, const double* losses, const double* slope, double loss0, double c1,
+                         int nt, int tried, double* st, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);
 // the damping rule of Section 4.3 for n problems (pointer tables in device memory), and Alg. 4's
 // sketch-size update (out: device int64)

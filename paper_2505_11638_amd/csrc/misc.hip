@@ -41,6 +41,27 @@ __global__ void theta_trial_kernel(const T* __restrict__ theta, const double* __
   if (j < P) out[t * stride + j] = (T)((double)theta[j] - a * d[j]);
 }
 
+// Armijo decision on the device (Alg. 1's line search) for trials tried .. tried + nt - 1 with steps
+// alphas[t] and losses[t]: the first t with loss <= loss0 - c1 alpha slope is taken, in the same
+// operation order as on the host (no fused multiply-add), unless an earlier round took one.
+// st: [0] found (0 / 1), [1] alpha, [2] loss, [3] index.
+__global__ void armijo_kernel(const double* __restrict__ alphas, const double* __restrict__ losses,
+                              const double* __restrict__ slope, double loss0, double c1, int nt, int tried,
+                              double* __restrict__ st) {
+  if (threadIdx.x != 0 || st[0] != 0.0) return;
+  const double g = *slope;
+  for (int t = 0; t < nt; ++t) {
+    const double a = alphas[t], Lt = losses[t];
+    if (Lt <= __dsub_rn(loss0, __dmul_rn(__dmul_rn(c1, a), g))) {
+      st[0] = 1.0;
+      st[1] = a;
+      st[2] = Lt;
+      st[3] = (double)(tried + t);
+      return;
+    }
+  }
+}
+
 // The sketch's summary for the host, gathered so that one copy brings it back:
 // out[0] = lam[0], out[1] = lam[L-1], out[2] = #{lam > 0}, out[3] = core[1] (the shift nu),
 // out[4] = the modified-pivot count (an int stored at core[10]), out[5], out[6] = the error words.
@@ -204,6 +225,13 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
   else
     hipLaunchKernelGGL(theta_trial_kernel<float>, grid, dim3(256), 0, s, (const float*)theta, d, alphas, alpha0, P,
                        (float*)out, out_stride);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_armijo(const double* alphas, const double* losses, const double* slope, double loss0, double c1,
+                         int nt, int tried, double* st, hipStream_t s) {
+  hipLaunchKernelGGL(armijo_kernel, dim3(1), dim3(64), 0, s, alphas, losses, slope, loss0, c1, nt, tried, st);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -167,8 +167,9 @@ class NGD:
 class BatchNGD:
     """NGD (Alg. 1) on many independent problems at once: residuals and Jacobians of all problems in
     one batched launch, every problem's Nystrom sketch (Alg. 4/6, its own ell) side by side with no host
-    round trip, each problem's damping on the device and one batched PCG solve for all, then each
-    problem's Armijo step. Plain CG ("cg") takes each problem's lam1_hat from 4 power iterations."""
+    round trip, each problem's damping on the device and one batched PCG solve for all, then every
+    problem's Armijo step in one batched line search. Plain CG ("cg") takes each problem's lam1_hat from
+    4 power iterations."""
 
     def __init__(self, datas, thetas0, *, solver="nystrom", rtol=1e-6, gamma=10.0, seed=0):
         self.batch = Batch(datas, dtype="f32")
@@ -199,9 +200,6 @@ class BatchNGD:
                 mus.append(m.damping(l1, loss, self.gamma * self.eps, 1e-4)[1])
             outs = b.pcg_solve(self.Js, grads, mus, None, rtol=self.rtol, maxit=max(m.P for m in b.members))
         L0 = torch.cat(losses).cpu().numpy()
-        news = []
-        for m, th, o, g, l0 in zip(b.members, self.thetas, outs, grads, L0):
-            _, alpha, l1 = m.line_search(th, o.d, g, float(l0), theta_out=th)
-            news.append(l1)
+        _, _, news = b.line_search(self.thetas, [o.d for o in outs], grads, L0, theta_outs=self.thetas)
         self.k += 1
         return L0, np.array(news), outs

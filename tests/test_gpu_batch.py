@@ -169,3 +169,44 @@ def test_batch_sketch_equals_member_sketches():
         assert torch.equal(one.lam_hat, pcs[i].lam_hat), f"member {i}: eigenvalues differ"
         assert torch.equal(one.U[:, :m.P], pcs[i].U[:, :m.P]), f"member {i}: U differs"
     b.close()
+
+
+def test_batch_line_search_equals_member_line_searches():
+    """The batched line search (decisions on the device, one host wait per round for all members) against
+    each member's own ngd_line_search from the same theta, d, gradient and loss: the same step, the same
+    new loss and the same theta_out, bitwise. Members get a descent direction (the gradient, scaled so
+    that some accept alpha = 1 and some need halvings) or an ascent direction (never accepted: alpha = 0
+    after max_halvings halvings, theta unchanged)."""
+    mem = _members(n=6, seed=11)
+    b = Batch([p for p, _ in mem], dtype="f32")
+    thetas = [m.theta(th) for m, (_, th) in zip(b.members, mem)]
+    Js = [m.new_jacobian() for m in b.members]
+    _, grads, losses = b.residual_jacobian(thetas, Js)
+    L0 = [float(l.item()) for l in losses]
+    scales = [1.0, 40.0, -1.0, 0.3, 300.0, -5.0]
+    ds = [g * s for g, s in zip(grads, scales)]
+    for max_h in (4, 30):
+        ref = []
+        for m, th, d, g, l0 in zip(b.members, thetas, ds, grads, L0):
+            out, a, ln = m.line_search(th, d, g, l0, max_halvings=max_h)
+            ref.append((out, a, ln))
+        outs, alphas, news = b.line_search(thetas, ds, grads, L0, max_halvings=max_h)
+        torch.cuda.synchronize()
+        for i, (out, a, ln) in enumerate(ref):
+            print(f"max_halvings {max_h} member {i}: scale {scales[i]}, alpha {a} / {alphas[i]}, "
+                  f"loss {l0_fmt(L0[i])} -> {ln:.6e} / {news[i]:.6e}", flush=True)
+            assert alphas[i] == a and news[i] == ln
+            assert torch.equal(outs[i], out)
+            if scales[i] < 0:
+                assert a == 0.0 and torch.equal(out, thetas[i])
+    # in place: theta_outs aliasing thetas
+    before = [t.clone() for t in thetas]
+    _, alphas, _ = b.line_search(thetas, ds, grads, L0, theta_outs=thetas)
+    for i, m in enumerate(b.members):
+        exp, _, _ = m.line_search(before[i], ds[i], grads[i], L0[i])
+        assert torch.equal(thetas[i], exp)
+    b.close()
+
+
+def l0_fmt(x):
+    return f"{x:.6e}"
