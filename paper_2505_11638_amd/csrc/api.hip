@@ -605,10 +605,10 @@ ngd_status core_gram(ngd_problem* h, void* Bt, int64_t L, hipStream_t s) {
   return launch_gemm(g5, s);
 }
 
-// non-FP64 problems, once h->M has been tridiagonalised: the rest of the eigensolver, then
-// U^T = (V Sigma^{-1})^T B^T
+// non-FP64 problems, once h->M has gone through the eigensolver's batched stages: the rest of it,
+// then U^T = (V Sigma^{-1})^T B^T
 ngd_status core_svd_finish(ngd_problem* h, void* Bt, int64_t L, void* U, int64_t ldU, double* lam_hat, hipStream_t s) {
-  NGD_TRY(launch_sym_eig_finish((int)L, kDropRel, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_fork, h->ev_join));
+  NGD_TRY(launch_sym_eig_rest((int)L, kDropRel, lam_hat, h->Ev, h->eigw, s, h->side, h->ev_join));
   NGD_TRY(launch_whitening(lam_hat, h->Ev, (int)L, h->F, s));
   GemmArgs g6{L, h->P, L, h->F, L, false, Bt, h->ldP, false, U, ldU, NGD_F64, h->dtype, h->dtype, G_F64, 1.0, 0.0};
   return launch_gemm(g6, s);
@@ -1723,9 +1723,10 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
   auto cost = [&](int i) { return (double)ells[i] * (double)b->inst[i]->P * (double)(b->inst[i]->N + ells[i]); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
   // FP32 members: each sketch up to its core's Gram matrix side by side, then every core's
-  // tridiagonalisation in batched launches on the caller's stream (a member's is a chain of grid
-  // barriers on a few CUs; side by side on four streams most of the device idled), then the rest of
-  // each core side by side again
+  // tridiagonalisation, multisection, inverse iteration and cluster orthogonalisation in batched
+  // launches on the caller's stream (a member's tridiagonalisation is a chain of grid barriers on a
+  // few CUs and the next stages are a few waves each: side by side on four streams most of the device
+  // idled), then the rest of each core side by side again
   bool batch_eig = true;
   for (int i = 0; i < n; ++i) batch_eig = batch_eig && b->inst[i]->dtype != NGD_F64;
   auto fork = [&] {
@@ -1752,8 +1753,12 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
   NGD_TRY(join());
   if (!batch_eig) return NGD_OK;
   std::vector<EigJob> jobs(n);
-  for (int i = 0; i < n; ++i) jobs[i] = EigJob{static_cast<double*>(b->inst[i]->M), (int)ells[i], b->inst[i]->eigw, false};
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    jobs[i] = EigJob{h->M, (int)ells[i], h->eigw, false, kDropRel, h->side, h->ev_fork, h->ev_join};
+  }
   NGD_TRY(launch_sym_eig_tridiag_batch(jobs.data(), n, s));
+  NGD_TRY(launch_sym_eig_middle_batch(jobs.data(), n, s));
   NGD_TRY(fork());
   for (int k = 0; k < n; ++k) {
     const int i = order[k];

@@ -286,8 +286,18 @@ struct EigJob {
   int n;
   void* work;
   bool keep_err;
+  double drop_rel;
+  hipStream_t side;   // the job's own second stream for the explicit Q (may be NULL)
+  hipEvent_t fork, join;
 };
 ngd_status launch_sym_eig_tridiag_batch(const EigJob* jobs, int n, hipStream_t s);
+// After launch_sym_eig_tridiag_batch: every job's explicit Q on its side stream, then multisection,
+// inverse iteration and the cluster orthogonalisation of all jobs in one launch each on s;
+// launch_sym_eig_rest then completes one job on any stream ordered after s. Together with the
+// tridiagonalisation these compute what launch_sym_eig computes, bitwise.
+ngd_status launch_sym_eig_middle_batch(const EigJob* jobs, int n, hipStream_t s);
+ngd_status launch_sym_eig_rest(int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
+                               hipStream_t s, hipStream_t side = nullptr, hipEvent_t join = nullptr);
 ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, double* evecs_rows, void* work,
                                  hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
                                  hipEvent_t join = nullptr);

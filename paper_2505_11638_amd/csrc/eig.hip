@@ -346,9 +346,9 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
 // eigenvalue pay off while they still find a SIMD of their own. Every eigenvalue starts from the same
 // Gershgorin interval and every round divides its width by the same factor, so the number of rounds
 // is the same for all of them and is fixed up front (workgroup barriers stay uniform).
-__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
-                                                     int n, int wpe, double* __restrict__ e2,
-                                                     double* __restrict__ lam_asc, double* __restrict__ tnorm) {
+__device__ __forceinline__ void bisect_body(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                            int wpe, double* __restrict__ e2, double* __restrict__ lam_asc,
+                                            double* __restrict__ tnorm, const int bid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sd = reinterpret_cast<double*>(smem_raw);
   double* se2 = sd + n;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
     sd[j] = dj;
     if (j < n - 1) {
       se2[j] = ej * ej;
-      if (blockIdx.x == 0) e2[j] = ej * ej;
+      if (bid == 0) e2[j] = ej * ej;
     }
     const double r = (j > 0 ? fabs(e[j - 1]) : 0.0) + fabs(ej);
     glo = fmin(glo, dj - r);
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
   glo = fmin(fmin(red_lo[0], red_lo[1]), fmin(red_lo[2], red_lo[3]));
   ghi = fmax(fmax(red_hi[0], red_hi[1]), fmax(red_hi[2], red_hi[3]));
   const double tn = fmax(fabs(glo), fabs(ghi));
-  if (blockIdx.x == 0 && threadIdx.x == 0) *tnorm = tn;
+  if (bid == 0 && threadIdx.x == 0) *tnorm = tn;
   const double pivmin = fmax(1e-300, 2.2250738585072014e-308 * fmax(1.0, tn * tn));
   double lo = glo - 1e-14 * tn - pivmin, hi = ghi + 1e-14 * tn + pivmin;
   const double tol = 4.0 * 2.220446049250313e-16 * tn + pivmin;
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
   int rounds = 0;
   for (double w = hi - lo; w > tol && rounds < 16; w /= div) ++rounds;
   const int pair = wid / wpe, half = wid - pair * wpe;
-  const int i = blockIdx.x * (4 / wpe) + pair;
+  const int i = bid * (4 / wpe) + pair;
   const int ic = i < n ? i : n - 1;  // waves past the end follow a valid eigenvalue and store nothing
   for (int it = 0; it < rounds; ++it) {
     const double h = (hi - lo) / div;
@@ -414,6 +414,12 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
   if (i < n && half == 0 && lane == 0) lam_asc[i] = 0.5 * (lo + hi);
 }
 
+__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                     int n, int wpe, double* __restrict__ e2,
+                                                     double* __restrict__ lam_asc, double* __restrict__ tnorm) {
+  bisect_body(d, e, n, wpe, e2, lam_asc, tnorm, (int)blockIdx.x);
+}
+
 // inverse iteration for eigenvalue i: solve (T - lam I) x = b by LU with partial pivoting
 // (tridiagonal; the U factor has two superdiagonals), two sweeps. One thread per eigenvalue, 64
 // eigenvalues per wave: the factors live in a global workspace laid out [array][j][i] (consecutive
@@ -427,14 +433,12 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-__global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
-                                                    const double* __restrict__ lam_asc,
-                                                    const double* __restrict__ tnorm, double drop_rel,
-                                                    double* __restrict__ ML, double* __restrict__ SW,
-                                                    double* __restrict__ U1, double* __restrict__ U2,
-                                                    double* __restrict__ RI, double* __restrict__ Y,
-                                                    double* __restrict__ Z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void invit_body(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                           const double* __restrict__ lam_asc, const double* __restrict__ tnorm,
+                                           double drop_rel, double* __restrict__ ML, double* __restrict__ SW,
+                                           double* __restrict__ U1, double* __restrict__ U2, double* __restrict__ RI,
+                                           double* __restrict__ Y, double* __restrict__ Z, const int bid) {
+  const int i = bid * 64 + threadIdx.x;
   if (i >= n) return;
   const double lam = lam_asc[i];
   const double drop = drop_rel * (*tnorm);
@@ -562,11 +566,22 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d,
   }
 }
 
+__global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
+                                                    const double* __restrict__ lam_asc,
+                                                    const double* __restrict__ tnorm, double drop_rel,
+                                                    double* __restrict__ ML, double* __restrict__ SW,
+                                                    double* __restrict__ U1, double* __restrict__ U2,
+                                                    double* __restrict__ RI, double* __restrict__ Y,
+                                                    double* __restrict__ Z) {
+  invit_body(d, e, n, lam_asc, tnorm, drop_rel, ML, SW, U1, U2, RI, Y, Z, (int)blockIdx.x);
+}
+
 // modified Gram-Schmidt within each cluster of close eigenvalues (one workgroup per cluster start)
-__global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, const double* __restrict__ tnorm,
-                                   double drop_rel, double* __restrict__ Z) {
+__device__ __forceinline__ void cluster_mgs_body(const double* __restrict__ lam_asc, int n,
+                                                 const double* __restrict__ tnorm, double drop_rel,
+                                                 double* __restrict__ Z, const int bid) {
   __shared__ double red[4];
-  const int s0 = blockIdx.x;
+  const int s0 = bid;
   const double drop = drop_rel * (*tnorm);
   const double tol = 1e-12 * (*tnorm);
   if (lam_asc[s0] < drop) return;
@@ -589,6 +604,52 @@ __global__ void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n, co
     for (int j = threadIdx.x; j < n; j += blockDim.x) Z[(int64_t)j * n + c] *= sc;
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void cluster_mgs_kernel(const double* __restrict__ lam_asc, int n,
+                                                          const double* __restrict__ tnorm, double drop_rel,
+                                                          double* __restrict__ Z) {
+  cluster_mgs_body(lam_asc, n, tnorm, drop_rel, Z, (int)blockIdx.x);
+}
+
+// The three stages above for several matrices in one launch each: matrix m has workgroups
+// first[m] .. first[m + 1] - 1 (numbered from 0 within it). The arguments travel by value.
+constexpr int kMidBatchMax = 16;
+struct MidItem {
+  const double* d;
+  const double* e;
+  int n, wpe;
+  double* e2;
+  double* lam;
+  double* tnorm;
+  double drop_rel;
+  double *ML, *SW, *U1, *U2, *RI, *Y, *Z;
+};
+struct MidBatch {
+  MidItem it[kMidBatchMax];
+  int first[kMidBatchMax + 1];
+  int n;
+};
+__device__ __forceinline__ int mid_member(const MidBatch& b) {
+  int m = 0;
+  while (m + 1 < b.n && (int)blockIdx.x >= b.first[m + 1]) ++m;
+  return m;
+}
+__global__ __launch_bounds__(256) void bisect_batch_kernel(MidBatch b) {
+  const int m = mid_member(b);
+  const MidItem& q = b.it[m];
+  bisect_body(q.d, q.e, q.n, q.wpe, q.e2, q.lam, q.tnorm, (int)blockIdx.x - b.first[m]);
+}
+__global__ __launch_bounds__(64) void invit_batch_kernel(MidBatch b) {
+  const int m = mid_member(b);
+  const MidItem& q = b.it[m];
+  invit_body(q.d, q.e, q.n, q.lam, q.tnorm, q.drop_rel, q.ML, q.SW, q.U1, q.U2, q.RI, q.Y, q.Z,
+             (int)blockIdx.x - b.first[m]);
+}
+__global__ __launch_bounds__(256) void cluster_mgs_batch_kernel(MidBatch b) {
+  const int m = mid_member(b);
+  const MidItem& q = b.it[m];
+  cluster_mgs_body(q.lam, q.n, q.tnorm, q.drop_rel, q.Z, (int)blockIdx.x - b.first[m]);
 }
 
 // Back-transformation V = H_0 H_1 ... H_{n-3} Z with the reflectors taken kWy at a time in compact
@@ -993,60 +1054,55 @@ ngd_status launch_sym_eig_tridiag_batch(const EigJob* jobs, int n, hipStream_t s
   return launch_tridiag_batch(items.data(), (int)items.size(), s);
 }
 
-ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
-                                 hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
-  if (n <= 0) return NGD_OK;
+namespace {
+
+// wy_t and form_q (the explicit Q) on the side stream, forked from s, or on s itself
+ngd_status eig_side_q(int n, void* work, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
   EigWs ws(work, n);
-  double* A1 = ws.A1;
-  double* V = ws.V;
-  double* Z = ws.Z;
-  double* wk = ws.wk;
-  double* dvec = ws.dvec;
-  double* evec = ws.evec;
-  double* tau = ws.tau;
-  double* e2 = ws.e2;
-  double* lam = ws.lam;
-  double* tnorm = ws.tnorm;
   // The explicit Q = H_0 ... H_{n-3} needs only the reflectors: on the side stream (when given) it
-  // overlaps the eigenvalues, the eigenvectors of T and their orthogonalisation below, and the
+  // overlaps the eigenvalues, the eigenvectors of T and their orthogonalisation, and the
   // back-transformation becomes one product Q Z at the end.
   hipStream_t qs = side != nullptr ? side : s;
   if (side != nullptr) {
     NGD_HIP_TRY(hipEventRecord(fork, s));
     NGD_HIP_TRY(hipStreamWaitEvent(side, fork, 0));
   }
-  {
-    const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
-    if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, qs, V, tau, n, ws.Tall);
-    const int nt = (n + 15) / 16;
-    const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kWpSlots * 256);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)form_q_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-    hipLaunchKernelGGL(form_q_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, qs, V, ws.Tall, n, ws.Qm);
-    NGD_HIP_TRY(hipGetLastError());
-  }
-  if (side != nullptr) NGD_HIP_TRY(hipEventRecord(join, side));
-  const int tb = 256;
-  {
-    // two waves per eigenvalue while the 2n waves find a SIMD each, else one
-    int dev = 0, cus = 0;
-    NGD_HIP_TRY(hipGetDevice(&dev));
-    NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int wpe = 2 * n <= 4 * cus ? 2 : 1;
-    const int per_block = 4 / wpe;
-    hipLaunchKernelGGL(bisect_kernel, dim3((n + per_block - 1) / per_block), dim3(tb), 2 * sizeof(double) * n, s, dvec,
-                       evec, n, wpe, e2, lam, tnorm);
-  }
-  {
-    // the factors of inverse iteration: five n x n arrays in wk, the interchanges in A1 (both free
-    // after the tridiagonalisation)
-    const size_t nn = (size_t)n * n;
-    hipLaunchKernelGGL(invit_kernel, dim3((n + 63) / 64), dim3(64), 0, s, dvec, evec, n, lam, tnorm, drop_rel,
-                       wk, A1, wk + nn, wk + 2 * nn, wk + 3 * nn, wk + 4 * nn, Z);
-    NGD_HIP_TRY(hipGetLastError());
-  }
-  hipLaunchKernelGGL(cluster_mgs_kernel, dim3(n), dim3(256), 0, s, lam, n, tnorm, drop_rel, Z);
+  const int nblk = n > 2 ? (n - 2 + kWy - 1) / kWy : 0;
+  if (nblk > 0) hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, qs, ws.V, ws.tau, n, ws.Tall);
+  const int nt = (n + 15) / 16;
+  const size_t lds = sizeof(double) * ((size_t)kWy * (nt * 16 + 1) + (size_t)kWpSlots * 256);
+  NGD_HIP_TRY(hipFuncSetAttribute((const void*)form_q_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+  hipLaunchKernelGGL(form_q_mfma_kernel, dim3(nt), dim3(64 * kBtWaves), lds, qs, ws.V, ws.Tall, n, ws.Qm);
   NGD_HIP_TRY(hipGetLastError());
+  if (side != nullptr) NGD_HIP_TRY(hipEventRecord(join, side));
+  return NGD_OK;
+}
+
+// the arguments of multisection, inverse iteration and the cluster orthogonalisation for one matrix
+ngd_status eig_mid_item(int n, double drop_rel, void* work, MidItem* q) {
+  EigWs ws(work, n);
+  // two waves per eigenvalue while the 2n waves find a SIMD each, else one
+  int dev = 0, cus = 0;
+  NGD_HIP_TRY(hipGetDevice(&dev));
+  NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // the factors of inverse iteration: five n x n arrays in wk, the interchanges in A1 (both free
+  // after the tridiagonalisation)
+  const size_t nn = (size_t)n * n;
+  *q = MidItem{ws.dvec, ws.evec, n, 2 * n <= 4 * cus ? 2 : 1, ws.e2, ws.lam, ws.tnorm, drop_rel,
+               ws.wk, ws.A1, ws.wk + nn, ws.wk + 2 * nn, ws.wk + 3 * nn, ws.wk + 4 * nn, ws.Z};
+  return NGD_OK;
+}
+
+// Newton-Schulz, the product with Q (after the side stream's join) and the eigenvector rows
+ngd_status eig_rest(int n, double drop_rel, double* evals_desc, double* evec_rows, void* work, hipStream_t s,
+                    hipStream_t side, hipEvent_t join) {
+  EigWs ws(work, n);
+  double* A1 = ws.A1;
+  double* Z = ws.Z;
+  double* wk = ws.wk;
+  double* lam = ws.lam;
+  double* tnorm = ws.tnorm;
   // one Newton-Schulz step Z <- 1.5 Z - 0.5 Z (Z^T Z) removes the residual non-orthogonality of the
   // inverse-iteration vectors (quadratic convergence; dropped columns stay zero)
   double* E = A1;   // free after the tridiagonalisation
@@ -1077,6 +1133,67 @@ ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, dou
                      evals_desc, evec_rows);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
+}
+
+
+}  // namespace
+
+ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
+                                 hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+  if (n <= 0) return NGD_OK;
+  NGD_TRY(eig_side_q(n, work, s, side, fork, join));
+  MidItem q;
+  NGD_TRY(eig_mid_item(n, drop_rel, work, &q));
+  const int per_block = 4 / q.wpe;
+  hipLaunchKernelGGL(bisect_kernel, dim3((n + per_block - 1) / per_block), dim3(256), 2 * sizeof(double) * n, s, q.d,
+                     q.e, n, q.wpe, q.e2, q.lam, q.tnorm);
+  hipLaunchKernelGGL(invit_kernel, dim3((n + 63) / 64), dim3(64), 0, s, q.d, q.e, n, q.lam, q.tnorm, drop_rel, q.ML,
+                     q.SW, q.U1, q.U2, q.RI, q.Y, q.Z);
+  NGD_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cluster_mgs_kernel, dim3(n), dim3(256), 0, s, q.lam, n, q.tnorm, drop_rel, q.Z);
+  NGD_HIP_TRY(hipGetLastError());
+  return eig_rest(n, drop_rel, evals_desc, evec_rows, work, s, side, join);
+}
+
+ngd_status launch_sym_eig_middle_batch(const EigJob* jobs, int n, hipStream_t s) {
+  std::vector<MidItem> items;
+  for (int i = 0; i < n; ++i) {
+    const EigJob& j = jobs[i];
+    if (j.n <= 0) continue;
+    NGD_TRY(eig_side_q(j.n, j.work, s, j.side, j.fork, j.join));
+    MidItem q;
+    NGD_TRY(eig_mid_item(j.n, j.drop_rel, j.work, &q));
+    items.push_back(q);
+  }
+  const int m = (int)items.size();
+  for (int c0 = 0; c0 < m; c0 += kMidBatchMax) {
+    MidBatch b{};
+    b.n = std::min(kMidBatchMax, m - c0);
+    for (int k = 0; k < b.n; ++k) b.it[k] = items[c0 + k];
+    auto launch = [&](auto kernel, auto blocks_of, int threads, size_t lds) {
+      int total = 0;
+      for (int k = 0; k < b.n; ++k) {
+        b.first[k] = total;
+        total += blocks_of(b.it[k]);
+      }
+      b.first[b.n] = total;
+      hipLaunchKernelGGL(kernel, dim3(total), dim3(threads), lds, s, b);
+      NGD_HIP_TRY(hipGetLastError());
+      return NGD_OK;
+    };
+    size_t lds = 0;
+    for (int k = 0; k < b.n; ++k) lds = std::max(lds, 2 * sizeof(double) * b.it[k].n);
+    NGD_TRY(launch(bisect_batch_kernel, [](const MidItem& q) { return (q.n + 4 / q.wpe - 1) / (4 / q.wpe); }, 256, lds));
+    NGD_TRY(launch(invit_batch_kernel, [](const MidItem& q) { return (q.n + 63) / 64; }, 64, 0));
+    NGD_TRY(launch(cluster_mgs_batch_kernel, [](const MidItem& q) { return q.n; }, 256, 0));
+  }
+  return NGD_OK;
+}
+
+ngd_status launch_sym_eig_rest(int n, double drop_rel, double* evals_desc, double* evec_rows, void* work,
+                               hipStream_t s, hipStream_t side, hipEvent_t join) {
+  if (n <= 0) return NGD_OK;
+  return eig_rest(n, drop_rel, evals_desc, evec_rows, work, s, side, join);
 }
 
 const int* eig_error_flag(void* work, int n) { return EigWs(work, n).err; }
