@@ -1397,6 +1397,8 @@ ngd_problem* ngd_batch_problem(ngd_batch* b, int32_t i) {
   return (b != nullptr && i >= 0 && i < (int32_t)b->inst.size()) ? b->inst[i] : nullptr;
 }
 
+ngd_status batch_streams(ngd_batch* b);
+
 ngd_status ngd_batch_residual_jacobian(ngd_batch* b, const void* const* theta, void* const* r_w, void* const* J_w,
                                        const int64_t* ldJ, double* const* grad, double* const* loss, void* stream) {
   NGD_CHECK(b != nullptr && theta != nullptr && r_w != nullptr && J_w != nullptr && ldJ != nullptr, "NULL argument");
@@ -1449,16 +1451,28 @@ ngd_status ngd_batch_residual_jacobian(ngd_batch* b, const void* const* theta, v
   NGD_HIP_TRY(hipMemcpyAsync(b->d_res, b->h_res, sizeof(BatchResidualItem) * n, hipMemcpyHostToDevice, s));
   for (const Group& gr : groups)
     NGD_TRY(launch_batch_residual_jacobian(b->dtype, b->d_res + gr.first, gr.count, gr.tiles, gr.lds, s));
-  for (int i = 0; i < n; ++i) {
-    ngd_problem* h = b->inst[i];
-    const int nt = (int)((h->N + tps[i] - 1) / tps[i]);
-    if (loss != nullptr && loss[i] != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, nt, 1, 0.5, loss[i], s));
+  // each member's loss and gradient (one pass over its J_w) side by side on the batch's streams
+  for (int i = 0; i < n; ++i)
     if (grad != nullptr && grad[i] != nullptr) {
       const ngd_operator op{theta[i], J_w[i], ldJ[i]};
-      NGD_TRY(check_op(h, &op));
-      NGD_TRY(launch_grad_rows(h->dtype, J_w[i], ldJ[i], h->N, r_w[i], h->partial, h->nwg, s));
-      NGD_TRY(launch_gram_reduce(h->dtype, h->partial, h->nwg, ldJ[i], h->P, nullptr, 0.0, grad[i], s));
+      NGD_TRY(check_op(b->inst[i], &op));
     }
+  NGD_TRY(batch_streams(b));
+  NGD_HIP_TRY(hipEventRecord(b->sk_fork, s));
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) NGD_HIP_TRY(hipStreamWaitEvent(b->sk_stream[q], b->sk_fork, 0));
+  for (int i = 0; i < n; ++i) {
+    ngd_problem* h = b->inst[i];
+    hipStream_t qs = b->sk_stream[i % ngd_batch::kSketchStreams];
+    const int nt = (int)((h->N + tps[i] - 1) / tps[i]);
+    if (loss != nullptr && loss[i] != nullptr) NGD_TRY(launch_reduce_sum(h->loss_part, nt, 1, 0.5, loss[i], qs));
+    if (grad != nullptr && grad[i] != nullptr) {
+      NGD_TRY(launch_grad_rows(h->dtype, J_w[i], ldJ[i], h->N, r_w[i], h->partial, h->nwg, qs));
+      NGD_TRY(launch_gram_reduce(h->dtype, h->partial, h->nwg, ldJ[i], h->P, nullptr, 0.0, grad[i], qs));
+    }
+  }
+  for (int q = 0; q < ngd_batch::kSketchStreams; ++q) {
+    NGD_HIP_TRY(hipEventRecord(b->sk_join[q], b->sk_stream[q]));
+    NGD_HIP_TRY(hipStreamWaitEvent(s, b->sk_join[q], 0));
   }
   return NGD_OK;
 }
@@ -1770,7 +1784,8 @@ ngd_status ngd_batch_nystrom_sketch(ngd_batch* b, const ngd_operator* ops, const
 
 // Every member's Armijo line search (as ngd_line_search) with the decisions on the device: each round
 // evaluates the next trial steps of every member still searching (side by side on the batch's
-// streams) and the host reads back only which members are done, once per round for all of them.
+// streams) and the host reads back only which members are done, once per round for all of them. The
+// accepted step does not depend on how the trials are grouped into launches.
 ngd_status ngd_batch_line_search(ngd_batch* b, void* const* theta, double* const* d, double* const* grad,
                                  const double* loss0, double c1, int32_t max_halvings, void* const* theta_out,
                                  double* alpha, double* loss_new, void* stream) {
