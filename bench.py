@@ -39,7 +39,8 @@ WORKLOADS = {
 }
 WORKLOADS["c5"] = ("32 independent 2D/3D Poisson PINNs, hidden widths from {32,48,64,96}, depth 2-4 (P 1,185-28,417), "
                     "N_int 1,024-8,192 + N_int/8 boundary points, ell from {50,100,200,400}, FP32; batched residual/"
-                    "Jacobian launch, per-problem Nystrom sketch, batched graph-replayed PCG, per-problem Armijo")
+                    "Jacobian launch, per-problem Nystrom sketch with batched eigensolver stages, batched graph-replayed "
+                    "PCG, batched Armijo line search")
 WORKLOADS["paper3d"] = ("the paper's 3D Poisson PINN: 3-64-64-64-1 tanh (P=8,641), 10,000 + 1,000 random points, FP64, "
                          "u* = sin(pi x) sin(pi y) sin(pi z); Nystrom NGD with adaptive sketch size (ell from 20 in "
                          "steps of 20 up to 500), at most 20 PCG iterations at rtol 1e-6, mu = max(10 eps lam1_hat, "
