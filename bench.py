@@ -53,7 +53,7 @@ WORKLOADS["paper_heat"] = ("the paper's heat equation in 3+1D: 4-64-64-64-1 tanh
 PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1, "direct": 317.7}
 PAPER3D_BASELINE_SPS = {k: 1000.0 / v for k, v in PAPER3D_BASELINE_S.items()}
 _VARIANT_NAME = {"rpchol": "RPCholNGD", "direct": "NGD full (direct Cholesky)"}
-# FP32 vector peak without packed FP32 instructions (which this build leaves out): 256 CUs x 128 FLOP
+# FP32 vector peak without packed FP32 instructions (the library is compiled without them): 256 CUs x 128 FLOP
 # per clock (4 SIMDs x 16 lanes x an FMA) x 2.4 GHz = 78.6 TFLOP/s; the 157.3 of the data sheet counts
 # packed FP32
 FP32_VECTOR_PEAK_TFLOPS = 78.6
@@ -371,7 +371,7 @@ def main(argv=None):
                     help="c2: skip the time-to-rtol solves and the 5D sub-run")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         return 2
 
     if a.config == "c5":

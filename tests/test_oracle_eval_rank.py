@@ -1,6 +1,5 @@
 """Pins of the oracle's adaptive sketch-size rule (Alg. 4), its accuracy measure (relative L2 / H1
-errors, Section 5) and the paper's 3D Poisson workload; plus the driver's own rank rule against the
-oracle's (host logic, CPU only)."""
+errors, Section 5) and the paper's 3D Poisson workload (CPU only)."""
 
 import numpy as np
 import pytest

@@ -50,7 +50,7 @@ class Problem:
     recompute: bool = False       # products with J_w recomputed from theta instead of a stored J_w
     ell_max: Optional[int] = None # adaptive sketch size up to ell_max (None: ell fixed)
     dell: int = 20                # rank increase of the adaptive rule
-    maxit: Optional[int] = None   # PCG iteration cap (None: the driver's default)
+    maxit: Optional[int] = None   # PCG iteration cap (None: driver.NGD's default)
     solution: str = ""            # manufactured solution ("sinprod", "sinsum", "heat") for evaluation
 
     @property
