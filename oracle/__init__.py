@@ -11,6 +11,9 @@ Contents, each following the passage of arXiv 2505.11638 it cites:
              Laplacian and time derivative, residuals of the Poisson (eq. energy_poisson) and heat
              (eq. heat_energy) least-squares energies, the exact reverse-mode residual Jacobian
              (Section 4.1.1) and the gradient.
+* `navier_stokes`  the steady Navier-Stokes rows of the Kovasznay flow (Section 5.1.3, eq.
+             navier_residual): velocity and pressure networks, residual rows, loss and the exact
+             Gauss-Newton Jacobian by the reverse sweep with per-row seeds.
 * `linalg`   the Gramian G = J^T W J of Theorem thm:matfree (eq. G_matrixfree), its damped matvec,
              and the direct solve of Alg. 2 (Cholesky) with two independent cross-checks.
 * `nystrom`  Alg. 6 (randomized Nystrom, stable form) taken step by step, the Nystrom approximation

@@ -25,9 +25,18 @@ KIND_INITIAL = 2    # initial-condition row (heat): res = u - g
 
 PDE_POISSON = 0     # interior res = Laplace(u) + f      (-Laplace(u) = f)
 PDE_HEAT = 1        # interior res = u_t - Laplace_x(u) - f (last input coordinate is time)
+PDE_NAVIER_STOKES = 2  # steady incompressible flow, velocity and pressure networks (rows below)
+
+# rows of the Navier-Stokes problem (Section 5.1.3, eq. navier_residual): an interior point gives the
+# two momentum rows and the continuity row, a boundary point one Dirichlet row per velocity component
+KIND_NS_MOMENTUM_X = 3  # -nu Laplace u_1 + (u . grad) u_1 + dp/dx - f
+KIND_NS_MOMENTUM_Y = 4  # -nu Laplace u_2 + (u . grad) u_2 + dp/dy - f
+KIND_NS_CONTINUITY = 5  # div u
+KIND_NS_BOUNDARY_U = 6  # u_1 - g
+KIND_NS_BOUNDARY_V = 7  # u_2 - g
 
 # purposes for independent random streams
-_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE, _P_SHAPES, _P_EVAL = range(8)
+_P_THETA, _P_INTERIOR, _P_BOUNDARY, _P_INITIAL, _P_OMEGA, _P_PROBE, _P_SHAPES, _P_EVAL, _P_THETA_P = range(9)
 
 
 @dataclasses.dataclass
@@ -52,6 +61,7 @@ class Problem:
     dell: int = 20                # rank increase of the adaptive rule
     maxit: Optional[int] = None   # PCG iteration cap (None: driver.NGD's default)
     solution: str = ""            # manufactured solution ("sinprod", "sinsum", "heat") for evaluation
+    nu: float = 0.0               # viscosity (Navier-Stokes rows only)
 
     @property
     def n_rows(self) -> int:
@@ -63,6 +73,8 @@ class Problem:
 
     @property
     def n_params(self) -> int:
+        if self.pde == PDE_NAVIER_STOKES:
+            return ns_num_params(self.widths)
         return num_params(self.widths)
 
     def cast(self, dtype: str) -> "Problem":
@@ -83,6 +95,17 @@ def num_params(widths: Sequence[int]) -> int:
     return int(sum(a * b + b for a, b in zip(widths[:-1], widths[1:])))
 
 
+def pressure_widths(widths: Sequence[int]) -> tuple:
+    """The pressure network of the Navier-Stokes problem: the velocity network's input and hidden
+    widths with one output (Section 5.1.3 uses two such networks with three hidden layers of 45)."""
+    return tuple(int(v) for v in widths[:-1]) + (1,)
+
+
+def ns_num_params(widths: Sequence[int]) -> int:
+    """p of theta = [theta_u, theta_p] (Section 5.1.3): both networks' parameters."""
+    return num_params(widths) + num_params(pressure_widths(widths))
+
+
 def _rng(seed: int, purpose: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([int(seed), int(purpose)]))
 
@@ -93,6 +116,19 @@ def glorot_theta(widths: Sequence[int], seed: int) -> np.ndarray:
     rng = _rng(seed, _P_THETA)
     parts = []
     for n_in, n_out in zip(widths[:-1], widths[1:]):
+        a = math.sqrt(6.0 / (n_in + n_out))
+        parts.append(rng.uniform(-a, a, size=(n_out, n_in)).ravel())
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts)
+
+
+def ns_glorot_theta(widths: Sequence[int], seed: int) -> np.ndarray:
+    """theta = [theta_u, theta_p] for the Navier-Stokes problem, each network Glorot-uniform as
+    glorot_theta, the pressure network from its own stream."""
+    rng = _rng(seed, _P_THETA_P)
+    parts = [glorot_theta(widths, seed)]
+    pw = pressure_widths(widths)
+    for n_in, n_out in zip(pw[:-1], pw[1:]):
         a = math.sqrt(6.0 / (n_in + n_out))
         parts.append(rng.uniform(-a, a, size=(n_out, n_in)).ravel())
         parts.append(np.zeros(n_out))
@@ -256,6 +292,88 @@ def heat3d_paper(widths=(4, 64, 64, 64, 1), n_interior=10000, n_boundary=1000, s
                      sketch_dtype=sketch_dtype, seed=seed, solution="heatcos")
 
 
+# Kovasznay flow (Section 5.1.3) on (-1/2, 1) x (-1/2, 3/2)
+_KOV_BOX = ((-0.5, 1.0), (-0.5, 1.5))
+
+
+def kovasznay_lambda(nu: float) -> float:
+    """lambda = 1/(2 nu) - sqrt(1/(4 nu^2) + 4 pi^2) of the Kovasznay solution."""
+    return 1.0 / (2.0 * nu) - math.sqrt(1.0 / (4.0 * nu * nu) + 4.0 * math.pi ** 2)
+
+
+def kovasznay_solution(X: np.ndarray, nu: float = 1.0 / 40.0) -> tuple:
+    """The exact Kovasznay flow at the points X (n x 2): velocity (n, 2), its gradient (n, 2, 2) with
+    [k, j] = d u_k / d x_j, and the pressure (n,) normalised to mean zero over the domain."""
+    X = np.asarray(X, dtype=np.float64)
+    lam = kovasznay_lambda(nu)
+    x, y = X[:, 0], X[:, 1]
+    e = np.exp(lam * x)
+    c, s = np.cos(2 * np.pi * y), np.sin(2 * np.pi * y)
+    u = np.stack([1.0 - e * c, lam / (2 * np.pi) * e * s], axis=1)
+    grad = np.empty((X.shape[0], 2, 2))
+    grad[:, 0, 0] = -lam * e * c
+    grad[:, 0, 1] = 2 * np.pi * e * s
+    grad[:, 1, 0] = lam * lam / (2 * np.pi) * e * s
+    grad[:, 1, 1] = lam * e * c
+    (x0, x1), (y0, y1) = _KOV_BOX
+    # mean of 1/2 (1 - exp(2 lambda x)) over the box (it does not depend on y)
+    mean = 0.5 * (1.0 - (math.exp(2 * lam * x1) - math.exp(2 * lam * x0)) / (2 * lam * (x1 - x0)))
+    p = 0.5 * (1.0 - np.exp(2 * lam * x)) - mean
+    return u, grad, p
+
+
+def _kovasznay_boundary(rng, n: int) -> np.ndarray:
+    """n points uniform on the boundary of the Kovasznay box: an edge with probability proportional to
+    its length, then a uniform point on it."""
+    (x0, x1), (y0, y1) = _KOV_BOX
+    lx, ly = x1 - x0, y1 - y0
+    t = rng.uniform(0.0, 2 * (lx + ly), size=n)
+    X = np.empty((n, 2))
+    for i, ti in enumerate(t):
+        if ti < lx:
+            X[i] = (x0 + ti, y0)
+        elif ti < lx + ly:
+            X[i] = (x1, y0 + ti - lx)
+        elif ti < 2 * lx + ly:
+            X[i] = (x1 - (ti - lx - ly), y1)
+        else:
+            X[i] = (x0, y1 - (ti - 2 * lx - ly))
+    return X
+
+
+def kovasznay(widths=(2, 45, 45, 45, 2), n_interior=10000, n_boundary=1000, nu=1.0 / 40.0, seed=0,
+              dtype="f64", ell=20, sketch_dtype="f64") -> Problem:
+    """The paper's Kovasznay flow (Section 5.1.3, Re = 1/nu = 40, f = 0) as Navier-Stokes rows.
+
+    Uniform random interior and boundary points of (-1/2, 1) x (-1/2, 3/2). Every interior point gives
+    three rows (momentum x, momentum y, continuity) with weight area / n_interior, every boundary point
+    two rows (u_1 - g_1, u_2 - g_2, g the exact velocity) with weight perimeter / n_boundary. `widths` is
+    the velocity network (two outputs); the pressure network has the same hidden widths and one output."""
+    rng_i, rng_b = _rng(seed, _P_INTERIOR), _rng(seed, _P_BOUNDARY)
+    (x0, x1), (y0, y1) = _KOV_BOX
+    Xi = np.stack([rng_i.uniform(x0, x1, n_interior), rng_i.uniform(y0, y1, n_interior)], axis=1)
+    Xb = _kovasznay_boundary(rng_b, n_boundary)
+    ub, _, _ = kovasznay_solution(Xb, nu)
+    wi = (x1 - x0) * (y1 - y0) / n_interior
+    wb = 2 * ((x1 - x0) + (y1 - y0)) / n_boundary
+    zi, zb = np.zeros(n_interior), np.zeros(n_boundary)
+    blocks = [(Xi, KIND_NS_MOMENTUM_X, wi, zi, zi), (Xi, KIND_NS_MOMENTUM_Y, wi, zi, zi),
+              (Xi, KIND_NS_CONTINUITY, wi, zi, zi),
+              (Xb, KIND_NS_BOUNDARY_U, wb, zb, ub[:, 0]), (Xb, KIND_NS_BOUNDARY_V, wb, zb, ub[:, 1])]
+    return _assemble("kovasznay", PDE_NAVIER_STOKES, widths, blocks, dtype=dtype, ell=ell, lam=None,
+                     sketch_dtype=sketch_dtype, seed=seed, solution="kovasznay", nu=float(nu))
+
+
+def kovasznay_evaluation_set(nu: float = 1.0 / 40.0, n: int = 100_000, seed: int = 0) -> tuple:
+    """n uniform random points of the Kovasznay box with the exact velocity and its gradient there:
+    (X, u (n, 2), grad u (n, 2, 2))."""
+    (x0, x1), (y0, y1) = _KOV_BOX
+    rng = _rng(seed, _P_EVAL)
+    X = np.stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)], axis=1)
+    u, grad, _ = kovasznay_solution(X, nu)
+    return X, u, grad
+
+
 # ----------------------------------------------------------------------------------------------
 # named configurations
 # ----------------------------------------------------------------------------------------------
@@ -273,7 +391,12 @@ def config(name: str, seed: int = 0) -> Problem:
         adaptive sketch size from 20 in steps of 20 up to 500, at most 20 PCG iterations.
     paper_heat: the paper's heat equation in 3+1D (Section 5.1.2), 4-64-64-64-1 tanh (P = 8,705), 10,000 +
         1,000 random points, FP64, the same solver settings as paper3d.
+    paper_ns: the paper's Kovasznay flow (Section 5.1.3), velocity 2-45-45-45-2 and pressure 2-45-45-45-1
+        tanh networks (P = 8,688), 10,000 + 1,000 random points (32,000 rows), FP64, the same sketch-size
+        settings as paper3d.
     """
+    if name == "paper_ns":
+        return dataclasses.replace(kovasznay(seed=seed), name="paper_ns", ell_max=500, dell=20, maxit=20)
     if name == "paper_heat":
         return dataclasses.replace(heat3d_paper(seed=seed), name="paper_heat", ell_max=500, dell=20, maxit=20)
     if name == "paper3d":
