@@ -48,10 +48,17 @@ WORKLOADS["paper3d"] = ("the paper's 3D Poisson PINN: 3-64-64-64-1 tanh (P=8,641
 WORKLOADS["paper_heat"] = ("the paper's heat equation in 3+1D: 4-64-64-64-1 tanh (P=8,705), 10,000 + 1,000 random "
                             "points, FP64, u* = (cos(pi x) + cos(pi y) + cos(pi z)) exp(-pi^2 t / 4); the paper3d "
                             "solver settings; relative H1 error (space-time gradient) on 100,000 random points")
-# The paper's Nystrom NGD on this problem: 66.8 s to its plateau error over at most 1,000 iterations on
-# one RTX 4090 in FP64, so at most 15.0 NGD steps/s (a derived upper bound on its rate).
-PAPER3D_BASELINE_S = {"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1, "direct": 317.7}
-PAPER3D_BASELINE_SPS = {k: 1000.0 / v for k, v in PAPER3D_BASELINE_S.items()}
+WORKLOADS["paper_ns"] = ("the paper's Kovasznay flow (steady Navier-Stokes, Re = 40): velocity 2-45-45-45-2 and pressure "
+                          "2-45-45-45-1 tanh networks (P=8,688), 10,000 + 1,000 random points (32,000 rows: two momentum "
+                          "and one continuity row per interior point, two Dirichlet rows per boundary point), FP64, "
+                          "Gauss-Newton metric, Levenberg-Marquardt damping, the paper3d sketch-size settings; relative "
+                          "H1 error of the velocity on 100,000 random points")
+# The paper's methods on its setups (one RTX 4090, FP64): time to the plateau error over at most 1,000 NGD
+# iterations (2,000 for the Kovasznay flow), so seconds / iterations bounds its time per step from below
+# (a derived upper bound on its rate).
+PAPER_BASELINE_S = {"paper3d": ({"gaussian": 66.8, "sampling": 81.2, "rpchol": 74.1, "direct": 317.7}, 1000),
+                    "paper_heat": ({"gaussian": 106.1, "sampling": 59.0, "rpchol": 111.9, "direct": 279.2}, 1000),
+                    "paper_ns": ({"gaussian": 878.5, "sampling": 548.0, "rpchol": 654.4, "direct": 5708.3}, 2000)}
 _VARIANT_NAME = {"rpchol": "RPCholNGD", "direct": "NGD full (direct Cholesky)"}
 # FP32 vector peak without packed FP32 instructions (the library is compiled without them): 256 CUs x 128 FLOP
 # per clock (4 SIMDs x 16 lanes x an FMA) x 2.4 GHz = 78.6 TFLOP/s; the 157.3 of the data sheet counts
@@ -68,7 +75,8 @@ def bench_paper(a):
     from paper_2505_11638_amd.driver import NGD
 
     prob = wl.config(a.config, seed=a.seed)
-    theta0 = wl.glorot_theta(prob.widths, a.seed)
+    ns = prob.pde == wl.PDE_NAVIER_STOKES
+    theta0 = wl.ns_glorot_theta(prob.widths, a.seed) if ns else wl.glorot_theta(prob.widths, a.seed)
     P, N = prob.n_params, prob.n_rows
     variant = a.solver if a.solver in ("rpchol", "direct") else a.test_matrix
     if a.solver == "rpchol":  # RPCholNGD (Alg. 5): block size 20, rank up to 500
@@ -78,7 +86,10 @@ def bench_paper(a):
     else:
         ngd = NGD(prob, theta0, solver="nystrom", rtol=1e-6, seed=a.seed, test_matrix=a.test_matrix)
     gp = ngd.gp
-    Xe, ue, ge = wl.evaluation_set(prob, 100_000, seed=a.seed)
+    if ns:  # the velocity's error (Section 5.1.3)
+        Xe, ue, ge = wl.kovasznay_evaluation_set(prob.nu, 100_000, seed=a.seed)
+    else:
+        Xe, ue, ge = wl.evaluation_set(prob, 100_000, seed=a.seed)
     _, h1_start, sums = gp.solution_error(ngd.theta, Xe, ue, ge)
     for _ in range(a.warmup):
         ngd.step()
@@ -96,23 +107,26 @@ def bench_paper(a):
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     sps = a.steps / dt
     ranks = [r.rank for r in reps]
+    base_s, base_iters = PAPER_BASELINE_S[a.config]
+    base_sps = base_iters / base_s[variant]
     line = {
         "metric": "NGD steps/s at PCG rtol 1e-6 (Nystrom vs plain CG); Gramian-matvec GB/s",
         "value": sps, "unit": "NGD steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": 1000.0 * dt / a.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": sps / PAPER3D_BASELINE_SPS[variant] if a.config == "paper3d" else None,
-        "baseline": None if a.config != "paper3d" else {"value": PAPER3D_BASELINE_SPS[variant], "unit": "NGD steps/s",
+        "vs_baseline": sps / base_sps,
+        "baseline": {"value": base_sps, "unit": "NGD steps/s",
                      "kind": f"the paper's {_VARIANT_NAME.get(variant, 'Nystrom NGD (' + variant + ' test matrix)')}"
-                             f" on this problem, RTX 4090, FP64: {PAPER3D_BASELINE_S[variant]} s to its plateau over "
-                             "at most 1,000 iterations (an upper bound on its rate)"},
+                             f" on this problem, RTX 4090, FP64: {base_s[variant]} s to its plateau over at most "
+                             f"{base_iters:,} iterations (an upper bound on its rate)"},
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}; {a.warmup} + {a.steps} NGD steps from a "
                                f"Glorot start (the last {a.steps} timed)", "P": P, "N": N,
                    "ell0": prob.ell, "ell_max": prob.ell_max, "dell": prob.dell, "maxit": prob.maxit,
-                   "preconditioner": variant},
+                   "preconditioner": variant, "damping": prob.damping},
         "ell_first_last_max": [ranks[0], ranks[-1], max(ranks)],
         "ell_trajectory": ranks,
         "mean_pcg_iters": float(np.mean([r.iters for r in reps])),
+        "mu_trajectory": [r.mu for r in reps],
         "loss_first_last": [reps[0].loss, reps[-1].loss_new],
         "rel_h1_error_start_end": [h1_start, h1_end], "rel_l2_error_end": l2_end,
         "roofline": {"bound": "hbm", "kernel": "pcg_rows_kernel (one-pass J^T(J v)), FP64", "achieved": achieved,
@@ -376,7 +390,7 @@ def main(argv=None):
 
     if a.config == "c5":
         return bench_batch(a)
-    if a.config in ("paper3d", "paper_heat"):
+    if a.config in ("paper3d", "paper_heat", "paper_ns"):
         return bench_paper(a)
 
     import numpy as np

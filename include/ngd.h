@@ -41,11 +41,23 @@ typedef enum {
 
 typedef enum { NGD_F64 = 0, NGD_F32 = 1, NGD_BF16 = 2 } ngd_dtype;
 
-/* PDE of the residual rows (Section 5.1.1 eq. energy_poisson, Section 5.1.2 eq. heat_energy). */
-typedef enum { NGD_PDE_POISSON = 0, NGD_PDE_HEAT = 1 } ngd_pde;
+/* PDE of the residual rows (Section 5.1.1 eq. energy_poisson, Section 5.1.2 eq. heat_energy,
+ * Section 5.1.3 eq. navier_residual). */
+typedef enum { NGD_PDE_POISSON = 0, NGD_PDE_HEAT = 1, NGD_PDE_NAVIER_STOKES = 2 } ngd_pde;
 
-/* Kind of one collocation row. */
-typedef enum { NGD_ROW_INTERIOR = 0, NGD_ROW_BOUNDARY = 1, NGD_ROW_INITIAL = 2 } ngd_row_kind;
+/* Kind of one collocation row. Poisson and heat problems use the first three; Navier-Stokes problems
+ * the last five (an interior point gives the two momentum rows and the continuity row, a boundary
+ * point one row per velocity component). */
+typedef enum {
+  NGD_ROW_INTERIOR = 0,
+  NGD_ROW_BOUNDARY = 1,
+  NGD_ROW_INITIAL = 2,
+  NGD_ROW_NS_MOMENTUM_X = 3, /* -nu Laplace u_1 + u_1 d_x u_1 + u_2 d_y u_1 + d_x p - f */
+  NGD_ROW_NS_MOMENTUM_Y = 4, /* -nu Laplace u_2 + u_1 d_x u_2 + u_2 d_y u_2 + d_y p - f */
+  NGD_ROW_NS_CONTINUITY = 5, /* d_x u_1 + d_y u_2 */
+  NGD_ROW_NS_BOUNDARY_U = 6, /* u_1 - g */
+  NGD_ROW_NS_BOUNDARY_V = 7  /* u_2 - g */
+} ngd_row_kind;
 
 /*
  * One PINN least-squares problem: a tanh MLP (Section 2.3) and fixed quadrature data.
@@ -55,6 +67,16 @@ typedef enum { NGD_ROW_INTERIOR = 0, NGD_ROW_BOUNDARY = 1, NGD_ROW_INITIAL = 2 }
  *   Boundary and initial rows: residual = u - g. Weighted residual r_w = sqrt(w) * residual.
  * Parameter vector theta (length P): [W_1, b_1, ..., W_L+1, b_L+1], each W row-major (out x in).
  * Limits: 1 <= n_layers <= 8, 1 <= d <= 6, widths <= 256, N >= 1.
+ *
+ * Navier-Stokes (steady incompressible flow, Section 5.1.3, eq. navier_residual; the Gauss-Newton
+ * metric of that section is J_w^T J_w): two tanh MLPs with inputs (x, y). `widths` describes the
+ * velocity network (widths[0] = 2, widths[n_layers] = 2 outputs (u_1, u_2), hidden widths <= 64, at
+ * least one hidden layer); the pressure network has the same input and hidden widths and one output.
+ * theta = [theta_u, theta_p], P the sum of both counts. Rows use the NGD_ROW_NS_* kinds, f holds the
+ * momentum rows' forcing, g the boundary rows' target, `viscosity` is nu. Such a handle supports the
+ * stored-J_w path (ngd_residual_jacobian with J_w, the products, sketches, solves and line search) and
+ * ngd_solution_error on the velocity; the recompute mode (ngd_jvp, ngd_vjp, operators with J == NULL)
+ * and batches refuse it with NGD_ERR_INVALID.
  */
 typedef struct {
   int32_t n_layers;        /* number of affine layers (hidden layers + 1) */
@@ -69,6 +91,7 @@ typedef struct {
   const int8_t* row_kind;  /* device, N: ngd_row_kind */
   int32_t max_ell;         /* largest sketch size that will be used with this handle, 1 .. 1024
                               (the FP64 ell x ell core kernels keep their operands in registers) */
+  double viscosity;        /* nu of the Navier-Stokes rows (> 0); ignored for other PDEs */
 } ngd_problem_desc;
 
 typedef struct ngd_problem ngd_problem;  /* opaque; owns device workspace only */
@@ -347,6 +370,22 @@ ngd_status ngd_power_lambda_max(ngd_problem* h, const ngd_operator* op, const do
  */
 ngd_status ngd_damping(ngd_problem* h, const double* lam1, const double* loss, double c_lam, double c_loss,
                        double* mu, double* mu_host, void* stream);
+
+/*
+ * Levenberg-Marquardt damping update (the heuristic by which the Navier-Stokes experiment of Section
+ * 5.1.3 adapts mu; the factors are those of the trust-region radius rule of Nocedal and Wright). From
+ * the step theta_new = theta - alpha d just taken, the gain ratio of the actual decrease over the
+ * Gauss-Newton model's,
+ *   rho = (loss0 - loss1) / (alpha g^T d - alpha^2 d^T G d / 2),   G = J_w^T J_w,
+ * gives mu_next = 4 mu if rho < 1/4, mu / 2 if rho > 3/4, mu otherwise, and at least mu_floor. A step
+ * not taken (alpha = 0) or a model without decrease counts as rho < 1/4 and reports rho = -1.
+ *   d, grad : device, P doubles (the direction and the gradient of that step).
+ *   alpha >= 0, mu > 0, mu_floor >= 0. mu_next : host, out. rho : host, nullable, out.
+ * One Gramian product with d (stored J_w). Synchronises `stream`.
+ */
+ngd_status ngd_lm_damping(ngd_problem* h, const ngd_operator* op, const double* d, const double* grad, double alpha,
+                          double loss0, double loss1, double mu, double mu_floor, double* mu_next, double* rho,
+                          void* stream);
 
 /*
  * Alg. 4's update of the sketch size (Section 4.3) from one step's eigenvalue estimates:

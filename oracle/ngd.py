@@ -13,6 +13,9 @@ Readings of points the paper leaves open:
 * adaptive sketch size (Alg. 4, Section 4.3, experimental setup of Section 5): the next rank from
   lam_hat_ell / mu against 10, growing by dell = 20 up to ell_max = 500, shrinking to the first index
   below the threshold plus an offset of 1; the initial rank is not stated and is taken as dell.
+* Levenberg-Marquardt damping (the Navier-Stokes experiment, Section 5.1.3): the first step takes mu
+  from the rule above, later steps from the gain ratio of the previous step (gain_ratio, lm_update),
+  never below the rule's roundoff term gamma eps lam1_hat.
 * the sketch is of the undamped Gramian (Alg. 4 sketches G_fun and forms mu afterwards); the CG
   operator is G + mu I and the preconditioner uses the same mu (Alg. 3, Alg. 4).
 """
@@ -50,6 +53,24 @@ def next_rank(lam_hat, mu: float, ell: int, ell_max: int, dell: int, offset: int
     if below.size == 0:
         return min(ell, ell_max)
     return min(int(below[0]) + 1 + offset, ell_max)
+
+
+def gain_ratio(loss0: float, loss1: float, alpha: float, gd: float, dGd: float) -> float:
+    """Actual over predicted decrease of the step theta - alpha d, the prediction from the Gauss-Newton
+    model of the loss, L(theta - s) ~ L - g^T s + s^T G s / 2: rho = (L0 - L1) / (alpha g^T d -
+    alpha^2 d^T G d / 2); -1 when no step was taken or the model predicts no decrease."""
+    pred = alpha * gd - 0.5 * alpha * alpha * dGd
+    if alpha <= 0.0 or pred <= 0.0:
+        return -1.0
+    return (loss0 - loss1) / pred
+
+
+def lm_update(mu: float, rho: float, floor: float = 0.0) -> float:
+    """Levenberg-Marquardt damping update (the heuristic of Section 5.1.3; the factors of the trust-region
+    radius rule of Nocedal and Wright, with the damping moving opposite to the radius): 4 mu for a poor
+    step (rho < 1/4), mu / 2 for a good one (rho > 3/4), else unchanged, and never below `floor`."""
+    m = 4.0 * mu if rho < 0.25 else (0.5 * mu if rho > 0.75 else mu)
+    return max(m, floor)
 
 
 def power_method(G_fun, v0: np.ndarray, iters: int = 4) -> float:

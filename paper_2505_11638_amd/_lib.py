@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libngd.so")
 
 NGD_OK, NGD_ERR_INVALID, NGD_ERR_OOM, NGD_ERR_NOT_PD, NGD_ERR_BREAKDOWN, NGD_ERR_NOT_CONVERGED, NGD_ERR_HIP = range(7)
 NGD_F64, NGD_F32, NGD_BF16 = 0, 1, 2
-NGD_PDE_POISSON, NGD_PDE_HEAT = 0, 1
+NGD_PDE_POISSON, NGD_PDE_HEAT, NGD_PDE_NAVIER_STOKES = 0, 1, 2
 NGD_NOALLOC_SCRATCH_BYTES = 40 * 1024 * 1024
 
 STATUS_NAMES = {0: "NGD_OK", 1: "NGD_ERR_INVALID", 2: "NGD_ERR_OOM", 3: "NGD_ERR_NOT_PD", 4: "NGD_ERR_BREAKDOWN",
@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "NGD_OK", 1: "NGD_ERR_INVALID", 2: "NGD_ERR_OOM", 3: "NGD_ERR
 class ProblemDesc(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("widths", C.POINTER(C.c_int32)), ("pde", C.c_int32),
                 ("dtype", C.c_int32), ("n_rows", C.c_int64), ("X", C.c_void_p), ("w", C.c_void_p),
-                ("f", C.c_void_p), ("g", C.c_void_p), ("row_kind", C.c_void_p), ("max_ell", C.c_int32)]
+                ("f", C.c_void_p), ("g", C.c_void_p), ("row_kind", C.c_void_p), ("max_ell", C.c_int32),
+                ("viscosity", C.c_double)]
 
 
 class Operator(C.Structure):
@@ -72,6 +73,9 @@ SIGNATURES = {
                               C.POINTER(C.c_double), C.c_void_p]),
     "ngd_next_rank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int64, C.c_int64, C.c_int64,
                                 C.POINTER(C.c_int64), C.c_void_p]),
+    "ngd_lm_damping": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.c_void_p]),
     "ngd_line_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                   C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "ngd_nystrom_sketch_columns": (C.c_int, [C.c_void_p, C.POINTER(Operator), C.c_int64, C.c_void_p, C.c_int32,

@@ -91,7 +91,8 @@ class Problem:
         self._widths_c = (C.c_int32 * len(self.widths))(*self.widths)
         self.desc = L.ProblemDesc(len(self.widths) - 1, self._widths_c, self.pde, self.dtype, self.N,
                                   self.X.data_ptr(), self.w.data_ptr(), self.f.data_ptr(), self.g.data_ptr(),
-                                  self.kind.data_ptr(), int(max_ell or getattr(data, "ell", 1)))
+                                  self.kind.data_ptr(), int(max_ell or getattr(data, "ell", 1)),
+                                  float(getattr(data, "nu", 0.0)))
         self._owned = _batch is None
         if _batch is not None:  # a batch member: the batch creates and owns the handle
             return
@@ -289,6 +290,18 @@ class Problem:
                                      C.byref(mh) if host else None, _stream()), "ngd_damping")
         return mu, (mh.value if host else None)
 
+    def lm_damping(self, J, d: torch.Tensor, grad: torch.Tensor, alpha: float, loss0: float, loss1: float, mu: float,
+                   mu_floor: float = 0.0):
+        """ngd_lm_damping: the Levenberg-Marquardt update of mu from the step just taken; returns
+        (mu_next, rho)."""
+        _need(d, torch.float64, "d")
+        _need(grad, torch.float64, "grad")
+        mn, rho = C.c_double(), C.c_double()
+        L.check(self.lib.ngd_lm_damping(self.h, C.byref(self._op(J)), _ptr(d), _ptr(grad), float(alpha), float(loss0),
+                                        float(loss1), float(mu), float(mu_floor), C.byref(mn), C.byref(rho),
+                                        _stream()), "ngd_lm_damping")
+        return mn.value, rho.value
+
     def next_rank(self, lam_hat: torch.Tensor, ell: int, mu: float, dell: int, offset: int, ell_max: int) -> int:
         """ngd_next_rank: Alg. 4's next sketch size from lam_hat[:ell] and the step's damping mu."""
         _need(lam_hat, torch.float64, "lam_hat")
@@ -370,7 +383,10 @@ class Problem:
         to = lambda a: torch.as_tensor(np.asarray(a), dtype=self.tdtype, device=self.device).contiguous()
         X, u_ref, grad_u_ref = to(X), to(u_ref), to(grad_u_ref)
         n = int(X.shape[0]) if X.ndim == 2 else 0
-        if X.ndim != 2 or X.shape[1] != self.widths[0] or u_ref.shape != (n,) or grad_u_ref.shape != X.shape:
+        if self.pde == L.NGD_PDE_NAVIER_STOKES:  # the velocity: u_ref n x 2, grad_u_ref n x 2 x 2 ([k][j])
+            if X.ndim != 2 or X.shape[1] != 2 or u_ref.shape != (n, 2) or grad_u_ref.shape != (n, 2, 2):
+                raise ValueError("solution_error: X must be n x 2, u_ref n x 2, grad_u_ref n x 2 x 2")
+        elif X.ndim != 2 or X.shape[1] != self.widths[0] or u_ref.shape != (n,) or grad_u_ref.shape != X.shape:
             raise ValueError("solution_error: X must be n x d, u_ref n, grad_u_ref n x d")
         _need(theta, self.tdtype, "theta")
         sums = torch.empty(4, dtype=torch.float64, device=self.device) if sums is None else sums

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libngd.so")
-SOURCES = ["api.hip", "residual.hip", "matvec.hip", "gemm.hip", "eig.hip", "chol.hip", "misc.hip", "sketch_gemm.hip", "eval.hip", "pivots.hip", "noalloc.hip", "direct.hip"]
+SOURCES = ["api.hip", "residual.hip", "matvec.hip", "gemm.hip", "eig.hip", "chol.hip", "misc.hip", "sketch_gemm.hip", "eval.hip", "pivots.hip", "noalloc.hip", "direct.hip", "ns.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -18,6 +18,8 @@ using namespace ngd;
 
 struct ngd_problem {
   NetDesc net;
+  bool ns = false;   // Navier-Stokes rows: two networks (nsd), their own residual kernel
+  NsDesc nsd{};
   int dtype;
   int64_t N, P, ldP;
   int max_ell;
@@ -209,6 +211,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 ngd_status check_op(const ngd_problem* h, const ngd_operator* op) {
   NGD_CHECK(op != nullptr, "operator is NULL");
   if (op->J == nullptr) {  // recompute mode: J_w products from theta by the JVP / adjoint kernels
+    NGD_CHECK(!h->ns, "the recompute mode (J == NULL) is not available for Navier-Stokes rows");
     NGD_CHECK(op->theta != nullptr, "recompute mode (J == NULL) needs theta");
     return NGD_OK;
   }
@@ -253,7 +256,9 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   *out = nullptr;
   NGD_CHECK(d->n_layers >= 1 && d->n_layers <= kMaxLayers, "n_layers out of range [1, 8]");
   NGD_CHECK(d->widths != nullptr, "widths is NULL");
-  NGD_CHECK(d->pde == NGD_PDE_POISSON || d->pde == NGD_PDE_HEAT, "unknown pde");
+  NGD_CHECK(d->pde == NGD_PDE_POISSON || d->pde == NGD_PDE_HEAT || d->pde == NGD_PDE_NAVIER_STOKES,
+            "unknown pde");
+  const bool ns = d->pde == NGD_PDE_NAVIER_STOKES;
   NGD_CHECK(d->dtype == NGD_F64 || d->dtype == NGD_F32, "dtype must be NGD_F64 or NGD_F32");
   NGD_CHECK(d->n_rows >= 1, "n_rows must be >= 1");
   NGD_CHECK(d->X && d->w && d->f && d->g && d->row_kind, "problem data pointer is NULL");
@@ -268,14 +273,25 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
     net.widths[l] = d->widths[l];
     maxw = std::max(maxw, d->widths[l]);
   }
-  NGD_CHECK(d->widths[d->n_layers] == 1, "the output width must be 1");
+  NGD_CHECK(ns || d->widths[d->n_layers] == 1, "the output width must be 1");
+  NsDesc nsd{};
+  if (ns) {
+    NGD_CHECK(d->n_layers >= 2, "Navier-Stokes networks need at least one hidden layer");
+    NGD_CHECK(d->widths[0] == 2 && d->widths[d->n_layers] == 2,
+              "Navier-Stokes velocity network: 2 inputs (x, y) and 2 outputs (u_1, u_2)");
+    for (int l = 1; l < d->n_layers; ++l) NGD_CHECK(d->widths[l] <= 64, "Navier-Stokes hidden widths must be <= 64");
+    NGD_CHECK(d->viscosity > 0.0, "viscosity must be > 0");
+    NGD_TRY(ns_describe(d->n_layers, d->widths, d->viscosity, &nsd));
+    NGD_CHECK(ns_lds_bytes(nsd, d->dtype) <= 160 * 1024,
+              "Navier-Stokes networks too large for the residual kernel's LDS budget");
+  }
   for (int l = 0; l < d->n_layers; ++l) {
     net.woff[l] = off;
     off += (int64_t)net.widths[l] * net.widths[l + 1];
     net.boff[l] = off;
     off += net.widths[l + 1];
   }
-  net.P = off;
+  net.P = ns ? nsd.P : off;
   net.d = d->widths[0];
   NGD_CHECK(net.d <= kMaxDim, "input dimension must be <= 6");
   NGD_CHECK(d->pde != NGD_PDE_HEAT || net.d >= 2, "heat needs at least one space and the time input");
@@ -287,6 +303,8 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
 
   ngd_problem* h = new ngd_problem();
   h->net = net;
+  h->ns = ns;
+  h->nsd = nsd;
   h->dtype = d->dtype;
   h->N = d->n_rows;
   h->P = net.P;
@@ -299,8 +317,9 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   h->kind = d->row_kind;
   h->elem = d->dtype == NGD_F64 ? 8 : 4;
   h->tp = residual_block_rows(net, d->dtype);
-  h->res_blocks = (int)((h->N + h->tp - 1) / h->tp);
-  h->ls_batch = residual_trials_per_launch(net, d->dtype, h->N, kTrials);
+  h->res_blocks = ns ? ns_blocks(h->N) : (int)((h->N + h->tp - 1) / h->tp);
+  // Navier-Stokes trial losses: four per launch (each launch is a few rounds of resident workgroups)
+  h->ls_batch = ns ? std::min(4, kTrials) : residual_trials_per_launch(net, d->dtype, h->N, kTrials);
   h->nwg = gram_rows_grid(d->dtype, h->N, h->P);
   h->nwg_vjp = vjp_grid(net, d->dtype, h->N, h->nwg);
 
@@ -423,11 +442,16 @@ ngd_status ngd_residual_jacobian(ngd_problem* h, const void* theta, void* r_w, v
   NGD_CHECK(h != nullptr && theta != nullptr && r_w != nullptr, "NULL argument");
 
   if (J_w != nullptr) NGD_CHECK(ldJ >= h->P, "ldJ < P");
+  NGD_CHECK(!h->ns || J_w != nullptr || grad == nullptr,
+            "the gradient of Navier-Stokes rows needs J_w (no recompute mode)");
   hipStream_t s = S(stream);
   // residual workgroups of this launch (fewer without the Jacobian), each with one loss partial
-  const int nb = residual_blocks(h->net, h->dtype, h->N, J_w != nullptr);
+  const int nb = h->ns ? ns_blocks(h->N) : residual_blocks(h->net, h->dtype, h->N, J_w != nullptr);
   NGD_CHECK(nb <= h->res_blocks, "residual launch exceeds its loss-partial buffer");
   NGD_TRY(timed(h, J_w ? NGD_TIMER_RESIDUAL_JACOBIAN : -1, s, [&] {
+    if (h->ns)
+      return launch_ns_residual(h->nsd, h->dtype, theta, 0, 1, h->N, h->X, h->w, h->f, h->g, h->kind, r_w, J_w, ldJ,
+                                h->loss_part, s);
     return launch_residual_jacobian(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, r_w, J_w, ldJ,
                                     h->loss_part, 0, 1, s, nullptr);
   }));
@@ -491,6 +515,7 @@ ngd_status ngd_gramian_matvec(ngd_problem* h, const ngd_operator* op, const void
 ngd_status ngd_jvp(ngd_problem* h, const void* theta, const void* V, int64_t ldV, int64_t k, void* Y, int64_t ldY,
                    void* stream) {
   NGD_CHECK(h != nullptr && theta != nullptr && V != nullptr && Y != nullptr, "NULL argument");
+  NGD_CHECK(!h->ns, "ngd_jvp is not available for Navier-Stokes rows");
   NGD_CHECK(k >= 1, "k must be >= 1");
   NGD_CHECK(k == 1 || (ldV >= h->P && ldY >= h->N), "ldV >= P and ldY >= N required");
   return launch_jvp(h->net, h->dtype, theta, V, ldV, k, h->N, h->X, h->w, h->kind, h->dtype, Y, 1, ldY, S(stream));
@@ -498,6 +523,7 @@ ngd_status ngd_jvp(ngd_problem* h, const void* theta, const void* V, int64_t ldV
 
 ngd_status ngd_vjp(ngd_problem* h, const void* theta, const void* wv, double* out, void* stream) {
   NGD_CHECK(h != nullptr && theta != nullptr && wv != nullptr && out != nullptr, "NULL argument");
+  NGD_CHECK(!h->ns, "ngd_vjp is not available for Navier-Stokes rows");
   hipStream_t s = S(stream);
   NGD_TRY(launch_cast(h->dtype, wv, NGD_F64, h->nvec[1], h->N, s));
   NGD_TRY(launch_vjp(h->net, h->dtype, theta, h->N, h->X, h->w, h->f, h->g, h->kind, h->nvec[1], 1, h->partial,
@@ -1190,6 +1216,28 @@ ngd_status ngd_damping(ngd_problem* h, const double* lam1, const double* loss, d
   return NGD_OK;
 }
 
+ngd_status ngd_lm_damping(ngd_problem* h, const ngd_operator* op, const double* d, const double* grad, double alpha,
+                          double loss0, double loss1, double mu, double mu_floor, double* mu_next, double* rho,
+                          void* stream) {
+  NGD_CHECK(h != nullptr && d != nullptr && grad != nullptr && mu_next != nullptr, "NULL argument");
+  NGD_CHECK(std::isfinite(mu) && mu > 0.0, "mu must be finite and > 0");
+  NGD_CHECK(std::isfinite(mu_floor) && mu_floor >= 0.0, "mu_floor must be finite and >= 0");
+  NGD_CHECK(std::isfinite(alpha) && alpha >= 0.0, "alpha must be finite and >= 0");
+  NGD_TRY(check_op(h, op));
+  hipStream_t s = S(stream);
+  double* sc = h->scal;  // [4] g^T d, [5] d^T G d, [6] mu_next, [7] rho, [8..] dot workspace
+  NGD_TRY(gram_apply(h, op, d, 0.0, h->vtmp[3], s));
+  NGD_TRY(launch_dot(grad, d, h->P, sc + 8, sc + 4, s));
+  NGD_TRY(launch_dot(d, h->vtmp[3], h->P, sc + 8, sc + 5, s));
+  NGD_TRY(launch_lm_damping(sc + 4, sc + 5, alpha, loss0, loss1, mu, mu_floor, sc + 6, s));
+  double* hv = reinterpret_cast<double*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, sc + 6, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  *mu_next = hv[0];
+  if (rho != nullptr) *rho = hv[1];
+  return NGD_OK;
+}
+
 ngd_status ngd_next_rank(ngd_problem* h, const double* lam_hat, int64_t ell, double mu, int64_t dell,
                          int64_t offset, int64_t ell_max, int64_t* next_ell, void* stream) {
   NGD_CHECK(h != nullptr && lam_hat != nullptr && next_ell != nullptr, "NULL argument");
@@ -1210,6 +1258,9 @@ ngd_status ngd_solution_error(ngd_problem* h, const void* theta, const void* X, 
   NGD_CHECK(h != nullptr && sums != nullptr, "NULL argument");
   NGD_CHECK(n >= 0, "n must be >= 0");
   NGD_CHECK(n == 0 || (theta && X && u_ref && grad_u_ref), "NULL argument");
+  if (h->ns)
+    return launch_ns_velocity_error(h->nsd, h->dtype, theta, X, n, u_ref, grad_u_ref, h->err_part, kEvalBlocks, sums,
+                                    S(stream));
   return launch_solution_error(h->net, h->dtype, theta, X, n, u_ref, grad_u_ref, h->err_part, sums, S(stream));
 }
 
@@ -1234,10 +1285,14 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
     for (int t = 0; t < nt; ++t) hv[8 + t] = std::ldexp(1.0, -(tried + t));
     NGD_HIP_TRY(hipMemcpyAsync(h->alphas, hv + 8, sizeof(double) * nt, hipMemcpyHostToDevice, s));
     NGD_TRY(launch_axpy_theta(h->dtype, theta, d, h->alphas, nt, P, h->trial, h->ldP, s));
-    const int nb = residual_blocks(h->net, h->dtype, h->N, false);
+    const int nb = h->ns ? ns_blocks(h->N) : residual_blocks(h->net, h->dtype, h->N, false);
     NGD_CHECK(nb <= h->res_blocks, "residual launch exceeds its loss-partial buffer");
-    NGD_TRY(launch_residual_jacobian(h->net, h->dtype, h->trial, h->N, h->X, h->w, h->f, h->g, h->kind, nullptr,
-                                     nullptr, 0, h->loss_part, h->ldP, nt, s, nullptr));
+    if (h->ns)
+      NGD_TRY(launch_ns_residual(h->nsd, h->dtype, h->trial, h->ldP, nt, h->N, h->X, h->w, h->f, h->g, h->kind,
+                                 nullptr, nullptr, 0, h->loss_part, s));
+    else
+      NGD_TRY(launch_residual_jacobian(h->net, h->dtype, h->trial, h->N, h->X, h->w, h->f, h->g, h->kind, nullptr,
+                                       nullptr, 0, h->loss_part, h->ldP, nt, s, nullptr));
     NGD_TRY(launch_reduce_sum(h->loss_part, nb, nt, 0.5, h->losses, s));
     NGD_HIP_TRY(hipMemcpyAsync(hv + 16, h->losses, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
     NGD_HIP_TRY(hipStreamSynchronize(s));
@@ -1359,6 +1414,11 @@ ngd_status ngd_batch_create(const ngd_problem_desc* descs, int32_t n, ngd_batch*
     if (descs[i].dtype != b->dtype) {
       batch_release(b);
       set_error("all problems of a batch must share one dtype");
+      return NGD_ERR_INVALID;
+    }
+    if (descs[i].pde == NGD_PDE_NAVIER_STOKES) {
+      batch_release(b);
+      set_error("batches take Poisson and heat problems only");
       return NGD_ERR_INVALID;
     }
     ngd_problem* h = nullptr;

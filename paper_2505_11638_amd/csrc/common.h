@@ -33,6 +33,19 @@ struct NetDesc {
   int64_t P;
 };
 
+// Two networks of the Navier-Stokes rows (velocity: widths[n_layers] = 2 outputs; pressure: the same
+// input and hidden widths, one output), theta = [theta_u, theta_p].
+struct NsDesc {
+  int n_layers;                  // affine layers of each network
+  int widths[kMaxLayers + 1];    // the velocity network
+  int64_t toff[2];               // start of each network's parameters in theta
+  int64_t tl[2][kMaxLayers];     // offset of layer l's W within its network's parameters
+  int wl[2][kMaxLayers];         // LDS offset of layer l's staged rows (n_out x (n_in + 1))
+  int w_elems;                   // LDS elements of both networks' staged weights
+  int64_t P;
+  double nu;                     // viscosity
+};
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64 multiplications,
 // word recombination with the key, and a Weyl increment of the key between rounds.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -199,6 +212,18 @@ __device__ __forceinline__ bool publish_and_reduce(double v, double* part, int b
 
 // ---- launchers (defined in the .hip files) ------------------------------------------------------
 
+// ns.hip
+ngd_status ns_describe(int n_layers, const int* widths, double nu, NsDesc* nd);
+size_t ns_lds_bytes(const NsDesc& nd, int dtype);
+int ns_blocks(int64_t N);
+ngd_status launch_ns_residual(const NsDesc& nd, int dtype, const void* theta, int64_t theta_stride, int n_theta,
+                              int64_t N, const void* X, const void* w, const void* f, const void* g,
+                              const int8_t* kind, void* r_w, void* J, int64_t ldJ, double* loss_partial,
+                              hipStream_t s);
+ngd_status launch_ns_velocity_error(const NsDesc& nd, int dtype, const void* theta, const void* X, int64_t n,
+                                    const void* u_ref, const void* grad_ref, double* part, int max_blocks,
+                                    double* sums, hipStream_t s);
+
 // residual.hip
 ngd_status launch_residual_jacobian(const NetDesc& net, int dtype, const void* theta, int64_t N,
                                     const void* X, const void* w, const void* f, const void* g,
@@ -313,6 +338,8 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
 ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
                               double* out, hipStream_t s);
 // Armijo decision for nt trials on the device: st = [found, alpha, loss, index] (left as it is once found)
+ngd_status launch_lm_damping(const double* gd, const double* dgd, double alpha, double loss0, double loss1, double mu,
+                             double floor_mu, double* out, hipStream_t s);
 ngd_status launch_armijo(const double* alphas, const double* losses, const double* slope, double loss0, double c1,
                          int nt, int tried, double* st, hipStream_t s);
 ngd_status launch_zero(void* p, size_t bytes, hipStream_t s);

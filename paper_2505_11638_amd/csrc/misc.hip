@@ -62,6 +62,22 @@ __global__ void armijo_kernel(const double* __restrict__ alphas, const double* _
   }
 }
 
+// Levenberg-Marquardt update of the damping from the step just taken (the heuristic of the Navier-Stokes
+// experiment, Section 5.1.3, with the factors of the trust-region radius rule of Nocedal and Wright):
+// gain ratio rho = (loss0 - loss1) / pred with the Gauss-Newton model's decrease
+// pred = alpha g^T d - alpha^2 d^T G d / 2; mu * 4 if rho < 1/4, mu / 2 if rho > 3/4, else mu; never below
+// floor. No step (alpha = 0) or a model without decrease (pred <= 0) counts as rho < 1/4 (rho = -1).
+// out[0] = mu_next, out[1] = rho.
+__global__ void lm_damping_kernel(const double* __restrict__ gd, const double* __restrict__ dgd, double alpha,
+                                  double loss0, double loss1, double mu, double floor_mu, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const double pred = __dsub_rn(__dmul_rn(alpha, *gd), __dmul_rn(__dmul_rn(0.5, __dmul_rn(alpha, alpha)), *dgd));
+  const double rho = (alpha > 0.0 && pred > 0.0) ? (loss0 - loss1) / pred : -1.0;
+  const double m = rho < 0.25 ? 4.0 * mu : (rho > 0.75 ? 0.5 * mu : mu);
+  out[0] = fmax(m, floor_mu);
+  out[1] = rho;
+}
+
 // The sketch's summary for the host, gathered so that one copy brings it back:
 // out[0] = lam[0], out[1] = lam[L-1], out[2] = #{lam > 0}, out[3] = core[1] (the shift nu),
 // out[4] = the modified-pivot count (an int stored at core[10]), out[5], out[6] = the error words.
@@ -232,6 +248,13 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
 ngd_status launch_armijo(const double* alphas, const double* losses, const double* slope, double loss0, double c1,
                          int nt, int tried, double* st, hipStream_t s) {
   hipLaunchKernelGGL(armijo_kernel, dim3(1), dim3(64), 0, s, alphas, losses, slope, loss0, c1, nt, tried, st);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_lm_damping(const double* gd, const double* dgd, double alpha, double loss0, double loss1, double mu,
+                             double floor_mu, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(lm_damping_kernel, dim3(1), dim3(64), 0, s, gd, dgd, alpha, loss0, loss1, mu, floor_mu, out);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

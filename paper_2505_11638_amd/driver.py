@@ -10,6 +10,10 @@ with gamma = 10 and eps the unit roundoff of the working precision, unless a fix
 rule runs in the library (ngd_pcg_solve_damped, ngd_damping). Plain CG, RPCholNGD and NGD full take
 lam1_hat from 4 power iterations.
 
+Levenberg-Marquardt damping (damping="lm", the Navier-Stokes experiment of Section 5.1.3): the first
+step takes mu from the rule above, every later one from ngd_lm_damping's update after the previous
+step (gain ratio of the actual over the Gauss-Newton model's decrease), never below gamma eps lam1_hat.
+
 Sketch size: fixed, or adaptive as in Alg. 4 (Section 4.3) when a maximum is given: after each step
 ngd_next_rank gives the next size (grow by dell while lam_hat_ell > 10 mu, else the first index with
 lam_hat_i < 10 mu plus one, never above ell_max).
@@ -47,7 +51,7 @@ class StepReport:
 class NGD:
     def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
                  maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None,
-                 ell_max=None, dell=None, rank_offset=1, test_matrix="gaussian"):
+                 ell_max=None, dell=None, rank_offset=1, test_matrix="gaussian", damping=None):
         # adaptive sketch size when a maximum is given (here or by the problem)
         self.ell_max = ell_max if ell_max is not None else getattr(data, "ell_max", None)
         self.dell = int(dell if dell is not None else getattr(data, "dell", 20))
@@ -78,6 +82,10 @@ class NGD:
             maxit = getattr(data, "maxit", None)
         self.maxit = maxit if maxit is not None else (gp.P if solver == "cg" else 1000)
         self.lam = lam if lam is not None else getattr(data, "lam", None)
+        self.damping = damping or getattr(data, "damping", "rule")
+        if self.damping not in ("rule", "lm"):
+            raise ValueError("damping must be 'rule' or 'lm'")
+        self.mu_lm = None  # the Levenberg-Marquardt damping for the next step
         self.gamma = gamma
         self.seed = seed
         self.eps = EPS[gp.dtype_name]
@@ -124,9 +132,10 @@ class NGD:
                                    want_info=False, out=self.pc, cols=cols)
             self.pc = pc
             self.lam1_host.copy_(pc.lam_hat[:1], non_blocking=True)
-            if self.lam is not None:
-                out = gp.pcg_solve(J, grad, self.lam, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
-                mu = self.lam
+            fixed = self.lam if self.lam is not None else self.mu_lm
+            if fixed is not None:
+                out = gp.pcg_solve(J, grad, fixed, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
+                mu = fixed
             else:
                 out = gp.pcg_solve(J, grad, None, precond=pc, rtol=self.rtol, maxit=self.maxit,
                                    damping=(self.gamma * self.eps, 1e-4, loss), out=self.d)
@@ -140,8 +149,8 @@ class NGD:
             # damping rule on the device
             lam1 = gp.power_lambda_max(J, self.v0, 4, out=self.lam1_dev)
             L0 = float(self.loss_np[0])
-            if self.lam is not None:
-                mu = self.lam
+            if self.lam is not None or self.mu_lm is not None:
+                mu = self.lam if self.lam is not None else self.mu_lm
             else:
                 _, mu = gp.damping(self.lam1_dev, loss, self.gamma * self.eps, 1e-4, out=self.mu_dev)
             pc = None
@@ -158,6 +167,9 @@ class NGD:
             else:
                 out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=self.rtol, maxit=self.maxit, out=self.d)
         _, alpha, L1 = gp.line_search(self.theta, out.d, grad, L0, theta_out=self.theta)
+        if self.damping == "lm" and self.lam is None:
+            # J and grad still belong to the step's starting point
+            self.mu_lm, _ = gp.lm_damping(J, out.d, grad, alpha, L0, L1, mu, self.gamma * self.eps * float(lam1))
         self.k += 1
         rank = ell if self.solver == "nystrom" else (self.last_rank if self.solver == "rpchol" else -1)
         return StepReport(L0, mu, lam1, out.iters, out.rel_res, out.converged, alpha, L1, rank)

@@ -55,3 +55,20 @@ def test_binding_declares_every_symbol_and_validates_on_host():
     desc = _lib.ProblemDesc(2, widths, 0, 1, 10, 1, 1, 1, 1, 1, 4)
     assert lib.ngd_problem_create(ctypes.byref(desc), ctypes.byref(h)) == _lib.NGD_ERR_INVALID
     assert b"output width" in lib.ngd_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libngd.so not built")
+def test_navier_stokes_descriptor_checks_on_host():
+    """Navier-Stokes handles (Section 5.1.3): velocity network 2 -> ... -> 2, hidden widths <= 64,
+    viscosity > 0; each violation is refused before any device work."""
+    from paper_2505_11638_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    ns = _lib.NGD_PDE_NAVIER_STOKES
+    for widths, nu, msg in [((2, 8, 1), 0.025, b"2 outputs"), ((3, 8, 2), 0.025, b"2 inputs"),
+                            ((2, 65, 2), 0.025, b"<= 64"), ((2, 8, 2), 0.0, b"viscosity"),
+                            ((2, 2), 0.025, b"hidden layer")]:
+        w = (ctypes.c_int32 * len(widths))(*widths)
+        desc = _lib.ProblemDesc(len(widths) - 1, w, ns, 1, 10, 1, 1, 1, 1, 1, 4, nu)
+        assert lib.ngd_problem_create(ctypes.byref(desc), ctypes.byref(h)) == _lib.NGD_ERR_INVALID
+        assert msg in lib.ngd_last_error(), (widths, lib.ngd_last_error())

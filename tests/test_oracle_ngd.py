@@ -70,3 +70,32 @@ def test_nystrom_and_plain_cg_steps_agree():
     for info in (i1, i2):
         assert np.linalg.norm(info.direction - dstar) <= 1e-6 * np.linalg.norm(dstar)
         assert info.loss_new <= info.loss
+
+
+def test_gain_ratio_is_one_for_a_linear_residual():
+    """For a linear residual r(theta) = A theta - b the Gauss-Newton model of the loss is exact, so any
+    step has gain ratio 1 and the Levenberg-Marquardt rule halves mu (Section 5.1.3)."""
+    rng = np.random.default_rng(3)
+    A, b, th = rng.standard_normal((9, 4)), rng.standard_normal(9), rng.standard_normal(4)
+    L = lambda t: 0.5 * float(np.sum((A @ t - b) ** 2))
+    g = A.T @ (A @ th - b)
+    G = A.T @ A
+    d = np.linalg.solve(G + 0.3 * np.eye(4), g)
+    for alpha in (1.0, 0.5, 0.125):
+        rho = ngd.gain_ratio(L(th), L(th - alpha * d), alpha, g @ d, d @ G @ d)
+        assert abs(rho - 1.0) < 1e-12
+        assert ngd.lm_update(0.3, rho) == 0.15
+
+
+def test_gain_ratio_of_a_poor_step_and_no_step():
+    """Hand-worked cases: a step of alpha = 1/2 along d with g^T d = d^T G d = 1 predicts a decrease of
+    1/2 - 1/8 = 3/8; an actual decrease of 0.05 gives rho = 2/15 (mu grows 4x), one of 0.3 gives 4/5
+    (mu halves), one of 0.15 gives 2/5 (kept); alpha = 0 counts as a poor step; the floor holds."""
+    assert abs(ngd.gain_ratio(1.0, 0.95, 0.5, 1.0, 1.0) - 2.0 / 15.0) < 1e-15
+    assert ngd.lm_update(1.0, ngd.gain_ratio(1.0, 0.95, 0.5, 1.0, 1.0)) == 4.0
+    assert ngd.lm_update(1.0, ngd.gain_ratio(1.0, 0.7, 0.5, 1.0, 1.0)) == 0.5
+    assert ngd.lm_update(1.0, ngd.gain_ratio(1.0, 0.85, 0.5, 1.0, 1.0)) == 1.0
+    assert ngd.gain_ratio(1.0, 1.0, 0.0, 1.0, 1.0) == -1.0
+    assert ngd.gain_ratio(1.0, 0.9, 1.0, 1.0, 4.0) == -1.0  # the model predicts an increase
+    assert ngd.lm_update(1.0, -1.0) == 4.0
+    assert ngd.lm_update(1e-9, 0.9, floor=1e-8) == 1e-8

@@ -62,6 +62,7 @@ class Problem:
     maxit: Optional[int] = None   # PCG iteration cap (None: driver.NGD's default)
     solution: str = ""            # manufactured solution ("sinprod", "sinsum", "heat") for evaluation
     nu: float = 0.0               # viscosity (Navier-Stokes rows only)
+    damping: str = "rule"         # "rule" (Section 4.3) or "lm" (Levenberg-Marquardt, Section 5.1.3)
 
     @property
     def n_rows(self) -> int:
@@ -361,7 +362,7 @@ def kovasznay(widths=(2, 45, 45, 45, 2), n_interior=10000, n_boundary=1000, nu=1
               (Xi, KIND_NS_CONTINUITY, wi, zi, zi),
               (Xb, KIND_NS_BOUNDARY_U, wb, zb, ub[:, 0]), (Xb, KIND_NS_BOUNDARY_V, wb, zb, ub[:, 1])]
     return _assemble("kovasznay", PDE_NAVIER_STOKES, widths, blocks, dtype=dtype, ell=ell, lam=None,
-                     sketch_dtype=sketch_dtype, seed=seed, solution="kovasznay", nu=float(nu))
+                     sketch_dtype=sketch_dtype, seed=seed, solution="kovasznay", nu=float(nu), damping="lm")
 
 
 def kovasznay_evaluation_set(nu: float = 1.0 / 40.0, n: int = 100_000, seed: int = 0) -> tuple:
