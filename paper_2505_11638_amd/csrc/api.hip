@@ -950,7 +950,9 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
     }
     if (nt) return launch_nt_gemm(NGD_F32, op->J, op->ldJ, om_type, om_nt, ld_nt, gt, N, L, P, NGD_F32, h->Z, L,
                                   false, 1.0, h->sk_work, h->sk_work_elems, s);
-    GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0};
+    // split K over the Gram products' workspace where the output has too few tiles (small ell)
+    GemmArgs g1{N, L, P, op->J, op->ldJ, true, omega, ldO, true, h->Z, L, T, T, T, gt, 1.0, 0.0,
+                h->gemm_work, h->gemm_work_elems, 0};
     return launch_gemm(g1, s);
   }));
   // J^T in BF16 for the second product, on the side stream: it overlaps the latency-bound FP64 core
@@ -998,7 +1000,8 @@ ngd_status sketch_impl(ngd_problem* h, const ngd_operator* op, int64_t ell, uint
                             1.0, h->sk_work, h->sk_work_elems, s, true);
     if (nt) return launch_nt_gemm(et, h->Jt, h->ldN, et, h->Qt, h->ldN, gt, P, L, N, NGD_F32, h->Bt, h->ldP, true,
                                   1.0, h->sk_work, h->sk_work_elems, s);
-    GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0};
+    GemmArgs g4{L, P, N, h->Q, L, false, op->J, op->ldJ, false, h->Bt, h->ldP, NGD_F64, T, T, gt, 1.0, 0.0,
+                h->gemm_work, h->gemm_work_elems, 0};
     return launch_gemm(g4, s);
   }));
   // A = B^T B (FP64) and its eigenpairs lam_hat = Sigma^2, V; U^T = (V Sigma^{-1})^T B^T (FP64
