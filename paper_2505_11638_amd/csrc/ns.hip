@@ -41,6 +41,24 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// sum_i w[i] h[i] + y0 over i < n: four products in flight per step (the LDS reads of a step issue
+// together instead of one latency each), two partial sums
+template <typename T>
+__device__ __forceinline__ V4<T> ns_dot(const T* __restrict__ w, const V4<T>* __restrict__ h, int n, V4<T> y0) {
+  V4<T> y1 = {T(0), T(0), T(0), T(0)};
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {
+    const T w0 = w[i], w1 = w[i + 1], w2 = w[i + 2], w3 = w[i + 3];
+    const V4<T> h0 = h[i], h1 = h[i + 1], h2 = h[i + 2], h3 = h[i + 3];
+    y0 += w0 * h0;
+    y1 += w1 * h1;
+    y0 += w2 * h2;
+    y1 += w3 * h3;
+  }
+  for (; i < n; ++i) y0 += w[i] * h[i];
+  return y0 + y1;
+}
+
 __host__ __device__ inline int ns_out_width(const NsDesc& nd, int net, int l) {
   return l == nd.n_layers - 1 ? (net == 0 ? nd.widths[nd.n_layers] : 1) : nd.widths[l + 1];
 }
@@ -88,8 +106,7 @@ __device__ void ns_forward(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, T x0
     const V4<T>* h = sc + S.in + 64 * l;
     if (lane < n_out) {
       const T* wr = Ws + nd.wl[n][l] + lane * (n_in + 1);
-      V4<T> z = {wr[n_in], T(0), T(0), T(0)};
-      for (int i = 0; i < n_in; ++i) z += wr[i] * h[i];
+      const V4<T> z = ns_dot(wr, h, n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
       sc[S.pre + 64 * l + lane] = V4<T>{T(0), z.y, z.z, z.w};
       const T a = tanh(z.x), s1 = T(1) - a * a, s2 = T(-2) * a * s1;
       sc[S.in + 64 * (l + 1) + lane] = V4<T>{a, s1 * z.y, s1 * z.z, s1 * z.w + s2 * (z.y * z.y + z.z * z.z)};
@@ -101,8 +118,7 @@ __device__ void ns_forward(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, T x0
   V4<T> y = {T(0), T(0), T(0), T(0)};
   if (lane < n_out) {
     const T* wr = Ws + nd.wl[n][l] + lane * (n_in + 1);
-    y.x = wr[n_in];
-    for (int i = 0; i < n_in; ++i) y += wr[i] * h[i];
+    y = ns_dot(wr, h, n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
   }
   for (int k = 0; k < 2; ++k)
     out[k] = V4<T>{__shfl(y.x, k), __shfl(y.y, k), __shfl(y.z, k), __shfl(y.w, k)};
@@ -147,6 +163,7 @@ __device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, cons
     const int tot = n_out * n_in;
     const int q = 64 / n_in, rm = 64 - q * n_in;
     int o = lane / n_in, i = lane - o * n_in;
+#pragma unroll 2
     for (int e = lane; e < tot; e += 64) {
       const V4<T> z = zb[o], hv = h[i];
       dst[e] = z.x * hv.x + z.y * hv.y + z.z * hv.z + z.w * hv.w;
@@ -161,9 +178,19 @@ __device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, cons
     if (l > 0) {
       // adjoint of the layer's inputs: abar_c[i] = sum_o zbar_c[o] W[o][i]
       if (lane < n_in) {
-        V4<T> acc = {T(0), T(0), T(0), T(0)};
-        for (int o2 = 0; o2 < n_out; ++o2) acc += W[o2 * pitch + lane] * zb[o2];
-        adj[lane] = acc;
+        V4<T> a0 = {T(0), T(0), T(0), T(0)}, a1 = a0;
+        int o2 = 0;
+        for (; o2 + 4 <= n_out; o2 += 4) {
+          const T w0 = W[o2 * pitch + lane], w1 = W[(o2 + 1) * pitch + lane];
+          const T w2 = W[(o2 + 2) * pitch + lane], w3 = W[(o2 + 3) * pitch + lane];
+          const V4<T> z0 = zb[o2], z1 = zb[o2 + 1], z2 = zb[o2 + 2], z3 = zb[o2 + 3];
+          a0 += w0 * z0;
+          a1 += w1 * z1;
+          a0 += w2 * z2;
+          a1 += w3 * z3;
+        }
+        for (; o2 < n_out; ++o2) a0 += W[o2 * pitch + lane] * zb[o2];
+        adj[lane] = a0 + a1;
       }
       wave_sync();
     }
