@@ -80,7 +80,8 @@ def bench_paper(a):
     P, N = prob.n_params, prob.n_rows
     variant = a.solver if a.solver in ("rpchol", "direct") else a.test_matrix
     if a.solver == "rpchol":  # RPCholNGD (Alg. 5): block size 20, rank up to 500
-        ngd = NGD(prob, theta0, solver="rpchol", rtol=1e-6, seed=a.seed, ell_max=prob.ell_max)
+        ngd = NGD(prob, theta0, solver="rpchol", rtol=1e-6, seed=a.seed, ell_max=prob.ell_max,
+                  rpchol_form=a.rpchol_form)
     elif a.solver == "direct":  # NGD full (Alg. 2): explicit FP64 Gramian and its Cholesky factor
         ngd = NGD(prob, theta0, solver="direct", seed=a.seed)
     else:
@@ -122,7 +123,8 @@ def bench_paper(a):
         "config": {"workload": f"{a.config}: {WORKLOADS[a.config]}; {a.warmup} + {a.steps} NGD steps from a "
                                f"Glorot start (the last {a.steps} timed)", "P": P, "N": N,
                    "ell0": prob.ell, "ell_max": prob.ell_max, "dell": prob.dell, "maxit": prob.maxit,
-                   "preconditioner": variant, "damping": prob.damping},
+                   "preconditioner": variant if variant != "rpchol" else f"rpchol ({a.rpchol_form})",
+                   "damping": prob.damping},
         "ell_first_last_max": [ranks[0], ranks[-1], max(ranks)],
         "ell_trajectory": ranks,
         "mean_pcg_iters": float(np.mean([r.iters for r in reps])),
@@ -375,6 +377,9 @@ def main(argv=None):
     ap.add_argument("--no-cg", action="store_true", help="skip the plain-CG comparison loop")
     ap.add_argument("--phase-steps", type=int, default=5,
                     help="further Nystrom steps, after the timed ones, with every phase timer on")
+    ap.add_argument("--rpchol-form", default="woodbury", choices=["woodbury", "svd"],
+                    help="RPCholNGD's preconditioner: Woodbury-Cholesky (eq. rpchol_precond) or from the eigenpairs "
+                         "of F^T F")
     ap.add_argument("--solver", default="nystrom", choices=["nystrom", "rpchol", "direct"],
                     help="paper3d: Nystrom NGD, RPCholNGD or NGD full")
     ap.add_argument("--test-matrix", default="gaussian", choices=["gaussian", "sampling"],

@@ -305,6 +305,23 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
 ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int64_t rank, void* U, int64_t ldU,
                               double* lam_hat, void* stream);
 
+/*
+ * The RPCholesky preconditioner P = F F^T + mu I in the Woodbury-Cholesky form the paper adopts
+ * (Section 4.2.2, eq. rpchol_precond): P^{-1} v = mu^{-1} (v - W W^T v) with W = F R^{-1},
+ * R^T R = F^T F + mu I (FP64 Gram product and Cholesky factor of the rank x rank core, then W by one
+ * triangular solve; no eigendecomposition). Written in the form ngd_pcg_solve takes: U gets the rows of
+ * W^T and a trailing zero row, lam_hat = [+inf, ..., +inf, 0] (rank + 1 values), for which the apply of
+ * eq. nystrom_inverse, U (Lambda + mu I)^{-1} U^T v + (lam_hat[rank] + mu)^{-1} (v - U U^T v), is
+ * exactly mu^{-1} (v - W W^T v) in IEEE arithmetic. So it preconditions solves with lambda = mu only,
+ * through ngd_pcg_solve (not the damped solve, whose rule reads lam_hat[0]).
+ *   Ft : device, rank x ldF doubles (from ngd_rpcholesky). mu > 0. U : device, (rank + 1) x ldU, dtype,
+ *   out. lam_hat : device, rank + 1 doubles, out. rank + 1 <= max_ell. The handle allocates P x max_ell
+ * doubles on the first call and keeps them (NGD_ERR_OOM if that fails). Synchronises `stream` (checks
+ * the factorisation's exchanges).
+ */
+ngd_status ngd_rpchol_precond_woodbury(ngd_problem* h, const double* Ft, int64_t ldF, int64_t rank, double mu,
+                                       void* U, int64_t ldU, double* lam_hat, void* stream);
+
 /* Nystrom preconditioner of eq. nystrom_inverse for G + mu I with mu = the solve's lambda:
  * P^{-1} v = U (Lambda + mu I)^{-1} U^T v + (lam_hat[ell-1] + mu)^{-1} (v - U U^T v). */
 typedef struct {

@@ -89,6 +89,8 @@ SIGNATURES = {
                                  C.POINTER(C.c_double), C.c_void_p]),
     "ngd_rpchol_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                      C.c_void_p]),
+    "ngd_rpchol_precond_woodbury": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_void_p,
+                                              C.c_int64, C.c_void_p, C.c_void_p]),
     "ngd_solution_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]),
     "ngd_batch_create": (C.c_int, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_void_p)]),

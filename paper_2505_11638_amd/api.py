@@ -367,14 +367,20 @@ class Problem:
                                         _stream()), "ngd_rpcholesky")
         return Ft, int(r.value), float(tr.value)
 
-    def rpchol_precond(self, Ft: torch.Tensor, rank: int) -> NystromResult:
-        """The RPCholesky preconditioner as (U, lam_hat) with a trailing zero pair (ngd_rpchol_precond);
-        use it as `precond` of pcg_solve."""
+    def rpchol_precond(self, Ft: torch.Tensor, rank: int, mu: Optional[float] = None) -> NystromResult:
+        """The RPCholesky preconditioner as (U, lam_hat) with a trailing zero pair; use it as `precond` of
+        pcg_solve. With mu: the Woodbury-Cholesky form for solves with lambda = mu
+        (ngd_rpchol_precond_woodbury); without: the form from the eigenpairs of F^T F (ngd_rpchol_precond),
+        valid for any lambda."""
         U = torch.zeros((rank + 1, self.ld), dtype=self.tdtype, device=self.device)
         lam = torch.empty(rank + 1, dtype=torch.float64, device=self.device)
-        L.check(self.lib.ngd_rpchol_precond(self.h, _ptr(Ft), Ft.stride(0), int(rank), _ptr(U), U.stride(0), _ptr(lam),
-                                            _stream()), "ngd_rpchol_precond")
-        return NystromResult(U, lam, {"rank": rank})
+        if mu is None:
+            L.check(self.lib.ngd_rpchol_precond(self.h, _ptr(Ft), Ft.stride(0), int(rank), _ptr(U), U.stride(0),
+                                                _ptr(lam), _stream()), "ngd_rpchol_precond")
+            return NystromResult(U, lam, {"rank": rank})
+        L.check(self.lib.ngd_rpchol_precond_woodbury(self.h, _ptr(Ft), Ft.stride(0), int(rank), float(mu), _ptr(U),
+                                                     U.stride(0), _ptr(lam), _stream()), "ngd_rpchol_precond_woodbury")
+        return NystromResult(U, lam, {"rank": rank, "woodbury_mu": float(mu)})
 
     def solution_error(self, theta: torch.Tensor, X, u_ref, grad_u_ref, sums: Optional[torch.Tensor] = None):
         """Relative L2 and H1 errors of u_theta against (u_ref, grad u_ref) on the points X (n x d), the

@@ -45,6 +45,7 @@ struct ngd_problem {
   int64_t *rp_idx, *rp_st;
   int *rp_cnt, *rp_keep;
   void* rp_Jcols;
+  double* rp_F = nullptr;  // Woodbury form: F row-major (P x max_ell doubles), on first use
   // full-Gramian solve workspace (allocated on first use): G / its factor (P x ldP), the panels'
   // inverse diagonal blocks, the panel staging rows, substitution partials, y, the pivot word
   void* dr_blob = nullptr;
@@ -426,6 +427,7 @@ ngd_status ngd_problem_destroy(ngd_problem* h) {
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->Jc) (void)hipFree(h->Jc);
   if (h->rp_blob) (void)hipFree(h->rp_blob);
+  if (h->rp_F) (void)hipFree(h->rp_F);
   if (h->dr_blob) (void)hipFree(h->dr_blob);
   (void)hipFree(h->base);
   (void)hipHostFree(h->host);
@@ -821,6 +823,46 @@ ngd_status ngd_rpchol_precond(ngd_problem* h, const double* Ft, int64_t ldF, int
   NGD_HIP_TRY(hipStreamSynchronize(s));
   if (hv[0] != 0) {
     set_error("exchange between the workgroups of the tridiagonalisation timed out");
+    return NGD_ERR_HIP;
+  }
+  return NGD_OK;
+}
+
+ngd_status ngd_rpchol_precond_woodbury(ngd_problem* h, const double* Ft, int64_t ldF, int64_t rank, double mu,
+                                       void* U, int64_t ldU, double* lam_hat, void* stream) {
+  NGD_CHECK(h != nullptr && Ft != nullptr && U != nullptr && lam_hat != nullptr, "NULL argument");
+  NGD_CHECK(rank >= 0 && rank + 1 <= h->max_ell, "rank + 1 must be <= max_ell");
+  NGD_CHECK(ldF >= h->P && ldU >= h->P, "ldF and ldU must be >= P");
+  NGD_CHECK(std::isfinite(mu) && mu > 0.0, "mu must be finite and > 0");
+  hipStream_t s = S(stream);
+  const int64_t P = h->P, L = rank;
+  NGD_TRY(launch_zero(static_cast<char*>(U) + (size_t)L * ldU * h->elem, (size_t)ldU * h->elem, s));
+  NGD_TRY(launch_woodbury_lam(lam_hat, (int)L, s));
+  if (L == 0) return NGD_OK;
+  if (h->rp_F == nullptr) {
+    if (hipMalloc((void**)&h->rp_F, sizeof(double) * (size_t)P * h->max_ell) != hipSuccess) {
+      (void)hipGetLastError();
+      h->rp_F = nullptr;
+      set_error("hipMalloc of the Woodbury factor's buffer failed");
+      return NGD_ERR_OOM;
+    }
+  }
+  // R^T R = F^T F + mu I (FP64 Gram product, the Cholesky factor L = R^T of the core), then
+  // W^T = (F L^{-T})^T row by row into U in the working precision
+  GemmArgs g{L, L, P, Ft, ldF, true, Ft, ldF, true, h->M, L, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
+             h->gemm_work, h->gemm_work_elems, 1};
+  NGD_TRY(launch_gemm(g, s));
+  NGD_TRY(launch_add_diag(h->M, L, L, mu, s));
+  // no extra shift; a pivot that rounding left non-positive is floored at 1e-18 tr(M) (far below mu)
+  NGD_TRY(launch_shifted_cholesky(h->M, (int)L, 0.0, 1e-18, h->scal + 200, reinterpret_cast<int*>(h->scal + 210),
+                                  h->cholsync, ++h->chol_epoch, s));
+  NGD_TRY(launch_transpose_cast(NGD_F64, Ft, ldF, L, P, NGD_F64, h->rp_F, L, s));
+  NGD_TRY(launch_trsm_q(h->M, (int)L, NGD_F64, h->rp_F, P, nullptr, h->dtype, U, ldU, s));
+  int* hv = reinterpret_cast<int*>(h->host);
+  NGD_HIP_TRY(hipMemcpyAsync(hv, h->cholsync + 128, sizeof(int), hipMemcpyDeviceToHost, s));
+  NGD_HIP_TRY(hipStreamSynchronize(s));
+  if (hv[0] != 0) {
+    set_error("exchange between the workgroups of the Cholesky factorisation timed out");
     return NGD_ERR_HIP;
   }
   return NGD_OK;

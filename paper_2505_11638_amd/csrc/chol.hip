@@ -8,6 +8,7 @@
 // factorisation never fails; the directions involved are left shrunk in Q (the effect of the
 // shift nu in Alg. 6). Their count is reported as a rank deficit.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -127,7 +128,10 @@ __global__ __launch_bounds__(64 * kTqWaves) void trsm_q_kernel(const double* __r
           const int c = j0 + 4 * lq + r;
           if (c < ell) {
             if (Q != nullptr) Q[row * ell + c] = b[r];
-            if (Qt != nullptr) Qt[(int64_t)c * ldqt + row] = (TQT)(float)b[r];
+            if (Qt != nullptr) {
+              if constexpr (std::is_same<TQT, double>::value) Qt[(int64_t)c * ldqt + row] = b[r];
+              else Qt[(int64_t)c * ldqt + row] = (TQT)(float)b[r];
+            }
           }
         }
       }
@@ -419,7 +423,7 @@ ngd_status launch_shifted_cholesky(double* M, int n, double shift_rel, double fl
 }
 
 // Q = Z L^{-T} for Z (N x ell, ld ell, FP32 or FP64): Q in FP64 (N x ell, ld ell) and / or Q^T
-// (ell x ldqt) in `qt_type` (FP32 or BF16); either output may be NULL. ell <= 1024.
+// (ell x ldqt) in `qt_type` (FP32 or BF16; FP64 for FP64 Z); either output may be NULL. ell <= 1024.
 ngd_status launch_trsm_q(const double* L, int ell, int z_type, const void* Z, int64_t N, double* Q, int qt_type,
                          void* Qt, int64_t ldqt, hipStream_t s) {
   if (N <= 0 || ell <= 0) return NGD_OK;
@@ -428,6 +432,7 @@ ngd_status launch_trsm_q(const double* L, int ell, int z_type, const void* Z, in
   if (z_type == NGD_F32 && qt_type == NGD_F32) return run_trsm_q<float, float>(L, ell, Z, N, Q, Qt, ldqt, s);
   if (z_type == NGD_F32 && qt_type == NGD_BF16) return run_trsm_q<float, __bf16>(L, ell, Z, N, Q, Qt, ldqt, s);
   if (z_type == NGD_F64 && qt_type == NGD_BF16) return run_trsm_q<double, __bf16>(L, ell, Z, N, Q, Qt, ldqt, s);
+  if (z_type == NGD_F64 && qt_type == NGD_F64) return run_trsm_q<double, double>(L, ell, Z, N, Q, Qt, ldqt, s);
   set_error("trsm: unsupported types");
   return NGD_ERR_INVALID;
 }

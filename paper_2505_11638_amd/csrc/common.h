@@ -338,6 +338,7 @@ ngd_status launch_axpy_theta(int dtype, const void* theta, const double* d, cons
 ngd_status launch_sketch_info(const double* lam, int L, const double* core, const int* eig_err, const int* chol_err,
                               double* out, hipStream_t s);
 // Armijo decision for nt trials on the device: st = [found, alpha, loss, index] (left as it is once found)
+ngd_status launch_woodbury_lam(double* lam, int n, hipStream_t s);
 ngd_status launch_lm_damping(const double* gd, const double* dgd, double alpha, double loss0, double loss1, double mu,
                              double floor_mu, double* out, hipStream_t s);
 ngd_status launch_armijo(const double* alphas, const double* losses, const double* slope, double loss0, double c1,

@@ -78,6 +78,13 @@ __global__ void lm_damping_kernel(const double* __restrict__ gd, const double* _
   out[1] = rho;
 }
 
+// lam[i] = +inf for i < n, lam[n] = 0: the eigenvalue slots under which the preconditioner apply of
+// eq. nystrom_inverse reproduces the Woodbury form eq. rpchol_precond exactly
+__global__ void woodbury_lam_kernel(double* __restrict__ lam, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x)
+    lam[i] = i < n ? __builtin_huge_val() : 0.0;
+}
+
 // The sketch's summary for the host, gathered so that one copy brings it back:
 // out[0] = lam[0], out[1] = lam[L-1], out[2] = #{lam > 0}, out[3] = core[1] (the shift nu),
 // out[4] = the modified-pivot count (an int stored at core[10]), out[5], out[6] = the error words.
@@ -255,6 +262,12 @@ ngd_status launch_armijo(const double* alphas, const double* losses, const doubl
 ngd_status launch_lm_damping(const double* gd, const double* dgd, double alpha, double loss0, double loss1, double mu,
                              double floor_mu, double* out, hipStream_t s) {
   hipLaunchKernelGGL(lm_damping_kernel, dim3(1), dim3(64), 0, s, gd, dgd, alpha, loss0, loss1, mu, floor_mu, out);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
+ngd_status launch_woodbury_lam(double* lam, int n, hipStream_t s) {
+  hipLaunchKernelGGL(woodbury_lam_kernel, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, lam, n);
   NGD_HIP_TRY(hipGetLastError());
   return NGD_OK;
 }

@@ -317,14 +317,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void transpose_cast_kernel(const TS* __restrict__ src, int64_t ld_s, int64_t rows,
                                                              int64_t cols, TD* __restrict__ dst, int64_t ld_d) {
-  __shared__ float tile[64][65];
+  // staged in FP32 (the value is rounded to TD anyway), in FP64 for an FP64 destination
+  using TT = typename std::conditional<std::is_same<TD, double>::value, double, float>::type;
+  __shared__ TT tile[64][65];
   const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int r = ty + 4 * k;
     const int64_t gr = r0 + r, gc = c0 + tx;
-    tile[r][tx] = (gr < rows && gc < cols) ? (float)src[gr * ld_s + gc] : 0.f;
+    tile[r][tx] = (gr < rows && gc < cols) ? (TT)src[gr * ld_s + gc] : TT(0);
   }
   __syncthreads();
 #pragma unroll
@@ -557,6 +559,7 @@ ngd_status launch_transpose_cast(int src_type, const void* src, int64_t ld_s, in
   else if (src_type == NGD_F32 && dst_type == NGD_F32) NGD_TC(float, float);
   else if (src_type == NGD_F64 && dst_type == NGD_BF16) NGD_TC(double, __bf16);
   else if (src_type == NGD_F64 && dst_type == NGD_F32) NGD_TC(double, float);
+  else if (src_type == NGD_F64 && dst_type == NGD_F64) NGD_TC(double, double);
   else {
     set_error("transpose_cast: unsupported types");
     return NGD_ERR_INVALID;

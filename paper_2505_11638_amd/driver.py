@@ -51,7 +51,8 @@ class StepReport:
 class NGD:
     def __init__(self, data, theta0, *, solver="nystrom", ell=None, sketch_dtype=None, rtol=1e-6,
                  maxit=None, lam=None, gamma=10.0, seed=0, power_v0=None, dtype=None, recompute=None,
-                 ell_max=None, dell=None, rank_offset=1, test_matrix="gaussian", damping=None):
+                 ell_max=None, dell=None, rank_offset=1, test_matrix="gaussian", damping=None,
+                 rpchol_form="woodbury"):
         # adaptive sketch size when a maximum is given (here or by the problem)
         self.ell_max = ell_max if ell_max is not None else getattr(data, "ell_max", None)
         self.dell = int(dell if dell is not None else getattr(data, "dell", 20))
@@ -72,6 +73,9 @@ class NGD:
         if self.ell_max is not None:
             self.ell_max = min(int(self.ell_max), gp.P - (1 if solver == "rpchol" else 0))
         self.rp_block = 20  # block size of the block RPCholesky (experimental setup of Section 5)
+        if rpchol_form not in ("woodbury", "svd"):
+            raise ValueError("rpchol_form must be 'woodbury' or 'svd'")
+        self.rpchol_form = rpchol_form  # Woodbury-Cholesky (eq. rpchol_precond) or the SVD form
         self.Ft = None
         self.ell = min(int(ell or data.ell), gp.P, self.ell_max or gp.P)
         self.sketch_dtype = sketch_dtype or getattr(data, "sketch_dtype", None)
@@ -159,7 +163,8 @@ class NGD:
                 self.diag = gp.gramian_diagonal(J, out=self.diag)
                 self.Ft, rank, _ = gp.rpcholesky(J, self.diag, self.ell_max, self.rp_block, seed=self.seed,
                                                  counter=self.k, eps=mu * gp.P, Ft=self.Ft)
-                pc = gp.rpchol_precond(self.Ft, rank)
+                # the Woodbury-Cholesky form the paper adopts (eq. rpchol_precond), for this step's mu
+                pc = gp.rpchol_precond(self.Ft, rank, mu=mu if self.rpchol_form == "woodbury" else None)
                 self.last_rank = rank
             if self.solver == "direct":
                 d = gp.direct_solve(J, grad, mu, out=self.d)

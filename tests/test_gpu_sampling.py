@@ -15,6 +15,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("no GPU", allow_module_level=True)
 
 from oracle import mlp, nystrom, sampling  # noqa: E402
+from paper_2505_11638_amd import _lib as L  # noqa: E402
 from paper_2505_11638_amd.api import Problem, Recompute  # noqa: E402
 from paper_2505_11638_amd.driver import NGD  # noqa: E402
 
@@ -256,6 +257,64 @@ def test_rpchol_preconditioner_and_solve(name):
     else:
         # rtol 1e-6 sits a few units above FP32 roundoff: the FP32 matvec needs a few more iterations
         assert ref.iters - 3 <= out.iters <= ref.iters + max(6, 0.5 * ref.iters)
+    gp.close()
+
+
+@pytest.mark.parametrize("name", ["poisson2d_f64", "poisson2d_f32"])
+@pytest.mark.parametrize("ell_max", [30, 7])
+def test_rpchol_woodbury_preconditioner_and_solve(name, ell_max):
+    """The Woodbury-Cholesky form (eq. rpchol_precond): U holds W^T = (F R^{-1})^T with R^T R = F^T F + mu I
+    and a zero row, lam_hat = [inf, ..., inf, 0]; the apply it implies equals the oracle's Woodbury apply on
+    the GPU's own F; PCG with it solves (G + mu I) d = g in the oracle's Woodbury-PCG iteration count."""
+    from oracle import cg, linalg
+    prob, th, gp0, theta, J = _setup(name)
+    gp0.close()
+    gp = Problem(prob, dtype=prob.dtype, max_ell=ell_max + 1)
+    theta = gp.theta(th)
+    J = gp.new_jacobian()
+    r_, J, grad, loss = gp.residual_jacobian(theta, J)
+    Jg = J.cpu().numpy().astype(np.float64)[:, :gp.P]
+    G = Jg.T @ Jg
+    mu = prob.lam
+    d = gp.gramian_diagonal(J)
+    Ft, r, _ = gp.rpcholesky(J, d, ell_max, 10, seed=1, counter=0, eps=mu * gp.P)
+    pc = gp.rpchol_precond(Ft, r, mu=mu)
+    U = pc.U.cpu().numpy().astype(np.float64)[:, :gp.P]
+    lam = pc.lam_hat.cpu().numpy()
+    assert lam.size == r + 1 and lam[-1] == 0 and np.all(np.isinf(lam[:-1])) and np.all(U[-1] == 0)
+    F = Ft.cpu().numpy()[:r, :gp.P].T
+    Lc = np.linalg.cholesky(F.T @ F + mu * np.eye(r))
+    Wt = np.linalg.solve(Lc, F.T)  # rows of W^T = L^{-1} F^T
+    tol = 1e-10 if prob.dtype == "f64" else 1e-5
+    assert np.linalg.norm(U[:r] - Wt) <= tol * np.linalg.norm(Wt)
+    X = wl.probe_vectors(gp.P, 4, seed=2)
+    applied = (X - U[:r].T @ (U[:r] @ X)) / mu
+    ref_apply = sampling.rpchol_precond_apply(F, mu, X)
+    assert np.linalg.norm(applied - ref_apply) <= tol * np.linalg.norm(ref_apply)
+    g = grad.cpu().numpy()
+    rtol = 1e-8 if prob.dtype == "f64" else 1e-6
+    out = gp.pcg_solve(J, grad, mu, precond=pc, rtol=rtol, maxit=2000)
+    assert out.converged
+    dstar = linalg.solve_cholesky(G, g, mu)
+    res = np.linalg.norm(g - G @ out.d.cpu().numpy() - mu * out.d.cpu().numpy())
+    assert res <= 10 * rtol * np.linalg.norm(g)
+    assert np.linalg.norm(out.d.cpu().numpy() - dstar) <= res / mu * (1 + 1e-6) + 1e-12 * np.linalg.norm(dstar)
+    ref = cg.pcg(lambda v: G @ v + mu * v, g, rtol, 2000, lambda v: sampling.rpchol_precond_apply(F, mu, v))
+    assert ref.converged
+    # the same operator as the form from the eigenpairs of F^T F: about the same iteration count
+    out_svd = gp.pcg_solve(J, grad, mu, precond=gp.rpchol_precond(Ft, r), rtol=rtol, maxit=2000)
+    if prob.dtype == "f64":
+        assert abs(out.iters - ref.iters) <= max(3, 0.25 * ref.iters)
+        assert abs(out_svd.iters - out.iters) <= max(2, 0.1 * out.iters)
+    else:
+        # U in FP32: both forms apply mu^{-1} v minus a near-equal FP32 correction along the kept directions
+        # (the cancellation 1 - sigma^2 / (sigma^2 + mu)), so with few pivots (a weak preconditioner, rtol a few
+        # units above FP32 roundoff) the FP32 solve takes more iterations than the FP64 oracle; the two forms
+        # stay alike
+        assert ref.iters - 3 <= out.iters <= 2 * ref.iters + 6
+        assert abs(out_svd.iters - out.iters) <= max(3, 0.25 * out.iters)
+    with pytest.raises(L.NgdError):
+        gp.rpchol_precond(Ft, r, mu=0.0)
     gp.close()
 
 
