@@ -363,7 +363,9 @@ ngd_status run_f64(const GemmArgs& g, hipStream_t s) {
   if (tiles == 0) return NGD_OK;
   int ks = 1;
   if (g.work != nullptr && g.work_elems > 0) {
-    while (tiles * ks * 2 <= 1024 && g.K / (ks * 2) >= 8 * kDK && (int64_t)ks * 2 * g.M * g.N <= g.work_elems) ks *= 2;
+    // a workgroup keeps one 16-deep slab of each operand in flight, so a long K over few output tiles (the
+    // sketch products at small ell) needs several workgroups per CU to cover the memory latency
+    while (tiles * ks * 2 <= 4096 && g.K / (ks * 2) >= 8 * kDK && (int64_t)ks * 2 * g.M * g.N <= g.work_elems) ks *= 2;
   }
   const int64_t kchunk = ks == 1 ? g.K : ((g.K + ks - 1) / ks + kDK - 1) / kDK * kDK;
   const int av = vec_ok<TA>(g.A, g.lda), bv = vec_ok<TB>(g.B, g.ldb);
