@@ -8,9 +8,10 @@
 // with respect to the networks' output channels: the Gauss-Newton linearisation of the convective term
 // puts the row's own velocity and velocity gradient into the seeds.
 //
-// Layout: one workgroup stages both networks' weights in LDS once; each of its waves takes one row at
-// a time, one lane per hidden unit (widths <= 64), its channels in a per-wave LDS scratch with the four
-// channels of a unit side by side (one vector read per unit). The waves of a workgroup never wait for
+// Layout: one workgroup stages both networks' weights in LDS once; each of its waves (eight where the
+// LDS allows, else four) takes one row at a time, one lane per hidden unit (widths <= 64), the hidden
+// layers' output channels in a per-wave LDS scratch with the four channels of a unit side by side (one
+// vector read per unit), the pre-activation channels in registers (the depth is a template parameter). The waves of a workgroup never wait for
 // each other between rows; lanes of one wave exchange values through LDS behind a wave barrier. The
 // Jacobian row is written layer by layer with consecutive lanes on consecutive parameters.
 #include "common.h"
@@ -18,7 +19,7 @@
 namespace ngd {
 namespace {
 
-constexpr int kNsWaves = 4;
+constexpr int kNsWavesMax = 8;
 
 template <typename T>
 struct V4t;
@@ -81,44 +82,43 @@ __device__ void ns_stage_weights(const NsDesc& nd, const T* __restrict__ theta, 
   }
 }
 
-// Per-wave scratch (V4 units): in[l][64] for l < n_layers (input channels of affine layer l), pre[l][64]
-// for hidden l (pre-activation d/dx, d/dy, Laplacian), adj[64] (adjoint of a layer's outputs), zb[64]
-// (adjoint of its pre-activations).
-struct Scratch {
-  int in, pre, adj, zb;
-};
-__host__ __device__ inline Scratch ns_scratch(int n_layers) {
-  return Scratch{0, 64 * n_layers, 64 * (2 * n_layers - 1), 64 * 2 * n_layers};
-}
-__host__ __device__ inline int ns_scratch_v4(int n_layers) { return 64 * (2 * n_layers + 1); }
+// Per-wave scratch (V4 units): hid[l][64] for l < n_layers - 1 (the channels of hidden layer l's outputs,
+// the inputs of layer l + 1), adj[64] (adjoint of a layer's outputs) and zb[64] (adjoint of its
+// pre-activations). The input layer's channels are (x, 1, 0, 0) and (y, 0, 1, 0) and are formed in
+// place; each hidden unit's pre-activation derivative channels stay in its lane's registers.
+__host__ __device__ inline int ns_scratch_v4(int n_layers) { return 64 * (n_layers + 1); }
 
 // Output channels of network n at (x0, x1): out[k] = (value, d/dx, d/dy, Laplacian) of output k, in
-// every lane. Hidden layers: z = W h + b on the value channel, W h on the others, then a = tanh z,
-// s1 = 1 - a^2, s2 = -2 a s1: (a, s1 Gz, s1 Lz + s2 |Gz|^2).
-template <typename T>
-__device__ void ns_forward(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, T x0, T x1, V4<T> out[2]) {
-  const int lane = threadIdx.x & 63, NL = nd.n_layers;
-  const Scratch S = ns_scratch(NL);
-  if (lane < 2) sc[S.in + lane] = lane == 0 ? V4<T>{x0, T(1), T(0), T(0)} : V4<T>{x1, T(0), T(1), T(0)};
-  wave_sync();
+// every lane; pre[l] = the pre-activation channels of hidden layer l in lane = unit. Hidden layers:
+// z = W h + b on the value channel, W h on the others, then a = tanh z, s1 = 1 - a^2, s2 = -2 a s1:
+// (a, s1 Gz, s1 Lz + s2 |Gz|^2).
+template <typename T, int NL>
+__device__ void ns_forward(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, T x0, T x1, V4<T> (&pre)[NL - 1],
+                           V4<T> out[2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
   for (int l = 0; l < NL - 1; ++l) {
     const int n_in = nd.widths[l], n_out = nd.widths[l + 1];
-    const V4<T>* h = sc + S.in + 64 * l;
     if (lane < n_out) {
       const T* wr = Ws + nd.wl[n][l] + lane * (n_in + 1);
-      const V4<T> z = ns_dot(wr, h, n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
-      sc[S.pre + 64 * l + lane] = V4<T>{T(0), z.y, z.z, z.w};
+      V4<T> z;
+      if (l == 0) {  // inputs (x, y): n_in = 2, the bias at wr[2]
+        const T w0 = wr[0], w1 = wr[1];
+        z = V4<T>{wr[2] + w0 * x0 + w1 * x1, w0, w1, T(0)};
+      } else {
+        z = ns_dot(wr, sc + 64 * (l - 1), n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
+      }
+      pre[l] = z;
       const T a = tanh(z.x), s1 = T(1) - a * a, s2 = T(-2) * a * s1;
-      sc[S.in + 64 * (l + 1) + lane] = V4<T>{a, s1 * z.y, s1 * z.z, s1 * z.w + s2 * (z.y * z.y + z.z * z.z)};
+      sc[64 * l + lane] = V4<T>{a, s1 * z.y, s1 * z.z, s1 * z.w + s2 * (z.y * z.y + z.z * z.z)};
     }
     wave_sync();
   }
   const int l = NL - 1, n_in = nd.widths[l], n_out = ns_out_width(nd, n, l);
-  const V4<T>* h = sc + S.in + 64 * l;
   V4<T> y = {T(0), T(0), T(0), T(0)};
   if (lane < n_out) {
     const T* wr = Ws + nd.wl[n][l] + lane * (n_in + 1);
-    y = ns_dot(wr, h, n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
+    y = ns_dot(wr, sc + 64 * (l - 1), n_in, V4<T>{wr[n_in], T(0), T(0), T(0)});
   }
   for (int k = 0; k < 2; ++k)
     out[k] = V4<T>{__shfl(y.x, k), __shfl(y.y, k), __shfl(y.z, k), __shfl(y.w, k)};
@@ -126,31 +126,31 @@ __device__ void ns_forward(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, T x0
 
 // Reverse sweep of network n seeded with seed[k] = d r / d(value, d/dx, d/dy, Laplacian of output k),
 // writing the parameter derivatives into Jn (the row's columns of network n). The forward sweep of the
-// same network must have filled the scratch. For z = W h + b with pre-activation adjoint zbar:
+// same network must have filled the scratch and pre. For z = W h + b with pre-activation adjoint zbar:
 // dW[o][i] = sum_c zbar_c[o] h_c[i], db[o] = zbar_value[o]; hidden-layer zbar from the output adjoint
 // abar by the tanh channel rules (s3 = -2 s1 (s1 - 2 a^2)):
 //   zbar_L = s1 abar_L, zbar_G = s1 abar_G + 2 s2 abar_L Gz,
 //   zbar_v = s1 abar_v + s2 Gz . abar_G + (s2 Lz + s3 |Gz|^2) abar_L.
-template <typename T>
-__device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, const V4<T> seed[2], T* __restrict__ Jn) {
-  const int lane = threadIdx.x & 63, NL = nd.n_layers;
-  const Scratch S = ns_scratch(NL);
-  V4<T>* zb = sc + S.zb;
-  V4<T>* adj = sc + S.adj;
+template <typename T, int NL>
+__device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, const V4<T> (&pre)[NL - 1], T x0, T x1,
+                           const V4<T> seed[2], T* __restrict__ Jn) {
+  const int lane = threadIdx.x & 63;
+  V4<T>* adj = sc + 64 * (NL - 1);
+  V4<T>* zb = sc + 64 * NL;
   {
     const int n_out = ns_out_width(nd, n, NL - 1);
     if (lane < n_out) zb[lane] = lane == 0 ? seed[0] : seed[1];
     wave_sync();
   }
+#pragma unroll
   for (int l = NL - 1; l >= 0; --l) {
     const int n_in = nd.widths[l], n_out = ns_out_width(nd, n, l), pitch = n_in + 1;
     const T* W = Ws + nd.wl[n][l];
-    const V4<T>* h = sc + S.in + 64 * l;
     if (l < NL - 1) {
       if (lane < n_out) {
-        const T a = sc[S.in + 64 * (l + 1) + lane].x;
+        const T a = sc[64 * l + lane].x;
         const T s1 = T(1) - a * a, s2 = T(-2) * a * s1, s3 = T(-2) * s1 * (s1 - T(2) * a * a);
-        const V4<T> p = sc[S.pre + 64 * l + lane];
+        const V4<T> p = pre[l];
         const V4<T> ab = adj[lane];
         const T gsq = p.y * p.y + p.z * p.z;
         zb[lane] = V4<T>{s1 * ab.x + s2 * (p.y * ab.y + p.z * ab.z) + (s2 * p.w + s3 * gsq) * ab.w,
@@ -161,17 +161,25 @@ __device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, cons
     // the layer's weight block (n_out x n_in, row-major) and then its bias
     T* dst = Jn + nd.tl[n][l];
     const int tot = n_out * n_in;
-    const int q = 64 / n_in, rm = 64 - q * n_in;
-    int o = lane / n_in, i = lane - o * n_in;
+    if (l == 0) {  // inputs (x, 1, 0, 0) and (y, 0, 1, 0)
+      for (int e = lane; e < tot; e += 64) {
+        const V4<T> z = zb[e >> 1];
+        dst[e] = (e & 1) ? z.x * x1 + z.z : z.x * x0 + z.y;
+      }
+    } else {
+      const V4<T>* h = sc + 64 * (l - 1);
+      const int q = 64 / n_in, rm = 64 - q * n_in;
+      int o = lane / n_in, i = lane - o * n_in;
 #pragma unroll 2
-    for (int e = lane; e < tot; e += 64) {
-      const V4<T> z = zb[o], hv = h[i];
-      dst[e] = z.x * hv.x + z.y * hv.y + z.z * hv.z + z.w * hv.w;
-      o += q;
-      i += rm;
-      if (i >= n_in) {
-        i -= n_in;
-        ++o;
+      for (int e = lane; e < tot; e += 64) {
+        const V4<T> z = zb[o], hv = h[i];
+        dst[e] = z.x * hv.x + z.y * hv.y + z.z * hv.z + z.w * hv.w;
+        o += q;
+        i += rm;
+        if (i >= n_in) {
+          i -= n_in;
+          ++o;
+        }
       }
     }
     if (lane < n_out) dst[tot + lane] = zb[lane].x;
@@ -198,32 +206,35 @@ __device__ void ns_reverse(const NsDesc& nd, int n, const T* Ws, V4<T>* sc, cons
   wave_sync();  // the caller's next forward sweep overwrites what the last layer's stores read
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64 * kNsWaves) ns_residual_kernel(NsDesc nd, const T* __restrict__ theta,
-                                                                     int64_t theta_stride, int64_t N,
-                                                                     const T* __restrict__ X, const T* __restrict__ w,
-                                                                     const T* __restrict__ f, const T* __restrict__ g,
-                                                                     const int8_t* __restrict__ kind, T* __restrict__ r_w,
-                                                                     T* __restrict__ J, int64_t ldJ, double* loss_partial,
-                                                                     int rows_per_block) {
+// One wave per row, blockDim.x / 64 (4 or 8) waves per workgroup sharing the staged weights.
+template <typename T, int NL>
+__global__ void __launch_bounds__(64 * kNsWavesMax) ns_residual_kernel(NsDesc nd, const T* __restrict__ theta,
+                                                                        int64_t theta_stride, int64_t N,
+                                                                        const T* __restrict__ X, const T* __restrict__ w,
+                                                                        const T* __restrict__ f, const T* __restrict__ g,
+                                                                        const int8_t* __restrict__ kind,
+                                                                        T* __restrict__ r_w, T* __restrict__ J,
+                                                                        int64_t ldJ, double* loss_partial,
+                                                                        int rows_per_block) {
   extern __shared__ __align__(32) unsigned char ns_smem[];
-  __shared__ double red[kNsWaves];
+  __shared__ double red[kNsWavesMax];
   theta += blockIdx.y * theta_stride;
   T* Ws = reinterpret_cast<T*>(ns_smem);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  V4<T>* sc = reinterpret_cast<V4<T>*>(ns_smem + (size_t)nd.w_elems * sizeof(T)) + wid * ns_scratch_v4(nd.n_layers);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  V4<T>* sc = reinterpret_cast<V4<T>*>(ns_smem + (size_t)nd.w_elems * sizeof(T)) + wid * ns_scratch_v4(NL);
   ns_stage_weights(nd, theta, Ws);
   __syncthreads();
   const T nu = (T)nd.nu;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < N ? r0 + rows_per_block : N;
   double lsum = 0.0;
-  for (int64_t r = r0 + wid; r < r1; r += kNsWaves) {
+  V4<T> pre[NL - 1];
+  for (int64_t r = r0 + wid; r < r1; r += nw) {
     const int k = kind[r];
     const T sw = sqrt(w[r]);
     const T x0 = X[2 * r], x1 = X[2 * r + 1];
     V4<T> U[2];  // U[k] = (u_k, d_x u_k, d_y u_k, Laplace u_k)
-    ns_forward(nd, 0, Ws, sc, x0, x1, U);
+    ns_forward<T, NL>(nd, 0, Ws, sc, x0, x1, pre, U);
     const bool mom = k == NGD_ROW_NS_MOMENTUM_X || k == NGD_ROW_NS_MOMENTUM_Y;
     const int c = k == NGD_ROW_NS_MOMENTUM_Y ? 1 : 0;
     T* Jr = J ? J + r * ldJ : nullptr;
@@ -247,12 +258,12 @@ __global__ void __launch_bounds__(64 * kNsWaves) ns_residual_kernel(NsDesc nd, c
       }
       s[0] *= sw;
       s[1] *= sw;
-      ns_reverse(nd, 0, Ws, sc, s, Jr + nd.toff[0]);
+      ns_reverse<T, NL>(nd, 0, Ws, sc, pre, x0, x1, s, Jr + nd.toff[0]);
     }
     T res = T(0);
     if (mom) {
       V4<T> Pc[2];
-      ns_forward(nd, 1, Ws, sc, x0, x1, Pc);
+      ns_forward<T, NL>(nd, 1, Ws, sc, x0, x1, pre, Pc);
       const T dp = c == 0 ? Pc[0].y : Pc[0].z;
       res = -nu * U[c].w + (U[0].x * U[c].y + U[1].x * U[c].z) + dp - f[r];
       if (Jr) {
@@ -260,7 +271,7 @@ __global__ void __launch_bounds__(64 * kNsWaves) ns_residual_kernel(NsDesc nd, c
         V4<T> s[2] = {zero, zero};
         if (c == 0) s[0].y = sw;
         else s[0].z = sw;
-        ns_reverse(nd, 1, Ws, sc, s, Jr + nd.toff[1]);
+        ns_reverse<T, NL>(nd, 1, Ws, sc, pre, x0, x1, s, Jr + nd.toff[1]);
       }
     } else {
       if (k == NGD_ROW_NS_CONTINUITY) res = U[0].y + U[1].z;
@@ -280,7 +291,7 @@ __global__ void __launch_bounds__(64 * kNsWaves) ns_residual_kernel(NsDesc nd, c
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int i = 0; i < kNsWaves; ++i) s += red[i];
+    for (int i = 0; i < nw; ++i) s += red[i];
     loss_partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
 }
@@ -288,23 +299,24 @@ __global__ void __launch_bounds__(64 * kNsWaves) ns_residual_kernel(NsDesc nd, c
 // Velocity error sums at evaluation points (relative L2 / H1 errors on u of Section 5.1.3): one wave
 // per point, per-wave partials, workgroup partials in a fixed order, [|u - u_ref|^2, |grad u -
 // grad u_ref|^2, |u_ref|^2, |grad u_ref|^2].
-template <typename T>
-__global__ void __launch_bounds__(64 * kNsWaves) ns_velocity_error_kernel(NsDesc nd, const T* __restrict__ theta,
-                                                                           const T* __restrict__ X, int64_t n,
-                                                                           const T* __restrict__ u_ref,
-                                                                           const T* __restrict__ grad_ref,
-                                                                           double* part) {
+template <typename T, int NL>
+__global__ void __launch_bounds__(64 * kNsWavesMax) ns_velocity_error_kernel(NsDesc nd, const T* __restrict__ theta,
+                                                                              const T* __restrict__ X, int64_t n,
+                                                                              const T* __restrict__ u_ref,
+                                                                              const T* __restrict__ grad_ref,
+                                                                              double* part) {
   extern __shared__ __align__(32) unsigned char ns_smem[];
-  __shared__ double red[4 * kNsWaves];
+  __shared__ double red[4 * kNsWavesMax];
   T* Ws = reinterpret_cast<T*>(ns_smem);
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  V4<T>* sc = reinterpret_cast<V4<T>*>(ns_smem + (size_t)nd.w_elems * sizeof(T)) + wid * ns_scratch_v4(nd.n_layers);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  V4<T>* sc = reinterpret_cast<V4<T>*>(ns_smem + (size_t)nd.w_elems * sizeof(T)) + wid * ns_scratch_v4(NL);
   ns_stage_weights(nd, theta, Ws);
   __syncthreads();
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t p = (int64_t)blockIdx.x * kNsWaves + wid; p < n; p += (int64_t)gridDim.x * kNsWaves) {
+  V4<T> pre[NL - 1];
+  for (int64_t p = (int64_t)blockIdx.x * nw + wid; p < n; p += (int64_t)gridDim.x * nw) {
     V4<T> U[2];
-    ns_forward(nd, 0, Ws, sc, X[2 * p], X[2 * p + 1], U);
+    ns_forward<T, NL>(nd, 0, Ws, sc, X[2 * p], X[2 * p + 1], pre, U);
     for (int k = 0; k < 2; ++k) {
       const double ur = u_ref[2 * p + k], gx = grad_ref[4 * p + 2 * k], gy = grad_ref[4 * p + 2 * k + 1];
       const double du = (double)U[k].x - ur, dx = (double)U[k].y - gx, dy = (double)U[k].z - gy;
@@ -320,7 +332,7 @@ __global__ void __launch_bounds__(64 * kNsWaves) ns_velocity_error_kernel(NsDesc
   __syncthreads();
   if (threadIdx.x < 4) {
     double t = 0.0;
-    for (int i = 0; i < kNsWaves; ++i) t += red[4 * i + threadIdx.x];
+    for (int i = 0; i < nw; ++i) t += red[4 * i + threadIdx.x];
     part[4 * (size_t)blockIdx.x + threadIdx.x] = t;
   }
 }
@@ -361,22 +373,67 @@ ngd_status ns_describe(int n_layers, const int* widths, double nu, NsDesc* nd) {
   return NGD_OK;
 }
 
+// Waves per workgroup: eight where their scratch fits beside the weights, else four.
+static int ns_waves(const NsDesc& nd, int dtype) {
+  const size_t e = dtype == NGD_F64 ? 8 : 4;
+  const size_t per_wave = (size_t)ns_scratch_v4(nd.n_layers) * 4 * e;
+  return (size_t)nd.w_elems * e + kNsWavesMax * per_wave <= 160 * 1024 ? kNsWavesMax : 4;
+}
+
 size_t ns_lds_bytes(const NsDesc& nd, int dtype) {
   const size_t e = dtype == NGD_F64 ? 8 : 4;
-  return (size_t)nd.w_elems * e + (size_t)kNsWaves * ns_scratch_v4(nd.n_layers) * 4 * e;
+  return (size_t)nd.w_elems * e + (size_t)ns_waves(nd, dtype) * ns_scratch_v4(nd.n_layers) * 4 * e;
 }
 
 int ns_rows_per_block(int64_t N) {
-  // about a thousand workgroups, whole rounds of waves
+  // about a thousand workgroups, whole rounds of the widest workgroup's waves
   int64_t rpb = (N + 1023) / 1024;
-  rpb = (rpb + kNsWaves - 1) / kNsWaves * kNsWaves;
-  return (int)(rpb < kNsWaves ? kNsWaves : rpb);
+  rpb = (rpb + kNsWavesMax - 1) / kNsWavesMax * kNsWavesMax;
+  return (int)(rpb < kNsWavesMax ? kNsWavesMax : rpb);
 }
 
 int ns_blocks(int64_t N) {
   const int rpb = ns_rows_per_block(N);
   return (int)((N + rpb - 1) / rpb);
 }
+
+namespace {
+
+// the kernel instance for the networks' depth (2 .. 8 affine layers)
+template <typename T, int NL>
+const void* ns_res_ptr() { return (const void*)ns_residual_kernel<T, NL>; }
+template <typename T, int NL>
+const void* ns_err_ptr() { return (const void*)ns_velocity_error_kernel<T, NL>; }
+
+template <typename T>
+const void* ns_residual_for(int nl) {
+  switch (nl) {
+    case 2: return ns_res_ptr<T, 2>();
+    case 3: return ns_res_ptr<T, 3>();
+    case 4: return ns_res_ptr<T, 4>();
+    case 5: return ns_res_ptr<T, 5>();
+    case 6: return ns_res_ptr<T, 6>();
+    case 7: return ns_res_ptr<T, 7>();
+    case 8: return ns_res_ptr<T, 8>();
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+const void* ns_error_for(int nl) {
+  switch (nl) {
+    case 2: return ns_err_ptr<T, 2>();
+    case 3: return ns_err_ptr<T, 3>();
+    case 4: return ns_err_ptr<T, 4>();
+    case 5: return ns_err_ptr<T, 5>();
+    case 6: return ns_err_ptr<T, 6>();
+    case 7: return ns_err_ptr<T, 7>();
+    case 8: return ns_err_ptr<T, 8>();
+    default: return nullptr;
+  }
+}
+
+}  // namespace
 
 ngd_status launch_ns_residual(const NsDesc& nd, int dtype, const void* theta, int64_t theta_stride, int n_theta,
                               int64_t N, const void* X, const void* w, const void* f, const void* g,
@@ -387,18 +444,21 @@ ngd_status launch_ns_residual(const NsDesc& nd, int dtype, const void* theta, in
     set_error("Navier-Stokes networks too large for the residual kernel's LDS budget");
     return NGD_ERR_INVALID;
   }
+  const void* k = dtype == NGD_F64 ? ns_residual_for<double>(nd.n_layers) : ns_residual_for<float>(nd.n_layers);
+  if (k == nullptr) {
+    set_error("Navier-Stokes networks need 2 to 8 affine layers");
+    return NGD_ERR_INVALID;
+  }
   if (N <= 0) return NGD_OK;
   const int rpb = ns_rows_per_block(N);
   dim3 grid((unsigned)((N + rpb - 1) / rpb), (unsigned)n_theta);
-  auto go = [&](auto k, auto tag) -> ngd_status {
-    using T = decltype(tag);
-    NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    hipLaunchKernelGGL(k, grid, dim3(64 * kNsWaves), bytes, s, nd, (const T*)theta, theta_stride, N, (const T*)X,
-                       (const T*)w, (const T*)f, (const T*)g, kind, (T*)r_w, (T*)J, ldJ, loss_partial, rpb);
-    return NGD_OK;
-  };
-  NGD_TRY(dtype == NGD_F64 ? go(ns_residual_kernel<double>, 0.0) : go(ns_residual_kernel<float>, 0.f));
-  NGD_HIP_TRY(hipGetLastError());
+  NGD_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  NsDesc ndc = nd;
+  int64_t ts = theta_stride, n = N, ld = ldJ;
+  int rp = rpb;
+  void* args[] = {&ndc, (void*)&theta, &ts, &n, (void*)&X, (void*)&w, (void*)&f, (void*)&g, (void*)&kind,
+                  &r_w, &J, &ld, &loss_partial, &rp};
+  NGD_HIP_TRY(hipLaunchKernel(k, grid, dim3(64 * ns_waves(nd, dtype)), args, bytes, s));
   return NGD_OK;
 }
 
@@ -410,17 +470,20 @@ ngd_status launch_ns_velocity_error(const NsDesc& nd, int dtype, const void* the
     set_error("Navier-Stokes networks too large for the evaluation kernel's LDS budget");
     return NGD_ERR_INVALID;
   }
-  int64_t nb = (n + 8 * kNsWaves - 1) / (8 * kNsWaves);
+  const void* k = dtype == NGD_F64 ? ns_error_for<double>(nd.n_layers) : ns_error_for<float>(nd.n_layers);
+  if (k == nullptr) {
+    set_error("Navier-Stokes networks need 2 to 8 affine layers");
+    return NGD_ERR_INVALID;
+  }
+  const int nw = ns_waves(nd, dtype);
+  int64_t nb = (n + 8 * nw - 1) / (8 * nw);
   nb = nb < 1 ? 1 : (nb > max_blocks ? max_blocks : nb);
   if (n > 0) {
-    auto go = [&](auto k, auto tag) -> ngd_status {
-      using T = decltype(tag);
-      NGD_HIP_TRY(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-      hipLaunchKernelGGL(k, dim3((unsigned)nb), dim3(64 * kNsWaves), bytes, s, nd, (const T*)theta, (const T*)X, n,
-                         (const T*)u_ref, (const T*)grad_ref, part);
-      return NGD_OK;
-    };
-    NGD_TRY(dtype == NGD_F64 ? go(ns_velocity_error_kernel<double>, 0.0) : go(ns_velocity_error_kernel<float>, 0.f));
+    NGD_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    NsDesc ndc = nd;
+    int64_t nn = n;
+    void* args[] = {&ndc, (void*)&theta, (void*)&X, &nn, (void*)&u_ref, (void*)&grad_ref, &part};
+    NGD_HIP_TRY(hipLaunchKernel(k, dim3((unsigned)nb), dim3(64 * nw), args, bytes, s));
   } else {
     nb = 0;
   }
