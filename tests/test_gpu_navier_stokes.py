@@ -1,8 +1,8 @@
 """The Navier-Stokes rows (the Kovasznay flow of Section 5.1.3) on the GPU against the FP64 oracle (MI355X).
 
 Tolerances (relative): 1e-10 in FP64, 1e-5 in FP32 (the Jacobian row by row); FP32 results are compared
-with the oracle on the FP32-rounded inputs. Row counts are ragged against the kernel's four rows per
-workgroup round; the paper's size (32,000 rows, P = 8,688, FP64) is checked on sampled rows."""
+with the oracle on the FP32-rounded inputs. Row counts are ragged against the kernel's rounds of one row
+per wave; the paper's size (32,000 rows, P = 8,688, FP64) is checked on sampled rows."""
 import numpy as np
 import pytest
 
@@ -183,3 +183,31 @@ def test_ns_refuses_the_recompute_mode_and_batches():
     r, _, _, _ = gp.residual_jacobian(theta, J)
     torch.cuda.synchronize()
     assert rel(r.cpu().numpy(), ns.weighted_residual(th, prob)) <= 1e-10
+
+
+@pytest.mark.parametrize("variant", ["rpchol", "sampling"])
+def test_ns_rpchol_and_sampling_ngd_steps(variant):
+    """The paper's other preconditioners on the Navier-Stokes rows (Section 5.1.3 runs both): RPCholNGD with
+    the Woodbury-Cholesky preconditioner and Nystrom NGD with a sampling test matrix, Levenberg-Marquardt
+    damping; every PCG direction within the residual bound of the direct solve on the oracle's Gramian and
+    the loss falling."""
+    prob, th = _make(**CASES["small_f64"])
+    if variant == "rpchol":
+        ngd = NGD(prob, th, solver="rpchol", rtol=1e-10, ell_max=40, seed=4)
+    else:
+        ngd = NGD(prob, th, solver="nystrom", test_matrix="sampling", rtol=1e-10, ell=30, ell_max=60, seed=4)
+    theta = th.copy()
+    losses = []
+    for k in range(5):
+        rep = ngd.step()
+        r_o, J_o = ns.residual_and_jacobian(theta, prob)
+        g = J_o.T @ r_o
+        G = J_o.T @ J_o
+        d_star = np.linalg.solve(G + rep.mu * np.eye(G.shape[0]), g)
+        d = ngd.d.cpu().numpy()
+        bound = max(rep.rel_res, 1e-10) * np.linalg.norm(g) / rep.mu
+        assert np.linalg.norm(d - d_star) <= 1.01 * bound + 1e-9 * np.linalg.norm(d_star)
+        assert rep.loss_new <= rep.loss
+        losses.append(rep.loss)
+        theta = ngd.theta.cpu().numpy()
+    assert losses[-1] < 0.5 * losses[0]
