@@ -140,16 +140,24 @@ template <typename T>
 __device__ __forceinline__ void mfma_forward(const T* Ws, int n_in, int n_out, const T* hb, int nm, int npc, int C,
                                              const T* __restrict__ b, T* pre, int ldo = 0) {
   if (ldo == 0) ldo = n_out;
-  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // the tile index is wave-uniform: scalar registers keep its divisions off the vector ALUs
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int tm = (npc + 15) / 16, tn = (n_out + 15) / 16;
+  // the lane's accumulator rows are r0, r0 + rs, r0 + 2 rs, r0 + 3 rs of the tile (the MFMA layouts)
+  const int kq = (threadIdx.x & 63) >> 4;
+  const int r0 = sizeof(T) == 8 ? kq : 4 * kq, rs = sizeof(T) == 8 ? 4 : 1;
   for (int t = wid; t < tm * tn; t += nw) {
     const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    // channel of the lane's first row (pc % C, the value channel takes the bias), then stepped by rs
+    int ch = (m0 + r0) % C;
     mfma_tile<T>(
         n_in, [&](int r, int k) { const int pc = m0 + r; return (pc < npc && k < n_in) ? hb[pc * nm + k] : T(0); },
         [&](int k, int c) { const int o = n0 + c; return (o < n_out && k < n_in) ? Ws[o * (n_in + 1) + k] : T(0); },
         [&](int r, int c, T v) {
           const int pc = m0 + r, o = n0 + c;
-          if (pc < npc && o < n_out) pre[pc * ldo + o] = v + (pc % C == 0 ? b[o] : T(0));
+          if (pc < npc && o < n_out) pre[pc * ldo + o] = v + (ch == 0 ? b[o] : T(0));
+          ch += rs;
+          while (ch >= C) ch -= C;
         });
   }
 }
@@ -159,7 +167,7 @@ template <typename T>
 __device__ __forceinline__ void mfma_forward_tangent(const T* Ws, const T* Wd, int n_in, int n_out, const T* hb,
                                                      const T* hd, int nm, int npc, int C, const T* __restrict__ bd,
                                                      T* zd) {
-  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int tm = (npc + 15) / 16, tn = (n_out + 15) / 16;
   for (int t = wid; t < tm * tn; t += nw) {
     const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
@@ -179,7 +187,7 @@ __device__ __forceinline__ void mfma_forward_tangent(const T* Ws, const T* Wd, i
 // ab[pc][i] = sum_o W[o][i] zb[pc][o] for pc < npc, i < n_in (the adjoint product W^T z)
 template <typename T>
 __device__ __forceinline__ void mfma_adjoint(const T* Ws, int n_in, int n_out, const T* zb, int nm, int npc, T* ab) {
-  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int tm = (npc + 15) / 16, tn = (n_in + 15) / 16;
   for (int t = wid; t < tm * tn; t += nw) {
     const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
@@ -465,9 +473,12 @@ __device__ void residual_body(const NetDesc& net, const T* __restrict__ theta, i
         put(bo + o, acc);
       }
     } else {
-      // per point p: the W_l block of J_p is zbar_p (n_out x C) times h_p^T (C x n_in), K = C
-      for (int t = wid; t < nvalid * tmo * tni; t += nw) {
-        const int p = t / (tmo * tni), tt = t - p * (tmo * tni);
+      // per point p: the W_l block of J_p is zbar_p (n_out x C) times h_p^T (C x n_in), K = C. The tile
+      // index is the same in every lane of a wave: kept in scalar registers, so that its divisions do
+      // not occupy the vector ALUs
+      const int tpp = tmo * tni, wid_s = __builtin_amdgcn_readfirstlane(wid);
+      for (int t = wid_s; t < nvalid * tpp; t += nw) {
+        const int p = t / tpp, tt = t - p * tpp;
         const int o0 = (tt / tni) * 16, i0 = (tt % tni) * 16;
         const T* zbp = s.zb + (int64_t)p * C * nm;
         const T* hbp = s.hb + (int64_t)p * C * nm;
