@@ -319,8 +319,9 @@ ngd_status ngd_problem_create(const ngd_problem_desc* d, ngd_problem** out) {
   h->elem = d->dtype == NGD_F64 ? 8 : 4;
   h->tp = residual_block_rows(net, d->dtype);
   h->res_blocks = ns ? ns_blocks(h->N) : (int)((h->N + h->tp - 1) / h->tp);
-  // Navier-Stokes trial losses: four per launch (each launch is a few rounds of resident workgroups)
-  h->ls_batch = ns ? std::min(4, kTrials) : residual_trials_per_launch(net, d->dtype, h->N, kTrials);
+  // Navier-Stokes trial losses: one per launch (a trial fills the device by itself, so a batch of trials
+  // costs their sum and gains only the host round trips)
+  h->ls_batch = ns ? 1 : residual_trials_per_launch(net, d->dtype, h->N, kTrials);
   h->nwg = gram_rows_grid(d->dtype, h->N, h->P);
   h->nwg_vjp = vjp_grid(net, d->dtype, h->N, h->nwg);
 
