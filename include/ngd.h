@@ -440,6 +440,10 @@ ngd_status ngd_line_search(ngd_problem* h, const void* theta, const double* d, c
  *   sums  : device, 4 doubles, out (zeros for n = 0). The arithmetic is FP64 and its order is fixed.
  * Asynchronous on `stream`. NGD_ERR_INVALID for n < 0 or NULL pointers (any pointer may be NULL
  * when n = 0 except sums).
+ * Navier-Stokes handles measure the velocity (the error of Section 5.1.3): X is n x 2, u_ref n x 2
+ * (u_1, u_2), grad_u_ref n x 2 x 2 row-major ([k][j] = d u_k / d x_j), and the sums run over both
+ * components; the network is evaluated in the problem's dtype, the sums in FP64 (per wave in point
+ * order, then per workgroup, then over workgroups, all in a fixed order).
  */
 ngd_status ngd_solution_error(ngd_problem* h, const void* theta, const void* X, int64_t n, const void* u_ref,
                               const void* grad_u_ref, double* sums, void* stream);
