@@ -284,8 +284,9 @@ ngd_status ngd_direct_solve(ngd_problem* h, const ngd_operator* op, const double
  *   diag  : device, P doubles: d^(0) = diag(G) (ngd_gramian_diagonal); not modified.
  *   Ft    : device, ell_max x ldF doubles, out: row k = column k of F (rows >= rank are zero).
  *   rank  : host, out: r. trace : host, nullable, out: sum(d) at the end.
- * 1 <= block <= 64, 1 <= ell_max <= min(1024, P), ldF >= P, eps >= 0. Needs the stored J_w
- * (op->J != NULL). Synchronises `stream`.
+ * 1 <= block <= 64, 1 <= ell_max <= min(1024, P), ldF >= P, eps >= 0. Stored J_w, or the recompute
+ * mode (op->J == NULL: every round recomputes J_w's rows a block at a time for its columns products).
+ * Synchronises `stream`.
  */
 ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* diag, int64_t ell_max,
                           int32_t block, uint64_t seed, uint64_t counter, double eps, double* Ft, int64_t ldF,

@@ -753,12 +753,13 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
                           double* trace, void* stream) {
   NGD_CHECK(h != nullptr && op != nullptr && diag != nullptr && Ft != nullptr && rank != nullptr, "NULL argument");
   NGD_TRY(check_op(h, op));
-  NGD_CHECK(op->J != nullptr, "rpcholesky needs the stored J_w (the recompute mode is not supported)");
   NGD_CHECK(block >= 1 && block <= kRpBlockMax, "block must be in [1, 64]");
   NGD_CHECK(ell_max >= 1 && ell_max <= std::min<int64_t>(kMaxEll, h->P), "ell_max must be in [1, min(1024, P)]");
   NGD_CHECK(ldF >= h->P, "ldF < P");
   NGD_CHECK(eps >= 0.0, "eps must be >= 0");
   NGD_TRY(rp_ensure(h));
+  const bool rec = op->J == nullptr;  // recompute mode: J_w's rows a block at a time, every round
+  if (rec) NGD_TRY(jc_ensure(h));
   hipStream_t s = S(stream);
   const int64_t P = h->P, N = h->N;
   const int T = h->dtype;
@@ -770,11 +771,23 @@ ngd_status ngd_rpcholesky(ngd_problem* h, const ngd_operator* op, const double* 
   for (int64_t i = 0; i < rounds; ++i) {
     // S' = Unique(b draws ~ d); C^T = (G[:, S'] - F F[S', :]^T)^T = J[:, S']^T J - F[S', :] F^T
     NGD_TRY(launch_sample_pivots(h->rp_d, P, seed, counter, (uint32_t)i, b, 1, h->rp_idx, h->rp_cnt, s, h->rp_st + 1));
-    NGD_TRY(launch_gather_cols(T, op->J, op->ldJ, N, h->rp_idx, b, h->rp_Jcols, b, s));
-    // (a b x P output over K = N: split K through the core's GEMM workspace, idle here)
-    GemmArgs g1{b, P, N, h->rp_Jcols, b, false, op->J, op->ldJ, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64, 1.0,
-                0.0, h->gemm_work, h->gemm_work_elems};
-    NGD_TRY(launch_gemm(g1, s));
+    if (!rec) {
+      NGD_TRY(launch_gather_cols(T, op->J, op->ldJ, N, h->rp_idx, b, h->rp_Jcols, b, s));
+      // (a b x P output over K = N: split K through the core's GEMM workspace, idle here)
+      GemmArgs g1{b, P, N, h->rp_Jcols, b, false, op->J, op->ldJ, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64, 1.0,
+                  0.0, h->gemm_work, h->gemm_work_elems};
+      NGD_TRY(launch_gemm(g1, s));
+    } else {
+      // C^T summed over row blocks of J_w recomputed from theta
+      for (int64_t r0 = 0; r0 < N; r0 += h->jc_rows) {
+        const int64_t rows = std::min<int64_t>(h->jc_rows, N - r0);
+        NGD_TRY(jc_rows_at(h, op->theta, r0, rows, s));
+        NGD_TRY(launch_gather_cols(T, h->Jc, h->ldP, rows, h->rp_idx, b, h->rp_Jcols, b, s));
+        GemmArgs g1{b, P, rows, h->rp_Jcols, b, false, h->Jc, h->ldP, false, h->rp_Ct, h->ldP, T, T, NGD_F64, G_F64,
+                    1.0, r0 == 0 ? 0.0 : 1.0, h->gemm_work, h->gemm_work_elems};
+        NGD_TRY(launch_gemm(g1, s));
+      }
+    }
     const int64_t kmax = std::min<int64_t>(i * b, ell_max);
     if (kmax > 0) {
       NGD_TRY(launch_rp_gather_f(Ft, ldF, h->rp_idx, b, kmax, h->rp_W, kmax, s));

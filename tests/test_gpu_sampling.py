@@ -217,6 +217,51 @@ def test_rpcholesky_matches_oracle(name, ell_max, block, frac):
     gp.close()
 
 
+@pytest.mark.parametrize("cfg", ["small", "c2"])
+def test_rpcholesky_recompute_mode_matches_stored(cfg):
+    """Block RPCholesky with J_w recomputed from theta a block of rows at a time (two blocks at the
+    benchmark's 2D size) against the same call on the stored J_w: the same rank and trace, F to rounding."""
+    if cfg == "small":
+        prob, th = make(CASES["poisson2d_f64"]())
+    else:
+        prob = wl.config("c2")
+        th = wl.glorot_theta(prob.widths, 0)
+    print("rpcholesky recompute mode,", cfg, flush=True)
+    ell_max = 60
+    gp = Problem(prob, dtype=prob.dtype, max_ell=ell_max + 1)
+    theta = gp.theta(th)
+    J = gp.new_jacobian()
+    gp.residual_jacobian(theta, J)
+    d = gp.gramian_diagonal(J)
+    Ft, r, tr = gp.rpcholesky(J, d, ell_max, 20, seed=5, counter=2, eps=0.0)
+    Ft2, r2, tr2 = gp.rpcholesky(Recompute(theta), d, ell_max, 20, seed=5, counter=2, eps=0.0)
+    assert r2 == r and abs(tr2 - tr) <= 1e-9 * float(d.sum())
+    F, F2 = Ft.cpu().numpy()[:r, :gp.P], Ft2.cpu().numpy()[:r, :gp.P]
+    tol = 1e-9 if prob.dtype == "f64" else 1e-6
+    assert np.abs(F2 - F).max() <= tol * np.abs(F).max()
+    gp.close()
+
+
+def test_rpchol_ngd_steps_recompute_mode():
+    """RPCholNGD with J_w never stored follows the stored-J_w steps (same pivots and ranks, losses to the
+    solves' tolerance)."""
+    prob = wl.poisson_random(d=3, widths=(3, 24, 24, 1), n_interior=400, n_boundary=80, seed=6, dtype="f64",
+                             ell=40, sketch_dtype="f64")
+    th0 = wl.glorot_theta(prob.widths, 6)
+    a = NGD(prob, th0, solver="rpchol", seed=6, ell_max=60, maxit=20)
+    b = NGD(prob, th0, solver="rpchol", seed=6, ell_max=60, maxit=20, recompute=True)
+    L0 = None
+    for _ in range(5):
+        ra, rb = a.step(), b.step()
+        L0 = ra.loss if L0 is None else L0
+        assert rb.rank == ra.rank
+        # the solves stop at rtol 1e-6 on either path, so the trajectories agree to about that
+        assert abs(rb.loss_new - ra.loss_new) <= 1e-6 * ra.loss
+    assert rb.loss_new < 0.5 * L0
+    a.gp.close()
+    b.gp.close()
+
+
 @pytest.mark.parametrize("name", ["poisson2d_f64", "poisson2d_f32"])
 def test_rpchol_preconditioner_and_solve(name):
     """(U, lam_hat) reproduce F F^T with a trailing zero pair, and PCG with it solves (G + mu I) d = g
@@ -341,8 +386,6 @@ def test_rpcholesky_and_sampling_reject_bad_arguments():
         args.update(kw)
         with pytest.raises(Exception):
             gp.rpcholesky(J, d, args["ell_max"], args["block"], eps=args["eps"])
-    with pytest.raises(Exception):  # the recompute mode has no stored J_w
-        gp.rpcholesky(Recompute(theta), d, 10, 5)
     with pytest.raises(Exception):
         gp.sample_pivots(d, 4097)
     with pytest.raises(Exception):
