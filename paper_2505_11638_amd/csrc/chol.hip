@@ -41,52 +41,70 @@ __global__ __launch_bounds__(64 * kTqWaves) void trsm_q_kernel(const double* __r
   tq_d4 X[MAXS];
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) X[s] = tq_d4{0.0, 0.0, 0.0, 0.0};
-  for (int J = 0; J < ntile; ++J) {
-    const int j0 = 16 * J, par = J & 1, owner = J % kTqWaves;
-    const bool own = wid == owner;
-    // loads first (all in flight together): the owner's L_JJ entries and Z_J, every wave's blocks
-    // of the rows of L it multiplies (tiles t < J with t % kTqWaves == wid)
-    double ldv[4], rdv = 0.0, zv[4];
-    if (own) {
+  // the loads of panel J: the owner's L_JJ entries and Z_J, every wave's blocks of the rows of L it
+  // multiplies (tiles t < J with t % kTqWaves == wid). Panel J + 1's are issued as soon as panel J's
+  // products have consumed theirs, so that their latency overlaps panel J's exchange and substitution:
+  // the addresses are clamped into the matrices instead of branching around the edge entries, and the
+  // raw values are masked and converted only where they are used.
+  double ldv[4], rdv = 0.0, a[MAXS][4];
+  TZ zr[4];
+  auto load_panel = [&](int J) {
+    const int j0 = 16 * J;
+    if (wid == J % kTqWaves) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int e = lane + 64 * u, ra = e >> 4, cb = e & 15;
-        ldv[u] = (j0 + ra < ell && cb <= ra) ? L[(int64_t)(j0 + ra) * ell + j0 + cb] : 0.0;
+        const int e = lane + 64 * u;
+        ldv[u] = L[(int64_t)min(j0 + (e >> 4), ell - 1) * ell + min(j0 + (e & 15), ell - 1)];
       }
-      if (lane < 16 && j0 + lane < ell) rdv = L[(int64_t)(j0 + lane) * ell + j0 + lane];
+      const int k = min(j0 + lr, ell - 1);
+      rdv = L[(int64_t)k * ell + k];
+      const int64_t zrow = row < N ? row : N - 1;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int c = j0 + 4 * lq + r;
-        zv[r] = (row < N && c < ell) ? (double)Z[row * ell + c] : 0.0;
-      }
+      for (int r = 0; r < 4; ++r) zr[r] = Z[zrow * ell + min(j0 + 4 * lq + r, ell - 1)];
     }
-    const bool lrow = j0 + lr < ell;
-    const double* Lrow = L + (int64_t)(j0 + lr) * ell + 4 * lq;
-    double a[MAXS][4];
+    const double* Lrow = L + (int64_t)min(j0 + lr, ell - 1) * ell + 4 * lq;
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const int t = wid + kTqWaves * s;
       if (t < J) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[s][r] = lrow ? Lrow[16 * t + r] : 0.0;
+        for (int r = 0; r < 4; ++r) a[s][r] = Lrow[16 * t + r];
       }
     }
+  };
+  load_panel(0);
+  for (int J = 0; J < ntile; ++J) {
+    const int j0 = 16 * J, par = J & 1, owner = J % kTqWaves;
+    const bool own = wid == owner;
+    // rows of L past ell (the last panel's) take no part in the products
+    const bool lrow = j0 + lr < ell;
     tq_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const int t = wid + kTqWaves * s;
       if (t < J) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][r], X[s][r], acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lrow ? a[s][r] : 0.0, X[s][r], acc, 0, 0, 0);
       }
     }
+    double ldc[4], zc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = lane + 64 * u, ra = e >> 4, cb = e & 15;
+      ldc[u] = (j0 + ra < ell && cb <= ra) ? ldv[u] : 0.0;
+    }
+    const double rdc = (lane < 16 && j0 + lane < ell) ? rdv : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) zc[r] = (row < N && j0 + 4 * lq + r < ell) ? (double)zr[r] : 0.0;
+    if (J + 1 < ntile) load_panel(J + 1);
     if (own) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = lane + 64 * u;
-        Ld[par][e >> 4][e & 15] = ldv[u];
+        Ld[par][e >> 4][e & 15] = ldc[u];
       }
-      if (lane < 16) Rd[par][lane] = rdv != 0.0 ? 1.0 / rdv : 0.0;
+      if (lane < 16) Rd[par][lane] = rdc != 0.0 ? 1.0 / rdc : 0.0;
     }
     // accumulator element r: S^T(lq + 4 r, lr) = S(row lr, column j0 + lq + 4 r)
 #pragma unroll
@@ -101,7 +119,7 @@ __global__ __launch_bounds__(64 * kTqWaves) void trsm_q_kernel(const double* __r
         double sv = 0.0;
 #pragma unroll
         for (int w = 0; w < kTqWaves; ++w) sv += Sp[par][w][c * 16 + lr];
-        b[r] = zv[r] - sv;
+        b[r] = zc[r] - sv;
       }
       // forward substitution over the 16 columns: x_c = b_c / L_cc, then b_c' -= x_c L_c'c
 #pragma unroll
@@ -154,6 +172,7 @@ ngd_status run_trsm_q(const double* L, int ell, const void* Z, int64_t N, double
   else if (s4 <= 6) NGD_TQ(6, 4);
   else if (s4 <= 8) NGD_TQ(8, 4);
   else if (s8 <= 6) NGD_TQ(6, 8);
+  else if (s8 <= 7) NGD_TQ(7, 8);
   else if (s8 <= 8) NGD_TQ(8, 8);
   else {
     set_error("trsm: ell above 1024");

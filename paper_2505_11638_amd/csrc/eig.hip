@@ -7,9 +7,10 @@
 //     in registers; each step applies the previous step's rank-2 update lazily while forming
 //     p = tau A v.
 //  2. Eigenvalues of T by multisection on Sturm counts (one wave per eigenvalue).
-//  3. Eigenvectors of T by inverse iteration with partial-pivoting LU of T - lambda I (one thread
-//     per eigenvector), modified Gram-Schmidt inside clusters of (nearly) equal eigenvalues, and two
-//     Newton-Schulz steps that restore orthonormality to working precision.
+//  3. Eigenvectors of T by inverse iteration with partial-pivoting LU of T - lambda I (one wave
+//     per eigenvector, the factors in its registers), modified Gram-Schmidt inside clusters of
+//     (nearly) equal eigenvalues, and two Newton-Schulz steps that restore orthonormality to
+//     working precision.
 //  4. Back-transformation V = Q Z. Q = H_0 H_1 ... H_{n-3} is formed explicitly from the compact
 //     WY blocks on the FP64 matrix cores (one workgroup per 16 columns) as soon as step 1 is done,
 //     on a second stream where one is given, so that it runs beside steps 2 and 3; V is then a
@@ -421,159 +422,165 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
 }
 
 // inverse iteration for eigenvalue i: solve (T - lam I) x = b by LU with partial pivoting
-// (tridiagonal; the U factor has two superdiagonals), two sweeps. One thread per eigenvalue, 64
-// eigenvalues per wave: the factors live in a global workspace laid out [array][j][i] (consecutive
-// eigenvalues adjacent, so every access is coalesced), and the sequential recurrences read them in
-// chunks of 32 that are loaded before they are used. Quotients are a hardware reciprocal refined
-// by one Newton step.
-constexpr int kInvChunk = 32;
+// (tridiagonal; the U factor has two superdiagonals), two sweeps. One wave per eigenvalue: the
+// recurrences run on wave-uniform values, and T's diagonals and the LU factors stay in registers
+// spread over the lanes (entry j in register j / 64 of lane j % 64), so a step reads its operands
+// with readlane and writes its results into lane j % 64 with a select; nothing goes through
+// memory. T's inputs are held shifted by one entry as well (d_{j+1}, e_{j+1}) since step j needs
+// them. kInvWaves eigenvalues per workgroup; their eigenvectors leave through LDS so that each row
+// of Z is written in one run. Quotients are a hardware reciprocal refined by one Newton step.
+constexpr int kInvWaves = 4;
+// register shapes ceil(n / 64) of the inverse iteration (n <= 1024)
+#define NGD_INVIT_SHAPES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// x[j / 64] at lane j % 64 <- v (j wave-uniform, possibly a run-time value)
+__device__ __forceinline__ float read_lane_f(float t, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), l));
+}
+
+#define NGD_SET_ENTRY(x, QN, j, v)                                   \
+  do {                                                               \
+    const int qs_ = (j) >> 6, ls_ = (j) & 63;                        \
+    _Pragma("unroll") for (int u_ = 0; u_ < (QN); ++u_)              \
+      if (u_ == qs_) (x)[u_] = lane == ls_ ? (v) : (x)[u_];          \
+  } while (0)
+
+template <int QN>
 __device__ __forceinline__ void invit_body(const double* __restrict__ d, const double* __restrict__ e, int n,
                                            const double* __restrict__ lam_asc, const double* __restrict__ tnorm,
-                                           double drop_rel, double* __restrict__ ML, double* __restrict__ SW,
-                                           double* __restrict__ U1, double* __restrict__ U2, double* __restrict__ RI,
-                                           double* __restrict__ Y, double* __restrict__ Z, const int bid) {
-  const int i = bid * 64 + threadIdx.x;
-  if (i >= n) return;
-  const double lam = lam_asc[i];
-  const double drop = drop_rel * (*tnorm);
-  if (lam < drop) {
-    for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = 0.0;
-    return;
-  }
-  const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
-  const double inv_tiny = recip(tiny);
-  auto at = [&](int j) { return (int64_t)j * n + i; };
-  // factorisation of T - lam I fused with the first forward sweep (start vector: deterministic
-  // pseudo-random entries in [0.5, 1.5))
-  unsigned h = 2166136261u ^ ((unsigned)i * 16777619u);
-  h = (h ^ 0u) * 16777619u + 0x9E3779B9u;
-  double carry = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
-  double a = d[0] - lam, b = n > 1 ? e[0] : 0.0;
-  for (int j0 = 0; j0 < n - 1; j0 += kInvChunk) {
-    double cj[kInvChunk], dj[kInvChunk], ej[kInvChunk];
+                                           double drop_rel, double* __restrict__ Z, const int bid) {
+  __shared__ double zs[64 * QN][kInvWaves];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int i = bid * kInvWaves + w;
+  double yr[QN];
 #pragma unroll
-    for (int u = 0; u < kInvChunk; ++u) {
-      const int j = min(j0 + u, n - 2);
-      cj[u] = e[j];
-      dj[u] = d[j + 1];
-      ej[u] = j + 1 < n - 1 ? e[j + 1] : 0.0;
+  for (int q = 0; q < QN; ++q) yr[q] = 0.0;
+  if (i < n && lam_asc[i] >= drop_rel * (*tnorm)) {
+    const double lam = lam_asc[i];
+    const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
+    const double inv_tiny = recip(tiny);
+    // e_j, d_{j+1}, e_{j+1} (zero past the ends), the factors: multiplier, first superdiagonal of U,
+    // 1 / pivot, interchange flag (the second superdiagonal is e_{j+1} where rows were swapped)
+    double er[QN], ds[QN], es[QN], ml[QN], u1[QN], ri[QN];
+    float sw[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      const int j = 64 * q + lane;
+      er[q] = j < n - 1 ? e[j] : 0.0;
+      ds[q] = j + 1 < n ? d[j + 1] : 0.0;
+      es[q] = j + 1 < n - 1 ? e[j + 1] : 0.0;
+      ml[q] = u1[q] = ri[q] = 0.0;
+      sw[q] = 0.f;
     }
+    // factorisation of T - lam I fused with the first forward sweep (start vector: deterministic
+    // pseudo-random entries in [0.5, 1.5))
+    unsigned h = 2166136261u ^ ((unsigned)i * 16777619u);
+    h = (h ^ 0u) * 16777619u + 0x9E3779B9u;
+    double carry = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
+    double a = d[0] - lam, b = n > 1 ? e[0] : 0.0;
 #pragma unroll
-    for (int u = 0; u < kInvChunk; ++u) {
-      const int j = j0 + u;
-      if (j < n - 1) {
-        const double c = cj[u], dn = dj[u] - lam, en = ej[u];
+    for (int q = 0; q < QN; ++q) {
+      const int lend = min(64, n - 1 - 64 * q);
+      for (int l = 0; l < lend; ++l) {
+        const int j = 64 * q + l;
+        const bool me = lane == l;
+        const double c = read_lane(er[q], l), dn = read_lane(ds[q], l) - lam, en = read_lane(es[q], l);
         h = (h ^ (unsigned)(j + 1)) * 16777619u + 0x9E3779B9u;
         const double nxt = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);
-        // partial pivoting between rows j (a, b) and j + 1 (c, dn, en), without branches (the lanes
-        // of a wave pivot differently) and with one reciprocal: the pivot's serves the multiplier
-        // and, unless the pivot is below `tiny` (then replaced by +-tiny), the stored 1/pivot
-        const bool sw = !(fabs(a) >= fabs(c));
-        const double piv = sw ? c : a, oth = sw ? a : c;
+        // partial pivoting between rows j (a, b) and j + 1 (c, dn, en) with one reciprocal: the
+        // pivot's serves the multiplier and, unless the pivot is below `tiny` (then replaced by
+        // +-tiny), the stored 1/pivot
+        const bool swp = !(fabs(a) >= fabs(c));
+        const double piv = swp ? c : a, oth = swp ? a : c;
         const double rp = recip(piv);
         const double m = piv != 0.0 ? oth * rp : 0.0;
-        U1[at(j)] = sw ? dn : b;
-        U2[at(j)] = sw ? en : 0.0;
-        SW[at(j)] = sw ? 1.0 : 0.0;
-        const double an = (sw ? b : dn) - m * (sw ? dn : b);
-        b = sw ? -m * en : en;
+        u1[q] = me ? (swp ? dn : b) : u1[q];
+        sw[q] = me ? (swp ? 1.f : 0.f) : sw[q];
+        const double an = (swp ? b : dn) - m * (swp ? dn : b);
+        b = swp ? -m * en : en;
         a = an;
-        const double x0 = sw ? nxt : carry, x1 = sw ? carry : nxt;
-        ML[at(j)] = m;
-        RI[at(j)] = fabs(piv) < tiny ? (piv < 0.0 ? -inv_tiny : inv_tiny) : rp;
-        Y[at(j)] = x0;
+        const double x0 = swp ? nxt : carry, x1 = swp ? carry : nxt;
+        ml[q] = me ? m : ml[q];
+        ri[q] = me ? (fabs(piv) < tiny ? (piv < 0.0 ? -inv_tiny : inv_tiny) : rp) : ri[q];
+        yr[q] = me ? x0 : yr[q];
         carry = x1 - m * x0;
       }
     }
-  }
-  if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-  RI[at(n - 1)] = recip(a);
-  U1[at(n - 1)] = 0.0;
-  U2[at(n - 1)] = 0.0;
-  Y[at(n - 1)] = carry;
-  double scale = 1.0, ss = 0.0;
-  for (int it = 0; it < 2; ++it) {
-    if (it == 1) {
-      // forward sweep with the stored interchanges and multipliers on the scaled previous solution
-      carry = Y[at(0)] * scale;
-      for (int j0 = 0; j0 < n - 1; j0 += kInvChunk) {
-        double ml[kInvChunk], sw[kInvChunk], yn[kInvChunk];
+    if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+    NGD_SET_ENTRY(ri, QN, n - 1, recip(a));
+    NGD_SET_ENTRY(u1, QN, n - 1, 0.0);
+    NGD_SET_ENTRY(sw, QN, n - 1, 0.f);
+    NGD_SET_ENTRY(yr, QN, n - 1, carry);
+    double scale = 1.0, ss = 0.0;
+    for (int it = 0; it < 2; ++it) {
+      if (it == 1) {
+        // forward sweep with the stored interchanges and multipliers on the scaled previous solution
+        carry = read_lane(yr[0], 0) * scale;
 #pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) {
-          const int j = min(j0 + u, n - 2);
-          ml[u] = ML[at(j)];
-          sw[u] = SW[at(j)];
-          yn[u] = Y[at(j + 1)];
-        }
-#pragma unroll
-        for (int u = 0; u < kInvChunk; ++u) {
-          const int j = j0 + u;
-          if (j < n - 1) {
-            const double nxt = yn[u] * scale;
-            const bool swp = sw[u] != 0.0;
+        for (int q = 0; q < QN; ++q) {
+          const int lend = min(64, n - 1 - 64 * q);
+          for (int l = 0; l < lend; ++l) {
+            const int l1 = (l + 1) & 63;
+            // y_{j+1}: lane j + 1 of the same register, or lane 0 of the next (the last register
+            // never holds step 63, since its steps end before n - 1)
+            const double ya = read_lane(yr[q], l1), yb = read_lane(yr[q + 1 < QN ? q + 1 : q], l1);
+            const double nxt = (l < 63 ? ya : yb) * scale;
+            const bool swp = read_lane_f(sw[q], l) != 0.f;
             const double x0 = swp ? nxt : carry, x1 = swp ? carry : nxt;
-            Y[at(j)] = x0;
-            carry = x1 - ml[u] * x0;
+            yr[q] = lane == l ? x0 : yr[q];
+            carry = x1 - read_lane(ml[q], l) * x0;
           }
         }
+        NGD_SET_ENTRY(yr, QN, n - 1, carry);
       }
-      Y[at(n - 1)] = carry;
-    }
-    // backward substitution with U, in place on y; the max-norm for scaling (and, on the last sweep,
-    // the sum of squares for the final normalisation)
-    double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-    ss = 0.0;
-    for (int j0 = n - 1; j0 >= 0; j0 -= kInvChunk) {
-      double yv[kInvChunk], u1[kInvChunk], u2[kInvChunk], ri[kInvChunk];
+      // backward substitution with U, in place on y; the max-norm for scaling (and, on the last
+      // sweep, the sum of squares for the final normalisation)
+      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+      ss = 0.0;
 #pragma unroll
-      for (int u = 0; u < kInvChunk; ++u) {
-        const int j = max(j0 - u, 0);
-        yv[u] = Y[at(j)];
-        u1[u] = U1[at(j)];
-        u2[u] = U2[at(j)];
-        ri[u] = RI[at(j)];
-      }
-#pragma unroll
-      for (int u = 0; u < kInvChunk; ++u) {
-        const int j = j0 - u;
-        if (j >= 0) {
-          const double x = (yv[u] - u1[u] * x1 - u2[u] * x2) * ri[u];
-          Y[at(j)] = x;
+      for (int q = QN - 1; q >= 0; --q) {
+        for (int l = min(63, n - 1 - 64 * q); l >= 0; --l) {
+          const double u2 = read_lane_f(sw[q], l) != 0.f ? read_lane(es[q], l) : 0.0;
+          const double x = (read_lane(yr[q], l) - read_lane(u1[q], l) * x1 - u2 * x2) * read_lane(ri[q], l);
+          yr[q] = lane == l ? x : yr[q];
           x2 = x1;
           x1 = x;
           nrm = fmax(nrm, fabs(x));
           ss += x * x;
         }
       }
+      scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
     }
-    scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    // unit 2-norm: ss is the sum of squares of the unscaled last solution
+    const double s2 = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+#pragma unroll
+    for (int q = 0; q < QN; ++q) yr[q] *= s2;
   }
-  // unit 2-norm: ss is the sum of squares of the unscaled last solution
-  const double s2 = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
-  for (int j0 = 0; j0 < n; j0 += kInvChunk) {
-    double yv[kInvChunk];
 #pragma unroll
-    for (int u = 0; u < kInvChunk; ++u) yv[u] = Y[at(min(j0 + u, n - 1))];
-#pragma unroll
-    for (int u = 0; u < kInvChunk; ++u)
-      if (j0 + u < n) Z[at(j0 + u)] = yv[u] * s2;
+  for (int q = 0; q < QN; ++q)
+    if (64 * q + lane < n) zs[64 * q + lane][w] = yr[q];
+  __syncthreads();
+  const int i0 = bid * kInvWaves, ni = min(kInvWaves, n - i0);
+  for (int t = threadIdx.x; t < n * kInvWaves; t += blockDim.x) {
+    const int j = t / kInvWaves, c = t % kInvWaves;
+    if (c < ni) Z[(int64_t)j * n + i0 + c] = zs[j][c];
   }
 }
+#undef NGD_SET_ENTRY
 
-__global__ __launch_bounds__(64) void invit_kernel(const double* __restrict__ d, const double* __restrict__ e, int n,
-                                                    const double* __restrict__ lam_asc,
-                                                    const double* __restrict__ tnorm, double drop_rel,
-                                                    double* __restrict__ ML, double* __restrict__ SW,
-                                                    double* __restrict__ U1, double* __restrict__ U2,
-                                                    double* __restrict__ RI, double* __restrict__ Y,
-                                                    double* __restrict__ Z) {
-  invit_body(d, e, n, lam_asc, tnorm, drop_rel, ML, SW, U1, U2, RI, Y, Z, (int)blockIdx.x);
+template <int QN>
+__global__ __launch_bounds__(64 * kInvWaves) void invit_kernel(const double* __restrict__ d,
+                                                               const double* __restrict__ e, int n,
+                                                               const double* __restrict__ lam_asc,
+                                                               const double* __restrict__ tnorm, double drop_rel,
+                                                               double* __restrict__ Z) {
+  invit_body<QN>(d, e, n, lam_asc, tnorm, drop_rel, Z, (int)blockIdx.x);
 }
 
 // modified Gram-Schmidt within each cluster of close eigenvalues (one workgroup per cluster start)
@@ -623,7 +630,7 @@ struct MidItem {
   double* lam;
   double* tnorm;
   double drop_rel;
-  double *ML, *SW, *U1, *U2, *RI, *Y, *Z;
+  double* Z;
 };
 struct MidBatch {
   MidItem it[kMidBatchMax];
@@ -640,11 +647,11 @@ __global__ __launch_bounds__(256) void bisect_batch_kernel(MidBatch b) {
   const MidItem& q = b.it[m];
   bisect_body(q.d, q.e, q.n, q.wpe, q.e2, q.lam, q.tnorm, (int)blockIdx.x - b.first[m]);
 }
-__global__ __launch_bounds__(64) void invit_batch_kernel(MidBatch b) {
+template <int QN>
+__global__ __launch_bounds__(64 * kInvWaves) void invit_batch_kernel(MidBatch b) {
   const int m = mid_member(b);
   const MidItem& q = b.it[m];
-  invit_body(q.d, q.e, q.n, q.lam, q.tnorm, q.drop_rel, q.ML, q.SW, q.U1, q.U2, q.RI, q.Y, q.Z,
-             (int)blockIdx.x - b.first[m]);
+  invit_body<QN>(q.d, q.e, q.n, q.lam, q.tnorm, q.drop_rel, q.Z, (int)blockIdx.x - b.first[m]);
 }
 __global__ __launch_bounds__(256) void cluster_mgs_batch_kernel(MidBatch b) {
   const int m = mid_member(b);
@@ -1086,11 +1093,7 @@ ngd_status eig_mid_item(int n, double drop_rel, void* work, MidItem* q) {
   int dev = 0, cus = 0;
   NGD_HIP_TRY(hipGetDevice(&dev));
   NGD_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  // the factors of inverse iteration: five n x n arrays in wk, the interchanges in A1 (both free
-  // after the tridiagonalisation)
-  const size_t nn = (size_t)n * n;
-  *q = MidItem{ws.dvec, ws.evec, n, 2 * n <= 4 * cus ? 2 : 1, ws.e2, ws.lam, ws.tnorm, drop_rel,
-               ws.wk, ws.A1, ws.wk + nn, ws.wk + 2 * nn, ws.wk + 3 * nn, ws.wk + 4 * nn, ws.Z};
+  *q = MidItem{ws.dvec, ws.evec, n, 2 * n <= 4 * cus ? 2 : 1, ws.e2, ws.lam, ws.tnorm, drop_rel, ws.Z};
   return NGD_OK;
 }
 
@@ -1147,8 +1150,11 @@ ngd_status launch_sym_eig_finish(int n, double drop_rel, double* evals_desc, dou
   const int per_block = 4 / q.wpe;
   hipLaunchKernelGGL(bisect_kernel, dim3((n + per_block - 1) / per_block), dim3(256), 2 * sizeof(double) * n, s, q.d,
                      q.e, n, q.wpe, q.e2, q.lam, q.tnorm);
-  hipLaunchKernelGGL(invit_kernel, dim3((n + 63) / 64), dim3(64), 0, s, q.d, q.e, n, q.lam, q.tnorm, drop_rel, q.ML,
-                     q.SW, q.U1, q.U2, q.RI, q.Y, q.Z);
+  const dim3 inv_grid((n + kInvWaves - 1) / kInvWaves), inv_block(64 * kInvWaves);
+#define NGD_INVIT(QN) \
+  case QN: hipLaunchKernelGGL(invit_kernel<QN>, inv_grid, inv_block, 0, s, q.d, q.e, n, q.lam, q.tnorm, drop_rel, q.Z); break;
+  switch ((n + 63) / 64) { NGD_INVIT_SHAPES(NGD_INVIT) }
+#undef NGD_INVIT
   NGD_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(cluster_mgs_kernel, dim3(n), dim3(256), 0, s, q.lam, n, q.tnorm, drop_rel, q.Z);
   NGD_HIP_TRY(hipGetLastError());
@@ -1184,7 +1190,13 @@ ngd_status launch_sym_eig_middle_batch(const EigJob* jobs, int n, hipStream_t s)
     size_t lds = 0;
     for (int k = 0; k < b.n; ++k) lds = std::max(lds, 2 * sizeof(double) * b.it[k].n);
     NGD_TRY(launch(bisect_batch_kernel, [](const MidItem& q) { return (q.n + 4 / q.wpe - 1) / (4 / q.wpe); }, 256, lds));
-    NGD_TRY(launch(invit_batch_kernel, [](const MidItem& q) { return (q.n + 63) / 64; }, 64, 0));
+    int qn = 1;
+    for (int k = 0; k < b.n; ++k) qn = std::max(qn, (b.it[k].n + 63) / 64);
+    const auto inv_blocks = [](const MidItem& q) { return (q.n + kInvWaves - 1) / kInvWaves; };
+#define NGD_INVIT(QN) \
+  case QN: NGD_TRY(launch(invit_batch_kernel<QN>, inv_blocks, 64 * kInvWaves, 0)); break;
+    switch (qn) { NGD_INVIT_SHAPES(NGD_INVIT) }
+#undef NGD_INVIT
     NGD_TRY(launch(cluster_mgs_batch_kernel, [](const MidItem& q) { return q.n; }, 256, 0));
   }
   return NGD_OK;
