@@ -242,10 +242,28 @@ __global__ __launch_bounds__(64 * W) void chol_rows_kernel(double* __restrict__ 
         zv[r] = (row < n && c < n && c <= row) ? M[(int64_t)row * n + c] : 0.0;
       }
     }
-    if (!diag && lane == 0) wait_flag(flags + J, epoch, err);  // L_J,<J is final
+    // when row block J is complete already (flag B, set after flag A), one look at that flag
+    // replaces both waits and every load of this step is issued together; otherwise wait for flag A
+    // now (the products with L_J,<J overlap the factorisation of L_JJ) and for flag B below
+    bool ready = false;
+    if (!diag) {
+      unsigned fb = 0;
+      if (lane == 0) fb = __hip_atomic_load(flags + kCholFlagsB + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ready = __builtin_amdgcn_readfirstlane(fb) == epoch;
+      if (!ready && lane == 0) wait_flag(flags + J, epoch, err);  // L_J,<J is final
+    }
     // this wave's share of S^T = L_J,<J L_R,<J^T over the tiles t < J held here (t % W == wid); the
     // rows of L_J come from workgroup J, or are this workgroup's own tiles when J == R
     // (all loads issued before the first product, so that their latencies overlap)
+    auto load_ljj = [&] {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u, ra = e >> 4, cb = e & 15;
+        ldv[u] = (j0 + ra < n && cb <= ra) ? ld_co(M + (int64_t)(j0 + ra) * n + j0 + cb) : 0.0;
+      }
+      if (lane < 16 && j0 + lane < n) rdv = ld_co(M + (int64_t)(j0 + lane) * n + j0 + lane);
+    };
+    if (own && !diag && ready) load_ljj();
     tq_d4 acc = {0.0, 0.0, 0.0, 0.0};
     const bool lrow = j0 + lr < n;
     double* Lrow = M + (int64_t)(j0 + lr) * n + 4 * lq;
@@ -272,13 +290,10 @@ __global__ __launch_bounds__(64 * W) void chol_rows_kernel(double* __restrict__ 
       }
     }
     if (own && !diag) {
-      if (lane == 0) wait_flag(flags + kCholFlagsB + J, epoch, err);  // L_JJ is final
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = lane + 64 * u, ra = e >> 4, cb = e & 15;
-        ldv[u] = (j0 + ra < n && cb <= ra) ? ld_co(M + (int64_t)(j0 + ra) * n + j0 + cb) : 0.0;
+      if (!ready) {
+        if (lane == 0) wait_flag(flags + kCholFlagsB + J, epoch, err);  // L_JJ is final
+        load_ljj();
       }
-      if (lane < 16 && j0 + lane < n) rdv = ld_co(M + (int64_t)(j0 + lane) * n + j0 + lane);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = lane + 64 * u;
