@@ -19,8 +19,9 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 from oracle import nystrom  # noqa: E402
 from paper_2505_11638_amd.api import Problem  # noqa: E402
 
-# one sketch size per register shape of the core kernels (ceil(ell / 64) = 1, 2, ..., 16), ragged
-ELLS = [37, 100, 150, 250, 300, 380, 420, 500, 560, 620, 690, 750, 800, 880, 940, 1024]
+# one sketch size per register shape of the core kernels (ceil(ell / 64) = 1, 2, ..., 16), ragged, and
+# two where the last step of the tridiagonal recurrences sits at lane 63 of a register (ell - 1 = 64 k)
+ELLS = [37, 65, 100, 129, 150, 250, 300, 380, 420, 500, 560, 620, 690, 750, 800, 880, 940, 1024]
 
 
 @pytest.fixture(scope="module")
