@@ -872,9 +872,90 @@ __global__ void eig_finalize_kernel(const double* __restrict__ Xt, const double*
   if (row < n) evec_rows[(int64_t)(n - 1 - col) * n + row] = keep ? Xt[(int64_t)col * n + row] : 0.0;
 }
 
+// The n x n FP64 products of the last stage (two Newton-Schulz steps and (Q Z)^T):
+// D = alpha op(A) op(B) + beta C, with op(A)(i, k) = A[k n + i] when AT (else A[i n + k]) and
+// op(B)(k, j) = B[j n + k] when BT (else B[k n + j]); all row-major with ld n, C may be null when beta
+// is 0. A 256-thread workgroup forms a 32 x 32 tile of D, each wave 16 x 16 of it over the whole of K
+// (at these sizes a split of K and its reduction cost more in latency than they save), from L2.
+// K is taken 16 at a time, in four MFMA steps whose K index for lane group q = l / 16 is 16 c + 4 q + s
+// (a fixed permutation of K): an operand whose K direction is contiguous in memory then comes as four
+// consecutive doubles per lane (whole cache lines per load instruction), the other as four loads of 16
+// consecutive doubles per lane group. kSdChunks chunks are in flight; two accumulators in turn.
+// Rows, columns and K past n are read clamped (or up to 3 doubles past a row's end, which stays within
+// the workspace: it ends in a pad) and never stored or masked, so that the loop has no branch.
+constexpr int kSdChunks = 4;
+
+// (at most two waves per SIMD: the grid is small, and the registers hold the loads in flight)
+template <bool AT, bool BT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void small_dgemm_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                                                          const double* __restrict__ C, double* __restrict__ D,
+                                                          int n, double alpha, double beta) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int i0 = blockIdx.y * 32 + (wid >> 1) * 16, j0 = blockIdx.x * 32 + (wid & 1) * 16;
+  const int ia = min(i0 + lr, n - 1), jb = min(j0 + lr, n - 1);
+  const int chunks = (n + 15) / 16;
+  double av[kSdChunks][4], bv[kSdChunks][4];
+  auto load = [&](int c, double (&a)[4], double (&b)[4]) {
+    const int k = 16 * c + 4 * lq;
+    if (AT) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = A[(int64_t)min(k + t, n - 1) * n + ia];
+    } else {
+      const double* p = A + (int64_t)ia * n + min(k, n - 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = p[t];
+    }
+    if (BT) {
+      const double* p = B + (int64_t)jb * n + min(k, n - 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t] = p[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t] = B[(int64_t)min(k + t, n - 1) * n + jb];
+    }
+  };
+#pragma unroll
+  for (int u = 0; u < kSdChunks; ++u) load(u, av[u], bv[u]);
+  bt_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < chunks; c0 += kSdChunks) {
+#pragma unroll
+    for (int u = 0; u < kSdChunks; ++u) {
+      const int k = 16 * (c0 + u) + 4 * lq;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double a = k + t < n ? av[u][t] : 0.0;  // K past n adds nothing
+        if (t & 1) acc1 = mfma64(a, bv[u][t], acc1);
+        else acc0 = mfma64(a, bv[u][t], acc0);
+      }
+      load(c0 + u + kSdChunks, av[u], bv[u]);
+      __builtin_amdgcn_sched_barrier(0);  // the loads stay here, a whole ring of chunks ahead of their use
+    }
+  }
+  const int j = j0 + lr;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + lq + 4 * r;
+    if (i < n && j < n) {
+      const double v = alpha * (acc0[r] + acc1[r]);
+      D[(int64_t)i * n + j] = beta != 0.0 ? v + beta * C[(int64_t)i * n + j] : v;
+    }
+  }
+}
+
+template <bool AT, bool BT>
+ngd_status small_dgemm(const double* A, const double* B, const double* C, double* D, int n, double alpha,
+                       double beta, hipStream_t s) {
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL((small_dgemm_kernel<AT, BT>), dim3(t, t), dim3(256), 0, s, A, B, C, D, n, alpha, beta);
+  NGD_HIP_TRY(hipGetLastError());
+  return NGD_OK;
+}
+
 // Workspace layout (doubles unless noted): A1, V, Z (n^2 each), wk (5 n^2), d, e, tau, e2, lam
 // (n each), tnorm (8), the barrier flags (256 unsigned) and the error word (in a 1 KiB slot), the
-// T factors of the reflector blocks, then Qm (n^2, the explicit product of the reflectors).
+// T factors of the reflector blocks, then Qm (n^2, the explicit product of the reflectors) and a pad
+// of 8.
 struct EigWs {
   double *A1, *V, *Z, *wk, *dvec, *evec, *tau, *e2, *lam, *tnorm, *Tall, *Qm;
   unsigned* flags;
@@ -898,7 +979,7 @@ struct EigWs {
     Tall = tnorm + 8 + 128;  // the 1 KiB slot of the flags and the error word
     const size_t nblk = (size_t)n + 1;  // blocks of as few as one reflector
     Qm = Tall + nblk * kWy * kWy;
-    bytes = (size_t)((Qm + nn) - w) * sizeof(double);
+    bytes = (size_t)((Qm + nn + 8) - w) * sizeof(double);  // + a pad for the small products' row reads
   }
 };
 
@@ -1110,18 +1191,9 @@ ngd_status eig_rest(int n, double drop_rel, double* evals_desc, double* evec_row
   // inverse-iteration vectors (quadratic convergence; dropped columns stay zero)
   double* E = A1;   // free after the tridiagonalisation
   double* Z2 = wk;  // free after inverse iteration
-  double* nswork = wk + (size_t)n * n;  // split-K partials of the n x n products (4 n^2)
   for (int ns = 0; ns < 2; ++ns) {
-    GemmArgs e{n, n, n, Z, n, false, Z, n, false, E, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
-               nswork, 4 * (int64_t)n * n, 1};
-    ngd_status st = launch_gemm(e, s);
-    if (st != NGD_OK) return st;
-    st = launch_cast(NGD_F64, Z, NGD_F64, Z2, (int64_t)n * n, s);
-    if (st != NGD_OK) return st;
-    GemmArgs u{n, n, n, Z, n, true, E, n, false, Z2, n, NGD_F64, NGD_F64, NGD_F64, G_F64, -0.5, 1.5,
-               nswork, 4 * (int64_t)n * n};
-    st = launch_gemm(u, s);
-    if (st != NGD_OK) return st;
+    NGD_TRY((small_dgemm<true, false>(Z, Z, nullptr, E, n, 1.0, 0.0, s)));
+    NGD_TRY((small_dgemm<false, false>(Z, E, Z, Z2, n, -0.5, 1.5, s)));
     double* t = Z;
     Z = Z2;
     Z2 = t;
@@ -1129,9 +1201,7 @@ ngd_status eig_rest(int n, double drop_rel, double* evals_desc, double* evec_row
   // (Q Z)^T = Z^T Q^T once Q is there, then the eigenvector rows in descending order
   if (side != nullptr) NGD_HIP_TRY(hipStreamWaitEvent(s, join, 0));
   double* Xt = wk;  // free after the Newton-Schulz steps (Z is back in its own buffer)
-  GemmArgs q{n, n, n, Z, n, false, ws.Qm, n, true, Xt, n, NGD_F64, NGD_F64, NGD_F64, G_F64, 1.0, 0.0,
-             wk + (size_t)n * n, 4 * (int64_t)n * n};
-  NGD_TRY(launch_gemm(q, s));
+  NGD_TRY((small_dgemm<true, true>(Z, ws.Qm, nullptr, Xt, n, 1.0, 0.0, s)));
   hipLaunchKernelGGL(eig_finalize_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, Xt, lam, n, tnorm, drop_rel,
                      evals_desc, evec_rows);
   NGD_HIP_TRY(hipGetLastError());
