@@ -158,6 +158,23 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
       }
 }
 
+// sum over the ks slices (stride `count`) of element idx, added in slice order (deterministic), with
+// eight loads in flight
+template <typename T>
+__device__ __forceinline__ T sum_slices(const T* __restrict__ work, int ks, int64_t count, int64_t idx) {
+  T acc = 0;
+  int s = 0;
+  for (; s + 8 <= ks; s += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = work[(int64_t)(s + u) * count + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; s < ks; ++s) acc += work[(int64_t)s * count + idx];
+  return acc;
+}
+
 // C = alpha * sum_s work[s] + beta * C, slices summed in a fixed order (deterministic)
 template <typename TC>
 __global__ void splitk_reduce_kernel(const double* __restrict__ work, int ks, int64_t M, int64_t N, TC* __restrict__ C,
@@ -165,8 +182,7 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ work, int ks, in
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int64_t m = idx / N, n = idx - m * N;
-  double acc = 0.0;
-  for (int s = 0; s < ks; ++s) acc += work[(int64_t)s * M * N + idx];
+  const double acc = sum_slices(work, ks, M * N, idx);
   double v = alpha * acc;
   if (beta != 0.0) v += beta * (double)C[m * ldc + n];
   C[m * ldc + n] = (TC)v;
@@ -328,22 +344,25 @@ __global__ __launch_bounds__(NT) void dgemm_kernel(int64_t M, int64_t N, int64_t
       }
 }
 
-// split-K reduction of a symmetric product: tiles above the diagonal read their mirror (sym == 1)
-// or are skipped (sym == 2)
+// split-K reduction of a symmetric product: only the tiles on and below the diagonal are read (the
+// partials hold nothing else), each element summed once; with sym == 1 a thread also writes the
+// mirror of an element below the diagonal tiles, with sym == 2 the upper tiles are left untouched
 template <typename TC>
 __global__ void splitk_reduce_sym_kernel(const double* __restrict__ work, int ks, int64_t M, TC* __restrict__ C,
                                          int64_t ldc, double alpha, double beta, int sym) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * M) return;
   const int64_t m = idx / M, n = idx - m * M;
-  const bool lower = m / BM >= n / BN;
-  if (!lower && sym == 2) return;
-  const int64_t src = lower ? idx : n * M + m;
-  double acc = 0.0;
-  for (int s = 0; s < ks; ++s) acc += work[(int64_t)s * M * M + src];
+  if (m / BM < n / BN) return;  // an upper tile: no partials here
+  const double acc = sum_slices(work, ks, M * M, idx);
   double v = alpha * acc;
   if (beta != 0.0) v += beta * (double)C[m * ldc + n];
   C[m * ldc + n] = (TC)v;
+  if (sym == 1 && m / BM > n / BN) {
+    double w = alpha * acc;
+    if (beta != 0.0) w += beta * (double)C[n * ldc + m];
+    C[n * ldc + m] = (TC)w;
+  }
 }
 
 template <typename TS>

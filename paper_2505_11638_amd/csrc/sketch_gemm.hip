@@ -344,8 +344,17 @@ __global__ void splitk_sum_kernel(const float* __restrict__ work, int ks, int64_
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t count = rows * cols;
   if (idx >= count) return;
+  // slices added in order, eight loads in flight
   float acc = 0.f;
-  for (int q = 0; q < ks; ++q) acc += work[(int64_t)q * count + idx];
+  int q = 0;
+  for (; q + 8 <= ks; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = work[(int64_t)(q + u) * count + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; q < ks; ++q) acc += work[(int64_t)q * count + idx];
   const int64_t r = idx / cols, c = idx - r * cols;
   out[r * ld_out + c] = alpha * acc;
 }
