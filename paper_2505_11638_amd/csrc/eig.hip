@@ -461,7 +461,7 @@ __device__ __forceinline__ void invit_body(const double* __restrict__ d, const d
   double yr[QN];
 #pragma unroll
   for (int q = 0; q < QN; ++q) yr[q] = 0.0;
-  if (i < n && lam_asc[i] >= drop_rel * (*tnorm)) {
+  if (i < n && !(lam_asc[i] < drop_rel * (*tnorm))) {  // below the drop threshold: a zero vector
     const double lam = lam_asc[i];
     const double tiny = 2.220446049250313e-16 * fmax(*tnorm, 1e-300);
     const double inv_tiny = recip(tiny);
